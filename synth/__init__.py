@@ -1,0 +1,150 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module generates inputs only -- initial velocity fields, synthetic LRS
+model parameters and the workload descriptions -- and holds none of the
+method's arithmetic (no streaming, collision, filters, QoIs or closure
+evaluation).  Both the HIP library (through its Python binding) and the CPU
+oracle consume what it produces, so neither depends on the other.
+
+The paper's own inputs (DNS burn-in fields, reference QoI trajectories and
+trained LRS models) are not available; the generators below stand in for
+them with the shapes, amplitudes and structure of the paper's workloads:
+the 2-D Kolmogorov flow (Sec. 6) and the 3-D channel at Re_tau = 180
+(Sec. 7).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# Initial velocity fields
+# ---------------------------------------------------------------------------
+
+
+def noise_velocity(d: int, shape, amp: float, seed: int) -> np.ndarray:
+    """u = amp * (2U - 1) per component and cell, U ~ uniform[0, 1) (PCG64).
+
+    ``shape`` is (nz, ny, nx) (nz = 1 in 2-D); the result has shape
+    (d, nz*ny*nx) with x fastest.
+    """
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(shape))
+    return amp * (2.0 * rng.random((d, n)) - 1.0)
+
+
+def channel_velocity(nx: int, ny: int, nz: int, uc: float = 0.1, noise: float = 0.05,
+                     seed: int = 0) -> np.ndarray:
+    """Parabolic streamwise profile with centreline ``uc`` between halfway
+    bounce-back walls at y = -1/2 and y = ny - 1/2, plus uniform noise of
+    amplitude ``noise * uc`` on every component (the channel initial state of
+    the workload recipe; the paper's own start is a DNS burn-in field)."""
+    rng = np.random.default_rng(seed)
+    y = np.arange(ny) + 0.5            # distance from the lower wall
+    h2 = float(ny)                     # channel height 2H
+    prof = uc * 4.0 * y * (h2 - y) / (h2 * h2)
+    u = np.zeros((3, nz, ny, nx))
+    u[0] = prof[None, :, None]
+    u += noise * uc * (2.0 * rng.random(u.shape) - 1.0)
+    return u.reshape(3, -1)
+
+
+# ---------------------------------------------------------------------------
+# Channel physics in lattice units (paper Sec. 7.1 scaling: centreline
+# velocity U_c+ = 18.3 maps to 0.1, Re_tau = 180).
+# ---------------------------------------------------------------------------
+
+
+def channel_params(ny: int, re_tau: float = 180.0, uc_plus: float = 18.3, uc: float = 0.1):
+    """Return (tau, F_x) for a channel with ``ny`` fluid rows (H = ny/2)."""
+    H = ny / 2.0
+    u_tau = uc / uc_plus
+    nu = u_tau * H / re_tau
+    tau = 0.5 + 3.0 * nu
+    F = u_tau * u_tau / H
+    return tau, F
+
+
+# ---------------------------------------------------------------------------
+# Synthetic LRS model (stands in for a ridge fit on tracking data)
+# ---------------------------------------------------------------------------
+
+
+def lrs_model(nq: int, seed_a: int, seed_b: int, seed_sigma: int, std: float = 0.01,
+              kappa: float = 0.05):
+    """Synthetic h = 0 LRS model in scaled QoI units.
+
+    A and b are drawn N(0, std^2); A is shifted to A_s = A - (max(0, a) +
+    kappa) I, a the spectral abscissa of A, so that the scaled QoIs relax
+    towards one.  The model is returned in the regression form of the LRS
+    equation with input row [z*, 1]:  C = [(I + A_s)^T ; (b - A_s 1)^T],
+    mu = 0 and Sigma = 1e-4 (M M^T / nq + 0.1 I) with M ~ N(0, 1).
+    """
+    A = std * np.random.default_rng(seed_a).standard_normal((nq, nq))
+    b = std * np.random.default_rng(seed_b).standard_normal(nq)
+    M = np.random.default_rng(seed_sigma).standard_normal((nq, nq))
+    alpha = float(np.max(np.linalg.eigvals(A).real))
+    As = A - (max(0.0, alpha) + kappa) * np.eye(nq)
+    C = np.zeros((nq + 1, nq))
+    C[:nq, :] = (np.eye(nq) + As).T
+    C[nq, :] = b - As @ np.ones(nq)
+    Sigma = 1e-4 * (M @ M.T / nq + 0.1 * np.eye(nq))
+    Sigma = 0.5 * (Sigma + Sigma.T)
+    return C, np.zeros(nq), Sigma
+
+
+def lrs_model_channel(nq: int, seed_a: int, seed_sigma: int, kappa: float = 0.05,
+                      spread: float = 0.01, noise: float = 1e-5):
+    """Synthetic h = 0 LRS model for the 12-QoI channel closure.
+
+    Per-QoI mean reversion of the scaled QoIs towards one with seeded rates
+    kappa + spread |a_k|, a ~ N(0, 1), no bias, and seeded SPD residual
+    covariance Sigma = noise^2 (M M^T / nq + 0.1 I).  Random off-diagonal
+    coupling and random bias terms are left out: the twelve channel
+    sensitivities are nearly linearly dependent (the mean flow dominates
+    the large-scale energy and the mean-profile bands), so corrections that
+    are not consistent with that dependence call for very large dv and
+    diverge within a few hundred steps.
+    """
+    a = np.abs(np.random.default_rng(seed_a).standard_normal(nq))
+    As = -np.diag(kappa + spread * a)
+    M = np.random.default_rng(seed_sigma).standard_normal((nq, nq))
+    C = np.zeros((nq + 1, nq))
+    C[:nq, :] = (np.eye(nq) + As).T
+    C[nq, :] = -As @ np.ones(nq)
+    Sigma = noise * noise * (M @ M.T / nq + 0.1 * np.eye(nq))
+    Sigma = 0.5 * (Sigma + Sigma.T)
+    return C, np.zeros(nq), Sigma
+
+
+# ---------------------------------------------------------------------------
+# QoI sets of the workloads
+# ---------------------------------------------------------------------------
+
+#: 2-D Kolmogorov TO-LES: energy and enstrophy after the 3x3 binomial filter.
+QOIS_2D = [("E", "B", 0), ("Z", "B", 0)]
+
+#: 3-D channel: {E, Z} x {B^2, B - B^2, I - B} plus six mean-profile bands.
+QOIS_3D = ([("E", "B2", 0), ("Z", "B2", 0), ("E", "BMID", 0), ("Z", "BMID", 0),
+            ("E", "IMB", 0), ("Z", "IMB", 0)] + [("MP", "I", j) for j in range(6)])
+
+
+def kolmogorov_workload(n: int, tau: float, amp: float = 1e-5, k: int = 4,
+                        noise: float = 1e-4, seed: int = 2):
+    cfg = dict(lattice=0, nx=n, ny=n, nz=1, walls_y=0, tau=tau, substrate=0, cmodel=0.0,
+               force_kind=1, force_amp=amp, force_k=k, drag=0.0)
+    u0 = noise_velocity(2, (1, n, n), noise, seed)
+    return cfg, u0
+
+
+def channel_workload(nx: int, ny: int, nz: int, substrate: int = 1, cmodel: float = 0.1,
+                     seed: int = 6):
+    tau, F = channel_params(ny)
+    cfg = dict(lattice=1, nx=nx, ny=ny, nz=nz, walls_y=1, tau=tau, substrate=substrate,
+               cmodel=cmodel, force_kind=2, force_amp=F, force_k=0, drag=0.0)
+    u0 = channel_velocity(nx, ny, nz, seed=seed)
+    return cfg, u0
+
+
+def channel_bands(ny: int, nb: int = 6):
+    """(nbands, dmin, dmax): centres from the first fluid node to the centreline."""
+    return nb, 0.5, ny / 2.0
