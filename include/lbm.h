@@ -1,0 +1,224 @@
+/*
+ * lbm.h -- C ABI of the MI355X TO-LRS lattice Boltzmann LES library
+ * (liblbm_hip.so, HIP kernels for gfx950).
+ *
+ * The library advances lattice Boltzmann LES runs with the Tau-orthogonal
+ * (TO) closure of Hoekstra, Xue, Coveney and Edeling, "Reduced Subgrid-Scale
+ * Terms for Turbulence Simulations with the Lattice Boltzmann Method":
+ *   - one LES step is eqs. LES-1..LES-3 (Sec. 3): BGK relaxation with an
+ *     optional eddy-viscosity substrate (Sec. 5: eq. eff-relaxation, the
+ *     Smagorinsky closed form, WALE), exact-difference forcing with the
+ *     body force and the SGS velocity increment dv_SGS (eq. LES-2), then
+ *     streaming (eq. LES-3) with halfway bounce-back walls (Sec. 7.1);
+ *   - dv_SGS = sum_i gamma_i O_i (eq. TO-ansatz) with patterns built from
+ *     the QoI sensitivities (eq. O-from-V, App. A) so that
+ *     <dQ_i/dv, O_j> = 0 for i != j (eq. orthogonality);
+ *   - the coefficients follow from dQ (eq. tau-from-dQ-for-tracking), with
+ *     dQ from a reference trajectory (tracking, eq. dQ-from-ref) or from a
+ *     linear regression with stochastic residuals (eq. LRS, h = 0).
+ * QoIs (Sec. 4.1): filtered energy E_R = 1/2 sum |R v|^2, filtered enstrophy
+ * Z_R = 1/2 sum |R curl v|^2 and mean-profile QoIs sum w_j(y) v_x
+ * (eq. mean-profile-qoi, bands of eq. 3d-mp-band-weights); integrals are sums
+ * over cells with unit volume.  Filters are polynomials in the 3^d binomial
+ * operator B = (x)_a [1,2,1]/4 with zero padding on the wall axis.
+ *
+ * Conventions
+ *   - Fields are structure-of-arrays, x fastest: cell = x + nx*(y + ny*z).
+ *   - Host arrays passed to the library are double precision.
+ *   - All device work of a context is ordered on the HIP stream given at
+ *     creation; calls that return host data synchronise that stream.
+ *   - Every call returns LBM_OK (0) or a negative status; the message of the
+ *     last failure on the calling thread is in lbm_last_error().  No call
+ *     aborts or throws.  Invalid arguments leave the object unchanged.
+ *   - One context (or batch, or server) per host thread at a time.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_MAX_QOI 16
+
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,     /* invalid argument or configuration */
+    LBM_ENOMEM = -2,     /* arena too small / allocation failed */
+    LBM_EDEVICE = -3,    /* HIP runtime error */
+    LBM_EUNSTABLE = -4,  /* a run produced a non-finite value or |v| > 0.5 (sticky) */
+    LBM_ESTATE = -5      /* request outside the retained state (e.g. overwritten records) */
+};
+
+enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
+/* Population storage: FP32 deviations g = f - w_i (arithmetic in FP32),
+ * FP64 deviations, or plain FP32 populations f (the unshifted baseline). */
+enum { LBM_FP32_SHIFTED = 0, LBM_FP64 = 1, LBM_FP32_PLAIN = 2 };
+enum { LBM_BGK = 0, LBM_SMAGORINSKY = 1, LBM_WALE = 2 };
+/* Body force: none, F_x = amp sin(2 pi k y / ny) (Kolmogorov flow, Sec. 6.1,
+ * y the integer row index), or constant F_x = amp (channel, Sec. 7.1).
+ * An optional linear drag subtracts drag * rho * v. */
+enum { LBM_FORCE_NONE = 0, LBM_FORCE_SIN_Y = 1, LBM_FORCE_CONST_X = 2 };
+
+typedef struct {
+    int lattice;        /* LBM_D2Q9 or LBM_D3Q19 */
+    int precision;      /* LBM_FP32_SHIFTED, LBM_FP64, LBM_FP32_PLAIN */
+    int nx, ny, nz;     /* nz must be 1 for D2Q9 */
+    int walls_y;        /* 0 periodic in y; 1 halfway bounce-back walls at y=-1/2, ny-1/2 */
+    double tau;         /* BGK relaxation time, > 1/2 */
+    int substrate;      /* LBM_BGK, LBM_SMAGORINSKY, LBM_WALE (WALE: D3Q19 only) */
+    double c_model;     /* C_smag or C_w */
+    int force_kind;
+    double force_amp;
+    int force_k;
+    double drag;
+    int diag;           /* plain runs: 1 records mass, momentum, E and Z of the
+                           post-streaming velocity every step */
+    int rec_cap;        /* capacity of the per-step record ring (0: 4096) */
+} lbm_config;
+
+enum { LBM_QOI_E = 0, LBM_QOI_Z = 1, LBM_QOI_MP = 2 };
+/* Filters R of the scale-aware QoIs: I, B, B^2, B - B^2, I - B. */
+enum { LBM_FILT_ID = 0, LBM_FILT_B = 1, LBM_FILT_B2 = 2, LBM_FILT_BMID = 3, LBM_FILT_IMB = 4 };
+typedef struct {
+    int kind;           /* LBM_QOI_E, LBM_QOI_Z, LBM_QOI_MP (MP needs walls_y = 1) */
+    int filter;         /* for E and Z */
+    int band;           /* for MP: band index in [0, nbands) */
+} lbm_qoi_spec;
+
+enum { LBM_CLOSURE_OFF = 0, LBM_CLOSURE_TRACK = 1, LBM_CLOSURE_LRS = 2 };
+/* TO closure.  All arrays are host memory and are deep-copied.
+ *  - mode OFF: the full TO machinery runs with dQ = 0 (QoIs are recorded).
+ *  - TRACK:    dQ = qref[step] - q* (eq. dQ-from-ref); steps beyond nref get dQ = 0.
+ *  - LRS:      h = 0 regression on scaled QoIs: z* = q* / s, x = [z*, 1],
+ *              z = x C + eta, eta ~ N(mu, Sigma), dQ = s z - q* (eq. LRS).
+ *              s = scale if given, else |q*| at the first corrected step
+ *              (zero replaced by one).  Sigma is SPD, or all zero.
+ *  - dQ = 0 for steps < spinup in every mode.
+ * Band weights (eq. 3d-mp-band-weights): d_w(y) = min(y+1/2, ny-1/2-y),
+ * centres log-spaced in d_w over [band_dmin, band_dmax], sigma equal to the
+ * centre spacing in ln d_w, normalised so that sum_y w_j(y) = 1. */
+typedef struct {
+    int nq;                     /* 1..LBM_MAX_QOI; at most 8 E/Z QoIs */
+    const lbm_qoi_spec* q;      /* nq entries */
+    int nbands;
+    double band_dmin, band_dmax;
+    int mode;
+    long spinup;
+    int h;                      /* history length; must be 0 */
+    const double* C;            /* (nq+1) x nq row-major (LRS) */
+    const double* mu;           /* nq (LRS; NULL = 0) */
+    const double* Sigma;        /* nq x nq (LRS) */
+    const double* scale;        /* nq or NULL */
+    const double* qref;         /* nref x nq (TRACK) */
+    long nref;
+    uint64_t seed;              /* LRS noise key (Philox4x32-10) */
+} lbm_closure;
+
+/* One record per step.  flags: bit0 unstable, bit1 Gram matrix singular
+ * (correction skipped for that step).  mass/mom: sums over cells of rho and
+ * rho v of the post-streaming state.  q: QoIs of the predictor v^{p,n*}. */
+typedef struct {
+    int64_t step;
+    int32_t flags;
+    int32_t nq;
+    double mass;
+    double mom[3];
+    double diag_e, diag_z;
+    double q[LBM_MAX_QOI], dq[LBM_MAX_QOI], gamma[LBM_MAX_QOI];
+} lbm_qoi_rec;
+
+typedef struct lbm_ctx lbm_ctx;
+typedef struct lbm_batch lbm_batch;
+typedef struct lbm_server lbm_server;
+
+/* Library and lattice information. */
+const char* lbm_last_error(void);
+const char* lbm_version(void);
+/* Velocity table (3 ints per velocity) and weights of the library's own
+ * lattice ordering; returns Q or a negative status. */
+int lbm_lattice_info(int lattice, int* c, double* w);
+
+/* Device bytes a context needs for cfg (and the closure it will run, or
+ * NULL for a plain run).  Returns 0 for an invalid configuration. */
+size_t lbm_required_bytes(const lbm_config* cfg, const lbm_closure* closure);
+
+/* Create a context on the current HIP device.  dev_arena: caller-owned
+ * device memory of at least lbm_required_bytes(cfg, closure) bytes, 256-byte
+ * aligned, which must outlive the context; the library never frees it.
+ * stream: hipStream_t (NULL: the context creates its own non-blocking
+ * stream).  closure may be NULL.  The
+ * initial state is rho = 1, v = 0 until lbm_init_velocity is called. */
+int lbm_create(const lbm_config* cfg, const lbm_closure* closure, void* dev_arena,
+               size_t bytes, void* stream, lbm_ctx** out);
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Set the post-collision state to feq(rho, u) (host arrays; rho may be NULL
+ * for rho = 1; u has d*N entries).  Resets the step counter and records. */
+int lbm_init_velocity(lbm_ctx* ctx, const double* rho, const double* u);
+
+/* Replace the closure (between steps).  NULL switches the TO step off.  The
+ * closure must fit the workspace planned at creation (else LBM_ENOMEM). */
+int lbm_set_closure(lbm_ctx* ctx, const lbm_closure* closure);
+
+/* Enqueue nsteps LES steps on the context stream (non-blocking).  Repeated
+ * chunks are replayed from a captured hipGraph. */
+int lbm_step(lbm_ctx* ctx, long nsteps);
+int lbm_sync(lbm_ctx* ctx);             /* waits; LBM_EUNSTABLE if flagged */
+long lbm_step_count(const lbm_ctx* ctx);
+
+/* Copy records of steps [first, first+count) into out (syncs). */
+int lbm_qoi(lbm_ctx* ctx, long first, long count, lbm_qoi_rec* out);
+
+/* Density (N) and post-streaming moment velocity (d*N) of the current
+ * state, in double precision (syncs).  rho may be NULL. */
+int lbm_fields(lbm_ctx* ctx, double* rho, double* u);
+
+/* Full post-collision populations f (Q*N, library ordering, double) of the
+ * current state, including a pending SGS correction; and the inverse. */
+int lbm_get_populations(lbm_ctx* ctx, double* f);
+int lbm_set_populations(lbm_ctx* ctx, const double* f);
+
+/* Stream the current populations once without collision (index-map check). */
+int lbm_stream_only(lbm_ctx* ctx);
+
+/* Checkpoint: opaque byte image of the dynamic state (populations, pending
+ * correction, counters, LRS scale, records).  Restoring it into a context
+ * created with the same cfg and closure resumes bitwise identically. */
+size_t lbm_state_bytes(const lbm_ctx* ctx);
+int lbm_get_state(lbm_ctx* ctx, void* host, size_t bytes);
+int lbm_set_state(lbm_ctx* ctx, const void* host, size_t bytes);
+
+/* Batch: advance several contexts (created on the same device and stream)
+ * together, one launch per kernel phase for all members of the same kind,
+ * replayed from a hipGraph.  Each member's results are bitwise identical to
+ * stepping it alone.  The batch does not own the members. */
+int lbm_batch_create(int n, lbm_ctx* const* members, lbm_batch** out);
+int lbm_batch_step(lbm_batch* b, long nsteps);
+int lbm_batch_sync(lbm_batch* b);
+void lbm_batch_destroy(lbm_batch* b);
+
+/* Per-phase timing for measurement: runs nsteps steps eagerly on the context
+ * stream with HIP events between the kernel phases and returns the mean
+ * duration per step of each phase in ms[6]: stream-collide (with the WALE
+ * moments pass), curl, binomial powers, reduce, solve, apply (plain runs
+ * with records: their diagnostics in the last slot); launches[6] (nullable)
+ * receives the kernel launches per step of each phase.  Advances the run. */
+int lbm_profile_phases(lbm_ctx* ctx, long nsteps, double* ms, int* launches);
+
+/* Test hooks of the device random-number generator (allocate their own
+ * scratch; not used by the stepping path).
+ * lbm_test_philox: n Philox4x32-10 evaluations; in6 holds (ctr0..3, key0,
+ * key1) per evaluation, out4 the four output words.
+ * lbm_test_normals: the LRS standard normals of steps step0..step0+nsteps-1
+ * for a closure with n QoIs and the given seed (nsteps x n, row-major). */
+int lbm_test_philox(const uint32_t* in6, uint32_t* out4, int n);
+int lbm_test_normals(uint64_t seed, long step0, int nsteps, int n, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

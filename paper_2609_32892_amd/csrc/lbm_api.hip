@@ -1,0 +1,1021 @@
+// lbm_api.hip -- host side of liblbm_hip: arena planning, the C ABI of
+// include/lbm.h, hipGraph replay and ensemble batches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm_dev.h"
+#include "lbm_launch.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                                      \
+    do {                                                                                                  \
+        hipError_t e_ = (expr);                                                                           \
+        if (e_ != hipSuccess) return fail(LBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int filter_deg(int f) { return f == LBM_FILT_ID ? 0 : (f == LBM_FILT_B || f == LBM_FILT_IMB ? 1 : 2); }
+
+// R as a polynomial in B: coefficients of B^0, B^1, B^2.
+void filter_poly(int f, double r[3])
+{
+    r[0] = r[1] = r[2] = 0;
+    switch (f) {
+    case LBM_FILT_ID: r[0] = 1; break;
+    case LBM_FILT_B: r[1] = 1; break;
+    case LBM_FILT_B2: r[2] = 1; break;
+    case LBM_FILT_BMID: r[1] = 1; r[2] = -1; break;
+    case LBM_FILT_IMB: r[0] = 1; r[1] = -1; break;
+    }
+}
+
+struct ClosureShape {
+    int nq = 0, nsa = 0, nmp = 0, jv = 0, jw = 0, has_z = 0, has_e = 0, nbands = 0;
+    int npart() const { return nsa + nsa * (nsa + 1) / 2 + (nmp > 0 ? 1 + nsa : 0); }
+};
+
+int closure_shape(const lbm_config* cfg, const lbm_closure* cl, ClosureShape* out)
+{
+    ClosureShape s;
+    if (!cl) { *out = s; return LBM_OK; }
+    if (cl->nq < 1 || cl->nq > LBM_MAX_QOI || !cl->q) return fail(LBM_EINVAL, "closure: nq must be in [1,%d]", LBM_MAX_QOI);
+    if (cl->h != 0) return fail(LBM_EINVAL, "closure: only history length h = 0 is supported");
+    if (cl->mode < LBM_CLOSURE_OFF || cl->mode > LBM_CLOSURE_LRS) return fail(LBM_EINVAL, "closure: bad mode");
+    s.nq = cl->nq;
+    s.nbands = cl->nbands;
+    for (int k = 0; k < cl->nq; ++k) {
+        const lbm_qoi_spec& q = cl->q[k];
+        if (q.kind == LBM_QOI_E || q.kind == LBM_QOI_Z) {
+            if (q.filter < LBM_FILT_ID || q.filter > LBM_FILT_IMB) return fail(LBM_EINVAL, "closure: QoI %d bad filter", k);
+            const int p = 2 * filter_deg(q.filter);
+            if (q.kind == LBM_QOI_E) { s.jv = std::max(s.jv, p); s.has_e = 1; }
+            else { s.jw = std::max(s.jw, p); s.has_z = 1; }
+            s.nsa++;
+        } else if (q.kind == LBM_QOI_MP) {
+            if (!cfg->walls_y) return fail(LBM_EINVAL, "closure: mean-profile QoIs need walls_y = 1");
+            if (q.band < 0 || q.band >= cl->nbands) return fail(LBM_EINVAL, "closure: QoI %d band out of range", k);
+            s.nmp++;
+        } else
+            return fail(LBM_EINVAL, "closure: QoI %d bad kind", k);
+    }
+    if (s.nsa > kMaxSA) return fail(LBM_EINVAL, "closure: at most %d energy/enstrophy QoIs", kMaxSA);
+    if (s.nmp > 0 && !(cl->band_dmin > 0 && cl->band_dmax > cl->band_dmin)) return fail(LBM_EINVAL, "closure: band range");
+    if (cl->mode == LBM_CLOSURE_LRS && (!cl->C || !cl->Sigma)) return fail(LBM_EINVAL, "closure: LRS needs C and Sigma");
+    if (cl->mode == LBM_CLOSURE_TRACK && (!cl->qref || cl->nref < 0)) return fail(LBM_EINVAL, "closure: tracking needs qref");
+    *out = s;
+    return LBM_OK;
+}
+
+int check_config(const lbm_config* c)
+{
+    if (!c) return fail(LBM_EINVAL, "config is NULL");
+    if (c->lattice != LBM_D2Q9 && c->lattice != LBM_D3Q19) return fail(LBM_EINVAL, "bad lattice");
+    if (c->precision < LBM_FP32_SHIFTED || c->precision > LBM_FP32_PLAIN) return fail(LBM_EINVAL, "bad precision");
+    if (c->nx < 3 || c->ny < 3 || c->nz < 1) return fail(LBM_EINVAL, "grid must be at least 3 cells per axis");
+    if (c->lattice == LBM_D2Q9 && c->nz != 1) return fail(LBM_EINVAL, "D2Q9 needs nz = 1");
+    if (c->lattice == LBM_D3Q19 && c->nz < 3) return fail(LBM_EINVAL, "D3Q19 needs nz >= 3");
+    if ((double)c->nx * c->ny * c->nz > 2.0e9) return fail(LBM_EINVAL, "grid too large");
+    if (!(c->tau > 0.5)) return fail(LBM_EINVAL, "tau must exceed 1/2");
+    if (c->substrate < LBM_BGK || c->substrate > LBM_WALE) return fail(LBM_EINVAL, "bad substrate");
+    if (c->substrate == LBM_WALE && c->lattice != LBM_D3Q19) return fail(LBM_EINVAL, "WALE needs D3Q19");
+    if (c->force_kind < LBM_FORCE_NONE || c->force_kind > LBM_FORCE_CONST_X) return fail(LBM_EINVAL, "bad force kind");
+    if (c->rec_cap < 0) return fail(LBM_EINVAL, "rec_cap < 0");
+    return LBM_OK;
+}
+
+struct Plan {
+    size_t member, param, ctl, recs, g0, g1, fprof, vn, part_stats, part_diag, work1, workm;
+    size_t rho, vs, dv, P, W, part_to, bandw, cmp, workr;
+    size_t total;
+    int N, D, NC, Q, esz, nb1, nbx2, cpt2, nbr, rec_cap;
+    ClosureShape cap;
+};
+
+void make_plan(const lbm_config* c, const ClosureShape& cs, Plan* p)
+{
+    Plan P{};
+    P.N = c->nx * c->ny * c->nz;
+    P.D = c->lattice == LBM_D2Q9 ? 2 : 3;
+    P.NC = P.D == 2 ? 1 : 3;
+    P.Q = c->lattice == LBM_D2Q9 ? 9 : 19;
+    P.esz = c->precision == LBM_FP64 ? 8 : 4;
+    P.nb1 = (P.N + kBlock - 1) / kBlock;
+    P.rec_cap = c->rec_cap > 0 ? c->rec_cap : 4096;
+    P.cap = cs;
+    const int plane = c->nx * c->nz;
+    P.cpt2 = std::max(1, std::min(8, P.N / (kBlock * 2048)));
+    P.nbx2 = (plane + kBlock * P.cpt2 - 1) / (kBlock * P.cpt2);
+    P.nbr = P.nbx2 * c->ny;
+    const size_t N = P.N, e = P.esz;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    P.member = take(sizeof(DevMember));
+    P.param = take(sizeof(DevParam));
+    P.ctl = take(sizeof(DevCtl));
+    P.recs = take(sizeof(lbm_qoi_rec) * P.rec_cap);
+    P.g0 = take(e * P.Q * N);
+    P.g1 = take(e * P.Q * N);
+    P.fprof = take(sizeof(double) * c->ny);
+    P.vn = take(e * P.D * N);
+    P.part_stats = take(sizeof(double) * 4 * P.nb1);
+    P.part_diag = take(sizeof(double) * 2 * P.nb1);
+    P.work1 = take(sizeof(int2) * P.nb1);
+    P.workm = take(sizeof(int));
+    if (cs.nq > 0) {
+        P.rho = take(e * N);
+        P.vs = take(e * P.D * N);
+        P.dv = take(e * P.D * N);
+        P.P = take(e * (size_t)std::max(cs.jv, 1) * P.D * N);
+        P.W = take(cs.has_z ? e * (size_t)(cs.jw + 1) * P.NC * N : kAlign);
+        P.part_to = take(sizeof(double) * (size_t)std::max(cs.npart(), 1) * P.nbr);
+        P.bandw = take(sizeof(double) * (size_t)std::max(cs.nbands, 1) * c->ny);
+        P.cmp = take(sizeof(double) * c->ny);
+        P.workr = take(sizeof(int2) * P.nbr);
+    }
+    P.total = o;
+    *p = P;
+}
+
+// Band weights (eq. 3d-mp-band-weights) in the reading of the library header.
+void band_weights(int ny, int nb, double dmin, double dmax, std::vector<double>& w)
+{
+    w.assign((size_t)nb * ny, 0.0);
+    const double sig = nb > 1 ? (std::log(dmax) - std::log(dmin)) / (nb - 1) : 1.0;
+    for (int j = 0; j < nb; ++j) {
+        const double lc = std::log(dmin) + j * sig;
+        double A = 0;
+        for (int y = 0; y < ny; ++y) {
+            const double dw = std::min(y + 0.5, ny - 0.5 - y);
+            const double t = (std::log(dw) - lc) / sig;
+            w[(size_t)j * ny + y] = std::exp(-0.5 * t * t);
+            A += w[(size_t)j * ny + y];
+        }
+        for (int y = 0; y < ny; ++y) w[(size_t)j * ny + y] /= A;
+    }
+}
+
+// Lower Cholesky factor of an SPD matrix (n x n, row-major) into L with
+// leading dimension ld; the all-zero matrix gives L = 0.  Returns false if
+// the matrix is neither.
+bool cholesky_host(const double* A, int n, double* L, int ld)
+{
+    bool zero = true;
+    for (int k = 0; k < n * n; ++k) zero = zero && A[k] == 0.0;
+    for (int i = 0; i < n; ++i) for (int j = 0; j < ld; ++j) L[i * ld + j] = 0;
+    if (zero) return true;
+    for (int j = 0; j < n; ++j) {
+        double s = A[j * n + j];
+        for (int k = 0; k < j; ++k) s -= L[j * ld + k] * L[j * ld + k];
+        if (!(s > 0)) return false;
+        L[j * ld + j] = std::sqrt(s);
+        for (int i = j + 1; i < n; ++i) {
+            double t = A[i * n + j];
+            for (int k = 0; k < j; ++k) t -= L[i * ld + k] * L[j * ld + k];
+            L[i * ld + j] = t / L[j * ld + j];
+        }
+    }
+    return true;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_config cfg{};
+    Plan plan{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char* arena = nullptr;
+    DevMember hm{};
+    DevMember* dm = nullptr;
+    DevParam hp{};
+    ClosureShape cur{};   // active closure (nq = 0: none)
+    bool has_to = false;  // TO buffers exist
+    int phase = 0;        // state is in g[parity ^ phase]
+    long host_step = 0;
+    long version = 0;     // bumps whenever launch parameters change
+    double* qref_dev = nullptr;
+    size_t qref_cap = 0;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    long gver[2] = {-1, -1};
+    int gchunk = 32;
+    int mode() const { return cur.nq > 0 ? 2 : (cfg.diag ? 1 : 0); }
+};
+
+struct lbm_batch {
+    std::vector<lbm_ctx*> mem;
+    std::vector<int> phase0;     // member phase when the batch tables were built
+    std::vector<long> ver0;
+    hipStream_t stream = nullptr;
+    DevMember* dmem = nullptr;
+    int2* dwork = nullptr;
+    int* dworkm = nullptr;
+    std::vector<LaunchGroup> groups;
+    int phase = 0;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    bool graph_ok[2] = {false, false};
+    int gchunk = 16;
+};
+
+namespace {
+
+LaunchGroup ctx_group(const lbm_ctx* c)
+{
+    LaunchGroup g{};
+    g.lattice = c->cfg.lattice;
+    g.precision = c->cfg.precision;
+    g.substrate = c->cfg.substrate;
+    g.mode = c->mode();
+    g.any_z = c->cur.has_z;
+    g.maxpow = std::max(c->cur.jv, c->cur.jw);
+    g.maxsa = c->cur.nsa;
+    g.mems = c->dm;
+    g.work1 = (const int2*)(c->arena + c->plan.work1);
+    g.nb1 = c->plan.nb1;
+    g.workr = (const int2*)(c->arena + c->plan.workr);
+    g.nbr = c->plan.nbr;
+    g.workm = (const int*)(c->arena + c->plan.workm);
+    g.nmem = 1;
+    return g;
+}
+
+int upload(lbm_ctx* c, void* dst, const void* src, size_t bytes)
+{
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+void drop_graphs(lbm_ctx* c)
+{
+    for (int k = 0; k < 2; ++k) {
+        if (c->gexec[k]) hipGraphExecDestroy(c->gexec[k]);
+        c->gexec[k] = nullptr;
+        c->gver[k] = -1;
+    }
+}
+
+// Build DevParam from a closure (host side) and upload it.
+int apply_closure(lbm_ctx* c, const lbm_closure* cl)
+{
+    ClosureShape cs;
+    int rc = closure_shape(&c->cfg, cl, &cs);
+    if (rc) return rc;
+    if (cl) {
+        const ClosureShape& cap = c->plan.cap;
+        if (!c->has_to || cs.nsa > cap.nsa || cs.jv > cap.jv || (cs.has_z && (!cap.has_z || cs.jw > cap.jw)) ||
+            cs.npart() > cap.npart() || cs.nbands > std::max(cap.nbands, 1))
+            return fail(LBM_ENOMEM, "closure does not fit the workspace planned at creation");
+    }
+    // a pending correction of the previous closure is folded in first
+    if (c->has_to && c->cur.nq > 0)
+        launch_state(OP_FLUSH, c->cfg.lattice, c->cfg.precision, c->dm, c->plan.N, true, c->phase, c->stream,
+                     nullptr, nullptr);
+    DevParam p{};
+    if (cl) {
+        p.nq = cl->nq;
+        p.mode = cl->mode;
+        p.nsa = cs.nsa;
+        p.nmp = cs.nmp;
+        p.nbands = cl->nbands;
+        p.jv = cs.jv;
+        p.jw = cs.jw;
+        p.has_z = cs.has_z;
+        p.has_e = cs.has_e;
+        p.spinup = cl->spinup;
+        p.seed = cl->seed;
+        int isa = 0, imp = 0;
+        for (int k = 0; k < cl->nq; ++k) {
+            const lbm_qoi_spec& q = cl->q[k];
+            if (q.kind == LBM_QOI_MP) {
+                p.mp_slot[imp] = k;
+                p.mp_band[imp] = q.band;
+                imp++;
+            } else {
+                p.sa_slot[isa] = k;
+                p.sa_kind[isa] = q.kind == LBM_QOI_E ? 0 : 1;
+                double r[3];
+                filter_poly(q.filter, r);
+                for (int j = 0; j < 3; ++j) p.r[isa][j] = r[j];
+                for (int j = 0; j <= kMaxPow; ++j) p.rr[isa][j] = 0;
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) p.rr[isa][a + b] += r[a] * r[b];
+                isa++;
+            }
+        }
+        const int nq = cl->nq;
+        if (cl->mode == LBM_CLOSURE_LRS) {
+            for (int i = 0; i <= nq; ++i)
+                for (int k = 0; k < nq; ++k) p.C[i * kMaxQ + k] = cl->C[i * nq + k];
+            for (int k = 0; k < nq; ++k) p.mu[k] = cl->mu ? cl->mu[k] : 0.0;
+            if (!cholesky_host(cl->Sigma, nq, p.L, kMaxQ)) return fail(LBM_EINVAL, "closure: Sigma is not SPD");
+            if (cl->scale) {
+                p.have_scale = 1;
+                for (int k = 0; k < nq; ++k) p.scale[k] = cl->scale[k];
+            }
+        }
+        std::vector<double> bw;
+        if (cs.nmp > 0) {
+            band_weights(c->cfg.ny, cl->nbands, cl->band_dmin, cl->band_dmax, bw);
+            const double nxz = (double)c->cfg.nx * c->cfg.nz;
+            for (int a = 0; a < cs.nmp; ++a)
+                for (int b = 0; b < cs.nmp; ++b) {
+                    double s = 0;
+                    for (int y = 0; y < c->cfg.ny; ++y)
+                        s += bw[(size_t)p.mp_band[a] * c->cfg.ny + y] * bw[(size_t)p.mp_band[b] * c->cfg.ny + y];
+                    p.gmp[a * kMaxQ + b] = nxz * s;
+                }
+            rc = upload(c, c->arena + c->plan.bandw, bw.data(), sizeof(double) * bw.size());
+            if (rc) return rc;
+        }
+        if (cl->mode == LBM_CLOSURE_TRACK && cl->nref > 0) {
+            const size_t need = sizeof(double) * (size_t)cl->nref * nq;
+            if (need > c->qref_cap) {
+                if (c->qref_dev) HIPCHK(hipFree(c->qref_dev));
+                c->qref_dev = nullptr;
+                HIPCHK(hipMalloc(&c->qref_dev, need));
+                c->qref_cap = need;
+            }
+            rc = upload(c, c->qref_dev, cl->qref, need);
+            if (rc) return rc;
+            p.qref = c->qref_dev;
+            p.nref = (int)cl->nref;
+        }
+    }
+    rc = upload(c, c->arena + c->plan.param, &p, sizeof p);
+    if (rc) return rc;
+    // fresh LRS scale and a recorded closure shape
+    DevCtl ctl{};
+    HIPCHK(hipMemcpyAsync(&ctl, c->arena + c->plan.ctl, sizeof ctl, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    ctl.s_set = 0;
+    rc = upload(c, c->arena + c->plan.ctl, &ctl, sizeof ctl);
+    if (rc) return rc;
+    c->hp = p;
+    c->cur = cl ? cs : ClosureShape{};
+    c->hm.npart = c->cur.npart();
+    rc = upload(c, c->dm, &c->hm, sizeof c->hm);
+    if (rc) return rc;
+    c->version++;
+    drop_graphs(c);
+    return LBM_OK;
+}
+
+int reset_ctl(lbm_ctx* c)
+{
+    DevCtl ctl{};
+    int rc = upload(c, c->arena + c->plan.ctl, &ctl, sizeof ctl);
+    c->host_step = 0;
+    return rc;
+}
+
+int enqueue_steps(lbm_ctx* c, long n)
+{
+    const LaunchGroup g = ctx_group(c);
+    for (long k = 0; k < n; ++k) {
+        launch_step(g, c->stream, c->phase);
+        c->phase ^= 1;
+    }
+    HIPCHK(hipGetLastError());
+    return LBM_OK;
+}
+
+int capture(hipStream_t st, const std::vector<LaunchGroup>& groups, int nsteps, int phase0, hipGraphExec_t* out)
+{
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+    for (int k = 0; k < nsteps; ++k)
+        for (const LaunchGroup& g : groups) launch_step(g, st, phase0 ^ (k & 1));
+    hipError_t e = hipStreamEndCapture(st, &graph);
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+const char* lbm_version(void) { return "lbm_hip 0.1 (gfx950)"; }
+
+int lbm_lattice_info(int lattice, int* c, double* w)
+{
+    if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) return fail(LBM_EINVAL, "bad lattice");
+    if (!c || !w) return fail(LBM_EINVAL, "NULL output");
+    return lattice_table(lattice, c, w);
+}
+
+size_t lbm_required_bytes(const lbm_config* cfg, const lbm_closure* closure)
+{
+    if (check_config(cfg)) return 0;
+    ClosureShape cs;
+    if (closure_shape(cfg, closure, &cs)) return 0;
+    Plan p;
+    make_plan(cfg, cs, &p);
+    return p.total;
+}
+
+int lbm_create(const lbm_config* cfg, const lbm_closure* closure, void* dev_arena, size_t bytes, void* stream,
+               lbm_ctx** out)
+{
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = check_config(cfg);
+    if (rc) return rc;
+    ClosureShape cs;
+    rc = closure_shape(cfg, closure, &cs);
+    if (rc) return rc;
+    if (!dev_arena || ((uintptr_t)dev_arena % kAlign)) return fail(LBM_EINVAL, "arena must be 256-byte aligned device memory");
+    Plan plan;
+    make_plan(cfg, cs, &plan);
+    if (bytes < plan.total) return fail(LBM_ENOMEM, "arena has %zu bytes, %zu needed", bytes, plan.total);
+    lbm_ctx* c = new lbm_ctx();
+    c->cfg = *cfg;
+    c->plan = plan;
+    c->arena = (char*)dev_arena;
+    c->stream = (hipStream_t)stream;
+    if (!c->stream) {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return fail(LBM_EDEVICE, "stream creation failed");
+        }
+        c->own_stream = true;
+    }
+    c->has_to = cs.nq > 0;
+    char* A = c->arena;
+    DevMember& m = c->hm;
+    m.nx = cfg->nx; m.ny = cfg->ny; m.nz = cfg->nz; m.N = plan.N;
+    m.walls = cfg->walls_y; m.substrate = cfg->substrate; m.force_kind = cfg->force_kind; m.force_k = cfg->force_k;
+    m.parity = 0; m.has_to = c->has_to; m.diag = cfg->diag; m.rec_cap = plan.rec_cap;
+    m.tau = cfg->tau; m.cmodel = cfg->c_model; m.force_amp = cfg->force_amp; m.drag = cfg->drag;
+    m.g[0] = A + plan.g0; m.g[1] = A + plan.g1;
+    m.vn = A + plan.vn;
+    m.part_stats = (double*)(A + plan.part_stats);
+    m.part_diag = (double*)(A + plan.part_diag);
+    m.nb1 = plan.nb1; m.nbx2 = plan.nbx2; m.cpt2 = plan.cpt2; m.npart = 0;
+    m.prm = (DevParam*)(A + plan.param);
+    m.ctl = (DevCtl*)(A + plan.ctl);
+    m.recs = (lbm_qoi_rec*)(A + plan.recs);
+    m.fprof = (double*)(A + plan.fprof);
+    if (c->has_to) {
+        m.rho = A + plan.rho; m.vs = A + plan.vs; m.dv = A + plan.dv; m.P = A + plan.P; m.W = A + plan.W;
+        m.part_to = (double*)(A + plan.part_to);
+        m.bandw = (double*)(A + plan.bandw);
+        m.cmp = (double*)(A + plan.cmp);
+    }
+    c->dm = (DevMember*)(A + plan.member);
+    // host tables
+    std::vector<double> fp(cfg->ny, 0.0);
+    for (int y = 0; y < cfg->ny; ++y) {
+        if (cfg->force_kind == LBM_FORCE_SIN_Y)
+            fp[y] = cfg->force_amp * std::sin(2.0 * M_PI * cfg->force_k * y / cfg->ny);
+        else if (cfg->force_kind == LBM_FORCE_CONST_X)
+            fp[y] = cfg->force_amp;
+    }
+    std::vector<int2> w1(plan.nb1);
+    for (int b = 0; b < plan.nb1; ++b) w1[b] = make_int2(0, b);
+    int zero = 0;
+    rc = upload(c, A + plan.fprof, fp.data(), sizeof(double) * fp.size());
+    if (!rc) rc = upload(c, A + plan.work1, w1.data(), sizeof(int2) * w1.size());
+    if (!rc) rc = upload(c, A + plan.workm, &zero, sizeof zero);
+    if (!rc && c->has_to) {
+        std::vector<int2> wr(plan.nbr);
+        for (int b = 0; b < plan.nbr; ++b) wr[b] = make_int2(0, b);
+        rc = upload(c, A + plan.workr, wr.data(), sizeof(int2) * wr.size());
+    }
+    if (!rc) rc = upload(c, c->dm, &m, sizeof m);
+    if (!rc) rc = reset_ctl(c);
+    if (!rc) {
+        DevParam p{};
+        rc = upload(c, A + plan.param, &p, sizeof p);
+    }
+    // initial state rho = 1, v = 0
+    if (!rc) {
+        std::vector<double> u((size_t)plan.D * plan.N, 0.0);
+        double* du = nullptr;
+        if (hipMalloc(&du, sizeof(double) * u.size()) != hipSuccess) rc = fail(LBM_ENOMEM, "staging allocation failed");
+        else {
+            rc = upload(c, du, u.data(), sizeof(double) * u.size());
+            if (!rc) {
+                launch_state(OP_INIT, cfg->lattice, cfg->precision, c->dm, plan.N, c->has_to, 0, c->stream, nullptr, du);
+                if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(LBM_EDEVICE, "init failed");
+            }
+            hipFree(du);
+        }
+    }
+    if (!rc && closure) rc = apply_closure(c, closure);
+    if (rc) {
+        if (c->own_stream) hipStreamDestroy(c->stream);
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c)
+{
+    if (!c) return;
+    hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    if (c->qref_dev) hipFree(c->qref_dev);
+    if (c->own_stream) hipStreamDestroy(c->stream);
+    delete c;
+}
+
+int lbm_init_velocity(lbm_ctx* c, const double* rho, const double* u)
+{
+    if (!c || !u) return fail(LBM_EINVAL, "NULL argument");
+    const size_t N = c->plan.N, D = c->plan.D;
+    double* buf = nullptr;
+    HIPCHK(hipMalloc(&buf, sizeof(double) * (D + 1) * N));
+    int rc = upload(c, buf, u, sizeof(double) * D * N);
+    if (!rc && rho) rc = upload(c, buf + D * N, rho, sizeof(double) * N);
+    if (!rc) {
+        c->phase = 0;
+        launch_state(OP_INIT, c->cfg.lattice, c->cfg.precision, c->dm, (int)N, c->has_to, 0, c->stream,
+                     rho ? buf + D * N : nullptr, buf);
+        if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(LBM_EDEVICE, "init kernel failed");
+    }
+    hipFree(buf);
+    if (!rc) rc = reset_ctl(c);
+    c->version++;
+    return rc;
+}
+
+int lbm_set_closure(lbm_ctx* c, const lbm_closure* cl)
+{
+    if (!c) return fail(LBM_EINVAL, "NULL context");
+    return apply_closure(c, cl);
+}
+
+int lbm_step(lbm_ctx* c, long n)
+{
+    if (!c || n < 0) return fail(LBM_EINVAL, "bad arguments");
+    while (n > 0) {
+        if (n >= c->gchunk) {
+            const int ph = c->phase;
+            if (!c->gexec[ph] || c->gver[ph] != c->version) {
+                if (c->gexec[ph]) hipGraphExecDestroy(c->gexec[ph]);
+                c->gexec[ph] = nullptr;
+                std::vector<LaunchGroup> gs{ctx_group(c)};
+                int rc = capture(c->stream, gs, c->gchunk, ph, &c->gexec[ph]);
+                if (rc) return rc;
+                c->gver[ph] = c->version;
+            }
+            HIPCHK(hipGraphLaunch(c->gexec[ph], c->stream));
+            n -= c->gchunk;
+            c->host_step += c->gchunk;
+            // gchunk is even: the phase is unchanged
+        } else {
+            int rc = enqueue_steps(c, n);
+            if (rc) return rc;
+            c->host_step += n;
+            n = 0;
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_sync(lbm_ctx* c)
+{
+    if (!c) return fail(LBM_EINVAL, "NULL context");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    int flags = 0;
+    HIPCHK(hipMemcpy(&flags, c->arena + c->plan.ctl + offsetof(DevCtl, flags), sizeof flags, hipMemcpyDeviceToHost));
+    if (flags & 1) return fail(LBM_EUNSTABLE, "run became unstable (non-finite value or |v| > 0.5)");
+    return LBM_OK;
+}
+
+long lbm_step_count(const lbm_ctx* c) { return c ? c->host_step : -1; }
+
+int lbm_qoi(lbm_ctx* c, long first, long count, lbm_qoi_rec* out)
+{
+    if (!c || first < 0 || count < 0 || (count && !out)) return fail(LBM_EINVAL, "bad arguments");
+    if (c->mode() == 0) return fail(LBM_ESTATE, "no records: plain run without diagnostics");
+    const long cap = c->plan.rec_cap;
+    if (first + count > c->host_step || first < c->host_step - cap)
+        return fail(LBM_ESTATE, "records [%ld,%ld) not retained (have [%ld,%ld))", first, first + count,
+                    std::max(0L, c->host_step - cap), c->host_step);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const lbm_qoi_rec* d = (const lbm_qoi_rec*)(c->arena + c->plan.recs);
+    long k = 0;
+    while (k < count) {
+        const long slot = (first + k) % cap;
+        const long run = std::min(count - k, cap - slot);
+        HIPCHK(hipMemcpy(out + k, d + slot, sizeof(lbm_qoi_rec) * run, hipMemcpyDeviceToHost));
+        k += run;
+    }
+    return LBM_OK;
+}
+
+int lbm_fields(lbm_ctx* c, double* rho, double* u)
+{
+    if (!c || !u) return fail(LBM_EINVAL, "NULL argument");
+    const size_t N = c->plan.N, D = c->plan.D;
+    double* buf = nullptr;
+    HIPCHK(hipMalloc(&buf, sizeof(double) * (D + 1) * N));
+    launch_fields(c->cfg.lattice, c->cfg.precision, c->dm, (const int2*)(c->arena + c->plan.work1), c->plan.nb1,
+                  c->has_to, c->phase, c->stream, buf + D * N);
+    int rc = LBM_OK;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(LBM_EDEVICE, "moments kernel failed");
+    // velocity is in vn (element type of the run); widen on the host
+    if (!rc) {
+        const size_t e = c->plan.esz;
+        std::vector<char> tmp(e * D * N);
+        if (hipMemcpy(tmp.data(), c->arena + c->plan.vn, tmp.size(), hipMemcpyDeviceToHost) != hipSuccess)
+            rc = fail(LBM_EDEVICE, "copy failed");
+        else {
+            for (size_t k = 0; k < D * N; ++k)
+                u[k] = e == 8 ? ((const double*)tmp.data())[k] : (double)((const float*)tmp.data())[k];
+            if (rho && hipMemcpy(rho, buf + D * N, sizeof(double) * N, hipMemcpyDeviceToHost) != hipSuccess)
+                rc = fail(LBM_EDEVICE, "copy failed");
+        }
+    }
+    hipFree(buf);
+    return rc;
+}
+
+int lbm_get_populations(lbm_ctx* c, double* f)
+{
+    if (!c || !f) return fail(LBM_EINVAL, "NULL argument");
+    const size_t n = (size_t)c->plan.Q * c->plan.N;
+    double* buf = nullptr;
+    HIPCHK(hipMalloc(&buf, sizeof(double) * n));
+    launch_state(OP_GET_POP, c->cfg.lattice, c->cfg.precision, c->dm, c->plan.N, c->has_to, c->phase, c->stream,
+                 nullptr, buf);
+    int rc = LBM_OK;
+    if (hipStreamSynchronize(c->stream) != hipSuccess || hipMemcpy(f, buf, sizeof(double) * n, hipMemcpyDeviceToHost) != hipSuccess)
+        rc = fail(LBM_EDEVICE, "population read failed");
+    hipFree(buf);
+    return rc;
+}
+
+int lbm_set_populations(lbm_ctx* c, const double* f)
+{
+    if (!c || !f) return fail(LBM_EINVAL, "NULL argument");
+    const size_t n = (size_t)c->plan.Q * c->plan.N;
+    double* buf = nullptr;
+    HIPCHK(hipMalloc(&buf, sizeof(double) * n));
+    int rc = upload(c, buf, f, sizeof(double) * n);
+    if (!rc) {
+        launch_state(OP_SET_POP, c->cfg.lattice, c->cfg.precision, c->dm, c->plan.N, c->has_to, c->phase, c->stream,
+                     buf, nullptr);
+        if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(LBM_EDEVICE, "population write failed");
+    }
+    hipFree(buf);
+    c->version++;
+    return rc;
+}
+
+int lbm_stream_only(lbm_ctx* c)
+{
+    if (!c) return fail(LBM_EINVAL, "NULL context");
+    // a pending SGS correction is folded into the populations first
+    if (c->has_to)
+        launch_state(OP_FLUSH, c->cfg.lattice, c->cfg.precision, c->dm, c->plan.N, true, c->phase, c->stream,
+                     nullptr, nullptr);
+    launch_state(OP_STREAM, c->cfg.lattice, c->cfg.precision, c->dm, c->plan.N, false, c->phase, c->stream,
+                 nullptr, nullptr);
+    c->phase ^= 1;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->version++;
+    return LBM_OK;
+}
+
+// Checkpoint image: header, current populations, TO buffers, control block,
+// records.
+struct StateHeader {
+    uint64_t magic;
+    int64_t host_step;
+    int32_t Q, N, esz, has_to;
+};
+
+size_t lbm_state_bytes(const lbm_ctx* c)
+{
+    if (!c) return 0;
+    const Plan& p = c->plan;
+    size_t b = sizeof(StateHeader) + (size_t)p.esz * p.Q * p.N + sizeof(DevCtl) + sizeof(lbm_qoi_rec) * p.rec_cap;
+    if (c->has_to) b += (size_t)p.esz * p.N * (1 + 2 * p.D);
+    return b;
+}
+
+int lbm_get_state(lbm_ctx* c, void* host, size_t bytes)
+{
+    if (!c || !host) return fail(LBM_EINVAL, "NULL argument");
+    if (bytes < lbm_state_bytes(c)) return fail(LBM_EINVAL, "buffer too small");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const Plan& p = c->plan;
+    char* o = (char*)host;
+    StateHeader h{0x4C424D53544154ULL, c->host_step, p.Q, p.N, p.esz, c->has_to};
+    memcpy(o, &h, sizeof h);
+    o += sizeof h;
+    const size_t gb = (size_t)p.esz * p.Q * p.N;
+    HIPCHK(hipMemcpy(o, c->hm.g[c->hm.parity ^ c->phase], gb, hipMemcpyDeviceToHost));
+    o += gb;
+    if (c->has_to) {
+        const size_t fb = (size_t)p.esz * p.N;
+        HIPCHK(hipMemcpy(o, c->hm.rho, fb, hipMemcpyDeviceToHost)); o += fb;
+        HIPCHK(hipMemcpy(o, c->hm.vs, fb * p.D, hipMemcpyDeviceToHost)); o += fb * p.D;
+        HIPCHK(hipMemcpy(o, c->hm.dv, fb * p.D, hipMemcpyDeviceToHost)); o += fb * p.D;
+    }
+    HIPCHK(hipMemcpy(o, c->arena + p.ctl, sizeof(DevCtl), hipMemcpyDeviceToHost));
+    o += sizeof(DevCtl);
+    HIPCHK(hipMemcpy(o, c->arena + p.recs, sizeof(lbm_qoi_rec) * p.rec_cap, hipMemcpyDeviceToHost));
+    return LBM_OK;
+}
+
+int lbm_set_state(lbm_ctx* c, const void* host, size_t bytes)
+{
+    if (!c || !host) return fail(LBM_EINVAL, "NULL argument");
+    if (bytes < lbm_state_bytes(c)) return fail(LBM_EINVAL, "buffer too small");
+    const Plan& p = c->plan;
+    const char* o = (const char*)host;
+    StateHeader h;
+    memcpy(&h, o, sizeof h);
+    if (h.magic != 0x4C424D53544154ULL || h.Q != p.Q || h.N != p.N || h.esz != p.esz || h.has_to != (int)c->has_to)
+        return fail(LBM_EINVAL, "state image does not match this context");
+    o += sizeof h;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->phase = 0;
+    const size_t gb = (size_t)p.esz * p.Q * p.N;
+    HIPCHK(hipMemcpy(c->hm.g[c->hm.parity], o, gb, hipMemcpyHostToDevice));
+    o += gb;
+    if (c->has_to) {
+        const size_t fb = (size_t)p.esz * p.N;
+        HIPCHK(hipMemcpy(c->hm.rho, o, fb, hipMemcpyHostToDevice)); o += fb;
+        HIPCHK(hipMemcpy(c->hm.vs, o, fb * p.D, hipMemcpyHostToDevice)); o += fb * p.D;
+        HIPCHK(hipMemcpy(c->hm.dv, o, fb * p.D, hipMemcpyHostToDevice)); o += fb * p.D;
+    }
+    HIPCHK(hipMemcpy(c->arena + p.ctl, o, sizeof(DevCtl), hipMemcpyHostToDevice));
+    o += sizeof(DevCtl);
+    HIPCHK(hipMemcpy(c->arena + p.recs, o, sizeof(lbm_qoi_rec) * p.rec_cap, hipMemcpyHostToDevice));
+    c->host_step = h.host_step;
+    c->version++;
+    return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+static void batch_free_dev(lbm_batch* b)
+{
+    for (int k = 0; k < 2; ++k) {
+        if (b->gexec[k]) hipGraphExecDestroy(b->gexec[k]);
+        b->gexec[k] = nullptr;
+        b->graph_ok[k] = false;
+    }
+    if (b->dmem) hipFree(b->dmem);
+    if (b->dwork) hipFree(b->dwork);
+    if (b->dworkm) hipFree(b->dworkm);
+    b->dmem = nullptr;
+    b->dwork = nullptr;
+    b->dworkm = nullptr;
+    b->groups.clear();
+}
+
+static int batch_build(lbm_batch* b)
+{
+    batch_free_dev(b);
+    const int n = (int)b->mem.size();
+    // group members by kernel kind
+    struct Key { int lat, prec, sub, mode, sa2; };
+    std::vector<Key> keys;
+    std::vector<std::vector<int>> gm;
+    for (int i = 0; i < n; ++i) {
+        const lbm_ctx* c = b->mem[i];
+        Key k{c->cfg.lattice, c->cfg.precision, c->cfg.substrate, c->mode(), c->cur.nsa <= 2};
+        int gi = -1;
+        for (size_t j = 0; j < keys.size(); ++j)
+            if (!memcmp(&keys[j], &k, sizeof k)) gi = (int)j;
+        if (gi < 0) { keys.push_back(k); gm.emplace_back(); gi = (int)keys.size() - 1; }
+        gm[gi].push_back(i);
+    }
+    std::vector<DevMember> hmem(n);
+    std::vector<int2> work;
+    std::vector<int> workm;
+    struct Off { size_t w1, nb1, wr, nbr, wm, nm; };
+    std::vector<Off> offs;
+    for (size_t gi = 0; gi < keys.size(); ++gi) {
+        Off o{};
+        o.w1 = work.size();
+        for (int i : gm[gi])
+            for (int k = 0; k < b->mem[i]->plan.nb1; ++k) work.push_back(make_int2(i, k));
+        o.nb1 = work.size() - o.w1;
+        o.wr = work.size();
+        if (keys[gi].mode == 2)
+            for (int i : gm[gi])
+                for (int k = 0; k < b->mem[i]->plan.nbr; ++k) work.push_back(make_int2(i, k));
+        o.nbr = work.size() - o.wr;
+        o.wm = workm.size();
+        for (int i : gm[gi]) workm.push_back(i);
+        o.nm = workm.size() - o.wm;
+        offs.push_back(o);
+    }
+    b->phase0.resize(n);
+    b->ver0.resize(n);
+    for (int i = 0; i < n; ++i) {
+        lbm_ctx* c = b->mem[i];
+        hmem[i] = c->hm;
+        hmem[i].parity = c->hm.parity ^ c->phase;
+        b->phase0[i] = c->phase;
+        b->ver0[i] = c->version;
+    }
+    b->phase = 0;
+    HIPCHK(hipMalloc(&b->dmem, sizeof(DevMember) * n));
+    HIPCHK(hipMalloc(&b->dwork, sizeof(int2) * std::max<size_t>(work.size(), 1)));
+    HIPCHK(hipMalloc(&b->dworkm, sizeof(int) * std::max<size_t>(workm.size(), 1)));
+    HIPCHK(hipMemcpyAsync(b->dmem, hmem.data(), sizeof(DevMember) * n, hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipMemcpyAsync(b->dwork, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipMemcpyAsync(b->dworkm, workm.data(), sizeof(int) * workm.size(), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    for (size_t gi = 0; gi < keys.size(); ++gi) {
+        LaunchGroup g{};
+        g.lattice = keys[gi].lat;
+        g.precision = keys[gi].prec;
+        g.substrate = keys[gi].sub;
+        g.mode = keys[gi].mode;
+        for (int i : gm[gi]) {
+            const lbm_ctx* c = b->mem[i];
+            g.any_z |= c->cur.has_z;
+            g.maxpow = std::max(g.maxpow, std::max(c->cur.jv, c->cur.jw));
+            g.maxsa = std::max(g.maxsa, c->cur.nsa);
+        }
+        g.mems = b->dmem;
+        g.work1 = b->dwork + offs[gi].w1;
+        g.nb1 = (int)offs[gi].nb1;
+        g.workr = b->dwork + offs[gi].wr;
+        g.nbr = (int)offs[gi].nbr;
+        g.workm = b->dworkm + offs[gi].wm;
+        g.nmem = (int)offs[gi].nm;
+        b->groups.push_back(g);
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_create(int n, lbm_ctx* const* members, lbm_batch** out)
+{
+    if (!out || n < 1 || !members) return fail(LBM_EINVAL, "bad arguments");
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        if (!members[i]) return fail(LBM_EINVAL, "member %d is NULL", i);
+        if (members[i]->stream != members[0]->stream) return fail(LBM_EINVAL, "members must share one stream");
+        for (int j = 0; j < i; ++j)
+            if (members[j] == members[i]) return fail(LBM_EINVAL, "member %d repeated", i);
+    }
+    lbm_batch* b = new lbm_batch();
+    b->mem.assign(members, members + n);
+    b->stream = members[0]->stream;
+    int rc = batch_build(b);
+    if (rc) { batch_free_dev(b); delete b; return rc; }
+    *out = b;
+    return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch* b, long n)
+{
+    if (!b || n < 0) return fail(LBM_EINVAL, "bad arguments");
+    bool stale = false;
+    for (size_t i = 0; i < b->mem.size(); ++i)
+        stale = stale || b->mem[i]->version != b->ver0[i] || (b->mem[i]->phase ^ b->phase) != b->phase0[i];
+    if (stale) {
+        int rc = batch_build(b);
+        if (rc) return rc;
+    }
+    long left = n;
+    while (left > 0) {
+        if (left >= b->gchunk) {
+            const int ph = b->phase;
+            if (!b->graph_ok[ph]) {
+                int rc = capture(b->stream, b->groups, b->gchunk, ph, &b->gexec[ph]);
+                if (rc) return rc;
+                b->graph_ok[ph] = true;
+            }
+            HIPCHK(hipGraphLaunch(b->gexec[ph], b->stream));
+            left -= b->gchunk;
+        } else {
+            for (const LaunchGroup& g : b->groups) launch_step(g, b->stream, b->phase);
+            b->phase ^= 1;
+            left -= 1;
+        }
+    }
+    HIPCHK(hipGetLastError());
+    for (lbm_ctx* c : b->mem) {
+        c->host_step += n;
+        c->phase ^= (int)(n & 1);
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_sync(lbm_batch* b)
+{
+    if (!b) return fail(LBM_EINVAL, "NULL batch");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    int rc = LBM_OK;
+    for (lbm_ctx* c : b->mem) {
+        int r = lbm_sync(c);
+        if (r && !rc) rc = r;
+    }
+    return rc;
+}
+
+void lbm_batch_destroy(lbm_batch* b)
+{
+    if (!b) return;
+    hipStreamSynchronize(b->stream);
+    batch_free_dev(b);
+    delete b;
+}
+
+// Per-phase timing: nsteps eager steps with events at the phase boundaries,
+// on the context stream.  ms[k] is the mean duration of phase k per step
+// (stream-collide, curl, binomial powers, reduce, solve, apply); launches[k]
+// the number of kernel launches of phase k per step.
+int lbm_profile_phases(lbm_ctx* c, long nsteps, double* ms, int* launches)
+{
+    if (!c || nsteps < 1 || !ms) return fail(LBM_EINVAL, "bad arguments");
+    hipEvent_t ev[kNumPhases + 1];
+    for (int k = 0; k <= kNumPhases; ++k) HIPCHK(hipEventCreate(&ev[k]));
+    double acc[kNumPhases] = {0, 0, 0, 0, 0, 0};
+    const LaunchGroup g = ctx_group(c);
+    int rc = LBM_OK;
+    for (long s = 0; s < nsteps && !rc; ++s) {
+        launch_step(g, c->stream, c->phase, ev);
+        c->phase ^= 1;
+        c->host_step += 1;
+        if (hipEventSynchronize(ev[kNumPhases]) != hipSuccess) { rc = fail(LBM_EDEVICE, "event sync failed"); break; }
+        for (int k = 0; k < kNumPhases; ++k) {
+            float t = 0;
+            if (hipEventElapsedTime(&t, ev[k], ev[k + 1]) != hipSuccess) { rc = fail(LBM_EDEVICE, "event timing failed"); break; }
+            acc[k] += t;
+        }
+    }
+    for (int k = 0; k <= kNumPhases; ++k) (void)hipEventDestroy(ev[k]);
+    for (int k = 0; k < kNumPhases; ++k) ms[k] = acc[k] / nsteps;
+    if (launches) {
+        const int m = g.mode;
+        launches[0] = 1 + (g.substrate == LBM_WALE ? 1 : 0);
+        launches[1] = m == 2 && g.any_z ? 1 : 0;
+        launches[2] = m == 2 ? g.maxpow : 0;
+        launches[3] = m == 2 ? 1 : 0;
+        launches[4] = m == 2 ? 1 : 0;
+        launches[5] = m == 2 ? 1 : (m == 1 ? 2 : 0);
+    }
+    return rc;
+}
+
+// Test hooks for the random-number generator (not part of the stepping path).
+int lbm_test_philox(const uint32_t* in6, uint32_t* out4, int n)
+{
+    uint32_t *din = nullptr, *dout = nullptr;
+    HIPCHK(hipMalloc(&din, sizeof(uint32_t) * 6 * n));
+    HIPCHK(hipMalloc(&dout, sizeof(uint32_t) * 4 * n));
+    HIPCHK(hipMemcpy(din, in6, sizeof(uint32_t) * 6 * n, hipMemcpyHostToDevice));
+    launch_philox_test(din, dout, n, nullptr);
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(out4, dout, sizeof(uint32_t) * 4 * n, hipMemcpyDeviceToHost));
+    hipFree(din);
+    hipFree(dout);
+    return LBM_OK;
+}
+
+int lbm_test_normals(uint64_t seed, long step0, int nsteps, int n, double* out)
+{
+    if (n < 1 || n > LBM_MAX_QOI || nsteps < 1) return fail(LBM_EINVAL, "bad arguments");
+    double* d = nullptr;
+    HIPCHK(hipMalloc(&d, sizeof(double) * (size_t)nsteps * n));
+    launch_normals_test(seed, step0, nsteps, n, d, nullptr);
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(out, d, sizeof(double) * (size_t)nsteps * n, hipMemcpyDeviceToHost));
+    hipFree(d);
+    return LBM_OK;
+}
+
+}  // extern "C"

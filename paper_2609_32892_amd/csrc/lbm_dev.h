@@ -1,0 +1,76 @@
+// lbm_dev.h -- internal device-side structures of liblbm_hip (not installed).
+//
+// Every LES run ("member") is described to the kernels by a DevMember record
+// in device memory.  Kernels are launched over work tables whose entries map
+// a workgroup to (member, local block), so one launch advances one member or
+// any number of members of the same kind.
+#pragma once
+#include <stdint.h>
+
+#include "../../include/lbm.h"
+
+namespace lbm {
+
+constexpr int kMaxQ = LBM_MAX_QOI;
+constexpr int kMaxSA = 8;       // E/Z QoIs per closure
+constexpr int kMaxPow = 4;      // highest power of B in R R (filters up to degree 2)
+constexpr int kBlock = 256;     // threads per workgroup of the cell kernels
+
+// Constant closure parameters (written by the host at set_closure).
+struct DevParam {
+    int nq, mode, nsa, nmp;
+    int nbands, have_scale, nref, jv;  // jv: highest power of B applied to v
+    int jw, has_z, has_e, pad0;        // jw: highest power applied to curl v
+    long long spinup;
+    unsigned long long seed;
+    int sa_slot[kMaxSA];               // user index of each E/Z QoI
+    int sa_kind[kMaxSA];               // 0 E, 1 Z
+    int mp_slot[kMaxQ];                // user index of each MP QoI
+    int mp_band[kMaxQ];
+    double r[kMaxSA][3];               // R   = sum_j r[j]  B^j
+    double rr[kMaxSA][kMaxPow + 1];    // R R = sum_j rr[j] B^j
+    double C[(kMaxQ + 1) * kMaxQ];
+    double mu[kMaxQ];
+    double L[kMaxQ * kMaxQ];           // Cholesky factor of Sigma
+    double scale[kMaxQ];
+    double gmp[kMaxQ * kMaxQ];         // <w_i e_x, w_j e_x> = nx nz sum_y w_i w_j
+    const double* qref;                // nref x nq
+};
+
+// Per-step control state written by the kernels.
+struct DevCtl {
+    long long step;
+    int flags;                         // sticky bit0: unstable
+    int s_set;
+    double s[kMaxQ];                   // LRS scale
+    double cv[kMaxPow + 1];            // dv = sum_j cv[j] B^j v + curl^T(sum_j cw[j] B^j w) + e_x cmp(y)
+    double cw[kMaxPow + 1];
+    double pad[6];
+};
+
+struct DevMember {
+    int nx, ny, nz, N;
+    int walls, substrate, force_kind, force_k;
+    int parity;                        // index of the buffer holding the state at flip 0
+    int has_to, diag, rec_cap;
+    double tau, cmodel, force_amp, drag;
+    void* g[2];                        // populations [Q][N]
+    void* rho;                         // rho - 1 of the predictor [N]      (TO)
+    void* vs;                          // predictor velocity v* [D][N]      (TO)
+    void* dv;                          // pending SGS increment [D][N]      (TO)
+    void* vn;                          // post-streaming velocity [D][N]    (diag, WALE)
+    void* P;                           // B^j v*, j = 1..jv   [jv][D][N]
+    void* W;                           // B^j curl v*, j=0..jw [jw+1][NC][N]
+    double* part_stats;                // [nb1][4]: sum(rho-1), sum(rho v)
+    double* part_to;                   // [ny][nbx2][npart]
+    double* part_diag;                 // [nb1][2]
+    int nb1, nbx2, npart, cpt2;        // block counts; cells per thread of the reduce
+    DevParam* prm;
+    DevCtl* ctl;
+    lbm_qoi_rec* recs;
+    double* bandw;                     // [nbands][ny]
+    double* cmp;                       // [ny]
+    double* fprof;                     // body force F_x(y) [ny]
+};
+
+}  // namespace lbm

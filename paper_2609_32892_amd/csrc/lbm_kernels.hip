@@ -1,0 +1,1255 @@
+// lbm_kernels.hip -- HIP kernels of the TO-LRS lattice Boltzmann LES step for
+// gfx950 (MI355X).
+//
+// Populations are stored structure-of-arrays [Q][N] (x fastest) in two
+// ping-pong buffers.  One step (eqs. LES-1..LES-3 with the TO correction):
+//   k_step     pull-stream with halfway bounce-back (eq. LES-3, Sec. 7.1) while
+//              applying the pending SGS increment of the previous step at each
+//              source cell, moments, effective relaxation time (Sec. 5), BGK
+//              relaxation and exact-difference forcing (eq. LES-1/LES-2);
+//              writes the predictor populations and rho, v* = v^{p,n*}.
+//   k_curl     w = curl v* (second-order central differences).
+//   k_binom    powers B^j v*, B^j w of the binomial filter (Sec. 4.1).
+//   k_reduce   per-cell QoIs, sensitivities (App. A) and Gram products,
+//              reduced per workgroup in FP64.
+//   k_solve    one workgroup per member: fixed-order sums, dQ (tracking or
+//              LRS, eqs. dQ-from-ref, LRS), Gram solve (eq. O-from-V,
+//              eq. orthogonality), gamma (eq. tau-from-dQ-for-tracking).
+//   k_apply    dv_SGS = sum_i gamma_i O_i (eq. TO-ansatz), evaluated as
+//              sum_j beta_j V_j with beta = G^-1 dQ.
+// Every kernel takes a table of members and a work table mapping each
+// workgroup to (member, local block), so one launch serves a whole ensemble.
+// All reductions have a fixed order that depends only on the member's own
+// geometry, so a member gives bitwise the same result alone or in a batch.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "lbm_dev.h"
+#include "lbm_launch.h"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// Lattices (Sec. 2).  Opposite of i >= 1 is i + 1 for odd i, i - 1 for even i.
+// ---------------------------------------------------------------------------
+template <int LAT> struct Lat;
+template <> struct Lat<LBM_D2Q9> {
+    static constexpr int Q = 9, D = 2, NC = 1;
+    static constexpr int cx[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+    static constexpr int cy[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
+    static constexpr int cz[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    static constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                    1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+};
+template <> struct Lat<LBM_D3Q19> {
+    static constexpr int Q = 19, D = 3, NC = 3;
+    static constexpr int cx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    static constexpr int cy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    static constexpr int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    static constexpr double w[19] = {1.0 / 3, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                                     1.0 / 18, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                     1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                     1.0 / 36};
+};
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+__device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+// ---------------------------------------------------------------------------
+// Reductions: butterfly over the 64-lane wavefront, then waves in order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum NV values over the workgroup (blockDim.x = kBlock); result valid in
+// thread 0.  Uses NV * 4 doubles of LDS.
+template <int NV>
+__device__ __forceinline__ void block_sum(double* v, double* lds)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = wave_sum(v[k]);
+        if (lane == 0) lds[k * (kBlock / 64) + wv] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0;
+#pragma unroll
+            for (int j = 0; j < kBlock / 64; ++j) s += lds[k * (kBlock / 64) + j];
+            v[k] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// feq_i(rho, a) - feq_i(rho, b) in difference form (exactly zero when a = b):
+// w rho [3 c.(a-b) + 9/2 (c.(a-b))(c.(a+b)) - 3/2 (a-b).(a+b)].
+template <typename T>
+__device__ __forceinline__ T dfeq(T w, T rho, T cd, T cs, T dd)
+{
+    return w * rho * (T(3) * cd + T(4.5) * cd * cs - T(1.5) * dd);
+}
+
+// ---------------------------------------------------------------------------
+// Pull gather of the post-collision populations of cell (x,y,z), including
+// the pending SGS correction of each source cell when TO is active.
+// ---------------------------------------------------------------------------
+template <int LAT, typename T, bool TO>
+__device__ __forceinline__ void gather(const DevMember& m, const T* __restrict__ gs, int x, int y, int z,
+                                       int cell, T* f)
+{
+    using L = Lat<LAT>;
+    constexpr int Q = L::Q, D = L::D;
+    const int N = m.N, nx = m.nx, ny = m.ny, nz = m.nz;
+    const T* __restrict__ rho = (const T*)m.rho;
+    const T* __restrict__ vs = (const T*)m.vs;
+    const T* __restrict__ dv = (const T*)m.dv;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int sy = y - L::cy[i];
+        int src, pi;
+        bool bb = m.walls && (sy < 0 || sy >= ny);
+        if (bb) {
+            src = cell;
+            pi = opp(i);
+        } else {
+            int sx = wrapi(x - L::cx[i], nx);
+            sy = wrapi(sy, ny);
+            int sz = D == 3 ? wrapi(z - L::cz[i], nz) : 0;
+            src = sx + nx * (sy + ny * sz);
+            pi = i;
+        }
+        T v = gs[(size_t)pi * N + src];
+        if (TO) {
+            // delta f_pi(src) = feq_pi(rho, v*+dv) - feq_pi(rho, v*); c_pi = s c_i
+            const T sg = bb ? T(-1) : T(1);
+            T r = T(1) + rho[src];
+            T cd = 0, cs = 0, dd = 0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const int ca = a == 0 ? L::cx[i] : (a == 1 ? L::cy[i] : L::cz[i]);
+                T d = dv[(size_t)a * N + src];
+                T s2 = T(2) * vs[(size_t)a * N + src] + d;
+                if (ca != 0) {
+                    cd += T(ca) * d;
+                    cs += T(ca) * s2;
+                }
+                dd += d * s2;
+            }
+            v += T(L::w[i]) * r * (T(3) * sg * cd + T(4.5) * cd * cs - T(1.5) * dd);
+        }
+        f[i] = v;
+    }
+}
+
+// Moments: rho - 1 and rho u from gathered populations.
+template <int LAT, typename T, int PREC>
+__device__ __forceinline__ void moments(const T* f, T& drho, T* j)
+{
+    using L = Lat<LAT>;
+    drho = 0;
+#pragma unroll
+    for (int a = 0; a < L::D; ++a) j[a] = 0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        drho += f[i];
+        if (L::cx[i]) j[0] += T(L::cx[i]) * f[i];
+        if (L::cy[i]) j[1] += T(L::cy[i]) * f[i];
+        if (L::D == 3 && L::cz[i]) j[2] += T(L::cz[i]) * f[i];
+    }
+    if (PREC == LBM_FP32_PLAIN) drho -= T(1);
+}
+
+// ---------------------------------------------------------------------------
+// K1: stream + collide + force.
+// MODE 0: plain; 1: plain with statistics and post-streaming velocity;
+// 2: TO predictor (statistics, rho, v*, pending correction applied).
+// ---------------------------------------------------------------------------
+template <int LAT, typename T, int PREC, int SUB, int MODE>
+__global__ __launch_bounds__(kBlock) void k_step(const DevMember* __restrict__ mems,
+                                                 const int2* __restrict__ work, int flip)
+{
+    using L = Lat<LAT>;
+    constexpr int Q = L::Q, D = L::D;
+    __shared__ double lds[4 * (kBlock / 64)];
+    const int2 wk = work[blockIdx.x];
+    const DevMember& m = mems[wk.x];
+    const int N = m.N, nx = m.nx, ny = m.ny;
+    const int cell = wk.y * kBlock + threadIdx.x;
+    const int cur = m.parity ^ flip;
+    const T* __restrict__ gs = (const T*)m.g[cur];
+    T* __restrict__ gd = (T*)m.g[cur ^ 1];
+    double st[4] = {0, 0, 0, 0};
+    int bad = 0;
+    if (cell < N) {
+        const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
+        T f[Q];
+        gather<LAT, T, MODE == 2>(m, gs, x, y, z, cell, f);
+        T drho, j[3] = {0, 0, 0};
+        moments<LAT, T, PREC>(f, drho, j);
+        const T rho = T(1) + drho;
+        const T ir = T(1) / rho;
+        T u[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < D; ++a) u[a] = j[a] * ir;
+        T uu = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) uu += u[a] * u[a];
+        if (!(uu <= T(0.25))) bad = 1;
+
+        // equilibrium deviations geq_i = feq_i - w_i (or feq_i for plain storage)
+        T geq[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            T cu = T(L::cx[i]) * u[0] + T(L::cy[i]) * u[1] + (D == 3 ? T(L::cz[i]) * u[2] : T(0));
+            T X = T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu;
+            if (PREC == LBM_FP32_PLAIN)
+                geq[i] = T(L::w[i]) * rho * (T(1) + X);
+            else
+                geq[i] = T(L::w[i]) * (drho + rho * X);
+        }
+
+        // effective relaxation time (Sec. 5)
+        T taue = T(m.tau);
+        if (SUB == LBM_SMAGORINSKY) {
+            T P[6] = {0, 0, 0, 0, 0, 0};  // xx yy zz xy xz yz
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                T fn = f[i] - geq[i];
+                const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i];
+                if (cx) P[0] += fn;
+                if (cy) P[1] += fn;
+                if (cz) P[2] += fn;
+                if (cx * cy) P[3] += T(cx * cy) * fn;
+                if (cx * cz) P[4] += T(cx * cz) * fn;
+                if (cy * cz) P[5] += T(cy * cz) * fn;
+            }
+            T PP = P[0] * P[0] + P[1] * P[1] + P[2] * P[2] + T(2) * (P[3] * P[3] + P[4] * P[4] + P[5] * P[5]);
+            T nP = sqrt(T(2) * PP);
+            T cm = T(m.cmodel);
+            taue = T(0.5) * (taue + sqrt(taue * taue + T(18) * cm * cm * nP * ir));
+        } else if (SUB == LBM_WALE) {
+            // velocity gradient g_ab = D_b v_a of the post-streaming field
+            const T* __restrict__ vn = (const T*)m.vn;
+            T g[3][3];
+            const int nz = m.nz;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                int xp = x, xm = x, yp = y, ym = y, zp = z, zm = z;
+                if (b == 0) { xp = wrapi(x + 1, nx); xm = wrapi(x - 1, nx); }
+                if (b == 1) { yp = y + 1; ym = y - 1; }
+                if (b == 2) { zp = wrapi(z + 1, nz); zm = wrapi(z - 1, nz); }
+                bool okp = true, okm = true;
+                if (b == 1) {
+                    if (m.walls) { okp = yp < ny; okm = ym >= 0; }
+                    else { yp = wrapi(yp, ny); ym = wrapi(ym, ny); }
+                }
+                const int cp = xp + nx * (yp + ny * zp), cm = xm + nx * (ym + ny * zm);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    T vp = okp ? vn[(size_t)a * N + cp] : T(0);
+                    T vm = okm ? vn[(size_t)a * N + cm] : T(0);
+                    g[a][b] = T(0.5) * (vp - vm);
+                }
+            }
+            T g2[3][3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) g2[a][b] = g[a][0] * g[0][b] + g[a][1] * g[1][b] + g[a][2] * g[2][b];
+            const T tr = g2[0][0] + g2[1][1] + g2[2][2];
+            T SS = 0, SdSd = 0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    T S = T(0.5) * (g[a][b] + g[b][a]);
+                    T Sd = T(0.5) * (g2[a][b] + g2[b][a]) - (a == b ? tr / T(3) : T(0));
+                    SS += S * S;
+                    SdSd += Sd * Sd;
+                }
+            T den = pow(SS, T(2.5)) + pow(SdSd, T(1.25));
+            T cm = T(m.cmodel);
+            T nut = den > T(0) ? cm * cm * pow(SdSd, T(1.5)) / den : T(0);
+            taue = taue + T(3) * nut;
+        }
+        const T om = T(1) / taue;
+
+        // body force, F/rho velocity increment, predictor velocity
+        T F[3] = {T(m.fprof[y]), 0, 0};
+        if (m.drag != 0.0) {
+#pragma unroll
+            for (int a = 0; a < D; ++a) F[a] -= T(m.drag) * rho * u[a];
+        }
+        T du[3] = {0, 0, 0}, us[3] = {0, 0, 0};
+        T dd = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            du[a] = F[a] * ir;
+            us[a] = u[a] + du[a];
+            dd += du[a] * (us[a] + u[a]);
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            T cd = T(L::cx[i]) * du[0] + T(L::cy[i]) * du[1] + (D == 3 ? T(L::cz[i]) * du[2] : T(0));
+            T cs = T(L::cx[i]) * (us[0] + u[0]) + T(L::cy[i]) * (us[1] + u[1]) +
+                   (D == 3 ? T(L::cz[i]) * (us[2] + u[2]) : T(0));
+            T out = f[i] - om * (f[i] - geq[i]) + dfeq<T>(T(L::w[i]), rho, cd, cs, dd);
+            gd[(size_t)i * N + cell] = out;
+        }
+        if (MODE == 2) {
+            ((T*)m.rho)[cell] = drho;
+#pragma unroll
+            for (int a = 0; a < D; ++a) ((T*)m.vs)[(size_t)a * N + cell] = us[a];
+        }
+        if (MODE == 1 && SUB != LBM_WALE) {  // (with WALE, k_moments wrote v^n)
+#pragma unroll
+            for (int a = 0; a < D; ++a) ((T*)m.vn)[(size_t)a * N + cell] = u[a];
+        }
+        if (MODE >= 1) {
+            st[0] = (double)drho;
+#pragma unroll
+            for (int a = 0; a < D; ++a) st[1 + a] = (double)(rho * u[a]);
+        }
+    }
+    if (MODE >= 1) {
+        block_sum<4>(st, lds);
+        if (threadIdx.x == 0) {
+            double* p = m.part_stats + (size_t)wk.y * 4;
+            p[0] = st[0]; p[1] = st[1]; p[2] = st[2]; p[3] = st[3];
+        }
+    }
+    const unsigned long long anybad = __ballot(bad);
+    if (anybad && (threadIdx.x & 63) == 0) atomicOr(&m.ctl->flags, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Post-streaming density and velocity of the current state (stream only,
+// including a pending correction): used for WALE gradients and lbm_fields.
+// ---------------------------------------------------------------------------
+template <int LAT, typename T, int PREC, bool TO>
+__global__ __launch_bounds__(kBlock) void k_moments(const DevMember* __restrict__ mems,
+                                                    const int2* __restrict__ work, int flip,
+                                                    double* __restrict__ rho_out)
+{
+    using L = Lat<LAT>;
+    const int2 wk = work[blockIdx.x];
+    const DevMember& m = mems[wk.x];
+    const int N = m.N, nx = m.nx, ny = m.ny;
+    const int cell = wk.y * kBlock + threadIdx.x;
+    if (cell >= N) return;
+    const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
+    const T* gs = (const T*)m.g[m.parity ^ flip];
+    T f[L::Q];
+    gather<LAT, T, TO>(m, gs, x, y, z, cell, f);
+    T drho, j[3] = {0, 0, 0};
+    moments<LAT, T, PREC>(f, drho, j);
+    const T rho = T(1) + drho;
+#pragma unroll
+    for (int a = 0; a < L::D; ++a) ((T*)m.vn)[(size_t)a * N + cell] = j[a] / rho;
+    if (rho_out) rho_out[cell] = (double)rho;
+}
+
+// ---------------------------------------------------------------------------
+// Helpers for stencils on scalar fields with the filter/derivative boundary
+// rule: periodic wrap, zero outside the domain on the wall axis.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T fld(const T* __restrict__ u, int x, int y, int z, int nx, int ny, int nz, int walls)
+{
+    x = wrapi(x, nx);
+    z = wrapi(z, nz);
+    if (walls) {
+        if (y < 0 || y >= ny) return T(0);
+    } else
+        y = wrapi(y, ny);
+    return u[x + nx * (y + ny * z)];
+}
+
+// Central-difference curl of a D-component field at (x,y,z) (2-D: scalar).
+template <int D, typename T>
+__device__ __forceinline__ void curl_at(const T* __restrict__ v, size_t N, int x, int y, int z, int nx, int ny,
+                                        int nz, int walls, T* w)
+{
+    const T* vx = v;
+    const T* vy = v + N;
+    if (D == 2) {
+        w[0] = T(0.5) * (fld(vy, x + 1, y, z, nx, ny, nz, walls) - fld(vy, x - 1, y, z, nx, ny, nz, walls)) -
+               T(0.5) * (fld(vx, x, y + 1, z, nx, ny, nz, walls) - fld(vx, x, y - 1, z, nx, ny, nz, walls));
+    } else {
+        const T* vz = v + 2 * N;
+        T dyvz = T(0.5) * (fld(vz, x, y + 1, z, nx, ny, nz, walls) - fld(vz, x, y - 1, z, nx, ny, nz, walls));
+        T dzvy = T(0.5) * (fld(vy, x, y, z + 1, nx, ny, nz, walls) - fld(vy, x, y, z - 1, nx, ny, nz, walls));
+        T dzvx = T(0.5) * (fld(vx, x, y, z + 1, nx, ny, nz, walls) - fld(vx, x, y, z - 1, nx, ny, nz, walls));
+        T dxvz = T(0.5) * (fld(vz, x + 1, y, z, nx, ny, nz, walls) - fld(vz, x - 1, y, z, nx, ny, nz, walls));
+        T dxvy = T(0.5) * (fld(vy, x + 1, y, z, nx, ny, nz, walls) - fld(vy, x - 1, y, z, nx, ny, nz, walls));
+        T dyvx = T(0.5) * (fld(vx, x, y + 1, z, nx, ny, nz, walls) - fld(vx, x, y - 1, z, nx, ny, nz, walls));
+        w[0] = dyvz - dzvy;
+        w[1] = dzvx - dxvz;
+        w[2] = dxvy - dyvx;
+    }
+}
+
+// K2a: w = curl v* into W_0.
+template <int LAT, typename T>
+__global__ __launch_bounds__(kBlock) void k_curl(const DevMember* __restrict__ mems, const int2* __restrict__ work)
+{
+    using L = Lat<LAT>;
+    const int2 wk = work[blockIdx.x];
+    const DevMember& m = mems[wk.x];
+    if (!m.prm->has_z) return;
+    const int N = m.N, nx = m.nx, ny = m.ny, nz = m.nz;
+    const int cell = wk.y * kBlock + threadIdx.x;
+    if (cell >= N) return;
+    const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
+    T w[3];
+    curl_at<L::D, T>((const T*)m.vs, (size_t)N, x, y, z, nx, ny, nz, m.walls, w);
+#pragma unroll
+    for (int a = 0; a < L::NC; ++a) ((T*)m.W)[(size_t)a * N + cell] = w[a];
+}
+
+// Binomial filter B = (x)_a [1,2,1]/4 of one scalar field at (x,y,z).
+template <int D, typename T>
+__device__ __forceinline__ T binom_at(const T* __restrict__ u, int x, int y, int z, int nx, int ny, int nz, int walls)
+{
+    const int xm = wrapi(x - 1, nx), xp = wrapi(x + 1, nx);
+    T acc = 0;
+    const int zr = D == 3 ? 1 : 0;
+#pragma unroll
+    for (int oz = -zr; oz <= zr; ++oz) {
+        const int zz = D == 3 ? wrapi(z + oz, nz) : 0;
+        T sy = 0;
+#pragma unroll
+        for (int oy = -1; oy <= 1; ++oy) {
+            int yy = y + oy;
+            T r = 0;
+            if (walls && (yy < 0 || yy >= ny)) {
+                r = T(0);
+            } else {
+                yy = wrapi(yy, ny);
+                const T* row = u + (size_t)nx * (yy + (size_t)ny * zz);
+                r = T(0.25) * (row[xm] + T(2) * row[x] + row[xp]);
+            }
+            sy += (oy == 0 ? T(0.5) : T(0.25)) * r;
+        }
+        acc += (D == 3 ? (oz == 0 ? T(0.5) : T(0.25)) : T(1)) * sy;
+    }
+    return acc;
+}
+
+// K2b: P_j = B P_{j-1} (P_0 = v*) for j <= jv and W_j = B W_{j-1} for j <= jw.
+template <int LAT, typename T>
+__global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ mems, const int2* __restrict__ work,
+                                                  int j)
+{
+    using L = Lat<LAT>;
+    constexpr int D = L::D, NC = L::NC;
+    const int2 wk = work[blockIdx.x];
+    const DevMember& m = mems[wk.x];
+    const DevParam* prm = m.prm;
+    const bool dov = j <= prm->jv, dow = prm->has_z && j <= prm->jw;
+    if (!dov && !dow) return;
+    const int N = m.N, nx = m.nx, ny = m.ny, nz = m.nz;
+    const int cell = wk.y * kBlock + threadIdx.x;
+    if (cell >= N) return;
+    const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
+    const size_t sN = (size_t)N;
+    if (dov) {
+        const T* src = j == 1 ? (const T*)m.vs : (const T*)m.P + (size_t)(j - 2) * D * sN;
+        T* dst = (T*)m.P + (size_t)(j - 1) * D * sN;
+#pragma unroll
+        for (int a = 0; a < D; ++a) dst[a * sN + cell] = binom_at<D, T>(src + a * sN, x, y, z, nx, ny, nz, m.walls);
+    }
+    if (dow) {
+        const T* src = (const T*)m.W + (size_t)(j - 1) * NC * sN;
+        T* dst = (T*)m.W + (size_t)j * NC * sN;
+#pragma unroll
+        for (int a = 0; a < NC; ++a) dst[a * sN + cell] = binom_at<D, T>(src + a * sN, x, y, z, nx, ny, nz, m.walls);
+    }
+}
+
+// Sensitivity of a Z QoI: curl^T psi with psi = sum_j c[j] W_j, evaluated
+// from neighbour values (2-D: (D_y psi, -D_x psi); 3-D: curl psi).
+template <int D, typename T>
+__device__ __forceinline__ void zsens(const T* __restrict__ W, size_t N, int jw, const double* c, int x, int y,
+                                      int z, int nx, int ny, int nz, int walls, T* V)
+{
+    constexpr int NC = D == 2 ? 1 : 3;
+    auto psi = [&](int a, int xx, int yy, int zz) -> T {
+        T s = 0;
+        for (int j = 0; j <= jw; ++j)
+            if (c[j] != 0.0) s += T(c[j]) * fld(W + ((size_t)j * NC + a) * N, xx, yy, zz, nx, ny, nz, walls);
+        return s;
+    };
+    if (D == 2) {
+        V[0] = T(0.5) * (psi(0, x, y + 1, z) - psi(0, x, y - 1, z));
+        V[1] = -T(0.5) * (psi(0, x + 1, y, z) - psi(0, x - 1, y, z));
+    } else {
+        T dy2 = T(0.5) * (psi(2, x, y + 1, z) - psi(2, x, y - 1, z));
+        T dz1 = T(0.5) * (psi(1, x, y, z + 1) - psi(1, x, y, z - 1));
+        T dz0 = T(0.5) * (psi(0, x, y, z + 1) - psi(0, x, y, z - 1));
+        T dx2 = T(0.5) * (psi(2, x + 1, y, z) - psi(2, x - 1, y, z));
+        T dx1 = T(0.5) * (psi(1, x + 1, y, z) - psi(1, x - 1, y, z));
+        T dy0 = T(0.5) * (psi(0, x, y + 1, z) - psi(0, x, y - 1, z));
+        V[0] = dy2 - dz1;
+        V[1] = dz0 - dx2;
+        V[2] = dx1 - dy0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K2c: per-cell QoIs, sensitivities and Gram products, FP64 partial sums per
+// workgroup.  Workgroups cover one y row (2-D) or one y plane (3-D) each, so
+// the mean-profile partial sums stay separated by y.
+// Partial layout: q_sa[nsa], G_sa[nsa(nsa+1)/2], then (with MP QoIs)
+// U = sum v*_x and P_s = sum V_s,x.
+// ---------------------------------------------------------------------------
+template <int LAT, typename T, int MAXSA>
+__global__ __launch_bounds__(kBlock) void k_reduce(const DevMember* __restrict__ mems, const int2* __restrict__ work)
+{
+    using L = Lat<LAT>;
+    constexpr int D = L::D, NC = L::NC;
+    constexpr int NG = MAXSA * (MAXSA + 1) / 2;
+    constexpr int NV = MAXSA + NG + 1 + MAXSA;
+    __shared__ double lds[NV * (kBlock / 64)];
+    const int2 wk = work[blockIdx.x];
+    const DevMember& m = mems[wk.x];
+    const DevParam* __restrict__ prm = m.prm;
+    const int N = m.N, nx = m.nx, ny = m.ny, nz = m.nz;
+    const int y = wk.y / m.nbx2, bx = wk.y % m.nbx2;
+    const int plane = nx * nz;
+    const int nsa = prm->nsa, jv = prm->jv, jw = prm->jw;
+    const bool hasmp = prm->nmp > 0;
+    const size_t sN = (size_t)N;
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0;
+    for (int c = 0; c < m.cpt2; ++c) {
+        const int p = (bx * m.cpt2 + c) * kBlock + threadIdx.x;
+        if (p >= plane) break;
+        const int x = p % nx, z = p / nx;
+        const int cell = x + nx * (y + ny * z);
+        // powers of B applied to v* at this cell
+        T pv[kMaxPow + 1][D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) pv[0][a] = ((const T*)m.vs)[a * sN + cell];
+#pragma unroll
+        for (int jj = 1; jj <= kMaxPow; ++jj)
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+                pv[jj][a] = jj <= jv ? ((const T*)m.P)[((size_t)(jj - 1) * D + a) * sN + cell] : T(0);
+        T V[MAXSA][D];
+#pragma unroll
+        for (int s = 0; s < MAXSA; ++s) {
+#pragma unroll
+            for (int a = 0; a < D; ++a) V[s][a] = 0;
+            if (s >= nsa) continue;
+            const double* r = prm->r[s];
+            const double* rr = prm->rr[s];
+            double q = 0;
+            if (prm->sa_kind[s] == 0) {
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    T rv = T(r[0]) * pv[0][a] + T(r[1]) * pv[1][a] + T(r[2]) * pv[2][a];
+                    q += 0.5 * (double)(rv * rv);
+                    T vv = 0;
+#pragma unroll
+                    for (int jj = 0; jj <= kMaxPow; ++jj) vv += T(rr[jj]) * pv[jj][a];
+                    V[s][a] = vv;
+                }
+            } else {
+                const T* Wc = (const T*)m.W;
+#pragma unroll
+                for (int a = 0; a < NC; ++a) {
+                    T rw = 0;
+#pragma unroll
+                    for (int jj = 0; jj <= 2; ++jj)
+                        if (jj <= jw && r[jj] != 0.0) rw += T(r[jj]) * Wc[((size_t)jj * NC + a) * sN + cell];
+                    q += 0.5 * (double)(rw * rw);
+                }
+                zsens<D, T>(Wc, sN, jw, rr, x, y, z, nx, ny, nz, m.walls, V[s]);
+            }
+            acc[s] += q;
+        }
+        int g = 0;
+#pragma unroll
+        for (int s = 0; s < MAXSA; ++s)
+#pragma unroll
+            for (int t2 = s; t2 < MAXSA; ++t2, ++g) {
+                T d = 0;
+#pragma unroll
+                for (int a = 0; a < D; ++a) d += V[s][a] * V[t2][a];
+                acc[MAXSA + g] += (double)d;
+            }
+        if (hasmp) {
+            acc[MAXSA + NG] += (double)pv[0][0];
+#pragma unroll
+            for (int s = 0; s < MAXSA; ++s) acc[MAXSA + NG + 1 + s] += (double)V[s][0];
+        }
+    }
+    block_sum<NV>(acc, lds);
+    if (threadIdx.x == 0) {
+        double* out = m.part_to + (size_t)wk.y * m.npart;
+        int o = 0;
+        for (int s = 0; s < nsa; ++s) out[o++] = acc[s];
+        for (int s = 0; s < nsa; ++s)
+            for (int t2 = s; t2 < nsa; ++t2) out[o++] = acc[MAXSA + s * MAXSA - s * (s - 1) / 2 + (t2 - s)];
+        if (hasmp) {
+            out[o++] = acc[MAXSA + NG];
+            for (int s = 0; s < nsa; ++s) out[o++] = acc[MAXSA + NG + 1 + s];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and Box-Muller normals.
+// Counter (block, step_lo, step_hi, "LRS1"), key (seed_lo, seed_hi).
+// ---------------------------------------------------------------------------
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+__device__ inline void lrs_normals(unsigned long long seed, long long step, int n, double* z)
+{
+    for (int blk = 0; 4 * blk < n; ++blk) {
+        uint32_t c[4] = {(uint32_t)blk, (uint32_t)(unsigned long long)step,
+                         (uint32_t)((unsigned long long)step >> 32), 0x4C525331u};
+        philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+        for (int p = 0; p < 2; ++p) {
+            const double u1 = ((double)c[2 * p] + 0.5) * 2.3283064365386963e-10;
+            const double u2 = ((double)c[2 * p + 1] + 0.5) * 2.3283064365386963e-10;
+            const double rad = sqrt(-2.0 * log(u1));
+            double sn, cs;
+            sincospi(2.0 * u2, &sn, &cs);
+            const int k = 4 * blk + 2 * p;
+            if (k < n) z[k] = rad * cs;
+            if (k + 1 < n) z[k + 1] = rad * sn;
+        }
+    }
+}
+
+__global__ void k_philox_test(const uint32_t* in, uint32_t* out, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t c[4] = {in[6 * i], in[6 * i + 1], in[6 * i + 2], in[6 * i + 3]};
+    philox4x32_10(c, in[6 * i + 4], in[6 * i + 5]);
+    for (int k = 0; k < 4; ++k) out[4 * i + k] = c[k];
+}
+
+__global__ void k_normals_test(unsigned long long seed, long long step0, int nsteps, int n, double* out)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsteps) return;
+    double z[kMaxQ];
+    lrs_normals(seed, step0 + s, n, z);
+    for (int k = 0; k < n; ++k) out[(size_t)s * n + k] = z[k];
+}
+
+// ---------------------------------------------------------------------------
+// K3: one workgroup per member.  Fixed-order sums of the partials, the QoI
+// vector and Gram matrix, dQ, the Cholesky solve G beta = dQ, gamma, the
+// per-step record and the coefficients of the dv build.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ mems, const int* __restrict__ work)
+{
+    __shared__ double red[4 * (kBlock / 64) * 8];
+    __shared__ double sflat[kMaxSA + kMaxSA * (kMaxSA + 1) / 2 + 4];
+    __shared__ double G[kMaxQ * kMaxQ];
+    __shared__ double q[kMaxQ];
+    __shared__ double beta[kMaxQ];
+    const DevMember& m = mems[work[blockIdx.x]];
+    const DevParam* __restrict__ prm = m.prm;
+    DevCtl* ctl = m.ctl;
+    const int tid = threadIdx.x;
+    const int nq = prm->nq, nsa = prm->nsa, nmp = prm->nmp;
+    const int ny = m.ny;
+    const int nblk = ny * m.nbx2;
+    const int nflat = nsa + nsa * (nsa + 1) / 2;
+    const int np = m.npart;
+
+    // (a) mass and momentum of the post-streaming state
+    {
+        double v[4] = {0, 0, 0, 0};
+        for (int b = tid; b < m.nb1; b += kBlock)
+            for (int k = 0; k < 4; ++k) v[k] += m.part_stats[(size_t)b * 4 + k];
+        block_sum<4>(v, red);
+        if (tid == 0) {
+            sflat[kMaxSA + kMaxSA * (kMaxSA + 1) / 2 + 0] = v[0];
+            sflat[kMaxSA + kMaxSA * (kMaxSA + 1) / 2 + 1] = v[1];
+            sflat[kMaxSA + kMaxSA * (kMaxSA + 1) / 2 + 2] = v[2];
+            sflat[kMaxSA + kMaxSA * (kMaxSA + 1) / 2 + 3] = v[3];
+        }
+    }
+    // (b) QoI and Gram sums over all workgroups of the reduce
+    for (int k0 = 0; k0 < nflat; k0 += 8) {
+        double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int b = tid; b < nblk; b += kBlock)
+            for (int k = 0; k < 8; ++k)
+                if (k0 + k < nflat) v[k] += m.part_to[(size_t)b * np + k0 + k];
+        block_sum<8>(v, red);
+        if (tid == 0)
+            for (int k = 0; k < 8; ++k)
+                if (k0 + k < nflat) sflat[k0 + k] = v[k];
+    }
+    __syncthreads();
+    // (c) mean-profile QoIs and mixed Gram entries from the y profiles
+    if (tid < kMaxQ) q[tid] = 0.0;
+    for (int k = tid; k < kMaxQ * kMaxQ; k += kBlock) G[k] = 0.0;
+    __syncthreads();
+    if (tid == 0) {
+        int g = nsa;
+        for (int s = 0; s < nsa; ++s) {
+            q[prm->sa_slot[s]] = sflat[s];
+            for (int t = s; t < nsa; ++t, ++g) {
+                G[prm->sa_slot[s] * nq + prm->sa_slot[t]] = sflat[g];
+                G[prm->sa_slot[t] * nq + prm->sa_slot[s]] = sflat[g];
+            }
+        }
+    }
+    if (nmp > 0) {
+        // pairs (j, c): c = 0 -> q_mp_j = sum_y w_j U(y); c = 1+s -> G[mp_j, sa_s] = sum_y w_j P_s(y)
+        const int npair = nmp * (1 + nsa);
+        for (int pr = tid; pr < npair; pr += kBlock) {
+            const int jm = pr / (1 + nsa), c = pr % (1 + nsa);
+            const double* w = m.bandw + (size_t)prm->mp_band[jm] * ny;
+            double acc = 0;
+            for (int yy = 0; yy < ny; ++yy) {
+                double py = 0;
+                for (int b = 0; b < m.nbx2; ++b) py += m.part_to[((size_t)yy * m.nbx2 + b) * np + nflat + c];
+                acc += w[yy] * py;
+            }
+            const int uj = prm->mp_slot[jm];
+            if (c == 0)
+                q[uj] = acc;
+            else {
+                const int us = prm->sa_slot[c - 1];
+                G[uj * nq + us] = acc;
+                G[us * nq + uj] = acc;
+            }
+        }
+        for (int pr = tid; pr < nmp * nmp; pr += kBlock) {
+            const int a = pr / nmp, b = pr % nmp;
+            G[prm->mp_slot[a] * nq + prm->mp_slot[b]] = prm->gmp[a * kMaxQ + b];
+        }
+    }
+    __syncthreads();
+
+    // (d) dQ, solve, record (serial: nq <= 16)
+    if (tid == 0) {
+        const long long step = ctl->step;
+        double dq[kMaxQ], gam[kMaxQ];
+        for (int k = 0; k < nq; ++k) { dq[k] = 0; gam[k] = 0; beta[k] = 0; }
+        if (step >= prm->spinup && prm->mode == LBM_CLOSURE_TRACK) {
+            if (step < prm->nref)
+                for (int k = 0; k < nq; ++k) dq[k] = prm->qref[(size_t)step * nq + k] - q[k];
+        } else if (step >= prm->spinup && prm->mode == LBM_CLOSURE_LRS) {
+            if (!ctl->s_set) {
+                for (int k = 0; k < nq; ++k) ctl->s[k] = prm->have_scale ? prm->scale[k] : (q[k] != 0.0 ? fabs(q[k]) : 1.0);
+                ctl->s_set = 1;
+            }
+            double z[kMaxQ], eta[kMaxQ], x[kMaxQ + 1];
+            lrs_normals(prm->seed, step, nq, z);
+            for (int k = 0; k < nq; ++k) {
+                double e = prm->mu[k];
+                for (int j = 0; j <= k; ++j) e += prm->L[k * kMaxQ + j] * z[j];
+                eta[k] = e;
+                x[k] = q[k] / ctl->s[k];
+            }
+            x[nq] = 1.0;
+            for (int k = 0; k < nq; ++k) {
+                double zh = eta[k];
+                for (int i = 0; i <= nq; ++i) zh += x[i] * prm->C[i * kMaxQ + k];
+                dq[k] = ctl->s[k] * zh - q[k];
+            }
+        }
+        // Cholesky G = L L^T; singular when a pivot <= 1e-14 max diag
+        double Lc[kMaxQ * kMaxQ];
+        double mx = 0;
+        for (int k = 0; k < nq; ++k) mx = fmax(mx, G[k * nq + k]);
+        int sg = !(mx > 0);
+        for (int jj = 0; jj < nq && !sg; ++jj) {
+            double s = G[jj * nq + jj];
+            for (int k = 0; k < jj; ++k) s -= Lc[jj * kMaxQ + k] * Lc[jj * kMaxQ + k];
+            if (!(s > 1e-14 * mx)) { sg = 1; break; }
+            const double d = sqrt(s);
+            Lc[jj * kMaxQ + jj] = d;
+            for (int i = jj + 1; i < nq; ++i) {
+                double t = G[i * nq + jj];
+                for (int k = 0; k < jj; ++k) t -= Lc[i * kMaxQ + k] * Lc[jj * kMaxQ + k];
+                Lc[i * kMaxQ + jj] = t / d;
+            }
+        }
+        if (!sg) {
+            // beta = G^-1 dQ by forward and back substitution
+            double yv[kMaxQ];
+            for (int i = 0; i < nq; ++i) {
+                double t = dq[i];
+                for (int k = 0; k < i; ++k) t -= Lc[i * kMaxQ + k] * yv[k];
+                yv[i] = t / Lc[i * kMaxQ + i];
+            }
+            for (int i = nq - 1; i >= 0; --i) {
+                double t = yv[i];
+                for (int k = i + 1; k < nq; ++k) t -= Lc[k * kMaxQ + i] * beta[k];
+                beta[i] = t / Lc[i * kMaxQ + i];
+            }
+            // gamma_k = dQ_k (G^-1)_kk, (G^-1)_kk = sum_m ((L^-1)_mk)^2
+            for (int k = 0; k < nq; ++k) {
+                double e[kMaxQ], s2 = 0;
+                for (int i = 0; i < nq; ++i) {
+                    double t = i == k ? 1.0 : 0.0;
+                    for (int j2 = 0; j2 < i; ++j2) t -= Lc[i * kMaxQ + j2] * e[j2];
+                    e[i] = i < k ? 0.0 : t / Lc[i * kMaxQ + i];
+                    s2 += e[i] * e[i];
+                }
+                gam[k] = dq[k] * s2;
+            }
+        } else {
+            for (int k = 0; k < nq; ++k) beta[k] = 0;
+        }
+        // coefficients of the dv build: sum over E QoIs of beta R R for v,
+        // over Z QoIs for curl v
+        for (int jj = 0; jj <= kMaxPow; ++jj) {
+            double a = 0, b = 0;
+            for (int s = 0; s < nsa; ++s) {
+                const double bs = beta[prm->sa_slot[s]];
+                if (prm->sa_kind[s] == 0) a += bs * prm->rr[s][jj];
+                else b += bs * prm->rr[s][jj];
+            }
+            ctl->cv[jj] = a;
+            ctl->cw[jj] = b;
+        }
+        // record
+        lbm_qoi_rec* rec = m.recs + (size_t)(step % m.rec_cap);
+        const double* st = sflat + kMaxSA + kMaxSA * (kMaxSA + 1) / 2;
+        rec->step = step;
+        rec->flags = (ctl->flags & 1) | (sg ? 2 : 0);
+        rec->nq = nq;
+        rec->mass = (double)m.N + st[0];
+        rec->mom[0] = st[1];
+        rec->mom[1] = st[2];
+        rec->mom[2] = st[3];
+        rec->diag_e = 0;
+        rec->diag_z = 0;
+        for (int k = 0; k < kMaxQ; ++k) {
+            rec->q[k] = k < nq ? q[k] : 0.0;
+            rec->dq[k] = k < nq ? dq[k] : 0.0;
+            rec->gamma[k] = k < nq ? gam[k] : 0.0;
+        }
+        ctl->step = step + 1;
+    }
+    __syncthreads();
+    // (e) mean-profile part of dv: cmp(y) = sum_j beta_mp_j w_j(y)
+    for (int yy = tid; yy < ny; yy += kBlock) {
+        double c = 0;
+        for (int jm = 0; jm < nmp; ++jm) c += beta[prm->mp_slot[jm]] * m.bandw[(size_t)prm->mp_band[jm] * ny + yy];
+        m.cmp[yy] = c;
+    }
+}
+
+// K4: dv = sum_j cv_j B^j v* + curl^T(sum_j cw_j B^j w) + e_x cmp(y).
+template <int LAT, typename T>
+__global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ mems, const int2* __restrict__ work)
+{
+    using L = Lat<LAT>;
+    constexpr int D = L::D;
+    const int2 wk = work[blockIdx.x];
+    const DevMember& m = mems[wk.x];
+    const DevParam* __restrict__ prm = m.prm;
+    const int N = m.N, nx = m.nx, ny = m.ny, nz = m.nz;
+    const int cell = wk.y * kBlock + threadIdx.x;
+    if (cell >= N) return;
+    const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
+    const size_t sN = (size_t)N;
+    const double* cv = m.ctl->cv;
+    const double* cw = m.ctl->cw;
+    T out[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        T s = T(cv[0]) * ((const T*)m.vs)[a * sN + cell];
+        for (int jj = 1; jj <= prm->jv; ++jj) s += T(cv[jj]) * ((const T*)m.P)[((size_t)(jj - 1) * D + a) * sN + cell];
+        out[a] = s;
+    }
+    if (prm->has_z) {
+        T V[3] = {0, 0, 0};
+        zsens<D, T>((const T*)m.W, sN, prm->jw, cw, x, y, z, nx, ny, nz, m.walls, V);
+#pragma unroll
+        for (int a = 0; a < D; ++a) out[a] += V[a];
+    }
+    if (prm->nmp > 0) out[0] += T(m.cmp[y]);
+#pragma unroll
+    for (int a = 0; a < D; ++a) ((T*)m.dv)[a * sN + cell] = out[a];
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics of plain runs: E and Z of the post-streaming velocity.
+// ---------------------------------------------------------------------------
+template <int LAT, typename T>
+__global__ __launch_bounds__(kBlock) void k_diag(const DevMember* __restrict__ mems, const int2* __restrict__ work)
+{
+    using L = Lat<LAT>;
+    constexpr int D = L::D;
+    __shared__ double lds[2 * (kBlock / 64)];
+    const int2 wk = work[blockIdx.x];
+    const DevMember& m = mems[wk.x];
+    const int N = m.N, nx = m.nx, ny = m.ny, nz = m.nz;
+    const int cell = wk.y * kBlock + threadIdx.x;
+    double v[2] = {0, 0};
+    if (cell < N) {
+        const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
+        const T* vn = (const T*)m.vn;
+        double e = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const double u = (double)vn[(size_t)a * N + cell];
+            e += 0.5 * u * u;
+        }
+        T w[3];
+        curl_at<D, T>(vn, (size_t)N, x, y, z, nx, ny, nz, m.walls, w);
+        double zz = 0;
+#pragma unroll
+        for (int a = 0; a < L::NC; ++a) zz += 0.5 * (double)w[a] * (double)w[a];
+        v[0] = e;
+        v[1] = zz;
+    }
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) {
+        m.part_diag[(size_t)wk.y * 2] = v[0];
+        m.part_diag[(size_t)wk.y * 2 + 1] = v[1];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fin_diag(const DevMember* __restrict__ mems, const int* __restrict__ work)
+{
+    __shared__ double red[6 * (kBlock / 64)];
+    const DevMember& m = mems[work[blockIdx.x]];
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < m.nb1; b += kBlock) {
+        for (int k = 0; k < 4; ++k) v[k] += m.part_stats[(size_t)b * 4 + k];
+        v[4] += m.part_diag[(size_t)b * 2];
+        v[5] += m.part_diag[(size_t)b * 2 + 1];
+    }
+    block_sum<6>(v, red);
+    if (threadIdx.x == 0) {
+        DevCtl* ctl = m.ctl;
+        const long long step = ctl->step;
+        lbm_qoi_rec* rec = m.recs + (size_t)(step % m.rec_cap);
+        rec->step = step;
+        rec->flags = ctl->flags & 1;
+        rec->nq = 0;
+        rec->mass = (double)m.N + v[0];
+        rec->mom[0] = v[1];
+        rec->mom[1] = v[2];
+        rec->mom[2] = v[3];
+        rec->diag_e = v[4];
+        rec->diag_z = v[5];
+        for (int k = 0; k < kMaxQ; ++k) { rec->q[k] = 0; rec->dq[k] = 0; rec->gamma[k] = 0; }
+        ctl->step = step + 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// State access kernels.
+// ---------------------------------------------------------------------------
+template <int LAT, typename T, int PREC>
+__global__ void k_init(const DevMember* __restrict__ mems, int flip, const double* __restrict__ rho0,
+                       const double* __restrict__ u0)
+{
+    using L = Lat<LAT>;
+    const DevMember& m = mems[0];
+    const int N = m.N;
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= N) return;
+    T* g = (T*)m.g[m.parity ^ flip];
+    const double r = rho0 ? rho0[cell] : 1.0;
+    double u[3] = {0, 0, 0}, uu = 0;
+    for (int a = 0; a < L::D; ++a) { u[a] = u0[(size_t)a * N + cell]; uu += u[a] * u[a]; }
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const double cu = L::cx[i] * u[0] + L::cy[i] * u[1] + L::cz[i] * u[2];
+        const double X = 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
+        const double feq = L::w[i] * r * (1.0 + X);
+        g[(size_t)i * N + cell] = PREC == LBM_FP32_PLAIN ? (T)feq : (T)(L::w[i] * ((r - 1.0) + r * X));
+    }
+    if (m.has_to) {
+        ((T*)m.rho)[cell] = 0;
+        for (int a = 0; a < L::D; ++a) {
+            ((T*)m.vs)[(size_t)a * N + cell] = 0;
+            ((T*)m.dv)[(size_t)a * N + cell] = 0;
+        }
+    }
+}
+
+template <int LAT, typename T, int PREC, bool TO>
+__global__ void k_get_pop(const DevMember* __restrict__ mems, int flip, double* __restrict__ f)
+{
+    using L = Lat<LAT>;
+    const DevMember& m = mems[0];
+    const int N = m.N;
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= N) return;
+    const T* g = (const T*)m.g[m.parity ^ flip];
+    double r = 0, vs[3] = {0, 0, 0}, dv[3] = {0, 0, 0};
+    if (TO) {
+        r = 1.0 + (double)((const T*)m.rho)[cell];
+        for (int a = 0; a < L::D; ++a) {
+            vs[a] = (double)((const T*)m.vs)[(size_t)a * N + cell];
+            dv[a] = (double)((const T*)m.dv)[(size_t)a * N + cell];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        double v = (double)g[(size_t)i * N + cell] + (PREC == LBM_FP32_PLAIN ? 0.0 : L::w[i]);
+        if (TO) {
+            double cd = 0, cs = 0, dd = 0;
+            const int c[3] = {L::cx[i], L::cy[i], L::cz[i]};
+            for (int a = 0; a < L::D; ++a) {
+                cd += c[a] * dv[a];
+                cs += c[a] * (2 * vs[a] + dv[a]);
+                dd += dv[a] * (2 * vs[a] + dv[a]);
+            }
+            v += L::w[i] * r * (3 * cd + 4.5 * cd * cs - 1.5 * dd);
+        }
+        f[(size_t)i * N + cell] = v;
+    }
+}
+
+template <int LAT, typename T, int PREC>
+__global__ void k_set_pop(const DevMember* __restrict__ mems, int flip, const double* __restrict__ f)
+{
+    using L = Lat<LAT>;
+    const DevMember& m = mems[0];
+    const int N = m.N;
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= N) return;
+    T* g = (T*)m.g[m.parity ^ flip];
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i)
+        g[(size_t)i * N + cell] = (T)(f[(size_t)i * N + cell] - (PREC == LBM_FP32_PLAIN ? 0.0 : L::w[i]));
+    if (m.has_to) {
+        ((T*)m.rho)[cell] = 0;
+        for (int a = 0; a < L::D; ++a) {
+            ((T*)m.vs)[(size_t)a * N + cell] = 0;
+            ((T*)m.dv)[(size_t)a * N + cell] = 0;
+        }
+    }
+}
+
+// Pure streaming (no collision) into the other buffer.
+template <int LAT, typename T, bool TO>
+__global__ void k_stream_only(const DevMember* __restrict__ mems, int flip)
+{
+    using L = Lat<LAT>;
+    const DevMember& m = mems[0];
+    const int N = m.N, nx = m.nx, ny = m.ny;
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= N) return;
+    const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
+    T f[L::Q];
+    gather<LAT, T, TO>(m, (const T*)m.g[m.parity ^ flip], x, y, z, cell, f);
+    T* gd = (T*)m.g[m.parity ^ flip ^ 1];
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) gd[(size_t)i * N + cell] = f[i];
+}
+
+// Fold a pending SGS increment into the stored populations (own cell) and
+// clear it, so that a run can continue without the TO step.
+template <int LAT, typename T, int PREC>
+__global__ void k_flush(const DevMember* __restrict__ mems, int flip)
+{
+    using L = Lat<LAT>;
+    const DevMember& m = mems[0];
+    const int N = m.N;
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= N) return;
+    T* g = (T*)m.g[m.parity ^ flip];
+    const T r = T(1) + ((const T*)m.rho)[cell];
+    T vs[3] = {0, 0, 0}, dv[3] = {0, 0, 0};
+    for (int a = 0; a < L::D; ++a) {
+        vs[a] = ((const T*)m.vs)[(size_t)a * N + cell];
+        dv[a] = ((const T*)m.dv)[(size_t)a * N + cell];
+    }
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const int c[3] = {L::cx[i], L::cy[i], L::cz[i]};
+        T cd = 0, cs = 0, dd = 0;
+        for (int a = 0; a < L::D; ++a) {
+            cd += T(c[a]) * dv[a];
+            cs += T(c[a]) * (T(2) * vs[a] + dv[a]);
+            dd += dv[a] * (T(2) * vs[a] + dv[a]);
+        }
+        g[(size_t)i * N + cell] += dfeq<T>(T(L::w[i]), r, cd, cs, dd);
+    }
+    for (int a = 0; a < L::D; ++a) ((T*)m.dv)[(size_t)a * N + cell] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Launch wrappers (host side), one instantiation per lattice/precision/kind.
+// ---------------------------------------------------------------------------
+template <int LAT, typename T, int PREC>
+static void launch_step_group(const LaunchGroup& g, hipStream_t st, int flip, hipEvent_t* ev)
+{
+    const dim3 blk(kBlock);
+    if (g.nb1 == 0) return;
+    auto mark = [&](int k) {
+        if (ev) (void)hipEventRecord(ev[k], st);
+    };
+    mark(0);
+    if (g.substrate == LBM_WALE) {
+        if (g.mode == 2)
+            hipLaunchKernelGGL((k_moments<LAT, T, PREC, true>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip,
+                               (double*)nullptr);
+        else
+            hipLaunchKernelGGL((k_moments<LAT, T, PREC, false>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip,
+                               (double*)nullptr);
+    }
+#define LBM_STEP_SUB(SUB)                                                                                  \
+    do {                                                                                                   \
+        if (g.mode == 2)                                                                                   \
+            hipLaunchKernelGGL((k_step<LAT, T, PREC, SUB, 2>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
+        else if (g.mode == 1)                                                                              \
+            hipLaunchKernelGGL((k_step<LAT, T, PREC, SUB, 1>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_step<LAT, T, PREC, SUB, 0>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
+    } while (0)
+    if (g.substrate == LBM_SMAGORINSKY)
+        LBM_STEP_SUB(LBM_SMAGORINSKY);
+    else if (g.substrate == LBM_WALE)
+        LBM_STEP_SUB(LBM_WALE);
+    else
+        LBM_STEP_SUB(LBM_BGK);
+#undef LBM_STEP_SUB
+    mark(1);
+    if (g.mode == 2) {
+        if (g.any_z) hipLaunchKernelGGL((k_curl<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1);
+        mark(2);
+        for (int j = 1; j <= g.maxpow; ++j)
+            hipLaunchKernelGGL((k_binom<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, j);
+        mark(3);
+        if (g.maxsa <= 2)
+            hipLaunchKernelGGL((k_reduce<LAT, T, 2>), dim3(g.nbr), blk, 0, st, g.mems, g.workr);
+        else
+            hipLaunchKernelGGL((k_reduce<LAT, T, kMaxSA>), dim3(g.nbr), blk, 0, st, g.mems, g.workr);
+        mark(4);
+        hipLaunchKernelGGL(k_solve, dim3(g.nmem), blk, 0, st, g.mems, g.workm);
+        mark(5);
+        hipLaunchKernelGGL((k_apply<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1);
+        mark(6);
+    } else if (g.mode == 1) {
+        hipLaunchKernelGGL((k_diag<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1);
+        hipLaunchKernelGGL(k_fin_diag, dim3(g.nmem), blk, 0, st, g.mems, g.workm);
+        mark(2); mark(3); mark(4); mark(5); mark(6);
+    } else {
+        mark(2); mark(3); mark(4); mark(5); mark(6);
+    }
+}
+
+void launch_step(const LaunchGroup& g, hipStream_t st, int flip, hipEvent_t* ev)
+{
+    const int key = g.lattice * 3 + g.precision;
+    switch (key) {
+    case LBM_D2Q9 * 3 + LBM_FP32_SHIFTED: launch_step_group<LBM_D2Q9, float, LBM_FP32_SHIFTED>(g, st, flip, ev); break;
+    case LBM_D2Q9 * 3 + LBM_FP64: launch_step_group<LBM_D2Q9, double, LBM_FP64>(g, st, flip, ev); break;
+    case LBM_D2Q9 * 3 + LBM_FP32_PLAIN: launch_step_group<LBM_D2Q9, float, LBM_FP32_PLAIN>(g, st, flip, ev); break;
+    case LBM_D3Q19 * 3 + LBM_FP32_SHIFTED: launch_step_group<LBM_D3Q19, float, LBM_FP32_SHIFTED>(g, st, flip, ev); break;
+    case LBM_D3Q19 * 3 + LBM_FP64: launch_step_group<LBM_D3Q19, double, LBM_FP64>(g, st, flip, ev); break;
+    case LBM_D3Q19 * 3 + LBM_FP32_PLAIN: launch_step_group<LBM_D3Q19, float, LBM_FP32_PLAIN>(g, st, flip, ev); break;
+    }
+}
+
+template <int LAT, typename T, int PREC>
+static void launch_state_t(int op, const DevMember* dm, int N, bool has_to, int flip, hipStream_t st,
+                           const double* a, double* b)
+{
+    const dim3 blk(kBlock), grd((N + kBlock - 1) / kBlock);
+    switch (op) {
+    case OP_INIT: hipLaunchKernelGGL((k_init<LAT, T, PREC>), grd, blk, 0, st, dm, flip, a, (const double*)b); break;
+    case OP_GET_POP:
+        if (has_to) hipLaunchKernelGGL((k_get_pop<LAT, T, PREC, true>), grd, blk, 0, st, dm, flip, b);
+        else hipLaunchKernelGGL((k_get_pop<LAT, T, PREC, false>), grd, blk, 0, st, dm, flip, b);
+        break;
+    case OP_SET_POP: hipLaunchKernelGGL((k_set_pop<LAT, T, PREC>), grd, blk, 0, st, dm, flip, a); break;
+    case OP_STREAM:
+        if (has_to) hipLaunchKernelGGL((k_stream_only<LAT, T, true>), grd, blk, 0, st, dm, flip);
+        else hipLaunchKernelGGL((k_stream_only<LAT, T, false>), grd, blk, 0, st, dm, flip);
+        break;
+    case OP_FLUSH:
+        if (has_to) hipLaunchKernelGGL((k_flush<LAT, T, PREC>), grd, blk, 0, st, dm, flip);
+        break;
+    }
+}
+
+void launch_state(int op, int lattice, int precision, const DevMember* dm, int N, bool has_to, int flip,
+                  hipStream_t st, const double* a, double* b)
+{
+    const int key = lattice * 3 + precision;
+    switch (key) {
+    case LBM_D2Q9 * 3 + LBM_FP32_SHIFTED: launch_state_t<LBM_D2Q9, float, LBM_FP32_SHIFTED>(op, dm, N, has_to, flip, st, a, b); break;
+    case LBM_D2Q9 * 3 + LBM_FP64: launch_state_t<LBM_D2Q9, double, LBM_FP64>(op, dm, N, has_to, flip, st, a, b); break;
+    case LBM_D2Q9 * 3 + LBM_FP32_PLAIN: launch_state_t<LBM_D2Q9, float, LBM_FP32_PLAIN>(op, dm, N, has_to, flip, st, a, b); break;
+    case LBM_D3Q19 * 3 + LBM_FP32_SHIFTED: launch_state_t<LBM_D3Q19, float, LBM_FP32_SHIFTED>(op, dm, N, has_to, flip, st, a, b); break;
+    case LBM_D3Q19 * 3 + LBM_FP64: launch_state_t<LBM_D3Q19, double, LBM_FP64>(op, dm, N, has_to, flip, st, a, b); break;
+    case LBM_D3Q19 * 3 + LBM_FP32_PLAIN: launch_state_t<LBM_D3Q19, float, LBM_FP32_PLAIN>(op, dm, N, has_to, flip, st, a, b); break;
+    }
+}
+
+void launch_fields(int lattice, int precision, const DevMember* dm, const int2* work1, int nb1, bool has_to,
+                   int flip, hipStream_t st, double* rho_out)
+{
+    const int key = lattice * 3 + precision;
+    const dim3 blk(kBlock), grd(nb1);
+#define LBM_MOM(LAT, T, PREC)                                                                                  \
+    do {                                                                                                       \
+        if (has_to) hipLaunchKernelGGL((k_moments<LAT, T, PREC, true>), grd, blk, 0, st, dm, work1, flip, rho_out); \
+        else hipLaunchKernelGGL((k_moments<LAT, T, PREC, false>), grd, blk, 0, st, dm, work1, flip, rho_out);    \
+    } while (0)
+    switch (key) {
+    case LBM_D2Q9 * 3 + LBM_FP32_SHIFTED: LBM_MOM(LBM_D2Q9, float, LBM_FP32_SHIFTED); break;
+    case LBM_D2Q9 * 3 + LBM_FP64: LBM_MOM(LBM_D2Q9, double, LBM_FP64); break;
+    case LBM_D2Q9 * 3 + LBM_FP32_PLAIN: LBM_MOM(LBM_D2Q9, float, LBM_FP32_PLAIN); break;
+    case LBM_D3Q19 * 3 + LBM_FP32_SHIFTED: LBM_MOM(LBM_D3Q19, float, LBM_FP32_SHIFTED); break;
+    case LBM_D3Q19 * 3 + LBM_FP64: LBM_MOM(LBM_D3Q19, double, LBM_FP64); break;
+    case LBM_D3Q19 * 3 + LBM_FP32_PLAIN: LBM_MOM(LBM_D3Q19, float, LBM_FP32_PLAIN); break;
+    }
+#undef LBM_MOM
+}
+
+void launch_philox_test(const uint32_t* in, uint32_t* out, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_philox_test, dim3((n + 63) / 64), dim3(64), 0, st, in, out, n);
+}
+
+void launch_normals_test(unsigned long long seed, long long step0, int nsteps, int n, double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_normals_test, dim3((nsteps + 63) / 64), dim3(64), 0, st, seed, step0, nsteps, n, out);
+}
+
+int lattice_table(int lattice, int* c, double* w)
+{
+    if (lattice == LBM_D2Q9) {
+        using L = Lat<LBM_D2Q9>;
+        for (int i = 0; i < L::Q; ++i) { c[3 * i] = L::cx[i]; c[3 * i + 1] = L::cy[i]; c[3 * i + 2] = L::cz[i]; w[i] = L::w[i]; }
+        return L::Q;
+    }
+    using L = Lat<LBM_D3Q19>;
+    for (int i = 0; i < L::Q; ++i) { c[3 * i] = L::cx[i]; c[3 * i + 1] = L::cy[i]; c[3 * i + 2] = L::cz[i]; w[i] = L::w[i]; }
+    return L::Q;
+}
+
+}  // namespace lbm

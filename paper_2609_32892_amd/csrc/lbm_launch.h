@@ -1,0 +1,39 @@
+// lbm_launch.h -- launch interface between the host library and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "lbm_dev.h"
+
+namespace lbm {
+
+// One launch per kernel phase covers every member of a group: members share
+// lattice, precision, substrate and mode, and are mapped to workgroups by
+// the work tables.
+struct LaunchGroup {
+    int lattice, precision, substrate, mode;  // mode 0 plain, 1 plain + records, 2 TO
+    int any_z, maxpow, maxsa;
+    const DevMember* mems;
+    const int2* work1;  // cell kernels: (member, block of kBlock cells)
+    int nb1;
+    const int2* workr;  // reduce: (member, y * nbx2 + bx)
+    int nbr;
+    const int* workm;   // one workgroup per member
+    int nmem;
+};
+
+enum { OP_INIT = 0, OP_GET_POP = 1, OP_SET_POP = 2, OP_STREAM = 3, OP_FLUSH = 4 };
+
+// ev (nullable): 7 events recorded at the phase boundaries of the step
+// (start, after stream-collide, after curl, after the binomial powers, after
+// the reduce, after the solve, after the apply).
+constexpr int kNumPhases = 6;
+void launch_step(const LaunchGroup& g, hipStream_t st, int flip, hipEvent_t* ev = nullptr);
+void launch_state(int op, int lattice, int precision, const DevMember* dm, int N, bool has_to, int flip,
+                  hipStream_t st, const double* a, double* b);
+void launch_fields(int lattice, int precision, const DevMember* dm, const int2* work1, int nb1, bool has_to,
+                   int flip, hipStream_t st, double* rho_out);
+void launch_philox_test(const uint32_t* in, uint32_t* out, int n, hipStream_t st);
+void launch_normals_test(unsigned long long seed, long long step0, int nsteps, int n, double* out, hipStream_t st);
+int lattice_table(int lattice, int* c, double* w);
+
+}  // namespace lbm

@@ -1,0 +1,343 @@
+"""ctypes binding of liblbm_hip.so (include/lbm.h).
+
+Argument marshalling only: every step of the LES runs in the library's HIP
+kernels.  PyTorch provides the device arena and the stream.  There is no
+fallback: without the built library or a GPU the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm_hip.so")
+MAX_QOI = 16
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
+D2Q9, D3Q19 = 0, 1
+FP32_SHIFTED, FP64, FP32_PLAIN = 0, 1, 2
+BGK, SMAGORINSKY, WALE = 0, 1, 2
+FORCE_NONE, FORCE_SIN_Y, FORCE_CONST_X = 0, 1, 2
+QOI_E, QOI_Z, QOI_MP = 0, 1, 2
+FILT = {"I": 0, "B": 1, "B2": 2, "BMID": 3, "IMB": 4}
+MODE = {"off": 0, "track": 1, "lrs": 2}
+PRECISION = {"fp32": FP32_SHIFTED, "fp64": FP64, "fp32_plain": FP32_PLAIN}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lbm error {code}: {msg}")
+        self.code = code
+
+
+class Config(ct.Structure):
+    _fields_ = [("lattice", ct.c_int), ("precision", ct.c_int), ("nx", ct.c_int), ("ny", ct.c_int),
+                ("nz", ct.c_int), ("walls_y", ct.c_int), ("tau", ct.c_double), ("substrate", ct.c_int),
+                ("c_model", ct.c_double), ("force_kind", ct.c_int), ("force_amp", ct.c_double),
+                ("force_k", ct.c_int), ("drag", ct.c_double), ("diag", ct.c_int), ("rec_cap", ct.c_int)]
+
+
+class QoiSpec(ct.Structure):
+    _fields_ = [("kind", ct.c_int), ("filter", ct.c_int), ("band", ct.c_int)]
+
+
+class Closure(ct.Structure):
+    _fields_ = [("nq", ct.c_int), ("q", ct.POINTER(QoiSpec)), ("nbands", ct.c_int),
+                ("band_dmin", ct.c_double), ("band_dmax", ct.c_double), ("mode", ct.c_int),
+                ("spinup", ct.c_long), ("h", ct.c_int), ("C", ct.POINTER(ct.c_double)),
+                ("mu", ct.POINTER(ct.c_double)), ("Sigma", ct.POINTER(ct.c_double)),
+                ("scale", ct.POINTER(ct.c_double)), ("qref", ct.POINTER(ct.c_double)),
+                ("nref", ct.c_long), ("seed", ct.c_uint64)]
+
+
+class QoiRec(ct.Structure):
+    _fields_ = [("step", ct.c_int64), ("flags", ct.c_int32), ("nq", ct.c_int32), ("mass", ct.c_double),
+                ("mom", ct.c_double * 3), ("diag_e", ct.c_double), ("diag_z", ct.c_double),
+                ("q", ct.c_double * MAX_QOI), ("dq", ct.c_double * MAX_QOI),
+                ("gamma", ct.c_double * MAX_QOI)]
+
+
+#: symbols declared in include/lbm.h
+EXPORTS = [
+    "lbm_last_error", "lbm_version", "lbm_lattice_info", "lbm_required_bytes", "lbm_create",
+    "lbm_destroy", "lbm_init_velocity", "lbm_set_closure", "lbm_step", "lbm_sync", "lbm_step_count",
+    "lbm_qoi", "lbm_fields", "lbm_get_populations", "lbm_set_populations", "lbm_stream_only",
+    "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_batch_create", "lbm_batch_step",
+    "lbm_batch_sync", "lbm_batch_destroy", "lbm_profile_phases", "lbm_test_philox", "lbm_test_normals",
+]
+PHASES = ["stream_collide", "curl", "binomial", "reduce", "solve", "apply"]
+
+_lib = None
+
+
+def lib():
+    """Load liblbm_hip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2609_32892_amd/build.py")
+        L = ct.CDLL(LIB_PATH)
+        P, I, Z = ct.c_void_p, ct.c_int, ct.c_size_t
+        L.lbm_last_error.restype = ct.c_char_p
+        L.lbm_version.restype = ct.c_char_p
+        L.lbm_lattice_info.argtypes = [I, P, P]
+        L.lbm_required_bytes.restype = Z
+        L.lbm_required_bytes.argtypes = [ct.POINTER(Config), ct.POINTER(Closure)]
+        L.lbm_create.argtypes = [ct.POINTER(Config), ct.POINTER(Closure), P, Z, P, ct.POINTER(P)]
+        L.lbm_destroy.argtypes = [P]
+        L.lbm_destroy.restype = None
+        L.lbm_init_velocity.argtypes = [P, P, P]
+        L.lbm_set_closure.argtypes = [P, ct.POINTER(Closure)]
+        L.lbm_step.argtypes = [P, ct.c_long]
+        L.lbm_sync.argtypes = [P]
+        L.lbm_step_count.restype = ct.c_long
+        L.lbm_step_count.argtypes = [P]
+        L.lbm_qoi.argtypes = [P, ct.c_long, ct.c_long, P]
+        L.lbm_fields.argtypes = [P, P, P]
+        L.lbm_get_populations.argtypes = [P, P]
+        L.lbm_set_populations.argtypes = [P, P]
+        L.lbm_stream_only.argtypes = [P]
+        L.lbm_state_bytes.restype = Z
+        L.lbm_state_bytes.argtypes = [P]
+        L.lbm_get_state.argtypes = [P, P, Z]
+        L.lbm_set_state.argtypes = [P, P, Z]
+        L.lbm_batch_create.argtypes = [I, ct.POINTER(P), ct.POINTER(P)]
+        L.lbm_batch_step.argtypes = [P, ct.c_long]
+        L.lbm_batch_sync.argtypes = [P]
+        L.lbm_batch_destroy.argtypes = [P]
+        L.lbm_batch_destroy.restype = None
+        L.lbm_profile_phases.argtypes = [P, ct.c_long, P, P]
+        L.lbm_test_philox.argtypes = [P, P, I]
+        L.lbm_test_normals.argtypes = [ct.c_uint64, ct.c_long, I, I, P]
+        _lib = L
+    return _lib
+
+
+def check(rc):
+    if rc < 0:
+        raise LbmError(rc, lib().lbm_last_error().decode())
+    return rc
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ct.c_void_p)
+
+
+def _dptr(a):
+    return None if a is None else a.ctypes.data_as(ct.POINTER(ct.c_double))
+
+
+def lattice_info(lattice: int):
+    c = np.zeros(57, dtype=np.int32)
+    w = np.zeros(19)
+    Q = check(lib().lbm_lattice_info(lattice, _p(c), _p(w)))
+    return c[: 3 * Q].reshape(Q, 3).copy(), w[:Q].copy()
+
+
+def make_config(lattice=D2Q9, precision=FP32_SHIFTED, nx=64, ny=64, nz=1, walls_y=0, tau=0.6,
+                substrate=BGK, cmodel=0.0, force_kind=FORCE_NONE, force_amp=0.0, force_k=0, drag=0.0,
+                diag=0, rec_cap=0) -> Config:
+    if isinstance(precision, str):
+        precision = PRECISION[precision]
+    return Config(lattice, precision, nx, ny, nz if lattice == D3Q19 else 1, walls_y, tau, substrate,
+                  cmodel, force_kind, force_amp, force_k, drag, diag, rec_cap)
+
+
+class ClosureSpec:
+    """Owns the host arrays a Closure struct points to."""
+
+    def __init__(self, qois, mode="off", spinup=0, C=None, mu=None, Sigma=None, scale=None,
+                 qref=None, nbands=0, dmin=0.5, dmax=1.0, seed=0):
+        nq = len(qois)
+        self.nq = nq
+        self._q = (QoiSpec * nq)()
+        for k, (kind, filt, band) in enumerate(qois):
+            self._q[k] = QoiSpec({"E": QOI_E, "Z": QOI_Z, "MP": QOI_MP}[kind], FILT[filt], band)
+        arr = lambda a, n: None if a is None else np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(n))
+        self._C = arr(C, (nq + 1) * nq)
+        self._mu = arr(mu, nq)
+        self._S = arr(Sigma, nq * nq)
+        self._scale = arr(scale, nq)
+        self._qref = None if qref is None else np.ascontiguousarray(np.asarray(qref, dtype=np.float64))
+        self.c = Closure()
+        self.c.nq = nq
+        self.c.q = ct.cast(self._q, ct.POINTER(QoiSpec))
+        self.c.nbands = nbands
+        self.c.band_dmin = dmin
+        self.c.band_dmax = dmax
+        self.c.mode = MODE[mode] if isinstance(mode, str) else mode
+        self.c.spinup = spinup
+        self.c.h = 0
+        self.c.C = _dptr(self._C)
+        self.c.mu = _dptr(self._mu)
+        self.c.Sigma = _dptr(self._S)
+        self.c.scale = _dptr(self._scale)
+        self.c.qref = _dptr(self._qref)
+        self.c.nref = 0 if self._qref is None else self._qref.shape[0]
+        self.c.seed = seed
+
+
+_default_stream = None
+
+
+def default_stream():
+    """A dedicated torch stream (default priority) shared by runs that are not given one."""
+    global _default_stream
+    import torch
+    if _default_stream is None:
+        _default_stream = torch.cuda.Stream()
+    return _default_stream
+
+
+class Run:
+    """One LES run (an lbm_ctx) whose state lives in a torch-allocated arena."""
+
+    def __init__(self, cfg: Config, closure: ClosureSpec | None = None, stream=None, device="cuda"):
+        import torch
+        self.L = lib()
+        self.cfg = cfg
+        self.d = 2 if cfg.lattice == D2Q9 else 3
+        self.Q = 9 if cfg.lattice == D2Q9 else 19
+        self.N = cfg.nx * cfg.ny * cfg.nz
+        self.shape = (cfg.nz, cfg.ny, cfg.nx)
+        self.closure = closure
+        clp = ct.byref(closure.c) if closure is not None else None
+        nbytes = self.L.lbm_required_bytes(ct.byref(cfg), clp)
+        if nbytes == 0:
+            raise LbmError(EINVAL, self.L.lbm_last_error().decode())
+        self.nbytes = nbytes
+        self.arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.arena.data_ptr()
+        off = (-base) % 256
+        self.stream = stream if stream is not None else default_stream()
+        h = ct.c_void_p()
+        with torch.cuda.device(self.arena.device):
+            check(self.L.lbm_create(ct.byref(cfg), clp, ct.c_void_p(base + off), nbytes,
+                                    ct.c_void_p(self.stream.cuda_stream), ct.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    # -- state ----------------------------------------------------------------
+    def init_velocity(self, u, rho=None):
+        u = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(self.d, self.N))
+        r = None if rho is None else np.ascontiguousarray(np.asarray(rho, dtype=np.float64).reshape(self.N))
+        check(self.L.lbm_init_velocity(self.h, _p(r), _p(u)))
+
+    def set_closure(self, closure: ClosureSpec | None):
+        self.closure = closure
+        check(self.L.lbm_set_closure(self.h, ct.byref(closure.c) if closure is not None else None))
+
+    def step(self, n=1):
+        check(self.L.lbm_step(self.h, n))
+
+    def sync(self):
+        return check(self.L.lbm_sync(self.h))
+
+    @property
+    def step_count(self):
+        return self.L.lbm_step_count(self.h)
+
+    def records(self, first=0, count=None):
+        if count is None:
+            count = self.step_count - first
+        arr = (QoiRec * count)()
+        check(self.L.lbm_qoi(self.h, first, count, ct.cast(arr, ct.c_void_p)))
+        return arr
+
+    def record_arrays(self, first=0, count=None):
+        recs = self.records(first, count)
+        nq = self.closure.nq if self.closure is not None else 0
+        return {
+            "step": np.array([r.step for r in recs]),
+            "flags": np.array([r.flags for r in recs]),
+            "mass": np.array([r.mass for r in recs]),
+            "mom": np.array([list(r.mom) for r in recs]),
+            "diag_e": np.array([r.diag_e for r in recs]),
+            "diag_z": np.array([r.diag_z for r in recs]),
+            "q": np.array([list(r.q)[:nq] for r in recs]),
+            "dq": np.array([list(r.dq)[:nq] for r in recs]),
+            "gamma": np.array([list(r.gamma)[:nq] for r in recs]),
+        }
+
+    def fields(self):
+        rho = np.zeros(self.N)
+        u = np.zeros((self.d, self.N))
+        check(self.L.lbm_fields(self.h, _p(rho), _p(u)))
+        return rho, u
+
+    def get_populations(self):
+        f = np.zeros((self.Q, self.N))
+        check(self.L.lbm_get_populations(self.h, _p(f)))
+        return f
+
+    def set_populations(self, f):
+        f = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(self.Q, self.N))
+        check(self.L.lbm_set_populations(self.h, _p(f)))
+
+    def stream_only(self):
+        check(self.L.lbm_stream_only(self.h))
+
+    def profile_phases(self, nsteps):
+        """Mean ms per step and launches per step of each kernel phase."""
+        ms = np.zeros(6)
+        nl = np.zeros(6, dtype=np.int32)
+        check(self.L.lbm_profile_phases(self.h, nsteps, _p(ms), _p(nl)))
+        return dict(zip(PHASES, ms.tolist())), dict(zip(PHASES, nl.tolist()))
+
+    def get_state(self) -> bytes:
+        n = self.L.lbm_state_bytes(self.h)
+        buf = ct.create_string_buffer(n)
+        check(self.L.lbm_get_state(self.h, buf, n))
+        return buf.raw
+
+    def set_state(self, data: bytes):
+        buf = ct.create_string_buffer(data, len(data))
+        check(self.L.lbm_set_state(self.h, buf, len(data)))
+
+
+class Batch:
+    """Several runs advanced together (lbm_batch)."""
+
+    def __init__(self, runs):
+        self.L = lib()
+        self.runs = list(runs)
+        arr = (ct.c_void_p * len(self.runs))(*[r.h.value for r in self.runs])
+        h = ct.c_void_p()
+        check(self.L.lbm_batch_create(len(self.runs), arr, ct.byref(h)))
+        self.h = h
+
+    def step(self, n=1):
+        check(self.L.lbm_batch_step(self.h, n))
+
+    def sync(self):
+        return check(self.L.lbm_batch_sync(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.lbm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+def test_philox(vectors):
+    v = np.ascontiguousarray(np.asarray(vectors, dtype=np.uint32).reshape(-1, 6))
+    out = np.zeros((v.shape[0], 4), dtype=np.uint32)
+    check(lib().lbm_test_philox(_p(v), _p(out), v.shape[0]))
+    return out
+
+
+def test_normals(seed, step0, nsteps, n):
+    out = np.zeros((nsteps, n))
+    check(lib().lbm_test_normals(ct.c_uint64(seed), step0, nsteps, n, _p(out)))
+    return out

@@ -1,0 +1,117 @@
+"""System behaviour of the HIP library on the GPU: bitwise determinism, graph
+replay equal to eager launches, batch members equal to solo runs, bitwise
+checkpoint/resume, closure switching."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import closure_args, gpu_run, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _case2d(n=80, seed=2):
+    cfg, _ = synth.kolmogorov_workload(n, tau=0.51, seed=seed)
+    u0 = synth.noise_velocity(2, (1, n, n), 1e-3, seed)
+    qois, cargs = closure_args("2d", spinup=10, seed=100 + seed)
+    return cfg, u0, qois, cargs
+
+
+def test_repeat_runs_bitwise_and_graph_equals_eager():
+    lbm = need_gpu()
+    cfg, u0, qois, cargs = _case2d()
+    a = gpu_run(lbm, cfg, u0, "fp32", qois, cargs)
+    b = gpu_run(lbm, cfg, u0, "fp32", qois, cargs)
+    c = gpu_run(lbm, cfg, u0, "fp32", qois, cargs)
+    a.step(70)                      # graph chunks + eager remainder
+    for _ in range(70):
+        b.step(1)                   # eager only
+    c.step(70)
+    for r in (a, b, c):
+        r.sync()
+    fa, fb, fc = a.get_populations(), b.get_populations(), c.get_populations()
+    assert np.array_equal(fa, fb)
+    assert np.array_equal(fa, fc)
+    assert np.array_equal(a.record_arrays()["q"], b.record_arrays()["q"])
+
+
+def test_batch_members_bitwise_equal_to_solo():
+    lbm = need_gpu()
+    members = [_case2d(n, seed=s) for n, s in ((48, 1), (80, 2), (64, 3))]
+    channel = synth.channel_workload(16, 24, 8)
+    qois3, cargs3 = closure_args("3d", ny=24, spinup=10)
+    solo, batched = [], []
+    for cfg, u0, qois, cargs in members:
+        solo.append(gpu_run(lbm, cfg, u0, "fp32", qois, cargs))
+        batched.append(gpu_run(lbm, cfg, u0, "fp32", qois, cargs))
+    for lst in (solo, batched):
+        lst.append(gpu_run(lbm, channel[0], channel[1], "fp32", qois3, cargs3))
+    for r in solo:
+        r.step(41)
+    batch = lbm.Batch(batched)
+    batch.step(41)
+    batch.sync()
+    for r, s in zip(batched, solo):
+        s.sync()
+        assert r.step_count == 41
+        assert np.array_equal(r.get_populations(), s.get_populations())
+        assert np.array_equal(r.record_arrays()["q"], s.record_arrays()["q"])
+    # a member stepped alone afterwards continues consistently
+    batched[0].step(3)
+    solo[0].step(3)
+    assert np.array_equal(batched[0].get_populations(), solo[0].get_populations())
+    batch.step(5)
+    for r in solo:
+        r.step(5)
+    for r, s in zip(batched, solo):
+        assert np.array_equal(r.get_populations(), s.get_populations())
+
+
+def test_checkpoint_resume_bitwise():
+    lbm = need_gpu()
+    cfg, u0, qois, cargs = _case2d()
+    a = gpu_run(lbm, cfg, u0, "fp32", qois, cargs)
+    a.step(33)
+    img = a.get_state()
+    a.step(40)
+    b = gpu_run(lbm, cfg, np.zeros_like(u0), "fp32", qois, cargs)
+    b.set_state(img)
+    assert b.step_count == 33
+    b.step(40)
+    assert np.array_equal(a.get_populations(), b.get_populations())
+    assert np.array_equal(a.record_arrays(33, 40)["dq"], b.record_arrays(33, 40)["dq"])
+
+
+def test_closure_off_and_on_again():
+    """Switching the closure off folds the pending correction in; switching
+    it back on continues without error."""
+    lbm = need_gpu()
+    cfg, u0, qois, cargs = _case2d()
+    a = gpu_run(lbm, cfg, u0, "fp64", qois, cargs)
+    a.step(20)
+    f_before = a.get_populations()
+    a.set_closure(None)
+    assert np.allclose(a.get_populations(), f_before, rtol=0, atol=1e-15)
+    a.step(5)
+    a.set_closure(lbm.ClosureSpec(qois, **cargs))
+    a.step(5)
+    assert a.sync() == 0
+
+
+def test_invalid_arguments_rejected():
+    lbm = need_gpu()
+    with pytest.raises(lbm.LbmError):
+        lbm.Run(lbm.make_config(nx=2, ny=8))
+    cfg, u0, qois, cargs = _case2d()
+    with pytest.raises(lbm.LbmError):   # mean-profile QoI without walls
+        lbm.Run(lbm.make_config(**cfg), lbm.ClosureSpec([("MP", "I", 0)], nbands=1, dmin=0.5, dmax=2))
+    r = gpu_run(lbm, cfg, u0, "fp32", qois, cargs)
+    with pytest.raises(lbm.LbmError):   # more QoIs than the planned workspace
+        r.set_closure(lbm.ClosureSpec([("E", "B2", 0)] * 3))
+    r.step(2)
+    with pytest.raises(lbm.LbmError):   # records not yet produced
+        r.records(0, 5)
