@@ -39,6 +39,16 @@ def workload(name):
                 "12 QoIs (E/Z x {B^2,B-B^2,I-B} + 6 mean-profile bands), LRS h=0 from step 2500")
         return dict(cfg=cfg, u0=u0, qois=synth.QOIS_3D, cargs=cargs, precision="fp32", desc=desc,
                     job_steps=10000, b_alg=232)
+    if name == "channel_large":
+        nx, ny, nz = 384, 192, 192
+        cfg, u0 = synth.channel_workload(nx, ny, nz, substrate=1, cmodel=0.1, seed=6)
+        nb, dmin, dmax = synth.channel_bands(ny)
+        C, mu, S = synth.lrs_model_channel(12, 7, 9)
+        cargs = dict(mode="lrs", spinup=250, C=C, mu=mu, Sigma=S, seed=8, nbands=nb, dmin=dmin, dmax=dmax)
+        desc = ("D3Q19 channel TO-LES 384x192x192 (HBM-resident scale-up, same physics per cell), FP32 "
+                "shifted populations, Smagorinsky Cs=0.1, 12 QoIs, LRS h=0 from step 250")
+        return dict(cfg=cfg, u0=u0, qois=synth.QOIS_3D, cargs=cargs, precision="fp32", desc=desc,
+                    job_steps=1000, b_alg=232)
     if name == "kolmogorov":
         n = 256
         cfg, _ = synth.kolmogorov_workload(n, tau=0.51, seed=2)
@@ -88,7 +98,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's job length)")
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="channel", choices=["channel", "kolmogorov", "fine"])
+    ap.add_argument("--workload", default="channel", choices=["channel", "channel_large", "kolmogorov", "fine"])
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -56,7 +56,7 @@ void filter_poly(int f, double r[3])
 
 struct ClosureShape {
     int nq = 0, nsa = 0, nmp = 0, jv = 0, jw = 0, has_z = 0, has_e = 0, nbands = 0;
-    int npart() const { return nsa + nsa * (nsa + 1) / 2 + (nmp > 0 ? 1 + nsa : 0); }
+    int npart() const { return nsa + nsa * (nsa + 1) / 2 + nmp * (1 + nsa); }
 };
 
 int closure_shape(const lbm_config* cfg, const lbm_closure* cl, ClosureShape* out)
@@ -110,9 +110,9 @@ int check_config(const lbm_config* c)
 
 struct Plan {
     size_t member, param, ctl, recs, g0, g1, fprof, vn, part_stats, part_diag, work1, workm;
-    size_t rho, vs, dv, P, W, part_to, bandw, cmp, workr;
+    size_t rho, vs, dv, P, W, part_to, bandw, cmp, workr, workb, sums, works;
     size_t total;
-    int N, D, NC, Q, esz, nb1, nbx2, cpt2, nbr, rec_cap;
+    int N, D, NC, Q, esz, nb1, nbx2, cpt2, nbr, nbb, nbs, zc, rec_cap;
     ClosureShape cap;
 };
 
@@ -131,6 +131,12 @@ void make_plan(const lbm_config* c, const ClosureShape& cs, Plan* p)
     P.cpt2 = std::max(1, std::min(8, P.N / (kBlock * 2048)));
     P.nbx2 = (plane + kBlock * P.cpt2 - 1) / (kBlock * P.cpt2);
     P.nbr = P.nbx2 * c->ny;
+    {
+        // z chunk: as many planes per workgroup as keeps >= 1024 workgroups
+        const int nxy = ((c->nx + kBinTX - 1) / kBinTX) * ((c->ny + kBinTY - 1) / kBinTY);
+        P.zc = P.D == 3 ? std::max(1, std::min(kBinZCMax, nxy * c->nz / 1024)) : 1;
+        P.nbb = nxy * (P.D == 3 ? (c->nz + P.zc - 1) / P.zc : 1);
+    }
     const size_t N = P.N, e = P.esz;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
@@ -156,6 +162,10 @@ void make_plan(const lbm_config* c, const ClosureShape& cs, Plan* p)
         P.bandw = take(sizeof(double) * (size_t)std::max(cs.nbands, 1) * c->ny);
         P.cmp = take(sizeof(double) * c->ny);
         P.workr = take(sizeof(int2) * P.nbr);
+        P.workb = take(sizeof(int2) * P.nbb);
+        P.nbs = 4 + cs.npart();
+        P.sums = take(sizeof(double) * P.nbs);
+        P.works = take(sizeof(int2) * P.nbs);
     }
     P.total = o;
     *p = P;
@@ -258,6 +268,10 @@ LaunchGroup ctx_group(const lbm_ctx* c)
     g.nb1 = c->plan.nb1;
     g.workr = (const int2*)(c->arena + c->plan.workr);
     g.nbr = c->plan.nbr;
+    g.workb = (const int2*)(c->arena + c->plan.workb);
+    g.nbb = c->plan.nbb;
+    g.works = (const int2*)(c->arena + c->plan.works);
+    g.nbs = c->plan.nbs;
     g.workm = (const int*)(c->arena + c->plan.workm);
     g.nmem = 1;
     return g;
@@ -479,7 +493,7 @@ int lbm_create(const lbm_config* cfg, const lbm_closure* closure, void* dev_aren
     m.vn = A + plan.vn;
     m.part_stats = (double*)(A + plan.part_stats);
     m.part_diag = (double*)(A + plan.part_diag);
-    m.nb1 = plan.nb1; m.nbx2 = plan.nbx2; m.cpt2 = plan.cpt2; m.npart = 0;
+    m.nb1 = plan.nb1; m.nbx2 = plan.nbx2; m.cpt2 = plan.cpt2; m.npart = 0; m.zc = plan.zc;
     m.prm = (DevParam*)(A + plan.param);
     m.ctl = (DevCtl*)(A + plan.ctl);
     m.recs = (lbm_qoi_rec*)(A + plan.recs);
@@ -489,6 +503,7 @@ int lbm_create(const lbm_config* cfg, const lbm_closure* closure, void* dev_aren
         m.part_to = (double*)(A + plan.part_to);
         m.bandw = (double*)(A + plan.bandw);
         m.cmp = (double*)(A + plan.cmp);
+        m.sums = (double*)(A + plan.sums);
     }
     c->dm = (DevMember*)(A + plan.member);
     // host tables
@@ -509,6 +524,12 @@ int lbm_create(const lbm_config* cfg, const lbm_closure* closure, void* dev_aren
         std::vector<int2> wr(plan.nbr);
         for (int b = 0; b < plan.nbr; ++b) wr[b] = make_int2(0, b);
         rc = upload(c, A + plan.workr, wr.data(), sizeof(int2) * wr.size());
+        std::vector<int2> wb(plan.nbb);
+        for (int b = 0; b < plan.nbb; ++b) wb[b] = make_int2(0, b);
+        if (!rc) rc = upload(c, A + plan.workb, wb.data(), sizeof(int2) * wb.size());
+        std::vector<int2> ws(plan.nbs);
+        for (int b = 0; b < plan.nbs; ++b) ws[b] = make_int2(0, b);
+        if (!rc) rc = upload(c, A + plan.works, ws.data(), sizeof(int2) * ws.size());
     }
     if (!rc) rc = upload(c, c->dm, &m, sizeof m);
     if (!rc) rc = reset_ctl(c);
@@ -806,12 +827,12 @@ static int batch_build(lbm_batch* b)
     batch_free_dev(b);
     const int n = (int)b->mem.size();
     // group members by kernel kind
-    struct Key { int lat, prec, sub, mode, sa2; };
+    struct Key { int lat, prec, sub, mode, sab; };
     std::vector<Key> keys;
     std::vector<std::vector<int>> gm;
     for (int i = 0; i < n; ++i) {
         const lbm_ctx* c = b->mem[i];
-        Key k{c->cfg.lattice, c->cfg.precision, c->cfg.substrate, c->mode(), c->cur.nsa <= 2};
+        Key k{c->cfg.lattice, c->cfg.precision, c->cfg.substrate, c->mode(), c->cur.nsa <= 2 ? 2 : (c->cur.nsa <= 6 ? 6 : 8)};
         int gi = -1;
         for (size_t j = 0; j < keys.size(); ++j)
             if (!memcmp(&keys[j], &k, sizeof k)) gi = (int)j;
@@ -821,7 +842,7 @@ static int batch_build(lbm_batch* b)
     std::vector<DevMember> hmem(n);
     std::vector<int2> work;
     std::vector<int> workm;
-    struct Off { size_t w1, nb1, wr, nbr, wm, nm; };
+    struct Off { size_t w1, nb1, wr, nbr, wb, nbb, ws, nbs, wm, nm; };
     std::vector<Off> offs;
     for (size_t gi = 0; gi < keys.size(); ++gi) {
         Off o{};
@@ -834,6 +855,16 @@ static int batch_build(lbm_batch* b)
             for (int i : gm[gi])
                 for (int k = 0; k < b->mem[i]->plan.nbr; ++k) work.push_back(make_int2(i, k));
         o.nbr = work.size() - o.wr;
+        o.wb = work.size();
+        if (keys[gi].mode == 2)
+            for (int i : gm[gi])
+                for (int k = 0; k < b->mem[i]->plan.nbb; ++k) work.push_back(make_int2(i, k));
+        o.nbb = work.size() - o.wb;
+        o.ws = work.size();
+        if (keys[gi].mode == 2)
+            for (int i : gm[gi])
+                for (int k = 0; k < b->mem[i]->plan.nbs; ++k) work.push_back(make_int2(i, k));
+        o.nbs = work.size() - o.ws;
         o.wm = workm.size();
         for (int i : gm[gi]) workm.push_back(i);
         o.nm = workm.size() - o.wm;
@@ -873,6 +904,10 @@ static int batch_build(lbm_batch* b)
         g.nb1 = (int)offs[gi].nb1;
         g.workr = b->dwork + offs[gi].wr;
         g.nbr = (int)offs[gi].nbr;
+        g.workb = b->dwork + offs[gi].wb;
+        g.nbb = (int)offs[gi].nbb;
+        g.works = b->dwork + offs[gi].ws;
+        g.nbs = (int)offs[gi].nbs;
         g.workm = b->dworkm + offs[gi].wm;
         g.nmem = (int)offs[gi].nm;
         b->groups.push_back(g);

@@ -15,6 +15,9 @@ constexpr int kMaxQ = LBM_MAX_QOI;
 constexpr int kMaxSA = 8;       // E/Z QoIs per closure
 constexpr int kMaxPow = 4;      // highest power of B in R R (filters up to degree 2)
 constexpr int kBlock = 256;     // threads per workgroup of the cell kernels
+constexpr int kBinTX = 32;      // binomial-filter tile: x extent
+constexpr int kBinTY = kBlock / kBinTX;  // y extent
+constexpr int kBinZCMax = 8;    // most z planes per workgroup (3-D)
 
 // Constant closure parameters (written by the host at set_closure).
 struct DevParam {
@@ -65,12 +68,14 @@ struct DevMember {
     double* part_to;                   // [ny][nbx2][npart]
     double* part_diag;                 // [nb1][2]
     int nb1, nbx2, npart, cpt2;        // block counts; cells per thread of the reduce
+    int zc, pad1;                      // z planes per binomial-filter workgroup
     DevParam* prm;
     DevCtl* ctl;
     lbm_qoi_rec* recs;
     double* bandw;                     // [nbands][ny]
     double* cmp;                       // [ny]
     double* fprof;                     // body force F_x(y) [ny]
+    double* sums;                      // [4 + npart]: reduced statistics and TO partials
 };
 
 }  // namespace lbm

@@ -445,33 +445,103 @@ __device__ __forceinline__ T binom_at(const T* __restrict__ u, int x, int y, int
 }
 
 // K2b: P_j = B P_{j-1} (P_0 = v*) for j <= jv and W_j = B W_{j-1} for j <= jw.
+// 2.5-D tiling: a workgroup owns a kBinTX x kBinTY tile of the xy plane and
+// a chunk of zc planes (chosen per grid for enough workgroups); every plane of the chunk (plus one halo plane on
+// each side) is staged with its xy halo in LDS, filtered in x and y there,
+// and the z pass runs on a three-plane window kept in registers.
+__device__ __forceinline__ int modi(int a, int n) { int r = a % n; return r < 0 ? r + n : r; }
+
 template <int LAT, typename T>
 __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ mems, const int2* __restrict__ work,
                                                   int j)
 {
     using L = Lat<LAT>;
-    constexpr int D = L::D, NC = L::NC;
+    constexpr int D = L::D, NC = L::NC, NCMP = D + NC;
+    constexpr int HX = kBinTX + 2, HY = kBinTY + 2, HXY = HX * HY;
+    __shared__ T tile[NCMP][HXY];
     const int2 wk = work[blockIdx.x];
     const DevMember& m = mems[wk.x];
     const DevParam* prm = m.prm;
     const bool dov = j <= prm->jv, dow = prm->has_z && j <= prm->jw;
     if (!dov && !dow) return;
-    const int N = m.N, nx = m.nx, ny = m.ny, nz = m.nz;
-    const int cell = wk.y * kBlock + threadIdx.x;
-    if (cell >= N) return;
-    const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
-    const size_t sN = (size_t)N;
-    if (dov) {
-        const T* src = j == 1 ? (const T*)m.vs : (const T*)m.P + (size_t)(j - 2) * D * sN;
-        T* dst = (T*)m.P + (size_t)(j - 1) * D * sN;
+    const int nx = m.nx, ny = m.ny, nz = m.nz;
+    const size_t sN = (size_t)m.N;
+    const int ntx = (nx + kBinTX - 1) / kBinTX, nty = (ny + kBinTY - 1) / kBinTY;
+    const int zc = m.zc;
+    const int tx0 = (wk.y % ntx) * kBinTX;
+    const int ty0 = ((wk.y / ntx) % nty) * kBinTY;
+    const int tz0 = (wk.y / (ntx * nty)) * zc;
+    const int lx = threadIdx.x % kBinTX, ly = threadIdx.x / kBinTX;
+    const int x = tx0 + lx, y = ty0 + ly;
+    const bool own = x < nx && y < ny;
+    // source and destination component pointers
+    const T* src[NCMP];
+    T* dst[NCMP];
 #pragma unroll
-        for (int a = 0; a < D; ++a) dst[a * sN + cell] = binom_at<D, T>(src + a * sN, x, y, z, nx, ny, nz, m.walls);
+    for (int c = 0; c < NCMP; ++c) { src[c] = nullptr; dst[c] = nullptr; }
+    if (dov) {
+        const T* sv = j == 1 ? (const T*)m.vs : (const T*)m.P + (size_t)(j - 2) * D * sN;
+        T* dv = (T*)m.P + (size_t)(j - 1) * D * sN;
+#pragma unroll
+        for (int a = 0; a < D; ++a) { src[a] = sv + a * sN; dst[a] = dv + a * sN; }
     }
     if (dow) {
-        const T* src = (const T*)m.W + (size_t)(j - 1) * NC * sN;
-        T* dst = (T*)m.W + (size_t)j * NC * sN;
+        const T* sw = (const T*)m.W + (size_t)(j - 1) * NC * sN;
+        T* dw = (T*)m.W + (size_t)j * NC * sN;
 #pragma unroll
-        for (int a = 0; a < NC; ++a) dst[a * sN + cell] = binom_at<D, T>(src + a * sN, x, y, z, nx, ny, nz, m.walls);
+        for (int a = 0; a < NC; ++a) { src[D + a] = sw + a * sN; dst[D + a] = dw + a * sN; }
+    }
+    const int zr = D == 3 ? 1 : 0;
+    const int zend = D == 3 ? min(tz0 + zc, nz) : 1;
+    T s0[NCMP], s1[NCMP];
+#pragma unroll
+    for (int c = 0; c < NCMP; ++c) { s0[c] = 0; s1[c] = 0; }
+    for (int pz = tz0 - zr; pz <= zend - 1 + zr; ++pz) {
+        const int zz = D == 3 ? modi(pz, nz) : 0;
+        // stage plane zz with its xy halo
+        for (int e = threadIdx.x; e < HXY; e += kBlock) {
+            const int hx = e % HX, hy = e / HX;
+            const int gx = modi(tx0 + hx - 1, nx);
+            int gy = ty0 + hy - 1;
+            bool ok = true;
+            if (m.walls) ok = gy >= 0 && gy < ny;
+            else gy = modi(gy, ny);
+            const size_t gi = ok ? (size_t)gx + (size_t)nx * (gy + (size_t)ny * zz) : 0;
+#pragma unroll
+            for (int c = 0; c < NCMP; ++c)
+                if (src[c]) tile[c][e] = ok ? src[c][gi] : T(0);
+        }
+        __syncthreads();
+        T sn[NCMP];
+#pragma unroll
+        for (int c = 0; c < NCMP; ++c) {
+            sn[c] = 0;
+            if (!src[c]) continue;
+            const T* t = tile[c] + ly * HX + lx;   // (lx, ly) is the lower-left halo corner
+            const T r0 = T(0.25) * (t[0] + T(2) * t[1] + t[2]);
+            const T r1 = T(0.25) * (t[HX] + T(2) * t[HX + 1] + t[HX + 2]);
+            const T r2 = T(0.25) * (t[2 * HX] + T(2) * t[2 * HX + 1] + t[2 * HX + 2]);
+            sn[c] = T(0.25) * r0 + T(0.5) * r1 + T(0.25) * r2;
+        }
+        __syncthreads();
+        if (D == 2) {
+            if (own) {
+                const size_t ci = (size_t)x + (size_t)nx * y;
+#pragma unroll
+                for (int c = 0; c < NCMP; ++c)
+                    if (dst[c]) dst[c][ci] = sn[c];
+            }
+        } else {
+            const int zo = pz - 1;  // output plane once its upper neighbour is staged
+            if (pz >= tz0 + 1 && own) {
+                const size_t ci = (size_t)x + (size_t)nx * (y + (size_t)ny * zo);
+#pragma unroll
+                for (int c = 0; c < NCMP; ++c)
+                    if (dst[c]) dst[c][ci] = T(0.25) * s0[c] + T(0.5) * s1[c] + T(0.25) * sn[c];
+            }
+#pragma unroll
+            for (int c = 0; c < NCMP; ++c) { s0[c] = s1[c]; s1[c] = sn[c]; }
+        }
     }
 }
 
@@ -505,6 +575,112 @@ __device__ __forceinline__ void zsens(const T* __restrict__ W, size_t N, int jw,
 }
 
 // ---------------------------------------------------------------------------
+// Per-cell sensitivities of all E/Z QoIs (App. A):
+//   E: V = R R v = sum_j rr_j B^j v (local);
+//   Z: V = curl^T psi, psi = R R w = sum_j rr_j B^j w, from central
+//      differences of the stored powers at the six neighbours, shared by
+//      all Z QoIs (2-D: curl^T psi = (D_y psi, -D_x psi); 3-D: curl psi).
+// Also returns the QoI densities 1/2 |R v|^2 and 1/2 |R w|^2 of the cell.
+// ---------------------------------------------------------------------------
+template <int LAT, typename T, int MAXSA>
+__device__ __forceinline__ void cell_sens(const DevMember& m, const DevParam* __restrict__ prm, int x, int y, int z,
+                                          int cell, T (&pv)[kMaxPow + 1][Lat<LAT>::D], T (&V)[MAXSA][Lat<LAT>::D],
+                                          double (&qd)[MAXSA])
+{
+    using L = Lat<LAT>;
+    constexpr int D = L::D, NC = L::NC;
+    const int nsa = prm->nsa, jv = prm->jv, jw = prm->jw;
+    const size_t sN = (size_t)m.N;
+    const T* __restrict__ P = (const T*)m.P;
+    const T* __restrict__ W = (const T*)m.W;
+#pragma unroll
+    for (int a = 0; a < D; ++a) pv[0][a] = ((const T*)m.vs)[a * sN + cell];
+#pragma unroll
+    for (int jj = 1; jj <= kMaxPow; ++jj)
+#pragma unroll
+        for (int a = 0; a < D; ++a) pv[jj][a] = jj <= jv ? P[((size_t)(jj - 1) * D + a) * sN + cell] : T(0);
+    T wc[3][NC];
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+        for (int a = 0; a < NC; ++a) wc[jj][a] = (prm->has_z && jj <= jw) ? W[((size_t)jj * NC + a) * sN + cell] : T(0);
+#pragma unroll
+    for (int s = 0; s < MAXSA; ++s) {
+        qd[s] = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) V[s][a] = 0;
+        if (s >= nsa) continue;
+        const double* r = prm->r[s];
+        if (prm->sa_kind[s] == 0) {
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const T rv = T(r[0]) * pv[0][a] + T(r[1]) * pv[1][a] + T(r[2]) * pv[2][a];
+                qd[s] += 0.5 * (double)(rv * rv);
+                T vv = 0;
+#pragma unroll
+                for (int jj = 0; jj <= kMaxPow; ++jj) vv += T(prm->rr[s][jj]) * pv[jj][a];
+                V[s][a] = vv;
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < NC; ++a) {
+                const T rw = T(r[0]) * wc[0][a] + T(r[1]) * wc[1][a] + T(r[2]) * wc[2][a];
+                qd[s] += 0.5 * (double)(rw * rw);
+            }
+        }
+    }
+    if (!prm->has_z) return;
+    const int nx = m.nx, ny = m.ny, nz = m.nz;
+    // derivative D_b of component a of every psi_s; (b, a, target, sign)
+    constexpr int NT = D == 2 ? 2 : 6;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        int b, a, tgt;
+        T sg;
+        if (D == 2) {
+            b = t; a = 0;
+            tgt = t == 0 ? 1 : 0;
+            sg = t == 0 ? T(-1) : T(1);
+        } else {
+            // D_x psi_z -> V_y -, D_x psi_y -> V_z +, D_y psi_z -> V_x +,
+            // D_y psi_x -> V_z -, D_z psi_y -> V_x -, D_z psi_x -> V_y +
+            constexpr int B3[6] = {0, 0, 1, 1, 2, 2};
+            constexpr int A3[6] = {2, 1, 2, 0, 1, 0};
+            constexpr int T3[6] = {1, 2, 0, 2, 0, 1};
+            constexpr int S3[6] = {-1, 1, 1, -1, -1, 1};
+            b = B3[t]; a = A3[t]; tgt = T3[t]; sg = T(S3[t]);
+        }
+        int xp = x, xm = x, yp = y, ym = y, zp = z, zm = z;
+        bool okp = true, okm = true;
+        if (b == 0) { xp = wrapi(x + 1, nx); xm = wrapi(x - 1, nx); }
+        if (b == 1) {
+            yp = y + 1; ym = y - 1;
+            if (m.walls) { okp = yp < ny; okm = ym >= 0; }
+            else { yp = wrapi(yp, ny); ym = wrapi(ym, ny); }
+        }
+        if (b == 2) { zp = wrapi(z + 1, nz); zm = wrapi(z - 1, nz); }
+        const size_t cp = (size_t)xp + (size_t)nx * (yp + (size_t)ny * zp);
+        const size_t cm = (size_t)xm + (size_t)nx * (ym + (size_t)ny * zm);
+        T diff[kMaxPow + 1];
+#pragma unroll
+        for (int jj = 0; jj <= kMaxPow; ++jj) {
+            const T* Wj = W + ((size_t)jj * NC + a) * sN;
+            const T fp = (jj <= jw && okp) ? Wj[cp] : T(0);
+            const T fm = (jj <= jw && okm) ? Wj[cm] : T(0);
+            diff[jj] = T(0.5) * (fp - fm);
+        }
+#pragma unroll
+        for (int s = 0; s < MAXSA; ++s) {
+            if (s >= nsa || prm->sa_kind[s] == 0) continue;
+            T d = 0;
+#pragma unroll
+            for (int jj = 0; jj <= kMaxPow; ++jj) d += T(prm->rr[s][jj]) * diff[jj];
+            V[s][tgt] += sg * d;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // K2c: per-cell QoIs, sensitivities and Gram products, FP64 partial sums per
 // workgroup.  Workgroups cover one y row (2-D) or one y plane (3-D) each, so
 // the mean-profile partial sums stay separated by y.
@@ -515,19 +691,18 @@ template <int LAT, typename T, int MAXSA>
 __global__ __launch_bounds__(kBlock) void k_reduce(const DevMember* __restrict__ mems, const int2* __restrict__ work)
 {
     using L = Lat<LAT>;
-    constexpr int D = L::D, NC = L::NC;
+    constexpr int D = L::D;
     constexpr int NG = MAXSA * (MAXSA + 1) / 2;
     constexpr int NV = MAXSA + NG + 1 + MAXSA;
     __shared__ double lds[NV * (kBlock / 64)];
     const int2 wk = work[blockIdx.x];
     const DevMember& m = mems[wk.x];
     const DevParam* __restrict__ prm = m.prm;
-    const int N = m.N, nx = m.nx, ny = m.ny, nz = m.nz;
+    const int nx = m.nx, ny = m.ny, nz = m.nz;
     const int y = wk.y / m.nbx2, bx = wk.y % m.nbx2;
     const int plane = nx * nz;
-    const int nsa = prm->nsa, jv = prm->jv, jw = prm->jw;
+    const int nsa = prm->nsa;
     const bool hasmp = prm->nmp > 0;
-    const size_t sN = (size_t)N;
     double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0;
@@ -536,48 +711,12 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const DevMember* __restrict__
         if (p >= plane) break;
         const int x = p % nx, z = p / nx;
         const int cell = x + nx * (y + ny * z);
-        // powers of B applied to v* at this cell
         T pv[kMaxPow + 1][D];
-#pragma unroll
-        for (int a = 0; a < D; ++a) pv[0][a] = ((const T*)m.vs)[a * sN + cell];
-#pragma unroll
-        for (int jj = 1; jj <= kMaxPow; ++jj)
-#pragma unroll
-            for (int a = 0; a < D; ++a)
-                pv[jj][a] = jj <= jv ? ((const T*)m.P)[((size_t)(jj - 1) * D + a) * sN + cell] : T(0);
         T V[MAXSA][D];
+        double qd[MAXSA];
+        cell_sens<LAT, T, MAXSA>(m, prm, x, y, z, cell, pv, V, qd);
 #pragma unroll
-        for (int s = 0; s < MAXSA; ++s) {
-#pragma unroll
-            for (int a = 0; a < D; ++a) V[s][a] = 0;
-            if (s >= nsa) continue;
-            const double* r = prm->r[s];
-            const double* rr = prm->rr[s];
-            double q = 0;
-            if (prm->sa_kind[s] == 0) {
-#pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    T rv = T(r[0]) * pv[0][a] + T(r[1]) * pv[1][a] + T(r[2]) * pv[2][a];
-                    q += 0.5 * (double)(rv * rv);
-                    T vv = 0;
-#pragma unroll
-                    for (int jj = 0; jj <= kMaxPow; ++jj) vv += T(rr[jj]) * pv[jj][a];
-                    V[s][a] = vv;
-                }
-            } else {
-                const T* Wc = (const T*)m.W;
-#pragma unroll
-                for (int a = 0; a < NC; ++a) {
-                    T rw = 0;
-#pragma unroll
-                    for (int jj = 0; jj <= 2; ++jj)
-                        if (jj <= jw && r[jj] != 0.0) rw += T(r[jj]) * Wc[((size_t)jj * NC + a) * sN + cell];
-                    q += 0.5 * (double)(rw * rw);
-                }
-                zsens<D, T>(Wc, sN, jw, rr, x, y, z, nx, ny, nz, m.walls, V[s]);
-            }
-            acc[s] += q;
-        }
+        for (int s = 0; s < MAXSA; ++s) acc[s] += qd[s];
         int g = 0;
 #pragma unroll
         for (int s = 0; s < MAXSA; ++s)
@@ -596,14 +735,29 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const DevMember* __restrict__
     }
     block_sum<NV>(acc, lds);
     if (threadIdx.x == 0) {
+        // compile-time indices into acc keep it in registers
         double* out = m.part_to + (size_t)wk.y * m.npart;
-        int o = 0;
-        for (int s = 0; s < nsa; ++s) out[o++] = acc[s];
-        for (int s = 0; s < nsa; ++s)
-            for (int t2 = s; t2 < nsa; ++t2) out[o++] = acc[MAXSA + s * MAXSA - s * (s - 1) / 2 + (t2 - s)];
+#pragma unroll
+        for (int s = 0; s < MAXSA; ++s)
+            if (s < nsa) out[s] = acc[s];
+        int g = 0;
+#pragma unroll
+        for (int s = 0; s < MAXSA; ++s)
+#pragma unroll
+            for (int t2 = s; t2 < MAXSA; ++t2, ++g)
+                if (t2 < nsa) out[nsa + s * nsa - s * (s - 1) / 2 + (t2 - s)] = acc[MAXSA + g];
         if (hasmp) {
-            out[o++] = acc[MAXSA + NG];
-            for (int s = 0; s < nsa; ++s) out[o++] = acc[MAXSA + NG + 1 + s];
+            // mean-profile terms, weighted by the band weights of this row:
+            // w_j(y) sum v*_x and w_j(y) sum V_s,x for every band j
+            const int o = nsa + nsa * (nsa + 1) / 2;
+            for (int jm = 0; jm < prm->nmp; ++jm) {
+                const double wj = m.bandw[(size_t)prm->mp_band[jm] * ny + y];
+                double* oj = out + o + jm * (1 + nsa);
+                oj[0] = wj * acc[MAXSA + NG];
+#pragma unroll
+                for (int s = 0; s < MAXSA; ++s)
+                    if (s < nsa) oj[1 + s] = wj * acc[MAXSA + NG + 1 + s];
+            }
         }
     }
 }
@@ -663,183 +817,181 @@ __global__ void k_normals_test(unsigned long long seed, long long step0, int nst
 }
 
 // ---------------------------------------------------------------------------
+// K2d: cross-block sums, one workgroup per (member, value slot).  Slots 0..3
+// sum the statistics of the stream-collide workgroups, slots 4.. the TO
+// partials of the reduce workgroups; the order is fixed by the member's own
+// block counts.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_sum(const DevMember* __restrict__ mems, const int2* __restrict__ work)
+{
+    __shared__ double red[kBlock / 64];
+    const int2 wk = work[blockIdx.x];
+    const DevMember& m = mems[wk.x];
+    const int slot = wk.y;
+    if (slot >= 4 + m.npart) return;
+    double v[1] = {0};
+    if (slot < 4) {
+        for (int b = threadIdx.x; b < m.nb1; b += kBlock) v[0] += m.part_stats[(size_t)b * 4 + slot];
+    } else {
+        const int nblk = m.ny * m.nbx2;
+        for (int b = threadIdx.x; b < nblk; b += kBlock) v[0] += m.part_to[(size_t)b * m.npart + slot - 4];
+    }
+    block_sum<1>(v, red);
+    if (threadIdx.x == 0) m.sums[slot] = v[0];
+}
+
+// ---------------------------------------------------------------------------
 // K3: one workgroup per member.  Fixed-order sums of the partials, the QoI
-// vector and Gram matrix, dQ, the Cholesky solve G beta = dQ, gamma, the
-// per-step record and the coefficients of the dv build.
+// vector and Gram matrix, dQ, beta = G^-1 dQ and gamma_k = dQ_k (G^-1)_kk,
+// the per-step record and the coefficients of the dv build.  All small
+// matrices live in LDS and every stage is spread over the workgroup.
+// G is symmetric positive semi-definite, so Gauss-Jordan elimination needs
+// no pivoting; its pivots are the squared Cholesky pivots, and G counts as
+// singular when one of them is not above 1e-14 times the largest diagonal
+// entry.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ mems, const int* __restrict__ work)
 {
-    __shared__ double red[4 * (kBlock / 64) * 8];
-    __shared__ double sflat[kMaxSA + kMaxSA * (kMaxSA + 1) / 2 + 4];
-    __shared__ double G[kMaxQ * kMaxQ];
-    __shared__ double q[kMaxQ];
-    __shared__ double beta[kMaxQ];
+    __shared__ double st[4];
+    __shared__ double M[kMaxQ][2 * kMaxQ];
+    __shared__ double q[kMaxQ], dq[kMaxQ], beta[kMaxQ], gam[kMaxQ], z[kMaxQ], fac[kMaxQ];
+    __shared__ int sing;
     const DevMember& m = mems[work[blockIdx.x]];
     const DevParam* __restrict__ prm = m.prm;
     DevCtl* ctl = m.ctl;
     const int tid = threadIdx.x;
     const int nq = prm->nq, nsa = prm->nsa, nmp = prm->nmp;
     const int ny = m.ny;
-    const int nblk = ny * m.nbx2;
     const int nflat = nsa + nsa * (nsa + 1) / 2;
-    const int np = m.npart;
+    const long long step = ctl->step;
 
-    // (a) mass and momentum of the post-streaming state
-    {
-        double v[4] = {0, 0, 0, 0};
-        for (int b = tid; b < m.nb1; b += kBlock)
-            for (int k = 0; k < 4; ++k) v[k] += m.part_stats[(size_t)b * 4 + k];
-        block_sum<4>(v, red);
-        if (tid == 0) {
-            sflat[kMaxSA + kMaxSA * (kMaxSA + 1) / 2 + 0] = v[0];
-            sflat[kMaxSA + kMaxSA * (kMaxSA + 1) / 2 + 1] = v[1];
-            sflat[kMaxSA + kMaxSA * (kMaxSA + 1) / 2 + 2] = v[2];
-            sflat[kMaxSA + kMaxSA * (kMaxSA + 1) / 2 + 3] = v[3];
+    // (a) sums of the statistics and TO partials (from k_sum)
+    for (int k = tid; k < kMaxQ * 2 * kMaxQ; k += kBlock) M[k / (2 * kMaxQ)][k % (2 * kMaxQ)] = 0.0;
+    if (tid < kMaxQ) { q[tid] = 0; dq[tid] = 0; beta[tid] = 0; gam[tid] = 0; }
+    if (tid < 4) st[tid] = m.sums[tid];
+    if (tid == 0) sing = 0;
+    __syncthreads();
+    const double* sf = m.sums + 4;
+    // (b) assemble q and G (left half of M)
+    if (tid < nsa) {
+        const int s = tid;
+        q[prm->sa_slot[s]] = sf[s];
+        int g = nsa + s * nsa - s * (s - 1) / 2;
+        for (int t = s; t < nsa; ++t, ++g) {
+            M[prm->sa_slot[s]][prm->sa_slot[t]] = sf[g];
+            M[prm->sa_slot[t]][prm->sa_slot[s]] = sf[g];
         }
     }
-    // (b) QoI and Gram sums over all workgroups of the reduce
-    for (int k0 = 0; k0 < nflat; k0 += 8) {
-        double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int b = tid; b < nblk; b += kBlock)
-            for (int k = 0; k < 8; ++k)
-                if (k0 + k < nflat) v[k] += m.part_to[(size_t)b * np + k0 + k];
-        block_sum<8>(v, red);
-        if (tid == 0)
-            for (int k = 0; k < 8; ++k)
-                if (k0 + k < nflat) sflat[k0 + k] = v[k];
+    // (c) mean-profile QoIs and mixed Gram entries
+    for (int pr = tid; pr < nmp * (1 + nsa); pr += kBlock) {
+        const int jm = pr / (1 + nsa), c = pr % (1 + nsa);
+        const double v = sf[nflat + pr];
+        const int uj = prm->mp_slot[jm];
+        if (c == 0)
+            q[uj] = v;
+        else {
+            const int us = prm->sa_slot[c - 1];
+            M[uj][us] = v;
+            M[us][uj] = v;
+        }
+    }
+    for (int pr = tid; pr < nmp * nmp; pr += kBlock) {
+        const int a = pr / nmp, b = pr % nmp;
+        M[prm->mp_slot[a]][prm->mp_slot[b]] = prm->gmp[a * kMaxQ + b];
+    }
+    if (tid < nq) M[tid][kMaxQ + tid] = 1.0;
+    // (d) dQ: tracking, or the LRS draw
+    const bool active = step >= prm->spinup;
+    if (active && prm->mode == LBM_CLOSURE_LRS && tid < (nq + 3) / 4) {
+        // four normals per Philox block
+        double zz[4];
+        uint32_t c[4] = {(uint32_t)tid, (uint32_t)(unsigned long long)step,
+                         (uint32_t)((unsigned long long)step >> 32), 0x4C525331u};
+        philox4x32_10(c, (uint32_t)prm->seed, (uint32_t)(prm->seed >> 32));
+        for (int p = 0; p < 2; ++p) {
+            const double u1 = ((double)c[2 * p] + 0.5) * 2.3283064365386963e-10;
+            const double u2 = ((double)c[2 * p + 1] + 0.5) * 2.3283064365386963e-10;
+            const double rad = sqrt(-2.0 * log(u1));
+            double sn, cs;
+            sincospi(2.0 * u2, &sn, &cs);
+            zz[2 * p] = rad * cs;
+            zz[2 * p + 1] = rad * sn;
+        }
+        for (int k = 0; k < 4; ++k)
+            if (4 * tid + k < nq) z[4 * tid + k] = zz[k];
     }
     __syncthreads();
-    // (c) mean-profile QoIs and mixed Gram entries from the y profiles
-    if (tid < kMaxQ) q[tid] = 0.0;
-    for (int k = tid; k < kMaxQ * kMaxQ; k += kBlock) G[k] = 0.0;
+    if (active && tid < nq) {
+        const int k = tid;
+        if (prm->mode == LBM_CLOSURE_TRACK) {
+            if (step < prm->nref) dq[k] = prm->qref[(size_t)step * nq + k] - q[k];
+        } else if (prm->mode == LBM_CLOSURE_LRS) {
+            if (!ctl->s_set) ctl->s[k] = prm->have_scale ? prm->scale[k] : (q[k] != 0.0 ? fabs(q[k]) : 1.0);
+        }
+    }
     __syncthreads();
-    if (tid == 0) {
-        int g = nsa;
+    if (active && prm->mode == LBM_CLOSURE_LRS && tid < nq) {
+        const int k = tid;
+        double e = prm->mu[k];
+        for (int j = 0; j <= k; ++j) e += prm->L[k * kMaxQ + j] * z[j];
+        double zh = e;
+        for (int i = 0; i < nq; ++i) zh += (q[i] / ctl->s[i]) * prm->C[i * kMaxQ + k];
+        zh += prm->C[nq * kMaxQ + k];
+        dq[k] = ctl->s[k] * zh - q[k];
+    }
+    // (e) Gauss-Jordan on [G | I]
+    double mx = 0;
+    for (int k = 0; k < nq; ++k) mx = fmax(mx, M[k][k]);
+    if (!(mx > 0)) {
+        if (tid == 0) sing = 1;
+    }
+    __syncthreads();
+    for (int j = 0; j < nq && !sing; ++j) {
+        const double piv = M[j][j];
+        if (!(piv > 1e-14 * mx)) {
+            __syncthreads();
+            if (tid == 0) sing = 1;
+            __syncthreads();
+            break;
+        }
+        if (tid < nq) fac[tid] = M[tid][j];
+        __syncthreads();
+        for (int cidx = tid; cidx < 2 * kMaxQ; cidx += kBlock) M[j][cidx] /= piv;
+        __syncthreads();
+        for (int e = tid; e < nq * 2 * kMaxQ; e += kBlock) {
+            const int i = e / (2 * kMaxQ), cc = e % (2 * kMaxQ);
+            if (i != j) M[i][cc] -= fac[i] * M[j][cc];
+        }
+        __syncthreads();
+    }
+    // (f) beta = G^-1 dQ, gamma_k = dQ_k (G^-1)_kk
+    if (!sing && tid < nq) {
+        double b = 0;
+        for (int j = 0; j < nq; ++j) b += M[tid][kMaxQ + j] * dq[j];
+        beta[tid] = b;
+        gam[tid] = dq[tid] * M[tid][kMaxQ + tid];
+    }
+    __syncthreads();
+    // (g) dv coefficients, record, counters
+    if (tid <= kMaxPow) {
+        double a = 0, b = 0;
         for (int s = 0; s < nsa; ++s) {
-            q[prm->sa_slot[s]] = sflat[s];
-            for (int t = s; t < nsa; ++t, ++g) {
-                G[prm->sa_slot[s] * nq + prm->sa_slot[t]] = sflat[g];
-                G[prm->sa_slot[t] * nq + prm->sa_slot[s]] = sflat[g];
-            }
+            const double bs = beta[prm->sa_slot[s]];
+            if (prm->sa_kind[s] == 0) a += bs * prm->rr[s][tid];
+            else b += bs * prm->rr[s][tid];
         }
+        ctl->cv[tid] = a;
+        ctl->cw[tid] = b;
     }
-    if (nmp > 0) {
-        // pairs (j, c): c = 0 -> q_mp_j = sum_y w_j U(y); c = 1+s -> G[mp_j, sa_s] = sum_y w_j P_s(y)
-        const int npair = nmp * (1 + nsa);
-        for (int pr = tid; pr < npair; pr += kBlock) {
-            const int jm = pr / (1 + nsa), c = pr % (1 + nsa);
-            const double* w = m.bandw + (size_t)prm->mp_band[jm] * ny;
-            double acc = 0;
-            for (int yy = 0; yy < ny; ++yy) {
-                double py = 0;
-                for (int b = 0; b < m.nbx2; ++b) py += m.part_to[((size_t)yy * m.nbx2 + b) * np + nflat + c];
-                acc += w[yy] * py;
-            }
-            const int uj = prm->mp_slot[jm];
-            if (c == 0)
-                q[uj] = acc;
-            else {
-                const int us = prm->sa_slot[c - 1];
-                G[uj * nq + us] = acc;
-                G[us * nq + uj] = acc;
-            }
-        }
-        for (int pr = tid; pr < nmp * nmp; pr += kBlock) {
-            const int a = pr / nmp, b = pr % nmp;
-            G[prm->mp_slot[a] * nq + prm->mp_slot[b]] = prm->gmp[a * kMaxQ + b];
-        }
+    lbm_qoi_rec* rec = m.recs + (size_t)(step % m.rec_cap);
+    if (tid < kMaxQ) {
+        rec->q[tid] = tid < nq ? q[tid] : 0.0;
+        rec->dq[tid] = tid < nq ? dq[tid] : 0.0;
+        rec->gamma[tid] = tid < nq ? gam[tid] : 0.0;
     }
-    __syncthreads();
-
-    // (d) dQ, solve, record (serial: nq <= 16)
     if (tid == 0) {
-        const long long step = ctl->step;
-        double dq[kMaxQ], gam[kMaxQ];
-        for (int k = 0; k < nq; ++k) { dq[k] = 0; gam[k] = 0; beta[k] = 0; }
-        if (step >= prm->spinup && prm->mode == LBM_CLOSURE_TRACK) {
-            if (step < prm->nref)
-                for (int k = 0; k < nq; ++k) dq[k] = prm->qref[(size_t)step * nq + k] - q[k];
-        } else if (step >= prm->spinup && prm->mode == LBM_CLOSURE_LRS) {
-            if (!ctl->s_set) {
-                for (int k = 0; k < nq; ++k) ctl->s[k] = prm->have_scale ? prm->scale[k] : (q[k] != 0.0 ? fabs(q[k]) : 1.0);
-                ctl->s_set = 1;
-            }
-            double z[kMaxQ], eta[kMaxQ], x[kMaxQ + 1];
-            lrs_normals(prm->seed, step, nq, z);
-            for (int k = 0; k < nq; ++k) {
-                double e = prm->mu[k];
-                for (int j = 0; j <= k; ++j) e += prm->L[k * kMaxQ + j] * z[j];
-                eta[k] = e;
-                x[k] = q[k] / ctl->s[k];
-            }
-            x[nq] = 1.0;
-            for (int k = 0; k < nq; ++k) {
-                double zh = eta[k];
-                for (int i = 0; i <= nq; ++i) zh += x[i] * prm->C[i * kMaxQ + k];
-                dq[k] = ctl->s[k] * zh - q[k];
-            }
-        }
-        // Cholesky G = L L^T; singular when a pivot <= 1e-14 max diag
-        double Lc[kMaxQ * kMaxQ];
-        double mx = 0;
-        for (int k = 0; k < nq; ++k) mx = fmax(mx, G[k * nq + k]);
-        int sg = !(mx > 0);
-        for (int jj = 0; jj < nq && !sg; ++jj) {
-            double s = G[jj * nq + jj];
-            for (int k = 0; k < jj; ++k) s -= Lc[jj * kMaxQ + k] * Lc[jj * kMaxQ + k];
-            if (!(s > 1e-14 * mx)) { sg = 1; break; }
-            const double d = sqrt(s);
-            Lc[jj * kMaxQ + jj] = d;
-            for (int i = jj + 1; i < nq; ++i) {
-                double t = G[i * nq + jj];
-                for (int k = 0; k < jj; ++k) t -= Lc[i * kMaxQ + k] * Lc[jj * kMaxQ + k];
-                Lc[i * kMaxQ + jj] = t / d;
-            }
-        }
-        if (!sg) {
-            // beta = G^-1 dQ by forward and back substitution
-            double yv[kMaxQ];
-            for (int i = 0; i < nq; ++i) {
-                double t = dq[i];
-                for (int k = 0; k < i; ++k) t -= Lc[i * kMaxQ + k] * yv[k];
-                yv[i] = t / Lc[i * kMaxQ + i];
-            }
-            for (int i = nq - 1; i >= 0; --i) {
-                double t = yv[i];
-                for (int k = i + 1; k < nq; ++k) t -= Lc[k * kMaxQ + i] * beta[k];
-                beta[i] = t / Lc[i * kMaxQ + i];
-            }
-            // gamma_k = dQ_k (G^-1)_kk, (G^-1)_kk = sum_m ((L^-1)_mk)^2
-            for (int k = 0; k < nq; ++k) {
-                double e[kMaxQ], s2 = 0;
-                for (int i = 0; i < nq; ++i) {
-                    double t = i == k ? 1.0 : 0.0;
-                    for (int j2 = 0; j2 < i; ++j2) t -= Lc[i * kMaxQ + j2] * e[j2];
-                    e[i] = i < k ? 0.0 : t / Lc[i * kMaxQ + i];
-                    s2 += e[i] * e[i];
-                }
-                gam[k] = dq[k] * s2;
-            }
-        } else {
-            for (int k = 0; k < nq; ++k) beta[k] = 0;
-        }
-        // coefficients of the dv build: sum over E QoIs of beta R R for v,
-        // over Z QoIs for curl v
-        for (int jj = 0; jj <= kMaxPow; ++jj) {
-            double a = 0, b = 0;
-            for (int s = 0; s < nsa; ++s) {
-                const double bs = beta[prm->sa_slot[s]];
-                if (prm->sa_kind[s] == 0) a += bs * prm->rr[s][jj];
-                else b += bs * prm->rr[s][jj];
-            }
-            ctl->cv[jj] = a;
-            ctl->cw[jj] = b;
-        }
-        // record
-        lbm_qoi_rec* rec = m.recs + (size_t)(step % m.rec_cap);
-        const double* st = sflat + kMaxSA + kMaxSA * (kMaxSA + 1) / 2;
         rec->step = step;
-        rec->flags = (ctl->flags & 1) | (sg ? 2 : 0);
+        rec->flags = (ctl->flags & 1) | (sing ? 2 : 0);
         rec->nq = nq;
         rec->mass = (double)m.N + st[0];
         rec->mom[0] = st[1];
@@ -847,15 +999,10 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
         rec->mom[2] = st[3];
         rec->diag_e = 0;
         rec->diag_z = 0;
-        for (int k = 0; k < kMaxQ; ++k) {
-            rec->q[k] = k < nq ? q[k] : 0.0;
-            rec->dq[k] = k < nq ? dq[k] : 0.0;
-            rec->gamma[k] = k < nq ? gam[k] : 0.0;
-        }
+        if (active && prm->mode == LBM_CLOSURE_LRS) ctl->s_set = 1;
         ctl->step = step + 1;
     }
-    __syncthreads();
-    // (e) mean-profile part of dv: cmp(y) = sum_j beta_mp_j w_j(y)
+    // (h) mean-profile part of dv: cmp(y) = sum_j beta_mp_j w_j(y)
     for (int yy = tid; yy < ny; yy += kBlock) {
         double c = 0;
         for (int jm = 0; jm < nmp; ++jm) c += beta[prm->mp_slot[jm]] * m.bandw[(size_t)prm->mp_band[jm] * ny + yy];
@@ -1140,13 +1287,16 @@ static void launch_step_group(const LaunchGroup& g, hipStream_t st, int flip, hi
         if (g.any_z) hipLaunchKernelGGL((k_curl<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1);
         mark(2);
         for (int j = 1; j <= g.maxpow; ++j)
-            hipLaunchKernelGGL((k_binom<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, j);
+            hipLaunchKernelGGL((k_binom<LAT, T>), dim3(g.nbb), blk, 0, st, g.mems, g.workb, j);
         mark(3);
         if (g.maxsa <= 2)
             hipLaunchKernelGGL((k_reduce<LAT, T, 2>), dim3(g.nbr), blk, 0, st, g.mems, g.workr);
+        else if (g.maxsa <= 6)
+            hipLaunchKernelGGL((k_reduce<LAT, T, 6>), dim3(g.nbr), blk, 0, st, g.mems, g.workr);
         else
             hipLaunchKernelGGL((k_reduce<LAT, T, kMaxSA>), dim3(g.nbr), blk, 0, st, g.mems, g.workr);
         mark(4);
+        hipLaunchKernelGGL(k_sum, dim3(g.nbs), blk, 0, st, g.mems, g.works);
         hipLaunchKernelGGL(k_solve, dim3(g.nmem), blk, 0, st, g.mems, g.workm);
         mark(5);
         hipLaunchKernelGGL((k_apply<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1);

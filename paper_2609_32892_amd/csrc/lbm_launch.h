@@ -17,6 +17,10 @@ struct LaunchGroup {
     int nb1;
     const int2* workr;  // reduce: (member, y * nbx2 + bx)
     int nbr;
+    const int2* workb;  // binomial filter: (member, xyz tile)
+    int nbb;
+    const int2* works;  // cross-block sums: (member, value slot)
+    int nbs;
     const int* workm;   // one workgroup per member
     int nmem;
 };
@@ -25,7 +29,7 @@ enum { OP_INIT = 0, OP_GET_POP = 1, OP_SET_POP = 2, OP_STREAM = 3, OP_FLUSH = 4 
 
 // ev (nullable): 7 events recorded at the phase boundaries of the step
 // (start, after stream-collide, after curl, after the binomial powers, after
-// the reduce, after the solve, after the apply).
+// the reduce, after the cross-block sums and solve, after the apply).
 constexpr int kNumPhases = 6;
 void launch_step(const LaunchGroup& g, hipStream_t st, int flip, hipEvent_t* ev = nullptr);
 void launch_state(int op, int lattice, int precision, const DevMember* dm, int N, bool has_to, int flip,
