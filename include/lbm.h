@@ -78,6 +78,8 @@ typedef struct {
     int diag;           /* plain runs: 1 records mass, momentum, E and Z of the
                            post-streaming velocity every step */
     int rec_cap;        /* capacity of the per-step record ring (0: 4096) */
+    int tune_zc;        /* tuning: z planes per binomial-filter workgroup (0: automatic) */
+    int tune_cpt;       /* tuning: cells per thread of the QoI reduction (0: automatic) */
 } lbm_config;
 
 enum { LBM_QOI_E = 0, LBM_QOI_Z = 1, LBM_QOI_MP = 2 };

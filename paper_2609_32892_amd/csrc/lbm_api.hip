@@ -105,12 +105,13 @@ int check_config(const lbm_config* c)
     if (c->substrate == LBM_WALE && c->lattice != LBM_D3Q19) return fail(LBM_EINVAL, "WALE needs D3Q19");
     if (c->force_kind < LBM_FORCE_NONE || c->force_kind > LBM_FORCE_CONST_X) return fail(LBM_EINVAL, "bad force kind");
     if (c->rec_cap < 0) return fail(LBM_EINVAL, "rec_cap < 0");
+    if (c->tune_zc < 0 || c->tune_cpt < 0) return fail(LBM_EINVAL, "tuning values must be >= 0");
     return LBM_OK;
 }
 
 struct Plan {
     size_t member, param, ctl, recs, g0, g1, fprof, vn, part_stats, part_diag, work1, workm;
-    size_t rho, vs, dv, P, W, part_to, bandw, cmp, workr, workb, sums, works;
+    size_t rho, vs, dv, P, W, Cf, part_to, bandw, cmp, workr, workb, sums, works;
     size_t total;
     int N, D, NC, Q, esz, nb1, nbx2, cpt2, nbr, nbb, nbs, zc, rec_cap;
     ClosureShape cap;
@@ -128,13 +129,15 @@ void make_plan(const lbm_config* c, const ClosureShape& cs, Plan* p)
     P.rec_cap = c->rec_cap > 0 ? c->rec_cap : 4096;
     P.cap = cs;
     const int plane = c->nx * c->nz;
-    P.cpt2 = std::max(1, std::min(8, P.N / (kBlock * 2048)));
+    P.cpt2 = c->tune_cpt > 0 ? std::min(c->tune_cpt, 64) : std::max(2, std::min(8, P.N / (kBlock * 2048)));
     P.nbx2 = (plane + kBlock * P.cpt2 - 1) / (kBlock * P.cpt2);
     P.nbr = P.nbx2 * c->ny;
     {
         // z chunk: as many planes per workgroup as keeps >= 1024 workgroups
         const int nxy = ((c->nx + kBinTX - 1) / kBinTX) * ((c->ny + kBinTY - 1) / kBinTY);
-        P.zc = P.D == 3 ? std::max(1, std::min(kBinZCMax, nxy * c->nz / 1024)) : 1;
+        P.zc = P.D == 3 ? (c->tune_zc > 0 ? std::min(c->tune_zc, c->nz)
+                                           : std::max(1, std::min(kBinZCMax, nxy * c->nz / 1024)))
+                        : 1;
         P.nbb = nxy * (P.D == 3 ? (c->nz + P.zc - 1) / P.zc : 1);
     }
     const size_t N = P.N, e = P.esz;
@@ -155,9 +158,10 @@ void make_plan(const lbm_config* c, const ClosureShape& cs, Plan* p)
     if (cs.nq > 0) {
         P.rho = take(e * N);
         P.vs = take(e * P.D * N);
-        P.dv = take(e * P.D * N);
+        P.dv = take(e * 8 * N);
         P.P = take(e * (size_t)std::max(cs.jv, 1) * P.D * N);
         P.W = take(cs.has_z ? e * (size_t)(cs.jw + 1) * P.NC * N : kAlign);
+        P.Cf = take(cs.has_z ? e * (size_t)(cs.jw + 1) * P.D * N : kAlign);
         P.part_to = take(sizeof(double) * (size_t)std::max(cs.npart(), 1) * P.nbr);
         P.bandw = take(sizeof(double) * (size_t)std::max(cs.nbands, 1) * c->ny);
         P.cmp = take(sizeof(double) * c->ny);
@@ -263,6 +267,7 @@ LaunchGroup ctx_group(const lbm_ctx* c)
     g.any_z = c->cur.has_z;
     g.maxpow = std::max(c->cur.jv, c->cur.jw);
     g.maxsa = c->cur.nsa;
+    g.npass = std::max(c->cur.jv, c->cur.has_z ? c->cur.jw + 1 : 0);
     g.mems = c->dm;
     g.work1 = (const int2*)(c->arena + c->plan.work1);
     g.nb1 = c->plan.nb1;
@@ -499,7 +504,7 @@ int lbm_create(const lbm_config* cfg, const lbm_closure* closure, void* dev_aren
     m.recs = (lbm_qoi_rec*)(A + plan.recs);
     m.fprof = (double*)(A + plan.fprof);
     if (c->has_to) {
-        m.rho = A + plan.rho; m.vs = A + plan.vs; m.dv = A + plan.dv; m.P = A + plan.P; m.W = A + plan.W;
+        m.rho = A + plan.rho; m.vs = A + plan.vs; m.pc = A + plan.dv; m.P = A + plan.P; m.W = A + plan.W; m.C = A + plan.Cf;
         m.part_to = (double*)(A + plan.part_to);
         m.bandw = (double*)(A + plan.bandw);
         m.cmp = (double*)(A + plan.cmp);
@@ -744,7 +749,7 @@ size_t lbm_state_bytes(const lbm_ctx* c)
     if (!c) return 0;
     const Plan& p = c->plan;
     size_t b = sizeof(StateHeader) + (size_t)p.esz * p.Q * p.N + sizeof(DevCtl) + sizeof(lbm_qoi_rec) * p.rec_cap;
-    if (c->has_to) b += (size_t)p.esz * p.N * (1 + 2 * p.D);
+    if (c->has_to) b += (size_t)p.esz * p.N * (1 + p.D + 8);
     return b;
 }
 
@@ -765,7 +770,7 @@ int lbm_get_state(lbm_ctx* c, void* host, size_t bytes)
         const size_t fb = (size_t)p.esz * p.N;
         HIPCHK(hipMemcpy(o, c->hm.rho, fb, hipMemcpyDeviceToHost)); o += fb;
         HIPCHK(hipMemcpy(o, c->hm.vs, fb * p.D, hipMemcpyDeviceToHost)); o += fb * p.D;
-        HIPCHK(hipMemcpy(o, c->hm.dv, fb * p.D, hipMemcpyDeviceToHost)); o += fb * p.D;
+        HIPCHK(hipMemcpy(o, c->hm.pc, fb * 8, hipMemcpyDeviceToHost)); o += fb * 8;
     }
     HIPCHK(hipMemcpy(o, c->arena + p.ctl, sizeof(DevCtl), hipMemcpyDeviceToHost));
     o += sizeof(DevCtl);
@@ -793,7 +798,7 @@ int lbm_set_state(lbm_ctx* c, const void* host, size_t bytes)
         const size_t fb = (size_t)p.esz * p.N;
         HIPCHK(hipMemcpy(c->hm.rho, o, fb, hipMemcpyHostToDevice)); o += fb;
         HIPCHK(hipMemcpy(c->hm.vs, o, fb * p.D, hipMemcpyHostToDevice)); o += fb * p.D;
-        HIPCHK(hipMemcpy(c->hm.dv, o, fb * p.D, hipMemcpyHostToDevice)); o += fb * p.D;
+        HIPCHK(hipMemcpy(c->hm.pc, o, fb * 8, hipMemcpyHostToDevice)); o += fb * 8;
     }
     HIPCHK(hipMemcpy(c->arena + p.ctl, o, sizeof(DevCtl), hipMemcpyHostToDevice));
     o += sizeof(DevCtl);
@@ -898,6 +903,7 @@ static int batch_build(lbm_batch* b)
             g.any_z |= c->cur.has_z;
             g.maxpow = std::max(g.maxpow, std::max(c->cur.jv, c->cur.jw));
             g.maxsa = std::max(g.maxsa, c->cur.nsa);
+            g.npass = std::max(g.npass, std::max(c->cur.jv, c->cur.has_z ? c->cur.jw + 1 : 0));
         }
         g.mems = b->dmem;
         g.work1 = b->dwork + offs[gi].w1;
@@ -1018,7 +1024,7 @@ int lbm_profile_phases(lbm_ctx* c, long nsteps, double* ms, int* launches)
         const int m = g.mode;
         launches[0] = 1 + (g.substrate == LBM_WALE ? 1 : 0);
         launches[1] = m == 2 && g.any_z ? 1 : 0;
-        launches[2] = m == 2 ? g.maxpow : 0;
+        launches[2] = m == 2 ? g.npass : 0;
         launches[3] = m == 2 ? 1 : 0;
         launches[4] = m == 2 ? 1 : 0;
         launches[5] = m == 2 ? 1 : (m == 1 ? 2 : 0);

@@ -17,7 +17,7 @@ constexpr int kMaxPow = 4;      // highest power of B in R R (filters up to degr
 constexpr int kBlock = 256;     // threads per workgroup of the cell kernels
 constexpr int kBinTX = 32;      // binomial-filter tile: x extent
 constexpr int kBinTY = kBlock / kBinTX;  // y extent
-constexpr int kBinZCMax = 8;    // most z planes per workgroup (3-D)
+constexpr int kBinZCMax = 16;   // most z planes per workgroup chosen automatically (3-D)
 
 // Constant closure parameters (written by the host at set_closure).
 struct DevParam {
@@ -60,10 +60,11 @@ struct DevMember {
     void* g[2];                        // populations [Q][N]
     void* rho;                         // rho - 1 of the predictor [N]      (TO)
     void* vs;                          // predictor velocity v* [D][N]      (TO)
-    void* dv;                          // pending SGS increment [D][N]      (TO)
+    void* pc;                          // pending SGS correction records [N] (TO): 8 values per cell
     void* vn;                          // post-streaming velocity [D][N]    (diag, WALE)
     void* P;                           // B^j v*, j = 1..jv   [jv][D][N]
     void* W;                           // B^j curl v*, j=0..jw [jw+1][NC][N]
+    void* C;                           // curl^T B^j curl v*, j=0..jw [jw+1][D][N]
     double* part_stats;                // [nb1][4]: sum(rho-1), sum(rho v)
     double* part_to;                   // [ny][nbx2][npart]
     double* part_diag;                 // [nb1][2]

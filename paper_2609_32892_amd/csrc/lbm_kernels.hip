@@ -101,6 +101,28 @@ __device__ __forceinline__ T dfeq(T w, T rho, T cd, T cs, T dd)
 // Pull gather of the post-collision populations of cell (x,y,z), including
 // the pending SGS correction of each source cell when TO is active.
 // ---------------------------------------------------------------------------
+// Packed pending-correction record of a cell (written by k_apply): with
+// a = rho dv, b = 2 v* + dv and e = rho dv.(2 v* + dv), the SGS change of
+// the post-collision population i is
+//   delta f_i = feq_i(rho, v* + dv) - feq_i(rho, v*)
+//             = w_i [3 c_i.a + 9/2 (c_i.a)(c_i.b) - 3/2 e].
+// Layout: u = (a_x, a_y, a_z, e), v = (b_x, b_y, b_z, 0) (2-D: a_z = b_z = 0).
+template <typename T> struct alignas(4 * sizeof(T)) Vec4 { T x, y, z, w; };
+template <typename T> struct PendRec { Vec4<T> u, v; };
+
+template <int LAT, typename T>
+__device__ __forceinline__ T pend_df(const PendRec<T>& r, int i, T sg)
+{
+    using L = Lat<LAT>;
+    const T ca = T(L::cx[i]) * r.u.x + T(L::cy[i]) * r.u.y + (L::D == 3 ? T(L::cz[i]) * r.u.z : T(0));
+    const T cb = T(L::cx[i]) * r.v.x + T(L::cy[i]) * r.v.y + (L::D == 3 ? T(L::cz[i]) * r.v.z : T(0));
+    return T(L::w[i]) * (T(3) * sg * ca + T(4.5) * ca * cb - T(1.5) * r.u.w);
+}
+
+// ---------------------------------------------------------------------------
+// Pull gather of the post-collision populations of cell (x,y,z), including
+// the pending SGS correction of each source cell when TO is active.
+// ---------------------------------------------------------------------------
 template <int LAT, typename T, bool TO>
 __device__ __forceinline__ void gather(const DevMember& m, const T* __restrict__ gs, int x, int y, int z,
                                        int cell, T* f)
@@ -108,9 +130,7 @@ __device__ __forceinline__ void gather(const DevMember& m, const T* __restrict__
     using L = Lat<LAT>;
     constexpr int Q = L::Q, D = L::D;
     const int N = m.N, nx = m.nx, ny = m.ny, nz = m.nz;
-    const T* __restrict__ rho = (const T*)m.rho;
-    const T* __restrict__ vs = (const T*)m.vs;
-    const T* __restrict__ dv = (const T*)m.dv;
+    const PendRec<T>* __restrict__ pc = (const PendRec<T>*)m.pc;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         int sy = y - L::cy[i];
@@ -128,22 +148,9 @@ __device__ __forceinline__ void gather(const DevMember& m, const T* __restrict__
         }
         T v = gs[(size_t)pi * N + src];
         if (TO) {
-            // delta f_pi(src) = feq_pi(rho, v*+dv) - feq_pi(rho, v*); c_pi = s c_i
-            const T sg = bb ? T(-1) : T(1);
-            T r = T(1) + rho[src];
-            T cd = 0, cs = 0, dd = 0;
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                const int ca = a == 0 ? L::cx[i] : (a == 1 ? L::cy[i] : L::cz[i]);
-                T d = dv[(size_t)a * N + src];
-                T s2 = T(2) * vs[(size_t)a * N + src] + d;
-                if (ca != 0) {
-                    cd += T(ca) * d;
-                    cs += T(ca) * s2;
-                }
-                dd += d * s2;
-            }
-            v += T(L::w[i]) * r * (T(3) * sg * cd + T(4.5) * cd * cs - T(1.5) * dd);
+            // delta f_pi(src) with c_pi = s c_i
+            const PendRec<T> r = pc[src];
+            v += pend_df<LAT, T>(r, i, bb ? T(-1) : T(1));
         }
         f[i] = v;
     }
@@ -462,8 +469,10 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
     const int2 wk = work[blockIdx.x];
     const DevMember& m = mems[wk.x];
     const DevParam* prm = m.prm;
+    // this pass: B^j v (j <= jv), B^j w (j <= jw) and C_{j-1} = curl^T B^{j-1} w (j - 1 <= jw)
     const bool dov = j <= prm->jv, dow = prm->has_z && j <= prm->jw;
-    if (!dov && !dow) return;
+    const bool doc = prm->has_z && j - 1 <= prm->jw;
+    if (!dov && !doc) return;
     const int nx = m.nx, ny = m.ny, nz = m.nz;
     const size_t sN = (size_t)m.N;
     const int ntx = (nx + kBinTX - 1) / kBinTX, nty = (ny + kBinTY - 1) / kBinTY;
@@ -485,43 +494,83 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
 #pragma unroll
         for (int a = 0; a < D; ++a) { src[a] = sv + a * sN; dst[a] = dv + a * sN; }
     }
-    if (dow) {
+    T* cdst = nullptr;
+    if (doc) {
         const T* sw = (const T*)m.W + (size_t)(j - 1) * NC * sN;
         T* dw = (T*)m.W + (size_t)j * NC * sN;
 #pragma unroll
-        for (int a = 0; a < NC; ++a) { src[D + a] = sw + a * sN; dst[D + a] = dw + a * sN; }
+        for (int a = 0; a < NC; ++a) { src[D + a] = sw + a * sN; dst[D + a] = dow ? dw + a * sN : nullptr; }
+        cdst = (T*)m.C + (size_t)(j - 1) * D * sN;
     }
     const int zr = D == 3 ? 1 : 0;
     const int zend = D == 3 ? min(tz0 + zc, nz) : 1;
     T s0[NCMP], s1[NCMP];
+    T r1[NC], r2[NC], dxy[NC][2];   // w at planes z-1 and z (own cell), xy derivatives at z
 #pragma unroll
     for (int c = 0; c < NCMP; ++c) { s0[c] = 0; s1[c] = 0; }
-    for (int pz = tz0 - zr; pz <= zend - 1 + zr; ++pz) {
-        const int zz = D == 3 ? modi(pz, nz) : 0;
-        // stage plane zz with its xy halo
-        for (int e = threadIdx.x; e < HXY; e += kBlock) {
-            const int hx = e % HX, hy = e / HX;
-            const int gx = modi(tx0 + hx - 1, nx);
-            int gy = ty0 + hy - 1;
-            bool ok = true;
-            if (m.walls) ok = gy >= 0 && gy < ny;
-            else gy = modi(gy, ny);
-            const size_t gi = ok ? (size_t)gx + (size_t)nx * (gy + (size_t)ny * zz) : 0;
 #pragma unroll
-            for (int c = 0; c < NCMP; ++c)
-                if (src[c]) tile[c][e] = ok ? src[c][gi] : T(0);
+    for (int a = 0; a < NC; ++a) { r1[a] = 0; r2[a] = 0; dxy[a][0] = 0; dxy[a][1] = 0; }
+    // the (at most two) halo elements this thread stages, as offsets within a plane
+    constexpr int NE = (HXY + kBlock - 1) / kBlock;
+    int eoff[NE];
+    bool eok[NE];
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+        const int e = threadIdx.x + k * kBlock;
+        const int hx = e % HX, hy = e / HX;
+        int gx = tx0 + hx - 1;       // in [-1, nx + kBinTX - 1]
+        gx = gx < 0 ? gx + nx : (gx >= nx ? modi(gx, nx) : gx);
+        int gy = ty0 + hy - 1;       // in [-1, ny + kBinTY - 1]
+        bool ok = e < HXY;
+        if (m.walls) ok = ok && gy >= 0 && gy < ny;
+        else gy = gy < 0 ? gy + ny : (gy >= ny ? modi(gy, ny) : gy);
+        eok[k] = ok;
+        eoff[k] = ok ? gx + nx * gy : 0;
+    }
+    const int plane = nx * ny;
+    // software pipeline: the loads of the next plane are in flight while the
+    // current plane is filtered
+    T pre[NE][NCMP];
+    auto fetch = [&](int pz) {
+        const int zz = D == 3 ? modi(pz, nz) : 0;
+        const size_t zo = (size_t)plane * zz;
+#pragma unroll
+        for (int k = 0; k < NE; ++k)
+#pragma unroll
+            for (int c = 0; c < NCMP; ++c) pre[k][c] = (src[c] && eok[k]) ? src[c][zo + eoff[k]] : T(0);
+    };
+    fetch(tz0 - zr);
+    for (int pz = tz0 - zr; pz <= zend - 1 + zr; ++pz) {
+#pragma unroll
+        for (int k = 0; k < NE; ++k) {
+            const int e = threadIdx.x + k * kBlock;
+            if (e < HXY) {
+#pragma unroll
+                for (int c = 0; c < NCMP; ++c)
+                    if (src[c]) tile[c][e] = pre[k][c];
+            }
         }
         __syncthreads();
-        T sn[NCMP];
+        if (pz + 1 <= zend - 1 + zr) fetch(pz + 1);
+        T sn[NCMP], rn[NC], dn[NC][2];
 #pragma unroll
         for (int c = 0; c < NCMP; ++c) {
             sn[c] = 0;
             if (!src[c]) continue;
             const T* t = tile[c] + ly * HX + lx;   // (lx, ly) is the lower-left halo corner
-            const T r0 = T(0.25) * (t[0] + T(2) * t[1] + t[2]);
-            const T r1 = T(0.25) * (t[HX] + T(2) * t[HX + 1] + t[HX + 2]);
-            const T r2 = T(0.25) * (t[2 * HX] + T(2) * t[2 * HX + 1] + t[2 * HX + 2]);
-            sn[c] = T(0.25) * r0 + T(0.5) * r1 + T(0.25) * r2;
+            const T q0 = T(0.25) * (t[0] + T(2) * t[1] + t[2]);
+            const T q1 = T(0.25) * (t[HX] + T(2) * t[HX + 1] + t[HX + 2]);
+            const T q2 = T(0.25) * (t[2 * HX] + T(2) * t[2 * HX + 1] + t[2 * HX + 2]);
+            sn[c] = T(0.25) * q0 + T(0.5) * q1 + T(0.25) * q2;
+        }
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+            rn[a] = 0; dn[a][0] = 0; dn[a][1] = 0;
+            if (!doc) continue;
+            const T* t = tile[D + a] + (ly + 1) * HX + lx + 1;
+            rn[a] = t[0];
+            dn[a][0] = T(0.5) * (t[1] - t[-1]);
+            dn[a][1] = T(0.5) * (t[HX] - t[-HX]);
         }
         __syncthreads();
         if (D == 2) {
@@ -530,6 +579,10 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
 #pragma unroll
                 for (int c = 0; c < NCMP; ++c)
                     if (dst[c]) dst[c][ci] = sn[c];
+                if (cdst) {   // curl^T of a scalar: (D_y w, -D_x w)
+                    cdst[ci] = dn[0][1];
+                    cdst[sN + ci] = -dn[0][0];
+                }
             }
         } else {
             const int zo = pz - 1;  // output plane once its upper neighbour is staged
@@ -538,48 +591,29 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
 #pragma unroll
                 for (int c = 0; c < NCMP; ++c)
                     if (dst[c]) dst[c][ci] = T(0.25) * s0[c] + T(0.5) * s1[c] + T(0.25) * sn[c];
+                if (cdst) {   // curl w at plane zo: D_z from the planes above and below
+                    const T dzx = T(0.5) * (rn[0] - r1[0]), dzy = T(0.5) * (rn[1] - r1[1]);
+                    cdst[ci] = dxy[2][1] - dzy;             // D_y w_z - D_z w_y
+                    cdst[sN + ci] = dzx - dxy[2][0];        // D_z w_x - D_x w_z
+                    cdst[2 * sN + ci] = dxy[1][0] - dxy[0][1];  // D_x w_y - D_y w_x
+                }
             }
 #pragma unroll
             for (int c = 0; c < NCMP; ++c) { s0[c] = s1[c]; s1[c] = sn[c]; }
+#pragma unroll
+            for (int a = 0; a < NC; ++a) {
+                r1[a] = r2[a]; r2[a] = rn[a];
+                dxy[a][0] = dn[a][0]; dxy[a][1] = dn[a][1];
+            }
         }
-    }
-}
-
-// Sensitivity of a Z QoI: curl^T psi with psi = sum_j c[j] W_j, evaluated
-// from neighbour values (2-D: (D_y psi, -D_x psi); 3-D: curl psi).
-template <int D, typename T>
-__device__ __forceinline__ void zsens(const T* __restrict__ W, size_t N, int jw, const double* c, int x, int y,
-                                      int z, int nx, int ny, int nz, int walls, T* V)
-{
-    constexpr int NC = D == 2 ? 1 : 3;
-    auto psi = [&](int a, int xx, int yy, int zz) -> T {
-        T s = 0;
-        for (int j = 0; j <= jw; ++j)
-            if (c[j] != 0.0) s += T(c[j]) * fld(W + ((size_t)j * NC + a) * N, xx, yy, zz, nx, ny, nz, walls);
-        return s;
-    };
-    if (D == 2) {
-        V[0] = T(0.5) * (psi(0, x, y + 1, z) - psi(0, x, y - 1, z));
-        V[1] = -T(0.5) * (psi(0, x + 1, y, z) - psi(0, x - 1, y, z));
-    } else {
-        T dy2 = T(0.5) * (psi(2, x, y + 1, z) - psi(2, x, y - 1, z));
-        T dz1 = T(0.5) * (psi(1, x, y, z + 1) - psi(1, x, y, z - 1));
-        T dz0 = T(0.5) * (psi(0, x, y, z + 1) - psi(0, x, y, z - 1));
-        T dx2 = T(0.5) * (psi(2, x + 1, y, z) - psi(2, x - 1, y, z));
-        T dx1 = T(0.5) * (psi(1, x + 1, y, z) - psi(1, x - 1, y, z));
-        T dy0 = T(0.5) * (psi(0, x, y + 1, z) - psi(0, x, y - 1, z));
-        V[0] = dy2 - dz1;
-        V[1] = dz0 - dx2;
-        V[2] = dx1 - dy0;
     }
 }
 
 // ---------------------------------------------------------------------------
 // Per-cell sensitivities of all E/Z QoIs (App. A):
-//   E: V = R R v = sum_j rr_j B^j v (local);
-//   Z: V = curl^T psi, psi = R R w = sum_j rr_j B^j w, from central
-//      differences of the stored powers at the six neighbours, shared by
-//      all Z QoIs (2-D: curl^T psi = (D_y psi, -D_x psi); 3-D: curl psi).
+//   E: V = R R v = sum_j rr_j B^j v;
+//   Z: V = curl^T R R w = sum_j rr_j C_j with C_j = curl^T B^j w, formed by
+//      the binomial passes (2-D: curl^T psi = (D_y psi, -D_x psi); 3-D: curl).
 // Also returns the QoI densities 1/2 |R v|^2 and 1/2 |R w|^2 of the cell.
 // ---------------------------------------------------------------------------
 template <int LAT, typename T, int MAXSA>
@@ -630,52 +664,22 @@ __device__ __forceinline__ void cell_sens(const DevMember& m, const DevParam* __
         }
     }
     if (!prm->has_z) return;
-    const int nx = m.nx, ny = m.ny, nz = m.nz;
-    // derivative D_b of component a of every psi_s; (b, a, target, sign)
-    constexpr int NT = D == 2 ? 2 : 6;
+    // Z sensitivities from the stored C_j = curl^T B^j w
+    const T* __restrict__ Cc = (const T*)m.C;
+    T cv[kMaxPow + 1][D];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        int b, a, tgt;
-        T sg;
-        if (D == 2) {
-            b = t; a = 0;
-            tgt = t == 0 ? 1 : 0;
-            sg = t == 0 ? T(-1) : T(1);
-        } else {
-            // D_x psi_z -> V_y -, D_x psi_y -> V_z +, D_y psi_z -> V_x +,
-            // D_y psi_x -> V_z -, D_z psi_y -> V_x -, D_z psi_x -> V_y +
-            constexpr int B3[6] = {0, 0, 1, 1, 2, 2};
-            constexpr int A3[6] = {2, 1, 2, 0, 1, 0};
-            constexpr int T3[6] = {1, 2, 0, 2, 0, 1};
-            constexpr int S3[6] = {-1, 1, 1, -1, -1, 1};
-            b = B3[t]; a = A3[t]; tgt = T3[t]; sg = T(S3[t]);
-        }
-        int xp = x, xm = x, yp = y, ym = y, zp = z, zm = z;
-        bool okp = true, okm = true;
-        if (b == 0) { xp = wrapi(x + 1, nx); xm = wrapi(x - 1, nx); }
-        if (b == 1) {
-            yp = y + 1; ym = y - 1;
-            if (m.walls) { okp = yp < ny; okm = ym >= 0; }
-            else { yp = wrapi(yp, ny); ym = wrapi(ym, ny); }
-        }
-        if (b == 2) { zp = wrapi(z + 1, nz); zm = wrapi(z - 1, nz); }
-        const size_t cp = (size_t)xp + (size_t)nx * (yp + (size_t)ny * zp);
-        const size_t cm = (size_t)xm + (size_t)nx * (ym + (size_t)ny * zm);
-        T diff[kMaxPow + 1];
+    for (int jj = 0; jj <= kMaxPow; ++jj)
 #pragma unroll
-        for (int jj = 0; jj <= kMaxPow; ++jj) {
-            const T* Wj = W + ((size_t)jj * NC + a) * sN;
-            const T fp = (jj <= jw && okp) ? Wj[cp] : T(0);
-            const T fm = (jj <= jw && okm) ? Wj[cm] : T(0);
-            diff[jj] = T(0.5) * (fp - fm);
-        }
+        for (int a = 0; a < D; ++a) cv[jj][a] = jj <= jw ? Cc[((size_t)jj * D + a) * sN + cell] : T(0);
 #pragma unroll
-        for (int s = 0; s < MAXSA; ++s) {
-            if (s >= nsa || prm->sa_kind[s] == 0) continue;
-            T d = 0;
+    for (int s = 0; s < MAXSA; ++s) {
+        if (s >= nsa || prm->sa_kind[s] == 0) continue;
 #pragma unroll
-            for (int jj = 0; jj <= kMaxPow; ++jj) d += T(prm->rr[s][jj]) * diff[jj];
-            V[s][tgt] += sg * d;
+        for (int a = 0; a < D; ++a) {
+            T vv = 0;
+#pragma unroll
+            for (int jj = 0; jj <= kMaxPow; ++jj) vv += T(prm->rr[s][jj]) * cv[jj][a];
+            V[s][a] = vv;
         }
     }
 }
@@ -1010,7 +1014,8 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
     }
 }
 
-// K4: dv = sum_j cv_j B^j v* + curl^T(sum_j cw_j B^j w) + e_x cmp(y).
+// K4: dv = sum_j cv_j B^j v* + sum_j cw_j C_j + e_x cmp(y), then the packed
+// pending-correction record of the cell.
 template <int LAT, typename T>
 __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ mems, const int2* __restrict__ work)
 {
@@ -1034,14 +1039,30 @@ __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ 
         out[a] = s;
     }
     if (prm->has_z) {
-        T V[3] = {0, 0, 0};
-        zsens<D, T>((const T*)m.W, sN, prm->jw, cw, x, y, z, nx, ny, nz, m.walls, V);
 #pragma unroll
-        for (int a = 0; a < D; ++a) out[a] += V[a];
+        for (int a = 0; a < D; ++a) {
+            T sacc = 0;
+            for (int jj = 0; jj <= prm->jw; ++jj) sacc += T(cw[jj]) * ((const T*)m.C)[((size_t)jj * D + a) * sN + cell];
+            out[a] += sacc;
+        }
     }
     if (prm->nmp > 0) out[0] += T(m.cmp[y]);
+    // packed pending correction for the next stream-collide
+    const T rho = T(1) + ((const T*)m.rho)[cell];
+    PendRec<T> r;
+    T vs[3] = {0, 0, 0};
 #pragma unroll
-    for (int a = 0; a < D; ++a) ((T*)m.dv)[a * sN + cell] = out[a];
+    for (int a = 0; a < D; ++a) vs[a] = ((const T*)m.vs)[a * sN + cell];
+    const T bx = T(2) * vs[0] + out[0], by = T(2) * vs[1] + out[1], bz = D == 3 ? T(2) * vs[2] + out[2] : T(0);
+    r.u.x = rho * out[0];
+    r.u.y = rho * out[1];
+    r.u.z = D == 3 ? rho * out[2] : T(0);
+    r.u.w = rho * (out[0] * bx + out[1] * by + (D == 3 ? out[2] * bz : T(0)));
+    r.v.x = bx;
+    r.v.y = by;
+    r.v.z = bz;
+    r.v.w = T(0);
+    ((PendRec<T>*)m.pc)[cell] = r;
 }
 
 // ---------------------------------------------------------------------------
@@ -1136,10 +1157,8 @@ __global__ void k_init(const DevMember* __restrict__ mems, int flip, const doubl
     }
     if (m.has_to) {
         ((T*)m.rho)[cell] = 0;
-        for (int a = 0; a < L::D; ++a) {
-            ((T*)m.vs)[(size_t)a * N + cell] = 0;
-            ((T*)m.dv)[(size_t)a * N + cell] = 0;
-        }
+        for (int a = 0; a < L::D; ++a) ((T*)m.vs)[(size_t)a * N + cell] = 0;
+        ((PendRec<T>*)m.pc)[cell] = PendRec<T>{};
     }
 }
 
@@ -1152,27 +1171,12 @@ __global__ void k_get_pop(const DevMember* __restrict__ mems, int flip, double* 
     const int cell = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= N) return;
     const T* g = (const T*)m.g[m.parity ^ flip];
-    double r = 0, vs[3] = {0, 0, 0}, dv[3] = {0, 0, 0};
-    if (TO) {
-        r = 1.0 + (double)((const T*)m.rho)[cell];
-        for (int a = 0; a < L::D; ++a) {
-            vs[a] = (double)((const T*)m.vs)[(size_t)a * N + cell];
-            dv[a] = (double)((const T*)m.dv)[(size_t)a * N + cell];
-        }
-    }
+    PendRec<T> r{};
+    if (TO) r = ((const PendRec<T>*)m.pc)[cell];
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         double v = (double)g[(size_t)i * N + cell] + (PREC == LBM_FP32_PLAIN ? 0.0 : L::w[i]);
-        if (TO) {
-            double cd = 0, cs = 0, dd = 0;
-            const int c[3] = {L::cx[i], L::cy[i], L::cz[i]};
-            for (int a = 0; a < L::D; ++a) {
-                cd += c[a] * dv[a];
-                cs += c[a] * (2 * vs[a] + dv[a]);
-                dd += dv[a] * (2 * vs[a] + dv[a]);
-            }
-            v += L::w[i] * r * (3 * cd + 4.5 * cd * cs - 1.5 * dd);
-        }
+        if (TO) v += (double)pend_df<LAT, T>(r, i, T(1));
         f[(size_t)i * N + cell] = v;
     }
 }
@@ -1191,10 +1195,8 @@ __global__ void k_set_pop(const DevMember* __restrict__ mems, int flip, const do
         g[(size_t)i * N + cell] = (T)(f[(size_t)i * N + cell] - (PREC == LBM_FP32_PLAIN ? 0.0 : L::w[i]));
     if (m.has_to) {
         ((T*)m.rho)[cell] = 0;
-        for (int a = 0; a < L::D; ++a) {
-            ((T*)m.vs)[(size_t)a * N + cell] = 0;
-            ((T*)m.dv)[(size_t)a * N + cell] = 0;
-        }
+        for (int a = 0; a < L::D; ++a) ((T*)m.vs)[(size_t)a * N + cell] = 0;
+        ((PendRec<T>*)m.pc)[cell] = PendRec<T>{};
     }
 }
 
@@ -1226,24 +1228,11 @@ __global__ void k_flush(const DevMember* __restrict__ mems, int flip)
     const int cell = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= N) return;
     T* g = (T*)m.g[m.parity ^ flip];
-    const T r = T(1) + ((const T*)m.rho)[cell];
-    T vs[3] = {0, 0, 0}, dv[3] = {0, 0, 0};
-    for (int a = 0; a < L::D; ++a) {
-        vs[a] = ((const T*)m.vs)[(size_t)a * N + cell];
-        dv[a] = ((const T*)m.dv)[(size_t)a * N + cell];
-    }
+    PendRec<T>* pc = (PendRec<T>*)m.pc;
+    const PendRec<T> r = pc[cell];
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        const int c[3] = {L::cx[i], L::cy[i], L::cz[i]};
-        T cd = 0, cs = 0, dd = 0;
-        for (int a = 0; a < L::D; ++a) {
-            cd += T(c[a]) * dv[a];
-            cs += T(c[a]) * (T(2) * vs[a] + dv[a]);
-            dd += dv[a] * (T(2) * vs[a] + dv[a]);
-        }
-        g[(size_t)i * N + cell] += dfeq<T>(T(L::w[i]), r, cd, cs, dd);
-    }
-    for (int a = 0; a < L::D; ++a) ((T*)m.dv)[(size_t)a * N + cell] = 0;
+    for (int i = 0; i < L::Q; ++i) g[(size_t)i * N + cell] += pend_df<LAT, T>(r, i, T(1));
+    pc[cell] = PendRec<T>{};
 }
 
 // ---------------------------------------------------------------------------
@@ -1286,7 +1275,7 @@ static void launch_step_group(const LaunchGroup& g, hipStream_t st, int flip, hi
     if (g.mode == 2) {
         if (g.any_z) hipLaunchKernelGGL((k_curl<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1);
         mark(2);
-        for (int j = 1; j <= g.maxpow; ++j)
+        for (int j = 1; j <= g.npass; ++j)
             hipLaunchKernelGGL((k_binom<LAT, T>), dim3(g.nbb), blk, 0, st, g.mems, g.workb, j);
         mark(3);
         if (g.maxsa <= 2)

@@ -11,7 +11,7 @@ namespace lbm {
 // the work tables.
 struct LaunchGroup {
     int lattice, precision, substrate, mode;  // mode 0 plain, 1 plain + records, 2 TO
-    int any_z, maxpow, maxsa;
+    int any_z, maxpow, maxsa, npass;  // npass: binomial passes per step
     const DevMember* mems;
     const int2* work1;  // cell kernels: (member, block of kBlock cells)
     int nb1;

@@ -48,6 +48,24 @@ def channel_velocity(nx: int, ny: int, nz: int, uc: float = 0.1, noise: float = 
     return u.reshape(3, -1)
 
 
+def turbulent_velocity_2d(n: int, urms: float, kpeak: float = 8.0, seed: int = 0) -> np.ndarray:
+    """Divergence-free random 2-D velocity on an n x n periodic grid with a
+    spectrum peaked at wavenumber ``kpeak`` and rms speed ``urms``: a seeded
+    stand-in for the projected turbulent DNS field that starts the paper's
+    low-fidelity Kolmogorov runs.  Built from a random-phase streamfunction
+    psi_k ~ k^-2 exp(-(k/kpeak)^2), u = (d_y psi, -d_x psi) spectrally."""
+    rng = np.random.default_rng(seed)
+    k = np.fft.fftfreq(n, 1.0 / n)
+    ky, kx = np.meshgrid(k, k, indexing="ij")
+    kk = np.sqrt(kx * kx + ky * ky)
+    amp = np.where(kk > 0, (kk + 1e-30) ** -2.0 * np.exp(-(kk / kpeak) ** 2), 0.0)
+    psih = amp * np.exp(2j * np.pi * rng.random((n, n)))
+    ux = np.real(np.fft.ifft2(1j * ky * psih))
+    uy = np.real(np.fft.ifft2(-1j * kx * psih))
+    scale = urms / np.sqrt(np.mean(ux * ux + uy * uy))
+    return np.stack([ux.ravel(), uy.ravel()]) * scale
+
+
 # ---------------------------------------------------------------------------
 # Channel physics in lattice units (paper Sec. 7.1 scaling: centreline
 # velocity U_c+ = 18.3 maps to 0.1, Re_tau = 180).
