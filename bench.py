@@ -52,10 +52,11 @@ def workload(name):
     if name == "kolmogorov":
         n = 256
         cfg, _ = synth.kolmogorov_workload(n, tau=0.51, seed=2)
-        u0 = synth.noise_velocity(2, (1, n, n), 1e-4, 2)
+        u0 = synth.turbulent_velocity_2d(n, 0.03, seed=2)
         C, mu, S = synth.lrs_model(2, 3, 4, 5)
         cargs = dict(mode="lrs", spinup=5000, C=C, mu=mu, Sigma=S, seed=12)
-        desc = "D2Q9 Kolmogorov TO-LES 256x256, FP32 shifted, tau=0.51, E_B/Z_B QoIs, LRS h=0 from step 5000"
+        desc = ("D2Q9 Kolmogorov TO-LES 256x256, FP32 shifted, tau=0.51, E_B/Z_B QoIs, LRS h=0 from step 5000, "
+                "turbulent synthetic initial field")
         return dict(cfg=cfg, u0=u0, qois=synth.QOIS_2D, cargs=cargs, precision="fp32", desc=desc,
                     job_steps=20000, b_alg=128)
     if name == "fine":
@@ -93,6 +94,156 @@ def phase_bytes(w, ms, launches):
     return {k: per_cell[k] * N for k in per_cell}
 
 
+def kolmogorov_member(lbm, n, ic_seed, noise_seed, spinup, precision="fp32"):
+    import synth
+    cfg, _ = synth.kolmogorov_workload(n, tau=0.51, seed=ic_seed)
+    u0 = synth.turbulent_velocity_2d(n, 0.03, seed=ic_seed)
+    C, mu, S = synth.lrs_model(2, 3, 4, 5)
+    spec = lbm.ClosureSpec(synth.QOIS_2D, mode="lrs", spinup=spinup, C=C, mu=mu, Sigma=S, seed=noise_seed)
+    return lbm.make_config(precision=precision, **cfg), spec, u0
+
+
+def channel_request(lbm, m, seed, spinup):
+    import synth
+    ny = 24 * m
+    cfg, u0 = synth.channel_workload(48 * m, ny, 24 * m, substrate=1, cmodel=0.1, seed=seed)
+    nb, dmin, dmax = synth.channel_bands(ny)
+    C, mu, S = synth.lrs_model_channel(12, 7, 9)
+    spec = lbm.ClosureSpec(synth.QOIS_3D, mode="lrs", spinup=spinup, C=C, mu=mu, Sigma=S, seed=seed,
+                           nbands=nb, dmin=dmin, dmax=dmax)
+    return lbm.make_config(precision="fp32", **cfg), spec, u0
+
+
+def form_precision(lbm, w, steps):
+    """System form (1): FP32 shifted populations vs the plain FP32 kernel vs
+    FP64, same workload; error of the FP32 runs against the FP64 run."""
+    import numpy as np
+    import torch
+    cfg = w["cfg"]
+    N = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    out, vel = {}, {}
+    for prec in ("fp64", "fp32", "fp32_plain"):
+        spec = lbm.ClosureSpec(w["qois"], **w["cargs"])
+        r = lbm.Run(lbm.make_config(precision=prec, **cfg), spec)
+        r.init_velocity(w["u0"])
+        r.step(20)
+        r.sync()
+        t = time.perf_counter()
+        r.step(steps)
+        r.sync()
+        dt = time.perf_counter() - t
+        vel[prec] = r.fields()[1]
+        out[prec] = {"mlups": round(N * (steps + 20) / 1e6 / dt * steps / (steps + 20), 1)}
+        r.close()
+    for prec in ("fp32", "fp32_plain"):
+        out[prec]["max_rel_velocity_err_vs_fp64"] = float(
+            np.max(np.abs(vel[prec] - vel["fp64"])) / np.max(np.abs(vel["fp64"])))
+    out["steps"] = steps + 20
+    return out
+
+
+def form_batched(lbm, nmem, steps):
+    """System form (2): an ensemble of Kolmogorov TO-LES members on uneven
+    grids advanced as one batch (one launch per kernel phase for all members,
+    replayed from a hipGraph) vs the same members stepped one after another."""
+    import numpy as np
+    import synth
+    mem = synth.ensemble_members(nmem)
+    cells = sum(m["n"] ** 2 for m in mem)
+    runs_b, runs_s = [], []
+    for m in mem:
+        for lst in (runs_b, runs_s):
+            cfg, spec, u0 = kolmogorov_member(lbm, m["n"], m["ic_seed"], m["noise_seed"], spinup=steps // 4)
+            r = lbm.Run(cfg, spec)
+            r.init_velocity(u0)
+            lst.append(r)
+    batch = lbm.Batch(runs_b)
+    batch.step(16)
+    batch.sync()
+    t = time.perf_counter()
+    batch.step(steps)
+    batch.sync()
+    tb = time.perf_counter() - t
+    for r in runs_s:
+        r.step(16)
+        r.sync()
+    t = time.perf_counter()
+    for r in runs_s:
+        r.step(steps)
+        r.sync()
+    ts = time.perf_counter() - t
+    same = all(np.array_equal(runs_b[k].get_populations(), runs_s[k].get_populations()) for k in (0, nmem - 1))
+    res = {"members": nmem, "cells": cells, "steps": steps,
+           "batched_mlups": round(cells * steps / tb / 1e6, 1),
+           "sequential_mlups": round(cells * steps / ts / 1e6, 1),
+           "speedup": round(ts / tb, 3), "bitwise_equal_to_solo": bool(same)}
+    batch.close()
+    for r in runs_b + runs_s:
+        r.close()
+    return res
+
+
+def form_served(lbm, nreq, rate, steps, budget=0):
+    """System form (5): continuous-batching server on a Poisson trace of mixed
+    2-D/3-D TO-LES requests; latency = completion - arrival."""
+    import numpy as np
+    import synth
+    trace = synth.serve_trace(nreq, rate, steps=steps)
+    srv = lbm.Server(hbm_budget=budget)
+    t0 = srv.clock() + 0.05
+    reqs = []
+    for q in trace:
+        if q["kind"] == "2d":
+            cfg, spec, u0 = kolmogorov_member(lbm, q["n"], q["seed"], q["seed"], spinup=steps // 4)
+        else:
+            cfg, spec, u0 = channel_request(lbm, q["m"], q["seed"], spinup=steps // 4)
+        reqs.append((cfg, spec, u0, q["t"]))
+    # submit as arrivals happen; advance the server in between
+    results, k = [], 0
+    while k < len(reqs) or srv.pending() > 0:
+        now = srv.clock()
+        while k < len(reqs) and t0 + reqs[k][3] <= now:
+            cfg, spec, u0, ta = reqs[k]
+            srv.submit(cfg, spec, u0, steps, t0 + ta)
+            k += 1
+        if srv.pending() > 0:
+            srv.advance(srv.clock(), 64)
+            results += srv.poll()
+        else:
+            time.sleep(0.0005)
+    lat = np.array([r.t_done - r.t_arrival for r in results])
+    span = max(r.t_done for r in results) - t0
+    st = srv.stats()
+    ok = sum(1 for r in results if r.status == 0)
+    srv.close()
+    return {"requests": len(results), "completed_ok": ok, "rate_per_s": rate, "steps": steps,
+            "p50_latency_s": round(float(np.percentile(lat, 50)), 3),
+            "p99_latency_s": round(float(np.percentile(lat, 99)), 3),
+            "aggregate_mlups": round(st["lups"] / span / 1e6, 1),
+            "busy_mlups": round(st["lups"] / st["busy_s"] / 1e6, 1),
+            "budget_gb": round(st["budget"] / 1e9, 2)}
+
+
+def form_fine(lbm, steps):
+    w = workload("fine")
+    cfg = w["cfg"]
+    N = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    r = lbm.Run(lbm.make_config(precision="fp32", **cfg))
+    r.init_velocity(w["u0"])
+    r.step(10)
+    r.sync()
+    t = time.perf_counter()
+    r.step(steps)
+    r.sync()
+    dt = time.perf_counter() - t
+    ms, _ = r.profile_phases(20)
+    r.close()
+    mlups = N * steps / dt / 1e6
+    return {"grid": [cfg["nx"], cfg["ny"], cfg["nz"]], "steps": steps, "mlups": round(mlups, 1),
+            "hbm_frac_152B": round(mlups * 1e6 * 152 / (HBM_PEAK_GBS * 1e9), 4),
+            "stream_collide_gbs": round(152 * N / (ms["stream_collide"] * 1e-3) / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +253,10 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-system-forms", action="store_true",
+                    help="skip the precision / batched / served / fine-grid comparisons")
+    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--ensemble-steps", type=int, default=200)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -188,6 +343,18 @@ def main():
         "roofline": roofline,
         "phases": phases,
     }
+
+    if args.workload == "channel" and not args.no_system_forms:
+        forms = {}
+        forms["precision"] = form_precision(lbm, w, 1000)
+        print(f"[bench] precision forms: {forms['precision']}", file=sys.stderr, flush=True)
+        forms["batched"] = form_batched(lbm, 64, args.ensemble_steps)
+        print(f"[bench] batched: {forms['batched']}", file=sys.stderr, flush=True)
+        forms["served"] = form_served(lbm, args.serve_requests, 20.0, 2000)
+        print(f"[bench] served: {forms['served']}", file=sys.stderr, flush=True)
+        forms["fine_grid_plain"] = form_fine(lbm, 200)
+        print(f"[bench] fine grid: {forms['fine_grid_plain']}", file=sys.stderr, flush=True)
+        out["system_forms"] = forms
 
     if not args.no_cpu_baseline:
         import oracle

@@ -203,6 +203,41 @@ int lbm_batch_step(lbm_batch* b, long nsteps);
 int lbm_batch_sync(lbm_batch* b);
 void lbm_batch_destroy(lbm_batch* b);
 
+/* Serving: continuous batching of LES requests on one GPU.
+ * Requests (a config, an optional closure and the initial velocity) queue
+ * in arrival order.  lbm_server_advance admits every queued request whose
+ * arrival time has passed while the sum of the admitted arenas stays within
+ * the HBM budget (the server allocates and frees the arenas), advances all
+ * admitted requests together as one batch for a chunk of steps (no request
+ * runs past its own step count), and retires the finished ones.  Requests
+ * join and leave between chunks, so their work overlaps on the device; each
+ * request's result is bitwise the one it gets alone.  Times are seconds on
+ * the clock of lbm_server_clock. */
+typedef struct {
+    long id;
+    int status;                 /* LBM_OK, LBM_EUNSTABLE, or LBM_ENOMEM (larger than the budget) */
+    long steps;
+    long cells;
+    double t_arrival, t_admit, t_done;
+    lbm_qoi_rec last;           /* record of the last step (runs with records) */
+} lbm_result;
+double lbm_server_clock(void);
+/* hbm_budget: bytes for request arenas (0: 80% of the free device memory). */
+int lbm_server_create(size_t hbm_budget, void* stream, lbm_server** out);
+/* Copies everything it is given; keep_state retains the final state image
+ * (lbm_get_state layout) for lbm_server_take_state. */
+int lbm_server_submit(lbm_server* s, const lbm_config* cfg, const lbm_closure* closure, const double* u0,
+                      long nsteps, double t_arrival, int keep_state, long* id);
+/* Admit, step at most max_chunk steps (0: 64), retire; synchronises. */
+int lbm_server_advance(lbm_server* s, double now, long max_chunk, int* n_active);
+/* Move up to cap finished results into out (caller-owned). */
+int lbm_server_poll(lbm_server* s, lbm_result* out, int cap, int* n);
+int lbm_server_pending(const lbm_server* s);            /* queued + active requests */
+int lbm_server_stats(const lbm_server* s, double* busy_s, double* lups, size_t* used, size_t* budget);
+size_t lbm_server_state_bytes(const lbm_server* s, long id);
+int lbm_server_take_state(lbm_server* s, long id, void* host, size_t bytes);
+void lbm_server_destroy(lbm_server* s);
+
 /* Per-phase timing for measurement: runs nsteps steps eagerly on the context
  * stream with HIP events between the kernel phases and returns the mean
  * duration per step of each phase in ms[6]: stream-collide (with the WALE

@@ -3,7 +3,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <deque>
+#include <map>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -408,6 +411,10 @@ int reset_ctl(lbm_ctx* c)
 {
     DevCtl ctl{};
     int rc = upload(c, c->arena + c->plan.ctl, &ctl, sizeof ctl);
+    // an empty record ring (its slots are part of the checkpoint image)
+    if (!rc && hipMemsetAsync(c->arena + c->plan.recs, 0, sizeof(lbm_qoi_rec) * c->plan.rec_cap, c->stream) != hipSuccess)
+        rc = fail(LBM_EDEVICE, "record ring reset failed");
+    if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(LBM_EDEVICE, "record ring reset failed");
     c->host_step = 0;
     return rc;
 }
@@ -1057,6 +1064,288 @@ int lbm_test_normals(uint64_t seed, long step0, int nsteps, int n, double* out)
     HIPCHK(hipMemcpy(out, d, sizeof(double) * (size_t)nsteps * n, hipMemcpyDeviceToHost));
     hipFree(d);
     return LBM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Serving: continuous batching of LES requests.
+// ---------------------------------------------------------------------------
+namespace {
+
+double server_clock_now()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Deep copy of a closure (the lbm_closure points into caller memory).
+struct ClosureCopy {
+    bool set = false;
+    lbm_closure c{};
+    std::vector<lbm_qoi_spec> q;
+    std::vector<double> C, mu, Sigma, scale, qref;
+    void take(const lbm_closure* src)
+    {
+        if (!src) { set = false; return; }
+        set = true;
+        c = *src;
+        const int nq = src->nq;
+        q.assign(src->q, src->q + nq);
+        c.q = q.data();
+        auto cp = [](const double* p, size_t n, std::vector<double>& v) -> const double* {
+            if (!p) return nullptr;
+            v.assign(p, p + n);
+            return v.data();
+        };
+        c.C = cp(src->C, (size_t)(nq + 1) * nq, C);
+        c.mu = cp(src->mu, nq, mu);
+        c.Sigma = cp(src->Sigma, (size_t)nq * nq, Sigma);
+        c.scale = cp(src->scale, nq, scale);
+        c.qref = cp(src->qref, src->nref > 0 ? (size_t)src->nref * nq : 0, qref);
+    }
+    const lbm_closure* get() const { return set ? &c : nullptr; }
+};
+
+struct ServeReq {
+    long id = 0;
+    lbm_config cfg{};
+    ClosureCopy cl;
+    std::vector<double> u0;
+    long nsteps = 0, done = 0;
+    double t_arr = 0, t_adm = 0, t_done = 0;
+    int keep = 0;
+    size_t bytes = 0;
+    void* arena = nullptr;
+    lbm_ctx* ctx = nullptr;
+};
+
+}  // namespace
+
+struct lbm_server {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    size_t budget = 0, used = 0;
+    long next_id = 1;
+    std::deque<ServeReq*> queue;
+    std::vector<ServeReq*> active;
+    lbm_batch* batch = nullptr;
+    bool dirty = true;
+    std::vector<lbm_result> results;
+    std::map<long, std::vector<char>> states;
+    long chunk_default = 64;
+    double busy = 0;   // seconds spent stepping
+    double lups = 0;   // lattice updates done
+};
+
+namespace {
+
+void server_release(lbm_server* s, ServeReq* r)
+{
+    if (r->ctx) lbm_destroy(r->ctx);
+    if (r->arena) (void)hipFree(r->arena);
+    s->used -= r->bytes;
+    delete r;
+}
+
+int server_admit(lbm_server* s, double now)
+{
+    while (!s->queue.empty()) {
+        ServeReq* r = s->queue.front();
+        if (r->t_arr > now) break;
+        if (s->used + r->bytes > s->budget && !s->active.empty()) break;  // wait for memory
+        if (s->used + r->bytes > s->budget) {
+            // larger than the whole budget: reject
+            s->queue.pop_front();
+            lbm_result res{};
+            res.id = r->id;
+            res.status = LBM_ENOMEM;
+            res.t_arrival = r->t_arr;
+            res.t_admit = now;
+            res.t_done = now;
+            s->results.push_back(res);
+            delete r;
+            continue;
+        }
+        if (hipMalloc(&r->arena, r->bytes) != hipSuccess) return fail(LBM_ENOMEM, "server: arena allocation failed");
+        int rc = lbm_create(&r->cfg, r->cl.get(), r->arena, r->bytes, s->stream, &r->ctx);
+        if (!rc) rc = lbm_init_velocity(r->ctx, nullptr, r->u0.data());
+        if (rc) {
+            (void)hipFree(r->arena);
+            r->arena = nullptr;
+            return rc;
+        }
+        std::vector<double>().swap(r->u0);
+        s->queue.pop_front();
+        s->used += r->bytes;
+        r->t_adm = server_clock_now();
+        s->active.push_back(r);
+        s->dirty = true;
+    }
+    return LBM_OK;
+}
+
+int server_retire(lbm_server* s)
+{
+    std::vector<ServeReq*> keep;
+    for (ServeReq* r : s->active) {
+        if (r->done < r->nsteps) { keep.push_back(r); continue; }
+        lbm_result res{};
+        res.id = r->id;
+        res.status = lbm_sync(r->ctx);
+        res.steps = r->done;
+        res.t_arrival = r->t_arr;
+        res.t_admit = r->t_adm;
+        res.t_done = r->t_done;
+        res.cells = (long)r->cfg.nx * r->cfg.ny * r->cfg.nz;
+        if (r->ctx->mode() > 0 && r->done > 0) lbm_qoi(r->ctx, r->done - 1, 1, &res.last);
+        if (r->keep) {
+            std::vector<char> img(lbm_state_bytes(r->ctx));
+            if (lbm_get_state(r->ctx, img.data(), img.size()) == LBM_OK) s->states[r->id] = std::move(img);
+        }
+        s->results.push_back(res);
+        server_release(s, r);
+        s->dirty = true;
+    }
+    s->active.swap(keep);
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+double lbm_server_clock(void) { return server_clock_now(); }
+
+int lbm_server_create(size_t hbm_budget, void* stream, lbm_server** out)
+{
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    lbm_server* s = new lbm_server();
+    s->stream = (hipStream_t)stream;
+    if (!s->stream) {
+        if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete s;
+            return fail(LBM_EDEVICE, "stream creation failed");
+        }
+        s->own_stream = true;
+    }
+    if (hbm_budget == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) { delete s; return fail(LBM_EDEVICE, "hipMemGetInfo failed"); }
+        hbm_budget = (size_t)(0.8 * (double)fr);
+    }
+    s->budget = hbm_budget;
+    *out = s;
+    return LBM_OK;
+}
+
+int lbm_server_submit(lbm_server* s, const lbm_config* cfg, const lbm_closure* cl, const double* u0, long nsteps,
+                      double t_arrival, int keep_state, long* id)
+{
+    if (!s || !cfg || !u0 || nsteps < 1) return fail(LBM_EINVAL, "bad arguments");
+    const size_t bytes = lbm_required_bytes(cfg, cl);
+    if (!bytes) return LBM_EINVAL;  // message set by the validation
+    ServeReq* r = new ServeReq();
+    r->id = s->next_id++;
+    r->cfg = *cfg;
+    r->cl.take(cl);
+    const size_t n = (size_t)(cfg->lattice == LBM_D2Q9 ? 2 : 3) * cfg->nx * cfg->ny * cfg->nz;
+    r->u0.assign(u0, u0 + n);
+    r->nsteps = nsteps;
+    r->t_arr = t_arrival;
+    r->keep = keep_state;
+    r->bytes = align_up(bytes);
+    // keep the queue ordered by arrival time
+    auto it = s->queue.end();
+    while (it != s->queue.begin() && (*(it - 1))->t_arr > t_arrival) --it;
+    s->queue.insert(it, r);
+    if (id) *id = r->id;
+    return LBM_OK;
+}
+
+int lbm_server_advance(lbm_server* s, double now, long max_chunk, int* n_active)
+{
+    if (!s) return fail(LBM_EINVAL, "NULL server");
+    int rc = server_admit(s, now);
+    if (rc) return rc;
+    if (n_active) *n_active = (int)s->active.size();
+    if (s->active.empty()) return LBM_OK;
+    long chunk = max_chunk > 0 ? max_chunk : s->chunk_default;
+    for (ServeReq* r : s->active) chunk = std::min(chunk, r->nsteps - r->done);
+    if (s->dirty) {
+        if (s->batch) lbm_batch_destroy(s->batch);
+        s->batch = nullptr;
+        std::vector<lbm_ctx*> m;
+        for (ServeReq* r : s->active) m.push_back(r->ctx);
+        rc = lbm_batch_create((int)m.size(), m.data(), &s->batch);
+        if (rc) return rc;
+        s->dirty = false;
+    }
+    const double t0 = server_clock_now();
+    rc = lbm_batch_step(s->batch, chunk);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    const double t1 = server_clock_now();
+    s->busy += t1 - t0;
+    for (ServeReq* r : s->active) {
+        r->done += chunk;
+        s->lups += (double)chunk * r->cfg.nx * r->cfg.ny * r->cfg.nz;
+        if (r->done >= r->nsteps) r->t_done = t1;
+    }
+    rc = server_retire(s);
+    if (n_active) *n_active = (int)s->active.size();
+    return rc;
+}
+
+int lbm_server_poll(lbm_server* s, lbm_result* out, int cap, int* n)
+{
+    if (!s || !n || (cap > 0 && !out)) return fail(LBM_EINVAL, "bad arguments");
+    const int k = std::min<int>(cap, (int)s->results.size());
+    for (int i = 0; i < k; ++i) out[i] = s->results[i];
+    s->results.erase(s->results.begin(), s->results.begin() + k);
+    *n = k;
+    return LBM_OK;
+}
+
+int lbm_server_pending(const lbm_server* s) { return s ? (int)(s->queue.size() + s->active.size()) : -1; }
+
+int lbm_server_stats(const lbm_server* s, double* busy_s, double* lups, size_t* used, size_t* budget)
+{
+    if (!s) return fail(LBM_EINVAL, "NULL server");
+    if (busy_s) *busy_s = s->busy;
+    if (lups) *lups = s->lups;
+    if (used) *used = s->used;
+    if (budget) *budget = s->budget;
+    return LBM_OK;
+}
+
+size_t lbm_server_state_bytes(const lbm_server* s, long id)
+{
+    if (!s) return 0;
+    auto it = s->states.find(id);
+    return it == s->states.end() ? 0 : it->second.size();
+}
+
+int lbm_server_take_state(lbm_server* s, long id, void* host, size_t bytes)
+{
+    if (!s || !host) return fail(LBM_EINVAL, "bad arguments");
+    auto it = s->states.find(id);
+    if (it == s->states.end()) return fail(LBM_ESTATE, "no retained state for request %ld", id);
+    if (bytes < it->second.size()) return fail(LBM_EINVAL, "buffer too small");
+    memcpy(host, it->second.data(), it->second.size());
+    s->states.erase(it);
+    return LBM_OK;
+}
+
+void lbm_server_destroy(lbm_server* s)
+{
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    if (s->batch) lbm_batch_destroy(s->batch);
+    for (ServeReq* r : s->active) server_release(s, r);
+    for (ServeReq* r : s->queue) delete r;
+    if (s->own_stream) (void)hipStreamDestroy(s->stream);
+    delete s;
 }
 
 }  // extern "C"

@@ -60,6 +60,12 @@ class QoiRec(ct.Structure):
                 ("gamma", ct.c_double * MAX_QOI)]
 
 
+class Result(ct.Structure):
+    _fields_ = [("id", ct.c_long), ("status", ct.c_int), ("steps", ct.c_long), ("cells", ct.c_long),
+                ("t_arrival", ct.c_double), ("t_admit", ct.c_double), ("t_done", ct.c_double),
+                ("last", QoiRec)]
+
+
 #: symbols declared in include/lbm.h
 EXPORTS = [
     "lbm_last_error", "lbm_version", "lbm_lattice_info", "lbm_required_bytes", "lbm_create",
@@ -67,6 +73,9 @@ EXPORTS = [
     "lbm_qoi", "lbm_fields", "lbm_get_populations", "lbm_set_populations", "lbm_stream_only",
     "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_batch_create", "lbm_batch_step",
     "lbm_batch_sync", "lbm_batch_destroy", "lbm_profile_phases", "lbm_test_philox", "lbm_test_normals",
+    "lbm_server_clock", "lbm_server_create", "lbm_server_submit", "lbm_server_advance", "lbm_server_poll",
+    "lbm_server_pending", "lbm_server_stats", "lbm_server_state_bytes", "lbm_server_take_state",
+    "lbm_server_destroy",
 ]
 PHASES = ["stream_collide", "curl", "binomial", "reduce", "solve", "apply"]
 
@@ -112,6 +121,21 @@ def lib():
         L.lbm_profile_phases.argtypes = [P, ct.c_long, P, P]
         L.lbm_test_philox.argtypes = [P, P, I]
         L.lbm_test_normals.argtypes = [ct.c_uint64, ct.c_long, I, I, P]
+        L.lbm_server_clock.restype = ct.c_double
+        L.lbm_server_clock.argtypes = []
+        L.lbm_server_create.argtypes = [Z, P, ct.POINTER(P)]
+        L.lbm_server_submit.argtypes = [P, ct.POINTER(Config), ct.POINTER(Closure), P, ct.c_long, ct.c_double,
+                                        I, ct.POINTER(ct.c_long)]
+        L.lbm_server_advance.argtypes = [P, ct.c_double, ct.c_long, ct.POINTER(I)]
+        L.lbm_server_poll.argtypes = [P, P, I, ct.POINTER(I)]
+        L.lbm_server_pending.argtypes = [P]
+        L.lbm_server_stats.argtypes = [P, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), ct.POINTER(Z),
+                                       ct.POINTER(Z)]
+        L.lbm_server_state_bytes.restype = Z
+        L.lbm_server_state_bytes.argtypes = [P, ct.c_long]
+        L.lbm_server_take_state.argtypes = [P, ct.c_long, P, Z]
+        L.lbm_server_destroy.argtypes = [P]
+        L.lbm_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -325,6 +349,61 @@ class Batch:
     def close(self):
         if getattr(self, "h", None):
             self.L.lbm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Server:
+    """Continuous-batching LES server (lbm_server)."""
+
+    def __init__(self, hbm_budget=0, stream=None):
+        self.L = lib()
+        self.stream = stream if stream is not None else default_stream()
+        h = ct.c_void_p()
+        check(self.L.lbm_server_create(hbm_budget, ct.c_void_p(self.stream.cuda_stream), ct.byref(h)))
+        self.h = h
+
+    def clock(self):
+        return self.L.lbm_server_clock()
+
+    def submit(self, cfg: Config, closure: ClosureSpec | None, u0, nsteps, t_arrival, keep_state=False):
+        u0 = np.ascontiguousarray(np.asarray(u0, dtype=np.float64))
+        rid = ct.c_long()
+        check(self.L.lbm_server_submit(self.h, ct.byref(cfg), ct.byref(closure.c) if closure else None,
+                                       _p(u0), nsteps, t_arrival, int(keep_state), ct.byref(rid)))
+        return rid.value
+
+    def advance(self, now, max_chunk=0):
+        n = ct.c_int()
+        check(self.L.lbm_server_advance(self.h, now, max_chunk, ct.byref(n)))
+        return n.value
+
+    def poll(self, cap=1024):
+        arr = (Result * cap)()
+        n = ct.c_int()
+        check(self.L.lbm_server_poll(self.h, ct.cast(arr, ct.c_void_p), cap, ct.byref(n)))
+        return [arr[i] for i in range(n.value)]
+
+    def pending(self):
+        return self.L.lbm_server_pending(self.h)
+
+    def stats(self):
+        busy, lups = ct.c_double(), ct.c_double()
+        used, budget = ct.c_size_t(), ct.c_size_t()
+        check(self.L.lbm_server_stats(self.h, ct.byref(busy), ct.byref(lups), ct.byref(used), ct.byref(budget)))
+        return dict(busy_s=busy.value, lups=lups.value, used=used.value, budget=budget.value)
+
+    def take_state(self, rid) -> bytes:
+        n = self.L.lbm_server_state_bytes(self.h, rid)
+        buf = ct.create_string_buffer(n)
+        check(self.L.lbm_server_take_state(self.h, rid, buf, n))
+        return buf.raw
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.lbm_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

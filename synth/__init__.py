@@ -166,3 +166,31 @@ def channel_workload(nx: int, ny: int, nz: int, substrate: int = 1, cmodel: floa
 def channel_bands(ny: int, nb: int = 6):
     """(nbands, dmin, dmax): centres from the first fluid node to the centreline."""
     return nb, 0.5, ny / 2.0
+
+
+# ---------------------------------------------------------------------------
+# Ensembles and request traces
+# ---------------------------------------------------------------------------
+
+
+def ensemble_members(n: int = 64, sizes=(128, 192, 256, 384, 512), seed: int = 10):
+    """Grid sizes of a stochastic Kolmogorov TO-LES ensemble: n members drawn
+    uniformly from ``sizes`` (square grids), with member-indexed seeds."""
+    rng = np.random.default_rng(seed)
+    return [dict(n=int(rng.choice(sizes)), ic_seed=1000 + k, noise_seed=5000 + k) for k in range(n)]
+
+
+def serve_trace(nreq: int = 200, rate: float = 20.0, seed: int = 11, steps: int = 2000):
+    """Poisson request trace: exponential gaps with mean 1/rate seconds; 60%
+    D2Q9 Kolmogorov requests with N in {128, 256, ..., 1024}, 40% D3Q19
+    channel requests m*(48, 24, 24) with m in {1, 2, 3, 4}."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, nreq))
+    out = []
+    for k in range(nreq):
+        if rng.random() < 0.6:
+            out.append(dict(kind="2d", n=int(128 * rng.integers(1, 9)), t=float(t[k]), steps=steps,
+                            seed=20000 + k))
+        else:
+            out.append(dict(kind="3d", m=int(rng.integers(1, 5)), t=float(t[k]), steps=steps, seed=30000 + k))
+    return out

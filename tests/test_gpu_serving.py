@@ -1,0 +1,99 @@
+"""Continuous-batching server on the GPU: admission by HBM budget, requests of
+mixed size and kind overlapping on the device, each result bitwise equal to
+the same request run alone, and isolation of an unstable request."""
+import hashlib
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import closure_args, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests(lbm):
+    """Mixed D2Q9 Kolmogorov and D3Q19 channel TO-LES requests, FP32."""
+    reqs = []
+    for k, (n, steps) in enumerate(((48, 37), (64, 20), (40, 53))):
+        cfg, _ = synth.kolmogorov_workload(n, tau=0.51, seed=k)
+        u0 = synth.turbulent_velocity_2d(n, 0.03, seed=k)
+        qois, cargs = closure_args("2d", spinup=5, seed=200 + k)
+        reqs.append((lbm.make_config(precision="fp32", **cfg), lbm.ClosureSpec(qois, **cargs), u0, steps))
+    for k, (m, steps) in enumerate(((1, 29), (1, 11))):
+        cfg, u0 = synth.channel_workload(16 * m, 24, 8 * m, seed=20 + k)
+        qois, cargs = closure_args("3d", ny=24, spinup=5, seed=300 + k)
+        reqs.append((lbm.make_config(precision="fp32", **cfg), lbm.ClosureSpec(qois, **cargs), u0, steps))
+    return reqs
+
+
+def _alone(lbm, cfg, spec, u0, steps):
+    r = lbm.Run(cfg, spec)
+    r.init_velocity(u0)
+    r.step(steps)
+    status = 0
+    try:
+        r.sync()
+    except lbm.LbmError as e:
+        status = e.code
+    return r.get_state(), status
+
+
+def _drive(lbm, srv, deadline_s=60.0):
+    results = []
+    t_end = srv.clock() + deadline_s
+    while srv.pending() > 0:
+        srv.advance(srv.clock(), 16)
+        results += srv.poll()
+        assert srv.clock() < t_end, "server did not drain"
+    return results
+
+
+def test_server_mix_bitwise_equal_alone_and_budget():
+    lbm = need_gpu()
+    reqs = _requests(lbm)
+    # budget for about two of the larger requests: forces queueing
+    from paper_2609_32892_amd.lbm import lib
+    import ctypes as ct
+    sizes = [lib().lbm_required_bytes(ct.byref(c), ct.byref(s.c)) for c, s, _, _ in reqs]
+    budget = int(2.2 * max(sizes))
+    srv = lbm.Server(hbm_budget=budget)
+    t0 = srv.clock()
+    ids = []
+    for k, (cfg, spec, u0, steps) in enumerate(reqs):
+        ids.append(srv.submit(cfg, spec, u0, steps, t0 + 0.001 * k, keep_state=True))
+    results = _drive(lbm, srv)
+    st = srv.stats()
+    assert len(results) == len(reqs)
+    assert st["used"] == 0 and st["budget"] == budget
+    by_id = {r.id: r for r in results}
+    for rid, (cfg, spec, u0, steps) in zip(ids, reqs):
+        res = by_id[rid]
+        assert res.status == 0 and res.steps == steps
+        assert res.t_admit >= res.t_arrival - 1e-9 and res.t_done >= res.t_admit
+        assert res.last.step == steps - 1
+        img = srv.take_state(rid)
+        alone, status = _alone(lbm, cfg, spec, u0, steps)
+        assert status == 0
+        same = hashlib.sha256(img).digest() == hashlib.sha256(alone).digest()
+        assert same, f"request {rid}: result differs from the solo run"
+    srv.close()
+
+
+def test_server_isolates_unstable_request():
+    lbm = need_gpu()
+    reqs = _requests(lbm)[:2]
+    bad_cfg = dict(lattice=0, nx=16, ny=16, nz=1, walls_y=0, tau=0.5005, substrate=0, cmodel=0.0,
+                   force_kind=1, force_amp=5e-3, force_k=1, drag=0.0)
+    bad = (lbm.make_config(precision="fp32", **bad_cfg), None,
+           synth.noise_velocity(2, (1, 16, 16), 0.05, 7), 400)
+    srv = lbm.Server()
+    t0 = srv.clock()
+    ids = [srv.submit(c, s, u, n, t0, keep_state=True) for c, s, u, n in reqs + [bad]]
+    results = {r.id: r for r in _drive(lbm, srv)}
+    assert results[ids[-1]].status == lbm.EUNSTABLE
+    for rid, (cfg, spec, u0, steps) in zip(ids[:-1], reqs):
+        assert results[rid].status == 0
+        alone, _ = _alone(lbm, cfg, spec, u0, steps)
+        assert hashlib.sha256(srv.take_state(rid)).digest() == hashlib.sha256(alone).digest()
+    srv.close()
