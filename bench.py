@@ -94,6 +94,32 @@ def phase_bytes(w, ms, launches):
     return {k: per_cell[k] * N for k in per_cell}
 
 
+KERNEL_SYMBOL = {"stream_collide": "k_step", "curl": "k_curl", "binomial": "k_binom", "reduce": "k_reduce",
+                 "solve": "k_solve", "apply": "k_apply"}
+
+
+def measured_traffic(workload_name, phase):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, scaled by the copy-kernel
+    calibration; None if there is none for this kernel or the kernel source
+    has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{workload_name}_hbm_traffic.txt")
+    src = os.path.join(ROOT, "paper_2609_32892_amd", "csrc", "lbm_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    key = f"{KERNEL_SYMBOL[phase]}_bytes_per_launch"
+    if kv.get("kernel_source_sha256") != sha or key not in kv:
+        return None
+    return float(kv[key])
+
+
 def kolmogorov_member(lbm, n, ic_seed, noise_seed, spinup, precision="fp32"):
     import synth
     cfg, _ = synth.kolmogorov_workload(n, tau=0.51, seed=ic_seed)
@@ -280,9 +306,9 @@ def main():
         b = torch.empty_like(a)
         a.fill_(1.0)
         for _ in range(5):
-            b.copy_(a)
+            torch.mul(a, 1.0, out=b)   # plain elementwise kernel: reads and writes copy_probe MiB
         torch.cuda.synchronize()
-        print(f"[bench] copy probe: 5 x {args.copy_probe} MiB device-to-device copies", file=sys.stderr, flush=True)
+        print(f"[bench] copy probe: 5 x {args.copy_probe} MiB elementwise copies", file=sys.stderr, flush=True)
         del a, b
     w = workload(args.workload)
     K = args.steps if args.steps is not None else w["job_steps"]
@@ -318,8 +344,10 @@ def main():
     dom = max((k for k in ms if nl[k] > 0), key=lambda k: ms[k])
     dur_ms = ms[dom] / nl[dom]
     achieved = bytes_per_launch[dom] / (dur_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic),
                 "avg_launch_us": round(dur_ms * 1e3, 2), "bytes_per_launch": bytes_per_launch[dom]}
     phases = {k: {"ms_per_step": round(ms[k], 5), "launches": nl[k]} for k in ms}
 
