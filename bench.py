@@ -69,8 +69,9 @@ def workload(name):
 
 
 def phase_bytes(w, ms, launches):
-    """Algorithmic bytes per launch of each kernel phase (one read and one
-    write of every field the phase needs, per cell)."""
+    """Algorithmic bytes per launch of each kernel phase: one read of every
+    field element a launch needs and one write of every element it produces,
+    per cell; for the binomial passes, the mean over the passes of a step."""
     cfg = w["cfg"]
     N = cfg["nx"] * cfg["ny"] * cfg["nz"]
     d = 2 if cfg["lattice"] == 0 else 3
@@ -79,16 +80,27 @@ def phase_bytes(w, ms, launches):
     e = 8 if w["precision"] == "fp64" else 4
     to = w["qois"] is not None
     jv = jw = 0
+    has_z = False
     if to:
         deg = {"I": 0, "B": 1, "B2": 2, "BMID": 2, "IMB": 1}
         jv = max([2 * deg[f] for k, f, _ in w["qois"] if k == "E"] + [0])
         jw = max([2 * deg[f] for k, f, _ in w["qois"] if k == "Z"] + [0])
+        has_z = any(k == "Z" for k, _, _ in w["qois"])
+    npass = max(jv, jw + 1 if has_z else 0)
+    binom = 0
+    for j in range(1, npass + 1):
+        dov, dow, doc = j <= jv, has_z and j <= jw, has_z and j - 1 <= jw
+        binom += (d if dov else 0) * 2 + (nc if doc else 0) + (nc if dow else 0) + (d if doc else 0)
+    binom = binom / npass if npass else 0
+    wz = (min(jw, 2) + 1) * nc if has_z else 0   # W_0..W_2 read for the Z QoI densities
+    cz = (jw + 1) * d if has_z else 0             # C_0..C_jw
     per_cell = {
-        "stream_collide": e * (2 * Q + ((1 + 2 * d) + (1 + d) if to else 0)),
+        # populations in and out, pending record (8 elements) in, rho and v* out
+        "stream_collide": e * (2 * Q + (8 + 1 + d if to else 0)),
         "curl": e * (d + nc),
-        "binomial": e * 2 * (d + nc),
-        "reduce": e * (d + jv * d + (jw + 1) * nc),
-        "apply": e * (d + jv * d + (jw + 1) * nc + d),
+        "binomial": e * binom,
+        "reduce": e * (d + jv * d + wz + cz),
+        "apply": e * (d + jv * d + cz + 1 + 8),
         "solve": 0,
     }
     return {k: per_cell[k] * N for k in per_cell}
@@ -105,7 +117,7 @@ def measured_traffic(workload_name, phase):
     has changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"{workload_name}_hbm_traffic.txt")
-    src = os.path.join(ROOT, "paper_2609_32892_amd", "csrc", "lbm_kernels.hip")
+    srcs = [os.path.join(ROOT, "paper_2609_32892_amd", "csrc", f) for f in ("lbm_kernels.hip", "lbm_api.hip")]
     if not os.path.exists(path):
         return None
     kv = {}
@@ -113,7 +125,7 @@ def measured_traffic(workload_name, phase):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in srcs)).hexdigest()
     key = f"{KERNEL_SYMBOL[phase]}_bytes_per_launch"
     if kv.get("kernel_source_sha256") != sha or key not in kv:
         return None

@@ -178,6 +178,38 @@ void make_plan(const lbm_config* c, const ClosureShape& cs, Plan* p)
     *p = P;
 }
 
+// Work-table order for the 8 XCDs of MI355X, which receive workgroups
+// round-robin by workgroup index and each have their own L2: entry w runs on
+// XCD w % 8, so giving XCD k a contiguous range of blocks keeps the
+// neighbouring rows and planes that a block reads in the L2 that already
+// holds them.  Returns the block processed by each entry.
+constexpr int kXcd = 8;
+std::vector<int> xcd_order(int n)
+{
+    std::vector<int> order;
+    order.reserve(n);
+    const int q = (n + kXcd - 1) / kXcd;
+    std::vector<int> next(kXcd), end(kXcd);
+    for (int k = 0; k < kXcd; ++k) { next[k] = std::min(n, k * q); end[k] = std::min(n, (k + 1) * q); }
+    while ((int)order.size() < n)
+        for (int k = 0; k < kXcd && (int)order.size() < n; ++k)
+            if (next[k] < end[k]) order.push_back(next[k]++);
+    return order;
+}
+
+// The same for the binomial tiles: all z chunks of an xy tile are
+// consecutive within one XCD's range.
+std::vector<int> xcd_tile_order(int ntx, int nty, int ntz)
+{
+    std::vector<int> zmajor;  // tile ids with z fastest
+    for (int xy = 0; xy < ntx * nty; ++xy)
+        for (int tz = 0; tz < ntz; ++tz) zmajor.push_back(xy + ntx * nty * tz);
+    const std::vector<int> o = xcd_order((int)zmajor.size());
+    std::vector<int> out(o.size());
+    for (size_t w = 0; w < o.size(); ++w) out[w] = zmajor[o[w]];
+    return out;
+}
+
 // Band weights (eq. 3d-mp-band-weights) in the reading of the library header.
 void band_weights(int ny, int nb, double dmin, double dmax, std::vector<double>& w)
 {
@@ -346,6 +378,8 @@ int apply_closure(lbm_ctx* c, const lbm_closure* cl)
                 for (int j = 0; j <= kMaxPow; ++j) p.rr[isa][j] = 0;
                 for (int a = 0; a < 3; ++a)
                     for (int b = 0; b < 3; ++b) p.rr[isa][a + b] += r[a] * r[b];
+                for (int j = 0; j < 3; ++j) p.rf[isa][j] = (float)p.r[isa][j];
+                for (int j = 0; j <= kMaxPow; ++j) p.rrf[isa][j] = (float)p.rr[isa][j];
                 isa++;
             }
         }
@@ -527,7 +561,10 @@ int lbm_create(const lbm_config* cfg, const lbm_closure* closure, void* dev_aren
             fp[y] = cfg->force_amp;
     }
     std::vector<int2> w1(plan.nb1);
-    for (int b = 0; b < plan.nb1; ++b) w1[b] = make_int2(0, b);
+    {
+        const std::vector<int> o = xcd_order(plan.nb1);
+        for (int b = 0; b < plan.nb1; ++b) w1[b] = make_int2(0, o[b]);
+    }
     int zero = 0;
     rc = upload(c, A + plan.fprof, fp.data(), sizeof(double) * fp.size());
     if (!rc) rc = upload(c, A + plan.work1, w1.data(), sizeof(int2) * w1.size());
@@ -537,7 +574,11 @@ int lbm_create(const lbm_config* cfg, const lbm_closure* closure, void* dev_aren
         for (int b = 0; b < plan.nbr; ++b) wr[b] = make_int2(0, b);
         rc = upload(c, A + plan.workr, wr.data(), sizeof(int2) * wr.size());
         std::vector<int2> wb(plan.nbb);
-        for (int b = 0; b < plan.nbb; ++b) wb[b] = make_int2(0, b);
+        {
+            const int ntx = (cfg->nx + kBinTX - 1) / kBinTX, nty = (cfg->ny + kBinTY - 1) / kBinTY;
+            const std::vector<int> o = xcd_tile_order(ntx, nty, plan.nbb / (ntx * nty));
+            for (int b = 0; b < plan.nbb; ++b) wb[b] = make_int2(0, o[b]);
+        }
         if (!rc) rc = upload(c, A + plan.workb, wb.data(), sizeof(int2) * wb.size());
         std::vector<int2> ws(plan.nbs);
         for (int b = 0; b < plan.nbs; ++b) ws[b] = make_int2(0, b);
@@ -859,8 +900,10 @@ static int batch_build(lbm_batch* b)
     for (size_t gi = 0; gi < keys.size(); ++gi) {
         Off o{};
         o.w1 = work.size();
-        for (int i : gm[gi])
-            for (int k = 0; k < b->mem[i]->plan.nb1; ++k) work.push_back(make_int2(i, k));
+        for (int i : gm[gi]) {
+            const std::vector<int> o = xcd_order(b->mem[i]->plan.nb1);
+            for (int k = 0; k < b->mem[i]->plan.nb1; ++k) work.push_back(make_int2(i, o[k]));
+        }
         o.nb1 = work.size() - o.w1;
         o.wr = work.size();
         if (keys[gi].mode == 2)
@@ -869,8 +912,12 @@ static int batch_build(lbm_batch* b)
         o.nbr = work.size() - o.wr;
         o.wb = work.size();
         if (keys[gi].mode == 2)
-            for (int i : gm[gi])
-                for (int k = 0; k < b->mem[i]->plan.nbb; ++k) work.push_back(make_int2(i, k));
+            for (int i : gm[gi]) {
+                const lbm_config& mc = b->mem[i]->cfg;
+                const int ntx = (mc.nx + kBinTX - 1) / kBinTX, nty = (mc.ny + kBinTY - 1) / kBinTY;
+                const std::vector<int> o = xcd_tile_order(ntx, nty, b->mem[i]->plan.nbb / (ntx * nty));
+                for (int k = 0; k < b->mem[i]->plan.nbb; ++k) work.push_back(make_int2(i, o[k]));
+            }
         o.nbb = work.size() - o.wb;
         o.ws = work.size();
         if (keys[gi].mode == 2)

@@ -32,6 +32,8 @@ struct DevParam {
     int mp_band[kMaxQ];
     double r[kMaxSA][3];               // R   = sum_j r[j]  B^j
     double rr[kMaxSA][kMaxPow + 1];    // R R = sum_j rr[j] B^j
+    float rf[kMaxSA][3];               // the same rounded to FP32 (for the FP32 kernels)
+    float rrf[kMaxSA][kMaxPow + 1];
     double C[(kMaxQ + 1) * kMaxQ];
     double mu[kMaxQ];
     double L[kMaxQ * kMaxQ];           // Cholesky factor of Sigma
@@ -48,7 +50,9 @@ struct DevCtl {
     double s[kMaxQ];                   // LRS scale
     double cv[kMaxPow + 1];            // dv = sum_j cv[j] B^j v + curl^T(sum_j cw[j] B^j w) + e_x cmp(y)
     double cw[kMaxPow + 1];
-    double pad[6];
+    float cvf[kMaxPow + 1];            // cv, cw rounded to FP32
+    float cwf[kMaxPow + 1];
+    double pad[1];
 };
 
 struct DevMember {
@@ -78,5 +82,20 @@ struct DevMember {
     double* fprof;                     // body force F_x(y) [ny]
     double* sums;                      // [4 + npart]: reduced statistics and TO partials
 };
+
+#ifdef __HIP_DEVICE_COMPILE__
+#define LBM_K __attribute__((address_space(4)))
+#else
+#define LBM_K
+#endif
+// Kernels read member records and closure parameters, which no kernel writes
+// while it runs, through the constant address space: with a workgroup-uniform
+// address the loads go to the scalar unit and the parameters stay in scalar
+// registers, so they never wait behind the vector loads of the fields.
+using KMember = const LBM_K DevMember;
+using KParam = const LBM_K DevParam;
+using KCtl = const LBM_K DevCtl;
+template <typename X>
+__host__ __device__ __forceinline__ const LBM_K X* kc(const X* p) { return (const LBM_K X*)p; }
 
 }  // namespace lbm

@@ -56,13 +56,37 @@ __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i 
 __device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
 // ---------------------------------------------------------------------------
-// Reductions: butterfly over the 64-lane wavefront, then waves in order.
+// Reductions over the 64-lane wavefront with DPP lane moves (no LDS
+// traffic): pairs, quads, half rows and rows of 16 lanes by quad
+// permutations and mirrors, then the rows by the two row broadcasts, which
+// leaves the sum in lane 63.  The order of the additions is fixed.
 // ---------------------------------------------------------------------------
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_add(double v)
+{
+    const long long b = __double_as_longlong(v);
+    int lo, hi;
+    if (ROWMASK == 0xf) {   // every lane is written
+        lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xf, 0xf, false);
+        hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+    } else {                // rows outside the mask add zero
+        lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWMASK, 0xf, false);
+        hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xf, false);
+    }
+    return v + __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v = dpp_add<0xB1, 0xf>(v);    // quad_perm [1,0,3,2]
+    v = dpp_add<0x4E, 0xf>(v);    // quad_perm [2,3,0,1]
+    v = dpp_add<0x141, 0xf>(v);   // row_half_mirror
+    v = dpp_add<0x140, 0xf>(v);   // row_mirror
+    v = dpp_add<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 // Sum NV values over the workgroup (blockDim.x = kBlock); result valid in
@@ -124,7 +148,7 @@ __device__ __forceinline__ T pend_df(const PendRec<T>& r, int i, T sg)
 // the pending SGS correction of each source cell when TO is active.
 // ---------------------------------------------------------------------------
 template <int LAT, typename T, bool TO>
-__device__ __forceinline__ void gather(const DevMember& m, const T* __restrict__ gs, int x, int y, int z,
+__device__ __forceinline__ void gather(KMember& m, const T* __restrict__ gs, int x, int y, int z,
                                        int cell, T* f)
 {
     using L = Lat<LAT>;
@@ -187,7 +211,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const DevMember* __restrict__ m
     constexpr int Q = L::Q, D = L::D;
     __shared__ double lds[4 * (kBlock / 64)];
     const int2 wk = work[blockIdx.x];
-    const DevMember& m = mems[wk.x];
+    KMember& m = *kc(mems + wk.x);
     const int N = m.N, nx = m.nx, ny = m.ny;
     const int cell = wk.y * kBlock + threadIdx.x;
     const int cur = m.parity ^ flip;
@@ -348,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(const DevMember* __restrict_
 {
     using L = Lat<LAT>;
     const int2 wk = work[blockIdx.x];
-    const DevMember& m = mems[wk.x];
+    KMember& m = *kc(mems + wk.x);
     const int N = m.N, nx = m.nx, ny = m.ny;
     const int cell = wk.y * kBlock + threadIdx.x;
     if (cell >= N) return;
@@ -410,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_curl(const DevMember* __restrict__ m
 {
     using L = Lat<LAT>;
     const int2 wk = work[blockIdx.x];
-    const DevMember& m = mems[wk.x];
+    KMember& m = *kc(mems + wk.x);
     if (!m.prm->has_z) return;
     const int N = m.N, nx = m.nx, ny = m.ny, nz = m.nz;
     const int cell = wk.y * kBlock + threadIdx.x;
@@ -467,8 +491,8 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
     constexpr int HX = kBinTX + 2, HY = kBinTY + 2, HXY = HX * HY;
     __shared__ T tile[NCMP][HXY];
     const int2 wk = work[blockIdx.x];
-    const DevMember& m = mems[wk.x];
-    const DevParam* prm = m.prm;
+    KMember& m = *kc(mems + wk.x);
+    KParam* prm = kc(m.prm);
     // this pass: B^j v (j <= jv), B^j w (j <= jw) and C_{j-1} = curl^T B^{j-1} w (j - 1 <= jw)
     const bool dov = j <= prm->jv, dow = prm->has_z && j <= prm->jw;
     const bool doc = prm->has_z && j - 1 <= prm->jw;
@@ -616,8 +640,23 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
 //      the binomial passes (2-D: curl^T psi = (D_y psi, -D_x psi); 3-D: curl).
 // Also returns the QoI densities 1/2 |R v|^2 and 1/2 |R w|^2 of the cell.
 // ---------------------------------------------------------------------------
+// Filter coefficients in the kernel's arithmetic type (FP32 copies are made
+// on the host, so both read them from scalar registers without conversion).
+template <typename T> __device__ __forceinline__ T coef_r(KParam* p, int s, int j);
+template <> __device__ __forceinline__ float coef_r<float>(KParam* p, int s, int j) { return p->rf[s][j]; }
+template <> __device__ __forceinline__ double coef_r<double>(KParam* p, int s, int j) { return p->r[s][j]; }
+template <typename T> __device__ __forceinline__ T coef_rr(KParam* p, int s, int j);
+template <> __device__ __forceinline__ float coef_rr<float>(KParam* p, int s, int j) { return p->rrf[s][j]; }
+template <> __device__ __forceinline__ double coef_rr<double>(KParam* p, int s, int j) { return p->rr[s][j]; }
+template <typename T> __device__ __forceinline__ T coef_cv(KCtl* c, int j);
+template <> __device__ __forceinline__ float coef_cv<float>(KCtl* c, int j) { return c->cvf[j]; }
+template <> __device__ __forceinline__ double coef_cv<double>(KCtl* c, int j) { return c->cv[j]; }
+template <typename T> __device__ __forceinline__ T coef_cw(KCtl* c, int j);
+template <> __device__ __forceinline__ float coef_cw<float>(KCtl* c, int j) { return c->cwf[j]; }
+template <> __device__ __forceinline__ double coef_cw<double>(KCtl* c, int j) { return c->cw[j]; }
+
 template <int LAT, typename T, int MAXSA>
-__device__ __forceinline__ void cell_sens(const DevMember& m, const DevParam* __restrict__ prm, int x, int y, int z,
+__device__ __forceinline__ void cell_sens(KMember& m, KParam* prm, int x, int y, int z,
                                           int cell, T (&pv)[kMaxPow + 1][Lat<LAT>::D], T (&V)[MAXSA][Lat<LAT>::D],
                                           double (&qd)[MAXSA])
 {
@@ -627,50 +666,61 @@ __device__ __forceinline__ void cell_sens(const DevMember& m, const DevParam* __
     const size_t sN = (size_t)m.N;
     const T* __restrict__ P = (const T*)m.P;
     const T* __restrict__ W = (const T*)m.W;
+    // Every load is unconditional, with the power clamped to the highest one
+    // stored: a power above jv (jw) only ever meets a zero coefficient, and
+    // loads that no branch guards all stay in flight together.
+    const T* __restrict__ vs = (const T*)m.vs;
 #pragma unroll
-    for (int a = 0; a < D; ++a) pv[0][a] = ((const T*)m.vs)[a * sN + cell];
+    for (int jj = 0; jj <= kMaxPow; ++jj) {
+        const int je = jj < jv ? jj : jv;
+        const T* src = je == 0 ? vs : P + (size_t)(je - 1) * D * sN;
 #pragma unroll
-    for (int jj = 1; jj <= kMaxPow; ++jj)
-#pragma unroll
-        for (int a = 0; a < D; ++a) pv[jj][a] = jj <= jv ? P[((size_t)(jj - 1) * D + a) * sN + cell] : T(0);
+        for (int a = 0; a < D; ++a) pv[jj][a] = src[a * sN + cell];
+    }
     T wc[3][NC];
+    const bool hz = prm->has_z;
 #pragma unroll
-    for (int jj = 0; jj < 3; ++jj)
+    for (int jj = 0; jj < 3; ++jj) {
+        const T* src = hz ? W + (size_t)(jj < jw ? jj : jw) * NC * sN : vs;   // (unused without Z QoIs)
 #pragma unroll
-        for (int a = 0; a < NC; ++a) wc[jj][a] = (prm->has_z && jj <= jw) ? W[((size_t)jj * NC + a) * sN + cell] : T(0);
+        for (int a = 0; a < NC; ++a) wc[jj][a] = src[a * sN + cell];
+    }
+    // C_j = curl^T B^j w (Z sensitivities)
+    const T* __restrict__ Cc = (const T*)m.C;
+    T cv[kMaxPow + 1][D];
+#pragma unroll
+    for (int jj = 0; jj <= kMaxPow; ++jj) {
+        const T* src = hz ? Cc + (size_t)(jj < jw ? jj : jw) * D * sN : vs;
+#pragma unroll
+        for (int a = 0; a < D; ++a) cv[jj][a] = src[a * sN + cell];
+    }
 #pragma unroll
     for (int s = 0; s < MAXSA; ++s) {
         qd[s] = 0;
 #pragma unroll
         for (int a = 0; a < D; ++a) V[s][a] = 0;
         if (s >= nsa) continue;
-        const double* r = prm->r[s];
+        const T r0 = coef_r<T>(prm, s, 0), r1 = coef_r<T>(prm, s, 1), r2 = coef_r<T>(prm, s, 2);
         if (prm->sa_kind[s] == 0) {
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                const T rv = T(r[0]) * pv[0][a] + T(r[1]) * pv[1][a] + T(r[2]) * pv[2][a];
+                const T rv = r0 * pv[0][a] + r1 * pv[1][a] + r2 * pv[2][a];
                 qd[s] += 0.5 * (double)(rv * rv);
                 T vv = 0;
 #pragma unroll
-                for (int jj = 0; jj <= kMaxPow; ++jj) vv += T(prm->rr[s][jj]) * pv[jj][a];
+                for (int jj = 0; jj <= kMaxPow; ++jj) vv += coef_rr<T>(prm, s, jj) * pv[jj][a];
                 V[s][a] = vv;
             }
         } else {
 #pragma unroll
             for (int a = 0; a < NC; ++a) {
-                const T rw = T(r[0]) * wc[0][a] + T(r[1]) * wc[1][a] + T(r[2]) * wc[2][a];
+                const T rw = r0 * wc[0][a] + r1 * wc[1][a] + r2 * wc[2][a];
                 qd[s] += 0.5 * (double)(rw * rw);
             }
         }
     }
-    if (!prm->has_z) return;
+    if (!hz) return;
     // Z sensitivities from the stored C_j = curl^T B^j w
-    const T* __restrict__ Cc = (const T*)m.C;
-    T cv[kMaxPow + 1][D];
-#pragma unroll
-    for (int jj = 0; jj <= kMaxPow; ++jj)
-#pragma unroll
-        for (int a = 0; a < D; ++a) cv[jj][a] = jj <= jw ? Cc[((size_t)jj * D + a) * sN + cell] : T(0);
 #pragma unroll
     for (int s = 0; s < MAXSA; ++s) {
         if (s >= nsa || prm->sa_kind[s] == 0) continue;
@@ -678,7 +728,7 @@ __device__ __forceinline__ void cell_sens(const DevMember& m, const DevParam* __
         for (int a = 0; a < D; ++a) {
             T vv = 0;
 #pragma unroll
-            for (int jj = 0; jj <= kMaxPow; ++jj) vv += T(prm->rr[s][jj]) * cv[jj][a];
+            for (int jj = 0; jj <= kMaxPow; ++jj) vv += coef_rr<T>(prm, s, jj) * cv[jj][a];
             V[s][a] = vv;
         }
     }
@@ -700,8 +750,8 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const DevMember* __restrict__
     constexpr int NV = MAXSA + NG + 1 + MAXSA;
     __shared__ double lds[NV * (kBlock / 64)];
     const int2 wk = work[blockIdx.x];
-    const DevMember& m = mems[wk.x];
-    const DevParam* __restrict__ prm = m.prm;
+    KMember& m = *kc(mems + wk.x);
+    KParam* prm = kc(m.prm);
     const int nx = m.nx, ny = m.ny, nz = m.nz;
     const int y = wk.y / m.nbx2, bx = wk.y % m.nbx2;
     const int plane = nx * nz;
@@ -830,7 +880,7 @@ __global__ __launch_bounds__(kBlock) void k_sum(const DevMember* __restrict__ me
 {
     __shared__ double red[kBlock / 64];
     const int2 wk = work[blockIdx.x];
-    const DevMember& m = mems[wk.x];
+    KMember& m = *kc(mems + wk.x);
     const int slot = wk.y;
     if (slot >= 4 + m.npart) return;
     double v[1] = {0};
@@ -860,8 +910,8 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
     __shared__ double M[kMaxQ][2 * kMaxQ];
     __shared__ double q[kMaxQ], dq[kMaxQ], beta[kMaxQ], gam[kMaxQ], z[kMaxQ], fac[kMaxQ];
     __shared__ int sing;
-    const DevMember& m = mems[work[blockIdx.x]];
-    const DevParam* __restrict__ prm = m.prm;
+    KMember& m = *kc(mems + work[blockIdx.x]);
+    KParam* prm = kc(m.prm);
     DevCtl* ctl = m.ctl;
     const int tid = threadIdx.x;
     const int nq = prm->nq, nsa = prm->nsa, nmp = prm->nmp;
@@ -986,6 +1036,8 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
         }
         ctl->cv[tid] = a;
         ctl->cw[tid] = b;
+        ctl->cvf[tid] = (float)a;
+        ctl->cwf[tid] = (float)b;
     }
     lbm_qoi_rec* rec = m.recs + (size_t)(step % m.rec_cap);
     if (tid < kMaxQ) {
@@ -1022,27 +1074,31 @@ __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ 
     using L = Lat<LAT>;
     constexpr int D = L::D;
     const int2 wk = work[blockIdx.x];
-    const DevMember& m = mems[wk.x];
-    const DevParam* __restrict__ prm = m.prm;
+    KMember& m = *kc(mems + wk.x);
+    KParam* prm = kc(m.prm);
     const int N = m.N, nx = m.nx, ny = m.ny, nz = m.nz;
     const int cell = wk.y * kBlock + threadIdx.x;
     if (cell >= N) return;
     const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
     const size_t sN = (size_t)N;
-    const double* cv = m.ctl->cv;
-    const double* cw = m.ctl->cw;
+    KCtl* ctl = kc(m.ctl);
+    const int jv = prm->jv, jw = prm->jw;
     T out[3] = {0, 0, 0};
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        T s = T(cv[0]) * ((const T*)m.vs)[a * sN + cell];
-        for (int jj = 1; jj <= prm->jv; ++jj) s += T(cv[jj]) * ((const T*)m.P)[((size_t)(jj - 1) * D + a) * sN + cell];
+        T s = coef_cv<T>(ctl, 0) * ((const T*)m.vs)[a * sN + cell];
+#pragma unroll
+        for (int jj = 1; jj <= kMaxPow; ++jj)
+            if (jj <= jv) s += coef_cv<T>(ctl, jj) * ((const T*)m.P)[((size_t)(jj - 1) * D + a) * sN + cell];
         out[a] = s;
     }
     if (prm->has_z) {
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             T sacc = 0;
-            for (int jj = 0; jj <= prm->jw; ++jj) sacc += T(cw[jj]) * ((const T*)m.C)[((size_t)jj * D + a) * sN + cell];
+#pragma unroll
+            for (int jj = 0; jj <= kMaxPow; ++jj)
+                if (jj <= jw) sacc += coef_cw<T>(ctl, jj) * ((const T*)m.C)[((size_t)jj * D + a) * sN + cell];
             out[a] += sacc;
         }
     }
@@ -1075,7 +1131,7 @@ __global__ __launch_bounds__(kBlock) void k_diag(const DevMember* __restrict__ m
     constexpr int D = L::D;
     __shared__ double lds[2 * (kBlock / 64)];
     const int2 wk = work[blockIdx.x];
-    const DevMember& m = mems[wk.x];
+    KMember& m = *kc(mems + wk.x);
     const int N = m.N, nx = m.nx, ny = m.ny, nz = m.nz;
     const int cell = wk.y * kBlock + threadIdx.x;
     double v[2] = {0, 0};
@@ -1106,7 +1162,7 @@ __global__ __launch_bounds__(kBlock) void k_diag(const DevMember* __restrict__ m
 __global__ __launch_bounds__(kBlock) void k_fin_diag(const DevMember* __restrict__ mems, const int* __restrict__ work)
 {
     __shared__ double red[6 * (kBlock / 64)];
-    const DevMember& m = mems[work[blockIdx.x]];
+    KMember& m = *kc(mems + work[blockIdx.x]);
     double v[6] = {0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < m.nb1; b += kBlock) {
         for (int k = 0; k < 4; ++k) v[k] += m.part_stats[(size_t)b * 4 + k];
@@ -1140,7 +1196,7 @@ __global__ void k_init(const DevMember* __restrict__ mems, int flip, const doubl
                        const double* __restrict__ u0)
 {
     using L = Lat<LAT>;
-    const DevMember& m = mems[0];
+    KMember& m = *kc(mems);
     const int N = m.N;
     const int cell = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= N) return;
@@ -1166,7 +1222,7 @@ template <int LAT, typename T, int PREC, bool TO>
 __global__ void k_get_pop(const DevMember* __restrict__ mems, int flip, double* __restrict__ f)
 {
     using L = Lat<LAT>;
-    const DevMember& m = mems[0];
+    KMember& m = *kc(mems);
     const int N = m.N;
     const int cell = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= N) return;
@@ -1185,7 +1241,7 @@ template <int LAT, typename T, int PREC>
 __global__ void k_set_pop(const DevMember* __restrict__ mems, int flip, const double* __restrict__ f)
 {
     using L = Lat<LAT>;
-    const DevMember& m = mems[0];
+    KMember& m = *kc(mems);
     const int N = m.N;
     const int cell = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= N) return;
@@ -1205,7 +1261,7 @@ template <int LAT, typename T, bool TO>
 __global__ void k_stream_only(const DevMember* __restrict__ mems, int flip)
 {
     using L = Lat<LAT>;
-    const DevMember& m = mems[0];
+    KMember& m = *kc(mems);
     const int N = m.N, nx = m.nx, ny = m.ny;
     const int cell = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= N) return;
@@ -1223,7 +1279,7 @@ template <int LAT, typename T, int PREC>
 __global__ void k_flush(const DevMember* __restrict__ mems, int flip)
 {
     using L = Lat<LAT>;
-    const DevMember& m = mems[0];
+    KMember& m = *kc(mems);
     const int N = m.N;
     const int cell = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= N) return;
