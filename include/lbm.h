@@ -145,7 +145,10 @@ const char* lbm_version(void);
 int lbm_lattice_info(int lattice, int* c, double* w);
 
 /* Device bytes a context needs for cfg (and the closure it will run, or
- * NULL for a plain run).  Returns 0 for an invalid configuration. */
+ * NULL for a plain run).  Returns 0 for an invalid configuration.  Grids are
+ * limited to 2e9 cells; a run with a closure also needs N times the element
+ * size (4 or 8 bytes) below 4 GiB, since its kernels address each field
+ * component with 32-bit byte offsets. */
 size_t lbm_required_bytes(const lbm_config* cfg, const lbm_closure* closure);
 
 /* Create a context on the current HIP device.  dev_arena: caller-owned

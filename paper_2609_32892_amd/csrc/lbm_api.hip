@@ -69,6 +69,11 @@ int closure_shape(const lbm_config* cfg, const lbm_closure* cl, ClosureShape* ou
     if (cl->nq < 1 || cl->nq > LBM_MAX_QOI || !cl->q) return fail(LBM_EINVAL, "closure: nq must be in [1,%d]", LBM_MAX_QOI);
     if (cl->h != 0) return fail(LBM_EINVAL, "closure: only history length h = 0 is supported");
     if (cl->mode < LBM_CLOSURE_OFF || cl->mode > LBM_CLOSURE_LRS) return fail(LBM_EINVAL, "closure: bad mode");
+    {
+        // the TO kernels address every field component with 32-bit byte offsets
+        const double bytes = (double)cfg->nx * cfg->ny * cfg->nz * (cfg->precision == LBM_FP64 ? 8 : 4);
+        if (bytes >= 4294967296.0) return fail(LBM_EINVAL, "closure: grid too large for a TO run (N * element size must be below 4 GiB)");
+    }
     s.nq = cl->nq;
     s.nbands = cl->nbands;
     for (int k = 0; k < cl->nq; ++k) {
@@ -136,10 +141,12 @@ void make_plan(const lbm_config* c, const ClosureShape& cs, Plan* p)
     P.nbx2 = (plane + kBlock * P.cpt2 - 1) / (kBlock * P.cpt2);
     P.nbr = P.nbx2 * c->ny;
     {
-        // z chunk: as many planes per workgroup as keeps >= 1024 workgroups
+        // z chunk: as many planes per workgroup as keeps about 400 or more
+        // workgroups (measured on MI355X: fewer staged halo planes pay more
+        // than extra workgroups once the chip has 1.5 per CU)
         const int nxy = ((c->nx + kBinTX - 1) / kBinTX) * ((c->ny + kBinTY - 1) / kBinTY);
         P.zc = P.D == 3 ? (c->tune_zc > 0 ? std::min(c->tune_zc, c->nz)
-                                           : std::max(1, std::min(kBinZCMax, nxy * c->nz / 1024)))
+                                           : std::max(1, std::min(kBinZCMax, nxy * c->nz / 400)))
                         : 1;
         P.nbb = nxy * (P.D == 3 ? (c->nz + P.zc - 1) / P.zc : 1);
     }

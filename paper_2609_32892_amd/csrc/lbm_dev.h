@@ -70,7 +70,7 @@ struct DevMember {
     void* W;                           // B^j curl v*, j=0..jw [jw+1][NC][N]
     void* C;                           // curl^T B^j curl v*, j=0..jw [jw+1][D][N]
     double* part_stats;                // [nb1][4]: sum(rho-1), sum(rho v)
-    double* part_to;                   // [ny][nbx2][npart]
+    double* part_to;                   // [npart][ny * nbx2]
     double* part_diag;                 // [nb1][2]
     int nb1, nbx2, npart, cpt2;        // block counts; cells per thread of the reduce
     int zc, pad1;                      // z planes per binomial-filter workgroup

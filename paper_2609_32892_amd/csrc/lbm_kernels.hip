@@ -113,6 +113,21 @@ __device__ __forceinline__ void block_sum(double* v, double* lds)
     __syncthreads();
 }
 
+// Global accesses at an element index below 2^32 / sizeof(T) from a
+// workgroup-uniform base: the byte offset is formed in 32 bits, so the access
+// uses a scalar base plus one 32-bit vector offset (no 64-bit address per
+// lane).  The library rejects grids whose fields would not fit.
+template <typename T>
+__device__ __forceinline__ T ld_at(const T* base, unsigned i)
+{
+    return *(const T*)((const char*)base + i * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st_at(T* base, unsigned i, T v)
+{
+    *(T*)((char*)base + i * (unsigned)sizeof(T)) = v;
+}
+
 // feq_i(rho, a) - feq_i(rho, b) in difference form (exactly zero when a = b):
 // w rho [3 c.(a-b) + 9/2 (c.(a-b))(c.(a+b)) - 3/2 (a-b).(a+b)].
 template <typename T>
@@ -170,7 +185,8 @@ __device__ __forceinline__ void gather(KMember& m, const T* __restrict__ gs, int
             src = sx + nx * (sy + ny * sz);
             pi = i;
         }
-        T v = gs[(size_t)pi * N + src];
+        // (TO runs keep every field below 2^32 bytes: 32-bit offsets)
+        T v = TO ? ld_at(gs + (size_t)pi * N, (unsigned)src) : gs[(size_t)pi * N + src];
         if (TO) {
             // delta f_pi(src) with c_pi = s c_i
             const PendRec<T> r = pc[src];
@@ -333,12 +349,15 @@ __global__ __launch_bounds__(kBlock) void k_step(const DevMember* __restrict__ m
             T cs = T(L::cx[i]) * (us[0] + u[0]) + T(L::cy[i]) * (us[1] + u[1]) +
                    (D == 3 ? T(L::cz[i]) * (us[2] + u[2]) : T(0));
             T out = f[i] - om * (f[i] - geq[i]) + dfeq<T>(T(L::w[i]), rho, cd, cs, dd);
-            gd[(size_t)i * N + cell] = out;
+            if (MODE == 2)
+                st_at(gd + (size_t)i * N, (unsigned)cell, out);
+            else
+                gd[(size_t)i * N + cell] = out;
         }
         if (MODE == 2) {
-            ((T*)m.rho)[cell] = drho;
+            st_at((T*)m.rho, (unsigned)cell, drho);
 #pragma unroll
-            for (int a = 0; a < D; ++a) ((T*)m.vs)[(size_t)a * N + cell] = us[a];
+            for (int a = 0; a < D; ++a) st_at((T*)m.vs + (size_t)a * N, (unsigned)cell, us[a]);
         }
         if (MODE == 1 && SUB != LBM_WALE) {  // (with WALE, k_moments wrote v^n)
 #pragma unroll
@@ -489,7 +508,8 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
     using L = Lat<LAT>;
     constexpr int D = L::D, NC = L::NC, NCMP = D + NC;
     constexpr int HX = kBinTX + 2, HY = kBinTY + 2, HXY = HX * HY;
-    __shared__ T tile[NCMP][HXY];
+    // the staged plane [component][halo tile]
+    __shared__ T tile[NCMP * HXY];
     const int2 wk = work[blockIdx.x];
     KMember& m = *kc(mems + wk.x);
     KParam* prm = kc(m.prm);
@@ -507,34 +527,29 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
     const int lx = threadIdx.x % kBinTX, ly = threadIdx.x / kBinTX;
     const int x = tx0 + lx, y = ty0 + ly;
     const bool own = x < nx && y < ny;
-    // source and destination component pointers
+    // Source and destination component pointers.  Every component is loaded
+    // unconditionally (no branch-joined loads, so the loads of a plane stay
+    // in flight together); a chain this pass does not advance re-reads the
+    // other chain's source (cache hits) and stores nothing.
     const T* src[NCMP];
     T* dst[NCMP];
+    const T* sv = j == 1 ? (const T*)m.vs : (const T*)m.P + (size_t)(j - 2) * D * sN;
+    const T* sw = (const T*)m.W + (size_t)(j - 1) * NC * sN;
 #pragma unroll
-    for (int c = 0; c < NCMP; ++c) { src[c] = nullptr; dst[c] = nullptr; }
-    if (dov) {
-        const T* sv = j == 1 ? (const T*)m.vs : (const T*)m.P + (size_t)(j - 2) * D * sN;
-        T* dv = (T*)m.P + (size_t)(j - 1) * D * sN;
-#pragma unroll
-        for (int a = 0; a < D; ++a) { src[a] = sv + a * sN; dst[a] = dv + a * sN; }
+    for (int a = 0; a < D; ++a) {
+        src[a] = dov ? sv + a * sN : sw + (a % NC) * sN;
+        dst[a] = dov ? (T*)m.P + ((size_t)(j - 1) * D + a) * sN : nullptr;
     }
-    T* cdst = nullptr;
-    if (doc) {
-        const T* sw = (const T*)m.W + (size_t)(j - 1) * NC * sN;
-        T* dw = (T*)m.W + (size_t)j * NC * sN;
 #pragma unroll
-        for (int a = 0; a < NC; ++a) { src[D + a] = sw + a * sN; dst[D + a] = dow ? dw + a * sN : nullptr; }
-        cdst = (T*)m.C + (size_t)(j - 1) * D * sN;
+    for (int a = 0; a < NC; ++a) {
+        src[D + a] = doc ? sw + a * sN : sv + (a % D) * sN;
+        dst[D + a] = dow ? (T*)m.W + ((size_t)j * NC + a) * sN : nullptr;
     }
+    T* cdst = doc ? (T*)m.C + (size_t)(j - 1) * D * sN : nullptr;
     const int zr = D == 3 ? 1 : 0;
     const int zend = D == 3 ? min(tz0 + zc, nz) : 1;
-    T s0[NCMP], s1[NCMP];
-    T r1[NC], r2[NC], dxy[NC][2];   // w at planes z-1 and z (own cell), xy derivatives at z
-#pragma unroll
-    for (int c = 0; c < NCMP; ++c) { s0[c] = 0; s1[c] = 0; }
-#pragma unroll
-    for (int a = 0; a < NC; ++a) { r1[a] = 0; r2[a] = 0; dxy[a][0] = 0; dxy[a][1] = 0; }
-    // the (at most two) halo elements this thread stages, as offsets within a plane
+    // the (at most two) halo elements this thread stages, as offsets within
+    // a plane; an element outside the walls loads cell 0 and stages zero
     constexpr int NE = (HXY + kBlock - 1) / kBlock;
     int eoff[NE];
     bool eok[NE];
@@ -552,36 +567,30 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
         eoff[k] = ok ? gx + nx * gy : 0;
     }
     const int plane = nx * ny;
-    // software pipeline: the loads of the next plane are in flight while the
-    // current plane is filtered
-    T pre[NE][NCMP];
-    auto fetch = [&](int pz) {
+    auto fetch = [&](int pz, T (&buf)[NE][NCMP]) {
         const int zz = D == 3 ? modi(pz, nz) : 0;
-        const size_t zo = (size_t)plane * zz;
+        const unsigned zo = (unsigned)(plane * zz);
 #pragma unroll
         for (int k = 0; k < NE; ++k)
 #pragma unroll
-            for (int c = 0; c < NCMP; ++c) pre[k][c] = (src[c] && eok[k]) ? src[c][zo + eoff[k]] : T(0);
+            for (int c = 0; c < NCMP; ++c) buf[k][c] = ld_at(src[c], zo + (unsigned)eoff[k]);
     };
-    fetch(tz0 - zr);
-    for (int pz = tz0 - zr; pz <= zend - 1 + zr; ++pz) {
+    auto stage = [&](int pl, const T (&buf)[NE][NCMP]) {
 #pragma unroll
         for (int k = 0; k < NE; ++k) {
             const int e = threadIdx.x + k * kBlock;
             if (e < HXY) {
 #pragma unroll
-                for (int c = 0; c < NCMP; ++c)
-                    if (src[c]) tile[c][e] = pre[k][c];
+                for (int c = 0; c < NCMP; ++c) tile[(pl * NCMP + c) * HXY + e] = eok[k] ? buf[k][c] : T(0);
             }
         }
-        __syncthreads();
-        if (pz + 1 <= zend - 1 + zr) fetch(pz + 1);
-        T sn[NCMP], rn[NC], dn[NC][2];
+    };
+    // x and y passes of the staged plane pl at the own cell; the own value
+    // and xy derivatives of w for the curl
+    auto xyfilter = [&](int pl, T (&sn)[NCMP], T (&rn)[NC], T (&dn)[NC][2]) {
 #pragma unroll
         for (int c = 0; c < NCMP; ++c) {
-            sn[c] = 0;
-            if (!src[c]) continue;
-            const T* t = tile[c] + ly * HX + lx;   // (lx, ly) is the lower-left halo corner
+            const T* t = tile + (pl * NCMP + c) * HXY + ly * HX + lx;   // (lx, ly): lower-left halo corner
             const T q0 = T(0.25) * (t[0] + T(2) * t[1] + t[2]);
             const T q1 = T(0.25) * (t[HX] + T(2) * t[HX + 1] + t[HX + 2]);
             const T q2 = T(0.25) * (t[2 * HX] + T(2) * t[2 * HX + 1] + t[2 * HX + 2]);
@@ -589,39 +598,66 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
         }
 #pragma unroll
         for (int a = 0; a < NC; ++a) {
-            rn[a] = 0; dn[a][0] = 0; dn[a][1] = 0;
-            if (!doc) continue;
-            const T* t = tile[D + a] + (ly + 1) * HX + lx + 1;
+            const T* t = tile + (pl * NCMP + D + a) * HXY + (ly + 1) * HX + lx + 1;
             rn[a] = t[0];
             dn[a][0] = T(0.5) * (t[1] - t[-1]);
             dn[a][1] = T(0.5) * (t[HX] - t[-HX]);
         }
+    };
+    // 3-D output of plane zo from the xy-filtered planes zo-1, zo, zo+1 (sa,
+    // sb, sc), w at zo-1 and zo+1 (ra, rc) and the xy derivatives at zo
+    auto emit3 = [&](int zo, const T (&sa)[NCMP], const T (&sb)[NCMP], const T (&sc)[NCMP], const T (&ra)[NC],
+                     const T (&rc)[NC], const T (&dxyb)[NC][2]) {
+        if (!own) return;
+        const size_t ci = (size_t)x + (size_t)nx * (y + (size_t)ny * zo);
+#pragma unroll
+        for (int c = 0; c < NCMP; ++c)
+            if (dst[c]) dst[c][ci] = T(0.25) * sa[c] + T(0.5) * sb[c] + T(0.25) * sc[c];
+        if (cdst) {   // curl w at plane zo: D_z from the planes above and below
+            const T dzx = T(0.5) * (rc[0] - ra[0]), dzy = T(0.5) * (rc[1] - ra[1]);
+            cdst[ci] = dxyb[2][1] - dzy;                  // D_y w_z - D_z w_y
+            cdst[sN + ci] = dzx - dxyb[2][0];             // D_z w_x - D_x w_z
+            cdst[2 * sN + ci] = dxyb[1][0] - dxyb[0][1];  // D_x w_y - D_y w_x
+        }
+    };
+    const int p0 = tz0 - zr, p1 = zend - 1 + zr;   // staged planes, inclusive
+    if (D == 2) {
+        T buf[NE][NCMP], sn[NCMP], rn[NC], dn[NC][2];
+        fetch(0, buf);
+        stage(0, buf);
         __syncthreads();
-        if (D == 2) {
-            if (own) {
-                const size_t ci = (size_t)x + (size_t)nx * y;
+        xyfilter(0, sn, rn, dn);
+        if (own) {
+            const size_t ci = (size_t)x + (size_t)nx * y;
 #pragma unroll
-                for (int c = 0; c < NCMP; ++c)
-                    if (dst[c]) dst[c][ci] = sn[c];
-                if (cdst) {   // curl^T of a scalar: (D_y w, -D_x w)
-                    cdst[ci] = dn[0][1];
-                    cdst[sN + ci] = -dn[0][0];
-                }
+            for (int c = 0; c < NCMP; ++c)
+                if (dst[c]) dst[c][ci] = sn[c];
+            if (cdst) {   // curl^T of a scalar: (D_y w, -D_x w)
+                cdst[ci] = dn[0][1];
+                cdst[sN + ci] = -dn[0][0];
             }
-        } else {
-            const int zo = pz - 1;  // output plane once its upper neighbour is staged
-            if (pz >= tz0 + 1 && own) {
-                const size_t ci = (size_t)x + (size_t)nx * (y + (size_t)ny * zo);
+        }
+    } else {
+        // zc output planes: software pipeline over a three-plane register
+        // window; the loads of the next plane are in flight while the
+        // current one is filtered.  (Measured on MI355X: deeper prefetch or
+        // a second LDS buffer do not pay here.)
+        T s0[NCMP], s1[NCMP];
+        T r1[NC], r2[NC], dxy[NC][2];   // w at planes z-1 and z (own cell), xy derivatives at z
 #pragma unroll
-                for (int c = 0; c < NCMP; ++c)
-                    if (dst[c]) dst[c][ci] = T(0.25) * s0[c] + T(0.5) * s1[c] + T(0.25) * sn[c];
-                if (cdst) {   // curl w at plane zo: D_z from the planes above and below
-                    const T dzx = T(0.5) * (rn[0] - r1[0]), dzy = T(0.5) * (rn[1] - r1[1]);
-                    cdst[ci] = dxy[2][1] - dzy;             // D_y w_z - D_z w_y
-                    cdst[sN + ci] = dzx - dxy[2][0];        // D_z w_x - D_x w_z
-                    cdst[2 * sN + ci] = dxy[1][0] - dxy[0][1];  // D_x w_y - D_y w_x
-                }
-            }
+        for (int c = 0; c < NCMP; ++c) { s0[c] = 0; s1[c] = 0; }
+#pragma unroll
+        for (int a = 0; a < NC; ++a) { r1[a] = 0; r2[a] = 0; dxy[a][0] = 0; dxy[a][1] = 0; }
+        T buf[NE][NCMP];
+        fetch(p0, buf);
+        for (int pz = p0; pz <= p1; ++pz) {
+            stage(0, buf);
+            __syncthreads();
+            if (pz < p1) fetch(pz + 1, buf);
+            T sn[NCMP], rn[NC], dn[NC][2];
+            xyfilter(0, sn, rn, dn);
+            __syncthreads();
+            if (pz >= tz0 + 1) emit3(pz - 1, s0, s1, sn, r1, rn, dxy);  // once its upper neighbour is staged
 #pragma unroll
             for (int c = 0; c < NCMP; ++c) { s0[c] = s1[c]; s1[c] = sn[c]; }
 #pragma unroll
@@ -787,30 +823,43 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const DevMember* __restrict__
             for (int s = 0; s < MAXSA; ++s) acc[MAXSA + NG + 1 + s] += (double)V[s][0];
         }
     }
+    // band weights w_j(y) of this row (workgroup-uniform: scalar loads,
+    // issued before the reduction so that their latency is hidden)
+    double wb[kMaxQ];
+    const int nmp = prm->nmp;
+    if (hasmp) {
+        const LBM_K double* bw = kc(m.bandw);
+#pragma unroll
+        for (int jm = 0; jm < kMaxQ; ++jm) wb[jm] = bw[(size_t)prm->mp_band[jm < nmp ? jm : nmp - 1] * ny + y];
+    }
     block_sum<NV>(acc, lds);
     if (threadIdx.x == 0) {
-        // compile-time indices into acc keep it in registers
-        double* out = m.part_to + (size_t)wk.y * m.npart;
+        // partials are stored value-major, [npart][ny * nbx2], so that the
+        // cross-block sums read them contiguously; compile-time indices into
+        // acc keep it in registers
+        const size_t nblk = (size_t)ny * m.nbx2;
+        double* out = m.part_to + wk.y;
 #pragma unroll
         for (int s = 0; s < MAXSA; ++s)
-            if (s < nsa) out[s] = acc[s];
+            if (s < nsa) out[s * nblk] = acc[s];
         int g = 0;
 #pragma unroll
         for (int s = 0; s < MAXSA; ++s)
 #pragma unroll
             for (int t2 = s; t2 < MAXSA; ++t2, ++g)
-                if (t2 < nsa) out[nsa + s * nsa - s * (s - 1) / 2 + (t2 - s)] = acc[MAXSA + g];
+                if (t2 < nsa) out[(nsa + s * nsa - s * (s - 1) / 2 + (t2 - s)) * nblk] = acc[MAXSA + g];
         if (hasmp) {
             // mean-profile terms, weighted by the band weights of this row:
             // w_j(y) sum v*_x and w_j(y) sum V_s,x for every band j
             const int o = nsa + nsa * (nsa + 1) / 2;
-            for (int jm = 0; jm < prm->nmp; ++jm) {
-                const double wj = m.bandw[(size_t)prm->mp_band[jm] * ny + y];
-                double* oj = out + o + jm * (1 + nsa);
-                oj[0] = wj * acc[MAXSA + NG];
+#pragma unroll
+            for (int jm = 0; jm < kMaxQ; ++jm) {
+                if (jm >= nmp) break;
+                double* oj = out + (o + jm * (1 + nsa)) * nblk;
+                oj[0] = wb[jm] * acc[MAXSA + NG];
 #pragma unroll
                 for (int s = 0; s < MAXSA; ++s)
-                    if (s < nsa) oj[1 + s] = wj * acc[MAXSA + NG + 1 + s];
+                    if (s < nsa) oj[(1 + s) * nblk] = wb[jm] * acc[MAXSA + NG + 1 + s];
             }
         }
     }
@@ -885,10 +934,13 @@ __global__ __launch_bounds__(kBlock) void k_sum(const DevMember* __restrict__ me
     if (slot >= 4 + m.npart) return;
     double v[1] = {0};
     if (slot < 4) {
+#pragma unroll 8
         for (int b = threadIdx.x; b < m.nb1; b += kBlock) v[0] += m.part_stats[(size_t)b * 4 + slot];
     } else {
         const int nblk = m.ny * m.nbx2;
-        for (int b = threadIdx.x; b < nblk; b += kBlock) v[0] += m.part_to[(size_t)b * m.npart + slot - 4];
+        const double* p = m.part_to + (size_t)(slot - 4) * nblk;
+#pragma unroll 8
+        for (int b = threadIdx.x; b < nblk; b += kBlock) v[0] += p[b];
     }
     block_sum<1>(v, red);
     if (threadIdx.x == 0) m.sums[slot] = v[0];
@@ -897,19 +949,27 @@ __global__ __launch_bounds__(kBlock) void k_sum(const DevMember* __restrict__ me
 // ---------------------------------------------------------------------------
 // K3: one workgroup per member.  Fixed-order sums of the partials, the QoI
 // vector and Gram matrix, dQ, beta = G^-1 dQ and gamma_k = dQ_k (G^-1)_kk,
-// the per-step record and the coefficients of the dv build.  All small
-// matrices live in LDS and every stage is spread over the workgroup.
+// the per-step record and the coefficients of the dv build.  Every input is
+// first staged into LDS in one parallel pass (one memory latency), and all
+// small matrices live there, every stage spread over the workgroup.
 // G is symmetric positive semi-definite, so Gauss-Jordan elimination needs
 // no pivoting; its pivots are the squared Cholesky pivots, and G counts as
 // singular when one of them is not above 1e-14 times the largest diagonal
-// entry.
+// entry.  The elimination ping-pongs between two copies of [G | I], one
+// barrier per pivot.
 // ---------------------------------------------------------------------------
+constexpr int kMaxSums = 4 + kMaxSA + kMaxSA * (kMaxSA + 1) / 2 + kMaxQ * (1 + kMaxSA);
+
 __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ mems, const int* __restrict__ work)
 {
-    __shared__ double st[4];
-    __shared__ double M[kMaxQ][2 * kMaxQ];
-    __shared__ double q[kMaxQ], dq[kMaxQ], beta[kMaxQ], gam[kMaxQ], z[kMaxQ], fac[kMaxQ];
-    __shared__ int sing;
+    __shared__ double M[2][kMaxQ][2 * kMaxQ];
+    __shared__ double sf[kMaxSums];
+    __shared__ double Cs[(kMaxQ + 1) * kMaxQ], Ls[kMaxQ * kMaxQ];
+    __shared__ double q[kMaxQ], dq[kMaxQ], beta[kMaxQ], gam[kMaxQ], z[kMaxQ], sc[kMaxQ], qs[kMaxQ];
+    __shared__ double rrs[kMaxSA][kMaxPow + 1], gmps[kMaxQ * kMaxQ];
+    __shared__ int kinds[kMaxSA], saslot[kMaxSA], mpslot[kMaxQ], mpband[kMaxQ];
+    __shared__ long long step_s;
+    __shared__ int sset_s, flags_s;
     KMember& m = *kc(mems + work[blockIdx.x]);
     KParam* prm = kc(m.prm);
     DevCtl* ctl = m.ctl;
@@ -917,46 +977,58 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
     const int nq = prm->nq, nsa = prm->nsa, nmp = prm->nmp;
     const int ny = m.ny;
     const int nflat = nsa + nsa * (nsa + 1) / 2;
-    const long long step = ctl->step;
+    const int nsum = 4 + nflat + nmp * (1 + nsa);
+    const bool lrs = prm->mode == LBM_CLOSURE_LRS;
 
-    // (a) sums of the statistics and TO partials (from k_sum)
-    for (int k = tid; k < kMaxQ * 2 * kMaxQ; k += kBlock) M[k / (2 * kMaxQ)][k % (2 * kMaxQ)] = 0.0;
-    if (tid < kMaxQ) { q[tid] = 0; dq[tid] = 0; beta[tid] = 0; gam[tid] = 0; }
-    if (tid < 4) st[tid] = m.sums[tid];
-    if (tid == 0) sing = 0;
+    // (a) stage the sums, the LRS model and the control state; clear M
+    for (int k = tid; k < nsum; k += kBlock) sf[k] = m.sums[k];
+    if (lrs) {
+        for (int k = tid; k < (nq + 1) * kMaxQ; k += kBlock) Cs[k] = prm->C[k];
+        for (int k = tid; k < nq * kMaxQ; k += kBlock) Ls[k] = prm->L[k];
+    }
+    for (int k = tid; k < 2 * kMaxQ * 2 * kMaxQ; k += kBlock) (&M[0][0][0])[k] = 0.0;
+    if (tid < kMaxSA * (kMaxPow + 1)) (&rrs[0][0])[tid] = (&prm->rr[0][0])[tid];
+    if (tid < kMaxSA) { kinds[tid] = prm->sa_kind[tid]; saslot[tid] = prm->sa_slot[tid]; }
+    if (tid < kMaxQ) { mpslot[tid] = prm->mp_slot[tid]; mpband[tid] = prm->mp_band[tid]; }
+    for (int pr = tid; pr < nmp * nmp; pr += kBlock) gmps[pr] = prm->gmp[(pr / nmp) * kMaxQ + pr % nmp];
+    if (tid < kMaxQ) {
+        q[tid] = 0; dq[tid] = 0; beta[tid] = 0; gam[tid] = 0;
+        sc[tid] = ctl->s[tid];
+    }
+    if (tid == 0) { step_s = ctl->step; sset_s = ctl->s_set; flags_s = ctl->flags; }
     __syncthreads();
-    const double* sf = m.sums + 4;
-    // (b) assemble q and G (left half of M)
+    const long long step = step_s;
+    const bool active = step >= prm->spinup;
+    // (b) assemble q and G (left half of M), the mean-profile entries and
+    // the identity (right half); the LRS normals meanwhile
+    const double* sfp = sf + 4;
     if (tid < nsa) {
         const int s = tid;
-        q[prm->sa_slot[s]] = sf[s];
+        q[saslot[s]] = sfp[s];
         int g = nsa + s * nsa - s * (s - 1) / 2;
         for (int t = s; t < nsa; ++t, ++g) {
-            M[prm->sa_slot[s]][prm->sa_slot[t]] = sf[g];
-            M[prm->sa_slot[t]][prm->sa_slot[s]] = sf[g];
+            M[0][saslot[s]][saslot[t]] = sfp[g];
+            M[0][saslot[t]][saslot[s]] = sfp[g];
         }
     }
-    // (c) mean-profile QoIs and mixed Gram entries
     for (int pr = tid; pr < nmp * (1 + nsa); pr += kBlock) {
         const int jm = pr / (1 + nsa), c = pr % (1 + nsa);
-        const double v = sf[nflat + pr];
-        const int uj = prm->mp_slot[jm];
+        const double v = sfp[nflat + pr];
+        const int uj = mpslot[jm];
         if (c == 0)
             q[uj] = v;
         else {
-            const int us = prm->sa_slot[c - 1];
-            M[uj][us] = v;
-            M[us][uj] = v;
+            const int us = saslot[c - 1];
+            M[0][uj][us] = v;
+            M[0][us][uj] = v;
         }
     }
     for (int pr = tid; pr < nmp * nmp; pr += kBlock) {
         const int a = pr / nmp, b = pr % nmp;
-        M[prm->mp_slot[a]][prm->mp_slot[b]] = prm->gmp[a * kMaxQ + b];
+        M[0][mpslot[a]][mpslot[b]] = gmps[pr];
     }
-    if (tid < nq) M[tid][kMaxQ + tid] = 1.0;
-    // (d) dQ: tracking, or the LRS draw
-    const bool active = step >= prm->spinup;
-    if (active && prm->mode == LBM_CLOSURE_LRS && tid < (nq + 3) / 4) {
+    if (tid < nq) M[0][tid][kMaxQ + tid] = 1.0;
+    if (active && lrs && tid < (nq + 3) / 4) {
         // four normals per Philox block
         double zz[4];
         uint32_t c[4] = {(uint32_t)tid, (uint32_t)(unsigned long long)step,
@@ -975,64 +1047,67 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
             if (4 * tid + k < nq) z[4 * tid + k] = zz[k];
     }
     __syncthreads();
+    // (c) dQ for tracking; the LRS scale (fixed at the first active step)
     if (active && tid < nq) {
         const int k = tid;
         if (prm->mode == LBM_CLOSURE_TRACK) {
             if (step < prm->nref) dq[k] = prm->qref[(size_t)step * nq + k] - q[k];
-        } else if (prm->mode == LBM_CLOSURE_LRS) {
-            if (!ctl->s_set) ctl->s[k] = prm->have_scale ? prm->scale[k] : (q[k] != 0.0 ? fabs(q[k]) : 1.0);
+        } else if (lrs) {
+            if (!sset_s) {
+                sc[k] = prm->have_scale ? prm->scale[k] : (q[k] != 0.0 ? fabs(q[k]) : 1.0);
+                ctl->s[k] = sc[k];
+            }
+            qs[k] = q[k] / sc[k];
         }
     }
     __syncthreads();
-    if (active && prm->mode == LBM_CLOSURE_LRS && tid < nq) {
+    // (d) the LRS draw
+    if (active && lrs && tid < nq) {
         const int k = tid;
         double e = prm->mu[k];
-        for (int j = 0; j <= k; ++j) e += prm->L[k * kMaxQ + j] * z[j];
+        for (int j = 0; j <= k; ++j) e += Ls[k * kMaxQ + j] * z[j];
         double zh = e;
-        for (int i = 0; i < nq; ++i) zh += (q[i] / ctl->s[i]) * prm->C[i * kMaxQ + k];
-        zh += prm->C[nq * kMaxQ + k];
-        dq[k] = ctl->s[k] * zh - q[k];
+        for (int i = 0; i < nq; ++i) zh += qs[i] * Cs[i * kMaxQ + k];
+        zh += Cs[nq * kMaxQ + k];
+        dq[k] = sc[k] * zh - q[k];
     }
-    // (e) Gauss-Jordan on [G | I]
+    // (e) Gauss-Jordan on [G | I]; only columns 0..nq-1 and kMaxQ..kMaxQ+nq-1
+    // are nonzero
     double mx = 0;
-    for (int k = 0; k < nq; ++k) mx = fmax(mx, M[k][k]);
-    if (!(mx > 0)) {
-        if (tid == 0) sing = 1;
-    }
-    __syncthreads();
+    for (int k = 0; k < nq; ++k) mx = fmax(mx, M[0][k][k]);
+    int sing = mx > 0 ? 0 : 1;
+    int cur = 0;
+    // thread layout: one column of [G | I] each, rows split over the
+    // kBlock / (2 nq) groups of threads, so one division per thread and pivot
+    const int ncol = 2 * nq, ngrp = kBlock / ncol;
+    const int gcol = tid % ncol, grow = tid / ncol;
+    const int cc = gcol < nq ? gcol : kMaxQ + gcol - nq;
     for (int j = 0; j < nq && !sing; ++j) {
-        const double piv = M[j][j];
-        if (!(piv > 1e-14 * mx)) {
-            __syncthreads();
-            if (tid == 0) sing = 1;
-            __syncthreads();
-            break;
+        const double piv = M[cur][j][j];
+        if (!(piv > 1e-14 * mx)) { sing = 1; break; }   // uniform: every thread reads the same pivot
+        if (grow < ngrp) {
+            const double pj = M[cur][j][cc] / piv;
+            for (int i = grow; i < nq; i += ngrp)
+                M[cur ^ 1][i][cc] = i == j ? pj : M[cur][i][cc] - M[cur][i][j] * pj;
         }
-        if (tid < nq) fac[tid] = M[tid][j];
-        __syncthreads();
-        for (int cidx = tid; cidx < 2 * kMaxQ; cidx += kBlock) M[j][cidx] /= piv;
-        __syncthreads();
-        for (int e = tid; e < nq * 2 * kMaxQ; e += kBlock) {
-            const int i = e / (2 * kMaxQ), cc = e % (2 * kMaxQ);
-            if (i != j) M[i][cc] -= fac[i] * M[j][cc];
-        }
+        cur ^= 1;
         __syncthreads();
     }
     // (f) beta = G^-1 dQ, gamma_k = dQ_k (G^-1)_kk
     if (!sing && tid < nq) {
         double b = 0;
-        for (int j = 0; j < nq; ++j) b += M[tid][kMaxQ + j] * dq[j];
+        for (int j = 0; j < nq; ++j) b += M[cur][tid][kMaxQ + j] * dq[j];
         beta[tid] = b;
-        gam[tid] = dq[tid] * M[tid][kMaxQ + tid];
+        gam[tid] = dq[tid] * M[cur][tid][kMaxQ + tid];
     }
     __syncthreads();
     // (g) dv coefficients, record, counters
     if (tid <= kMaxPow) {
         double a = 0, b = 0;
         for (int s = 0; s < nsa; ++s) {
-            const double bs = beta[prm->sa_slot[s]];
-            if (prm->sa_kind[s] == 0) a += bs * prm->rr[s][tid];
-            else b += bs * prm->rr[s][tid];
+            const double bs = beta[saslot[s]];
+            if (kinds[s] == 0) a += bs * rrs[s][tid];
+            else b += bs * rrs[s][tid];
         }
         ctl->cv[tid] = a;
         ctl->cw[tid] = b;
@@ -1047,22 +1122,31 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
     }
     if (tid == 0) {
         rec->step = step;
-        rec->flags = (ctl->flags & 1) | (sing ? 2 : 0);
+        rec->flags = (flags_s & 1) | (sing ? 2 : 0);
         rec->nq = nq;
-        rec->mass = (double)m.N + st[0];
-        rec->mom[0] = st[1];
-        rec->mom[1] = st[2];
-        rec->mom[2] = st[3];
+        rec->mass = (double)m.N + sf[0];
+        rec->mom[0] = sf[1];
+        rec->mom[1] = sf[2];
+        rec->mom[2] = sf[3];
         rec->diag_e = 0;
         rec->diag_z = 0;
-        if (active && prm->mode == LBM_CLOSURE_LRS) ctl->s_set = 1;
+        if (active && lrs) ctl->s_set = 1;
         ctl->step = step + 1;
     }
     // (h) mean-profile part of dv: cmp(y) = sum_j beta_mp_j w_j(y)
-    for (int yy = tid; yy < ny; yy += kBlock) {
-        double c = 0;
-        for (int jm = 0; jm < nmp; ++jm) c += beta[prm->mp_slot[jm]] * m.bandw[(size_t)prm->mp_band[jm] * ny + yy];
-        m.cmp[yy] = c;
+    if (nmp > 0) {
+        for (int yy = tid; yy < ny; yy += kBlock) {
+            // all band-weight loads first (clamped index; terms past nmp add exact zeros)
+            double wv[kMaxQ];
+#pragma unroll
+            for (int jm = 0; jm < kMaxQ; ++jm) wv[jm] = m.bandw[(size_t)mpband[jm < nmp ? jm : nmp - 1] * ny + yy];
+            double c = 0;
+#pragma unroll
+            for (int jm = 0; jm < kMaxQ; ++jm) c += jm < nmp ? beta[mpslot[jm]] * wv[jm] : 0.0;
+            m.cmp[yy] = c;
+        }
+    } else {
+        for (int yy = tid; yy < ny; yy += kBlock) m.cmp[yy] = 0.0;
     }
 }
 
@@ -1083,22 +1167,36 @@ __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ 
     const size_t sN = (size_t)N;
     KCtl* ctl = kc(m.ctl);
     const int jv = prm->jv, jw = prm->jw;
+    const bool hz = prm->has_z;
+    // Unconditional loads with the power clamped to the highest one stored:
+    // cv_j (cw_j) is zero above jv (jw), so the extra terms add exact zeros.
+    const T* __restrict__ vsp = (const T*)m.vs;
+    T fv[kMaxPow + 1][D], fc[kMaxPow + 1][D];
+#pragma unroll
+    for (int jj = 0; jj <= kMaxPow; ++jj) {
+        const int je = jj < jv ? jj : jv;
+        const T* src = je == 0 ? vsp : (const T*)m.P + (size_t)(je - 1) * D * sN;
+        const T* srcc = hz ? (const T*)m.C + (size_t)(jj < jw ? jj : jw) * D * sN : vsp;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            fv[jj][a] = src[a * sN + cell];
+            fc[jj][a] = srcc[a * sN + cell];
+        }
+    }
     T out[3] = {0, 0, 0};
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        T s = coef_cv<T>(ctl, 0) * ((const T*)m.vs)[a * sN + cell];
+        T s = coef_cv<T>(ctl, 0) * fv[0][a];
 #pragma unroll
-        for (int jj = 1; jj <= kMaxPow; ++jj)
-            if (jj <= jv) s += coef_cv<T>(ctl, jj) * ((const T*)m.P)[((size_t)(jj - 1) * D + a) * sN + cell];
+        for (int jj = 1; jj <= kMaxPow; ++jj) s += coef_cv<T>(ctl, jj) * fv[jj][a];
         out[a] = s;
     }
-    if (prm->has_z) {
+    if (hz) {
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             T sacc = 0;
 #pragma unroll
-            for (int jj = 0; jj <= kMaxPow; ++jj)
-                if (jj <= jw) sacc += coef_cw<T>(ctl, jj) * ((const T*)m.C)[((size_t)jj * D + a) * sN + cell];
+            for (int jj = 0; jj <= kMaxPow; ++jj) sacc += coef_cw<T>(ctl, jj) * fc[jj][a];
             out[a] += sacc;
         }
     }
@@ -1108,7 +1206,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ 
     PendRec<T> r;
     T vs[3] = {0, 0, 0};
 #pragma unroll
-    for (int a = 0; a < D; ++a) vs[a] = ((const T*)m.vs)[a * sN + cell];
+    for (int a = 0; a < D; ++a) vs[a] = fv[0][a];
     const T bx = T(2) * vs[0] + out[0], by = T(2) * vs[1] + out[1], bz = D == 3 ? T(2) * vs[2] + out[2] : T(0);
     r.u.x = rho * out[0];
     r.u.y = rho * out[1];
