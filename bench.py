@@ -95,12 +95,13 @@ def phase_bytes(w, ms, launches):
     wz = (min(jw, 2) + 1) * nc if has_z else 0   # W_0..W_2 read for the Z QoI densities
     cz = (jw + 1) * d if has_z else 0             # C_0..C_jw
     per_cell = {
-        # populations in and out, pending record (8 elements) in, rho and v* out
-        "stream_collide": e * (2 * Q + (8 + 1 + d if to else 0)),
+        # populations in and out, rho and v* out
+        "stream_collide": e * (2 * Q + (1 + d if to else 0)),
         "curl": e * (d + nc),
         "binomial": e * binom,
         "reduce": e * (d + jv * d + wz + cz),
-        "apply": e * (d + jv * d + cz + 1 + 8),
+        # v*, P_j, C_j and rho in; the populations read and written in place
+        "apply": e * (d + jv * d + cz + 1 + 2 * Q),
         "solve": 0,
     }
     return {k: per_cell[k] * N for k in per_cell}

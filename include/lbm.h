@@ -80,6 +80,8 @@ typedef struct {
     int rec_cap;        /* capacity of the per-step record ring (0: 4096) */
     int tune_zc;        /* tuning: z planes per binomial-filter workgroup (0: automatic) */
     int tune_cpt;       /* tuning: cells per thread of the QoI reduction (0: automatic) */
+    int tune_btx;       /* tuning: binomial tile width, 32 or 64 (0: automatic; 64 needs a
+                           D3Q19 grid; bitwise the same result either way) */
 } lbm_config;
 
 enum { LBM_QOI_E = 0, LBM_QOI_Z = 1, LBM_QOI_MP = 2 };
@@ -146,9 +148,10 @@ int lbm_lattice_info(int lattice, int* c, double* w);
 
 /* Device bytes a context needs for cfg (and the closure it will run, or
  * NULL for a plain run).  Returns 0 for an invalid configuration.  Grids are
- * limited to 2e9 cells; a run with a closure also needs N times the element
- * size (4 or 8 bytes) below 4 GiB, since its kernels address each field
- * component with 32-bit byte offsets. */
+ * limited to 2e9 cells; a run with a closure also needs 2 * N * (element
+ * size) below 4 GiB (N < 2^29 cells in FP32, 2^28 in FP64), since its
+ * kernels address each field, and pairs of population arrays, with 32-bit
+ * byte offsets. */
 size_t lbm_required_bytes(const lbm_config* cfg, const lbm_closure* closure);
 
 /* Create a context on the current HIP device.  dev_arena: caller-owned
@@ -183,16 +186,17 @@ int lbm_qoi(lbm_ctx* ctx, long first, long count, lbm_qoi_rec* out);
 int lbm_fields(lbm_ctx* ctx, double* rho, double* u);
 
 /* Full post-collision populations f (Q*N, library ordering, double) of the
- * current state, including a pending SGS correction; and the inverse. */
+ * current state (the SGS change of the last step included); and the
+ * inverse. */
 int lbm_get_populations(lbm_ctx* ctx, double* f);
 int lbm_set_populations(lbm_ctx* ctx, const double* f);
 
 /* Stream the current populations once without collision (index-map check). */
 int lbm_stream_only(lbm_ctx* ctx);
 
-/* Checkpoint: opaque byte image of the dynamic state (populations, pending
- * correction, counters, LRS scale, records).  Restoring it into a context
- * created with the same cfg and closure resumes bitwise identically. */
+/* Checkpoint: opaque byte image of the dynamic state (populations,
+ * counters, LRS scale, records).  Restoring it into a context created with
+ * the same cfg and closure resumes bitwise identically. */
 size_t lbm_state_bytes(const lbm_ctx* ctx);
 int lbm_get_state(lbm_ctx* ctx, void* host, size_t bytes);
 int lbm_set_state(lbm_ctx* ctx, const void* host, size_t bytes);

@@ -17,6 +17,7 @@ constexpr int kMaxPow = 4;      // highest power of B in R R (filters up to degr
 constexpr int kBlock = 256;     // threads per workgroup of the cell kernels
 constexpr int kBinTX = 32;      // binomial-filter tile: x extent
 constexpr int kBinTY = kBlock / kBinTX;  // y extent
+constexpr int kBinTXW = 64;     // the wide tile (64 x 4) of the one-pass binomial kernel
 constexpr int kBinZCMax = 16;   // most z planes per workgroup chosen automatically (3-D)
 
 // Constant closure parameters (written by the host at set_closure).
@@ -64,7 +65,6 @@ struct DevMember {
     void* g[2];                        // populations [Q][N]
     void* rho;                         // rho - 1 of the predictor [N]      (TO)
     void* vs;                          // predictor velocity v* [D][N]      (TO)
-    void* pc;                          // pending SGS correction records [N] (TO): 8 values per cell
     void* vn;                          // post-streaming velocity [D][N]    (diag, WALE)
     void* P;                           // B^j v*, j = 1..jv   [jv][D][N]
     void* W;                           // B^j curl v*, j=0..jw [jw+1][NC][N]
@@ -73,7 +73,7 @@ struct DevMember {
     double* part_to;                   // [npart][ny * nbx2]
     double* part_diag;                 // [nb1][2]
     int nb1, nbx2, npart, cpt2;        // block counts; cells per thread of the reduce
-    int zc, pad1;                      // z planes per binomial-filter workgroup
+    int zc, btx;                       // z planes per binomial-filter workgroup; its tile width
     DevParam* prm;
     DevCtl* ctl;
     lbm_qoi_rec* recs;

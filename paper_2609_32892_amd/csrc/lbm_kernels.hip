@@ -3,11 +3,10 @@
 //
 // Populations are stored structure-of-arrays [Q][N] (x fastest) in two
 // ping-pong buffers.  One step (eqs. LES-1..LES-3 with the TO correction):
-//   k_step     pull-stream with halfway bounce-back (eq. LES-3, Sec. 7.1) while
-//              applying the pending SGS increment of the previous step at each
-//              source cell, moments, effective relaxation time (Sec. 5), BGK
-//              relaxation and exact-difference forcing (eq. LES-1/LES-2);
-//              writes the predictor populations and rho, v* = v^{p,n*}.
+//   k_step     pull-stream with halfway bounce-back (eq. LES-3, Sec. 7.1),
+//              moments, effective relaxation time (Sec. 5), BGK relaxation and
+//              exact-difference forcing (eq. LES-1/LES-2); writes the
+//              predictor populations and rho, v* = v^{p,n*}.
 //   k_curl     w = curl v* (second-order central differences).
 //   k_binom    powers B^j v*, B^j w of the binomial filter (Sec. 4.1).
 //   k_reduce   per-cell QoIs, sensitivities (App. A) and Gram products,
@@ -16,7 +15,8 @@
 //              LRS, eqs. dQ-from-ref, LRS), Gram solve (eq. O-from-V,
 //              eq. orthogonality), gamma (eq. tau-from-dQ-for-tracking).
 //   k_apply    dv_SGS = sum_i gamma_i O_i (eq. TO-ansatz), evaluated as
-//              sum_j beta_j V_j with beta = G^-1 dQ.
+//              sum_j beta_j V_j with beta = G^-1 dQ, and its change of the
+//              equilibrium added to the predictor populations in place.
 // Every kernel takes a table of members and a work table mapping each
 // workgroup to (member, local block), so one launch serves a whole ensemble.
 // All reductions have a fixed order that depends only on the member's own
@@ -137,15 +137,11 @@ __device__ __forceinline__ T dfeq(T w, T rho, T cd, T cs, T dd)
 }
 
 // ---------------------------------------------------------------------------
-// Pull gather of the post-collision populations of cell (x,y,z), including
-// the pending SGS correction of each source cell when TO is active.
-// ---------------------------------------------------------------------------
-// Packed pending-correction record of a cell (written by k_apply): with
-// a = rho dv, b = 2 v* + dv and e = rho dv.(2 v* + dv), the SGS change of
-// the post-collision population i is
+// SGS change of the post-collision populations of a cell (k_apply): with
+// a = rho dv, b = 2 v* + dv and e = rho dv.(2 v* + dv),
 //   delta f_i = feq_i(rho, v* + dv) - feq_i(rho, v*)
-//             = w_i [3 c_i.a + 9/2 (c_i.a)(c_i.b) - 3/2 e].
-// Layout: u = (a_x, a_y, a_z, e), v = (b_x, b_y, b_z, 0) (2-D: a_z = b_z = 0).
+//             = w_i [3 c_i.a + 9/2 (c_i.a)(c_i.b) - 3/2 e],
+// u = (a_x, a_y, a_z, e), v = (b_x, b_y, b_z, 0) (2-D: a_z = b_z = 0).
 template <typename T> struct alignas(4 * sizeof(T)) Vec4 { T x, y, z, w; };
 template <typename T> struct PendRec { Vec4<T> u, v; };
 
@@ -159,17 +155,17 @@ __device__ __forceinline__ T pend_df(const PendRec<T>& r, int i, T sg)
 }
 
 // ---------------------------------------------------------------------------
-// Pull gather of the post-collision populations of cell (x,y,z), including
-// the pending SGS correction of each source cell when TO is active.
+// Pull gather of the post-collision populations of cell (x,y,z).  A32: the
+// run keeps 2 N * sizeof(T) below 4 GiB (every TO run does), so each load is
+// a 32-bit offset from a scalar base.
 // ---------------------------------------------------------------------------
-template <int LAT, typename T, bool TO>
+template <int LAT, typename T, bool A32>
 __device__ __forceinline__ void gather(KMember& m, const T* __restrict__ gs, int x, int y, int z,
                                        int cell, T* f)
 {
     using L = Lat<LAT>;
     constexpr int Q = L::Q, D = L::D;
     const int N = m.N, nx = m.nx, ny = m.ny, nz = m.nz;
-    const PendRec<T>* __restrict__ pc = (const PendRec<T>*)m.pc;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         int sy = y - L::cy[i];
@@ -185,14 +181,13 @@ __device__ __forceinline__ void gather(KMember& m, const T* __restrict__ gs, int
             src = sx + nx * (sy + ny * sz);
             pi = i;
         }
-        // (TO runs keep every field below 2^32 bytes: 32-bit offsets)
-        T v = TO ? ld_at(gs + (size_t)pi * N, (unsigned)src) : gs[(size_t)pi * N + src];
-        if (TO) {
-            // delta f_pi(src) with c_pi = s c_i
-            const PendRec<T> r = pc[src];
-            v += pend_df<LAT, T>(r, i, bb ? T(-1) : T(1));
+        if (A32) {
+            // base: population min(i, opp(i)); the bounce-back one is 0 or N further
+            const int lo = i < opp(i) ? i : opp(i);
+            f[i] = ld_at(gs + (size_t)lo * N, (unsigned)((pi - lo) * N + src));
+        } else {
+            f[i] = gs[(size_t)pi * N + src];
         }
-        f[i] = v;
     }
 }
 
@@ -217,7 +212,7 @@ __device__ __forceinline__ void moments(const T* f, T& drho, T* j)
 // ---------------------------------------------------------------------------
 // K1: stream + collide + force.
 // MODE 0: plain; 1: plain with statistics and post-streaming velocity;
-// 2: TO predictor (statistics, rho, v*, pending correction applied).
+// 2: TO predictor (statistics, rho, v*).
 // ---------------------------------------------------------------------------
 template <int LAT, typename T, int PREC, int SUB, int MODE>
 __global__ __launch_bounds__(kBlock) void k_step(const DevMember* __restrict__ mems,
@@ -382,7 +377,8 @@ __global__ __launch_bounds__(kBlock) void k_step(const DevMember* __restrict__ m
 
 // ---------------------------------------------------------------------------
 // Post-streaming density and velocity of the current state (stream only,
-// including a pending correction): used for WALE gradients and lbm_fields.
+// the SGS change of the last step included): used for WALE gradients and
+// lbm_fields.
 // ---------------------------------------------------------------------------
 template <int LAT, typename T, int PREC, bool TO>
 __global__ __launch_bounds__(kBlock) void k_moments(const DevMember* __restrict__ mems,
@@ -495,19 +491,22 @@ __device__ __forceinline__ T binom_at(const T* __restrict__ u, int x, int y, int
 }
 
 // K2b: P_j = B P_{j-1} (P_0 = v*) for j <= jv and W_j = B W_{j-1} for j <= jw.
-// 2.5-D tiling: a workgroup owns a kBinTX x kBinTY tile of the xy plane and
-// a chunk of zc planes (chosen per grid for enough workgroups); every plane of the chunk (plus one halo plane on
-// each side) is staged with its xy halo in LDS, filtered in x and y there,
-// and the z pass runs on a three-plane window kept in registers.
+// 2.5-D tiling: a workgroup owns a TX x TY tile of the xy plane (32 x 8, or
+// 64 x 4 on wide grids: each staged row then wastes fewer 128-byte lines on
+// its one-cell x halo) and a chunk of zc planes (chosen per grid for enough
+// workgroups); every plane of the chunk (plus one halo plane on each side)
+// is staged with its xy halo in LDS, filtered in x and y there, and the z
+// pass runs on a three-plane window kept in registers.
 __device__ __forceinline__ int modi(int a, int n) { int r = a % n; return r < 0 ? r + n : r; }
 
-template <int LAT, typename T>
+template <int LAT, typename T, int TX>
 __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ mems, const int2* __restrict__ work,
                                                   int j)
 {
     using L = Lat<LAT>;
     constexpr int D = L::D, NC = L::NC, NCMP = D + NC;
-    constexpr int HX = kBinTX + 2, HY = kBinTY + 2, HXY = HX * HY;
+    constexpr int TY = kBlock / TX;   // tile TX x TY (32 x 8 or 64 x 4)
+    constexpr int HX = TX + 2, HY = TY + 2, HXY = HX * HY;
     // the staged plane [component][halo tile]
     __shared__ T tile[NCMP * HXY];
     const int2 wk = work[blockIdx.x];
@@ -519,12 +518,12 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
     if (!dov && !doc) return;
     const int nx = m.nx, ny = m.ny, nz = m.nz;
     const size_t sN = (size_t)m.N;
-    const int ntx = (nx + kBinTX - 1) / kBinTX, nty = (ny + kBinTY - 1) / kBinTY;
+    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
     const int zc = m.zc;
-    const int tx0 = (wk.y % ntx) * kBinTX;
-    const int ty0 = ((wk.y / ntx) % nty) * kBinTY;
+    const int tx0 = (wk.y % ntx) * TX;
+    const int ty0 = ((wk.y / ntx) % nty) * TY;
     const int tz0 = (wk.y / (ntx * nty)) * zc;
-    const int lx = threadIdx.x % kBinTX, ly = threadIdx.x / kBinTX;
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     const int x = tx0 + lx, y = ty0 + ly;
     const bool own = x < nx && y < ny;
     // Source and destination component pointers.  Every component is loaded
@@ -557,9 +556,9 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
     for (int k = 0; k < NE; ++k) {
         const int e = threadIdx.x + k * kBlock;
         const int hx = e % HX, hy = e / HX;
-        int gx = tx0 + hx - 1;       // in [-1, nx + kBinTX - 1]
+        int gx = tx0 + hx - 1;       // in [-1, nx + TX - 1]
         gx = gx < 0 ? gx + nx : (gx >= nx ? modi(gx, nx) : gx);
-        int gy = ty0 + hy - 1;       // in [-1, ny + kBinTY - 1]
+        int gy = ty0 + hy - 1;       // in [-1, ny + TY - 1]
         bool ok = e < HXY;
         if (m.walls) ok = ok && gy >= 0 && gy < ny;
         else gy = gy < 0 ? gy + ny : (gy >= ny ? modi(gy, ny) : gy);
@@ -613,11 +612,10 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
 #pragma unroll
         for (int c = 0; c < NCMP; ++c)
             if (dst[c]) dst[c][ci] = T(0.25) * sa[c] + T(0.5) * sb[c] + T(0.25) * sc[c];
-        if (cdst) {   // curl w at plane zo: D_z from the planes above and below
-            const T dzx = T(0.5) * (rc[0] - ra[0]), dzy = T(0.5) * (rc[1] - ra[1]);
-            cdst[ci] = dxyb[2][1] - dzy;                  // D_y w_z - D_z w_y
-            cdst[sN + ci] = dzx - dxyb[2][0];             // D_z w_x - D_x w_z
-            cdst[2 * sN + ci] = dxyb[1][0] - dxyb[0][1];  // D_x w_y - D_y w_x
+        if (cdst) {   // curl w at plane zo, D_z from the planes below and above
+            cdst[ci] = (T(0.5) * ra[1] + dxyb[2][1]) - T(0.5) * rc[1];        // D_y w_z - D_z w_y
+            cdst[sN + ci] = (T(-0.5) * ra[0] - dxyb[2][0]) + T(0.5) * rc[0];  // D_z w_x - D_x w_z
+            cdst[2 * sN + ci] = dxyb[1][0] - dxyb[0][1];                      // D_x w_y - D_y w_x
         }
     };
     const int p0 = tz0 - zr, p1 = zend - 1 + zr;   // staged planes, inclusive
@@ -1150,10 +1148,12 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
     }
 }
 
-// K4: dv = sum_j cv_j B^j v* + sum_j cw_j C_j + e_x cmp(y), then the packed
-// pending-correction record of the cell.
+// K4: dv = sum_j cv_j B^j v* + sum_j cw_j C_j + e_x cmp(y), then
+// delta f_i = feq_i(rho, v* + dv) - feq_i(rho, v*) added in place to the
+// cell's predictor populations (the buffer k_step of this step wrote).
 template <int LAT, typename T>
-__global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ mems, const int2* __restrict__ work)
+__global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ mems, const int2* __restrict__ work,
+                                                  int flip)
 {
     using L = Lat<LAT>;
     constexpr int D = L::D;
@@ -1201,7 +1201,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ 
         }
     }
     if (prm->nmp > 0) out[0] += T(m.cmp[y]);
-    // packed pending correction for the next stream-collide
+    // the SGS change of the predictor populations
     const T rho = T(1) + ((const T*)m.rho)[cell];
     PendRec<T> r;
     T vs[3] = {0, 0, 0};
@@ -1216,7 +1216,13 @@ __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ 
     r.v.y = by;
     r.v.z = bz;
     r.v.w = T(0);
-    ((PendRec<T>*)m.pc)[cell] = r;
+    // (TO fields stay below 2^32 bytes: 32-bit offsets from scalar bases)
+    T* g = (T*)m.g[m.parity ^ flip ^ 1];
+    T gi[L::Q];
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) gi[i] = ld_at(g + (size_t)i * sN, (unsigned)cell);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) st_at(g + (size_t)i * sN, (unsigned)cell, gi[i] + pend_df<LAT, T>(r, i, T(1)));
 }
 
 // ---------------------------------------------------------------------------
@@ -1312,11 +1318,10 @@ __global__ void k_init(const DevMember* __restrict__ mems, int flip, const doubl
     if (m.has_to) {
         ((T*)m.rho)[cell] = 0;
         for (int a = 0; a < L::D; ++a) ((T*)m.vs)[(size_t)a * N + cell] = 0;
-        ((PendRec<T>*)m.pc)[cell] = PendRec<T>{};
     }
 }
 
-template <int LAT, typename T, int PREC, bool TO>
+template <int LAT, typename T, int PREC>
 __global__ void k_get_pop(const DevMember* __restrict__ mems, int flip, double* __restrict__ f)
 {
     using L = Lat<LAT>;
@@ -1325,14 +1330,9 @@ __global__ void k_get_pop(const DevMember* __restrict__ mems, int flip, double* 
     const int cell = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= N) return;
     const T* g = (const T*)m.g[m.parity ^ flip];
-    PendRec<T> r{};
-    if (TO) r = ((const PendRec<T>*)m.pc)[cell];
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        double v = (double)g[(size_t)i * N + cell] + (PREC == LBM_FP32_PLAIN ? 0.0 : L::w[i]);
-        if (TO) v += (double)pend_df<LAT, T>(r, i, T(1));
-        f[(size_t)i * N + cell] = v;
-    }
+    for (int i = 0; i < L::Q; ++i)
+        f[(size_t)i * N + cell] = (double)g[(size_t)i * N + cell] + (PREC == LBM_FP32_PLAIN ? 0.0 : L::w[i]);
 }
 
 template <int LAT, typename T, int PREC>
@@ -1350,7 +1350,6 @@ __global__ void k_set_pop(const DevMember* __restrict__ mems, int flip, const do
     if (m.has_to) {
         ((T*)m.rho)[cell] = 0;
         for (int a = 0; a < L::D; ++a) ((T*)m.vs)[(size_t)a * N + cell] = 0;
-        ((PendRec<T>*)m.pc)[cell] = PendRec<T>{};
     }
 }
 
@@ -1369,24 +1368,6 @@ __global__ void k_stream_only(const DevMember* __restrict__ mems, int flip)
     T* gd = (T*)m.g[m.parity ^ flip ^ 1];
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) gd[(size_t)i * N + cell] = f[i];
-}
-
-// Fold a pending SGS increment into the stored populations (own cell) and
-// clear it, so that a run can continue without the TO step.
-template <int LAT, typename T, int PREC>
-__global__ void k_flush(const DevMember* __restrict__ mems, int flip)
-{
-    using L = Lat<LAT>;
-    KMember& m = *kc(mems);
-    const int N = m.N;
-    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= N) return;
-    T* g = (T*)m.g[m.parity ^ flip];
-    PendRec<T>* pc = (PendRec<T>*)m.pc;
-    const PendRec<T> r = pc[cell];
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) g[(size_t)i * N + cell] += pend_df<LAT, T>(r, i, T(1));
-    pc[cell] = PendRec<T>{};
 }
 
 // ---------------------------------------------------------------------------
@@ -1429,8 +1410,12 @@ static void launch_step_group(const LaunchGroup& g, hipStream_t st, int flip, hi
     if (g.mode == 2) {
         if (g.any_z) hipLaunchKernelGGL((k_curl<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1);
         mark(2);
-        for (int j = 1; j <= g.npass; ++j)
-            hipLaunchKernelGGL((k_binom<LAT, T>), dim3(g.nbb), blk, 0, st, g.mems, g.workb, j);
+        for (int j = 1; j <= g.npass; ++j) {
+            if (g.btx == kBinTXW)
+                hipLaunchKernelGGL((k_binom<LAT, T, kBinTXW>), dim3(g.nbb), blk, 0, st, g.mems, g.workb, j);
+            else
+                hipLaunchKernelGGL((k_binom<LAT, T, kBinTX>), dim3(g.nbb), blk, 0, st, g.mems, g.workb, j);
+        }
         mark(3);
         if (g.maxsa <= 2)
             hipLaunchKernelGGL((k_reduce<LAT, T, 2>), dim3(g.nbr), blk, 0, st, g.mems, g.workr);
@@ -1442,7 +1427,7 @@ static void launch_step_group(const LaunchGroup& g, hipStream_t st, int flip, hi
         hipLaunchKernelGGL(k_sum, dim3(g.nbs), blk, 0, st, g.mems, g.works);
         hipLaunchKernelGGL(k_solve, dim3(g.nmem), blk, 0, st, g.mems, g.workm);
         mark(5);
-        hipLaunchKernelGGL((k_apply<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1);
+        hipLaunchKernelGGL((k_apply<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip);
         mark(6);
     } else if (g.mode == 1) {
         hipLaunchKernelGGL((k_diag<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1);
@@ -1473,17 +1458,11 @@ static void launch_state_t(int op, const DevMember* dm, int N, bool has_to, int 
     const dim3 blk(kBlock), grd((N + kBlock - 1) / kBlock);
     switch (op) {
     case OP_INIT: hipLaunchKernelGGL((k_init<LAT, T, PREC>), grd, blk, 0, st, dm, flip, a, (const double*)b); break;
-    case OP_GET_POP:
-        if (has_to) hipLaunchKernelGGL((k_get_pop<LAT, T, PREC, true>), grd, blk, 0, st, dm, flip, b);
-        else hipLaunchKernelGGL((k_get_pop<LAT, T, PREC, false>), grd, blk, 0, st, dm, flip, b);
-        break;
+    case OP_GET_POP: hipLaunchKernelGGL((k_get_pop<LAT, T, PREC>), grd, blk, 0, st, dm, flip, b); break;
     case OP_SET_POP: hipLaunchKernelGGL((k_set_pop<LAT, T, PREC>), grd, blk, 0, st, dm, flip, a); break;
     case OP_STREAM:
         if (has_to) hipLaunchKernelGGL((k_stream_only<LAT, T, true>), grd, blk, 0, st, dm, flip);
         else hipLaunchKernelGGL((k_stream_only<LAT, T, false>), grd, blk, 0, st, dm, flip);
-        break;
-    case OP_FLUSH:
-        if (has_to) hipLaunchKernelGGL((k_flush<LAT, T, PREC>), grd, blk, 0, st, dm, flip);
         break;
     }
 }

@@ -12,6 +12,7 @@ namespace lbm {
 struct LaunchGroup {
     int lattice, precision, substrate, mode;  // mode 0 plain, 1 plain + records, 2 TO
     int any_z, maxpow, maxsa, npass;  // npass: binomial passes per step
+    int btx;            // binomial tile width of every member (kBinTX or kBinTXW)
     const DevMember* mems;
     const int2* work1;  // cell kernels: (member, block of kBlock cells)
     int nb1;
@@ -25,7 +26,7 @@ struct LaunchGroup {
     int nmem;
 };
 
-enum { OP_INIT = 0, OP_GET_POP = 1, OP_SET_POP = 2, OP_STREAM = 3, OP_FLUSH = 4 };
+enum { OP_INIT = 0, OP_GET_POP = 1, OP_SET_POP = 2, OP_STREAM = 3 };
 
 // ev (nullable): 7 events recorded at the phase boundaries of the step
 // (start, after stream-collide, after curl, after the binomial powers, after

@@ -27,11 +27,11 @@ def closure_args(kind, ny=None, mode="lrs", spinup=20, seed=11):
                                nbands=nb, dmin=dmin, dmax=dmax)
 
 
-def gpu_run(lbm, cfg, u0, precision, qois=None, cargs=None, diag=0, qref=None):
+def gpu_run(lbm, cfg, u0, precision, qois=None, cargs=None, diag=0, qref=None, **tune):
     spec = None
     if qois is not None:
         spec = lbm.ClosureSpec(qois, qref=qref, **cargs)
-    run = lbm.Run(lbm.make_config(precision=precision, diag=diag, **cfg), spec)
+    run = lbm.Run(lbm.make_config(precision=precision, diag=diag, **cfg, **tune), spec)
     run.init_velocity(u0)
     return run
 

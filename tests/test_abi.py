@@ -58,7 +58,8 @@ def test_required_bytes_and_validation(lbm):
     to = L.lbm_required_bytes(ct.byref(cfg), ct.byref(spec.c))
     assert to > plain + 4 * N * (1 + 3 + 3)
     bad = [lbm.make_config(nx=2), lbm.make_config(tau=0.5), lbm.make_config(lattice=lbm.D2Q9, substrate=lbm.WALE),
-           lbm.make_config(precision=7)]
+           lbm.make_config(precision=7), lbm.make_config(tune_btx=48),
+           lbm.make_config(tune_btx=64)]                                          # wide tile needs D3Q19
     for b in bad:
         assert L.lbm_required_bytes(ct.byref(b), None) == 0
         assert L.lbm_last_error()
@@ -69,3 +70,7 @@ def test_required_bytes_and_validation(lbm):
         assert L.lbm_required_bytes(ct.byref(p2), ct.byref(sp.c)) == 0
     lrs = lbm.ClosureSpec([("E", "B", 0)], mode="lrs")                             # LRS without C
     assert L.lbm_required_bytes(ct.byref(p2), ct.byref(lrs.c)) == 0
+    # a closure run whose fields would pass 4 GiB per component
+    big = lbm.make_config(lattice=lbm.D3Q19, precision="fp64", nx=1024, ny=512, nz=520)
+    assert L.lbm_required_bytes(ct.byref(big), None) > 0
+    assert L.lbm_required_bytes(ct.byref(big), ct.byref(lbm.ClosureSpec([("E", "B", 0)]).c)) == 0

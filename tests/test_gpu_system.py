@@ -87,15 +87,16 @@ def test_checkpoint_resume_bitwise():
 
 
 def test_closure_off_and_on_again():
-    """Switching the closure off folds the pending correction in; switching
-    it back on continues without error."""
+    """Switching the closure off leaves the populations as they are (the SGS
+    change of every step is already in them); switching it back on
+    continues without error."""
     lbm = need_gpu()
     cfg, u0, qois, cargs = _case2d()
     a = gpu_run(lbm, cfg, u0, "fp64", qois, cargs)
     a.step(20)
     f_before = a.get_populations()
     a.set_closure(None)
-    assert np.allclose(a.get_populations(), f_before, rtol=0, atol=1e-15)
+    assert np.array_equal(a.get_populations(), f_before)
     a.step(5)
     a.set_closure(lbm.ClosureSpec(qois, **cargs))
     a.step(5)
@@ -115,3 +116,33 @@ def test_invalid_arguments_rejected():
     r.step(2)
     with pytest.raises(lbm.LbmError):   # records not yet produced
         r.records(0, 5)
+
+
+@pytest.mark.parametrize("walls", [1, 0])
+def test_binomial_tile_widths_bitwise_equal(walls):
+    """The 64 x 4 tile of the one-pass binomial kernel gives bitwise the
+    result of the 32 x 8 tile (rows of 128 cells, a ragged y extent, z
+    chunks of 1 and 3 planes)."""
+    lbm = need_gpu()
+    if walls:
+        cfg, u0 = synth.channel_workload(128, 22, 7, seed=8)
+        qois, cargs = closure_args("3d", ny=22, spinup=3)
+    else:
+        cfg = dict(lattice=1, nx=128, ny=18, nz=6, walls_y=0, tau=0.55, substrate=1, cmodel=0.1,
+                   force_kind=1, force_amp=1e-5, force_k=1, drag=0.0)
+        u0 = synth.noise_velocity(3, (6, 18, 128), 0.02, 9)
+        qois = [q for q in synth.QOIS_3D if q[0] in ("E", "Z")]
+        C, mu, S = synth.lrs_model_channel(len(qois), 7, 9)
+        cargs = dict(mode="lrs", spinup=3, C=C, mu=mu, Sigma=S, seed=13)
+    for zc in (1, 3):
+        _say(f"tile widths: walls={walls} zc={zc}")
+        runs = [gpu_run(lbm, cfg, u0, "fp32", qois, cargs, tune_zc=zc, tune_btx=b) for b in (32, 64)]
+        for r in runs:
+            r.step(8)
+            r.sync()
+        fa, fb = (r.get_populations() for r in runs)
+        assert np.array_equal(fa, fb), f"walls={walls} zc={zc}: populations differ"
+        qa, qb = (r.record_arrays()["q"] for r in runs)
+        assert np.array_equal(qa, qb)
+        for r in runs:
+            r.close()
