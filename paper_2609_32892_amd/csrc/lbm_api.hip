@@ -305,6 +305,16 @@ struct lbm_batch {
 
 namespace {
 
+// Union of the chains each binomial pass advances for member c: pass j
+// computes B^j v (j <= jv) and curl^T B^(j-1) w with B^j w (j - 1 <= jw).
+void add_pass_masks(const lbm_ctx* c, LaunchGroup& g)
+{
+    for (int j = 1; j <= 8; ++j) {
+        if (j <= c->cur.jv) g.bmask[j - 1] |= 1;
+        if (c->cur.has_z && j - 1 <= c->cur.jw) g.bmask[j - 1] |= 2;
+    }
+}
+
 LaunchGroup ctx_group(const lbm_ctx* c)
 {
     LaunchGroup g{};
@@ -317,6 +327,7 @@ LaunchGroup ctx_group(const lbm_ctx* c)
     g.maxsa = c->cur.nsa;
     g.npass = std::max(c->cur.jv, c->cur.has_z ? c->cur.jw + 1 : 0);
     g.btx = c->plan.btx;
+    add_pass_masks(c, g);
     g.mems = c->dm;
     g.work1 = (const int2*)(c->arena + c->plan.work1);
     g.nb1 = c->plan.nb1;
@@ -954,6 +965,7 @@ static int batch_build(lbm_batch* b)
             g.maxpow = std::max(g.maxpow, std::max(c->cur.jv, c->cur.jw));
             g.maxsa = std::max(g.maxsa, c->cur.nsa);
             g.npass = std::max(g.npass, std::max(c->cur.jv, c->cur.has_z ? c->cur.jw + 1 : 0));
+            add_pass_masks(c, g);
         }
         g.mems = b->dmem;
         g.work1 = b->dwork + offs[gi].w1;

@@ -443,22 +443,52 @@ __device__ __forceinline__ void curl_at(const T* __restrict__ v, size_t N, int x
     }
 }
 
-// K2a: w = curl v* into W_0.
+// K2a: w = curl v* into W_0 (the same differences as curl_at).  Every load
+// is unconditional, a 32-bit offset from a scalar base (TO fields stay below
+// 2^32 bytes); a neighbour beyond a wall loads the cell itself and counts
+// as zero, so no branch-joined load stalls the others.
 template <int LAT, typename T>
 __global__ __launch_bounds__(kBlock) void k_curl(const DevMember* __restrict__ mems, const int2* __restrict__ work)
 {
     using L = Lat<LAT>;
     const int2 wk = work[blockIdx.x];
     KMember& m = *kc(mems + wk.x);
-    if (!m.prm->has_z) return;
+    if (!kc(m.prm)->has_z) return;
     const int N = m.N, nx = m.nx, ny = m.ny, nz = m.nz;
     const int cell = wk.y * kBlock + threadIdx.x;
     if (cell >= N) return;
     const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
+    const size_t sN = (size_t)N;
+    const T* vx = (const T*)m.vs;
+    const T* vy = vx + sN;
+    const unsigned c = (unsigned)cell;
+    const unsigned cxm = c - x + wrapi(x - 1, nx), cxp = c - x + wrapi(x + 1, nx);
+    bool okm = true, okp = true;
+    int ym = y - 1, yp = y + 1;
+    if (m.walls) { okm = ym >= 0; okp = yp < ny; ym = okm ? ym : y; yp = okp ? yp : y; }
+    else { ym = wrapi(ym, ny); yp = wrapi(yp, ny); }
+    const unsigned cym = c + (unsigned)((ym - y) * nx), cyp = c + (unsigned)((yp - y) * nx);
+    auto y0 = [](bool ok, T v) { return ok ? v : T(0); };
     T w[3];
-    curl_at<L::D, T>((const T*)m.vs, (size_t)N, x, y, z, nx, ny, nz, m.walls, w);
+    if (L::D == 2) {
+        w[0] = T(0.5) * (ld_at(vy, cxp) - ld_at(vy, cxm)) - T(0.5) * (y0(okp, ld_at(vx, cyp)) - y0(okm, ld_at(vx, cym)));
+    } else {
+        const T* vz = vx + 2 * sN;
+        const int plane = nx * ny;
+        const unsigned czm = c + (unsigned)((wrapi(z - 1, nz) - z) * plane), czp = c + (unsigned)((wrapi(z + 1, nz) - z) * plane);
+        const T dyvz = T(0.5) * (y0(okp, ld_at(vz, cyp)) - y0(okm, ld_at(vz, cym)));
+        const T dzvy = T(0.5) * (ld_at(vy, czp) - ld_at(vy, czm));
+        const T dzvx = T(0.5) * (ld_at(vx, czp) - ld_at(vx, czm));
+        const T dxvz = T(0.5) * (ld_at(vz, cxp) - ld_at(vz, cxm));
+        const T dxvy = T(0.5) * (ld_at(vy, cxp) - ld_at(vy, cxm));
+        const T dyvx = T(0.5) * (y0(okp, ld_at(vx, cyp)) - y0(okm, ld_at(vx, cym)));
+        w[0] = dyvz - dzvy;
+        w[1] = dzvx - dxvz;
+        w[2] = dxvy - dyvx;
+    }
+    T* W = (T*)m.W;
 #pragma unroll
-    for (int a = 0; a < L::NC; ++a) ((T*)m.W)[(size_t)a * N + cell] = w[a];
+    for (int a = 0; a < L::NC; ++a) st_at(W + (size_t)a * sN, c, w[a]);
 }
 
 // Binomial filter B = (x)_a [1,2,1]/4 of one scalar field at (x,y,z).
@@ -499,12 +529,17 @@ __device__ __forceinline__ T binom_at(const T* __restrict__ u, int x, int y, int
 // pass runs on a three-plane window kept in registers.
 __device__ __forceinline__ int modi(int a, int n) { int r = a % n; return r < 0 ? r + n : r; }
 
-template <int LAT, typename T, int TX>
+// CH: the chains the launch advances (1: v, 2: w and its curl, 3: both);
+// the launch passes the union over its members, and a member whose chain
+// this pass does not advance either returns (CH = 1, 2) or re-reads the
+// other chain's source (CH = 3).
+template <int LAT, typename T, int TX, int CH>
 __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ mems, const int2* __restrict__ work,
                                                   int j)
 {
     using L = Lat<LAT>;
-    constexpr int D = L::D, NC = L::NC, NCMP = D + NC;
+    constexpr int D = L::D, NC = L::NC;
+    constexpr int NV = (CH & 1) ? D : 0, NW = (CH & 2) ? NC : 0, NCMP = NV + NW;   // tile: v, then w
     constexpr int TY = kBlock / TX;   // tile TX x TY (32 x 8 or 64 x 4)
     constexpr int HX = TX + 2, HY = TY + 2, HXY = HX * HY;
     // the staged plane [component][halo tile]
@@ -516,6 +551,7 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
     const bool dov = j <= prm->jv, dow = prm->has_z && j <= prm->jw;
     const bool doc = prm->has_z && j - 1 <= prm->jw;
     if (!dov && !doc) return;
+    if ((CH == 1 && !dov) || (CH == 2 && !doc)) return;
     const int nx = m.nx, ny = m.ny, nz = m.nz;
     const size_t sN = (size_t)m.N;
     const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
@@ -535,16 +571,16 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
     const T* sv = j == 1 ? (const T*)m.vs : (const T*)m.P + (size_t)(j - 2) * D * sN;
     const T* sw = (const T*)m.W + (size_t)(j - 1) * NC * sN;
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
+    for (int a = 0; a < NV; ++a) {
         src[a] = dov ? sv + a * sN : sw + (a % NC) * sN;
         dst[a] = dov ? (T*)m.P + ((size_t)(j - 1) * D + a) * sN : nullptr;
     }
 #pragma unroll
-    for (int a = 0; a < NC; ++a) {
-        src[D + a] = doc ? sw + a * sN : sv + (a % D) * sN;
-        dst[D + a] = dow ? (T*)m.W + ((size_t)j * NC + a) * sN : nullptr;
+    for (int a = 0; a < NW; ++a) {
+        src[NV + a] = doc ? sw + a * sN : sv + (a % D) * sN;
+        dst[NV + a] = dow ? (T*)m.W + ((size_t)j * NC + a) * sN : nullptr;
     }
-    T* cdst = doc ? (T*)m.C + (size_t)(j - 1) * D * sN : nullptr;
+    T* cdst = NW > 0 && doc ? (T*)m.C + (size_t)(j - 1) * D * sN : nullptr;
     const int zr = D == 3 ? 1 : 0;
     const int zend = D == 3 ? min(tz0 + zc, nz) : 1;
     // the (at most two) halo elements this thread stages, as offsets within
@@ -596,8 +632,8 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
             sn[c] = T(0.25) * q0 + T(0.5) * q1 + T(0.25) * q2;
         }
 #pragma unroll
-        for (int a = 0; a < NC; ++a) {
-            const T* t = tile + (pl * NCMP + D + a) * HXY + (ly + 1) * HX + lx + 1;
+        for (int a = 0; a < NW; ++a) {
+            const T* t = tile + (pl * NCMP + NV + a) * HXY + (ly + 1) * HX + lx + 1;
             rn[a] = t[0];
             dn[a][0] = T(0.5) * (t[1] - t[-1]);
             dn[a][1] = T(0.5) * (t[HX] - t[-HX]);
@@ -612,15 +648,17 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
 #pragma unroll
         for (int c = 0; c < NCMP; ++c)
             if (dst[c]) dst[c][ci] = T(0.25) * sa[c] + T(0.5) * sb[c] + T(0.25) * sc[c];
-        if (cdst) {   // curl w at plane zo, D_z from the planes below and above
-            cdst[ci] = (T(0.5) * ra[1] + dxyb[2][1]) - T(0.5) * rc[1];        // D_y w_z - D_z w_y
-            cdst[sN + ci] = (T(-0.5) * ra[0] - dxyb[2][0]) + T(0.5) * rc[0];  // D_z w_x - D_x w_z
-            cdst[2 * sN + ci] = dxyb[1][0] - dxyb[0][1];                      // D_x w_y - D_y w_x
+        if constexpr (D == 3 && NW > 0) {
+            if (cdst) {   // curl w at plane zo, D_z from the planes below and above
+                cdst[ci] = (T(0.5) * ra[1] + dxyb[2][1]) - T(0.5) * rc[1];        // D_y w_z - D_z w_y
+                cdst[sN + ci] = (T(-0.5) * ra[0] - dxyb[2][0]) + T(0.5) * rc[0];  // D_z w_x - D_x w_z
+                cdst[2 * sN + ci] = dxyb[1][0] - dxyb[0][1];                      // D_x w_y - D_y w_x
+            }
         }
     };
     const int p0 = tz0 - zr, p1 = zend - 1 + zr;   // staged planes, inclusive
     if (D == 2) {
-        T buf[NE][NCMP], sn[NCMP], rn[NC], dn[NC][2];
+        T buf[NE][NCMP], sn[NCMP], rn[NC] = {}, dn[NC][2] = {};
         fetch(0, buf);
         stage(0, buf);
         __syncthreads();
@@ -630,7 +668,7 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
 #pragma unroll
             for (int c = 0; c < NCMP; ++c)
                 if (dst[c]) dst[c][ci] = sn[c];
-            if (cdst) {   // curl^T of a scalar: (D_y w, -D_x w)
+            if (NW > 0 && cdst) {   // curl^T of a scalar: (D_y w, -D_x w)
                 cdst[ci] = dn[0][1];
                 cdst[sN + ci] = -dn[0][0];
             }
@@ -652,7 +690,7 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
             stage(0, buf);
             __syncthreads();
             if (pz < p1) fetch(pz + 1, buf);
-            T sn[NCMP], rn[NC], dn[NC][2];
+            T sn[NCMP], rn[NC] = {}, dn[NC][2] = {};
             xyfilter(0, sn, rn, dn);
             __syncthreads();
             if (pz >= tz0 + 1) emit3(pz - 1, s0, s1, sn, r1, rn, dxy);  // once its upper neighbour is staged
@@ -852,7 +890,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const DevMember* __restrict__
             const int o = nsa + nsa * (nsa + 1) / 2;
 #pragma unroll
             for (int jm = 0; jm < kMaxQ; ++jm) {
-                if (jm >= nmp) break;
+                if (jm >= nmp) continue;
                 double* oj = out + (o + jm * (1 + nsa)) * nblk;
                 oj[0] = wb[jm] * acc[MAXSA + NG];
 #pragma unroll
@@ -1411,10 +1449,14 @@ static void launch_step_group(const LaunchGroup& g, hipStream_t st, int flip, hi
         if (g.any_z) hipLaunchKernelGGL((k_curl<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1);
         mark(2);
         for (int j = 1; j <= g.npass; ++j) {
-            if (g.btx == kBinTXW)
-                hipLaunchKernelGGL((k_binom<LAT, T, kBinTXW>), dim3(g.nbb), blk, 0, st, g.mems, g.workb, j);
-            else
-                hipLaunchKernelGGL((k_binom<LAT, T, kBinTX>), dim3(g.nbb), blk, 0, st, g.mems, g.workb, j);
+#define LBM_BINOM(TXV, CHV) hipLaunchKernelGGL((k_binom<LAT, T, TXV, CHV>), dim3(g.nbb), blk, 0, st, g.mems, g.workb, j)
+            const int ch = g.bmask[j - 1];
+            if (g.btx == kBinTXW) {
+                if (ch == 1) LBM_BINOM(kBinTXW, 1); else if (ch == 2) LBM_BINOM(kBinTXW, 2); else LBM_BINOM(kBinTXW, 3);
+            } else {
+                if (ch == 1) LBM_BINOM(kBinTX, 1); else if (ch == 2) LBM_BINOM(kBinTX, 2); else LBM_BINOM(kBinTX, 3);
+            }
+#undef LBM_BINOM
         }
         mark(3);
         if (g.maxsa <= 2)

@@ -13,6 +13,7 @@ struct LaunchGroup {
     int lattice, precision, substrate, mode;  // mode 0 plain, 1 plain + records, 2 TO
     int any_z, maxpow, maxsa, npass;  // npass: binomial passes per step
     int btx;            // binomial tile width of every member (kBinTX or kBinTXW)
+    int bmask[8];       // per binomial pass j = 1..npass: chains advanced by some member (1 v, 2 w)
     const DevMember* mems;
     const int2* work1;  // cell kernels: (member, block of kBlock cells)
     int nb1;
