@@ -187,8 +187,9 @@ void make_plan(const lbm_config* c, const ClosureShape& cs, Plan* p)
         P.cmp = take(sizeof(double) * c->ny);
         P.workr = take(sizeof(int2) * P.nbr);
         P.workb = take(sizeof(int2) * P.nbb);
-        P.nbs = 4 + cs.npart();
-        P.sums = take(sizeof(double) * P.nbs);
+        // k_sum workgroups: the LRS draw (slot -1), then one per sum
+        P.nbs = 5 + cs.npart();
+        P.sums = take(sizeof(double) * (P.nbs - 1));
         P.works = take(sizeof(int2) * P.nbs);
     }
     P.total = o;
@@ -602,7 +603,7 @@ int lbm_create(const lbm_config* cfg, const lbm_closure* closure, void* dev_aren
         }
         if (!rc) rc = upload(c, A + plan.workb, wb.data(), sizeof(int2) * wb.size());
         std::vector<int2> ws(plan.nbs);
-        for (int b = 0; b < plan.nbs; ++b) ws[b] = make_int2(0, b);
+        for (int b = 0; b < plan.nbs; ++b) ws[b] = make_int2(0, b - 1);
         if (!rc) rc = upload(c, A + plan.works, ws.data(), sizeof(int2) * ws.size());
     }
     if (!rc) rc = upload(c, c->dm, &m, sizeof m);
@@ -928,7 +929,7 @@ static int batch_build(lbm_batch* b)
         o.ws = work.size();
         if (keys[gi].mode == 2)
             for (int i : gm[gi])
-                for (int k = 0; k < b->mem[i]->plan.nbs; ++k) work.push_back(make_int2(i, k));
+                for (int k = 0; k < b->mem[i]->plan.nbs; ++k) work.push_back(make_int2(i, k - 1));
         o.nbs = work.size() - o.ws;
         o.wm = workm.size();
         for (int i : gm[gi]) workm.push_back(i);

@@ -54,6 +54,7 @@ struct DevCtl {
     float cvf[kMaxPow + 1];            // cv, cw rounded to FP32
     float cwf[kMaxPow + 1];
     double pad[1];
+    double lrs_e[kMaxQ];               // mu + L xi of the current step's LRS draw
 };
 
 struct DevMember {

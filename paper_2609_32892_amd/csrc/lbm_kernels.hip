@@ -128,6 +128,26 @@ __device__ __forceinline__ void st_at(T* base, unsigned i, T v)
     *(T*)((char*)base + i * (unsigned)sizeof(T)) = v;
 }
 
+// The same sums with the result spread over the workgroup: thread k < NV
+// returns value k (added over the waves in the same order as block_sum).
+template <int NV>
+__device__ __forceinline__ double block_sum_spread(const double* v, double* lds)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = wave_sum(v[k]);
+        if (lane == 0) lds[k * (kBlock / 64) + wv] = s;
+    }
+    __syncthreads();
+    double r = 0;
+    if (threadIdx.x < NV) {
+#pragma unroll
+        for (int j = 0; j < kBlock / 64; ++j) r += lds[threadIdx.x * (kBlock / 64) + j];
+    }
+    return r;
+}
+
 // feq_i(rho, a) - feq_i(rho, b) in difference form (exactly zero when a = b):
 // w rho [3 c.(a-b) + 9/2 (c.(a-b))(c.(a+b)) - 3/2 (a-b).(a+b)].
 template <typename T>
@@ -868,35 +888,28 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const DevMember* __restrict__
 #pragma unroll
         for (int jm = 0; jm < kMaxQ; ++jm) wb[jm] = bw[(size_t)prm->mp_band[jm < nmp ? jm : nmp - 1] * ny + y];
     }
-    block_sum<NV>(acc, lds);
-    if (threadIdx.x == 0) {
-        // partials are stored value-major, [npart][ny * nbx2], so that the
-        // cross-block sums read them contiguously; compile-time indices into
-        // acc keep it in registers
-        const size_t nblk = (size_t)ny * m.nbx2;
-        double* out = m.part_to + wk.y;
-#pragma unroll
-        for (int s = 0; s < MAXSA; ++s)
-            if (s < nsa) out[s * nblk] = acc[s];
-        int g = 0;
-#pragma unroll
-        for (int s = 0; s < MAXSA; ++s)
-#pragma unroll
-            for (int t2 = s; t2 < MAXSA; ++t2, ++g)
-                if (t2 < nsa) out[(nsa + s * nsa - s * (s - 1) / 2 + (t2 - s)) * nblk] = acc[MAXSA + g];
-        if (hasmp) {
-            // mean-profile terms, weighted by the band weights of this row:
-            // w_j(y) sum v*_x and w_j(y) sum V_s,x for every band j
+    // partials are stored value-major, [npart][ny * nbx2], so that the
+    // cross-block sums read them contiguously; thread t writes value t
+    const double r = block_sum_spread<NV>(acc, lds);
+    const int t = threadIdx.x;
+    const size_t nblk = (size_t)ny * m.nbx2;
+    double* out = m.part_to + wk.y;
+    if (t < MAXSA) {
+        if (t < nsa) out[t * nblk] = r;
+    } else if (t < MAXSA + NG) {
+        int g = t - MAXSA, sa = 0;   // (sa, t2), sa <= t2 < MAXSA, in the order of acc
+        while (g >= MAXSA - sa) { g -= MAXSA - sa; ++sa; }
+        const int t2 = sa + g;
+        if (t2 < nsa) out[(nsa + sa * nsa - sa * (sa - 1) / 2 + (t2 - sa)) * nblk] = r;
+    } else if (hasmp && t < NV) {
+        // mean-profile terms, weighted by the band weights of this row:
+        // w_j(y) sum v*_x (column 0) and w_j(y) sum V_s,x (column 1 + s)
+        const int col = t - (MAXSA + NG);
+        if (col == 0 || col - 1 < nsa) {
             const int o = nsa + nsa * (nsa + 1) / 2;
 #pragma unroll
-            for (int jm = 0; jm < kMaxQ; ++jm) {
-                if (jm >= nmp) continue;
-                double* oj = out + (o + jm * (1 + nsa)) * nblk;
-                oj[0] = wb[jm] * acc[MAXSA + NG];
-#pragma unroll
-                for (int s = 0; s < MAXSA; ++s)
-                    if (s < nsa) oj[(1 + s) * nblk] = wb[jm] * acc[MAXSA + NG + 1 + s];
-            }
+            for (int jm = 0; jm < kMaxQ; ++jm)
+                if (jm < nmp) out[(o + jm * (1 + nsa) + col) * nblk] = wb[jm] * r;
         }
     }
 }
@@ -918,22 +931,31 @@ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
     }
 }
 
+// The four normals of Philox block blk of a step: Box-Muller on the block's
+// two pairs of uniforms.
+__device__ inline void lrs_block_normals(unsigned long long seed, long long step, int blk, double* zz)
+{
+    uint32_t c[4] = {(uint32_t)blk, (uint32_t)(unsigned long long)step,
+                     (uint32_t)((unsigned long long)step >> 32), 0x4C525331u};
+    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    for (int p = 0; p < 2; ++p) {
+        const double u1 = ((double)c[2 * p] + 0.5) * 2.3283064365386963e-10;
+        const double u2 = ((double)c[2 * p + 1] + 0.5) * 2.3283064365386963e-10;
+        const double rad = sqrt(-2.0 * log(u1));
+        double sn, cs;
+        sincospi(2.0 * u2, &sn, &cs);
+        zz[2 * p] = rad * cs;
+        zz[2 * p + 1] = rad * sn;
+    }
+}
+
 __device__ inline void lrs_normals(unsigned long long seed, long long step, int n, double* z)
 {
     for (int blk = 0; 4 * blk < n; ++blk) {
-        uint32_t c[4] = {(uint32_t)blk, (uint32_t)(unsigned long long)step,
-                         (uint32_t)((unsigned long long)step >> 32), 0x4C525331u};
-        philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-        for (int p = 0; p < 2; ++p) {
-            const double u1 = ((double)c[2 * p] + 0.5) * 2.3283064365386963e-10;
-            const double u2 = ((double)c[2 * p + 1] + 0.5) * 2.3283064365386963e-10;
-            const double rad = sqrt(-2.0 * log(u1));
-            double sn, cs;
-            sincospi(2.0 * u2, &sn, &cs);
-            const int k = 4 * blk + 2 * p;
-            if (k < n) z[k] = rad * cs;
-            if (k + 1 < n) z[k + 1] = rad * sn;
-        }
+        double zz[4];
+        lrs_block_normals(seed, step, blk, zz);
+        for (int k = 0; k < 4; ++k)
+            if (4 * blk + k < n) z[4 * blk + k] = zz[k];
     }
 }
 
@@ -959,7 +981,7 @@ __global__ void k_normals_test(unsigned long long seed, long long step0, int nst
 // K2d: cross-block sums, one workgroup per (member, value slot).  Slots 0..3
 // sum the statistics of the stream-collide workgroups, slots 4.. the TO
 // partials of the reduce workgroups; the order is fixed by the member's own
-// block counts.
+// block counts.  Slot -1 makes the member's LRS draw of the step.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_sum(const DevMember* __restrict__ mems, const int2* __restrict__ work)
 {
@@ -967,6 +989,29 @@ __global__ __launch_bounds__(kBlock) void k_sum(const DevMember* __restrict__ me
     const int2 wk = work[blockIdx.x];
     KMember& m = *kc(mems + wk.x);
     const int slot = wk.y;
+    if (slot < 0) {
+        // the member's LRS draw for this step, off the solve's critical
+        // path: normals xi (four per Philox block), then e = mu + L xi
+        __shared__ double z[kMaxQ];
+        KParam* prm = kc(m.prm);
+        DevCtl* ctl = m.ctl;
+        const long long step = ctl->step;
+        if (prm->mode != LBM_CLOSURE_LRS || step < prm->spinup) return;   // uniform
+        const int nq = prm->nq, tid = threadIdx.x;
+        if (tid < (nq + 3) / 4) {
+            double zz[4];
+            lrs_block_normals(prm->seed, step, tid, zz);
+            for (int k = 0; k < 4; ++k)
+                if (4 * tid + k < nq) z[4 * tid + k] = zz[k];
+        }
+        __syncthreads();
+        if (tid < nq) {
+            double e = prm->mu[tid];
+            for (int j = 0; j <= tid; ++j) e += prm->L[tid * kMaxQ + j] * z[j];
+            ctl->lrs_e[tid] = e;
+        }
+        return;
+    }
     if (slot >= 4 + m.npart) return;
     double v[1] = {0};
     if (slot < 4) {
@@ -983,16 +1028,15 @@ __global__ __launch_bounds__(kBlock) void k_sum(const DevMember* __restrict__ me
 }
 
 // ---------------------------------------------------------------------------
-// K3: one workgroup per member.  Fixed-order sums of the partials, the QoI
-// vector and Gram matrix, dQ, beta = G^-1 dQ and gamma_k = dQ_k (G^-1)_kk,
+// K3: one workgroup per member.  The QoI vector and Gram matrix from the
+// fixed-order sums (k_sum), dQ, beta = G^-1 dQ and gamma_k = dQ_k (G^-1)_kk,
 // the per-step record and the coefficients of the dv build.  Every input is
-// first staged into LDS in one parallel pass (one memory latency), and all
-// small matrices live there, every stage spread over the workgroup.
-// G is symmetric positive semi-definite, so Gauss-Jordan elimination needs
-// no pivoting; its pivots are the squared Cholesky pivots, and G counts as
-// singular when one of them is not above 1e-14 times the largest diagonal
-// entry.  The elimination ping-pongs between two copies of [G | I], one
-// barrier per pivot.
+// first staged into LDS in one parallel pass, and all small matrices live
+// there.  G is symmetric positive semi-definite, so Gauss-Jordan elimination
+// needs no pivoting; its pivots are the squared Cholesky pivots, and G counts
+// as singular when one of them is not above 1e-14 times the largest diagonal
+// entry.  The elimination takes four pivots per barrier, ping-ponging between
+// two copies of [G | I].
 // ---------------------------------------------------------------------------
 constexpr int kMaxSums = 4 + kMaxSA + kMaxSA * (kMaxSA + 1) / 2 + kMaxQ * (1 + kMaxSA);
 
@@ -1000,8 +1044,8 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
 {
     __shared__ double M[2][kMaxQ][2 * kMaxQ];
     __shared__ double sf[kMaxSums];
-    __shared__ double Cs[(kMaxQ + 1) * kMaxQ], Ls[kMaxQ * kMaxQ];
-    __shared__ double q[kMaxQ], dq[kMaxQ], beta[kMaxQ], gam[kMaxQ], z[kMaxQ], sc[kMaxQ], qs[kMaxQ];
+    __shared__ double Cs[(kMaxQ + 1) * kMaxQ], es[kMaxQ];
+    __shared__ double q[kMaxQ], dq[kMaxQ], beta[kMaxQ], gam[kMaxQ], sc[kMaxQ], qs[kMaxQ];
     __shared__ double rrs[kMaxSA][kMaxPow + 1], gmps[kMaxQ * kMaxQ];
     __shared__ int kinds[kMaxSA], saslot[kMaxSA], mpslot[kMaxQ], mpband[kMaxQ];
     __shared__ long long step_s;
@@ -1020,7 +1064,7 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
     for (int k = tid; k < nsum; k += kBlock) sf[k] = m.sums[k];
     if (lrs) {
         for (int k = tid; k < (nq + 1) * kMaxQ; k += kBlock) Cs[k] = prm->C[k];
-        for (int k = tid; k < nq * kMaxQ; k += kBlock) Ls[k] = prm->L[k];
+        if (tid < nq) es[tid] = ctl->lrs_e[tid];
     }
     for (int k = tid; k < 2 * kMaxQ * 2 * kMaxQ; k += kBlock) (&M[0][0][0])[k] = 0.0;
     if (tid < kMaxSA * (kMaxPow + 1)) (&rrs[0][0])[tid] = (&prm->rr[0][0])[tid];
@@ -1032,11 +1076,18 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
         sc[tid] = ctl->s[tid];
     }
     if (tid == 0) { step_s = ctl->step; sset_s = ctl->s_set; flags_s = ctl->flags; }
+    // band weights of row y = tid, used at the end (clamped index; loaded now
+    // so that their latency overlaps the solve)
+    double wv0[kMaxQ];
+    if (nmp > 0 && tid < ny) {
+#pragma unroll
+        for (int jm = 0; jm < kMaxQ; ++jm) wv0[jm] = m.bandw[(size_t)prm->mp_band[jm < nmp ? jm : nmp - 1] * ny + tid];
+    }
     __syncthreads();
     const long long step = step_s;
     const bool active = step >= prm->spinup;
     // (b) assemble q and G (left half of M), the mean-profile entries and
-    // the identity (right half); the LRS normals meanwhile
+    // the identity (right half)
     const double* sfp = sf + 4;
     if (tid < nsa) {
         const int s = tid;
@@ -1064,24 +1115,6 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
         M[0][mpslot[a]][mpslot[b]] = gmps[pr];
     }
     if (tid < nq) M[0][tid][kMaxQ + tid] = 1.0;
-    if (active && lrs && tid < (nq + 3) / 4) {
-        // four normals per Philox block
-        double zz[4];
-        uint32_t c[4] = {(uint32_t)tid, (uint32_t)(unsigned long long)step,
-                         (uint32_t)((unsigned long long)step >> 32), 0x4C525331u};
-        philox4x32_10(c, (uint32_t)prm->seed, (uint32_t)(prm->seed >> 32));
-        for (int p = 0; p < 2; ++p) {
-            const double u1 = ((double)c[2 * p] + 0.5) * 2.3283064365386963e-10;
-            const double u2 = ((double)c[2 * p + 1] + 0.5) * 2.3283064365386963e-10;
-            const double rad = sqrt(-2.0 * log(u1));
-            double sn, cs;
-            sincospi(2.0 * u2, &sn, &cs);
-            zz[2 * p] = rad * cs;
-            zz[2 * p + 1] = rad * sn;
-        }
-        for (int k = 0; k < 4; ++k)
-            if (4 * tid + k < nq) z[4 * tid + k] = zz[k];
-    }
     __syncthreads();
     // (c) dQ for tracking; the LRS scale (fixed at the first active step)
     if (active && tid < nq) {
@@ -1097,34 +1130,80 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
         }
     }
     __syncthreads();
-    // (d) the LRS draw
+    // (d) the LRS draw: dQ = s (z* C + C_bias + e) - q*, with e = mu + L xi
+    // drawn ahead of this kernel (k_sum); terms past nq add exact zeros
     if (active && lrs && tid < nq) {
         const int k = tid;
-        double e = prm->mu[k];
-        for (int j = 0; j <= k; ++j) e += Ls[k * kMaxQ + j] * z[j];
-        double zh = e;
-        for (int i = 0; i < nq; ++i) zh += qs[i] * Cs[i * kMaxQ + k];
+        double zh = es[k];
+#pragma unroll
+        for (int i = 0; i < kMaxQ; ++i) {
+            const int ic = i < nq ? i : 0;
+            const double t = qs[ic] * Cs[ic * kMaxQ + k];
+            zh += i < nq ? t : 0.0;
+        }
         zh += Cs[nq * kMaxQ + k];
         dq[k] = sc[k] * zh - q[k];
     }
-    // (e) Gauss-Jordan on [G | I]; only columns 0..nq-1 and kMaxQ..kMaxQ+nq-1
-    // are nonzero
+    // (e) Gauss-Jordan on [G | I] (only columns 0..nq-1 and kMaxQ..kMaxQ+nq-1
+    // are nonzero), four pivots per barrier.  For pivot rows j0..j0+3 every
+    // thread eliminates the 4x4 pivot block P in registers, applied to its
+    // column's pivot-row entries r (t = P^-1 r, pivots in order, each checked
+    // against the singular threshold; the block is identity-padded past nq),
+    // then row i of its column becomes t_(i-j0) inside the block and
+    // M[i][c] - sum_a M[i][j0+a] t_a outside it.  Every thread computes the
+    // same pivots from the same values, so the singular flag is uniform.
+    // The four eliminations of a block are those of four consecutive pivots.
     double mx = 0;
     for (int k = 0; k < nq; ++k) mx = fmax(mx, M[0][k][k]);
     int sing = mx > 0 ? 0 : 1;
     int cur = 0;
     // thread layout: one column of [G | I] each, rows split over the
-    // kBlock / (2 nq) groups of threads, so one division per thread and pivot
+    // kBlock / (2 nq) groups of threads
     const int ncol = 2 * nq, ngrp = kBlock / ncol;
     const int gcol = tid % ncol, grow = tid / ncol;
     const int cc = gcol < nq ? gcol : kMaxQ + gcol - nq;
-    for (int j = 0; j < nq && !sing; ++j) {
-        const double piv = M[cur][j][j];
-        if (!(piv > 1e-14 * mx)) { sing = 1; break; }   // uniform: every thread reads the same pivot
+    __syncthreads();
+    for (int j0 = 0; j0 < nq && !sing; j0 += 4) {
+        const int bs = min(4, nq - j0);   // rows j0..j0+3 stay inside M (nq <= kMaxQ)
+        double P[4][4], t[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+#pragma unroll
+            for (int b2 = 0; b2 < 4; ++b2) P[a][b2] = a < bs && b2 < bs ? M[cur][j0 + a][j0 + b2] : (a == b2 ? 1.0 : 0.0);
+            t[a] = a < bs ? M[cur][j0 + a][cc] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const double piv = P[a][a];
+            if (a < bs && !(piv > 1e-14 * mx)) sing = 1;
+            const double rp = 1.0 / piv;
+#pragma unroll
+            for (int b2 = a + 1; b2 < 4; ++b2) P[a][b2] *= rp;
+            t[a] *= rp;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (e == a) continue;
+                const double f = P[e][a];
+#pragma unroll
+                for (int b2 = a + 1; b2 < 4; ++b2) P[e][b2] -= f * P[a][b2];
+                t[e] -= f * t[a];
+            }
+        }
+        if (sing) break;   // uniform
         if (grow < ngrp) {
-            const double pj = M[cur][j][cc] / piv;
-            for (int i = grow; i < nq; i += ngrp)
-                M[cur ^ 1][i][cc] = i == j ? pj : M[cur][i][cc] - M[cur][i][j] * pj;
+            for (int i = grow; i < nq; i += ngrp) {
+                const int d = i - j0;
+                double v;
+                if (d >= 0 && d < bs) {
+                    v = d == 0 ? t[0] : d == 1 ? t[1] : d == 2 ? t[2] : t[3];
+                } else {
+                    // past nq the block columns of M are zero and t is zero
+                    v = M[cur][i][cc];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) v -= M[cur][i][j0 + a] * t[a];
+                }
+                M[cur ^ 1][i][cc] = v;
+            }
         }
         cur ^= 1;
         __syncthreads();
@@ -1175,7 +1254,8 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
             // all band-weight loads first (clamped index; terms past nmp add exact zeros)
             double wv[kMaxQ];
 #pragma unroll
-            for (int jm = 0; jm < kMaxQ; ++jm) wv[jm] = m.bandw[(size_t)mpband[jm < nmp ? jm : nmp - 1] * ny + yy];
+            for (int jm = 0; jm < kMaxQ; ++jm)
+                wv[jm] = yy == tid ? wv0[jm] : m.bandw[(size_t)mpband[jm < nmp ? jm : nmp - 1] * ny + yy];
             double c = 0;
 #pragma unroll
             for (int jm = 0; jm < kMaxQ; ++jm) c += jm < nmp ? beta[mpslot[jm]] * wv[jm] : 0.0;
