@@ -51,7 +51,8 @@ class Closure(ct.Structure):
                 ("dmax", ct.c_double), ("mode", ct.c_int), ("spinup", ct.c_long),
                 ("C", ct.c_double * ((OQMAX + 1) * OQMAX)), ("mu", ct.c_double * OQMAX),
                 ("Sigma", ct.c_double * (OQMAX * OQMAX)), ("scale", ct.c_double * OQMAX),
-                ("have_scale", ct.c_int), ("seed", ct.c_uint64)]
+                ("have_scale", ct.c_int), ("seed", ct.c_uint64), ("h", ct.c_int),
+                ("Chist", ct.POINTER(ct.c_double))]
 
 
 class Rec(ct.Structure):
@@ -155,9 +156,11 @@ def lrs_normals(seed: int, step: int, n: int) -> np.ndarray:
 
 
 def make_closure(qois, mode="off", spinup=0, C=None, mu=None, Sigma=None, scale=None,
-                 nbands=0, dmin=0.5, dmax=1.0, seed=0) -> Closure:
-    """qois: list of (kind, filter_name, band) with kind in {'E','Z','MP'}."""
+                 nbands=0, dmin=0.5, dmax=1.0, seed=0, h=0) -> Closure:
+    """qois: list of (kind, filter_name, band) with kind in {'E','Z','MP'}.
+    C is ((2h+1) nq + 1) x nq: rows for z^{n-1..n-h}, z*^n, z*^{n-1..n-h}, 1."""
     cl = Closure()
+    cl.h = h
     cl.nq = len(qois)
     for k, (kind, filt, band) in enumerate(qois):
         cl.kind[k] = {"E": QOI_E, "Z": QOI_Z, "MP": QOI_MP}[kind]
@@ -169,7 +172,11 @@ def make_closure(qois, mode="off", spinup=0, C=None, mu=None, Sigma=None, scale=
     cl.mode = MODE[mode]
     cl.spinup = spinup
     nq = len(qois)
-    if C is not None:
+    if C is not None and h > 0:
+        C = np.ascontiguousarray(np.asarray(C, dtype=np.float64).reshape((2 * h + 1) * nq + 1, nq))
+        cl._chist = C          # keeps the array alive; the oracle copies it
+        cl.Chist = C.ctypes.data_as(ct.POINTER(ct.c_double))
+    elif C is not None:
         C = np.asarray(C, dtype=np.float64).reshape(nq + 1, nq)
         for i in range(nq + 1):
             for j in range(nq):
@@ -331,3 +338,50 @@ class Oracle:
         t = np.zeros(self.N)
         self.L.orc_tau_wale_field(self.h, _p(v), _p(t))
         return t
+
+
+def lrs_inputs(q, qs, h, s):
+    """Rows of the LRS design matrix and targets from a trajectory (eq. LRS).
+
+    q, qs: (M, nq) corrected and predictor QoIs of steps 0..M-1; s: scale.
+    Row n (n = h..M-1) is x^n = [z^{n-1}, ..., z^{n-h}, z*^n, ..., z*^{n-h}, 1]
+    with z = q / s; its target is z^n."""
+    q = np.asarray(q, dtype=np.float64) / s
+    qs = np.asarray(qs, dtype=np.float64) / s
+    M, nq = q.shape
+    rows, tgt = [], []
+    for n in range(h, M):
+        x = [q[n - r] for r in range(1, h + 1)] + [qs[n - r] for r in range(0, h + 1)] + [np.ones(1)]
+        rows.append(np.concatenate(x))
+        tgt.append(q[n])
+    return np.array(rows), np.array(tgt)
+
+
+def lrs_fit(q, qs, h, lam, scale=None):
+    """Ridge fit of the LRS model (Sec. 4.4): C minimises
+    1/2 |Q_h X - Q|_F^2 + 1/2 sum_i lam_i |X_i|^2 column by column, with
+    lam_i = lam (sigma_i / sigma_1)^2 and sigma_i the standard deviation of
+    the scaled corrections z^n - z*^n; inputs and targets scaled by s (the
+    standard deviation of each QoI over the trajectory unless given; no mean
+    removal).  Residual statistics: mean and unbiased sample covariance of
+    Q - Q_h C.  Each column solves its normal equations directly.
+    Returns C, mu, Sigma, s."""
+    q = np.asarray(q, dtype=np.float64)
+    qs = np.asarray(qs, dtype=np.float64)
+    if scale is None:
+        s = q.std(axis=0)
+        s[s == 0] = 1.0
+    else:
+        s = np.asarray(scale, dtype=np.float64)
+    X, Y = lrs_inputs(q, qs, h, s)
+    corr = (q - qs)[h:] / s
+    sig = corr.std(axis=0)
+    lam_i = lam * (sig / sig[0]) ** 2 if sig[0] > 0 else np.full(len(sig), float(lam))
+    A = X.T @ X
+    C = np.zeros((X.shape[1], Y.shape[1]))
+    for i in range(Y.shape[1]):
+        C[:, i] = np.linalg.solve(A + lam_i[i] * np.eye(A.shape[0]), X.T @ Y[:, i])
+    R = Y - X @ C
+    mu = R.mean(axis=0)
+    Sigma = np.cov(R, rowvar=False, ddof=1).reshape(Y.shape[1], Y.shape[1])
+    return C, mu, Sigma, s

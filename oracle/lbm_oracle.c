@@ -73,6 +73,8 @@ typedef struct {
     double scale[OQMAX];
     int have_scale;
     uint64_t seed;
+    int h;                /* LRS history length (eq. LRS); 0 uses C above */
+    const double *Chist;  /* h > 0: the full ((2h+1) nq + 1) x nq matrix C (copied) */
 } orc_closure;
 
 typedef struct {
@@ -99,6 +101,7 @@ typedef struct {
     orc_closure cl;
     double L[OQMAX * OQMAX];  /* Cholesky factor of Sigma */
     double *qref; long nref;
+    double *Chist;        /* copy of the history-h regression matrix */
     double s[OQMAX]; int s_set;
     double *V, *O;        /* nq*d*N sensitivity and pattern fields */
     double *bandw;        /* nbands*ny */
@@ -217,6 +220,7 @@ void orc_destroy(void *h)
     if (!o) return;
     free(o->fp); free(o->f); free(o->rho); free(o->v); free(o->vs); free(o->dv);
     free(o->taueff); free(o->qref); free(o->V); free(o->O); free(o->bandw); free(o->recs);
+    free(o->Chist);
     free(o);
 }
 
@@ -719,12 +723,22 @@ void orc_lrs_normals(uint64_t seed, long step, int n, double *z)
 int orc_set_closure(void *h, const orc_closure *cl, const double *qref, long nref)
 {
     Orc *o = (Orc *)h;
-    free(o->V); free(o->O); free(o->bandw); free(o->qref);
-    o->V = o->O = o->bandw = o->qref = NULL;
+    free(o->V); free(o->O); free(o->bandw); free(o->qref); free(o->Chist);
+    o->V = o->O = o->bandw = o->qref = o->Chist = NULL;
     o->have_closure = 0;
     if (!cl) return 0;
     if (cl->nq < 1 || cl->nq > OQMAX) return -1;
+    /* a history model reads its inputs from the records of the h steps
+     * before the first corrected one, in scaled units fixed in advance */
+    if (cl->h < 0) return -1;
+    if (cl->h > 0 && (cl->mode != 2 || !cl->have_scale || !cl->Chist || cl->spinup < o->step + cl->h)) return -1;
     o->cl = *cl;
+    o->cl.Chist = NULL;
+    if (cl->h > 0) {
+        const size_t len = (size_t)(2 * cl->h + 1) * cl->nq + 1;
+        o->Chist = (double *)malloc(sizeof(double) * len * cl->nq);
+        memcpy(o->Chist, cl->Chist, sizeof(double) * len * cl->nq);
+    }
     const long n = (long)o->d * o->N;
     o->V = (double *)malloc(sizeof(double) * cl->nq * n);
     o->O = (double *)malloc(sizeof(double) * cl->nq * n);
@@ -750,14 +764,18 @@ int orc_set_closure(void *h, const orc_closure *cl, const double *qref, long nre
     return 0;
 }
 
-/* dQ for the step (Sec. 4.3 tracking; Sec. 4.4 LRS with h = 0).
- * LRS reading: scaled QoIs z* = q* / s with a per-QoI scale s (given, or
- * |q*| at the first corrected step, zero replaced by one); the model
- * predicts the corrected scaled QoIs z = [z*, 1] C + eta, eta ~ N(mu,
- * Sigma); the correction is dQ = s z - q*. */
+/* dQ for the step (Sec. 4.3 tracking; Sec. 4.4 LRS, eq. LRS).
+ * LRS reading: scaled QoIs z = q / s with a per-QoI scale s (given, or
+ * |q*| at the first corrected step, zero replaced by one; a history model
+ * needs it given).  The model input is
+ *   x = [z^{n-1}, ..., z^{n-h}, z*^n, z*^{n-1}, ..., z*^{n-h}, 1],
+ * where z*^m are the predictor QoIs of step m and z^m the corrected ones,
+ * q^m = q*^m + dQ^m (q*^m when that step's correction was skipped); the
+ * model predicts the corrected scaled QoIs z = x C + eta, eta ~ N(mu, Sigma),
+ * and the correction is dQ = s z - q*.  h = 0 leaves x = [z*^n, 1]. */
 static void closure_dq(Orc *o, const double *qs, double *dq)
 {
-    const int nq = o->cl.nq;
+    const int nq = o->cl.nq, h = o->cl.h;
     for (int k = 0; k < nq; k++) dq[k] = 0.0;
     if (o->step < o->cl.spinup || o->cl.mode == 0) return;
     if (o->cl.mode == 1) {
@@ -769,19 +787,31 @@ static void closure_dq(Orc *o, const double *qs, double *dq)
         for (int k = 0; k < nq; k++) o->s[k] = qs[k] != 0.0 ? fabs(qs[k]) : 1.0;
         o->s_set = 1;
     }
-    double z[OQMAX], x[OQMAX + 1], eta[OQMAX];
+    double z[OQMAX], eta[OQMAX];
     orc_lrs_normals(o->cl.seed, o->step, nq, z);
     for (int k = 0; k < nq; k++) {
         eta[k] = o->cl.mu[k];
         for (int j = 0; j <= k; j++) eta[k] += o->L[k * nq + j] * z[j];
     }
-    for (int k = 0; k < nq; k++) x[k] = qs[k] / o->s[k];
-    x[nq] = 1.0;
+    const long len = (long)(2 * h + 1) * nq + 1;
+    const double *C = h > 0 ? o->Chist : o->cl.C;
+    double *x = (double *)malloc(sizeof(double) * len);
+    for (int r = 1; r <= h; r++) {
+        const orc_rec *rc = &o->recs[o->step - r];   /* records are indexed by step */
+        for (int i = 0; i < nq; i++) {
+            const double qc = rc->q[i] + ((rc->flags & 2) ? 0.0 : rc->dq[i]);
+            x[(long)(r - 1) * nq + i] = qc / o->s[i];
+            x[(long)(h + r) * nq + i] = rc->q[i] / o->s[i];
+        }
+    }
+    for (int i = 0; i < nq; i++) x[(long)h * nq + i] = qs[i] / o->s[i];
+    x[len - 1] = 1.0;
     for (int k = 0; k < nq; k++) {
         double zh = eta[k];
-        for (int i = 0; i <= nq; i++) zh += x[i] * o->cl.C[i * nq + k];
+        for (long r = 0; r < len; r++) zh += x[r] * C[r * nq + k];
         dq[k] = o->s[k] * zh - qs[k];
     }
+    free(x);
 }
 
 /* ------------------------------------------------------------------ */
