@@ -43,6 +43,7 @@ extern "C" {
 #endif
 
 #define LBM_MAX_QOI 16
+#define LBM_MAX_HIST 1024   /* LRS history length; also 2 h nq <= 32768 */
 
 enum {
     LBM_OK = 0,
@@ -97,10 +98,18 @@ enum { LBM_CLOSURE_OFF = 0, LBM_CLOSURE_TRACK = 1, LBM_CLOSURE_LRS = 2 };
 /* TO closure.  All arrays are host memory and are deep-copied.
  *  - mode OFF: the full TO machinery runs with dQ = 0 (QoIs are recorded).
  *  - TRACK:    dQ = qref[step] - q* (eq. dQ-from-ref); steps beyond nref get dQ = 0.
- *  - LRS:      h = 0 regression on scaled QoIs: z* = q* / s, x = [z*, 1],
- *              z = x C + eta, eta ~ N(mu, Sigma), dQ = s z - q* (eq. LRS).
- *              s = scale if given, else |q*| at the first corrected step
- *              (zero replaced by one).  Sigma is SPD, or all zero.
+ *  - LRS:      regression on scaled QoIs z = q / s (eq. LRS):
+ *              x = [z^{n-1}, ..., z^{n-h}, z*^n, z*^{n-1}, ..., z*^{n-h}, 1],
+ *              z = x C + eta, eta ~ N(mu, Sigma), dQ = s z - q*; z*^m are the
+ *              predictor QoIs of step m, z^m the corrected ones,
+ *              q^m = q*^m + dQ^m (q*^m if that step's correction was skipped).
+ *              h = 0 leaves x = [z*, 1].  s = scale if given, else |q*| at
+ *              the first corrected step (zero replaced by one); h > 0 needs
+ *              scale.  Sigma is SPD, or all zero.
+ *              The history is read from the record ring, so h > 0 needs
+ *              rec_cap > h and spinup >= (steps taken so far) + h when the
+ *              closure is set: the h steps before the first corrected one
+ *              are recorded under this closure.
  *  - dQ = 0 for steps < spinup in every mode.
  * Band weights (eq. 3d-mp-band-weights): d_w(y) = min(y+1/2, ny-1/2-y),
  * centres log-spaced in d_w over [band_dmin, band_dmax], sigma equal to the
@@ -112,8 +121,8 @@ typedef struct {
     double band_dmin, band_dmax;
     int mode;
     long spinup;
-    int h;                      /* history length; must be 0 */
-    const double* C;            /* (nq+1) x nq row-major (LRS) */
+    int h;                      /* LRS history length, 0..LBM_MAX_HIST */
+    const double* C;            /* ((2h+1) nq + 1) x nq row-major (LRS), rows in the order of x */
     const double* mu;           /* nq (LRS; NULL = 0) */
     const double* Sigma;        /* nq x nq (LRS) */
     const double* scale;        /* nq or NULL */

@@ -59,6 +59,7 @@ void filter_poly(int f, double r[3])
 
 struct ClosureShape {
     int nq = 0, nsa = 0, nmp = 0, jv = 0, jw = 0, has_z = 0, has_e = 0, nbands = 0;
+    int h = 0, nhc = 0;   // LRS history length; k_sum workgroups of its product
     int npart() const { return nsa + nsa * (nsa + 1) / 2 + nmp * (1 + nsa); }
 };
 
@@ -67,8 +68,18 @@ int closure_shape(const lbm_config* cfg, const lbm_closure* cl, ClosureShape* ou
     ClosureShape s;
     if (!cl) { *out = s; return LBM_OK; }
     if (cl->nq < 1 || cl->nq > LBM_MAX_QOI || !cl->q) return fail(LBM_EINVAL, "closure: nq must be in [1,%d]", LBM_MAX_QOI);
-    if (cl->h != 0) return fail(LBM_EINVAL, "closure: only history length h = 0 is supported");
     if (cl->mode < LBM_CLOSURE_OFF || cl->mode > LBM_CLOSURE_LRS) return fail(LBM_EINVAL, "closure: bad mode");
+    if (cl->h < 0 || cl->h > LBM_MAX_HIST || 2L * cl->h * cl->nq > (long)kHistRows * kMaxHistChunks)
+        return fail(LBM_EINVAL, "closure: history length h must be in [0,%d] with 2 h nq <= %d", LBM_MAX_HIST,
+                    kHistRows * kMaxHistChunks);
+    if (cl->h > 0) {
+        if (cl->mode != LBM_CLOSURE_LRS) return fail(LBM_EINVAL, "closure: a history length needs mode LRS");
+        if (!cl->scale) return fail(LBM_EINVAL, "closure: a history model needs the scale s");
+        const int rc = cfg->rec_cap > 0 ? cfg->rec_cap : 4096;
+        if (rc <= cl->h) return fail(LBM_EINVAL, "closure: rec_cap must exceed the history length");
+        s.h = cl->h;
+        s.nhc = (2 * cl->h * cl->nq + kHistRows - 1) / kHistRows;
+    }
     {
         // the TO kernels address every field component, and pairs of
         // population arrays, with 32-bit byte offsets
@@ -125,7 +136,7 @@ int check_config(const lbm_config* c)
 
 struct Plan {
     size_t member, param, ctl, recs, g0, g1, fprof, vn, part_stats, part_diag, work1, workm;
-    size_t rho, vs, P, W, Cf, part_to, bandw, cmp, workr, workb, sums, works;
+    size_t rho, vs, P, W, Cf, part_to, bandw, cmp, workr, workb, sums, works, hpart;
     size_t total;
     int N, D, NC, Q, esz, nb1, nbx2, cpt2, nbr, nbb, nbs, zc, btx, rec_cap;
     ClosureShape cap;
@@ -187,14 +198,20 @@ void make_plan(const lbm_config* c, const ClosureShape& cs, Plan* p)
         P.cmp = take(sizeof(double) * c->ny);
         P.workr = take(sizeof(int2) * P.nbr);
         P.workb = take(sizeof(int2) * P.nbb);
-        // k_sum workgroups: the LRS draw (slot -1), then one per sum
-        P.nbs = 5 + cs.npart();
-        P.sums = take(sizeof(double) * (P.nbs - 1));
+        // k_sum workgroups: the LRS draw (slot -1), the history product
+        // (slots -2 - c), then one per sum
+        P.nbs = 5 + cs.nhc + cs.npart();
+        P.sums = take(sizeof(double) * (4 + cs.npart()));
         P.works = take(sizeof(int2) * P.nbs);
+        P.hpart = take(sizeof(double) * kMaxQ * std::max(cs.nhc, 1));
     }
     P.total = o;
     *p = P;
 }
+
+// Slot of k_sum workgroup k of a member whose plan holds nhc history
+// workgroups: -1 the LRS draw, -2 - c history chunk c, then the sums 0...
+int ksum_slot(int k, int nhc) { return k == 0 ? -1 : (k <= nhc ? -1 - k : k - 1 - nhc); }
 
 // Work-table order for the 8 XCDs of MI355X, which receive workgroups
 // round-robin by workgroup index and each have their own L2: entry w runs on
@@ -283,6 +300,8 @@ struct lbm_ctx {
     long version = 0;     // bumps whenever launch parameters change
     double* qref_dev = nullptr;
     size_t qref_cap = 0;
+    double* chist_dev = nullptr;   // history rows of the LRS matrix
+    size_t chist_cap = 0;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     long gver[2] = {-1, -1};
     int gchunk = 32;
@@ -368,8 +387,10 @@ int apply_closure(lbm_ctx* c, const lbm_closure* cl)
     if (cl) {
         const ClosureShape& cap = c->plan.cap;
         if (!c->has_to || cs.nsa > cap.nsa || cs.jv > cap.jv || (cs.has_z && (!cap.has_z || cs.jw > cap.jw)) ||
-            cs.npart() > cap.npart() || cs.nbands > std::max(cap.nbands, 1))
+            cs.npart() > cap.npart() || cs.nbands > std::max(cap.nbands, 1) || cs.nhc > cap.nhc)
             return fail(LBM_ENOMEM, "closure does not fit the workspace planned at creation");
+        if (cs.h > 0 && cl->spinup < c->host_step + cs.h)
+            return fail(LBM_EINVAL, "closure: spinup must be at least the step count plus the history length");
     }
     DevParam p{};
     if (cl) {
@@ -407,8 +428,33 @@ int apply_closure(lbm_ctx* c, const lbm_closure* cl)
         }
         const int nq = cl->nq;
         if (cl->mode == LBM_CLOSURE_LRS) {
-            for (int i = 0; i <= nq; ++i)
-                for (int k = 0; k < nq; ++k) p.C[i * kMaxQ + k] = cl->C[i * nq + k];
+            // rows of z*^n and the bias here; the history rows (z^{n-r} and
+            // z*^{n-r}, r = 1..h) to the history buffer
+            const int h = cs.h;
+            for (int i = 0; i <= nq; ++i) {
+                const long row = i < nq ? (long)h * nq + i : (long)(2 * h + 1) * nq;
+                for (int k = 0; k < nq; ++k) p.C[i * kMaxQ + k] = cl->C[row * nq + k];
+            }
+            p.h = h;
+            p.nhc = cs.nhc;
+            if (h > 0) {
+                const size_t rows = 2 * (size_t)h * nq;
+                std::vector<double> ch(rows * nq);
+                for (size_t r = 0; r < rows; ++r) {
+                    const size_t src = r < (size_t)h * nq ? r : r + nq;   // skip the z*^n rows
+                    for (int k = 0; k < nq; ++k) ch[r * nq + k] = cl->C[src * nq + k];
+                }
+                const size_t need = sizeof(double) * ch.size();
+                if (need > c->chist_cap) {
+                    if (c->chist_dev) HIPCHK(hipFree(c->chist_dev));
+                    c->chist_dev = nullptr;
+                    HIPCHK(hipMalloc(&c->chist_dev, need));
+                    c->chist_cap = need;
+                }
+                rc = upload(c, c->chist_dev, ch.data(), need);
+                if (rc) return rc;
+                p.chist = c->chist_dev;
+            }
             for (int k = 0; k < nq; ++k) p.mu[k] = cl->mu ? cl->mu[k] : 0.0;
             if (!cholesky_host(cl->Sigma, nq, p.L, kMaxQ)) return fail(LBM_EINVAL, "closure: Sigma is not SPD");
             if (cl->scale) {
@@ -572,6 +618,7 @@ int lbm_create(const lbm_config* cfg, const lbm_closure* closure, void* dev_aren
         m.bandw = (double*)(A + plan.bandw);
         m.cmp = (double*)(A + plan.cmp);
         m.sums = (double*)(A + plan.sums);
+        m.hpart = (double*)(A + plan.hpart);
     }
     c->dm = (DevMember*)(A + plan.member);
     // host tables
@@ -603,7 +650,7 @@ int lbm_create(const lbm_config* cfg, const lbm_closure* closure, void* dev_aren
         }
         if (!rc) rc = upload(c, A + plan.workb, wb.data(), sizeof(int2) * wb.size());
         std::vector<int2> ws(plan.nbs);
-        for (int b = 0; b < plan.nbs; ++b) ws[b] = make_int2(0, b - 1);
+        for (int b = 0; b < plan.nbs; ++b) ws[b] = make_int2(0, ksum_slot(b, plan.cap.nhc));
         if (!rc) rc = upload(c, A + plan.works, ws.data(), sizeof(int2) * ws.size());
     }
     if (!rc) rc = upload(c, c->dm, &m, sizeof m);
@@ -628,6 +675,8 @@ int lbm_create(const lbm_config* cfg, const lbm_closure* closure, void* dev_aren
     }
     if (!rc && closure) rc = apply_closure(c, closure);
     if (rc) {
+        if (c->qref_dev) hipFree(c->qref_dev);
+        if (c->chist_dev) hipFree(c->chist_dev);
         if (c->own_stream) hipStreamDestroy(c->stream);
         delete c;
         return rc;
@@ -642,6 +691,7 @@ void lbm_destroy(lbm_ctx* c)
     hipStreamSynchronize(c->stream);
     drop_graphs(c);
     if (c->qref_dev) hipFree(c->qref_dev);
+    if (c->chist_dev) hipFree(c->chist_dev);
     if (c->own_stream) hipStreamDestroy(c->stream);
     delete c;
 }
@@ -929,7 +979,8 @@ static int batch_build(lbm_batch* b)
         o.ws = work.size();
         if (keys[gi].mode == 2)
             for (int i : gm[gi])
-                for (int k = 0; k < b->mem[i]->plan.nbs; ++k) work.push_back(make_int2(i, k - 1));
+                for (int k = 0; k < b->mem[i]->plan.nbs; ++k)
+                    work.push_back(make_int2(i, ksum_slot(k, b->mem[i]->plan.cap.nhc)));
         o.nbs = work.size() - o.ws;
         o.wm = workm.size();
         for (int i : gm[gi]) workm.push_back(i);

@@ -19,12 +19,15 @@ constexpr int kBinTX = 32;      // binomial-filter tile: x extent
 constexpr int kBinTY = kBlock / kBinTX;  // y extent
 constexpr int kBinTXW = 64;     // the wide tile (64 x 4) of the one-pass binomial kernel
 constexpr int kBinZCMax = 16;   // most z planes per workgroup chosen automatically (3-D)
+constexpr int kHistRows = 512;   // LRS history rows (x entries) per k_sum workgroup
+constexpr int kMaxHistChunks = 64;                 // so 2 h nq <= 32768
 
 // Constant closure parameters (written by the host at set_closure).
 struct DevParam {
     int nq, mode, nsa, nmp;
     int nbands, have_scale, nref, jv;  // jv: highest power of B applied to v
-    int jw, has_z, has_e, pad0;        // jw: highest power applied to curl v
+    int jw, has_z, has_e, h;           // jw: highest power applied to curl v; h: LRS history length
+    int nhc, pad1;                     // workgroups of the history product (k_sum)
     long long spinup;
     unsigned long long seed;
     int sa_slot[kMaxSA];               // user index of each E/Z QoI
@@ -41,6 +44,8 @@ struct DevParam {
     double scale[kMaxQ];
     double gmp[kMaxQ * kMaxQ];         // <w_i e_x, w_j e_x> = nx nz sum_y w_i w_j
     const double* qref;                // nref x nq
+    const double* chist;               // h > 0: the history rows of C, [2 h nq][nq]: rows of
+                                       // z^{n-1..n-h}, then of z*^{n-1..n-h}
 };
 
 // Per-step control state written by the kernels.
@@ -82,6 +87,7 @@ struct DevMember {
     double* cmp;                       // [ny]
     double* fprof;                     // body force F_x(y) [ny]
     double* sums;                      // [4 + npart]: reduced statistics and TO partials
+    double* hpart;                     // [nhc][kMaxQ]: LRS history product per k_sum workgroup
 };
 
 #ifdef __HIP_DEVICE_COMPILE__

@@ -981,7 +981,8 @@ __global__ void k_normals_test(unsigned long long seed, long long step0, int nst
 // K2d: cross-block sums, one workgroup per (member, value slot).  Slots 0..3
 // sum the statistics of the stream-collide workgroups, slots 4.. the TO
 // partials of the reduce workgroups; the order is fixed by the member's own
-// block counts.  Slot -1 makes the member's LRS draw of the step.
+// block counts.  Slot -1 makes the member's LRS draw of the step, slots
+// -2 - c chunk c of the product of the LRS history with its rows of C.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_sum(const DevMember* __restrict__ mems, const int2* __restrict__ work)
 {
@@ -989,7 +990,7 @@ __global__ __launch_bounds__(kBlock) void k_sum(const DevMember* __restrict__ me
     const int2 wk = work[blockIdx.x];
     KMember& m = *kc(mems + wk.x);
     const int slot = wk.y;
-    if (slot < 0) {
+    if (slot == -1) {
         // the member's LRS draw for this step, off the solve's critical
         // path: normals xi (four per Philox block), then e = mu + L xi
         __shared__ double z[kMaxQ];
@@ -1010,6 +1011,41 @@ __global__ __launch_bounds__(kBlock) void k_sum(const DevMember* __restrict__ me
             for (int j = 0; j <= tid; ++j) e += prm->L[tid * kMaxQ + j] * z[j];
             ctl->lrs_e[tid] = e;
         }
+        return;
+    }
+    if (slot < -1) {
+        // history chunk c of the LRS product: sum over the x entries r in
+        // [c kHistRows, (c+1) kHistRows) of x_r C[r][k], where x runs over
+        // z^{n-1..n-h} then z*^{n-1..n-h} (z = q / s) from the record ring
+        __shared__ double lds[kMaxQ * (kBlock / 64)];
+        KParam* prm = kc(m.prm);
+        DevCtl* ctl = m.ctl;
+        const long long step = ctl->step;
+        const int c = -2 - slot;
+        if (prm->mode != LBM_CLOSURE_LRS || prm->h == 0 || c >= prm->nhc || step < prm->spinup) return;   // uniform
+        const int nq = prm->nq, h = prm->h, rows = 2 * h * nq;
+        double acc[kMaxQ];
+#pragma unroll
+        for (int k = 0; k < kMaxQ; ++k) acc[k] = 0.0;
+#pragma unroll
+        for (int u = 0; u < kHistRows / kBlock; ++u) {
+            const int r = c * kHistRows + u * kBlock + threadIdx.x;
+            if (r < rows) {
+                const int b = r / nq, i = r % nq;
+                const bool corr = b < h;                       // z^{n-1-b}, else z*^{n-1-(b-h)}
+                const long long mstep = step - 1 - (corr ? b : b - h);
+                const lbm_qoi_rec* rec = m.recs + (size_t)(mstep % m.rec_cap);
+                double qv = rec->q[i];
+                if (corr && !(rec->flags & 2)) qv += rec->dq[i];
+                const double x = qv / prm->scale[i];
+                const double* crow = prm->chist + (size_t)r * nq;
+#pragma unroll
+                for (int k = 0; k < kMaxQ; ++k)
+                    if (k < nq) acc[k] += x * crow[k];
+            }
+        }
+        const double v = block_sum_spread<kMaxQ>(acc, lds);
+        if (threadIdx.x < nq) m.hpart[c * kMaxQ + threadIdx.x] = v;
         return;
     }
     if (slot >= 4 + m.npart) return;
@@ -1044,7 +1080,7 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
 {
     __shared__ double M[2][kMaxQ][2 * kMaxQ];
     __shared__ double sf[kMaxSums];
-    __shared__ double Cs[(kMaxQ + 1) * kMaxQ], es[kMaxQ];
+    __shared__ double Cs[(kMaxQ + 1) * kMaxQ], es[kMaxQ], hps[kMaxHistChunks * kMaxQ];
     __shared__ double q[kMaxQ], dq[kMaxQ], beta[kMaxQ], gam[kMaxQ], sc[kMaxQ], qs[kMaxQ];
     __shared__ double rrs[kMaxSA][kMaxPow + 1], gmps[kMaxQ * kMaxQ];
     __shared__ int kinds[kMaxSA], saslot[kMaxSA], mpslot[kMaxQ], mpband[kMaxQ];
@@ -1065,6 +1101,7 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
     if (lrs) {
         for (int k = tid; k < (nq + 1) * kMaxQ; k += kBlock) Cs[k] = prm->C[k];
         if (tid < nq) es[tid] = ctl->lrs_e[tid];
+        for (int k = tid; k < prm->nhc * kMaxQ; k += kBlock) hps[k] = m.hpart[k];
     }
     for (int k = tid; k < 2 * kMaxQ * 2 * kMaxQ; k += kBlock) (&M[0][0][0])[k] = 0.0;
     if (tid < kMaxSA * (kMaxPow + 1)) (&rrs[0][0])[tid] = (&prm->rr[0][0])[tid];
@@ -1130,11 +1167,13 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
         }
     }
     __syncthreads();
-    // (d) the LRS draw: dQ = s (z* C + C_bias + e) - q*, with e = mu + L xi
-    // drawn ahead of this kernel (k_sum); terms past nq add exact zeros
+    // (d) the LRS draw: dQ = s (x C + e) - q*, with e = mu + L xi and the
+    // history part of x C formed ahead of this kernel (k_sum); terms past nq
+    // add exact zeros
     if (active && lrs && tid < nq) {
         const int k = tid;
         double zh = es[k];
+        for (int c = 0; c < prm->nhc; ++c) zh += hps[c * kMaxQ + k];
 #pragma unroll
         for (int i = 0; i < kMaxQ; ++i) {
             const int ic = i < nq ? i : 0;

@@ -174,14 +174,14 @@ class ClosureSpec:
     """Owns the host arrays a Closure struct points to."""
 
     def __init__(self, qois, mode="off", spinup=0, C=None, mu=None, Sigma=None, scale=None,
-                 qref=None, nbands=0, dmin=0.5, dmax=1.0, seed=0):
+                 qref=None, nbands=0, dmin=0.5, dmax=1.0, seed=0, h=0):
         nq = len(qois)
         self.nq = nq
         self._q = (QoiSpec * nq)()
         for k, (kind, filt, band) in enumerate(qois):
             self._q[k] = QoiSpec({"E": QOI_E, "Z": QOI_Z, "MP": QOI_MP}[kind], FILT[filt], band)
         arr = lambda a, n: None if a is None else np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(n))
-        self._C = arr(C, (nq + 1) * nq)
+        self._C = arr(C, ((2 * h + 1) * nq + 1) * nq)
         self._mu = arr(mu, nq)
         self._S = arr(Sigma, nq * nq)
         self._scale = arr(scale, nq)
@@ -194,7 +194,7 @@ class ClosureSpec:
         self.c.band_dmax = dmax
         self.c.mode = MODE[mode] if isinstance(mode, str) else mode
         self.c.spinup = spinup
-        self.c.h = 0
+        self.c.h = h
         self.c.C = _dptr(self._C)
         self.c.mu = _dptr(self._mu)
         self.c.Sigma = _dptr(self._S)

@@ -134,6 +134,35 @@ def lrs_model_channel(nq: int, seed_a: int, seed_sigma: int, kappa: float = 0.05
     return C, np.zeros(nq), Sigma
 
 
+def lrs_history_model(h: int, nq: int, seed_a: int, seed_sigma: int, seed_eps: int, kappa: float = 0.05,
+                      spread: float = 0.01, noise: float = 1e-5, w: float = 0.5, eps: float = 0.01):
+    """Synthetic history-h LRS model, per QoI (diagonal in the QoIs).
+
+    Rows follow the LRS input [z^{n-1..n-h}, z*^n, z*^{n-1..n-h}, 1].  Each
+    scaled QoI relaxes towards one at the seeded rate r = kappa + spread |a|,
+    a ~ N(0, 1), from a blend of its previous corrected value (weight w) and
+    its current predictor value:  z^n = (1 - r)(w z^{n-1} + (1 - w) z*^n) + r
+    + sum_{l=2..h} e_l (z^{n-l} - z*^{n-l}) + residual, with seeded
+    e_l ~ eps N(0, 1) / h, mu = 0 and Sigma = noise^2 (M M^T / nq + 0.1 I).
+    """
+    a = np.abs(np.random.default_rng(seed_a).standard_normal(nq))
+    r = kappa + spread * a
+    e = eps * np.random.default_rng(seed_eps).standard_normal((max(h, 1), nq)) / max(h, 1)
+    M = np.random.default_rng(seed_sigma).standard_normal((nq, nq))
+    C = np.zeros(((2 * h + 1) * nq + 1, nq))
+    k = np.arange(nq)
+    C[h * nq + k, k] = (1 - r) * (1 - w if h > 0 else 1.0)
+    if h > 0:
+        C[k, k] = (1 - r) * w
+    for lag in range(2, h + 1):
+        C[(lag - 1) * nq + k, k] = e[lag - 1]
+        C[(h + lag) * nq + k, k] = -e[lag - 1]
+    C[-1, :] = r
+    Sigma = noise * noise * (M @ M.T / nq + 0.1 * np.eye(nq))
+    Sigma = 0.5 * (Sigma + Sigma.T)
+    return C, np.zeros(nq), Sigma
+
+
 # ---------------------------------------------------------------------------
 # QoI sets of the workloads
 # ---------------------------------------------------------------------------

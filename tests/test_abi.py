@@ -74,3 +74,31 @@ def test_required_bytes_and_validation(lbm):
     big = lbm.make_config(lattice=lbm.D3Q19, precision="fp64", nx=1024, ny=512, nz=520)
     assert L.lbm_required_bytes(ct.byref(big), None) > 0
     assert L.lbm_required_bytes(ct.byref(big), ct.byref(lbm.ClosureSpec([("E", "B", 0)]).c)) == 0
+
+
+def test_history_closure_validation(lbm):
+    """History-h LRS closures (eq. LRS) the library accepts and rejects."""
+    L = lbm.lib()
+    p2 = lbm.make_config(nx=16, ny=16, rec_cap=64)
+    q2 = [("E", "B", 0), ("Z", "B", 0)]
+    S0 = np.zeros((2, 2))
+
+    def spec(h, **kw):
+        args = dict(mode="lrs", spinup=100, C=np.zeros(((2 * h + 1) * 2 + 1, 2)), Sigma=S0, scale=np.ones(2), h=h)
+        args.update(kw)
+        return lbm.ClosureSpec(q2, **args)
+
+    base = L.lbm_required_bytes(ct.byref(p2), ct.byref(spec(0).c))
+    ok = L.lbm_required_bytes(ct.byref(p2), ct.byref(spec(40).c))
+    assert base > 0 and ok >= base   # workspace of the history product
+    neg = spec(0)
+    neg.c.h = -1                                           # negative h
+    for bad in (spec(3, scale=None),                       # a history model needs s
+                spec(3, mode="track", qref=np.zeros((4, 2))),  # history only in LRS
+                spec(64),                                  # rec_cap must exceed h
+                neg):
+        assert L.lbm_required_bytes(ct.byref(p2), ct.byref(bad.c)) == 0
+        assert L.lbm_last_error()
+    big = lbm.make_config(nx=16, ny=16, rec_cap=4096)
+    assert L.lbm_required_bytes(ct.byref(big), ct.byref(spec(1024).c)) > 0          # 2 h nq = 4096
+    assert L.lbm_required_bytes(ct.byref(big), ct.byref(spec(1025).c)) == 0         # h > LBM_MAX_HIST

@@ -1,0 +1,142 @@
+"""History-h LRS on the GPU (eq. LRS with h > 0): the k_sum history product
+and the solve against the FP64 oracle, the zero-history reduction to h = 0,
+batch members with history models, and closure validation on the device."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import gpu_run, need_gpu, oracle_run, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _scale(cfg, u0, qois, cargs):
+    """s = |q*| of the last spin-up step of an uncorrected oracle run, zero
+    replaced by one."""
+    o = oracle_run(cfg, u0, qois, {k: v for k, v in cargs.items() if k in ("nbands", "dmin", "dmax")})
+    o.step(cargs["spinup"])
+    s = np.abs(o.record_arrays()["q"][-1])
+    s[s == 0] = 1.0
+    return s
+
+
+def _case2d(h, spinup, n=48, ny=40, seed=2):
+    cfg, _ = synth.kolmogorov_workload(n, tau=0.51, seed=seed)
+    cfg["ny"] = ny
+    u0 = synth.noise_velocity(2, (1, ny, n), 1e-3, seed)
+    qois = synth.QOIS_2D
+    C, mu, S = synth.lrs_history_model(h, 2, 3, 4, 5, noise=1e-4)
+    cargs = dict(mode="lrs", spinup=spinup, C=C, mu=mu, Sigma=S, seed=71, h=h)
+    cargs["scale"] = _scale(cfg, u0, qois, cargs)
+    return cfg, u0, qois, cargs
+
+
+def _case3d(h, spinup):
+    cfg, u0 = synth.channel_workload(20, 24, 12, substrate=1, cmodel=0.1)
+    qois = synth.QOIS_3D
+    nb, dmin, dmax = synth.channel_bands(24)
+    C, mu, S = synth.lrs_history_model(h, 12, 7, 9, 10)
+    cargs = dict(mode="lrs", spinup=spinup, C=C, mu=mu, Sigma=S, seed=72, h=h,
+                 nbands=nb, dmin=dmin, dmax=dmax)
+    cargs["scale"] = _scale(cfg, u0, qois, cargs)
+    return cfg, u0, qois, cargs
+
+
+def _compare(run, o):
+    rg, ro = run.record_arrays(), o.record_arrays()
+    ev = rel_err(run.fields()[1], o.velocity()[1])
+    eq = np.max(np.abs(rg["q"] - ro["q"]) / np.abs(ro["q"]))
+    edq = np.max(np.abs(rg["dq"] - ro["dq"]) / (np.max(np.abs(ro["dq"]), axis=0) + 1e-300))
+    eg = np.max(np.abs(rg["gamma"] - ro["gamma"]) / (np.max(np.abs(ro["gamma"]), axis=0) + 1e-300))
+    assert np.array_equal(rg["flags"], ro["flags"])
+    assert np.any(ro["dq"] != 0)
+    return ev, eq, edq, eg
+
+
+def test_history_lrs_parity_2d_fp64_many_chunks():
+    """h = 300, nq = 2: 1200 history entries over three k_sum workgroups."""
+    lbm = need_gpu()
+    h, S0, steps = 300, 305, 340
+    cfg, u0, qois, cargs = _case2d(h, S0)
+    _say(f"history 2d fp64 h={h}")
+    run = gpu_run(lbm, cfg, u0, "fp64", qois, cargs)
+    run.step(steps)
+    assert run.sync() == 0
+    o = oracle_run(cfg, u0, qois, cargs)
+    o.step(steps)
+    ev, eq, edq, eg = _compare(run, o)
+    _say(f"  velocity {ev:.2e}  q {eq:.2e}  dq {edq:.2e}  gamma {eg:.2e}")
+    assert ev <= 1e-11 and eq <= 1e-10 and edq <= 1e-8 and eg <= 1e-7
+
+
+def test_history_lrs_parity_channel_fp32():
+    """The 12-QoI channel closure with h = 3 in FP32 (bars of the h = 0
+    channel parity test)."""
+    lbm = need_gpu()
+    cfg, u0, qois, cargs = _case3d(3, 8)
+    _say("history channel fp32 h=3")
+    run = gpu_run(lbm, cfg, u0, "fp32", qois, cargs)
+    run.step(60)
+    assert run.sync() == 0
+    o = oracle_run(cfg, u0, qois, cargs)
+    o.step(60)
+    ev, eq, edq, eg = _compare(run, o)
+    _say(f"  velocity {ev:.2e}  q {eq:.2e}  dq {edq:.2e}  gamma {eg:.2e}")
+    assert ev <= 3e-5 and eq <= 1e-4 and edq <= 1e-2 and eg <= 1e-2
+
+
+def test_zero_history_rows_bitwise_equal_h0():
+    lbm = need_gpu()
+    h = 40
+    cfg, u0, qois, cargs = _case2d(h, 50)
+    C = cargs["C"]
+    C0 = np.vstack([C[h * 2:(h + 1) * 2], C[-1:]])
+    Ch = np.zeros_like(C)
+    Ch[h * 2:(h + 1) * 2] = C0[:2]
+    Ch[-1] = C0[2]
+    a = gpu_run(lbm, cfg, u0, "fp32", qois, dict(cargs, C=C0, h=0))
+    b = gpu_run(lbm, cfg, u0, "fp32", qois, dict(cargs, C=Ch))
+    a.step(90)
+    b.step(90)
+    a.sync()
+    b.sync()
+    ra, rb = a.record_arrays(), b.record_arrays()
+    for key in ("q", "dq", "gamma"):
+        assert np.array_equal(ra[key], rb[key]), key
+    assert np.array_equal(a.get_populations(), b.get_populations())
+
+
+def test_history_members_in_batch_bitwise():
+    lbm = need_gpu()
+    cases = [_case2d(40, 45, n=32, ny=32, seed=1), _case2d(0, 10, n=48, ny=40, seed=2), _case3d(3, 8)]
+    solo = [gpu_run(lbm, c, u, "fp32", q, a) for c, u, q, a in cases]
+    batched = [gpu_run(lbm, c, u, "fp32", q, a) for c, u, q, a in cases]
+    for r in solo:
+        r.step(70)
+    batch = lbm.Batch(batched)
+    batch.step(70)
+    batch.sync()
+    for r, s in zip(batched, solo):
+        s.sync()
+        assert np.array_equal(r.get_populations(), s.get_populations())
+        assert np.array_equal(r.record_arrays()["dq"], s.record_arrays()["dq"])
+
+
+def test_history_closure_needs_recorded_steps():
+    """spinup must leave h recorded steps under the closure when it is set."""
+    lbm = need_gpu()
+    cfg, u0, qois, cargs = _case2d(10, 12)
+    run = gpu_run(lbm, cfg, u0, "fp32", qois, cargs)
+    run.step(5)
+    run.sync()
+    with pytest.raises(lbm.LbmError):
+        run.set_closure(lbm.ClosureSpec(qois, **dict(cargs, spinup=12)))   # 12 < 5 + 10
+    run.set_closure(lbm.ClosureSpec(qois, **dict(cargs, spinup=15)))
+    run.step(20)
+    assert run.sync() == 0
+    r = run.record_arrays()
+    assert np.all(r["dq"][:15] == 0) and np.any(r["dq"][15:] != 0)
