@@ -181,6 +181,46 @@ def form_precision(lbm, w, steps):
     return out
 
 
+def form_history(lbm, w, steps, h=500):
+    """The paper's history-h LRS (h = 500: 12000 history entries for 12
+    QoIs) on the headline workload, against the same stretch with an h = 0
+    model: MLUPS over corrected steps only."""
+    import numpy as np
+    import synth
+    cfg = w["cfg"]
+    N = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    nq = len(w["qois"])
+    # scale: |q*| of the uncorrected flow after a short spin-up
+    r = lbm.Run(lbm.make_config(precision=w["precision"], **cfg),
+                lbm.ClosureSpec(w["qois"], **dict(w["cargs"], mode="off")))
+    r.init_velocity(w["u0"])
+    r.step(h)
+    r.sync()
+    s = np.abs(r.record_arrays()["q"][-1])
+    s[s == 0] = 1.0
+    r.close()
+    out = {"h": h, "history_entries": 2 * h * nq}
+    for hh in (h, 0):
+        C, mu, S = synth.lrs_history_model(hh, nq, 7, 9, 10)
+        spec = lbm.ClosureSpec(w["qois"], **dict(w["cargs"], C=C, mu=mu, Sigma=S, h=hh, scale=s, spinup=h + 5))
+        r = lbm.Run(lbm.make_config(precision=w["precision"], **cfg), spec)
+        r.init_velocity(w["u0"])
+        r.step(h + 20)
+        r.sync()
+        t = time.perf_counter()
+        r.step(steps)
+        try:
+            r.sync()
+        except lbm.LbmError as e:
+            out["error" if hh else "error_h0"] = str(e)
+        dt = time.perf_counter() - t
+        out["mlups" if hh else "mlups_h0"] = round(N * steps / dt / 1e6, 1)
+        r.close()
+    out["steps"] = steps
+    out["ratio_to_h0"] = round(out["mlups"] / out["mlups_h0"], 3)
+    return out
+
+
 def form_batched(lbm, nmem, steps):
     """System form (2): an ensemble of Kolmogorov TO-LES members on uneven
     grids advanced as one batch (one launch per kernel phase for all members,
@@ -389,6 +429,8 @@ def main():
         forms = {}
         forms["precision"] = form_precision(lbm, w, 1000)
         print(f"[bench] precision forms: {forms['precision']}", file=sys.stderr, flush=True)
+        forms["history_lrs"] = form_history(lbm, w, 2000)
+        print(f"[bench] history LRS: {forms['history_lrs']}", file=sys.stderr, flush=True)
         forms["batched"] = form_batched(lbm, 64, args.ensemble_steps)
         print(f"[bench] batched: {forms['batched']}", file=sys.stderr, flush=True)
         forms["served"] = form_served(lbm, args.serve_requests, 20.0, 2000)

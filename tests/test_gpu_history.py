@@ -140,3 +140,38 @@ def test_history_closure_needs_recorded_steps():
     assert run.sync() == 0
     r = run.record_arrays()
     assert np.all(r["dq"][:15] == 0) and np.any(r["dq"][15:] != 0)
+
+
+def test_full_size_channel_h500_property():
+    """The benchmark channel (96x48x48, FP32, 12 QoIs) with the paper's history
+    length h = 500: 12000 history entries over 24 k_sum workgroups.  At every
+    corrected step the recorded dQ equals the model applied to the recorded
+    history, dQ^n = s (x^n C + mu + L xi^n) - q*^n, with x^n assembled from
+    the records and xi^n the step's normals (both by the oracle's helpers)."""
+    import oracle
+    lbm = need_gpu()
+    h, S0, steps = 500, 505, 515
+    cfg, u0 = synth.channel_workload(96, 48, 48, substrate=1, cmodel=0.1, seed=6)
+    qois = synth.QOIS_3D
+    nb, dmin, dmax = synth.channel_bands(48)
+    C, mu, S = synth.lrs_history_model(h, 12, 7, 9, 10)
+    o = oracle.Oracle(**cfg)
+    q0, _ = o.qoi(oracle.make_closure(qois, nbands=nb, dmin=dmin, dmax=dmax), u0)
+    s = np.abs(q0)
+    cargs = dict(mode="lrs", spinup=S0, C=C, mu=mu, Sigma=S, seed=73, h=h, nbands=nb, dmin=dmin, dmax=dmax,
+                 scale=s)
+    run = gpu_run(lbm, cfg, u0, "fp32", qois, cargs)
+    run.step(steps)
+    assert run.sync() == 0
+    r = run.record_arrays()
+    q, dq = r["q"], r["dq"]
+    assert not np.any(r["flags"])
+    X, _ = oracle.lrs_inputs(q + dq, q, h, s)
+    Lc = np.linalg.cholesky(S)
+    for n in range(S0, steps):
+        eta = mu + Lc @ oracle.lrs_normals(73, n, 12)
+        want = s * (X[n - h] @ C + eta) - q[n]
+        err = np.max(np.abs(dq[n] - want) / s)
+        _say(f"  step {n}: max |dQ - model| / s = {err:.2e}")
+        assert err <= 1e-11
+    assert np.all(dq[:S0] == 0)
