@@ -148,6 +148,24 @@ typedef struct lbm_ctx lbm_ctx;
 typedef struct lbm_batch lbm_batch;
 typedef struct lbm_server lbm_server;
 
+/* Fit of the LRS model (Sec. 4.4, the regularised least-squares problem
+ * after eq. LRS) to a recorded trajectory, on the host (threads, FP64).
+ *  q_star, dq: nsteps x nq predictor QoIs and corrections of steps 0..nsteps-1
+ *    (e.g. the records of a tracking run); the corrected QoIs are
+ *    q = q_star + dq, or q_star where flags (NULL: none) has bit 1 set.
+ *  scale: nq (NULL: the standard deviation of each corrected QoI over the
+ *    trajectory, zero replaced by one); written to s_out (NULL: not returned).
+ *  Rows x^n (n = h..nsteps-1) as in lbm_closure, targets z^n = q^n / s.
+ *  C (((2h+1) nq + 1) x nq) minimises 1/2 |X C - Z|^2 + 1/2 sum_i lam_i |C_i|^2
+ *  with lam_i = lambda (sigma_i / sigma_1)^2, sigma_i the standard deviation
+ *  of the scaled corrections z^n - z*^n; mu (nq) and Sigma (nq x nq) are the
+ *  mean and unbiased sample covariance of the residuals Z - X C.
+ * Cost: about (nsteps - h) len^2 / 2 + nq len^3 / 3 multiply-adds,
+ * len = (2h+1) nq + 1, and 2 len^2 doubles of host memory.  LBM_EINVAL for
+ * bad sizes, or when lambda = 0 leaves the normal matrix singular. */
+int lbm_lrs_fit(int nq, int h, long nsteps, const double* q_star, const double* dq, const int* flags,
+                const double* scale, double lambda, double* C, double* mu, double* Sigma, double* s_out);
+
 /* Library and lattice information. */
 const char* lbm_last_error(void);
 const char* lbm_version(void);

@@ -284,6 +284,11 @@ bool cholesky_host(const double* A, int n, double* L, int ld)
 
 }  // namespace
 
+// Error reporting for the library's other translation units.
+namespace lbm {
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+}
+
 struct lbm_ctx {
     lbm_config cfg{};
     Plan plan{};

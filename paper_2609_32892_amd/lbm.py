@@ -75,7 +75,7 @@ EXPORTS = [
     "lbm_batch_sync", "lbm_batch_destroy", "lbm_profile_phases", "lbm_test_philox", "lbm_test_normals",
     "lbm_server_clock", "lbm_server_create", "lbm_server_submit", "lbm_server_advance", "lbm_server_poll",
     "lbm_server_pending", "lbm_server_stats", "lbm_server_state_bytes", "lbm_server_take_state",
-    "lbm_server_destroy",
+    "lbm_server_destroy", "lbm_lrs_fit",
 ]
 PHASES = ["stream_collide", "curl", "binomial", "reduce", "solve", "apply"]
 
@@ -136,6 +136,7 @@ def lib():
         L.lbm_server_take_state.argtypes = [P, ct.c_long, P, Z]
         L.lbm_server_destroy.argtypes = [P]
         L.lbm_server_destroy.restype = None
+        L.lbm_lrs_fit.argtypes = [I, I, ct.c_long, P, P, P, P, ct.c_double, P, P, P, P]
         _lib = L
     return _lib
 
@@ -148,6 +149,25 @@ def check(rc):
 
 def _p(a):
     return None if a is None else a.ctypes.data_as(ct.c_void_p)
+
+
+def lrs_fit(q_star, dq, h, lam, scale=None, flags=None):
+    """Fit the LRS model to a recorded trajectory (lbm_lrs_fit): q_star and
+    dq are (nsteps, nq) arrays (e.g. the records of a tracking run).
+    Returns (C, mu, Sigma, s) ready for ClosureSpec(mode="lrs", h=h, ...)."""
+    qs = np.ascontiguousarray(q_star, dtype=np.float64)
+    d = np.ascontiguousarray(dq, dtype=np.float64)
+    M, nq = qs.shape
+    if d.shape != qs.shape:
+        raise ValueError("q_star and dq must have the same shape")
+    fl = None if flags is None else np.ascontiguousarray(flags, dtype=np.int32)
+    sc = None if scale is None else np.ascontiguousarray(scale, dtype=np.float64)
+    C = np.zeros(((2 * h + 1) * nq + 1, nq))
+    mu = np.zeros(nq)
+    S = np.zeros((nq, nq))
+    s = np.zeros(nq)
+    check(lib().lbm_lrs_fit(nq, h, M, _p(qs), _p(d), _p(fl), _p(sc), float(lam), _p(C), _p(mu), _p(S), _p(s)))
+    return C, mu, S, s
 
 
 def _dptr(a):

@@ -175,3 +175,35 @@ def test_full_size_channel_h500_property():
         _say(f"  step {n}: max |dQ - model| / s = {err:.2e}")
         assert err <= 1e-11
     assert np.all(dq[:S0] == 0)
+
+
+def test_train_then_online_workflow():
+    """The paper's workflow on the device (Sec. 4.3-4.5): a tracking run
+    towards reference QoIs, the LRS fit (h = 3) to its records, then an
+    online run with the fitted model.  The online run stays stable and its
+    corrected QoIs stay near the training targets."""
+    lbm = need_gpu()
+    cfg, _ = synth.kolmogorov_workload(64, tau=0.51, seed=4)
+    u0 = synth.noise_velocity(2, (1, 64, 64), 1e-3, 4)
+    qois = synth.QOIS_2D
+    steps, S0, h = 600, 20, 3
+    o = oracle_run(cfg, u0, qois, dict(mode="off"))
+    o.step(steps)
+    qref = o.record_arrays()["q"] * (1 + 0.05 * np.sin(np.arange(steps) / 40.0))[:, None]
+    trk = gpu_run(lbm, cfg, u0, "fp32", qois, dict(mode="track", spinup=S0), qref=qref)
+    trk.step(steps)
+    assert trk.sync() == 0
+    r = trk.record_arrays()
+    C, mu, S, s = lbm.lrs_fit(r["q"][S0:], r["dq"][S0:], h, 1e-3, flags=r["flags"][S0:])
+    assert np.all(np.isfinite(C)) and np.all(np.linalg.eigvalsh(S) > 0)
+    on = gpu_run(lbm, cfg, u0, "fp32", qois, dict(mode="lrs", spinup=S0, C=C, mu=mu, Sigma=S, scale=s, h=h,
+                                                  seed=19))
+    on.step(steps)
+    assert on.sync() == 0
+    ro = on.record_arrays()
+    assert not np.any(ro["flags"])
+    qc = ro["q"][S0:] + ro["dq"][S0:]
+    lo, hi = qref[S0:].min(axis=0), qref[S0:].max(axis=0)
+    span = hi - lo
+    _say(f"  online corrected QoIs in [{qc.min(axis=0)}, {qc.max(axis=0)}], targets [{lo}, {hi}]")
+    assert np.all(qc.min(axis=0) > lo - span) and np.all(qc.max(axis=0) < hi + span)
