@@ -252,6 +252,16 @@ class Oracle:
     def stream_only(self):
         self.L.orc_stream_only(self.h)
 
+    def post_collision_velocity(self):
+        """rho and u = sum c f^p / sum f^p of the post-collision state f^p (the
+        run's state between steps; for a plain run with the exact-difference
+        force this is the predictor velocity v* of the step that made it)."""
+        fp = self.get_fp()
+        c, _ = lattice(self.cfg.lattice)
+        rho = fp.sum(axis=0)
+        u = np.array([(c[:, a][:, None] * fp).sum(axis=0) for a in range(self.d)]) / rho
+        return rho, u
+
     def velocity(self):
         rho = np.zeros(self.N)
         u = np.zeros((self.d, self.N))
@@ -385,3 +395,21 @@ def lrs_fit(q, qs, h, lam, scale=None):
     mu = R.mean(axis=0)
     Sigma = np.cov(R, rowvar=False, ddof=1).reshape(Y.shape[1], Y.shape[1])
     return C, mu, Sigma, s
+
+
+def project(field, shape, m):
+    """Wall-anchored stride-m projection phi_m (Sec. 3; Sec. 7.1 for the
+    channel): coarse cell (i, j, k) takes the fine cell (m i + o, m j + o,
+    m k + o), o = (m - 1) / 2 (m odd), so that the coarse walls, half a
+    coarse cell beyond the first and last coarse rows, sit where the fine
+    walls sit: the first coarse row is o + 1/2 = m / 2 fine cells from the
+    wall.  field: (ncomp, N) in the (z, y, x) layout of `shape` = (nz, ny, nx);
+    the z axis is kept as is when nz == 1."""
+    if m < 1 or m % 2 == 0:
+        raise ValueError("m must be odd")
+    nz, ny, nx = shape
+    f = np.asarray(field).reshape(-1, nz, ny, nx)
+    o = (m - 1) // 2
+    zs = slice(o, None, m) if nz > 1 else slice(None)
+    out = f[:, zs, o::m, o::m]
+    return np.ascontiguousarray(out.reshape(out.shape[0], -1))
