@@ -221,6 +221,26 @@ int lbm_set_populations(lbm_ctx* ctx, const double* f);
 /* Stream the current populations once without collision (index-map check). */
 int lbm_stream_only(lbm_ctx* ctx);
 
+/* HF -> LF projection (Sec. 3, the projection phi_m; Sec. 7.1, the
+ * wall-anchored stride-m subsampling): coarse cell (i, j, k) takes fine cell
+ * (m i + o, m j + o, m k + o), o = (m - 1) / 2, so the walls of both grids
+ * coincide.  The coarse context has the fine grid divided by m on every axis
+ * (nz = 1 in 2-D), the same lattice and wall setting; m is odd.  LBM_EINVAL
+ * otherwise.
+ *  - lbm_project_state: the coarse run's state becomes the projected fine
+ *    post-collision populations (f = phi_m f, any precisions); resets the
+ *    coarse step counter and records, like lbm_init_velocity.  Syncs.
+ *  - lbm_project_qoi: evaluates the probe's closure QoIs on the projected
+ *    post-collision velocity sum c f / sum f of the fine run's current state,
+ *    and appends them as the probe's next record (q; dq, gamma zero; mass and
+ *    momentum not meaningful).  The probe is a context with a closure in mode
+ *    OFF, used for nothing else; it shares the fine run's stream and the call
+ *    is enqueued there without blocking.  Called after every m fine steps,
+ *    its records are the reference trajectory q_ref of a coarse tracking run
+ *    (eq. dQ-from-ref): coarse step n <-> fine steps (n+1) m. */
+int lbm_project_state(lbm_ctx* fine, lbm_ctx* coarse, int m);
+int lbm_project_qoi(lbm_ctx* fine, lbm_ctx* probe, int m);
+
 /* Checkpoint: opaque byte image of the dynamic state (populations,
  * counters, LRS scale, records).  Restoring it into a context created with
  * the same cfg and closure resumes bitwise identically. */

@@ -857,6 +857,62 @@ int lbm_stream_only(lbm_ctx* c)
     return LBM_OK;
 }
 
+// HF -> LF projection (Sec. 3, phi_m; Sec. 7.1: wall-anchored stride-m
+// subsampling).  The coarse grid is the fine one divided by m on every axis
+// (z kept in 2-D), same lattice and wall setting; m odd.
+static int check_projection(const lbm_ctx* f, const lbm_ctx* c, int m)
+{
+    if (!f || !c) return fail(LBM_EINVAL, "NULL context");
+    if (m < 1 || m % 2 == 0) return fail(LBM_EINVAL, "projection: m must be odd and positive");
+    if (f->cfg.lattice != c->cfg.lattice || f->cfg.walls_y != c->cfg.walls_y)
+        return fail(LBM_EINVAL, "projection: lattice and walls must match");
+    const bool d3 = f->cfg.lattice == LBM_D3Q19;
+    if ((long)c->cfg.nx * m != f->cfg.nx || (long)c->cfg.ny * m != f->cfg.ny ||
+        (d3 ? (long)c->cfg.nz * m != f->cfg.nz : c->cfg.nz != 1))
+        return fail(LBM_EINVAL, "projection: the coarse grid must be the fine grid divided by m on every axis");
+    return LBM_OK;
+}
+
+int lbm_project_state(lbm_ctx* f, lbm_ctx* c, int m)
+{
+    int rc = check_projection(f, c, m);
+    if (rc) return rc;
+    const size_t Nc = c->plan.N, Q = c->plan.Q;
+    HIPCHK(hipStreamSynchronize(f->stream));   // the fine run's pending steps
+    double* buf = nullptr;
+    HIPCHK(hipMalloc(&buf, sizeof(double) * Q * Nc));
+    launch_project(f->cfg.lattice, f->cfg.precision, f->dm, f->phase, m, c->cfg.nx, c->cfg.ny, c->cfg.nz, buf,
+                   nullptr, 0, f->stream);
+    if (hipStreamSynchronize(f->stream) != hipSuccess) rc = fail(LBM_EDEVICE, "projection kernel failed");
+    if (!rc) {
+        c->phase = 0;
+        launch_state(OP_SET_POP, c->cfg.lattice, c->cfg.precision, c->dm, c->plan.N, c->has_to, 0, c->stream, buf,
+                     nullptr);
+        if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(LBM_EDEVICE, "population write failed");
+    }
+    hipFree(buf);
+    if (!rc) rc = reset_ctl(c);
+    c->version++;
+    return rc;
+}
+
+int lbm_project_qoi(lbm_ctx* f, lbm_ctx* p, int m)
+{
+    int rc = check_projection(f, p, m);
+    if (rc) return rc;
+    if (!p->has_to || p->cur.nq == 0 || p->hp.mode != LBM_CLOSURE_OFF)
+        return fail(LBM_EINVAL, "project_qoi: the probe needs a closure in mode OFF");
+    if (f->stream != p->stream) return fail(LBM_EINVAL, "project_qoi: fine run and probe must share one stream");
+    launch_project(f->cfg.lattice, f->cfg.precision, f->dm, f->phase, m, p->cfg.nx, p->cfg.ny, p->cfg.nz, nullptr,
+                   p->arena + p->plan.vs, p->cfg.precision == LBM_FP64, p->stream);
+    LaunchGroup g = ctx_group(p);
+    g.probe = 1;
+    launch_step(g, p->stream, p->phase);
+    if (hipGetLastError() != hipSuccess) return fail(LBM_EDEVICE, "project_qoi: launch failed");
+    p->host_step++;
+    return LBM_OK;
+}
+
 // Checkpoint image: header, current populations (the SGS change of the last
 // step is already in them), control block, records.
 struct StateHeader {

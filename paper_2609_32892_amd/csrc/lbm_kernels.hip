@@ -1510,6 +1510,68 @@ __global__ void k_set_pop(const DevMember* __restrict__ mems, int flip, const do
     }
 }
 
+// Wall-anchored stride-m projection (Sec. 3, the projection phi_m; Sec. 7.1
+// for the channel): coarse cell (i, j, k) takes the fine cell
+// (m i + o, m j + o, m k + o), o = (m - 1) / 2, so the coarse walls, half a
+// coarse cell beyond the first and last coarse rows, coincide with the fine
+// ones.  Writes the full populations (nullable fpop [Q][Nc]) and the velocity
+// sum c f / sum f of the post-collision state (nullable vout [D][Nc]).
+template <int LAT, typename T, int PREC>
+__global__ __launch_bounds__(kBlock) void k_project(const DevMember* __restrict__ fine, int flip, int m, int ncx,
+                                                    int ncy, int ncz, double* __restrict__ fpop,
+                                                    void* __restrict__ vout, int vout_fp64)
+{
+    using L = Lat<LAT>;
+    KMember& F = *kc(fine);
+    const int Nc = ncx * ncy * ncz;
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= Nc) return;
+    const int i = cell % ncx, t = cell / ncx, j = t % ncy, k = t / ncy;
+    const int o = (m - 1) / 2;
+    const int zf = L::D == 3 ? m * k + o : 0;
+    const size_t fc = ((size_t)zf * F.ny + (size_t)(m * j + o)) * F.nx + (size_t)(m * i + o);
+    const size_t NF = (size_t)F.N;
+    const T* g = (const T*)F.g[F.parity ^ flip];
+    double drho = 0, jm[3] = {0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+        const double gq = (double)g[(size_t)q * NF + fc];
+        if (fpop) fpop[(size_t)q * Nc + cell] = gq + (PREC == LBM_FP32_PLAIN ? 0.0 : L::w[q]);
+        drho += gq;
+        jm[0] += L::cx[q] * gq;
+        jm[1] += L::cy[q] * gq;
+        jm[2] += L::cz[q] * gq;
+    }
+    if (vout) {
+        // shifted storage: rho - 1 = sum g and rho v = sum c g (sum c w = 0)
+        const double rho = PREC == LBM_FP32_PLAIN ? drho : 1.0 + drho;
+#pragma unroll
+        for (int a = 0; a < L::D; ++a) {
+            const double u = jm[a] / rho;
+            if (vout_fp64) ((double*)vout)[(size_t)a * Nc + cell] = u;
+            else ((float*)vout)[(size_t)a * Nc + cell] = (float)u;
+        }
+    }
+}
+
+void launch_project(int lattice, int precision, const DevMember* fine, int flip, int m, int ncx, int ncy, int ncz,
+                    double* fpop, void* vout, int vout_fp64, hipStream_t st)
+{
+    const int Nc = ncx * ncy * ncz;
+    const dim3 blk(kBlock), grd((Nc + kBlock - 1) / kBlock);
+#define LBM_PROJ(LAT, T, PREC) \
+    hipLaunchKernelGGL((k_project<LAT, T, PREC>), grd, blk, 0, st, fine, flip, m, ncx, ncy, ncz, fpop, vout, vout_fp64)
+    switch (lattice * 3 + precision) {
+    case LBM_D2Q9 * 3 + LBM_FP32_SHIFTED: LBM_PROJ(LBM_D2Q9, float, LBM_FP32_SHIFTED); break;
+    case LBM_D2Q9 * 3 + LBM_FP64: LBM_PROJ(LBM_D2Q9, double, LBM_FP64); break;
+    case LBM_D2Q9 * 3 + LBM_FP32_PLAIN: LBM_PROJ(LBM_D2Q9, float, LBM_FP32_PLAIN); break;
+    case LBM_D3Q19 * 3 + LBM_FP32_SHIFTED: LBM_PROJ(LBM_D3Q19, float, LBM_FP32_SHIFTED); break;
+    case LBM_D3Q19 * 3 + LBM_FP64: LBM_PROJ(LBM_D3Q19, double, LBM_FP64); break;
+    case LBM_D3Q19 * 3 + LBM_FP32_PLAIN: LBM_PROJ(LBM_D3Q19, float, LBM_FP32_PLAIN); break;
+    }
+#undef LBM_PROJ
+}
+
 // Pure streaming (no collision) into the other buffer.
 template <int LAT, typename T, bool TO>
 __global__ void k_stream_only(const DevMember* __restrict__ mems, int flip)
@@ -1539,6 +1601,7 @@ static void launch_step_group(const LaunchGroup& g, hipStream_t st, int flip, hi
         if (ev) (void)hipEventRecord(ev[k], st);
     };
     mark(0);
+    if (g.probe) goto to_chain;
     if (g.substrate == LBM_WALE) {
         if (g.mode == 2)
             hipLaunchKernelGGL((k_moments<LAT, T, PREC, true>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip,
@@ -1563,6 +1626,7 @@ static void launch_step_group(const LaunchGroup& g, hipStream_t st, int flip, hi
     else
         LBM_STEP_SUB(LBM_BGK);
 #undef LBM_STEP_SUB
+to_chain:
     mark(1);
     if (g.mode == 2) {
         if (g.any_z) hipLaunchKernelGGL((k_curl<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1);
@@ -1588,7 +1652,7 @@ static void launch_step_group(const LaunchGroup& g, hipStream_t st, int flip, hi
         hipLaunchKernelGGL(k_sum, dim3(g.nbs), blk, 0, st, g.mems, g.works);
         hipLaunchKernelGGL(k_solve, dim3(g.nmem), blk, 0, st, g.mems, g.workm);
         mark(5);
-        hipLaunchKernelGGL((k_apply<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip);
+        if (!g.probe) hipLaunchKernelGGL((k_apply<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip);
         mark(6);
     } else if (g.mode == 1) {
         hipLaunchKernelGGL((k_diag<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1);

@@ -25,6 +25,8 @@ struct LaunchGroup {
     int nbs;
     const int* workm;   // one workgroup per member
     int nmem;
+    int probe;          // TO mode only: the QoI chain of the field already in v* (no
+                        // stream-collide, no apply); see lbm_project_qoi
 };
 
 enum { OP_INIT = 0, OP_GET_POP = 1, OP_SET_POP = 2, OP_STREAM = 3 };
@@ -41,5 +43,10 @@ void launch_fields(int lattice, int precision, const DevMember* dm, const int2* 
 void launch_philox_test(const uint32_t* in, uint32_t* out, int n, hipStream_t st);
 void launch_normals_test(unsigned long long seed, long long step0, int nsteps, int n, double* out, hipStream_t st);
 int lattice_table(int lattice, int* c, double* w);
+// Wall-anchored stride-m projection of a fine member's state (coarse grid
+// ncx x ncy x ncz): full populations into fpop [Q][Nc] (nullable) and the
+// post-collision velocity into vout [D][Nc] (nullable; double if vout_fp64).
+void launch_project(int lattice, int precision, const DevMember* fine, int flip, int m, int ncx, int ncy, int ncz,
+                    double* fpop, void* vout, int vout_fp64, hipStream_t st);
 
 }  // namespace lbm

@@ -75,7 +75,7 @@ EXPORTS = [
     "lbm_batch_sync", "lbm_batch_destroy", "lbm_profile_phases", "lbm_test_philox", "lbm_test_normals",
     "lbm_server_clock", "lbm_server_create", "lbm_server_submit", "lbm_server_advance", "lbm_server_poll",
     "lbm_server_pending", "lbm_server_stats", "lbm_server_state_bytes", "lbm_server_take_state",
-    "lbm_server_destroy", "lbm_lrs_fit",
+    "lbm_server_destroy", "lbm_lrs_fit", "lbm_project_state", "lbm_project_qoi",
 ]
 PHASES = ["stream_collide", "curl", "binomial", "reduce", "solve", "apply"]
 
@@ -137,6 +137,8 @@ def lib():
         L.lbm_server_destroy.argtypes = [P]
         L.lbm_server_destroy.restype = None
         L.lbm_lrs_fit.argtypes = [I, I, ct.c_long, P, P, P, P, ct.c_double, P, P, P, P]
+        L.lbm_project_state.argtypes = [P, P, I]
+        L.lbm_project_qoi.argtypes = [P, P, I]
         _lib = L
     return _lib
 
@@ -330,6 +332,16 @@ class Run:
 
     def stream_only(self):
         check(self.L.lbm_stream_only(self.h))
+
+    def project_state_from(self, fine: "Run", m: int):
+        """This (coarse) run's state := the wall-anchored stride-m projection
+        of the fine run's state (lbm_project_state)."""
+        check(self.L.lbm_project_state(fine.h, self.h, m))
+
+    def project_qoi_from(self, fine: "Run", m: int):
+        """Append the closure QoIs of the projected fine post-collision
+        velocity as this probe's next record (lbm_project_qoi)."""
+        check(self.L.lbm_project_qoi(fine.h, self.h, m))
 
     def profile_phases(self, nsteps):
         """Mean ms per step and launches per step of each kernel phase."""

@@ -1,0 +1,113 @@
+"""HF -> LF projection on the GPU (Sec. 3, phi_m; Sec. 7.1 wall-anchored
+stride-m subsampling; Sec. 4.3 tracking of projected HF QoIs): projected
+states and reference QoIs against the oracle, and the HF -> LF tracking
+workflow."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import gpu_run, match_populations, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _cases(kind):
+    """(fine cfg, fine u0, coarse cfg, qois, closure kwargs, m, precision)."""
+    m = 5
+    if kind == "2d":
+        cfg, _ = synth.kolmogorov_workload(80, tau=0.55, amp=2e-5, seed=3)
+        u0 = synth.noise_velocity(2, (1, 80, 80), 1e-3, 3)
+        ccfg, _ = synth.kolmogorov_workload(16, tau=0.5 + 0.05 / m, amp=2e-5 * m, seed=3)
+        return cfg, u0, ccfg, synth.QOIS_2D, {}, m, "fp64"
+    cfg, u0 = synth.channel_workload(60, 40, 30, substrate=0, cmodel=0.0, seed=4)
+    ccfg, _ = synth.channel_workload(12, 8, 6, substrate=0, cmodel=0.0, seed=4)
+    nb, dmin, dmax = synth.channel_bands(8)
+    return cfg, u0, ccfg, synth.QOIS_3D, dict(nbands=nb, dmin=dmin, dmax=dmax), m, "fp32"
+
+
+@pytest.mark.parametrize("kind", ["2d", "3d"])
+def test_project_qoi_matches_oracle(kind):
+    """Probe records = QoIs of the projected post-collision velocity of the
+    fine run after every m fine steps."""
+    lbm = need_gpu()
+    cfg, u0, ccfg, qois, bands, m, prec = _cases(kind)
+    _say(f"project_qoi {kind} {prec}")
+    fine = gpu_run(lbm, cfg, u0, prec)
+    probe = gpu_run(lbm, ccfg, np.zeros((2 if kind == "2d" else 3,) + (ccfg["nz"], ccfg["ny"], ccfg["nx"])), prec,
+                    qois, dict(mode="off", **bands))
+    o = oracle.Oracle(**cfg)
+    o.init(u0)
+    oc = oracle.Oracle(**ccfg)
+    cl = oracle.make_closure(qois, **bands)
+    nrec = 8
+    qo = []
+    for n in range(nrec):
+        fine.step(m)
+        probe.project_qoi_from(fine, m)
+        o.step(m)
+        _, up = o.post_collision_velocity()
+        qo.append(oc.qoi(cl, oracle.project(up, (cfg["nz"], cfg["ny"], cfg["nx"]), m))[0])
+    probe.sync()
+    qo = np.array(qo)
+    assert probe.step_count == nrec
+    qg = probe.record_arrays()["q"]
+    err = np.max(np.abs(qg - qo) / np.abs(qo))
+    _say(f"  max rel QoI error {err:.2e}")
+    assert err <= (1e-11 if prec == "fp64" else 1e-4)
+    assert np.all(probe.record_arrays()["dq"] == 0)
+
+
+def test_project_state_matches_oracle():
+    lbm = need_gpu()
+    cfg, u0, ccfg, qois, bands, m, _ = _cases("3d")
+    fine = gpu_run(lbm, cfg, u0, "fp64")
+    coarse = gpu_run(lbm, ccfg, np.zeros((3, ccfg["nz"], ccfg["ny"], ccfg["nx"])), "fp64")
+    fine.step(20)
+    coarse.step(3)
+    coarse.project_state_from(fine, m)
+    assert coarse.step_count == 0
+    o = oracle.Oracle(**cfg)
+    o.init(u0)
+    o.step(20)
+    want = oracle.project(o.get_fp(), (cfg["nz"], cfg["ny"], cfg["nx"]), m)
+    got = match_populations(lbm, 1, coarse.get_populations())
+    assert np.max(np.abs(got - want)) <= 1e-13
+    with pytest.raises(lbm.LbmError):   # even stride
+        coarse.project_state_from(fine, 2)
+
+
+def test_hf_to_lf_tracking_workflow():
+    """Fine FP32 run -> projected initial state and reference QoIs -> coarse
+    tracking run: the coarse corrected QoIs follow the projected reference
+    (eq. dQ-from-ref), which the uncorrected coarse run does not."""
+    lbm = need_gpu()
+    m, n_lf, S0 = 5, 60, 5
+    cfg, _ = synth.kolmogorov_workload(160, tau=0.55, amp=2e-5, seed=7)
+    u0 = synth.turbulent_velocity_2d(160, 0.02, seed=7)
+    ccfg, _ = synth.kolmogorov_workload(32, tau=0.5 + 0.05 / m, amp=2e-5 * m, seed=7)
+    zero = np.zeros((2, 1, 32, 32))
+    fine = gpu_run(lbm, cfg, u0, "fp32")
+    probe = gpu_run(lbm, ccfg, zero, "fp32", synth.QOIS_2D, dict(mode="off"))
+    for _ in range(n_lf):
+        fine.step(m)
+        probe.project_qoi_from(fine, m)
+    probe.sync()
+    qref = probe.record_arrays()["q"]
+    fine0 = gpu_run(lbm, cfg, u0, "fp32")   # the fine state at t = 0
+    runs = {}
+    for mode in ("track", "off"):
+        r = gpu_run(lbm, ccfg, zero, "fp32", synth.QOIS_2D, dict(mode=mode, spinup=S0), qref=qref)
+        r.project_state_from(fine0, m)
+        r.step(n_lf)
+        assert r.sync() == 0
+        runs[mode] = r.record_arrays()
+    t = runs["track"]
+    assert np.allclose(t["q"][S0:] + t["dq"][S0:], qref[S0:], rtol=1e-12, atol=0)
+    drift = np.max(np.abs(runs["off"]["q"][S0:] - qref[S0:]) / np.abs(qref[S0:]))
+    _say(f"  uncorrected coarse run vs projected reference: max rel {drift:.2e}")
+    assert drift > 1e-3
