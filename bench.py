@@ -323,6 +323,52 @@ def form_fine(lbm, steps):
             "stream_collide_gbs": round(152 * N / (ms["stream_collide"] * 1e-3) / 1e9, 1)}
 
 
+def form_hf_lf(lbm, hf_steps, m=5):
+    """The paper's HF -> LF channel pipeline at its grid sizes (Sec. 7.1):
+    plain BGK on the 1475 x 235 x 490 HF grid (the paper's 1475 x 237 x 490
+    with its two solid rows not stored), and after every m = 5 HF steps the
+    12 QoIs of the wall-anchored stride-5 projection onto the 295 x 47 x 98 LF
+    grid (lbm_project_qoi), the reference of LF tracking.  Reports the HF
+    throughput and the added cost per reference evaluation (the paper: under
+    1%, 0.8 ms on a 91 ms HF step)."""
+    import numpy as np
+    import synth
+    nx, ny, nz = 1475, 235, 490
+    cfg, _ = synth.channel_workload(8, ny, 8, substrate=0, cmodel=0.0, seed=13)
+    cfg.update(nx=nx, nz=nz)
+    N = nx * ny * nz
+    hf = lbm.Run(lbm.make_config(precision="fp32", **cfg))
+    hf.init_velocity(synth.channel_velocity(nx, ny, nz, seed=13))
+    lcfg, _ = synth.channel_workload(nx // m, ny // m, nz // m, substrate=1, cmodel=0.1, seed=13)
+    nb, dmin, dmax = synth.channel_bands(ny // m)
+    probe = lbm.Run(lbm.make_config(precision="fp32", **lcfg),
+                    lbm.ClosureSpec(synth.QOIS_3D, mode="off", nbands=nb, dmin=dmin, dmax=dmax))
+    probe.init_velocity(np.zeros((3, probe.N)))
+    hf.step(10)
+    probe.project_qoi_from(hf, m)
+    hf.sync()
+    t = time.perf_counter()
+    hf.step(hf_steps)
+    hf.sync()
+    t_plain = time.perf_counter() - t
+    t = time.perf_counter()
+    for _ in range(hf_steps // m):
+        hf.step(m)
+        probe.project_qoi_from(hf, m)
+    hf.sync()
+    t_ref = time.perf_counter() - t
+    q = probe.record_arrays()["q"]
+    out = {"hf_grid": [nx, ny, nz], "lf_grid": [nx // m, ny // m, nz // m], "hf_steps": hf_steps,
+           "hf_mlups": round(N * hf_steps / t_plain / 1e6, 1),
+           "hf_ms_per_step": round(t_plain / hf_steps * 1e3, 3),
+           "reference_ms_per_lf_step": round((t_ref - t_plain) / (hf_steps // m) * 1e3, 3),
+           "reference_overhead_frac": round((t_ref - t_plain) / t_plain, 4),
+           "qoi_records": int(q.shape[0]), "qoi_finite": bool(np.all(np.isfinite(q)))}
+    probe.close()
+    hf.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -437,6 +483,8 @@ def main():
         print(f"[bench] served: {forms['served']}", file=sys.stderr, flush=True)
         forms["fine_grid_plain"] = form_fine(lbm, 200)
         print(f"[bench] fine grid: {forms['fine_grid_plain']}", file=sys.stderr, flush=True)
+        forms["hf_to_lf"] = form_hf_lf(lbm, 200)
+        print(f"[bench] HF to LF: {forms['hf_to_lf']}", file=sys.stderr, flush=True)
         out["system_forms"] = forms
 
     if not args.no_cpu_baseline:
