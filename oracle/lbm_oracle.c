@@ -61,7 +61,7 @@ typedef struct {
 typedef struct {
     int nq;
     int kind[OQMAX];      /* 0 energy E_R, 1 enstrophy Z_R, 2 mean-profile */
-    int filt[OQMAX];      /* 0 I, 1 B, 2 B^2, 3 B-B^2, 4 I-B */
+    int filt[OQMAX];      /* 0 I, 1 B, 2 B^2, 3 B-B^2, 4 I-B, 5 G_s, 6 L_s */
     int band[OQMAX];      /* band index for mean-profile QoIs */
     int nbands;
     double dmin, dmax;    /* band-centre range in wall distance */
@@ -75,6 +75,7 @@ typedef struct {
     uint64_t seed;
     int h;                /* LRS history length (eq. LRS); 0 uses C above */
     const double *Chist;  /* h > 0: the full ((2h+1) nq + 1) x nq matrix C (copied) */
+    int fs[OQMAX];        /* scale s of the kernel filters 5 (G_s) and 6 (L_s) */
 } orc_closure;
 
 typedef struct {
@@ -375,8 +376,83 @@ static void binomial(const Orc *o, const double *in, double *out, int ncomp)
             }
 }
 
-/* R u for the filter code filt. */
-static void apply_filter(const Orc *o, int filt, const double *in, double *out, int ncomp)
+/* ------------------------------------------------------------------ */
+/* Kernel filters of Sec. 4.1 as direct d-dimensional convolutions.     */
+/*  G_s (eq. gaussian): exp(-|r|^2 / (2 s^2)) on the cube                */
+/*      [-alpha s, alpha s]^d, alpha = 4 in 2-D and 2 in 3-D, divided by  */
+/*      its sum over that cube.                                           */
+/*  L_s (eq. laplace): L_1 places the biharmonic stencil               */
+/*      l = [1, -4, 6, -4, 1] along each axis through the origin (the    */
+/*      d axis terms add at the origin); L_s replaces every entry of L_1 */
+/*      by an s^d block of equal value (s odd, so the block grid stays   */
+/*      centred), and is scaled so that sum |L_s| = 2.                    */
+/* Zero padding on the wall axis, periodic wrap elsewhere.              */
+/* ------------------------------------------------------------------ */
+static int kernel_build(const Orc *o, int filt, int s, double **K)
+{
+    const int d = o->d;
+    int R;
+    if (filt == 5) R = (d == 2 ? 4 : 2) * s;
+    else R = (5 * s - 1) / 2;
+    const int W = 2 * R + 1, nz = d == 3 ? W : 1;
+    double *k = (double *)calloc((size_t)W * W * nz, sizeof(double));
+    static const double l[5] = {1, -4, 6, -4, 1};
+    double norm = 0;
+    for (int iz = 0; iz < nz; iz++)
+        for (int iy = 0; iy < W; iy++)
+            for (int ix = 0; ix < W; ix++) {
+                int r[3] = {ix - R, iy - R, d == 3 ? iz - R : 0};
+                double v = 0;
+                if (filt == 5) {
+                    double rr = 0;
+                    for (int a = 0; a < d; a++) rr += (double)r[a] * r[a];
+                    v = exp(-rr / (2.0 * s * s));
+                    norm += v;
+                } else {
+                    int blk[3];
+                    for (int a = 0; a < d; a++) blk[a] = (int)floor((double)(r[a] + R) / s) - 2;
+                    for (int a = 0; a < d; a++) {
+                        int on_axis = 1;
+                        for (int b = 0; b < d; b++) if (b != a && blk[b] != 0) on_axis = 0;
+                        if (on_axis) v += l[blk[a] + 2];
+                    }
+                    norm += fabs(v);
+                }
+                k[((size_t)iz * W + iy) * W + ix] = v;
+            }
+    const double scale = filt == 5 ? 1.0 / norm : 2.0 / norm;
+    for (long i = 0; i < (long)W * W * nz; i++) k[i] *= scale;
+    *K = k;
+    return R;
+}
+
+static void kernel_filter(const Orc *o, int filt, int s, const double *in, double *out, int ncomp)
+{
+    double *K;
+    const int R = kernel_build(o, filt, s, &K), W = 2 * R + 1;
+    const int rz = o->d == 3 ? R : 0;
+    const long N = o->N;
+    #pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < o->c.nz; z++)
+        for (int y = 0; y < o->c.ny; y++)
+            for (int x = 0; x < o->c.nx; x++) {
+                long xc = cell(o, x, y, z);
+                for (int k = 0; k < ncomp; k++) {
+                    double acc = 0;
+                    for (int oz = -rz; oz <= rz; oz++)
+                        for (int oy = -R; oy <= R; oy++)
+                            for (int ox = -R; ox <= R; ox++) {
+                                double wgt = K[((size_t)(oz + rz) * W + (oy + R)) * W + (ox + R)];
+                                if (wgt != 0.0) acc += wgt * at(o, in + k * N, x + ox, y + oy, z + oz);
+                            }
+                    out[k * N + xc] = acc;
+                }
+            }
+    free(K);
+}
+
+/* R u for the filter code filt (scale s for the kernel filters). */
+static void apply_filter(const Orc *o, int filt, int s, const double *in, double *out, int ncomp)
 {
     const size_t n = (size_t)ncomp * o->N;
     double *t1 = (double *)malloc(sizeof(double) * n);
@@ -391,13 +467,25 @@ static void apply_filter(const Orc *o, int filt, const double *in, double *out, 
     case 4: binomial(o, in, out, ncomp);                                 /* I - B */
         for (size_t k = 0; k < n; k++) out[k] = in[k] - out[k];
         break;
+    case 5: case 6: kernel_filter(o, filt, s, in, out, ncomp); break;    /* G_s, L_s */
     }
     free(t1);
 }
 
-void orc_filter(void *h, int filt, const double *in, double *out, int ncomp)
+void orc_filter(void *h, int filt, int s, const double *in, double *out, int ncomp)
 {
-    apply_filter((Orc *)h, filt, in, out, ncomp);
+    apply_filter((Orc *)h, filt, s, in, out, ncomp);
+}
+
+/* The d-dimensional kernel of G_s / L_s ((2R+1)^d, x fastest); returns R. */
+int orc_kernel(void *h, int filt, int s, double *out)
+{
+    double *K;
+    const Orc *o = (const Orc *)h;
+    const int R = kernel_build(o, filt, s, &K), W = 2 * R + 1;
+    if (out) memcpy(out, K, sizeof(double) * W * W * (o->d == 3 ? W : 1));
+    free(K);
+    return R;
 }
 
 /* ------------------------------------------------------------------ */
@@ -448,20 +536,20 @@ static void qoi_and_sens(const Orc *o, const orc_closure *cl, const double *bw,
     for (int k = 0; k < cl->nq; k++) {
         double *Vk = V ? V + (size_t)k * d * N : NULL;
         if (cl->kind[k] == 0) {
-            apply_filter(o, cl->filt[k], v, r1, d);
+            apply_filter(o, cl->filt[k], cl->fs[k], v, r1, d);
             double s = 0;
             for (long x = 0; x < N; x++)
                 for (int a = 0; a < d; a++) s += 0.5 * r1[a * N + x] * r1[a * N + x];
             q[k] = s;
-            if (Vk) apply_filter(o, cl->filt[k], r1, Vk, d);
+            if (Vk) apply_filter(o, cl->filt[k], cl->fs[k], r1, Vk, d);
         } else if (cl->kind[k] == 1) {
-            apply_filter(o, cl->filt[k], w, r1, nc);
+            apply_filter(o, cl->filt[k], cl->fs[k], w, r1, nc);
             double s = 0;
             for (long x = 0; x < N; x++)
                 for (int a = 0; a < nc; a++) s += 0.5 * r1[a * N + x] * r1[a * N + x];
             q[k] = s;
             if (Vk) {
-                apply_filter(o, cl->filt[k], r1, r2, nc);
+                apply_filter(o, cl->filt[k], cl->fs[k], r1, r2, nc);
                 curl_adjoint(o, r2, Vk);
             }
         } else {
