@@ -86,12 +86,23 @@ typedef struct {
 } lbm_config;
 
 enum { LBM_QOI_E = 0, LBM_QOI_Z = 1, LBM_QOI_MP = 2 };
-/* Filters R of the scale-aware QoIs: I, B, B^2, B - B^2, I - B. */
-enum { LBM_FILT_ID = 0, LBM_FILT_B = 1, LBM_FILT_B2 = 2, LBM_FILT_BMID = 3, LBM_FILT_IMB = 4 };
+/* Filters R of the scale-aware QoIs (Sec. 4.1), all with zero padding on
+ * the wall axis:
+ *  - the compact binomial family I, B, B^2, B - B^2, I - B, with
+ *    B = (x)_a [1,2,1]/4;
+ *  - the kernel filters of eq. gaussian and eq. laplace: GAUSS, the Gaussian
+ *    of standard deviation s truncated to [-alpha s, alpha s]^d (alpha = 4 in
+ *    2-D, 2 in 3-D) and normalised to unit sum, radius alpha s <= 12; LAPL,
+ *    the biharmonic cross [1,-4,6,-4,1] along each axis dilated by s (odd)
+ *    and normalised to sum |L_s| = 2, radius (5s-1)/2 <= 12.
+ * A closure uses one family for all its E and Z QoIs (I belongs to both). */
+enum { LBM_FILT_ID = 0, LBM_FILT_B = 1, LBM_FILT_B2 = 2, LBM_FILT_BMID = 3, LBM_FILT_IMB = 4,
+       LBM_FILT_GAUSS = 5, LBM_FILT_LAPL = 6 };
 typedef struct {
     int kind;           /* LBM_QOI_E, LBM_QOI_Z, LBM_QOI_MP (MP needs walls_y = 1) */
     int filter;         /* for E and Z */
     int band;           /* for MP: band index in [0, nbands) */
+    int scale;          /* s of LBM_FILT_GAUSS / LBM_FILT_LAPL */
 } lbm_qoi_spec;
 
 enum { LBM_CLOSURE_OFF = 0, LBM_CLOSURE_TRACK = 1, LBM_CLOSURE_LRS = 2 };

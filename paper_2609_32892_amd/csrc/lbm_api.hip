@@ -60,6 +60,7 @@ void filter_poly(int f, double r[3])
 struct ClosureShape {
     int nq = 0, nsa = 0, nmp = 0, jv = 0, jw = 0, has_z = 0, has_e = 0, nbands = 0;
     int h = 0, nhc = 0;   // LRS history length; k_sum workgroups of its product
+    int kf = 0;           // E/Z QoIs use the kernel filters (materialised sensitivities)
     int npart() const { return nsa + nsa * (nsa + 1) / 2 + nmp * (1 + nsa); }
 };
 
@@ -89,11 +90,26 @@ int closure_shape(const lbm_config* cfg, const lbm_closure* cl, ClosureShape* ou
     }
     s.nq = cl->nq;
     s.nbands = cl->nbands;
+    bool binom = false;
+    for (int k = 0; k < cl->nq; ++k) {
+        const lbm_qoi_spec& q = cl->q[k];
+        if (q.kind != LBM_QOI_E && q.kind != LBM_QOI_Z) continue;
+        if (q.filter < LBM_FILT_ID || q.filter > LBM_FILT_LAPL) return fail(LBM_EINVAL, "closure: QoI %d bad filter", k);
+        if (q.filter == LBM_FILT_GAUSS || q.filter == LBM_FILT_LAPL) {
+            const int d = cfg->lattice == LBM_D2Q9 ? 2 : 3;
+            const int rad = q.filter == LBM_FILT_GAUSS ? (d == 2 ? 4 : 2) * q.scale : (5 * q.scale - 1) / 2;
+            if (q.scale < 1 || (q.filter == LBM_FILT_LAPL && q.scale % 2 == 0) || rad > kMaxRad)
+                return fail(LBM_EINVAL, "closure: QoI %d kernel-filter scale (odd for LAPL; radius at most %d)", k,
+                            kMaxRad);
+            s.kf = 1;
+        } else if (q.filter != LBM_FILT_ID)
+            binom = true;
+    }
+    if (s.kf && binom) return fail(LBM_EINVAL, "closure: binomial and kernel filters cannot be mixed");
     for (int k = 0; k < cl->nq; ++k) {
         const lbm_qoi_spec& q = cl->q[k];
         if (q.kind == LBM_QOI_E || q.kind == LBM_QOI_Z) {
-            if (q.filter < LBM_FILT_ID || q.filter > LBM_FILT_IMB) return fail(LBM_EINVAL, "closure: QoI %d bad filter", k);
-            const int p = 2 * filter_deg(q.filter);
+            const int p = s.kf ? 0 : 2 * filter_deg(q.filter);
             if (q.kind == LBM_QOI_E) { s.jv = std::max(s.jv, p); s.has_e = 1; }
             else { s.jw = std::max(s.jw, p); s.has_z = 1; }
             s.nsa++;
@@ -136,7 +152,7 @@ int check_config(const lbm_config* c)
 
 struct Plan {
     size_t member, param, ctl, recs, g0, g1, fprof, vn, part_stats, part_diag, work1, workm;
-    size_t rho, vs, P, W, Cf, part_to, bandw, cmp, workr, workb, sums, works, hpart;
+    size_t rho, vs, P, W, Cf, part_to, bandw, cmp, workr, workb, sums, works, hpart, kV, kT, ktaps;
     size_t total;
     int N, D, NC, Q, esz, nb1, nbx2, cpt2, nbr, nbb, nbs, zc, btx, rec_cap;
     ClosureShape cap;
@@ -204,6 +220,12 @@ void make_plan(const lbm_config* c, const ClosureShape& cs, Plan* p)
         P.sums = take(sizeof(double) * (4 + cs.npart()));
         P.works = take(sizeof(int2) * P.nbs);
         P.hpart = take(sizeof(double) * kMaxQ * std::max(cs.nhc, 1));
+        if (cs.kf) {
+            // kernel filters: V_s [nsa][D][N], four [3][N] work fields, tap tables
+            P.kV = take(e * (size_t)cs.nsa * P.D * N);
+            P.kT = take(e * 4 * 3 * N);
+            P.ktaps = take(e * kMaxSA * 3 * (2 * kMaxRad + 1));
+        }
     }
     P.total = o;
     *p = P;
@@ -307,6 +329,7 @@ struct lbm_ctx {
     size_t qref_cap = 0;
     double* chist_dev = nullptr;   // history rows of the LRS matrix
     size_t chist_cap = 0;
+    std::vector<KPass> kprog;      // kernel-filter sensitivity program (device addresses)
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     long gver[2] = {-1, -1};
     int gchunk = 32;
@@ -350,9 +373,12 @@ LaunchGroup ctx_group(const lbm_ctx* c)
     g.any_z = c->cur.has_z;
     g.maxpow = std::max(c->cur.jv, c->cur.jw);
     g.maxsa = c->cur.nsa;
-    g.npass = std::max(c->cur.jv, c->cur.has_z ? c->cur.jw + 1 : 0);
+    g.npass = c->cur.kf ? 0 : std::max(c->cur.jv, c->cur.has_z ? c->cur.jw + 1 : 0);
     g.btx = c->plan.btx;
     add_pass_masks(c, g);
+    g.kf = c->cur.kf;
+    g.kprog = c->kprog.data();
+    g.nkprog = (int)c->kprog.size();
     g.mems = c->dm;
     g.work1 = (const int2*)(c->arena + c->plan.work1);
     g.nb1 = c->plan.nb1;
@@ -383,6 +409,94 @@ void drop_graphs(lbm_ctx* c)
     }
 }
 
+// The kernel filters as sums of separable terms (Sec. 4.1): G_s is the
+// product of the 1-D truncated Gaussian g (radius alpha s, alpha = 4 in 2-D
+// and 2 in 3-D, normalised so that its cube sums to one); L_s is the sum over
+// the axes a of (dilated biharmonic l_s along a) x (box of width s across a),
+// scaled by 2 / sum |L_s| = 1 / (8 d s^d) (the d arms share the centre
+// block, where the kernel is 6 d; each arm adds 10 s^d in absolute value).
+// The identity is one term with unit taps.  Writes the tap tables into the
+// arena and the pass program: for E, V = R(R v*); for Z, V = curl^T R(R w).
+int build_kprog(lbm_ctx* c, const lbm_closure* cl, const ClosureShape& cs)
+{
+    const int D = c->plan.D, NC = c->plan.NC, W = 2 * kMaxRad + 1;
+    const size_t N = c->plan.N, e = c->plan.esz;
+    char* A = c->arena;
+    std::vector<double> taps((size_t)kMaxSA * 3 * W, 0.0);
+    int ntap = 0;
+    auto add = [&](const std::vector<double>& t) -> const void* {
+        std::copy(t.begin(), t.end(), taps.begin() + (size_t)ntap * W);
+        return A + c->plan.ktaps + (size_t)(ntap++) * W * e;
+    };
+    struct Term { double coef; const void* tap[3]; int rad[3]; };
+    c->kprog.clear();
+    char* T1 = A + c->plan.kT;
+    char* T2 = T1 + 3 * N * e;
+    char* Y1 = T2 + 3 * N * e;
+    char* Y2 = Y1 + 3 * N * e;
+    int isa = 0;
+    for (int k = 0; k < cl->nq; ++k) {
+        const lbm_qoi_spec& q = cl->q[k];
+        if (q.kind == LBM_QOI_MP) continue;
+        std::vector<Term> terms;
+        const int sc = q.scale;
+        if (q.filter == LBM_FILT_GAUSS) {
+            const int r = (D == 2 ? 4 : 2) * sc;
+            std::vector<double> g(2 * r + 1);
+            double sum = 0;
+            for (int i = -r; i <= r; ++i) sum += g[i + r] = std::exp(-(double)i * i / (2.0 * sc * sc));
+            for (double& v : g) v /= sum;
+            const void* tp = add(g);
+            terms.push_back({1.0, {tp, tp, tp}, {r, r, r}});
+        } else if (q.filter == LBM_FILT_LAPL) {
+            static const double l5[5] = {1, -4, 6, -4, 1};
+            const int rl = (5 * sc - 1) / 2, rb = (sc - 1) / 2;
+            std::vector<double> l(2 * rl + 1), b(2 * rb + 1, 1.0);
+            for (int i = 0; i < 5 * sc; ++i) l[i] = l5[i / sc];
+            const void* tl = add(l);
+            const void* tb = add(b);
+            double sd = 1;
+            for (int a = 0; a < D; ++a) sd *= sc;
+            const double coef = 1.0 / (8.0 * D * sd);
+            for (int a = 0; a < D; ++a) {
+                Term t{coef, {tb, tb, tb}, {rb, rb, rb}};
+                t.tap[a] = tl;
+                t.rad[a] = rl;
+                terms.push_back(t);
+            }
+        } else {
+            const void* t1 = add(std::vector<double>{1.0});
+            terms.push_back({1.0, {t1, t1, t1}, {0, 0, 0}});
+        }
+        const bool E = q.kind == LBM_QOI_E;
+        const int nc = E ? D : NC;
+        const void* X = E ? (const void*)(A + c->plan.vs) : (const void*)(A + c->plan.W);
+        char* Vs = A + c->plan.kV + (size_t)isa * D * N * e;
+        for (int app = 0; app < 2; ++app) {
+            const void* src = app == 0 ? X : (const void*)Y1;
+            void* dst = app == 0 ? (void*)Y1 : (E ? (void*)Vs : (void*)Y2);
+            for (size_t t = 0; t < terms.size(); ++t) {
+                const Term& tm = terms[t];
+                const int acc = t > 0;
+                c->kprog.push_back({0, 0, nc, tm.rad[0], 0, 1.0, tm.tap[0], src, T1});
+                if (D == 2) {
+                    c->kprog.push_back({0, 1, nc, tm.rad[1], acc, tm.coef, tm.tap[1], T1, dst});
+                } else {
+                    c->kprog.push_back({0, 1, nc, tm.rad[1], 0, 1.0, tm.tap[1], T1, T2});
+                    c->kprog.push_back({0, 2, nc, tm.rad[2], acc, tm.coef, tm.tap[2], T2, dst});
+                }
+            }
+        }
+        if (!E) c->kprog.push_back({1, 0, nc, 0, 0, 1.0, nullptr, Y2, Vs});
+        isa++;
+    }
+    (void)cs;
+    // tap tables in the run's element type
+    if (e == 8) return upload(c, A + c->plan.ktaps, taps.data(), sizeof(double) * taps.size());
+    std::vector<float> tf(taps.begin(), taps.end());
+    return upload(c, A + c->plan.ktaps, tf.data(), sizeof(float) * tf.size());
+}
+
 // Build DevParam from a closure (host side) and upload it.
 int apply_closure(lbm_ctx* c, const lbm_closure* cl)
 {
@@ -392,7 +506,8 @@ int apply_closure(lbm_ctx* c, const lbm_closure* cl)
     if (cl) {
         const ClosureShape& cap = c->plan.cap;
         if (!c->has_to || cs.nsa > cap.nsa || cs.jv > cap.jv || (cs.has_z && (!cap.has_z || cs.jw > cap.jw)) ||
-            cs.npart() > cap.npart() || cs.nbands > std::max(cap.nbands, 1) || cs.nhc > cap.nhc)
+            cs.npart() > cap.npart() || cs.nbands > std::max(cap.nbands, 1) || cs.nhc > cap.nhc ||
+            (cs.kf && !cap.kf))
             return fail(LBM_ENOMEM, "closure does not fit the workspace planned at creation");
         if (cs.h > 0 && cl->spinup < c->host_step + cs.h)
             return fail(LBM_EINVAL, "closure: spinup must be at least the step count plus the history length");
@@ -432,6 +547,11 @@ int apply_closure(lbm_ctx* c, const lbm_closure* cl)
             }
         }
         const int nq = cl->nq;
+        p.kf = cs.kf;
+        if (cs.kf) {
+            rc = build_kprog(c, cl, cs);
+            if (rc) return rc;
+        }
         if (cl->mode == LBM_CLOSURE_LRS) {
             // rows of z*^n and the bias here; the history rows (z^{n-r} and
             // z*^{n-r}, r = 1..h) to the history buffer
@@ -624,6 +744,7 @@ int lbm_create(const lbm_config* cfg, const lbm_closure* closure, void* dev_aren
         m.cmp = (double*)(A + plan.cmp);
         m.sums = (double*)(A + plan.sums);
         m.hpart = (double*)(A + plan.hpart);
+        if (plan.cap.kf) m.kV = A + plan.kV;
     }
     c->dm = (DevMember*)(A + plan.member);
     // host tables
@@ -996,13 +1117,13 @@ static int batch_build(lbm_batch* b)
     batch_free_dev(b);
     const int n = (int)b->mem.size();
     // group members by kernel kind
-    struct Key { int lat, prec, sub, mode, sab, btx; };
+    struct Key { int lat, prec, sub, mode, sab, btx, kfm; };   // kfm: kernel-filter member (own group)
     std::vector<Key> keys;
     std::vector<std::vector<int>> gm;
     for (int i = 0; i < n; ++i) {
         const lbm_ctx* c = b->mem[i];
         Key k{c->cfg.lattice, c->cfg.precision, c->cfg.substrate, c->mode(), c->cur.nsa <= 2 ? 2 : (c->cur.nsa <= 6 ? 6 : 8),
-              c->plan.btx};
+              c->plan.btx, c->mode() == 2 && c->cur.kf ? i : -1};
         int gi = -1;
         for (size_t j = 0; j < keys.size(); ++j)
             if (!memcmp(&keys[j], &k, sizeof k)) gi = (int)j;
@@ -1079,6 +1200,12 @@ static int batch_build(lbm_batch* b)
             g.maxsa = std::max(g.maxsa, c->cur.nsa);
             g.npass = std::max(g.npass, std::max(c->cur.jv, c->cur.has_z ? c->cur.jw + 1 : 0));
             add_pass_masks(c, g);
+            if (keys[gi].kfm >= 0) {
+                g.kf = 1;
+                g.npass = 0;
+                g.kprog = c->kprog.data();
+                g.nkprog = (int)c->kprog.size();
+            }
         }
         g.mems = b->dmem;
         g.work1 = b->dwork + offs[gi].w1;

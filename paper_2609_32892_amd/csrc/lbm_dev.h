@@ -21,13 +21,14 @@ constexpr int kBinTXW = 64;     // the wide tile (64 x 4) of the one-pass binomi
 constexpr int kBinZCMax = 16;   // most z planes per workgroup chosen automatically (3-D)
 constexpr int kHistRows = 512;   // LRS history rows (x entries) per k_sum workgroup
 constexpr int kMaxHistChunks = 64;                 // so 2 h nq <= 32768
+constexpr int kMaxRad = 12;     // kernel filters: largest radius of a 1-D factor
 
 // Constant closure parameters (written by the host at set_closure).
 struct DevParam {
     int nq, mode, nsa, nmp;
     int nbands, have_scale, nref, jv;  // jv: highest power of B applied to v
     int jw, has_z, has_e, h;           // jw: highest power applied to curl v; h: LRS history length
-    int nhc, pad1;                     // workgroups of the history product (k_sum)
+    int nhc, kf;                       // workgroups of the history product (k_sum); kernel filters
     long long spinup;
     unsigned long long seed;
     int sa_slot[kMaxSA];               // user index of each E/Z QoI
@@ -60,6 +61,8 @@ struct DevCtl {
     float cwf[kMaxPow + 1];
     double pad[1];
     double lrs_e[kMaxQ];               // mu + L xi of the current step's LRS draw
+    double bsa[kMaxSA];                // beta of each E/Z QoI (kernel-filter dv build)
+    float bsaf[kMaxSA];
 };
 
 struct DevMember {
@@ -88,6 +91,7 @@ struct DevMember {
     double* fprof;                     // body force F_x(y) [ny]
     double* sums;                      // [4 + npart]: reduced statistics and TO partials
     double* hpart;                     // [nhc][kMaxQ]: LRS history product per k_sum workgroup
+    void* kV;                          // kernel filters: V_s = R(R v*) or curl^T R(R w), [nsa][D][N]
 };
 
 #ifdef __HIP_DEVICE_COMPILE__

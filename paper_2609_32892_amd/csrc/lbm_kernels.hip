@@ -747,7 +747,7 @@ template <typename T> __device__ __forceinline__ T coef_cw(KCtl* c, int j);
 template <> __device__ __forceinline__ float coef_cw<float>(KCtl* c, int j) { return c->cwf[j]; }
 template <> __device__ __forceinline__ double coef_cw<double>(KCtl* c, int j) { return c->cw[j]; }
 
-template <int LAT, typename T, int MAXSA>
+template <int LAT, typename T, int MAXSA, bool KF>
 __device__ __forceinline__ void cell_sens(KMember& m, KParam* prm, int x, int y, int z,
                                           int cell, T (&pv)[kMaxPow + 1][Lat<LAT>::D], T (&V)[MAXSA][Lat<LAT>::D],
                                           double (&qd)[MAXSA])
@@ -756,6 +756,26 @@ __device__ __forceinline__ void cell_sens(KMember& m, KParam* prm, int x, int y,
     constexpr int D = L::D, NC = L::NC;
     const int nsa = prm->nsa, jv = prm->jv, jw = prm->jw;
     const size_t sN = (size_t)m.N;
+    if constexpr (KF) {
+        // kernel filters: the sensitivities V_s are materialised; both E and Z
+        // QoIs are 1/2 <v*, V_s> (R self-adjoint, curl^T the adjoint of curl)
+        const T* __restrict__ vs = (const T*)m.vs;
+        const T* __restrict__ kV = (const T*)m.kV;
+#pragma unroll
+        for (int a = 0; a < D; ++a) pv[0][a] = vs[a * sN + cell];
+#pragma unroll
+        for (int s2 = 0; s2 < MAXSA; ++s2) {
+            const int sc = s2 < nsa ? s2 : nsa - 1;
+            qd[s2] = 0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const T vv = kV[((size_t)sc * D + a) * sN + cell];
+                V[s2][a] = s2 < nsa ? vv : T(0);
+                qd[s2] += 0.5 * (double)(pv[0][a] * V[s2][a]);
+            }
+        }
+        return;
+    }
     const T* __restrict__ P = (const T*)m.P;
     const T* __restrict__ W = (const T*)m.W;
     // Every load is unconditional, with the power clamped to the highest one
@@ -833,7 +853,7 @@ __device__ __forceinline__ void cell_sens(KMember& m, KParam* prm, int x, int y,
 // Partial layout: q_sa[nsa], G_sa[nsa(nsa+1)/2], then (with MP QoIs)
 // U = sum v*_x and P_s = sum V_s,x.
 // ---------------------------------------------------------------------------
-template <int LAT, typename T, int MAXSA>
+template <int LAT, typename T, int MAXSA, bool KF>
 __global__ __launch_bounds__(kBlock) void k_reduce(const DevMember* __restrict__ mems, const int2* __restrict__ work)
 {
     using L = Lat<LAT>;
@@ -860,7 +880,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const DevMember* __restrict__
         T pv[kMaxPow + 1][D];
         T V[MAXSA][D];
         double qd[MAXSA];
-        cell_sens<LAT, T, MAXSA>(m, prm, x, y, z, cell, pv, V, qd);
+        cell_sens<LAT, T, MAXSA, KF>(m, prm, x, y, z, cell, pv, V, qd);
 #pragma unroll
         for (int s = 0; s < MAXSA; ++s) acc[s] += qd[s];
         int g = 0;
@@ -1256,6 +1276,11 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
     }
     __syncthreads();
     // (g) dv coefficients, record, counters
+    if (tid < kMaxSA) {
+        const double b = tid < nsa ? beta[saslot[tid]] : 0.0;
+        ctl->bsa[tid] = b;
+        ctl->bsaf[tid] = (float)b;
+    }
     if (tid <= kMaxPow) {
         double a = 0, b = 0;
         for (int s = 0; s < nsa; ++s) {
@@ -1308,7 +1333,11 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
 // K4: dv = sum_j cv_j B^j v* + sum_j cw_j C_j + e_x cmp(y), then
 // delta f_i = feq_i(rho, v* + dv) - feq_i(rho, v*) added in place to the
 // cell's predictor populations (the buffer k_step of this step wrote).
-template <int LAT, typename T>
+template <typename T> __device__ __forceinline__ T coef_bsa(KCtl* c, int s);
+template <> __device__ __forceinline__ float coef_bsa<float>(KCtl* c, int s) { return c->bsaf[s]; }
+template <> __device__ __forceinline__ double coef_bsa<double>(KCtl* c, int s) { return c->bsa[s]; }
+
+template <int LAT, typename T, bool KF>
 __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ mems, const int2* __restrict__ work,
                                                   int flip)
 {
@@ -1325,9 +1354,30 @@ __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ 
     KCtl* ctl = kc(m.ctl);
     const int jv = prm->jv, jw = prm->jw;
     const bool hz = prm->has_z;
+    const T* __restrict__ vsp = (const T*)m.vs;
+    T out[3] = {0, 0, 0};
+    T vs[3] = {0, 0, 0};
+    if constexpr (KF) {
+        // dv = sum_s beta_s V_s (clamped loads; beta_s = 0 past nsa)
+        const int nsa = prm->nsa;
+        const T* __restrict__ kV = (const T*)m.kV;
+#pragma unroll
+        for (int a = 0; a < D; ++a) vs[a] = vsp[a * sN + cell];
+        T kv[kMaxSA][D];
+#pragma unroll
+        for (int s2 = 0; s2 < kMaxSA; ++s2)
+#pragma unroll
+            for (int a = 0; a < D; ++a) kv[s2][a] = kV[((size_t)(s2 < nsa ? s2 : nsa - 1) * D + a) * sN + cell];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            T acc = 0;
+#pragma unroll
+            for (int s2 = 0; s2 < kMaxSA; ++s2) acc += coef_bsa<T>(ctl, s2) * kv[s2][a];
+            out[a] = acc;
+        }
+    } else {
     // Unconditional loads with the power clamped to the highest one stored:
     // cv_j (cw_j) is zero above jv (jw), so the extra terms add exact zeros.
-    const T* __restrict__ vsp = (const T*)m.vs;
     T fv[kMaxPow + 1][D], fc[kMaxPow + 1][D];
 #pragma unroll
     for (int jj = 0; jj <= kMaxPow; ++jj) {
@@ -1340,7 +1390,6 @@ __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ 
             fc[jj][a] = srcc[a * sN + cell];
         }
     }
-    T out[3] = {0, 0, 0};
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         T s = coef_cv<T>(ctl, 0) * fv[0][a];
@@ -1357,13 +1406,13 @@ __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ 
             out[a] += sacc;
         }
     }
+#pragma unroll
+    for (int a = 0; a < D; ++a) vs[a] = fv[0][a];
+    }
     if (prm->nmp > 0) out[0] += T(m.cmp[y]);
     // the SGS change of the predictor populations
     const T rho = T(1) + ((const T*)m.rho)[cell];
     PendRec<T> r;
-    T vs[3] = {0, 0, 0};
-#pragma unroll
-    for (int a = 0; a < D; ++a) vs[a] = fv[0][a];
     const T bx = T(2) * vs[0] + out[0], by = T(2) * vs[1] + out[1], bz = D == 3 ? T(2) * vs[2] + out[2] : T(0);
     r.u.x = rho * out[0];
     r.u.y = rho * out[1];
@@ -1380,6 +1429,70 @@ __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ 
     for (int i = 0; i < L::Q; ++i) gi[i] = ld_at(g + (size_t)i * sN, (unsigned)cell);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) st_at(g + (size_t)i * sN, (unsigned)cell, gi[i] + pend_df<LAT, T>(r, i, T(1)));
+}
+
+// ---------------------------------------------------------------------------
+// Kernel filters (Sec. 4.1, eq. gaussian and eq. laplace): each filter is a
+// sum of separable terms, applied as 1-D passes along x, y and z.
+// K2k: one pass, dst = coef * sum_r taps[r] src(. + r e_axis) (or dst +=),
+// with periodic wrap, or zero padding on the wall axis.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_kpass(const DevMember* __restrict__ mems, const int2* __restrict__ work,
+                                                  int axis, int ncomp, int radius, int acc, T coef,
+                                                  const T* __restrict__ taps, const T* __restrict__ src,
+                                                  T* __restrict__ dst)
+{
+    const int2 wk = work[blockIdx.x];
+    KMember& m = *kc(mems + wk.x);
+    const int N = m.N, nx = m.nx, ny = m.ny;
+    const int cell = wk.y * kBlock + threadIdx.x;
+    if (cell >= N) return;
+    const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
+    const int n = axis == 0 ? nx : (axis == 1 ? ny : m.nz);
+    const int pos = axis == 0 ? x : (axis == 1 ? y : z);
+    const int stride = axis == 0 ? 1 : (axis == 1 ? nx : nx * ny);
+    const bool pad = axis == 1 && m.walls;
+    for (int c = 0; c < ncomp; ++c) {
+        const T* sc = src + (size_t)c * N + (cell - (size_t)pos * stride);   // start of this cell's line
+        T sum = 0;
+        for (int r = -radius; r <= radius; ++r) {
+            int p = pos + r;
+            if (pad) {
+                if (p < 0 || p >= n) continue;
+            } else {
+                p %= n;
+                if (p < 0) p += n;
+            }
+            sum += taps[r + radius] * sc[(size_t)p * stride];
+        }
+        T* d = dst + (size_t)c * N + cell;
+        *d = acc ? *d + coef * sum : coef * sum;
+    }
+}
+
+// K2k': V = curl^T psi (2-D: (D_y psi, -D_x psi); 3-D: curl psi), central
+// differences with the wall padding of curl_at.
+template <int LAT, typename T>
+__global__ __launch_bounds__(kBlock) void k_curlT(const DevMember* __restrict__ mems, const int2* __restrict__ work,
+                                                  const T* __restrict__ src, T* __restrict__ dst)
+{
+    using L = Lat<LAT>;
+    const int2 wk = work[blockIdx.x];
+    KMember& m = *kc(mems + wk.x);
+    const int N = m.N, nx = m.nx, ny = m.ny, nz = m.nz;
+    const int cell = wk.y * kBlock + threadIdx.x;
+    if (cell >= N) return;
+    const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
+    if constexpr (L::D == 2) {
+        dst[cell] = T(0.5) * (fld(src, x, y + 1, z, nx, ny, nz, m.walls) - fld(src, x, y - 1, z, nx, ny, nz, m.walls));
+        dst[(size_t)N + cell] =
+            -T(0.5) * (fld(src, x + 1, y, z, nx, ny, nz, m.walls) - fld(src, x - 1, y, z, nx, ny, nz, m.walls));
+    } else {
+        T w[3];
+        curl_at<3, T>(src, (size_t)N, x, y, z, nx, ny, nz, m.walls, w);
+        for (int a = 0; a < 3; ++a) dst[(size_t)a * N + cell] = w[a];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1631,7 +1744,18 @@ to_chain:
     if (g.mode == 2) {
         if (g.any_z) hipLaunchKernelGGL((k_curl<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1);
         mark(2);
-        for (int j = 1; j <= g.npass; ++j) {
+        if (g.kf) {
+            for (int k = 0; k < g.nkprog; ++k) {
+                const KPass& p = g.kprog[k];
+                if (p.op == 0)
+                    hipLaunchKernelGGL(k_kpass<T>, dim3(g.nb1), blk, 0, st, g.mems, g.work1, p.axis, p.ncomp, p.radius,
+                                       p.acc, (T)p.coef, (const T*)p.taps, (const T*)p.src, (T*)p.dst);
+                else
+                    hipLaunchKernelGGL((k_curlT<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, (const T*)p.src,
+                                       (T*)p.dst);
+            }
+        }
+        for (int j = 1; j <= (g.kf ? 0 : g.npass); ++j) {
 #define LBM_BINOM(TXV, CHV) hipLaunchKernelGGL((k_binom<LAT, T, TXV, CHV>), dim3(g.nbb), blk, 0, st, g.mems, g.workb, j)
             const int ch = g.bmask[j - 1];
             if (g.btx == kBinTXW) {
@@ -1642,17 +1766,25 @@ to_chain:
 #undef LBM_BINOM
         }
         mark(3);
-        if (g.maxsa <= 2)
-            hipLaunchKernelGGL((k_reduce<LAT, T, 2>), dim3(g.nbr), blk, 0, st, g.mems, g.workr);
-        else if (g.maxsa <= 6)
-            hipLaunchKernelGGL((k_reduce<LAT, T, 6>), dim3(g.nbr), blk, 0, st, g.mems, g.workr);
-        else
-            hipLaunchKernelGGL((k_reduce<LAT, T, kMaxSA>), dim3(g.nbr), blk, 0, st, g.mems, g.workr);
+#define LBM_REDUCE(KFV)                                                                                      \
+    do {                                                                                                     \
+        if (g.maxsa <= 2)                                                                                    \
+            hipLaunchKernelGGL((k_reduce<LAT, T, 2, KFV>), dim3(g.nbr), blk, 0, st, g.mems, g.workr);        \
+        else if (g.maxsa <= 6)                                                                               \
+            hipLaunchKernelGGL((k_reduce<LAT, T, 6, KFV>), dim3(g.nbr), blk, 0, st, g.mems, g.workr);        \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_reduce<LAT, T, kMaxSA, KFV>), dim3(g.nbr), blk, 0, st, g.mems, g.workr);   \
+    } while (0)
+        if (g.kf) LBM_REDUCE(true); else LBM_REDUCE(false);
+#undef LBM_REDUCE
         mark(4);
         hipLaunchKernelGGL(k_sum, dim3(g.nbs), blk, 0, st, g.mems, g.works);
         hipLaunchKernelGGL(k_solve, dim3(g.nmem), blk, 0, st, g.mems, g.workm);
         mark(5);
-        if (!g.probe) hipLaunchKernelGGL((k_apply<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip);
+        if (!g.probe) {
+            if (g.kf) hipLaunchKernelGGL((k_apply<LAT, T, true>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip);
+            else hipLaunchKernelGGL((k_apply<LAT, T, false>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip);
+        }
         mark(6);
     } else if (g.mode == 1) {
         hipLaunchKernelGGL((k_diag<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1);

@@ -6,6 +6,18 @@
 
 namespace lbm {
 
+// One step of a kernel-filter closure's sensitivity program: a 1-D
+// convolution along an axis (op 0; periodic wrap or zero padding on the wall
+// axis; dst = coef * result, or dst += coef * result if acc), or the adjoint
+// curl curl^T (op 1).  Pointers are device addresses in the member's arena.
+struct KPass {
+    int op, axis, ncomp, radius, acc;
+    double coef;
+    const void* taps;   // 2 radius + 1 values, element type of the run
+    const void* src;
+    void* dst;
+};
+
 // One launch per kernel phase covers every member of a group: members share
 // lattice, precision, substrate and mode, and are mapped to workgroups by
 // the work tables.
@@ -27,6 +39,9 @@ struct LaunchGroup {
     int nmem;
     int probe;          // TO mode only: the QoI chain of the field already in v* (no
                         // stream-collide, no apply); see lbm_project_qoi
+    int kf;             // kernel-filter closure (one member per group): kprog replaces the
+    const KPass* kprog; // binomial passes
+    int nkprog;
 };
 
 enum { OP_INIT = 0, OP_GET_POP = 1, OP_SET_POP = 2, OP_STREAM = 3 };

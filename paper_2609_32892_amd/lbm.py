@@ -22,6 +22,14 @@ BGK, SMAGORINSKY, WALE = 0, 1, 2
 FORCE_NONE, FORCE_SIN_Y, FORCE_CONST_X = 0, 1, 2
 QOI_E, QOI_Z, QOI_MP = 0, 1, 2
 FILT = {"I": 0, "B": 1, "B2": 2, "BMID": 3, "IMB": 4}
+KFILT = {"G": 5, "L": 6}   # kernel filters with a scale: "G3" = G_3, "L1" = L_1
+
+
+def filter_code(name):
+    """(filter enum, scale) of a filter name: I, B, B2, BMID, IMB, G<s>, L<s>."""
+    if name in FILT:
+        return FILT[name], 0
+    return KFILT[name[0]], int(name[1:])
 MODE = {"off": 0, "track": 1, "lrs": 2}
 PRECISION = {"fp32": FP32_SHIFTED, "fp64": FP64, "fp32_plain": FP32_PLAIN}
 
@@ -41,7 +49,7 @@ class Config(ct.Structure):
 
 
 class QoiSpec(ct.Structure):
-    _fields_ = [("kind", ct.c_int), ("filter", ct.c_int), ("band", ct.c_int)]
+    _fields_ = [("kind", ct.c_int), ("filter", ct.c_int), ("band", ct.c_int), ("scale", ct.c_int)]
 
 
 class Closure(ct.Structure):
@@ -201,7 +209,8 @@ class ClosureSpec:
         self.nq = nq
         self._q = (QoiSpec * nq)()
         for k, (kind, filt, band) in enumerate(qois):
-            self._q[k] = QoiSpec({"E": QOI_E, "Z": QOI_Z, "MP": QOI_MP}[kind], FILT[filt], band)
+            code, sc = filter_code(filt)
+            self._q[k] = QoiSpec({"E": QOI_E, "Z": QOI_Z, "MP": QOI_MP}[kind], code, band, sc)
         arr = lambda a, n: None if a is None else np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(n))
         self._C = arr(C, ((2 * h + 1) * nq + 1) * nq)
         self._mu = arr(mu, nq)

@@ -102,3 +102,22 @@ def test_history_closure_validation(lbm):
     big = lbm.make_config(nx=16, ny=16, rec_cap=4096)
     assert L.lbm_required_bytes(ct.byref(big), ct.byref(spec(1024).c)) > 0          # 2 h nq = 4096
     assert L.lbm_required_bytes(ct.byref(big), ct.byref(spec(1025).c)) == 0         # h > LBM_MAX_HIST
+
+
+def test_kernel_filter_closure_validation(lbm):
+    """Closures with the kernel filters G_s / L_s (Sec. 4.1) the library
+    accepts and rejects."""
+    L = lbm.lib()
+    c3 = lbm.make_config(lattice=lbm.D3Q19, nx=24, ny=16, nz=16, walls_y=1)
+    ok = lbm.ClosureSpec([(k, f, 0) for f in ("G3", "L3", "L1") for k in ("E", "Z")] + [("MP", "I", 0)],
+                         nbands=1, dmin=0.5, dmax=8)
+    assert L.lbm_required_bytes(ct.byref(c3), ct.byref(ok.c)) > 0
+    for bad in ([("E", "G3", 0), ("Z", "B", 0)],     # families mixed
+                [("E", "L2", 0)],                     # even dilation
+                [("E", "G7", 0)],                     # radius 14 > 12
+                [("Z", "L7", 0)]):                    # radius 17 > 12
+        assert L.lbm_required_bytes(ct.byref(c3), ct.byref(lbm.ClosureSpec(bad).c)) == 0
+        assert L.lbm_last_error()
+    c2 = lbm.make_config(nx=32, ny=32)
+    assert L.lbm_required_bytes(ct.byref(c2), ct.byref(lbm.ClosureSpec([("E", "G3", 0)]).c)) > 0   # radius 12
+    assert L.lbm_required_bytes(ct.byref(c2), ct.byref(lbm.ClosureSpec([("E", "G4", 0)]).c)) == 0  # radius 16
