@@ -221,6 +221,32 @@ def form_history(lbm, w, steps, h=500):
     return out
 
 
+def form_kernel_filters(lbm, w, steps):
+    """The paper's own 3-D QoI set (Sec. 7: {E, Z} x {G_3, L_3, L_1} plus the
+    six mean-profile bands) on the headline channel, FP32, LRS h = 0:
+    MLUPS and the per-phase split (the filter phase is the kernel-filter
+    pass program)."""
+    import synth
+    cfg = w["cfg"]
+    N = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    qois = [(k, f, 0) for f in ("G3", "L3", "L1") for k in ("E", "Z")] + [q for q in w["qois"] if q[0] == "MP"]
+    spec = lbm.ClosureSpec(qois, **w["cargs"])
+    r = lbm.Run(lbm.make_config(precision=w["precision"], **cfg), spec)
+    r.init_velocity(w["u0"])
+    r.step(20)
+    r.sync()
+    t = time.perf_counter()
+    r.step(steps)
+    r.sync()
+    dt = time.perf_counter() - t
+    ms, nl = r.profile_phases(20)
+    r.close()
+    return {"qois": "E,Z x G3,L3,L1 + 6 mean-profile bands", "steps": steps,
+            "mlups": round(N * steps / dt / 1e6, 1),
+            "ms_per_step": {k: round(v, 4) for k, v in ms.items()},
+            "launches_per_step": {k: int(v) for k, v in nl.items()}}
+
+
 def form_batched(lbm, nmem, steps):
     """System form (2): an ensemble of Kolmogorov TO-LES members on uneven
     grids advanced as one batch (one launch per kernel phase for all members,
@@ -475,6 +501,8 @@ def main():
         forms = {}
         forms["precision"] = form_precision(lbm, w, 1000)
         print(f"[bench] precision forms: {forms['precision']}", file=sys.stderr, flush=True)
+        forms["kernel_filters"] = form_kernel_filters(lbm, w, 1000)
+        print(f"[bench] kernel filters: {forms['kernel_filters']}", file=sys.stderr, flush=True)
         forms["history_lrs"] = form_history(lbm, w, 2000)
         print(f"[bench] history LRS: {forms['history_lrs']}", file=sys.stderr, flush=True)
         forms["batched"] = form_batched(lbm, 64, args.ensemble_steps)

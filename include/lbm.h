@@ -306,8 +306,9 @@ void lbm_server_destroy(lbm_server* s);
 /* Per-phase timing for measurement: runs nsteps steps eagerly on the context
  * stream with HIP events between the kernel phases and returns the mean
  * duration per step of each phase in ms[6]: stream-collide (with the WALE
- * moments pass), curl, binomial powers, reduce, solve, apply (plain runs
- * with records: their diagnostics in the last slot); launches[6] (nullable)
+ * moments pass), curl, filters (binomial powers, or the kernel-filter pass
+ * program), reduce, cross-block sums and solve, apply (plain runs with
+ * records: their diagnostics in the last slot); launches[6] (nullable)
  * receives the kernel launches per step of each phase.  Advances the run. */
 int lbm_profile_phases(lbm_ctx* ctx, long nsteps, double* ms, int* launches);
 

@@ -61,6 +61,7 @@ struct ClosureShape {
     int nq = 0, nsa = 0, nmp = 0, jv = 0, jw = 0, has_z = 0, has_e = 0, nbands = 0;
     int h = 0, nhc = 0;   // LRS history length; k_sum workgroups of its product
     int kf = 0;           // E/Z QoIs use the kernel filters (materialised sensitivities)
+    int kslots = 0, nzq = 0;   // kernel filters: separable terms over the QoIs; Z QoIs
     int npart() const { return nsa + nsa * (nsa + 1) / 2 + nmp * (1 + nsa); }
 };
 
@@ -106,6 +107,13 @@ int closure_shape(const lbm_config* cfg, const lbm_closure* cl, ClosureShape* ou
             binom = true;
     }
     if (s.kf && binom) return fail(LBM_EINVAL, "closure: binomial and kernel filters cannot be mixed");
+    if (s.kf)
+        for (int k = 0; k < cl->nq; ++k) {
+            const lbm_qoi_spec& q = cl->q[k];
+            if (q.kind != LBM_QOI_E && q.kind != LBM_QOI_Z) continue;
+            s.kslots += q.filter == LBM_FILT_LAPL ? (cfg->lattice == LBM_D2Q9 ? 2 : 3) : 1;
+            s.nzq += q.kind == LBM_QOI_Z;
+        }
     for (int k = 0; k < cl->nq; ++k) {
         const lbm_qoi_spec& q = cl->q[k];
         if (q.kind == LBM_QOI_E || q.kind == LBM_QOI_Z) {
@@ -152,7 +160,7 @@ int check_config(const lbm_config* c)
 
 struct Plan {
     size_t member, param, ctl, recs, g0, g1, fprof, vn, part_stats, part_diag, work1, workm;
-    size_t rho, vs, P, W, Cf, part_to, bandw, cmp, workr, workb, sums, works, hpart, kV, kT, ktaps;
+    size_t rho, vs, P, W, Cf, part_to, bandw, cmp, workr, workb, sums, works, hpart, kV, kT, ktaps, kjobs;
     size_t total;
     int N, D, NC, Q, esz, nb1, nbx2, cpt2, nbr, nbb, nbs, zc, btx, rec_cap;
     ClosureShape cap;
@@ -221,10 +229,13 @@ void make_plan(const lbm_config* c, const ClosureShape& cs, Plan* p)
         P.works = take(sizeof(int2) * P.nbs);
         P.hpart = take(sizeof(double) * kMaxQ * std::max(cs.nhc, 1));
         if (cs.kf) {
-            // kernel filters: V_s [nsa][D][N], four [3][N] work fields, tap tables
+            // kernel filters: V_s [nsa][D][N]; [3][N] work fields: two per
+            // separable term, one per QoI, one more per Z QoI; tap tables;
+            // the job table of the pass program
             P.kV = take(e * (size_t)cs.nsa * P.D * N);
-            P.kT = take(e * 4 * 3 * N);
+            P.kT = take(e * 3 * N * (size_t)(2 * cs.kslots + cs.nsa + cs.nzq));
             P.ktaps = take(e * kMaxSA * 3 * (2 * kMaxRad + 1));
+            P.kjobs = take(sizeof(KJob) * (size_t)(2 * (2 * cs.kslots + cs.nsa) + cs.nzq + 1));
         }
     }
     P.total = o;
@@ -329,7 +340,7 @@ struct lbm_ctx {
     size_t qref_cap = 0;
     double* chist_dev = nullptr;   // history rows of the LRS matrix
     size_t chist_cap = 0;
-    std::vector<KPass> kprog;      // kernel-filter sensitivity program (device addresses)
+    std::vector<int2> klev;        // kernel filters: (first job, job count) per launch level
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     long gver[2] = {-1, -1};
     int gchunk = 32;
@@ -377,8 +388,9 @@ LaunchGroup ctx_group(const lbm_ctx* c)
     g.btx = c->plan.btx;
     add_pass_masks(c, g);
     g.kf = c->cur.kf;
-    g.kprog = c->kprog.data();
-    g.nkprog = (int)c->kprog.size();
+    g.kjobs = (const KJob*)(c->arena + c->plan.kjobs);
+    g.klev = c->klev.data();
+    g.nklev = (int)c->klev.size();
     g.mems = c->dm;
     g.work1 = (const int2*)(c->arena + c->plan.work1);
     g.nb1 = c->plan.nb1;
@@ -415,9 +427,13 @@ void drop_graphs(lbm_ctx* c)
 // the axes a of (dilated biharmonic l_s along a) x (box of width s across a),
 // scaled by 2 / sum |L_s| = 1 / (8 d s^d) (the d arms share the centre
 // block, where the kernel is 6 d; each arm adds 10 s^d in absolute value).
-// The identity is one term with unit taps.  Writes the tap tables into the
-// arena and the pass program: for E, V = R(R v*); for Z, V = curl^T R(R w).
-int build_kprog(lbm_ctx* c, const lbm_closure* cl, const ClosureShape& cs)
+// The identity is one term with unit taps.  The program: for E,
+// V = R(R v*); for Z, V = curl^T R(R w).  One application of R is a level of
+// x passes (one job per QoI and term), a level of y passes and a level of z
+// passes that also sums the terms (2-D: the y level sums them); a last level
+// forms the adjoint curls.  Writes the tap tables and the job table into the
+// arena and the level list into the context.
+int build_kjobs(lbm_ctx* c, const lbm_closure* cl)
 {
     const int D = c->plan.D, NC = c->plan.NC, W = 2 * kMaxRad + 1;
     const size_t N = c->plan.N, e = c->plan.esz;
@@ -428,17 +444,16 @@ int build_kprog(lbm_ctx* c, const lbm_closure* cl, const ClosureShape& cs)
         std::copy(t.begin(), t.end(), taps.begin() + (size_t)ntap * W);
         return A + c->plan.ktaps + (size_t)(ntap++) * W * e;
     };
-    struct Term { double coef; const void* tap[3]; int rad[3]; };
-    c->kprog.clear();
-    char* T1 = A + c->plan.kT;
-    char* T2 = T1 + 3 * N * e;
-    char* Y1 = T2 + 3 * N * e;
-    char* Y2 = Y1 + 3 * N * e;
+    char* tcur = A + c->plan.kT;
+    auto field = [&]() { char* f = tcur; tcur += 3 * N * e; return f; };
+    struct Term { double coef; const void* tap[3]; int rad[3]; char* T1; char* T2; };
+    struct QJob { std::vector<Term> terms; bool E; int nc; const void* X; char* Vs; char* Y1; char* Y2; };
+    std::vector<QJob> qj;
     int isa = 0;
     for (int k = 0; k < cl->nq; ++k) {
         const lbm_qoi_spec& q = cl->q[k];
         if (q.kind == LBM_QOI_MP) continue;
-        std::vector<Term> terms;
+        QJob j{};
         const int sc = q.scale;
         if (q.filter == LBM_FILT_GAUSS) {
             const int r = (D == 2 ? 4 : 2) * sc;
@@ -447,7 +462,7 @@ int build_kprog(lbm_ctx* c, const lbm_closure* cl, const ClosureShape& cs)
             for (int i = -r; i <= r; ++i) sum += g[i + r] = std::exp(-(double)i * i / (2.0 * sc * sc));
             for (double& v : g) v /= sum;
             const void* tp = add(g);
-            terms.push_back({1.0, {tp, tp, tp}, {r, r, r}});
+            j.terms.push_back({1.0, {tp, tp, tp}, {r, r, r}, nullptr, nullptr});
         } else if (q.filter == LBM_FILT_LAPL) {
             static const double l5[5] = {1, -4, 6, -4, 1};
             const int rl = (5 * sc - 1) / 2, rb = (sc - 1) / 2;
@@ -459,38 +474,73 @@ int build_kprog(lbm_ctx* c, const lbm_closure* cl, const ClosureShape& cs)
             for (int a = 0; a < D; ++a) sd *= sc;
             const double coef = 1.0 / (8.0 * D * sd);
             for (int a = 0; a < D; ++a) {
-                Term t{coef, {tb, tb, tb}, {rb, rb, rb}};
+                Term t{coef, {tb, tb, tb}, {rb, rb, rb}, nullptr, nullptr};
                 t.tap[a] = tl;
                 t.rad[a] = rl;
-                terms.push_back(t);
+                j.terms.push_back(t);
             }
         } else {
             const void* t1 = add(std::vector<double>{1.0});
-            terms.push_back({1.0, {t1, t1, t1}, {0, 0, 0}});
+            j.terms.push_back({1.0, {t1, t1, t1}, {0, 0, 0}, nullptr, nullptr});
         }
-        const bool E = q.kind == LBM_QOI_E;
-        const int nc = E ? D : NC;
-        const void* X = E ? (const void*)(A + c->plan.vs) : (const void*)(A + c->plan.W);
-        char* Vs = A + c->plan.kV + (size_t)isa * D * N * e;
-        for (int app = 0; app < 2; ++app) {
-            const void* src = app == 0 ? X : (const void*)Y1;
-            void* dst = app == 0 ? (void*)Y1 : (E ? (void*)Vs : (void*)Y2);
-            for (size_t t = 0; t < terms.size(); ++t) {
-                const Term& tm = terms[t];
-                const int acc = t > 0;
-                c->kprog.push_back({0, 0, nc, tm.rad[0], 0, 1.0, tm.tap[0], src, T1});
-                if (D == 2) {
-                    c->kprog.push_back({0, 1, nc, tm.rad[1], acc, tm.coef, tm.tap[1], T1, dst});
-                } else {
-                    c->kprog.push_back({0, 1, nc, tm.rad[1], 0, 1.0, tm.tap[1], T1, T2});
-                    c->kprog.push_back({0, 2, nc, tm.rad[2], acc, tm.coef, tm.tap[2], T2, dst});
-                }
-            }
-        }
-        if (!E) c->kprog.push_back({1, 0, nc, 0, 0, 1.0, nullptr, Y2, Vs});
+        for (Term& t : j.terms) { t.T1 = field(); t.T2 = field(); }
+        j.E = q.kind == LBM_QOI_E;
+        j.nc = j.E ? D : NC;
+        j.X = j.E ? (const void*)(A + c->plan.vs) : (const void*)(A + c->plan.W);
+        j.Vs = A + c->plan.kV + (size_t)isa * D * N * e;
+        j.Y1 = field();
+        j.Y2 = j.E ? nullptr : field();
+        qj.push_back(j);
         isa++;
     }
-    (void)cs;
+    const int per_app = D == 3 ? 3 : 2;
+    std::vector<std::vector<KJob>> lev(2 * per_app + 1);
+    for (int app = 0; app < 2; ++app) {
+        const int l0 = app * per_app;
+        for (const QJob& q : qj) {
+            const void* src = app == 0 ? q.X : (const void*)q.Y1;
+            void* dst = app == 0 ? (void*)q.Y1 : (q.E ? (void*)q.Vs : (void*)q.Y2);
+            KJob sum{};
+            sum.op = 0;
+            sum.axis = D == 3 ? 2 : 1;
+            sum.ncomp = q.nc;
+            sum.nterm = (int)q.terms.size();
+            sum.dst = dst;
+            for (size_t t = 0; t < q.terms.size(); ++t) {
+                const Term& tm = q.terms[t];
+                KJob x{};
+                x.op = 0; x.axis = 0; x.ncomp = q.nc; x.nterm = 1;
+                x.radius[0] = tm.rad[0]; x.coef[0] = 1.0; x.taps[0] = tm.tap[0]; x.src[0] = src; x.dst = tm.T1;
+                lev[l0].push_back(x);
+                if (D == 3) {
+                    KJob y = x;
+                    y.axis = 1; y.radius[0] = tm.rad[1]; y.taps[0] = tm.tap[1]; y.src[0] = tm.T1; y.dst = tm.T2;
+                    lev[l0 + 1].push_back(y);
+                }
+                const int fa = D == 3 ? 2 : 1;   // the axis whose pass sums the terms
+                sum.radius[t] = tm.rad[fa];
+                sum.coef[t] = tm.coef;
+                sum.taps[t] = tm.tap[fa];
+                sum.src[t] = D == 3 ? tm.T2 : tm.T1;
+            }
+            lev[l0 + per_app - 1].push_back(sum);
+        }
+    }
+    for (const QJob& q : qj)
+        if (!q.E) {
+            KJob cj{};
+            cj.op = 1; cj.ncomp = q.nc; cj.src[0] = q.Y2; cj.dst = q.Vs;
+            lev[2 * per_app].push_back(cj);
+        }
+    std::vector<KJob> all;
+    c->klev.clear();
+    for (const auto& l : lev) {
+        if (l.empty()) continue;
+        c->klev.push_back(make_int2((int)all.size(), (int)l.size()));
+        all.insert(all.end(), l.begin(), l.end());
+    }
+    int rc = upload(c, A + c->plan.kjobs, all.data(), sizeof(KJob) * all.size());
+    if (rc) return rc;
     // tap tables in the run's element type
     if (e == 8) return upload(c, A + c->plan.ktaps, taps.data(), sizeof(double) * taps.size());
     std::vector<float> tf(taps.begin(), taps.end());
@@ -507,7 +557,7 @@ int apply_closure(lbm_ctx* c, const lbm_closure* cl)
         const ClosureShape& cap = c->plan.cap;
         if (!c->has_to || cs.nsa > cap.nsa || cs.jv > cap.jv || (cs.has_z && (!cap.has_z || cs.jw > cap.jw)) ||
             cs.npart() > cap.npart() || cs.nbands > std::max(cap.nbands, 1) || cs.nhc > cap.nhc ||
-            (cs.kf && !cap.kf))
+            (cs.kf && (!cap.kf || cs.kslots > cap.kslots || cs.nzq > cap.nzq)))
             return fail(LBM_ENOMEM, "closure does not fit the workspace planned at creation");
         if (cs.h > 0 && cl->spinup < c->host_step + cs.h)
             return fail(LBM_EINVAL, "closure: spinup must be at least the step count plus the history length");
@@ -549,7 +599,7 @@ int apply_closure(lbm_ctx* c, const lbm_closure* cl)
         const int nq = cl->nq;
         p.kf = cs.kf;
         if (cs.kf) {
-            rc = build_kprog(c, cl, cs);
+            rc = build_kjobs(c, cl);
             if (rc) return rc;
         }
         if (cl->mode == LBM_CLOSURE_LRS) {
@@ -1203,8 +1253,9 @@ static int batch_build(lbm_batch* b)
             if (keys[gi].kfm >= 0) {
                 g.kf = 1;
                 g.npass = 0;
-                g.kprog = c->kprog.data();
-                g.nkprog = (int)c->kprog.size();
+                g.kjobs = (const KJob*)(c->arena + c->plan.kjobs);
+                g.klev = c->klev.data();
+                g.nklev = (int)c->klev.size();
             }
         }
         g.mems = b->dmem;
@@ -1326,9 +1377,9 @@ int lbm_profile_phases(lbm_ctx* c, long nsteps, double* ms, int* launches)
         const int m = g.mode;
         launches[0] = 1 + (g.substrate == LBM_WALE ? 1 : 0);
         launches[1] = m == 2 && g.any_z ? 1 : 0;
-        launches[2] = m == 2 ? g.npass : 0;
+        launches[2] = m == 2 ? (g.kf ? g.nklev : g.npass) : 0;
         launches[3] = m == 2 ? 1 : 0;
-        launches[4] = m == 2 ? 1 : 0;
+        launches[4] = m == 2 ? 2 : 0;   // cross-block sums, solve
         launches[5] = m == 2 ? 1 : (m == 1 ? 2 : 0);
     }
     return rc;

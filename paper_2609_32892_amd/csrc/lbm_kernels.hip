@@ -1433,57 +1433,63 @@ __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ 
 
 // ---------------------------------------------------------------------------
 // Kernel filters (Sec. 4.1, eq. gaussian and eq. laplace): each filter is a
-// sum of separable terms, applied as 1-D passes along x, y and z.
-// K2k: one pass, dst = coef * sum_r taps[r] src(. + r e_axis) (or dst +=),
-// with periodic wrap, or zero padding on the wall axis.
+// sum of separable terms, applied as 1-D passes along x, y and z; every
+// QoI's and every term's pass of the same depth runs in one launch.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_kpass(const DevMember* __restrict__ mems, const int2* __restrict__ work,
-                                                  int axis, int ncomp, int radius, int acc, T coef,
-                                                  const T* __restrict__ taps, const T* __restrict__ src,
-                                                  T* __restrict__ dst)
-{
-    const int2 wk = work[blockIdx.x];
-    KMember& m = *kc(mems + wk.x);
-    const int N = m.N, nx = m.nx, ny = m.ny;
-    const int cell = wk.y * kBlock + threadIdx.x;
-    if (cell >= N) return;
-    const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
-    const int n = axis == 0 ? nx : (axis == 1 ? ny : m.nz);
-    const int pos = axis == 0 ? x : (axis == 1 ? y : z);
-    const int stride = axis == 0 ? 1 : (axis == 1 ? nx : nx * ny);
-    const bool pad = axis == 1 && m.walls;
-    for (int c = 0; c < ncomp; ++c) {
-        const T* sc = src + (size_t)c * N + (cell - (size_t)pos * stride);   // start of this cell's line
-        T sum = 0;
-        for (int r = -radius; r <= radius; ++r) {
-            int p = pos + r;
-            if (pad) {
-                if (p < 0 || p >= n) continue;
-            } else {
-                p %= n;
-                if (p < 0) p += n;
-            }
-            sum += taps[r + radius] * sc[(size_t)p * stride];
-        }
-        T* d = dst + (size_t)c * N + cell;
-        *d = acc ? *d + coef * sum : coef * sum;
-    }
-}
-
-// K2k': V = curl^T psi (2-D: (D_y psi, -D_x psi); 3-D: curl psi), central
-// differences with the wall padding of curl_at.
+// K2k: one level of the program: job blockIdx.y, cells of block blockIdx.x.
+// op 0: dst = sum_t coef_t sum_r taps_t[r] src_t(. + r e_axis), periodic wrap
+// or zero padding on the wall axis; op 1: the adjoint curl (2-D:
+// (D_y psi, -D_x psi); 3-D: curl psi) with the wall padding of curl_at.
 template <int LAT, typename T>
-__global__ __launch_bounds__(kBlock) void k_curlT(const DevMember* __restrict__ mems, const int2* __restrict__ work,
-                                                  const T* __restrict__ src, T* __restrict__ dst)
+__global__ __launch_bounds__(kBlock) void k_kjob(const DevMember* __restrict__ mems, const int2* __restrict__ work,
+                                                 const KJob* __restrict__ jobs)
 {
     using L = Lat<LAT>;
+    const LBM_K KJob& j = *kc(jobs + blockIdx.y);
     const int2 wk = work[blockIdx.x];
     KMember& m = *kc(mems + wk.x);
     const int N = m.N, nx = m.nx, ny = m.ny, nz = m.nz;
     const int cell = wk.y * kBlock + threadIdx.x;
     if (cell >= N) return;
     const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
+    T* __restrict__ dst = (T*)j.dst;
+    if (j.op == 0) {
+        const int axis = j.axis;
+        const int n = axis == 0 ? nx : (axis == 1 ? ny : nz);
+        const int pos = axis == 0 ? x : (axis == 1 ? y : z);
+        const int stride = axis == 0 ? 1 : (axis == 1 ? nx : nx * ny);
+        const bool pad = axis == 1 && m.walls;
+        const size_t line = (size_t)cell - (size_t)pos * stride;   // first cell of this cell's line
+        for (int c = 0; c < j.ncomp; ++c) {
+            T out = 0;
+            for (int tt = 0; tt < j.nterm; ++tt) {
+                const T* __restrict__ sc = (const T*)j.src[tt] + (size_t)c * N + line;
+                const T* __restrict__ tp = (const T*)j.taps[tt];
+                const int rad = j.radius[tt];
+                T sum = 0;
+                if (pos - rad >= 0 && pos + rad < n) {
+                    // the whole stencil inside the line: no wrap, no padding
+                    const T* __restrict__ q = sc + (size_t)(pos - rad) * stride;
+                    for (int r = 0; r <= 2 * rad; ++r) sum += tp[r] * q[(size_t)r * stride];
+                } else {
+                    for (int r = -rad; r <= rad; ++r) {
+                        int p = pos + r;
+                        if (pad) {
+                            if (p < 0 || p >= n) continue;
+                        } else {
+                            p %= n;
+                            if (p < 0) p += n;
+                        }
+                        sum += tp[r + rad] * sc[(size_t)p * stride];
+                    }
+                }
+                out += T(j.coef[tt]) * sum;
+            }
+            dst[(size_t)c * N + cell] = out;
+        }
+        return;
+    }
+    const T* __restrict__ src = (const T*)j.src[0];
     if constexpr (L::D == 2) {
         dst[cell] = T(0.5) * (fld(src, x, y + 1, z, nx, ny, nz, m.walls) - fld(src, x, y - 1, z, nx, ny, nz, m.walls));
         dst[(size_t)N + cell] =
@@ -1745,15 +1751,9 @@ to_chain:
         if (g.any_z) hipLaunchKernelGGL((k_curl<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1);
         mark(2);
         if (g.kf) {
-            for (int k = 0; k < g.nkprog; ++k) {
-                const KPass& p = g.kprog[k];
-                if (p.op == 0)
-                    hipLaunchKernelGGL(k_kpass<T>, dim3(g.nb1), blk, 0, st, g.mems, g.work1, p.axis, p.ncomp, p.radius,
-                                       p.acc, (T)p.coef, (const T*)p.taps, (const T*)p.src, (T*)p.dst);
-                else
-                    hipLaunchKernelGGL((k_curlT<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, (const T*)p.src,
-                                       (T*)p.dst);
-            }
+            for (int l = 0; l < g.nklev; ++l)
+                hipLaunchKernelGGL((k_kjob<LAT, T>), dim3(g.nb1, g.klev[l].y), blk, 0, st, g.mems, g.work1,
+                                   g.kjobs + g.klev[l].x);
         }
         for (int j = 1; j <= (g.kf ? 0 : g.npass); ++j) {
 #define LBM_BINOM(TXV, CHV) hipLaunchKernelGGL((k_binom<LAT, T, TXV, CHV>), dim3(g.nbb), blk, 0, st, g.mems, g.workb, j)

@@ -6,15 +6,18 @@
 
 namespace lbm {
 
-// One step of a kernel-filter closure's sensitivity program: a 1-D
-// convolution along an axis (op 0; periodic wrap or zero padding on the wall
-// axis; dst = coef * result, or dst += coef * result if acc), or the adjoint
-// curl curl^T (op 1).  Pointers are device addresses in the member's arena.
-struct KPass {
-    int op, axis, ncomp, radius, acc;
-    double coef;
-    const void* taps;   // 2 radius + 1 values, element type of the run
-    const void* src;
+// One output field of a kernel-filter closure's sensitivity program (lives
+// in device memory; a launch runs every job of one level, one job per
+// blockIdx.y): op 0, dst = sum_t coef_t (1-D convolution of src_t along axis
+// with taps_t), periodic wrap or zero padding on the wall axis; op 1,
+// dst = curl^T src[0].  Pointers are device addresses in the member's arena.
+struct KJob {
+    int op, axis, ncomp, nterm;
+    int radius[3];
+    int pad;
+    double coef[3];
+    const void* taps[3];   // 2 radius + 1 values each, element type of the run
+    const void* src[3];
     void* dst;
 };
 
@@ -39,9 +42,10 @@ struct LaunchGroup {
     int nmem;
     int probe;          // TO mode only: the QoI chain of the field already in v* (no
                         // stream-collide, no apply); see lbm_project_qoi
-    int kf;             // kernel-filter closure (one member per group): kprog replaces the
-    const KPass* kprog; // binomial passes
-    int nkprog;
+    int kf;             // kernel-filter closure (one member per group): its job levels
+    const KJob* kjobs;  // replace the binomial passes; kjobs in device memory,
+    const int2* klev;   // klev[l] = (first job, job count) of level l (host memory)
+    int nklev;
 };
 
 enum { OP_INIT = 0, OP_GET_POP = 1, OP_SET_POP = 2, OP_STREAM = 3 };
