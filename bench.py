@@ -223,28 +223,31 @@ def form_history(lbm, w, steps, h=500):
 
 def form_kernel_filters(lbm, w, steps):
     """The paper's own 3-D QoI set (Sec. 7: {E, Z} x {G_3, L_3, L_1} plus the
-    six mean-profile bands) on the headline channel, FP32, LRS h = 0:
-    MLUPS and the per-phase split (the filter phase is the kernel-filter
-    pass program)."""
+    six mean-profile bands), FP32, LRS h = 0, on the headline channel (MLUPS
+    and the per-phase split; the filter phase is the kernel-filter pass
+    program) and on the paper's LF grid 295 x 47 x 98 (its 295 x 49 x 98 with
+    the two solid rows not stored), where the paper measures its LF TO-LRS."""
     import synth
-    cfg = w["cfg"]
-    N = cfg["nx"] * cfg["ny"] * cfg["nz"]
-    qois = [(k, f, 0) for f in ("G3", "L3", "L1") for k in ("E", "Z")] + [q for q in w["qois"] if q[0] == "MP"]
-    spec = lbm.ClosureSpec(qois, **w["cargs"])
-    r = lbm.Run(lbm.make_config(precision=w["precision"], **cfg), spec)
-    r.init_velocity(w["u0"])
-    r.step(20)
-    r.sync()
-    t = time.perf_counter()
-    r.step(steps)
-    r.sync()
-    dt = time.perf_counter() - t
-    ms, nl = r.profile_phases(20)
-    r.close()
-    return {"qois": "E,Z x G3,L3,L1 + 6 mean-profile bands", "steps": steps,
-            "mlups": round(N * steps / dt / 1e6, 1),
-            "ms_per_step": {k: round(v, 4) for k, v in ms.items()},
-            "launches_per_step": {k: int(v) for k, v in nl.items()}}
+    out = {"qois": "E,Z x G3,L3,L1 + 6 mean-profile bands", "steps": steps}
+    for name, (nx, ny, nz) in (("headline", (96, 48, 48)), ("paper_lf_grid", (295, 47, 98))):
+        cfg, u0 = synth.channel_workload(nx, ny, nz, substrate=1, cmodel=0.1, seed=6)
+        nb, dmin, dmax = synth.channel_bands(ny)
+        qois = [(k, f, 0) for f in ("G3", "L3", "L1") for k in ("E", "Z")] + [("MP", "I", j) for j in range(nb)]
+        spec = lbm.ClosureSpec(qois, **dict(w["cargs"], nbands=nb, dmin=dmin, dmax=dmax))
+        r = lbm.Run(lbm.make_config(precision=w["precision"], **cfg), spec)
+        r.init_velocity(u0)
+        r.step(20)
+        r.sync()
+        t = time.perf_counter()
+        r.step(steps)
+        r.sync()
+        dt = time.perf_counter() - t
+        ms, nl = r.profile_phases(20)
+        r.close()
+        out[name] = {"grid": [nx, ny, nz], "mlups": round(nx * ny * nz * steps / dt / 1e6, 1),
+                     "ms_per_step": {k: round(v, 4) for k, v in ms.items()},
+                     "launches_per_step": {k: int(v) for k, v in nl.items()}}
+    return out
 
 
 def form_batched(lbm, nmem, steps):
