@@ -28,10 +28,14 @@ KERNEL_FILT = {"G": 5, "L": 6}   # with a scale: "G3" is G_3, "L1" is L_1
 
 
 def filter_code(name):
-    """(code, scale) of a filter name: I, B, B2, BMID, IMB, or G<s> / L<s>."""
+    """(code, scale, m) of a filter name: I, B, B2, BMID, IMB, G<s>, L<s>, or
+    F<l>-<m> for the sharp Fourier band R_[l,m]."""
     if name in FILT:
-        return FILT[name], 0
-    return KERNEL_FILT[name[0]], int(name[1:])
+        return FILT[name], 0, 0
+    if name[0] == "F":
+        lo, hi = name[1:].split("-")
+        return 7, int(lo), int(hi)
+    return KERNEL_FILT[name[0]], int(name[1:]), 0
 
 
 MODE = {"off": 0, "track": 1, "lrs": 2}
@@ -62,7 +66,7 @@ class Closure(ct.Structure):
                 ("C", ct.c_double * ((OQMAX + 1) * OQMAX)), ("mu", ct.c_double * OQMAX),
                 ("Sigma", ct.c_double * (OQMAX * OQMAX)), ("scale", ct.c_double * OQMAX),
                 ("have_scale", ct.c_int), ("seed", ct.c_uint64), ("h", ct.c_int),
-                ("Chist", ct.POINTER(ct.c_double)), ("fs", ct.c_int * OQMAX)]
+                ("Chist", ct.POINTER(ct.c_double)), ("fs", ct.c_int * OQMAX), ("fm", ct.c_int * OQMAX)]
 
 
 class Rec(ct.Structure):
@@ -94,7 +98,7 @@ def lib():
         L.orc_velocity.argtypes = [P, P, P]
         L.orc_ncurl.argtypes = [P]
         L.orc_curl.argtypes = [P, P, P]
-        L.orc_filter.argtypes = [P, I, I, P, P, I]
+        L.orc_filter.argtypes = [P, I, I, I, P, P, I]
         L.orc_kernel.argtypes = [P, I, I, P]
         L.orc_band_weights.argtypes = [P, I, ct.c_double, ct.c_double, P]
         L.orc_qoi.argtypes = [P, ct.POINTER(Closure), P, P, P]
@@ -175,7 +179,7 @@ def make_closure(qois, mode="off", spinup=0, C=None, mu=None, Sigma=None, scale=
     cl.nq = len(qois)
     for k, (kind, filt, band) in enumerate(qois):
         cl.kind[k] = {"E": QOI_E, "Z": QOI_Z, "MP": QOI_MP}[kind]
-        cl.filt[k], cl.fs[k] = filter_code(filt)
+        cl.filt[k], cl.fs[k], cl.fm[k] = filter_code(filt)
         cl.band[k] = band
     cl.nbands = nbands
     cl.dmin = dmin
@@ -320,14 +324,14 @@ class Oracle:
         u = np.ascontiguousarray(u, dtype=np.float64)
         nc = u.size // self.N
         out = np.zeros_like(u)
-        code, sc = filter_code(filt)
-        self.L.orc_filter(self.h, code, sc, _p(u), _p(out), nc)
+        code, sc, fm = filter_code(filt)
+        self.L.orc_filter(self.h, code, sc, fm, _p(u), _p(out), nc)
         return out
 
     def kernel(self, name):
         """The d-dimensional kernel of G<s> or L<s>, shape (2R+1,)*d with
         axes (z,) y, x."""
-        code, sc = filter_code(name)
+        code, sc, _ = filter_code(name)
         R = self.L.orc_kernel(self.h, code, sc, None)
         W = 2 * R + 1
         k = np.zeros(W ** self.d)

@@ -61,7 +61,7 @@ typedef struct {
 typedef struct {
     int nq;
     int kind[OQMAX];      /* 0 energy E_R, 1 enstrophy Z_R, 2 mean-profile */
-    int filt[OQMAX];      /* 0 I, 1 B, 2 B^2, 3 B-B^2, 4 I-B, 5 G_s, 6 L_s */
+    int filt[OQMAX];      /* 0 I, 1 B, 2 B^2, 3 B-B^2, 4 I-B, 5 G_s, 6 L_s, 7 R_[l,m] */
     int band[OQMAX];      /* band index for mean-profile QoIs */
     int nbands;
     double dmin, dmax;    /* band-centre range in wall distance */
@@ -75,7 +75,8 @@ typedef struct {
     uint64_t seed;
     int h;                /* LRS history length (eq. LRS); 0 uses C above */
     const double *Chist;  /* h > 0: the full ((2h+1) nq + 1) x nq matrix C (copied) */
-    int fs[OQMAX];        /* scale s of the kernel filters 5 (G_s) and 6 (L_s) */
+    int fs[OQMAX];        /* scale s of the kernel filters 5 (G_s) and 6 (L_s); l of filter 7 */
+    int fm[OQMAX];        /* m of the Fourier band filter 7, R_[l,m] */
 } orc_closure;
 
 typedef struct {
@@ -451,6 +452,72 @@ static void kernel_filter(const Orc *o, int filt, int s, const double *in, doubl
     free(K);
 }
 
+/* ------------------------------------------------------------------ */
+/* Sharp Fourier band filter R_[l,m] (eq. scale-aware-energy-fourier,   */
+/* periodic grids): keep the DFT modes with l - 1/2 <= |k| < m + 1/2,   */
+/* k the integer mode index vector (index j of an axis of length n is   */
+/* k = j for j <= n/2, else j - n).  Plain separable DFT, no FFT.        */
+/* ------------------------------------------------------------------ */
+static void dft_axis(const Orc *o, double *re, double *im, int axis, int sign)
+{
+    const int n = axis == 0 ? o->c.nx : (axis == 1 ? o->c.ny : o->c.nz);
+    if (n == 1) return;
+    const long N = o->N;
+    const long stride = axis == 0 ? 1 : (axis == 1 ? o->c.nx : (long)o->c.nx * o->c.ny);
+    double *cs = (double *)malloc(sizeof(double) * n), *sn = (double *)malloc(sizeof(double) * n);
+    for (int j = 0; j < n; j++) { cs[j] = cos(2.0 * OPI * j / n); sn[j] = sin(2.0 * OPI * j / n); }
+    #pragma omp parallel for schedule(static)
+    for (long base = 0; base < N; base++) {
+        if ((base / stride) % n != 0) continue;      /* first cell of each line */
+        double *tr = (double *)malloc(sizeof(double) * n), *ti = (double *)malloc(sizeof(double) * n);
+        for (int kk = 0; kk < n; kk++) {
+            double ar = 0, ai = 0;
+            for (int j = 0; j < n; j++) {
+                const int t = (int)(((long)kk * j) % n);
+                const double c = cs[t], sv = sign * sn[t];
+                const double xr = re[base + j * stride], xi = im[base + j * stride];
+                ar += xr * c - xi * sv;
+                ai += xr * sv + xi * c;
+            }
+            tr[kk] = ar; ti[kk] = ai;
+        }
+        for (int kk = 0; kk < n; kk++) { re[base + kk * stride] = tr[kk]; im[base + kk * stride] = ti[kk]; }
+        free(tr); free(ti);
+    }
+    free(cs); free(sn);
+}
+
+static void fourier_band(const Orc *o, int l, int m, const double *in, double *out, int ncomp)
+{
+    const long N = o->N;
+    double *re = (double *)malloc(sizeof(double) * N), *im = (double *)malloc(sizeof(double) * N);
+    for (int k = 0; k < ncomp; k++) {
+        for (long x = 0; x < N; x++) { re[x] = in[k * N + x]; im[x] = 0.0; }
+        for (int a = 0; a < 3; a++) dft_axis(o, re, im, a, -1);
+        for (long x = 0; x < N; x++) {
+            const int jx = (int)(x % o->c.nx), jy = (int)((x / o->c.nx) % o->c.ny), jz = (int)(x / ((long)o->c.nx * o->c.ny));
+            const int kx = jx <= o->c.nx / 2 ? jx : jx - o->c.nx;
+            const int ky = jy <= o->c.ny / 2 ? jy : jy - o->c.ny;
+            const int kz = jz <= o->c.nz / 2 ? jz : jz - o->c.nz;
+            const double kn = sqrt((double)kx * kx + (double)ky * ky + (double)kz * kz);
+            if (!(kn >= l - 0.5 && kn < m + 0.5)) { re[x] = 0.0; im[x] = 0.0; }
+        }
+        for (int a = 0; a < 3; a++) dft_axis(o, re, im, a, +1);
+        for (long x = 0; x < N; x++) out[k * N + x] = re[x] / (double)N;
+    }
+    free(re); free(im);
+}
+
+static void apply_filter(const Orc *o, int filt, int s, const double *in, double *out, int ncomp);
+
+/* R u for the filter code filt (scale s for the kernel filters; the band
+ * [s, fm] for the Fourier filter). */
+static void apply_filter_b(const Orc *o, int filt, int s, int fm, const double *in, double *out, int ncomp)
+{
+    if (filt == 7) { fourier_band(o, s, fm, in, out, ncomp); return; }
+    apply_filter(o, filt, s, in, out, ncomp);
+}
+
 /* R u for the filter code filt (scale s for the kernel filters). */
 static void apply_filter(const Orc *o, int filt, int s, const double *in, double *out, int ncomp)
 {
@@ -472,9 +539,9 @@ static void apply_filter(const Orc *o, int filt, int s, const double *in, double
     free(t1);
 }
 
-void orc_filter(void *h, int filt, int s, const double *in, double *out, int ncomp)
+void orc_filter(void *h, int filt, int s, int fm, const double *in, double *out, int ncomp)
 {
-    apply_filter((Orc *)h, filt, s, in, out, ncomp);
+    apply_filter_b((Orc *)h, filt, s, fm, in, out, ncomp);
 }
 
 /* The d-dimensional kernel of G_s / L_s ((2R+1)^d, x fastest); returns R. */
@@ -536,20 +603,20 @@ static void qoi_and_sens(const Orc *o, const orc_closure *cl, const double *bw,
     for (int k = 0; k < cl->nq; k++) {
         double *Vk = V ? V + (size_t)k * d * N : NULL;
         if (cl->kind[k] == 0) {
-            apply_filter(o, cl->filt[k], cl->fs[k], v, r1, d);
+            apply_filter_b(o, cl->filt[k], cl->fs[k], cl->fm[k], v, r1, d);
             double s = 0;
             for (long x = 0; x < N; x++)
                 for (int a = 0; a < d; a++) s += 0.5 * r1[a * N + x] * r1[a * N + x];
             q[k] = s;
-            if (Vk) apply_filter(o, cl->filt[k], cl->fs[k], r1, Vk, d);
+            if (Vk) apply_filter_b(o, cl->filt[k], cl->fs[k], cl->fm[k], r1, Vk, d);
         } else if (cl->kind[k] == 1) {
-            apply_filter(o, cl->filt[k], cl->fs[k], w, r1, nc);
+            apply_filter_b(o, cl->filt[k], cl->fs[k], cl->fm[k], w, r1, nc);
             double s = 0;
             for (long x = 0; x < N; x++)
                 for (int a = 0; a < nc; a++) s += 0.5 * r1[a * N + x] * r1[a * N + x];
             q[k] = s;
             if (Vk) {
-                apply_filter(o, cl->filt[k], cl->fs[k], r1, r2, nc);
+                apply_filter_b(o, cl->filt[k], cl->fs[k], cl->fm[k], r1, r2, nc);
                 curl_adjoint(o, r2, Vk);
             }
         } else {
