@@ -250,6 +250,36 @@ def form_kernel_filters(lbm, w, steps):
     return out
 
 
+def form_fourier(lbm, steps):
+    """The sharp Fourier band QoIs of the paper's earlier formulation (App. E
+    variant; eq. scale-aware-energy-fourier) on the 256 x 256 Kolmogorov
+    TO-LES: {E, Z} x {R_[0,12], R_[13,32], R_[33,128]} through hipFFT (eager
+    launches), against the same run with the binomial pair {E_B, Z_B}."""
+    import synth
+    w = workload("kolmogorov")
+    cfg = w["cfg"]
+    N = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    out = {"grid": [cfg["nx"], cfg["ny"]], "steps": steps}
+    for name, qois in (("fourier_bands", [(k, f, 0) for f in ("F0-12", "F13-32", "F33-128") for k in ("E", "Z")]),
+                       ("binomial_pair", synth.QOIS_2D)):
+        C, mu, S = synth.lrs_history_model(0, len(qois), 3, 4, 5, noise=1e-4)
+        spec = lbm.ClosureSpec(qois, mode="lrs", spinup=steps // 2, C=C, mu=mu, Sigma=S, seed=12)
+        r = lbm.Run(lbm.make_config(precision=w["precision"], **cfg), spec)
+        r.init_velocity(w["u0"])
+        r.step(20)
+        r.sync()
+        t = time.perf_counter()
+        r.step(steps)
+        try:
+            r.sync()
+        except lbm.LbmError as e:
+            out[name + "_error"] = str(e)
+        dt = time.perf_counter() - t
+        out[name + "_mlups"] = round(N * steps / dt / 1e6, 1)
+        r.close()
+    return out
+
+
 def form_batched(lbm, nmem, steps):
     """System form (2): an ensemble of Kolmogorov TO-LES members on uneven
     grids advanced as one batch (one launch per kernel phase for all members,
@@ -506,6 +536,8 @@ def main():
         print(f"[bench] precision forms: {forms['precision']}", file=sys.stderr, flush=True)
         forms["kernel_filters"] = form_kernel_filters(lbm, w, 1000)
         print(f"[bench] kernel filters: {forms['kernel_filters']}", file=sys.stderr, flush=True)
+        forms["fourier_bands"] = form_fourier(lbm, 1000)
+        print(f"[bench] Fourier bands: {forms['fourier_bands']}", file=sys.stderr, flush=True)
         forms["history_lrs"] = form_history(lbm, w, 2000)
         print(f"[bench] history LRS: {forms['history_lrs']}", file=sys.stderr, flush=True)
         forms["batched"] = form_batched(lbm, 64, args.ensemble_steps)

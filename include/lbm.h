@@ -95,14 +95,20 @@ enum { LBM_QOI_E = 0, LBM_QOI_Z = 1, LBM_QOI_MP = 2 };
  *    2-D, 2 in 3-D) and normalised to unit sum, radius alpha s <= 12; LAPL,
  *    the biharmonic cross [1,-4,6,-4,1] along each axis dilated by s (odd)
  *    and normalised to sum |L_s| = 2, radius (5s-1)/2 <= 12.
- * A closure uses one family for all its E and Z QoIs (I belongs to both). */
+ *  - FOURIER, the sharp band filter R_[l,m] (eq. scale-aware-energy-fourier):
+ *    the DFT modes with l - 1/2 <= |k| < m + 1/2 are kept, k the integer mode
+ *    index vector; fully periodic grids only.  Runs through hipFFT, so a
+ *    closure with such QoIs steps without graph replay.
+ * A closure uses the binomial family or the others (kernel and Fourier
+ * filters may be mixed) for all its E and Z QoIs; I belongs to both. */
 enum { LBM_FILT_ID = 0, LBM_FILT_B = 1, LBM_FILT_B2 = 2, LBM_FILT_BMID = 3, LBM_FILT_IMB = 4,
-       LBM_FILT_GAUSS = 5, LBM_FILT_LAPL = 6 };
+       LBM_FILT_GAUSS = 5, LBM_FILT_LAPL = 6, LBM_FILT_FOURIER = 7 };
 typedef struct {
     int kind;           /* LBM_QOI_E, LBM_QOI_Z, LBM_QOI_MP (MP needs walls_y = 1) */
     int filter;         /* for E and Z */
     int band;           /* for MP: band index in [0, nbands) */
-    int scale;          /* s of LBM_FILT_GAUSS / LBM_FILT_LAPL */
+    int scale;          /* s of LBM_FILT_GAUSS / LBM_FILT_LAPL; l of LBM_FILT_FOURIER */
+    int kmax;           /* m of LBM_FILT_FOURIER */
 } lbm_qoi_spec;
 
 enum { LBM_CLOSURE_OFF = 0, LBM_CLOSURE_TRACK = 1, LBM_CLOSURE_LRS = 2 };

@@ -1,6 +1,7 @@
 // lbm_api.hip -- host side of liblbm_hip: arena planning, the C ABI of
 // include/lbm.h, hipGraph replay and ensemble batches.
 #include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
 
 #include <algorithm>
 #include <chrono>
@@ -62,6 +63,7 @@ struct ClosureShape {
     int h = 0, nhc = 0;   // LRS history length; k_sum workgroups of its product
     int kf = 0;           // E/Z QoIs use the kernel filters (materialised sensitivities)
     int kslots = 0, nzq = 0;   // kernel filters: separable terms over the QoIs; Z QoIs
+    int nf = 0;                // Fourier band QoIs
     int npart() const { return nsa + nsa * (nsa + 1) / 2 + nmp * (1 + nsa); }
 };
 
@@ -95,8 +97,13 @@ int closure_shape(const lbm_config* cfg, const lbm_closure* cl, ClosureShape* ou
     for (int k = 0; k < cl->nq; ++k) {
         const lbm_qoi_spec& q = cl->q[k];
         if (q.kind != LBM_QOI_E && q.kind != LBM_QOI_Z) continue;
-        if (q.filter < LBM_FILT_ID || q.filter > LBM_FILT_LAPL) return fail(LBM_EINVAL, "closure: QoI %d bad filter", k);
-        if (q.filter == LBM_FILT_GAUSS || q.filter == LBM_FILT_LAPL) {
+        if (q.filter < LBM_FILT_ID || q.filter > LBM_FILT_FOURIER) return fail(LBM_EINVAL, "closure: QoI %d bad filter", k);
+        if (q.filter == LBM_FILT_FOURIER) {
+            if (cfg->walls_y) return fail(LBM_EINVAL, "closure: Fourier filters need a fully periodic grid");
+            if (q.scale < 0 || q.kmax < q.scale) return fail(LBM_EINVAL, "closure: QoI %d Fourier band [l,m] needs 0 <= l <= m", k);
+            s.kf = 1;
+            s.nf++;
+        } else if (q.filter == LBM_FILT_GAUSS || q.filter == LBM_FILT_LAPL) {
             const int d = cfg->lattice == LBM_D2Q9 ? 2 : 3;
             const int rad = q.filter == LBM_FILT_GAUSS ? (d == 2 ? 4 : 2) * q.scale : (5 * q.scale - 1) / 2;
             if (q.scale < 1 || (q.filter == LBM_FILT_LAPL && q.scale % 2 == 0) || rad > kMaxRad)
@@ -111,7 +118,7 @@ int closure_shape(const lbm_config* cfg, const lbm_closure* cl, ClosureShape* ou
         for (int k = 0; k < cl->nq; ++k) {
             const lbm_qoi_spec& q = cl->q[k];
             if (q.kind != LBM_QOI_E && q.kind != LBM_QOI_Z) continue;
-            s.kslots += q.filter == LBM_FILT_LAPL ? (cfg->lattice == LBM_D2Q9 ? 2 : 3) : 1;
+            s.kslots += q.filter == LBM_FILT_LAPL ? (cfg->lattice == LBM_D2Q9 ? 2 : 3) : (q.filter == LBM_FILT_FOURIER ? 0 : 1);
             s.nzq += q.kind == LBM_QOI_Z;
         }
     for (int k = 0; k < cl->nq; ++k) {
@@ -161,6 +168,7 @@ int check_config(const lbm_config* c)
 struct Plan {
     size_t member, param, ctl, recs, g0, g1, fprof, vn, part_stats, part_diag, work1, workm;
     size_t rho, vs, P, W, Cf, part_to, bandw, cmp, workr, workb, sums, works, hpart, kV, kT, ktaps, kjobs;
+    size_t fspec_v, fspec_w, ftmp;
     size_t total;
     int N, D, NC, Q, esz, nb1, nbx2, cpt2, nbr, nbb, nbs, zc, btx, rec_cap;
     ClosureShape cap;
@@ -236,6 +244,12 @@ void make_plan(const lbm_config* c, const ClosureShape& cs, Plan* p)
             P.kT = take(e * 3 * N * (size_t)(2 * cs.kslots + cs.nsa + cs.nzq));
             P.ktaps = take(e * kMaxSA * 3 * (2 * kMaxRad + 1));
             P.kjobs = take(sizeof(KJob) * (size_t)(2 * (2 * cs.kslots + cs.nsa) + cs.nzq + 1));
+            if (cs.nf) {
+                // Fourier bands: spectra of v* and w and one work spectrum (complex)
+                P.fspec_v = take(2 * e * P.D * N);
+                P.fspec_w = take(2 * e * P.NC * N);
+                P.ftmp = take(2 * e * 3 * N);
+            }
         }
     }
     P.total = o;
@@ -341,6 +355,7 @@ struct lbm_ctx {
     double* chist_dev = nullptr;   // history rows of the LRS matrix
     size_t chist_cap = 0;
     std::vector<int2> klev;        // kernel filters: (first job, job count) per launch level
+    FourierProg fprog{};           // Fourier band QoIs (plans made at set_closure)
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     long gver[2] = {-1, -1};
     int gchunk = 32;
@@ -391,6 +406,7 @@ LaunchGroup ctx_group(const lbm_ctx* c)
     g.kjobs = (const KJob*)(c->arena + c->plan.kjobs);
     g.klev = c->klev.data();
     g.nklev = (int)c->klev.size();
+    g.fprog = c->cur.nf ? &c->fprog : nullptr;
     g.mems = c->dm;
     g.work1 = (const int2*)(c->arena + c->plan.work1);
     g.nb1 = c->plan.nb1;
@@ -421,6 +437,46 @@ void drop_graphs(lbm_ctx* c)
     }
 }
 
+// Fourier band QoIs: hipFFT plans (batched C2C / Z2Z over the components,
+// in place, dimensions z, y, x) and the program that launch_fourier runs.
+void drop_fourier(lbm_ctx* c)
+{
+    for (int k = 0; k < 2; ++k)
+        if (c->fprog.plan[k]) hipfftDestroy((hipfftHandle)c->fprog.plan[k]);
+    c->fprog = FourierProg{};
+}
+
+int build_fourier(lbm_ctx* c, const std::vector<FourierQ>& fq)
+{
+    drop_fourier(c);
+    if (fq.empty()) return LBM_OK;
+    FourierProg& f = c->fprog;
+    const int D = c->plan.D, NC = c->plan.NC, N = c->plan.N;
+    int n[3] = {c->cfg.nz, c->cfg.ny, c->cfg.nx};
+    const int rank = D == 3 ? 3 : 2;
+    int* dims = D == 3 ? n : n + 1;
+    const hipfftType type = c->cfg.precision == LBM_FP64 ? HIPFFT_Z2Z : HIPFFT_C2C;
+    const int batch[2] = {D, NC};
+    for (int k = 0; k < 2; ++k) {
+        hipfftHandle h;
+        if (hipfftPlanMany(&h, rank, dims, nullptr, 1, N, nullptr, 1, N, type, batch[k]) != HIPFFT_SUCCESS) {
+            drop_fourier(c);
+            return fail(LBM_EDEVICE, "hipFFT plan creation failed");
+        }
+        f.plan[k] = (void*)h;
+    }
+    char* A = c->arena;
+    f.spec_v = A + c->plan.fspec_v;
+    f.spec_w = A + c->plan.fspec_w;
+    f.tmp = A + c->plan.ftmp;
+    f.vs = A + c->plan.vs;
+    f.w = A + c->plan.W;
+    f.nx = c->cfg.nx; f.ny = c->cfg.ny; f.nz = c->cfg.nz;
+    f.q = fq;
+    for (const FourierQ& q : fq) f.nz_q |= !q.e;
+    return LBM_OK;
+}
+
 // The kernel filters as sums of separable terms (Sec. 4.1): G_s is the
 // product of the 1-D truncated Gaussian g (radius alpha s, alpha = 4 in 2-D
 // and 2 in 3-D, normalised so that its cube sums to one); L_s is the sum over
@@ -449,13 +505,16 @@ int build_kjobs(lbm_ctx* c, const lbm_closure* cl)
     struct Term { double coef; const void* tap[3]; int rad[3]; char* T1; char* T2; };
     struct QJob { std::vector<Term> terms; bool E; int nc; const void* X; char* Vs; char* Y1; char* Y2; };
     std::vector<QJob> qj;
+    std::vector<FourierQ> fq;
     int isa = 0;
     for (int k = 0; k < cl->nq; ++k) {
         const lbm_qoi_spec& q = cl->q[k];
         if (q.kind == LBM_QOI_MP) continue;
         QJob j{};
         const int sc = q.scale;
-        if (q.filter == LBM_FILT_GAUSS) {
+        if (q.filter == LBM_FILT_FOURIER) {
+            // no separable terms: the band goes through hipFFT
+        } else if (q.filter == LBM_FILT_GAUSS) {
             const int r = (D == 2 ? 4 : 2) * sc;
             std::vector<double> g(2 * r + 1);
             double sum = 0;
@@ -490,6 +549,7 @@ int build_kjobs(lbm_ctx* c, const lbm_closure* cl)
         j.Vs = A + c->plan.kV + (size_t)isa * D * N * e;
         j.Y1 = field();
         j.Y2 = j.E ? nullptr : field();
+        if (q.filter == LBM_FILT_FOURIER) fq.push_back({j.E ? 1 : 0, q.scale, q.kmax, j.E ? (void*)j.Vs : (void*)j.Y2});
         qj.push_back(j);
         isa++;
     }
@@ -523,7 +583,7 @@ int build_kjobs(lbm_ctx* c, const lbm_closure* cl)
                 sum.taps[t] = tm.tap[fa];
                 sum.src[t] = D == 3 ? tm.T2 : tm.T1;
             }
-            lev[l0 + per_app - 1].push_back(sum);
+            if (!q.terms.empty()) lev[l0 + per_app - 1].push_back(sum);
         }
     }
     for (const QJob& q : qj)
@@ -539,7 +599,9 @@ int build_kjobs(lbm_ctx* c, const lbm_closure* cl)
         c->klev.push_back(make_int2((int)all.size(), (int)l.size()));
         all.insert(all.end(), l.begin(), l.end());
     }
-    int rc = upload(c, A + c->plan.kjobs, all.data(), sizeof(KJob) * all.size());
+    int rc = all.empty() ? LBM_OK : upload(c, A + c->plan.kjobs, all.data(), sizeof(KJob) * all.size());
+    if (rc) return rc;
+    rc = build_fourier(c, fq);
     if (rc) return rc;
     // tap tables in the run's element type
     if (e == 8) return upload(c, A + c->plan.ktaps, taps.data(), sizeof(double) * taps.size());
@@ -557,7 +619,7 @@ int apply_closure(lbm_ctx* c, const lbm_closure* cl)
         const ClosureShape& cap = c->plan.cap;
         if (!c->has_to || cs.nsa > cap.nsa || cs.jv > cap.jv || (cs.has_z && (!cap.has_z || cs.jw > cap.jw)) ||
             cs.npart() > cap.npart() || cs.nbands > std::max(cap.nbands, 1) || cs.nhc > cap.nhc ||
-            (cs.kf && (!cap.kf || cs.kslots > cap.kslots || cs.nzq > cap.nzq)))
+            (cs.kf && (!cap.kf || cs.kslots > cap.kslots || cs.nzq > cap.nzq || cs.nf > cap.nf)))
             return fail(LBM_ENOMEM, "closure does not fit the workspace planned at creation");
         if (cs.h > 0 && cl->spinup < c->host_step + cs.h)
             return fail(LBM_EINVAL, "closure: spinup must be at least the step count plus the history length");
@@ -853,6 +915,7 @@ int lbm_create(const lbm_config* cfg, const lbm_closure* closure, void* dev_aren
     if (rc) {
         if (c->qref_dev) hipFree(c->qref_dev);
         if (c->chist_dev) hipFree(c->chist_dev);
+        drop_fourier(c);
         if (c->own_stream) hipStreamDestroy(c->stream);
         delete c;
         return rc;
@@ -868,6 +931,7 @@ void lbm_destroy(lbm_ctx* c)
     drop_graphs(c);
     if (c->qref_dev) hipFree(c->qref_dev);
     if (c->chist_dev) hipFree(c->chist_dev);
+    drop_fourier(c);
     if (c->own_stream) hipStreamDestroy(c->stream);
     delete c;
 }
@@ -902,7 +966,7 @@ int lbm_step(lbm_ctx* c, long n)
 {
     if (!c || n < 0) return fail(LBM_EINVAL, "bad arguments");
     while (n > 0) {
-        if (n >= c->gchunk) {
+        if (n >= c->gchunk && !c->cur.nf) {   // hipFFT runs outside graphs
             const int ph = c->phase;
             if (!c->gexec[ph] || c->gver[ph] != c->version) {
                 if (c->gexec[ph]) hipGraphExecDestroy(c->gexec[ph]);
@@ -1256,6 +1320,7 @@ static int batch_build(lbm_batch* b)
                 g.kjobs = (const KJob*)(c->arena + c->plan.kjobs);
                 g.klev = c->klev.data();
                 g.nklev = (int)c->klev.size();
+                g.fprog = c->cur.nf ? &c->fprog : nullptr;
             }
         }
         g.mems = b->dmem;
@@ -1303,9 +1368,11 @@ int lbm_batch_step(lbm_batch* b, long n)
         int rc = batch_build(b);
         if (rc) return rc;
     }
+    bool fft = false;   // hipFFT runs outside graphs
+    for (const LaunchGroup& g : b->groups) fft = fft || g.fprog;
     long left = n;
     while (left > 0) {
-        if (left >= b->gchunk) {
+        if (left >= b->gchunk && !fft) {
             const int ph = b->phase;
             if (!b->graph_ok[ph]) {
                 int rc = capture(b->stream, b->groups, b->gchunk, ph, &b->gexec[ph]);

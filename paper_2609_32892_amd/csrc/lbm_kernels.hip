@@ -22,7 +22,10 @@
 // All reductions have a fixed order that depends only on the member's own
 // geometry, so a member gives bitwise the same result alone or in a batch.
 #include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
 #include <math.h>
+
+#include <type_traits>
 
 #include "lbm_dev.h"
 #include "lbm_launch.h"
@@ -1502,6 +1505,82 @@ __global__ __launch_bounds__(kBlock) void k_kjob(const DevMember* __restrict__ m
 }
 
 // ---------------------------------------------------------------------------
+// Sharp Fourier band filters (eq. scale-aware-energy-fourier) through hipFFT:
+// real fields into complex ones, forward transforms, per QoI the band mask
+// (l - 1/2 <= |k| < m + 1/2, integer mode indices; with the 1/N of the
+// inverse transform), the inverse transform and the real part.
+// ---------------------------------------------------------------------------
+template <typename T, typename CT>
+__global__ __launch_bounds__(kBlock) void k_fpack(const T* __restrict__ src, CT* __restrict__ dst, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    CT c;
+    c.x = src[i];
+    c.y = T(0);
+    dst[i] = c;
+}
+
+template <typename T, typename CT>
+__global__ __launch_bounds__(kBlock) void k_fmask(const CT* __restrict__ spec, CT* __restrict__ out, int ncomp,
+                                                  int nx, int ny, int nz, int l, int m)
+{
+    const size_t N = (size_t)nx * ny * nz;
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= N * ncomp) return;
+    const size_t cell = i % N;
+    const int jx = (int)(cell % nx), jy = (int)((cell / nx) % ny), jz = (int)(cell / ((size_t)nx * ny));
+    const int kx = jx <= nx / 2 ? jx : jx - nx, ky = jy <= ny / 2 ? jy : jy - ny, kz = jz <= nz / 2 ? jz : jz - nz;
+    const double kn = sqrt((double)kx * kx + (double)ky * ky + (double)kz * kz);
+    const bool keep = kn >= l - 0.5 && kn < m + 0.5;
+    const T s = keep ? T(1.0 / (double)N) : T(0);
+    CT c = spec[i];
+    c.x *= s;
+    c.y *= s;
+    out[i] = c;
+}
+
+template <typename T, typename CT>
+__global__ __launch_bounds__(kBlock) void k_funpack(const CT* __restrict__ src, T* __restrict__ dst, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    dst[i] = src[i].x;
+}
+
+template <int LAT, typename T>
+static void launch_fourier(const FourierProg& f, hipStream_t st)
+{
+    using L = Lat<LAT>;
+    const int nx = f.nx, ny = f.ny, nz = f.nz;
+    using CT = typename std::conditional<std::is_same<T, float>::value, float2, double2>::type;
+    const size_t N = (size_t)nx * ny * nz;
+    const dim3 blk(kBlock);
+    auto grid = [&](size_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); };
+    auto exec = [&](void* plan, void* data, int dir) {
+        hipfftHandle h = (hipfftHandle)plan;
+        hipfftSetStream(h, st);
+        if constexpr (std::is_same<T, float>::value)
+            hipfftExecC2C(h, (hipfftComplex*)data, (hipfftComplex*)data, dir);
+        else
+            hipfftExecZ2Z(h, (hipfftDoubleComplex*)data, (hipfftDoubleComplex*)data, dir);
+    };
+    hipLaunchKernelGGL((k_fpack<T, CT>), grid(L::D * N), blk, 0, st, (const T*)f.vs, (CT*)f.spec_v, L::D * N);
+    exec(f.plan[0], f.spec_v, HIPFFT_FORWARD);
+    if (f.nz_q) {
+        hipLaunchKernelGGL((k_fpack<T, CT>), grid(L::NC * N), blk, 0, st, (const T*)f.w, (CT*)f.spec_w, L::NC * N);
+        exec(f.plan[1], f.spec_w, HIPFFT_FORWARD);
+    }
+    for (const FourierQ& q : f.q) {
+        const int nc = q.e ? L::D : L::NC;
+        hipLaunchKernelGGL((k_fmask<T, CT>), grid(nc * N), blk, 0, st, (const CT*)(q.e ? f.spec_v : f.spec_w),
+                           (CT*)f.tmp, nc, nx, ny, nz, q.l, q.m);
+        exec(f.plan[q.e ? 0 : 1], f.tmp, HIPFFT_BACKWARD);
+        hipLaunchKernelGGL((k_funpack<T, CT>), grid(nc * N), blk, 0, st, (const CT*)f.tmp, (T*)q.dst, nc * N);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Diagnostics of plain runs: E and Z of the post-streaming velocity.
 // ---------------------------------------------------------------------------
 template <int LAT, typename T>
@@ -1751,6 +1830,7 @@ to_chain:
         if (g.any_z) hipLaunchKernelGGL((k_curl<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1);
         mark(2);
         if (g.kf) {
+            if (g.fprog) launch_fourier<LAT, T>(*g.fprog, st);
             for (int l = 0; l < g.nklev; ++l)
                 hipLaunchKernelGGL((k_kjob<LAT, T>), dim3(g.nb1, g.klev[l].y), blk, 0, st, g.mems, g.work1,
                                    g.kjobs + g.klev[l].x);

@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "lbm_dev.h"
 
 namespace lbm {
@@ -19,6 +21,22 @@ struct KJob {
     const void* taps[3];   // 2 radius + 1 values each, element type of the run
     const void* src[3];
     void* dst;
+};
+
+// Fourier band QoIs of a member (host side): spectra of v* and w, a work
+// spectrum, and per QoI the band and the destination of R v* (E: V_s) or of
+// R w (Z: the input of its adjoint curl).  Plans are hipfftHandle values.
+struct FourierQ { int e, l, m; void* dst; };
+struct FourierProg {
+    void* plan[2];        // batch D (velocity) and batch NC (vorticity)
+    void* spec_v;         // [D][N] complex
+    void* spec_w;         // [NC][N] complex (Z QoIs only)
+    void* tmp;            // [3][N] complex
+    const void* vs;       // v* [D][N]
+    const void* w;        // w [NC][N]
+    int nz_q;             // Z QoIs present
+    int nx, ny, nz;
+    std::vector<FourierQ> q;
 };
 
 // One launch per kernel phase covers every member of a group: members share
@@ -46,6 +64,7 @@ struct LaunchGroup {
     const KJob* kjobs;  // replace the binomial passes; kjobs in device memory,
     const int2* klev;   // klev[l] = (first job, job count) of level l (host memory)
     int nklev;
+    const FourierProg* fprog;   // Fourier band QoIs (host memory; null if none)
 };
 
 enum { OP_INIT = 0, OP_GET_POP = 1, OP_SET_POP = 2, OP_STREAM = 3 };

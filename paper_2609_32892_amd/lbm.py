@@ -26,10 +26,14 @@ KFILT = {"G": 5, "L": 6}   # kernel filters with a scale: "G3" = G_3, "L1" = L_1
 
 
 def filter_code(name):
-    """(filter enum, scale) of a filter name: I, B, B2, BMID, IMB, G<s>, L<s>."""
+    """(filter enum, scale, kmax) of a filter name: I, B, B2, BMID, IMB, G<s>,
+    L<s>, or F<l>-<m> for the sharp Fourier band R_[l,m]."""
     if name in FILT:
-        return FILT[name], 0
-    return KFILT[name[0]], int(name[1:])
+        return FILT[name], 0, 0
+    if name[0] == "F":
+        lo, hi = name[1:].split("-")
+        return 7, int(lo), int(hi)
+    return KFILT[name[0]], int(name[1:]), 0
 MODE = {"off": 0, "track": 1, "lrs": 2}
 PRECISION = {"fp32": FP32_SHIFTED, "fp64": FP64, "fp32_plain": FP32_PLAIN}
 
@@ -49,7 +53,8 @@ class Config(ct.Structure):
 
 
 class QoiSpec(ct.Structure):
-    _fields_ = [("kind", ct.c_int), ("filter", ct.c_int), ("band", ct.c_int), ("scale", ct.c_int)]
+    _fields_ = [("kind", ct.c_int), ("filter", ct.c_int), ("band", ct.c_int), ("scale", ct.c_int),
+                ("kmax", ct.c_int)]
 
 
 class Closure(ct.Structure):
@@ -209,8 +214,8 @@ class ClosureSpec:
         self.nq = nq
         self._q = (QoiSpec * nq)()
         for k, (kind, filt, band) in enumerate(qois):
-            code, sc = filter_code(filt)
-            self._q[k] = QoiSpec({"E": QOI_E, "Z": QOI_Z, "MP": QOI_MP}[kind], code, band, sc)
+            code, sc, km = filter_code(filt)
+            self._q[k] = QoiSpec({"E": QOI_E, "Z": QOI_Z, "MP": QOI_MP}[kind], code, band, sc, km)
         arr = lambda a, n: None if a is None else np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(n))
         self._C = arr(C, ((2 * h + 1) * nq + 1) * nq)
         self._mu = arr(mu, nq)

@@ -121,3 +121,16 @@ def test_kernel_filter_closure_validation(lbm):
     c2 = lbm.make_config(nx=32, ny=32)
     assert L.lbm_required_bytes(ct.byref(c2), ct.byref(lbm.ClosureSpec([("E", "G3", 0)]).c)) > 0   # radius 12
     assert L.lbm_required_bytes(ct.byref(c2), ct.byref(lbm.ClosureSpec([("E", "G4", 0)]).c)) == 0  # radius 16
+
+
+def test_fourier_closure_validation(lbm):
+    """Sharp Fourier band QoIs (eq. scale-aware-energy-fourier): periodic
+    grids only, 0 <= l <= m; they may be mixed with the kernel filters."""
+    L = lbm.lib()
+    per = lbm.make_config(nx=32, ny=32)
+    walls = lbm.make_config(nx=32, ny=32, walls_y=1)
+    ok = lbm.ClosureSpec([("E", "F0-4", 0), ("Z", "F5-12", 0), ("E", "G3", 0)])
+    assert L.lbm_required_bytes(ct.byref(per), ct.byref(ok.c)) > 0
+    assert L.lbm_required_bytes(ct.byref(walls), ct.byref(ok.c)) == 0
+    assert L.lbm_required_bytes(ct.byref(per), ct.byref(lbm.ClosureSpec([("E", "F5-4", 0)]).c)) == 0
+    assert L.lbm_required_bytes(ct.byref(per), ct.byref(lbm.ClosureSpec([("E", "F0-4", 0), ("Z", "B", 0)]).c)) == 0
