@@ -1463,33 +1463,51 @@ __global__ __launch_bounds__(kBlock) void k_kjob(const DevMember* __restrict__ m
         const int stride = axis == 0 ? 1 : (axis == 1 ? nx : nx * ny);
         const bool pad = axis == 1 && m.walls;
         const size_t line = (size_t)cell - (size_t)pos * stride;   // first cell of this cell's line
-        for (int c = 0; c < j.ncomp; ++c) {
-            T out = 0;
-            for (int tt = 0; tt < j.nterm; ++tt) {
-                const T* __restrict__ sc = (const T*)j.src[tt] + (size_t)c * N + line;
-                const T* __restrict__ tp = (const T*)j.taps[tt];
-                const int rad = j.radius[tt];
-                T sum = 0;
-                if (pos - rad >= 0 && pos + rad < n) {
-                    // the whole stencil inside the line: no wrap, no padding
-                    const T* __restrict__ q = sc + (size_t)(pos - rad) * stride;
-                    for (int r = 0; r <= 2 * rad; ++r) sum += tp[r] * q[(size_t)r * stride];
-                } else {
-                    for (int r = -rad; r <= rad; ++r) {
-                        int p = pos + r;
-                        if (pad) {
-                            if (p < 0 || p >= n) continue;
-                        } else {
-                            p %= n;
-                            if (p < 0) p += n;
-                        }
-                        sum += tp[r + rad] * sc[(size_t)p * stride];
-                    }
+        // all components at once (up to three load streams in flight; a
+        // component past ncomp re-reads component 0 and is not stored)
+        const int nc = j.ncomp;
+        const size_t o1 = nc > 1 ? (size_t)N : 0, o2 = nc > 2 ? 2 * (size_t)N : 0;
+        T out[3] = {0, 0, 0};
+        for (int tt = 0; tt < j.nterm; ++tt) {
+            const T* __restrict__ sc = (const T*)j.src[tt] + line;
+            const LBM_K T* tp = kc((const T*)j.taps[tt]);   // uniform: scalar loads
+            const int rad = j.radius[tt];
+            T s0 = 0, s1 = 0, s2 = 0;
+            if (pos - rad >= 0 && pos + rad < n) {
+                // the whole stencil inside the line: no wrap, no padding
+                const T* __restrict__ q = sc + (size_t)(pos - rad) * stride;
+#pragma unroll 2
+                for (int r = 0; r <= 2 * rad; ++r) {
+                    const T t = tp[r];
+                    const size_t k = (size_t)r * stride;
+                    s0 += t * q[k];
+                    s1 += t * q[o1 + k];
+                    s2 += t * q[o2 + k];
                 }
-                out += T(j.coef[tt]) * sum;
+            } else {
+                for (int r = -rad; r <= rad; ++r) {
+                    int p = pos + r;
+                    if (pad) {
+                        if (p < 0 || p >= n) continue;
+                    } else {
+                        p %= n;
+                        if (p < 0) p += n;
+                    }
+                    const T t = tp[r + rad];
+                    const size_t k = (size_t)p * stride;
+                    s0 += t * sc[k];
+                    s1 += t * sc[o1 + k];
+                    s2 += t * sc[o2 + k];
+                }
             }
-            dst[(size_t)c * N + cell] = out;
+            const T cf = T(j.coef[tt]);
+            out[0] += cf * s0;
+            out[1] += cf * s1;
+            out[2] += cf * s2;
         }
+        dst[cell] = out[0];
+        if (nc > 1) dst[(size_t)N + cell] = out[1];
+        if (nc > 2) dst[2 * (size_t)N + cell] = out[2];
         return;
     }
     const T* __restrict__ src = (const T*)j.src[0];
