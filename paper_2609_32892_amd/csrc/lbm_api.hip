@@ -1511,7 +1511,10 @@ struct ClosureCopy {
             v.assign(p, p + n);
             return v.data();
         };
-        c.C = cp(src->C, (size_t)(nq + 1) * nq, C);
+        // ((2h+1) nq + 1) x nq for a history model (out-of-range h is
+        // rejected later by the closure checks; copy the h = 0 shape then)
+        const int h = src->h >= 0 && src->h <= LBM_MAX_HIST ? src->h : 0;
+        c.C = cp(src->C, ((size_t)(2 * h + 1) * nq + 1) * nq, C);
         c.mu = cp(src->mu, nq, mu);
         c.Sigma = cp(src->Sigma, (size_t)nq * nq, Sigma);
         c.scale = cp(src->scale, nq, scale);

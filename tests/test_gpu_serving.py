@@ -97,3 +97,34 @@ def test_server_isolates_unstable_request():
         alone, _ = _alone(lbm, cfg, spec, u0, steps)
         assert hashlib.sha256(srv.take_state(rid)).digest() == hashlib.sha256(alone).digest()
     srv.close()
+
+
+def test_server_kernel_filter_fourier_and_history_requests():
+    """Requests whose closures use the kernel filters, Fourier bands (eager
+    stepping) and a history-h LRS model, served together with a binomial
+    one: every result bitwise equal to the request run alone."""
+    lbm = need_gpu()
+    reqs = []
+    n = 32
+    cfg, _ = synth.kolmogorov_workload(n, tau=0.51, seed=7)
+    u0 = synth.noise_velocity(2, (1, n, n), 1e-3, 7)
+    for qois, h in (([(k, f, 0) for f in ("G3", "L1") for k in ("E", "Z")], 0),
+                    ([(k, f, 0) for f in ("F0-4", "F5-12") for k in ("E", "Z")], 0),
+                    (synth.QOIS_2D, 6)):
+        C, mu, S = synth.lrs_history_model(h, len(qois), 3, 4, 5, noise=1e-4)
+        spec = lbm.ClosureSpec(qois, mode="lrs", spinup=8, C=C, mu=mu, Sigma=S, seed=61, h=h,
+                               scale=np.full(len(qois), 1e-3) if h else None)
+        reqs.append((lbm.make_config(precision="fp32", **cfg), spec, u0, 30))
+    qois, cargs = closure_args("2d", spinup=5, seed=62)
+    reqs.append((lbm.make_config(precision="fp32", **cfg), lbm.ClosureSpec(qois, **cargs), u0, 30))
+    srv = lbm.Server()
+    t0 = srv.clock()
+    ids = [srv.submit(c, s, u, st, t0, keep_state=True) for c, s, u, st in reqs]
+    results = _drive(lbm, srv)
+    assert len(results) == len(reqs) and all(r.status == 0 for r in results)
+    for rid, (cfg_r, spec, u, steps) in zip(ids, reqs):
+        img = srv.take_state(rid)
+        alone, status = _alone(lbm, cfg_r, spec, u, steps)
+        assert status == 0
+        assert hashlib.sha256(img).digest() == hashlib.sha256(alone).digest(), f"request {rid} differs"
+    srv.close()
