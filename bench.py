@@ -280,6 +280,58 @@ def form_fourier(lbm, steps):
     return out
 
 
+def form_paper_table(lbm, steps):
+    """The rows of the paper's 3-D timing table (tab:timing-3d, H100, FP32)
+    that run on the LF channel grid, here on 295 x 47 x 98 fluid rows (the
+    paper's 295 x 49 x 98 with its two solid rows not stored): no model,
+    Smagorinsky, WALE, TO tracking and TO-LRS with the paper's 12 QoIs
+    ({E, Z} x {G3, L3, L1} + 6 bands).  ms per step, MLUPS over fluid nodes,
+    and the paper's ms per step beside them."""
+    import numpy as np
+    import synth
+    nx, ny, nz = 295, 47, 98
+    N = nx * ny * nz
+    nb, dmin, dmax = synth.channel_bands(ny)
+    qois = [(k, f, 0) for f in ("G3", "L3", "L1") for k in ("E", "Z")] + [("MP", "I", j) for j in range(nb)]
+    C, mu, S = synth.lrs_model_channel(12, 7, 9)
+    paper_ms = {"no_model": 0.81, "smagorinsky": 1.07, "wale": 1.04, "to_tracking": 11.45, "to_lrs": 11.38}
+    out = {"grid": [nx, ny, nz], "steps": steps}
+    for name in ("no_model", "smagorinsky", "wale", "to_tracking", "to_lrs"):
+        sub, cm = {"smagorinsky": (1, 0.1), "wale": (2, 2.2)}.get(name, (0, 0.0))
+        if name.startswith("to_"):
+            sub, cm = 1, 0.1
+        cfg, u0 = synth.channel_workload(nx, ny, nz, substrate=sub, cmodel=cm, seed=6)
+        spec = None
+        if name == "to_lrs":
+            spec = lbm.ClosureSpec(qois, mode="lrs", spinup=10, C=C, mu=mu, Sigma=S, seed=8, nbands=nb,
+                                   dmin=dmin, dmax=dmax)
+        elif name == "to_tracking":
+            # the reference: the uncorrected run's own QoIs, scaled by 1.01
+            ref = lbm.Run(lbm.make_config(precision="fp32", **cfg),
+                          lbm.ClosureSpec(qois, mode="off", nbands=nb, dmin=dmin, dmax=dmax))
+            ref.init_velocity(u0)
+            ref.step(20 + steps)
+            ref.sync()
+            qref = 1.01 * ref.record_arrays()["q"]
+            ref.close()
+            spec = lbm.ClosureSpec(qois, mode="track", spinup=10, qref=qref, nbands=nb, dmin=dmin, dmax=dmax)
+        r = lbm.Run(lbm.make_config(precision="fp32", **cfg), spec)
+        r.init_velocity(u0)
+        r.step(20)
+        r.sync()
+        t = time.perf_counter()
+        r.step(steps)
+        try:
+            r.sync()
+        except lbm.LbmError as e:
+            out[name + "_error"] = str(e)
+        dt = time.perf_counter() - t
+        r.close()
+        out[name] = {"ms_per_step": round(dt / steps * 1e3, 4), "mlups": round(N * steps / dt / 1e6, 1),
+                     "paper_ms_per_step": paper_ms[name]}
+    return out
+
+
 def form_batched(lbm, nmem, steps):
     """System form (2): an ensemble of Kolmogorov TO-LES members on uneven
     grids advanced as one batch (one launch per kernel phase for all members,
@@ -542,6 +594,8 @@ def main():
         print(f"[bench] precision forms: {forms['precision']}", file=sys.stderr, flush=True)
         forms["kernel_filters"] = form_kernel_filters(lbm, w, 1000)
         print(f"[bench] kernel filters: {forms['kernel_filters']}", file=sys.stderr, flush=True)
+        forms["paper_timing_table"] = form_paper_table(lbm, 500)
+        print(f"[bench] paper timing table: {forms['paper_timing_table']}", file=sys.stderr, flush=True)
         forms["fourier_bands"] = form_fourier(lbm, 1000)
         print(f"[bench] Fourier bands: {forms['fourier_bands']}", file=sys.stderr, flush=True)
         forms["history_lrs"] = form_history(lbm, w, 2000)
