@@ -207,3 +207,22 @@ def test_train_then_online_workflow():
     span = hi - lo
     _say(f"  online corrected QoIs in [{qc.min(axis=0)}, {qc.max(axis=0)}], targets [{lo}, {hi}]")
     assert np.all(qc.min(axis=0) > lo - span) and np.all(qc.max(axis=0) < hi + span)
+
+
+def test_history_checkpoint_resume_bitwise():
+    """The history of a history-h model is the record ring, which the
+    checkpoint image carries: resuming mid-run (after activation) is bitwise
+    equal to the uninterrupted run."""
+    lbm = need_gpu()
+    cfg, u0, qois, cargs = _case2d(12, 15, n=32, ny=32)
+    a = gpu_run(lbm, cfg, u0, "fp32", qois, cargs)
+    a.step(25)
+    img = a.get_state()
+    a.step(30)
+    b = gpu_run(lbm, cfg, np.zeros_like(u0), "fp32", qois, cargs)
+    b.set_state(img)
+    assert b.step_count == 25
+    b.step(30)
+    assert np.array_equal(a.get_populations(), b.get_populations())
+    ra, rb = a.record_arrays(25, 30), b.record_arrays(25, 30)
+    assert np.array_equal(ra["dq"], rb["dq"]) and np.any(ra["dq"] != 0)
