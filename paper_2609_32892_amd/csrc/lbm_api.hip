@@ -63,7 +63,7 @@ struct ClosureShape {
     int h = 0, nhc = 0;   // LRS history length; k_sum workgroups of its product
     int kf = 0;           // E/Z QoIs use the kernel filters (materialised sensitivities)
     int kslots = 0, nzq = 0;   // kernel filters: separable terms over the QoIs; Z QoIs
-    int nf = 0;                // Fourier band QoIs
+    int nf = 0, nfz = 0;       // Fourier band QoIs; of them Z QoIs
     int npart() const { return nsa + nsa * (nsa + 1) / 2 + nmp * (1 + nsa); }
 };
 
@@ -103,6 +103,7 @@ int closure_shape(const lbm_config* cfg, const lbm_closure* cl, ClosureShape* ou
             if (q.scale < 0 || q.kmax < q.scale) return fail(LBM_EINVAL, "closure: QoI %d Fourier band [l,m] needs 0 <= l <= m", k);
             s.kf = 1;
             s.nf++;
+            s.nfz += q.kind == LBM_QOI_Z;
         } else if (q.filter == LBM_FILT_GAUSS || q.filter == LBM_FILT_LAPL) {
             const int d = cfg->lattice == LBM_D2Q9 ? 2 : 3;
             const int rad = q.filter == LBM_FILT_GAUSS ? (d == 2 ? 4 : 2) * q.scale : (5 * q.scale - 1) / 2;
@@ -168,7 +169,7 @@ int check_config(const lbm_config* c)
 struct Plan {
     size_t member, param, ctl, recs, g0, g1, fprof, vn, part_stats, part_diag, work1, workm;
     size_t rho, vs, P, W, Cf, part_to, bandw, cmp, workr, workb, sums, works, hpart, kV, kT, ktaps, kjobs;
-    size_t fspec_v, fspec_w, ftmp;
+    size_t fspec_v, fspec_w, fband_e, fband_z;
     size_t total;
     int N, D, NC, Q, esz, nb1, nbx2, cpt2, nbr, nbb, nbs, zc, btx, rec_cap;
     ClosureShape cap;
@@ -248,7 +249,8 @@ void make_plan(const lbm_config* c, const ClosureShape& cs, Plan* p)
                 // Fourier bands: spectra of v* and w and one work spectrum (complex)
                 P.fspec_v = take(2 * e * P.D * N);
                 P.fspec_w = take(2 * e * P.NC * N);
-                P.ftmp = take(2 * e * 3 * N);
+                P.fband_e = take(2 * e * P.D * N * (size_t)std::max(cs.nf - cs.nfz, 1));
+                P.fband_z = take(2 * e * P.NC * N * (size_t)std::max(cs.nfz, 1));
             }
         }
     }
@@ -441,7 +443,7 @@ void drop_graphs(lbm_ctx* c)
 // in place, dimensions z, y, x) and the program that launch_fourier runs.
 void drop_fourier(lbm_ctx* c)
 {
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 4; ++k)
         if (c->fprog.plan[k]) hipfftDestroy((hipfftHandle)c->fprog.plan[k]);
     c->fprog = FourierProg{};
 }
@@ -456,8 +458,10 @@ int build_fourier(lbm_ctx* c, const std::vector<FourierQ>& fq)
     const int rank = D == 3 ? 3 : 2;
     int* dims = D == 3 ? n : n + 1;
     const hipfftType type = c->cfg.precision == LBM_FP64 ? HIPFFT_Z2Z : HIPFFT_C2C;
-    const int batch[2] = {D, NC};
-    for (int k = 0; k < 2; ++k) {
+    for (const FourierQ& q : fq) (q.e ? f.qe : f.qz).push_back(q);
+    const int batch[4] = {D, NC, (int)f.qe.size() * D, (int)f.qz.size() * NC};
+    for (int k = 0; k < 4; ++k) {
+        if (batch[k] == 0) continue;
         hipfftHandle h;
         if (hipfftPlanMany(&h, rank, dims, nullptr, 1, N, nullptr, 1, N, type, batch[k]) != HIPFFT_SUCCESS) {
             drop_fourier(c);
@@ -468,12 +472,11 @@ int build_fourier(lbm_ctx* c, const std::vector<FourierQ>& fq)
     char* A = c->arena;
     f.spec_v = A + c->plan.fspec_v;
     f.spec_w = A + c->plan.fspec_w;
-    f.tmp = A + c->plan.ftmp;
+    f.band_e = A + c->plan.fband_e;
+    f.band_z = A + c->plan.fband_z;
     f.vs = A + c->plan.vs;
     f.w = A + c->plan.W;
     f.nx = c->cfg.nx; f.ny = c->cfg.ny; f.nz = c->cfg.nz;
-    f.q = fq;
-    for (const FourierQ& q : fq) f.nz_q |= !q.e;
     return LBM_OK;
 }
 
@@ -619,7 +622,8 @@ int apply_closure(lbm_ctx* c, const lbm_closure* cl)
         const ClosureShape& cap = c->plan.cap;
         if (!c->has_to || cs.nsa > cap.nsa || cs.jv > cap.jv || (cs.has_z && (!cap.has_z || cs.jw > cap.jw)) ||
             cs.npart() > cap.npart() || cs.nbands > std::max(cap.nbands, 1) || cs.nhc > cap.nhc ||
-            (cs.kf && (!cap.kf || cs.kslots > cap.kslots || cs.nzq > cap.nzq || cs.nf > cap.nf)))
+            (cs.kf && (!cap.kf || cs.kslots > cap.kslots || cs.nzq > cap.nzq || cs.nf - cs.nfz > cap.nf - cap.nfz ||
+                       cs.nfz > cap.nfz)))
             return fail(LBM_ENOMEM, "closure does not fit the workspace planned at creation");
         if (cs.h > 0 && cl->spinup < c->host_step + cs.h)
             return fail(LBM_EINVAL, "closure: spinup must be at least the step count plus the history length");

@@ -1539,9 +1539,13 @@ __global__ __launch_bounds__(kBlock) void k_fpack(const T* __restrict__ src, CT*
     dst[i] = c;
 }
 
+struct FBands { int nb, l[kMaxBands], m[kMaxBands]; };
+template <typename T> struct FDst { T* d[kMaxBands]; };
+
+// the masked spectrum of every band, out[b][comp][cell]
 template <typename T, typename CT>
 __global__ __launch_bounds__(kBlock) void k_fmask(const CT* __restrict__ spec, CT* __restrict__ out, int ncomp,
-                                                  int nx, int ny, int nz, int l, int m)
+                                                  int nx, int ny, int nz, FBands bands)
 {
     const size_t N = (size_t)nx * ny * nz;
     const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
@@ -1550,20 +1554,24 @@ __global__ __launch_bounds__(kBlock) void k_fmask(const CT* __restrict__ spec, C
     const int jx = (int)(cell % nx), jy = (int)((cell / nx) % ny), jz = (int)(cell / ((size_t)nx * ny));
     const int kx = jx <= nx / 2 ? jx : jx - nx, ky = jy <= ny / 2 ? jy : jy - ny, kz = jz <= nz / 2 ? jz : jz - nz;
     const double kn = sqrt((double)kx * kx + (double)ky * ky + (double)kz * kz);
-    const bool keep = kn >= l - 0.5 && kn < m + 0.5;
-    const T s = keep ? T(1.0 / (double)N) : T(0);
-    CT c = spec[i];
-    c.x *= s;
-    c.y *= s;
-    out[i] = c;
+    const CT c = spec[i];
+    for (int b = 0; b < bands.nb; ++b) {
+        const bool keep = kn >= bands.l[b] - 0.5 && kn < bands.m[b] + 0.5;
+        const T s = keep ? T(1.0 / (double)N) : T(0);
+        CT o;
+        o.x = c.x * s;
+        o.y = c.y * s;
+        out[(size_t)b * ncomp * N + i] = o;
+    }
 }
 
+// the real parts of the inverse transforms into each band's destination
 template <typename T, typename CT>
-__global__ __launch_bounds__(kBlock) void k_funpack(const CT* __restrict__ src, T* __restrict__ dst, size_t n)
+__global__ __launch_bounds__(kBlock) void k_funpack(const CT* __restrict__ src, FDst<T> dst, int nb, size_t n)
 {
     const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    dst[i] = src[i].x;
+    if (i >= n * nb) return;
+    dst.d[i / n][i % n] = src[i].x;
 }
 
 template <int LAT, typename T>
@@ -1583,18 +1591,27 @@ static void launch_fourier(const FourierProg& f, hipStream_t st)
         else
             hipfftExecZ2Z(h, (hipfftDoubleComplex*)data, (hipfftDoubleComplex*)data, dir);
     };
-    hipLaunchKernelGGL((k_fpack<T, CT>), grid(L::D * N), blk, 0, st, (const T*)f.vs, (CT*)f.spec_v, L::D * N);
-    exec(f.plan[0], f.spec_v, HIPFFT_FORWARD);
-    if (f.nz_q) {
-        hipLaunchKernelGGL((k_fpack<T, CT>), grid(L::NC * N), blk, 0, st, (const T*)f.w, (CT*)f.spec_w, L::NC * N);
-        exec(f.plan[1], f.spec_w, HIPFFT_FORWARD);
-    }
-    for (const FourierQ& q : f.q) {
-        const int nc = q.e ? L::D : L::NC;
-        hipLaunchKernelGGL((k_fmask<T, CT>), grid(nc * N), blk, 0, st, (const CT*)(q.e ? f.spec_v : f.spec_w),
-                           (CT*)f.tmp, nc, nx, ny, nz, q.l, q.m);
-        exec(f.plan[q.e ? 0 : 1], f.tmp, HIPFFT_BACKWARD);
-        hipLaunchKernelGGL((k_funpack<T, CT>), grid(nc * N), blk, 0, st, (const CT*)f.tmp, (T*)q.dst, nc * N);
+    for (int kind = 0; kind < 2; ++kind) {   // E bands (of v*), then Z bands (of w)
+        const std::vector<FourierQ>& qs = kind == 0 ? f.qe : f.qz;
+        if (qs.empty()) continue;
+        const int nc = kind == 0 ? L::D : L::NC;
+        void* spec = kind == 0 ? f.spec_v : f.spec_w;
+        void* band = kind == 0 ? f.band_e : f.band_z;
+        hipLaunchKernelGGL((k_fpack<T, CT>), grid(nc * N), blk, 0, st, (const T*)(kind == 0 ? f.vs : f.w), (CT*)spec,
+                           nc * N);
+        exec(f.plan[kind], spec, HIPFFT_FORWARD);
+        FBands fb{};
+        FDst<T> fd{};
+        fb.nb = (int)qs.size();
+        for (size_t b = 0; b < qs.size(); ++b) {
+            fb.l[b] = qs[b].l;
+            fb.m[b] = qs[b].m;
+            fd.d[b] = (T*)qs[b].dst;
+        }
+        hipLaunchKernelGGL((k_fmask<T, CT>), grid(nc * N), blk, 0, st, (const CT*)spec, (CT*)band, nc, nx, ny, nz, fb);
+        exec(f.plan[2 + kind], band, HIPFFT_BACKWARD);
+        hipLaunchKernelGGL((k_funpack<T, CT>), grid(qs.size() * nc * N), blk, 0, st, (const CT*)band, fd, fb.nb,
+                           nc * N);
     }
 }
 

@@ -23,20 +23,22 @@ struct KJob {
     void* dst;
 };
 
-// Fourier band QoIs of a member (host side): spectra of v* and w, a work
-// spectrum, and per QoI the band and the destination of R v* (E: V_s) or of
-// R w (Z: the input of its adjoint curl).  Plans are hipfftHandle values.
+// Fourier band QoIs of a member (host side): spectra of v* and w, the
+// masked band spectra of all E QoIs and of all Z QoIs, and per QoI the band
+// and the destination of R v* (E: V_s) or of R w (Z: the input of its
+// adjoint curl).  Plans are hipfftHandle values.
+constexpr int kMaxBands = kMaxSA;   // every E/Z QoI may be a band
 struct FourierQ { int e, l, m; void* dst; };
 struct FourierProg {
-    void* plan[2];        // batch D (velocity) and batch NC (vorticity)
+    void* plan[4];        // forward: batch D (v*), batch NC (w); inverse: all E bands, all Z bands
     void* spec_v;         // [D][N] complex
     void* spec_w;         // [NC][N] complex (Z QoIs only)
-    void* tmp;            // [3][N] complex
+    void* band_e;         // [nE][D][N] complex
+    void* band_z;         // [nZ][NC][N] complex
     const void* vs;       // v* [D][N]
     const void* w;        // w [NC][N]
-    int nz_q;             // Z QoIs present
     int nx, ny, nz;
-    std::vector<FourierQ> q;
+    std::vector<FourierQ> qe, qz;   // E and Z bands
 };
 
 // One launch per kernel phase covers every member of a group: members share
