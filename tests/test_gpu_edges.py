@@ -1,0 +1,169 @@
+"""Edge cases of the TO-LES path on the GPU against the FP64 oracle: the
+smallest grids the library accepts (3 cells per axis, where every stencil
+and filter wraps or pads on itself, and the kernel filters of radius up to
+12 wrap several times), ragged grids that fill no binomial tile or z chunk,
+and the degenerate closures: one whose activation lies past the run, a
+tracking reference shorter than the run, and zero steps."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import closure_args, gpu_run, need_gpu, oracle_run, rel_err
+
+pytestmark = pytest.mark.gpu
+
+KQ2 = [(k, f, 0) for f in ("G3", "L3", "L1") for k in ("E", "Z")]
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _k2(nx, ny, walls, seed=3):
+    """A small 2-D Kolmogorov (periodic) or channel-forced (walls) grid."""
+    cfg, _ = synth.kolmogorov_workload(nx, tau=0.55, amp=1e-5, k=1, seed=seed)
+    cfg["ny"] = ny
+    if walls:
+        cfg.update(walls_y=1, force_kind=2, force_amp=1e-6)
+    return cfg, synth.noise_velocity(2, (1, ny, nx), 1e-3, seed)
+
+
+def _lrs(nq, seed=31):
+    C, mu, S = synth.lrs_history_model(0, nq, 3, 4, 5, noise=1e-4)
+    return dict(mode="lrs", spinup=5, C=C, mu=mu, Sigma=S, seed=seed)
+
+
+def _cases():
+    out = {}
+    qois2, ca2 = closure_args("2d", spinup=5)
+    for walls in (0, 1):
+        cfg, u0 = _k2(3, 3, walls)
+        out[f"binomial_3x3_walls{walls}"] = (cfg, u0, qois2, ca2, {})
+    # 3 x 3 x 3 channel: two mean-profile bands (three make the Gram matrix
+    # singular to within 2e-15 of its largest diagonal entry on three rows)
+    cfg, u0 = synth.channel_workload(3, 3, 3, substrate=1, cmodel=0.1)
+    q3 = synth.QOIS_3D[:6] + [("MP", "I", j) for j in range(2)]
+    C, mu, S = synth.lrs_model_channel(8, 7, 9)
+    out["binomial_3x3x3_channel"] = (cfg, u0, q3, dict(mode="lrs", spinup=5, C=C, mu=mu, Sigma=S, seed=5, nbands=2,
+                                                         dmin=0.5, dmax=1.5), {})
+    # ragged in x, y and z (45 x 13 x 11 against 32 x 8 tiles and z chunks of 4)
+    cfg, u0 = synth.channel_workload(45, 13, 11, substrate=1, cmodel=0.1)
+    q3, ca3 = closure_args("3d", ny=13, spinup=5)
+    out["binomial_ragged_45x13x11"] = (cfg, u0, q3, ca3, dict(tune_zc=4))
+    cfg, u0 = _k2(3, 3, 1)
+    out["kernel_3x3_walls"] = (cfg, u0, KQ2, _lrs(6), {})
+    cfg, u0 = _k2(5, 4, 0)
+    out["kernel_5x4_periodic"] = (cfg, u0, KQ2, _lrs(6), {})
+    cfg, u0 = _k2(6, 5, 0)
+    out["fourier_6x5"] = (cfg, u0, [(k, f, 0) for f in ("F0-1", "F2-2", "F3-4") for k in ("E", "Z")], _lrs(6), {})
+    cfg, u0 = synth.channel_workload(4, 3, 5, substrate=1, cmodel=0.1)
+    cfg.update(walls_y=0, force_kind=1, force_amp=1e-5, force_k=1)
+    out["fourier_4x3x5"] = (cfg, u0, [(k, f, 0) for f in ("F0-1", "F2-3") for k in ("E", "Z")], _lrs(4), {})
+    return out
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_small_and_ragged_grids_fp64(name):
+    """Velocity, q*, dQ and gamma after 30 steps, FP64.  dQ and gamma are
+    compared per QoI relative to their largest value over the run; q* per
+    QoI relative to its largest value too, since on these grids a filter
+    can leave a QoI many orders below the others (G_3 of radius 12 on a
+    5-cell axis is nearly the mean), where the relative error of each single
+    value measures cancellation, not the path."""
+    lbm = need_gpu()
+    cfg, u0, qois, cargs, tune = CASES[name]
+    steps = 30
+    _say(f"edge case {name}: grid {cfg['nx']}x{cfg['ny']}x{cfg['nz']} lattice {cfg['lattice']}")
+    run = gpu_run(lbm, cfg, u0, "fp64", qois, cargs, **tune)
+    run.step(steps)
+    assert run.sync() == 0
+    o = oracle_run(cfg, u0, qois, cargs)
+    o.step(steps)
+    rg, ro = run.record_arrays(), o.record_arrays()
+    ev = rel_err(run.fields()[1], o.velocity()[1])
+
+    def per_qoi(key):
+        sc = np.max(np.abs(ro[key]), axis=0) + 1e-300
+        return float(np.max(np.abs(rg[key] - ro[key]) / sc))
+
+    eq, edq, eg = per_qoi("q"), per_qoi("dq"), per_qoi("gamma")
+    _say(f"  velocity {ev:.2e}  q {eq:.2e}  dq {edq:.2e}  gamma {eg:.2e}")
+    assert np.array_equal(rg["flags"], ro["flags"]) and not np.any(ro["flags"])
+    assert np.any(ro["dq"] != 0)
+    bars = np.array([1e-11, 1e-10, 1e-8, 1e-7])
+    if len(qois) == 12:
+        # the 12-QoI channel closure (six mean-profile bands on 13 rows): its
+        # Gram system amplifies last-bit differences, so the bar is 10 times
+        # the oracle's own spread under a 1-ulp change of the start
+        b = oracle_run(cfg, u0 * (1 + 2.2e-16 * np.random.default_rng(0).choice([-1, 1], size=u0.shape)), qois,
+                       cargs)
+        b.step(steps)
+        rb = b.record_arrays()
+        floor = np.array([rel_err(b.velocity()[1], o.velocity()[1])] +
+                         [np.max(np.abs(rb[k] - ro[k]) / (np.max(np.abs(ro[k]), axis=0) + 1e-300))
+                          for k in ("q", "dq", "gamma")])
+        _say(f"  oracle 1-ulp floor: velocity {floor[0]:.2e}  q {floor[1]:.2e}  dq {floor[2]:.2e}")
+        bars = np.maximum(bars, 10 * floor)
+    assert ev <= bars[0] and eq <= bars[1] and edq <= bars[2] and eg <= bars[3]
+
+
+def test_closure_activation_past_the_run_is_the_uncorrected_run():
+    """An LRS closure whose spin-up outlasts the run applies nothing: the
+    populations and the recorded q* equal those of the same run with the
+    closure off, bitwise, and every dQ is zero."""
+    lbm = need_gpu()
+    cfg, u0 = synth.channel_workload(20, 24, 12, substrate=1, cmodel=0.1)
+    qois, cargs = closure_args("3d", ny=24, spinup=1000)
+    a = gpu_run(lbm, cfg, u0, "fp32", qois, cargs)
+    b = gpu_run(lbm, cfg, u0, "fp32", qois, dict(cargs, mode="off"))
+    a.step(50)
+    b.step(50)
+    a.sync()
+    b.sync()
+    ra, rb = a.record_arrays(), b.record_arrays()
+    assert np.array_equal(a.get_populations(), b.get_populations())
+    assert np.array_equal(ra["q"], rb["q"])
+    assert np.all(ra["dq"] == 0)
+
+
+def test_tracking_reference_shorter_than_the_run():
+    """Past the last reference step the tracking closure requests nothing
+    (dQ = 0, as in the oracle); before it q* + dQ = q_ref."""
+    lbm = need_gpu()
+    cfg, u0 = _k2(24, 20, 0, seed=4)
+    qois = synth.QOIS_2D
+    steps, nref, S0 = 60, 35, 5
+    o = oracle_run(cfg, u0, qois, dict(mode="off"))
+    o.step(nref)
+    qref = o.record_arrays()["q"] * (1 + 0.02 * np.cos(np.arange(nref) / 7.0))[:, None]
+    cargs = dict(mode="track", spinup=S0)
+    run = gpu_run(lbm, cfg, u0, "fp64", qois, cargs, qref=qref)
+    run.step(steps)
+    assert run.sync() == 0
+    ot = oracle_run(cfg, u0, qois, cargs, qref=qref)
+    ot.step(steps)
+    rg, ro = run.record_arrays(), ot.record_arrays()
+    assert np.all(rg["dq"][nref:] == 0) and np.all(rg["dq"][:S0] == 0)
+    assert np.allclose(rg["q"][S0:nref] + rg["dq"][S0:nref], qref[S0:], rtol=1e-12, atol=0)
+    ev = rel_err(run.fields()[1], ot.velocity()[1])
+    _say(f"  velocity {ev:.2e}")
+    assert ev <= 1e-11
+
+
+def test_zero_steps():
+    """step(0) changes nothing and records nothing."""
+    lbm = need_gpu()
+    cfg, u0 = _k2(24, 20, 0)
+    qois, cargs = closure_args("2d", spinup=5)
+    run = gpu_run(lbm, cfg, u0, "fp32", qois, cargs)
+    run.step(3)
+    run.sync()
+    f0 = run.get_populations()
+    run.step(0)
+    run.sync()
+    assert run.step_count == 3
+    assert np.array_equal(run.get_populations(), f0)
+    assert run.record_arrays()["q"].shape[0] == 3
