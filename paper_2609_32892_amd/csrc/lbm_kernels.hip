@@ -131,17 +131,45 @@ __device__ __forceinline__ void st_at(T* base, unsigned i, T v)
     *(T*)((char*)base + i * (unsigned)sizeof(T)) = v;
 }
 
-// The same sums with the result spread over the workgroup: thread k < NV
-// returns value k (added over the waves in the same order as block_sum).
+// Butterfly reduce-scatter over the wavefront: at lane distance D each lane
+// keeps one half of its list of L partial sums (the lower half where lane
+// bit D is clear, else the upper half, padded with a zero when L is odd)
+// and adds its partner's copy of that half.  A level costs ceil(L/2)
+// exchanges; after distances 32 .. 1 every lane holds one wave sum.  Returns
+// that sum's index in the list (-1 for a lane left holding padding, which
+// includes the upper lanes of every level with L = 1).  The order of the
+// additions is fixed.
+template <int L, int D>
+__device__ __forceinline__ int wave_scatter(double* cur, int lane)
+{
+    constexpr int H = (L + 1) / 2;
+    const bool hi = (lane & D) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const double lo_v = cur[i];
+        const double hi_v = H + i < L ? cur[H + i] : 0.0;
+        const double give = hi ? lo_v : hi_v;
+        cur[i] = (hi ? hi_v : lo_v) + __shfl_xor(give, D);
+    }
+    int p = 0;
+    if constexpr (D > 1) p = wave_scatter<H, D / 2>(cur, lane);
+    if (p < 0) return -1;
+    p += hi ? H : 0;
+    return p < L ? p : -1;
+}
+
+// The sums of block_sum with the result spread over the workgroup: thread
+// k < NV returns value k, the waves' sums added in wave order.
 template <int NV>
 __device__ __forceinline__ double block_sum_spread(const double* v, double* lds)
 {
+    static_assert(NV <= 64, "one value per lane after the butterfly");
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double cur[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        double s = wave_sum(v[k]);
-        if (lane == 0) lds[k * (kBlock / 64) + wv] = s;
-    }
+    for (int k = 0; k < NV; ++k) cur[k] = v[k];
+    const int idx = wave_scatter<NV, 32>(cur, lane);
+    if (idx >= 0) lds[idx * (kBlock / 64) + wv] = cur[0];
     __syncthreads();
     double r = 0;
     if (threadIdx.x < NV) {
@@ -750,64 +778,111 @@ template <typename T> __device__ __forceinline__ T coef_cw(KCtl* c, int j);
 template <> __device__ __forceinline__ float coef_cw<float>(KCtl* c, int j) { return c->cwf[j]; }
 template <> __device__ __forceinline__ double coef_cw<double>(KCtl* c, int j) { return c->cw[j]; }
 
+// The fields a cell's sensitivities are formed from, loaded in one batch
+// (no branch between the loads, so that the loads of several cells can be
+// in flight together) and evaluated afterwards.
+template <int LAT, typename T, int MAXSA>
+struct CellIn {
+    T pv[kMaxPow + 1][Lat<LAT>::D];   // B^j v*, j = 0..kMaxPow (clamped to jv)
+    T wc[3][Lat<LAT>::NC];            // B^j w, j = 0..2 (clamped to jw)
+    T cv[kMaxPow + 1][Lat<LAT>::D];   // C_j (clamped to jw)
+    T kv[MAXSA][Lat<LAT>::D];         // kernel filters: V_s (clamped to nsa - 1)
+};
+
 template <int LAT, typename T, int MAXSA, bool KF>
-__device__ __forceinline__ void cell_sens(KMember& m, KParam* prm, int x, int y, int z,
-                                          int cell, T (&pv)[kMaxPow + 1][Lat<LAT>::D], T (&V)[MAXSA][Lat<LAT>::D],
-                                          double (&qd)[MAXSA])
+__device__ __forceinline__ void cell_load(KMember& m, KParam* prm, int cell, CellIn<LAT, T, MAXSA>& in)
 {
     using L = Lat<LAT>;
     constexpr int D = L::D, NC = L::NC;
-    const int nsa = prm->nsa, jv = prm->jv, jw = prm->jw;
+    const int jv = prm->jv, jw = prm->jw;
     const size_t sN = (size_t)m.N;
+    const T* __restrict__ vs = (const T*)m.vs;
     if constexpr (KF) {
-        // kernel filters: the sensitivities V_s are materialised; both E and Z
-        // QoIs are 1/2 <v*, V_s> (R self-adjoint, curl^T the adjoint of curl)
-        const T* __restrict__ vs = (const T*)m.vs;
+        const int nsa = prm->nsa;
         const T* __restrict__ kV = (const T*)m.kV;
 #pragma unroll
-        for (int a = 0; a < D; ++a) pv[0][a] = vs[a * sN + cell];
+        for (int a = 0; a < D; ++a) in.pv[0][a] = vs[a * sN + cell];
 #pragma unroll
         for (int s2 = 0; s2 < MAXSA; ++s2) {
             const int sc = s2 < nsa ? s2 : nsa - 1;
-            qd[s2] = 0;
 #pragma unroll
-            for (int a = 0; a < D; ++a) {
-                const T vv = kV[((size_t)sc * D + a) * sN + cell];
-                V[s2][a] = s2 < nsa ? vv : T(0);
-                qd[s2] += 0.5 * (double)(pv[0][a] * V[s2][a]);
-            }
+            for (int a = 0; a < D; ++a) in.kv[s2][a] = kV[((size_t)sc * D + a) * sN + cell];
         }
         return;
     }
     const T* __restrict__ P = (const T*)m.P;
     const T* __restrict__ W = (const T*)m.W;
     // Every load is unconditional, with the power clamped to the highest one
-    // stored: a power above jv (jw) only ever meets a zero coefficient, and
-    // loads that no branch guards all stay in flight together.
-    const T* __restrict__ vs = (const T*)m.vs;
+    // stored: a power above jv (jw) only ever meets a zero coefficient.
 #pragma unroll
     for (int jj = 0; jj <= kMaxPow; ++jj) {
         const int je = jj < jv ? jj : jv;
         const T* src = je == 0 ? vs : P + (size_t)(je - 1) * D * sN;
 #pragma unroll
-        for (int a = 0; a < D; ++a) pv[jj][a] = src[a * sN + cell];
+        for (int a = 0; a < D; ++a) in.pv[jj][a] = src[a * sN + cell];
     }
-    T wc[3][NC];
     const bool hz = prm->has_z;
 #pragma unroll
     for (int jj = 0; jj < 3; ++jj) {
         const T* src = hz ? W + (size_t)(jj < jw ? jj : jw) * NC * sN : vs;   // (unused without Z QoIs)
 #pragma unroll
-        for (int a = 0; a < NC; ++a) wc[jj][a] = src[a * sN + cell];
+        for (int a = 0; a < NC; ++a) in.wc[jj][a] = src[a * sN + cell];
     }
     // C_j = curl^T B^j w (Z sensitivities)
     const T* __restrict__ Cc = (const T*)m.C;
-    T cv[kMaxPow + 1][D];
 #pragma unroll
     for (int jj = 0; jj <= kMaxPow; ++jj) {
         const T* src = hz ? Cc + (size_t)(jj < jw ? jj : jw) * D * sN : vs;
 #pragma unroll
-        for (int a = 0; a < D; ++a) cv[jj][a] = src[a * sN + cell];
+        for (int a = 0; a < D; ++a) in.cv[jj][a] = src[a * sN + cell];
+    }
+}
+
+// The closure's filter coefficients of every E/Z QoI, read once per
+// workgroup ahead of the field loads (zero past nsa, so that those QoIs
+// contribute exact zeros), and its kinds (1 for Z).
+template <typename T, int MAXSA>
+struct SensCoef {
+    T r[MAXSA][3], rr[MAXSA][kMaxPow + 1];
+    int z[MAXSA];
+    int nsa, hz;
+};
+
+template <typename T, int MAXSA>
+__device__ __forceinline__ void sens_coef(KParam* prm, SensCoef<T, MAXSA>& c)
+{
+    c.nsa = prm->nsa;
+    c.hz = prm->has_z;
+#pragma unroll
+    for (int s = 0; s < MAXSA; ++s) {
+        c.z[s] = prm->sa_kind[s];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) c.r[s][j] = coef_r<T>(prm, s, j);
+#pragma unroll
+        for (int j = 0; j <= kMaxPow; ++j) c.rr[s][j] = coef_rr<T>(prm, s, j);
+    }
+}
+
+template <int LAT, typename T, int MAXSA, bool KF>
+__device__ __forceinline__ void cell_eval(const SensCoef<T, MAXSA>& cf, const CellIn<LAT, T, MAXSA>& in,
+                                          T (&V)[MAXSA][Lat<LAT>::D], double (&qd)[MAXSA])
+{
+    using L = Lat<LAT>;
+    constexpr int D = L::D, NC = L::NC;
+    const int nsa = cf.nsa;
+    if constexpr (KF) {
+        // kernel filters: the sensitivities V_s are materialised; both E and Z
+        // QoIs are 1/2 <v*, V_s> (R self-adjoint, curl^T the adjoint of curl)
+#pragma unroll
+        for (int s2 = 0; s2 < MAXSA; ++s2) {
+            qd[s2] = 0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                V[s2][a] = s2 < nsa ? in.kv[s2][a] : T(0);
+                qd[s2] += 0.5 * (double)(in.pv[0][a] * V[s2][a]);
+            }
+        }
+        return;
     }
 #pragma unroll
     for (int s = 0; s < MAXSA; ++s) {
@@ -815,35 +890,35 @@ __device__ __forceinline__ void cell_sens(KMember& m, KParam* prm, int x, int y,
 #pragma unroll
         for (int a = 0; a < D; ++a) V[s][a] = 0;
         if (s >= nsa) continue;
-        const T r0 = coef_r<T>(prm, s, 0), r1 = coef_r<T>(prm, s, 1), r2 = coef_r<T>(prm, s, 2);
-        if (prm->sa_kind[s] == 0) {
+        const T r0 = cf.r[s][0], r1 = cf.r[s][1], r2 = cf.r[s][2];
+        if (cf.z[s] == 0) {
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                const T rv = r0 * pv[0][a] + r1 * pv[1][a] + r2 * pv[2][a];
+                const T rv = r0 * in.pv[0][a] + r1 * in.pv[1][a] + r2 * in.pv[2][a];
                 qd[s] += 0.5 * (double)(rv * rv);
                 T vv = 0;
 #pragma unroll
-                for (int jj = 0; jj <= kMaxPow; ++jj) vv += coef_rr<T>(prm, s, jj) * pv[jj][a];
+                for (int jj = 0; jj <= kMaxPow; ++jj) vv += cf.rr[s][jj] * in.pv[jj][a];
                 V[s][a] = vv;
             }
         } else {
 #pragma unroll
             for (int a = 0; a < NC; ++a) {
-                const T rw = r0 * wc[0][a] + r1 * wc[1][a] + r2 * wc[2][a];
+                const T rw = r0 * in.wc[0][a] + r1 * in.wc[1][a] + r2 * in.wc[2][a];
                 qd[s] += 0.5 * (double)(rw * rw);
             }
         }
     }
-    if (!hz) return;
+    if (!cf.hz) return;
     // Z sensitivities from the stored C_j = curl^T B^j w
 #pragma unroll
     for (int s = 0; s < MAXSA; ++s) {
-        if (s >= nsa || prm->sa_kind[s] == 0) continue;
+        if (s >= nsa || cf.z[s] == 0) continue;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             T vv = 0;
 #pragma unroll
-            for (int jj = 0; jj <= kMaxPow; ++jj) vv += coef_rr<T>(prm, s, jj) * cv[jj][a];
+            for (int jj = 0; jj <= kMaxPow; ++jj) vv += cf.rr[s][jj] * in.cv[jj][a];
             V[s][a] = vv;
         }
     }
@@ -875,31 +950,46 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const DevMember* __restrict__
     double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0;
-    for (int c = 0; c < m.cpt2; ++c) {
-        const int p = (bx * m.cpt2 + c) * kBlock + threadIdx.x;
-        if (p >= plane) break;
-        const int x = p % nx, z = p / nx;
-        const int cell = x + nx * (y + ny * z);
-        T pv[kMaxPow + 1][D];
-        T V[MAXSA][D];
-        double qd[MAXSA];
-        cell_sens<LAT, T, MAXSA, KF>(m, prm, x, y, z, cell, pv, V, qd);
+    SensCoef<T, MAXSA> cf;
+    sens_coef<T, MAXSA>(prm, cf);
+    // cells in pairs: both cells' fields are loaded before either is
+    // evaluated (a second cell past the plane re-loads the first and is not
+    // added); the additions keep the order of the cells
+    for (int c = 0; c < m.cpt2; c += 2) {
+        const int pa = (bx * m.cpt2 + c) * kBlock + threadIdx.x;
+        if (pa >= plane) break;
+        const int pb = pa + kBlock;
+        const bool hb = c + 1 < m.cpt2 && pb < plane;
+        CellIn<LAT, T, MAXSA> in[2];
 #pragma unroll
-        for (int s = 0; s < MAXSA; ++s) acc[s] += qd[s];
-        int g = 0;
+        for (int u = 0; u < 2; ++u) {
+            const int p = u == 0 || !hb ? pa : pb;
+            const int x = p % nx, z = p / nx;
+            cell_load<LAT, T, MAXSA, KF>(m, prm, x + nx * (y + ny * z), in[u]);
+        }
 #pragma unroll
-        for (int s = 0; s < MAXSA; ++s)
+        for (int u = 0; u < 2; ++u) {
+            if (u == 1 && !hb) break;
+            T V[MAXSA][D];
+            double qd[MAXSA];
+            cell_eval<LAT, T, MAXSA, KF>(cf, in[u], V, qd);
 #pragma unroll
-            for (int t2 = s; t2 < MAXSA; ++t2, ++g) {
-                T d = 0;
+            for (int s = 0; s < MAXSA; ++s) acc[s] += qd[s];
+            int g = 0;
 #pragma unroll
-                for (int a = 0; a < D; ++a) d += V[s][a] * V[t2][a];
-                acc[MAXSA + g] += (double)d;
+            for (int s = 0; s < MAXSA; ++s)
+#pragma unroll
+                for (int t2 = s; t2 < MAXSA; ++t2, ++g) {
+                    T d = 0;
+#pragma unroll
+                    for (int a = 0; a < D; ++a) d += V[s][a] * V[t2][a];
+                    acc[MAXSA + g] += (double)d;
+                }
+            if (hasmp) {
+                acc[MAXSA + NG] += (double)in[u].pv[0][0];
+#pragma unroll
+                for (int s = 0; s < MAXSA; ++s) acc[MAXSA + NG + 1 + s] += (double)V[s][0];
             }
-        if (hasmp) {
-            acc[MAXSA + NG] += (double)pv[0][0];
-#pragma unroll
-            for (int s = 0; s < MAXSA; ++s) acc[MAXSA + NG + 1 + s] += (double)V[s][0];
         }
     }
     // band weights w_j(y) of this row (workgroup-uniform: scalar loads,
