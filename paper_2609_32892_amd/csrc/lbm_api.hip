@@ -268,6 +268,13 @@ int ksum_slot(int k, int nhc) { return k == 0 ? -1 : (k <= nhc ? -1 - k : k - 1 
 // neighbouring rows and planes that a block reads in the L2 that already
 // holds them.  Returns the block processed by each entry.
 constexpr int kXcd = 8;
+
+// Whether a launch stores the fields the next kernel reads through the L2:
+// when its population buffers, pop_bytes in total, fit well within the
+// 32 MB of L2 summed over the 8 XCDs (measured on MI355X: faster on a
+// 96 x 48 x 48 channel, slower on 295 x 47 x 98, whose fields the next
+// kernel otherwise finds in the Infinity Cache).
+int write_through(double pop_bytes) { return pop_bytes <= 24.0 * 1024 * 1024; }
 std::vector<int> xcd_order(int n)
 {
     std::vector<int> order;
@@ -403,6 +410,7 @@ LaunchGroup ctx_group(const lbm_ctx* c)
     g.maxsa = c->cur.nsa;
     g.npass = c->cur.kf ? 0 : std::max(c->cur.jv, c->cur.has_z ? c->cur.jw + 1 : 0);
     g.btx = c->plan.btx;
+    g.wt = write_through((double)c->plan.N * c->plan.Q * c->plan.esz);
     add_pass_masks(c, g);
     g.kf = c->cur.kf;
     g.kjobs = (const KJob*)(c->arena + c->plan.kjobs);
@@ -1311,6 +1319,9 @@ static int batch_build(lbm_batch* b)
         g.substrate = keys[gi].sub;
         g.mode = keys[gi].mode;
         g.btx = keys[gi].btx;
+        double pop_bytes = 0;   // one launch covers the whole group
+        for (int i : gm[gi]) pop_bytes += (double)b->mem[i]->plan.N * b->mem[i]->plan.Q * b->mem[i]->plan.esz;
+        g.wt = write_through(pop_bytes);
         for (int i : gm[gi]) {
             const lbm_ctx* c = b->mem[i];
             g.any_z |= c->cur.has_z;

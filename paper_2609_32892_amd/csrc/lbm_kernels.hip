@@ -131,6 +131,31 @@ __device__ __forceinline__ void st_at(T* base, unsigned i, T v)
     *(T*)((char*)base + i * (unsigned)sizeof(T)) = v;
 }
 
+// Stores of fields that the next kernel reads.  On small grids (kernels
+// instantiated with WT) they are relaxed device-scope atomic stores, written
+// through each XCD's L2, so that no dirty lines are left for the L2
+// write-back at the end of the kernel, which the next kernel waits for.
+// Measured on MI355X (FP32 channel TO-LES): 2427 -> 2592 MLUPS on
+// 96 x 48 x 48; no change on 384 x 192 x 192; but 1328 -> 1130 MLUPS for
+// the kernel-filter closure on 295 x 47 x 98, whose fields the next kernel
+// otherwise finds in the Infinity Cache.  Plain stores there.
+template <typename T>
+__device__ __forceinline__ void st_dev(T* p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_fld(T* p, T v, int wt)
+{
+    if (wt) st_dev(p, v);
+    else *p = v;
+}
+template <typename T>
+__device__ __forceinline__ void st_fld_at(T* base, unsigned i, T v, int wt)
+{
+    st_fld((T*)((char*)base + i * (unsigned)sizeof(T)), v, wt);
+}
+
 // Butterfly reduce-scatter over the wavefront: at lane distance D each lane
 // keeps one half of its list of L partial sums (the lower half where lane
 // bit D is clear, else the upper half, padded with a zero when L is odd)
@@ -265,7 +290,7 @@ __device__ __forceinline__ void moments(const T* f, T& drho, T* j)
 // MODE 0: plain; 1: plain with statistics and post-streaming velocity;
 // 2: TO predictor (statistics, rho, v*).
 // ---------------------------------------------------------------------------
-template <int LAT, typename T, int PREC, int SUB, int MODE>
+template <int LAT, typename T, int PREC, int SUB, int MODE, bool WT = false>
 __global__ __launch_bounds__(kBlock) void k_step(const DevMember* __restrict__ mems,
                                                  const int2* __restrict__ work, int flip)
 {
@@ -396,14 +421,14 @@ __global__ __launch_bounds__(kBlock) void k_step(const DevMember* __restrict__ m
                    (D == 3 ? T(L::cz[i]) * (us[2] + u[2]) : T(0));
             T out = f[i] - om * (f[i] - geq[i]) + dfeq<T>(T(L::w[i]), rho, cd, cs, dd);
             if (MODE == 2)
-                st_at(gd + (size_t)i * N, (unsigned)cell, out);
+                st_fld_at(gd + (size_t)i * N, (unsigned)cell, out, WT);
             else
                 gd[(size_t)i * N + cell] = out;
         }
         if (MODE == 2) {
-            st_at((T*)m.rho, (unsigned)cell, drho);
+            st_fld_at((T*)m.rho, (unsigned)cell, drho, WT);
 #pragma unroll
-            for (int a = 0; a < D; ++a) st_at((T*)m.vs + (size_t)a * N, (unsigned)cell, us[a]);
+            for (int a = 0; a < D; ++a) st_fld_at((T*)m.vs + (size_t)a * N, (unsigned)cell, us[a], WT);
         }
         if (MODE == 1 && SUB != LBM_WALE) {  // (with WALE, k_moments wrote v^n)
 #pragma unroll
@@ -498,7 +523,7 @@ __device__ __forceinline__ void curl_at(const T* __restrict__ v, size_t N, int x
 // is unconditional, a 32-bit offset from a scalar base (TO fields stay below
 // 2^32 bytes); a neighbour beyond a wall loads the cell itself and counts
 // as zero, so no branch-joined load stalls the others.
-template <int LAT, typename T>
+template <int LAT, typename T, bool WT>
 __global__ __launch_bounds__(kBlock) void k_curl(const DevMember* __restrict__ mems, const int2* __restrict__ work)
 {
     using L = Lat<LAT>;
@@ -539,7 +564,7 @@ __global__ __launch_bounds__(kBlock) void k_curl(const DevMember* __restrict__ m
     }
     T* W = (T*)m.W;
 #pragma unroll
-    for (int a = 0; a < L::NC; ++a) st_at(W + (size_t)a * sN, c, w[a]);
+    for (int a = 0; a < L::NC; ++a) st_fld_at(W + (size_t)a * sN, c, w[a], WT);
 }
 
 // Binomial filter B = (x)_a [1,2,1]/4 of one scalar field at (x,y,z).
@@ -584,7 +609,7 @@ __device__ __forceinline__ int modi(int a, int n) { int r = a % n; return r < 0 
 // the launch passes the union over its members, and a member whose chain
 // this pass does not advance either returns (CH = 1, 2) or re-reads the
 // other chain's source (CH = 3).
-template <int LAT, typename T, int TX, int CH>
+template <int LAT, typename T, int TX, int CH, bool WT>
 __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ mems, const int2* __restrict__ work,
                                                   int j)
 {
@@ -698,12 +723,12 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
         const size_t ci = (size_t)x + (size_t)nx * (y + (size_t)ny * zo);
 #pragma unroll
         for (int c = 0; c < NCMP; ++c)
-            if (dst[c]) dst[c][ci] = T(0.25) * sa[c] + T(0.5) * sb[c] + T(0.25) * sc[c];
+            if (dst[c]) st_fld(dst[c] + ci, T(0.25) * sa[c] + T(0.5) * sb[c] + T(0.25) * sc[c], WT);
         if constexpr (D == 3 && NW > 0) {
             if (cdst) {   // curl w at plane zo, D_z from the planes below and above
-                cdst[ci] = (T(0.5) * ra[1] + dxyb[2][1]) - T(0.5) * rc[1];        // D_y w_z - D_z w_y
-                cdst[sN + ci] = (T(-0.5) * ra[0] - dxyb[2][0]) + T(0.5) * rc[0];  // D_z w_x - D_x w_z
-                cdst[2 * sN + ci] = dxyb[1][0] - dxyb[0][1];                      // D_x w_y - D_y w_x
+                st_fld(cdst + ci, (T(0.5) * ra[1] + dxyb[2][1]) - T(0.5) * rc[1], WT);        // D_y w_z - D_z w_y
+                st_fld(cdst + sN + ci, (T(-0.5) * ra[0] - dxyb[2][0]) + T(0.5) * rc[0], WT);  // D_z w_x - D_x w_z
+                st_fld(cdst + 2 * sN + ci, dxyb[1][0] - dxyb[0][1], WT);                      // D_x w_y - D_y w_x
             }
         }
     };
@@ -718,10 +743,10 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
             const size_t ci = (size_t)x + (size_t)nx * y;
 #pragma unroll
             for (int c = 0; c < NCMP; ++c)
-                if (dst[c]) dst[c][ci] = sn[c];
+                if (dst[c]) st_fld(dst[c] + ci, sn[c], WT);
             if (NW > 0 && cdst) {   // curl^T of a scalar: (D_y w, -D_x w)
-                cdst[ci] = dn[0][1];
-                cdst[sN + ci] = -dn[0][0];
+                st_fld(cdst + ci, dn[0][1], WT);
+                st_fld(cdst + sN + ci, -dn[0][0], WT);
             }
         }
     } else {
@@ -1430,7 +1455,7 @@ template <typename T> __device__ __forceinline__ T coef_bsa(KCtl* c, int s);
 template <> __device__ __forceinline__ float coef_bsa<float>(KCtl* c, int s) { return c->bsaf[s]; }
 template <> __device__ __forceinline__ double coef_bsa<double>(KCtl* c, int s) { return c->bsa[s]; }
 
-template <int LAT, typename T, bool KF>
+template <int LAT, typename T, bool KF, bool WT>
 __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ mems, const int2* __restrict__ work,
                                                   int flip)
 {
@@ -1521,7 +1546,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ 
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) gi[i] = ld_at(g + (size_t)i * sN, (unsigned)cell);
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) st_at(g + (size_t)i * sN, (unsigned)cell, gi[i] + pend_df<LAT, T>(r, i, T(1)));
+    for (int i = 0; i < L::Q; ++i)
+        st_fld_at(g + (size_t)i * sN, (unsigned)cell, gi[i] + pend_df<LAT, T>(r, i, T(1)), WT);
 }
 
 // ---------------------------------------------------------------------------
@@ -1533,7 +1559,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ 
 // op 0: dst = sum_t coef_t sum_r taps_t[r] src_t(. + r e_axis), periodic wrap
 // or zero padding on the wall axis; op 1: the adjoint curl (2-D:
 // (D_y psi, -D_x psi); 3-D: curl psi) with the wall padding of curl_at.
-template <int LAT, typename T>
+template <int LAT, typename T, bool WT>
 __global__ __launch_bounds__(kBlock) void k_kjob(const DevMember* __restrict__ mems, const int2* __restrict__ work,
                                                  const KJob* __restrict__ jobs)
 {
@@ -1595,9 +1621,9 @@ __global__ __launch_bounds__(kBlock) void k_kjob(const DevMember* __restrict__ m
             out[1] += cf * s1;
             out[2] += cf * s2;
         }
-        dst[cell] = out[0];
-        if (nc > 1) dst[(size_t)N + cell] = out[1];
-        if (nc > 2) dst[2 * (size_t)N + cell] = out[2];
+        st_fld(dst + cell, out[0], WT);
+        if (nc > 1) st_fld(dst + (size_t)N + cell, out[1], WT);
+        if (nc > 2) st_fld(dst + 2 * (size_t)N + cell, out[2], WT);
         return;
     }
     const T* __restrict__ src = (const T*)j.src[0];
@@ -1935,7 +1961,9 @@ static void launch_step_group(const LaunchGroup& g, hipStream_t st, int flip, hi
     }
 #define LBM_STEP_SUB(SUB)                                                                                  \
     do {                                                                                                   \
-        if (g.mode == 2)                                                                                   \
+        if (g.mode == 2 && g.wt)                                                                           \
+            hipLaunchKernelGGL((k_step<LAT, T, PREC, SUB, 2, true>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
+        else if (g.mode == 2)                                                                              \
             hipLaunchKernelGGL((k_step<LAT, T, PREC, SUB, 2>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
         else if (g.mode == 1)                                                                              \
             hipLaunchKernelGGL((k_step<LAT, T, PREC, SUB, 1>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
@@ -1952,16 +1980,28 @@ static void launch_step_group(const LaunchGroup& g, hipStream_t st, int flip, hi
 to_chain:
     mark(1);
     if (g.mode == 2) {
-        if (g.any_z) hipLaunchKernelGGL((k_curl<LAT, T>), dim3(g.nb1), blk, 0, st, g.mems, g.work1);
+        if (g.any_z) {
+            if (g.wt) hipLaunchKernelGGL((k_curl<LAT, T, true>), dim3(g.nb1), blk, 0, st, g.mems, g.work1);
+            else hipLaunchKernelGGL((k_curl<LAT, T, false>), dim3(g.nb1), blk, 0, st, g.mems, g.work1);
+        }
         mark(2);
         if (g.kf) {
             if (g.fprog) launch_fourier<LAT, T>(*g.fprog, st);
-            for (int l = 0; l < g.nklev; ++l)
-                hipLaunchKernelGGL((k_kjob<LAT, T>), dim3(g.nb1, g.klev[l].y), blk, 0, st, g.mems, g.work1,
-                                   g.kjobs + g.klev[l].x);
+            for (int l = 0; l < g.nklev; ++l) {
+                if (g.wt)
+                    hipLaunchKernelGGL((k_kjob<LAT, T, true>), dim3(g.nb1, g.klev[l].y), blk, 0, st, g.mems, g.work1,
+                                       g.kjobs + g.klev[l].x);
+                else
+                    hipLaunchKernelGGL((k_kjob<LAT, T, false>), dim3(g.nb1, g.klev[l].y), blk, 0, st, g.mems, g.work1,
+                                       g.kjobs + g.klev[l].x);
+            }
         }
         for (int j = 1; j <= (g.kf ? 0 : g.npass); ++j) {
-#define LBM_BINOM(TXV, CHV) hipLaunchKernelGGL((k_binom<LAT, T, TXV, CHV>), dim3(g.nbb), blk, 0, st, g.mems, g.workb, j)
+#define LBM_BINOM(TXV, CHV)                                                                                    \
+    do {                                                                                                       \
+        if (g.wt) hipLaunchKernelGGL((k_binom<LAT, T, TXV, CHV, true>), dim3(g.nbb), blk, 0, st, g.mems, g.workb, j); \
+        else hipLaunchKernelGGL((k_binom<LAT, T, TXV, CHV, false>), dim3(g.nbb), blk, 0, st, g.mems, g.workb, j); \
+    } while (0)
             const int ch = g.bmask[j - 1];
             if (g.btx == kBinTXW) {
                 if (ch == 1) LBM_BINOM(kBinTXW, 1); else if (ch == 2) LBM_BINOM(kBinTXW, 2); else LBM_BINOM(kBinTXW, 3);
@@ -1987,8 +2027,13 @@ to_chain:
         hipLaunchKernelGGL(k_solve, dim3(g.nmem), blk, 0, st, g.mems, g.workm);
         mark(5);
         if (!g.probe) {
-            if (g.kf) hipLaunchKernelGGL((k_apply<LAT, T, true>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip);
-            else hipLaunchKernelGGL((k_apply<LAT, T, false>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip);
+#define LBM_APPLY(KFV)                                                                                       \
+    do {                                                                                                     \
+        if (g.wt) hipLaunchKernelGGL((k_apply<LAT, T, KFV, true>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
+        else hipLaunchKernelGGL((k_apply<LAT, T, KFV, false>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
+    } while (0)
+            if (g.kf) LBM_APPLY(true); else LBM_APPLY(false);
+#undef LBM_APPLY
         }
         mark(6);
     } else if (g.mode == 1) {

@@ -67,6 +67,7 @@ struct LaunchGroup {
     const int2* klev;   // klev[l] = (first job, job count) of level l (host memory)
     int nklev;
     const FourierProg* fprog;   // Fourier band QoIs (host memory; null if none)
+    int wt;             // store the fields the next kernel reads through the L2 (small launches)
 };
 
 enum { OP_INIT = 0, OP_GET_POP = 1, OP_SET_POP = 2, OP_STREAM = 3 };
