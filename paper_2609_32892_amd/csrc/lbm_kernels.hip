@@ -977,24 +977,26 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const DevMember* __restrict__
     for (int k = 0; k < NV; ++k) acc[k] = 0;
     SensCoef<T, MAXSA> cf;
     sens_coef<T, MAXSA>(prm, cf);
-    // cells in pairs: both cells' fields are loaded before either is
+    // FP32: cells in pairs, both cells' fields loaded before either is
     // evaluated (a second cell past the plane re-loads the first and is not
-    // added); the additions keep the order of the cells
-    for (int c = 0; c < m.cpt2; c += 2) {
+    // added); FP64 one cell at a time (a pair would take the FP64 variant to
+    // one wave per SIMD).  The additions keep the order of the cells.
+    constexpr int NP = sizeof(T) == 4 ? 2 : 1;
+    for (int c = 0; c < m.cpt2; c += NP) {
         const int pa = (bx * m.cpt2 + c) * kBlock + threadIdx.x;
         if (pa >= plane) break;
-        const int pb = pa + kBlock;
-        const bool hb = c + 1 < m.cpt2 && pb < plane;
-        CellIn<LAT, T, MAXSA> in[2];
+        bool has[NP];
+        CellIn<LAT, T, MAXSA> in[NP];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int p = u == 0 || !hb ? pa : pb;
+        for (int u = 0; u < NP; ++u) {
+            has[u] = u == 0 || (c + u < m.cpt2 && pa + u * kBlock < plane);
+            const int p = has[u] ? pa + u * kBlock : pa;
             const int x = p % nx, z = p / nx;
             cell_load<LAT, T, MAXSA, KF>(m, prm, x + nx * (y + ny * z), in[u]);
         }
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            if (u == 1 && !hb) break;
+        for (int u = 0; u < NP; ++u) {
+            if (!has[u]) break;
             T V[MAXSA][D];
             double qd[MAXSA];
             cell_eval<LAT, T, MAXSA, KF>(cf, in[u], V, qd);
