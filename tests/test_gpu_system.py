@@ -146,3 +146,27 @@ def test_binomial_tile_widths_bitwise_equal(walls):
         assert np.array_equal(qa, qb)
         for r in runs:
             r.close()
+
+
+def test_write_through_and_plain_stores_bitwise_equal():
+    """Launches whose populations fit the L2s store their fields through it,
+    larger ones with plain stores; a batch decides for all its members
+    together.  A small TO member run alone (written through) and batched
+    with a large member (plain stores) are bitwise equal, in FP32 and FP64."""
+    lbm = need_gpu()
+    for prec in ("fp32", "fp64"):
+        cfg, u0 = synth.channel_workload(20, 24, 12, substrate=1, cmodel=0.1)
+        qois, cargs = closure_args("3d", ny=24, spinup=10)
+        big_cfg, big_u0 = synth.channel_workload(160, 48, 96, substrate=1, cmodel=0.1)   # 0.74 M cells
+        bq, bc = closure_args("3d", ny=48, spinup=10)
+        solo = gpu_run(lbm, cfg, u0, prec, qois, cargs)
+        small = gpu_run(lbm, cfg, u0, prec, qois, cargs)
+        big = gpu_run(lbm, big_cfg, big_u0, prec, bq, bc)
+        solo.step(30)
+        batch = lbm.Batch([small, big])
+        batch.step(30)
+        batch.sync()
+        solo.sync()
+        _say(f"  {prec}: small member solo vs batched with a 0.74 M-cell member")
+        assert np.array_equal(small.get_populations(), solo.get_populations())
+        assert np.array_equal(small.record_arrays()["dq"], solo.record_arrays()["dq"])
