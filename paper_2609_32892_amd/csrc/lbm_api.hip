@@ -770,6 +770,14 @@ int reset_ctl(lbm_ctx* c)
     return rc;
 }
 
+// A hipFFT call of the launches since the last check failed (cleared).
+int fft_status(lbm_ctx* c)
+{
+    if (!c->fprog.failed) return LBM_OK;
+    c->fprog.failed = 0;
+    return fail(LBM_EDEVICE, "hipFFT transform of a Fourier band QoI failed");
+}
+
 int enqueue_steps(lbm_ctx* c, long n)
 {
     const LaunchGroup g = ctx_group(c);
@@ -778,7 +786,7 @@ int enqueue_steps(lbm_ctx* c, long n)
         c->phase ^= 1;
     }
     HIPCHK(hipGetLastError());
-    return LBM_OK;
+    return fft_status(c);
 }
 
 int capture(hipStream_t st, const std::vector<LaunchGroup>& groups, int nsteps, int phase0, hipGraphExec_t* out)
@@ -994,8 +1002,8 @@ int lbm_step(lbm_ctx* c, long n)
             // gchunk is even: the phase is unchanged
         } else {
             int rc = enqueue_steps(c, n);
+            c->host_step += n;   // the steps were enqueued (and the phase advanced) even if one failed
             if (rc) return rc;
-            c->host_step += n;
             n = 0;
         }
     }
@@ -1403,11 +1411,13 @@ int lbm_batch_step(lbm_batch* b, long n)
         }
     }
     HIPCHK(hipGetLastError());
+    int fft_rc = LBM_OK;
+    for (lbm_ctx* c : b->mem) fft_rc = fft_rc ? fft_rc : fft_status(c);
     for (lbm_ctx* c : b->mem) {
         c->host_step += n;
         c->phase ^= (int)(n & 1);
     }
-    return LBM_OK;
+    return fft_rc;
 }
 
 int lbm_batch_sync(lbm_batch* b)

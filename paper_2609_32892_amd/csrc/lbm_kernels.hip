@@ -1703,11 +1703,14 @@ static void launch_fourier(const FourierProg& f, hipStream_t st)
     auto grid = [&](size_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); };
     auto exec = [&](void* plan, void* data, int dir) {
         hipfftHandle h = (hipfftHandle)plan;
-        hipfftSetStream(h, st);
-        if constexpr (std::is_same<T, float>::value)
-            hipfftExecC2C(h, (hipfftComplex*)data, (hipfftComplex*)data, dir);
-        else
-            hipfftExecZ2Z(h, (hipfftDoubleComplex*)data, (hipfftDoubleComplex*)data, dir);
+        hipfftResult r = hipfftSetStream(h, st);
+        if (r == HIPFFT_SUCCESS) {
+            if constexpr (std::is_same<T, float>::value)
+                r = hipfftExecC2C(h, (hipfftComplex*)data, (hipfftComplex*)data, dir);
+            else
+                r = hipfftExecZ2Z(h, (hipfftDoubleComplex*)data, (hipfftDoubleComplex*)data, dir);
+        }
+        if (r != HIPFFT_SUCCESS) f.failed = 1;
     };
     for (int kind = 0; kind < 2; ++kind) {   // E bands (of v*), then Z bands (of w)
         const std::vector<FourierQ>& qs = kind == 0 ? f.qe : f.qz;

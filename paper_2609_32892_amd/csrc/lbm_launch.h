@@ -39,6 +39,7 @@ struct FourierProg {
     const void* w;        // w [NC][N]
     int nx, ny, nz;
     std::vector<FourierQ> qe, qz;   // E and Z bands
+    mutable int failed = 0;         // set when a hipFFT call of a launch fails
 };
 
 // One launch per kernel phase covers every member of a group: members share
