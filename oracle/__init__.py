@@ -439,3 +439,17 @@ def project(field, shape, m):
     zs = slice(o, None, m) if nz > 1 else slice(None)
     out = f[:, zs, o::m, o::m]
     return np.ascontiguousarray(out.reshape(out.shape[0], -1))
+
+
+def ks_distance(a, b) -> float:
+    """KS distance of two scalar samples (Sec. 3.1, eq. KS):
+    the largest absolute difference between their empirical cumulative
+    distribution functions F and G.  Both are step functions that change
+    only at sample points, so the maximum is taken over the pooled sample
+    points, with F(x) the fraction of a at or below x."""
+    a = np.sort(np.asarray(a, dtype=np.float64).ravel())
+    b = np.sort(np.asarray(b, dtype=np.float64).ravel())
+    x = np.concatenate([a, b])
+    F = np.searchsorted(a, x, side="right") / a.size
+    G = np.searchsorted(b, x, side="right") / b.size
+    return float(np.max(np.abs(F - G)))
