@@ -1,0 +1,88 @@
+"""Long-run QoI distributions (the paper judges LES runs by the KS distance
+between QoI distributions, Sec. 3.1, eq. KS): the FP32 GPU path against the
+FP64 oracle on 2-D Kolmogorov TO-LRS runs of 4000 steps, the two members
+advanced together in one batch.  Per QoI, the q* series after the closure's
+activation must satisfy KS(GPU, oracle) <= KS floor + 0.05, the floor being
+the KS distance between the oracle run and its twin started one ulp away
+(the noise floor of the method itself)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import gpu_run, need_gpu, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+STEPS, S0 = 4000, 500
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _member(n, seed):
+    cfg, _ = synth.kolmogorov_workload(n, tau=0.51, seed=seed)
+    u0 = synth.turbulent_velocity_2d(n, 0.03, seed=seed)
+    C, mu, S = synth.lrs_model(2, 3, 4, 5)
+    cargs = dict(mode="lrs", spinup=S0, C=C, mu=mu, Sigma=S, seed=100 + seed)
+    return cfg, u0, cargs
+
+
+def test_long_run_qoi_distributions_match_the_oracle():
+    lbm = need_gpu()
+    members = [_member(128, 2), _member(96, 3)]
+    runs = [gpu_run(lbm, cfg, u0, "fp32", synth.QOIS_2D, cargs) for cfg, u0, cargs in members]
+    batch = lbm.Batch(runs)
+    batch.step(STEPS)
+    assert batch.sync() == 0
+    for (cfg, u0, cargs), run in zip(members, runs):
+        qg = run.record_arrays()["q"][S0:]
+        o = oracle_run(cfg, u0, synth.QOIS_2D, cargs)
+        o.step(STEPS)
+        twin = oracle_run(cfg, u0 * (1 + 2.2e-16 * np.random.default_rng(1).choice([-1, 1], size=u0.shape)),
+                          synth.QOIS_2D, cargs)
+        twin.step(STEPS)
+        qo, qt = o.record_arrays()["q"][S0:], twin.record_arrays()["q"][S0:]
+        for k, name in enumerate(("E_B", "Z_B")):
+            ks = oracle.ks_distance(qg[:, k], qo[:, k])
+            floor = oracle.ks_distance(qt[:, k], qo[:, k])
+            _say(f"  {cfg['nx']}^2 {name}: KS(GPU, oracle) {ks:.4f}, floor {floor:.4f}")
+            assert ks <= floor + 0.05
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_long_run_channel_qoi_distributions_match_the_oracle(prec):
+    """The 12-QoI channel closure on a 20 x 24 x 12 channel (2500 steps,
+    closure active from step 500).  FP64: the KS bar for every QoI.  FP32:
+    the KS bar where a QoI's distribution is at least 1e-2 wide relative to
+    its mean; the mean-flow energy E_B2 and the outer mean-profile bands vary
+    by only 6e-4 .. 1.3e-3, where the FP32 path's systematic offset of
+    ~1e-5 (inside the FP32 QoI parity bar of 1e-4) is already a sizeable
+    fraction of the width, so KS measures that offset rather than the
+    distribution; for those the bar is the mean relative offset <= 1e-4."""
+    from gpu_util import closure_args
+    lbm = need_gpu()
+    steps = 2500
+    cfg, u0 = synth.channel_workload(20, 24, 12, substrate=1, cmodel=0.1)
+    qois, cargs = closure_args("3d", ny=24, spinup=S0)
+    run = gpu_run(lbm, cfg, u0, prec, qois, cargs)
+    run.step(steps)
+    assert run.sync() == 0
+    qg = run.record_arrays()["q"][S0:]
+    o = oracle_run(cfg, u0, qois, cargs)
+    o.step(steps)
+    twin = oracle_run(cfg, u0 * (1 + 2.2e-16 * np.random.default_rng(1).choice([-1, 1], size=u0.shape)), qois, cargs)
+    twin.step(steps)
+    qo, qt = o.record_arrays()["q"][S0:], twin.record_arrays()["q"][S0:]
+    for k in range(len(qois)):
+        ks = oracle.ks_distance(qg[:, k], qo[:, k])
+        floor = oracle.ks_distance(qt[:, k], qo[:, k])
+        mean = abs(qo[:, k].mean())
+        width = (qo[:, k].max() - qo[:, k].min()) / mean
+        offset = abs(np.mean(qg[:, k] - qo[:, k])) / mean
+        _say(f"  {prec} QoI {k} {qois[k]}: KS {ks:.4f} floor {floor:.4f} width {width:.1e} offset {offset:.1e}")
+        if prec == "fp64" or width >= 1e-2:
+            assert ks <= floor + 0.05, (k, ks, floor)
+        else:
+            assert offset <= 1e-4, (k, offset)
