@@ -335,15 +335,29 @@ def form_paper_table(lbm, steps):
 def form_batched(lbm, nmem, steps):
     """System form (2): an ensemble of Kolmogorov TO-LES members on uneven
     grids advanced as one batch (one launch per kernel phase for all members,
-    replayed from a hipGraph) vs the same members stepped one after another."""
+    replayed from a hipGraph) vs the same members stepped one after another.
+    Each distinct member shape is autotuned once (lbm_autotune, with a tuning
+    cache in a temporary file); both sides use the tuned launch shapes."""
+    import os
+    import tempfile
     import numpy as np
     import synth
     mem = synth.ensemble_members(nmem)
     cells = sum(m["n"] ** 2 for m in mem)
+    cache = os.path.join(tempfile.mkdtemp(prefix="lbm_tune_"), "tune.txt")
+    tunings = {}
+    t = time.perf_counter()
+    for n in sorted({m["n"] for m in mem}):
+        m = next(x for x in mem if x["n"] == n)
+        cfg, spec, _ = kolmogorov_member(lbm, n, m["ic_seed"], m["noise_seed"], spinup=steps // 4)
+        tunings[n] = lbm.autotune(cfg, spec, steps=100, cache=cache)
+    tune_s = time.perf_counter() - t
     runs_b, runs_s = [], []
     for m in mem:
         for lst in (runs_b, runs_s):
             cfg, spec, u0 = kolmogorov_member(lbm, m["n"], m["ic_seed"], m["noise_seed"], spinup=steps // 4)
+            for k in ("tune_zc", "tune_cpt", "tune_btx"):
+                setattr(cfg, k, tunings[m["n"]][k])
             r = lbm.Run(cfg, spec)
             r.init_velocity(u0)
             lst.append(r)
@@ -366,7 +380,10 @@ def form_batched(lbm, nmem, steps):
     res = {"members": nmem, "cells": cells, "steps": steps,
            "batched_mlups": round(cells * steps / tb / 1e6, 1),
            "sequential_mlups": round(cells * steps / ts / 1e6, 1),
-           "speedup": round(ts / tb, 3), "bitwise_equal_to_solo": bool(same)}
+           "speedup": round(ts / tb, 3), "bitwise_equal_to_solo": bool(same),
+           "autotune": {"shapes": len(tunings), "seconds": round(tune_s, 2),
+                        "timed_candidates": sum(v["candidates"] for v in tunings.values()),
+                        "cpt": {str(n): v["tune_cpt"] for n, v in sorted(tunings.items())}}}
     batch.close()
     for r in runs_b + runs_s:
         r.close()

@@ -186,6 +186,10 @@ int lbm_lrs_fit(int nq, int h, long nsteps, const double* q_star, const double* 
 /* Library and lattice information. */
 const char* lbm_last_error(void);
 const char* lbm_version(void);
+/* Name of the current HIP device and its compute-unit count, e.g.
+ * "gfx950 256CU", into out (n bytes, NUL-terminated).  LBM_EDEVICE without
+ * a device. */
+int lbm_device_tag(char* out, size_t n);
 /* Velocity table (3 ints per velocity) and weights of the library's own
  * lattice ordering; returns Q or a negative status. */
 int lbm_lattice_info(int lattice, int* c, double* w);
@@ -264,6 +268,35 @@ int lbm_project_qoi(lbm_ctx* fine, lbm_ctx* probe, int m);
 size_t lbm_state_bytes(const lbm_ctx* ctx);
 int lbm_get_state(lbm_ctx* ctx, void* host, size_t bytes);
 int lbm_set_state(lbm_ctx* ctx, const void* host, size_t bytes);
+
+
+/* Autotuner of the launch shapes (the tune_* fields of lbm_config): the
+ * binomial tile width, the z planes per binomial workgroup and the cells
+ * per thread of the QoI reduction.  Candidates are timed on a scratch
+ * context in dev_arena (caller-owned, 256-byte aligned, at least
+ * lbm_autotune_bytes(cfg, closure) bytes; its contents are overwritten),
+ * each for `steps` steps after a warm-up, started from a small seeded
+ * velocity field: a coordinate descent from the automatic choice over the
+ * tile width, then the z chunk, then the cells per thread.  Every candidate
+ * gives the same per-cell results (tile width and z chunk bitwise; the
+ * cells per thread change only the order of the FP64 partial sums).
+ * cache_path (may be NULL): a text file with one line per device, grid and
+ * closure shape (key TAB zc cpt btx microseconds-per-step); a matching line
+ * is returned without timing (from_cache = 1), a new result is appended.
+ * Runs on the current device; syncs. */
+typedef struct {
+    int tune_zc, tune_cpt, tune_btx;   /* to copy into lbm_config */
+    double us_per_step;                /* the chosen candidate's time per step */
+    int from_cache;                    /* 1: read from the cache file */
+    int candidates;                    /* candidates timed (0 when cached) */
+} lbm_tuning;
+size_t lbm_autotune_bytes(const lbm_config* cfg, const lbm_closure* closure);
+/* The cache key of (device, cfg, closure) that lbm_autotune uses, into out
+ * (n bytes; LBM_EINVAL if too small).  Without a device the device part
+ * reads "unknown". */
+int lbm_autotune_key(const lbm_config* cfg, const lbm_closure* closure, char* out, size_t n);
+int lbm_autotune(const lbm_config* cfg, const lbm_closure* closure, void* dev_arena, size_t bytes,
+                 void* stream, int steps, const char* cache_path, lbm_tuning* out);
 
 /* Batch: advance several contexts (created on the same device and stream)
  * together, one launch per kernel phase for all members of the same kind,

@@ -19,7 +19,7 @@ FLAGS = [
 ]
 
 
-HOST_SOURCES = ["lbm_fit.cpp"]   # host-only code (the LRS fit)
+HOST_SOURCES = ["lbm_fit.cpp", "lbm_tune.cpp"]   # host-only code (the LRS fit, the autotuner)
 HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-pthread", "-Wall"]
 
 

@@ -810,6 +810,17 @@ extern "C" {
 const char* lbm_last_error(void) { return g_err.c_str(); }
 const char* lbm_version(void) { return "lbm_hip 0.1 (gfx950)"; }
 
+int lbm_device_tag(char* out, size_t n)
+{
+    if (!out || n == 0) return fail(LBM_EINVAL, "device_tag: no buffer");
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess)
+        return fail(LBM_EDEVICE, "device_tag: no HIP device");
+    std::snprintf(out, n, "%s %dCU", p.gcnArchName, p.multiProcessorCount);
+    return LBM_OK;
+}
+
 int lbm_lattice_info(int lattice, int* c, double* w)
 {
     if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) return fail(LBM_EINVAL, "bad lattice");

@@ -66,6 +66,11 @@ class Closure(ct.Structure):
                 ("nref", ct.c_long), ("seed", ct.c_uint64)]
 
 
+class Tuning(ct.Structure):
+    _fields_ = [("tune_zc", ct.c_int), ("tune_cpt", ct.c_int), ("tune_btx", ct.c_int),
+                ("us_per_step", ct.c_double), ("from_cache", ct.c_int), ("candidates", ct.c_int)]
+
+
 class QoiRec(ct.Structure):
     _fields_ = [("step", ct.c_int64), ("flags", ct.c_int32), ("nq", ct.c_int32), ("mass", ct.c_double),
                 ("mom", ct.c_double * 3), ("diag_e", ct.c_double), ("diag_z", ct.c_double),
@@ -88,7 +93,8 @@ EXPORTS = [
     "lbm_batch_sync", "lbm_batch_destroy", "lbm_profile_phases", "lbm_test_philox", "lbm_test_normals",
     "lbm_server_clock", "lbm_server_create", "lbm_server_submit", "lbm_server_advance", "lbm_server_poll",
     "lbm_server_pending", "lbm_server_stats", "lbm_server_state_bytes", "lbm_server_take_state",
-    "lbm_server_destroy", "lbm_lrs_fit", "lbm_project_state", "lbm_project_qoi",
+    "lbm_server_destroy", "lbm_lrs_fit", "lbm_project_state", "lbm_project_qoi", "lbm_device_tag",
+    "lbm_autotune_bytes", "lbm_autotune", "lbm_autotune_key",
 ]
 PHASES = ["stream_collide", "curl", "binomial", "reduce", "solve", "apply"]
 
@@ -150,6 +156,12 @@ def lib():
         L.lbm_server_destroy.argtypes = [P]
         L.lbm_server_destroy.restype = None
         L.lbm_lrs_fit.argtypes = [I, I, ct.c_long, P, P, P, P, ct.c_double, P, P, P, P]
+        L.lbm_device_tag.argtypes = [ct.c_char_p, Z]
+        L.lbm_autotune_key.argtypes = [ct.POINTER(Config), ct.POINTER(Closure), ct.c_char_p, Z]
+        L.lbm_autotune_bytes.restype = Z
+        L.lbm_autotune_bytes.argtypes = [ct.POINTER(Config), ct.POINTER(Closure)]
+        L.lbm_autotune.argtypes = [ct.POINTER(Config), ct.POINTER(Closure), P, Z, P, I, ct.c_char_p,
+                                   ct.POINTER(Tuning)]
         L.lbm_project_state.argtypes = [P, P, I]
         L.lbm_project_qoi.argtypes = [P, P, I]
         _lib = L
@@ -164,6 +176,51 @@ def check(rc):
 
 def _p(a):
     return None if a is None else a.ctypes.data_as(ct.c_void_p)
+
+
+def device_tag():
+    """The current HIP device's name and compute-unit count (lbm_device_tag)."""
+    L = lib()
+    buf = ct.create_string_buffer(128)
+    check(L.lbm_device_tag(buf, 128))
+    return buf.value.decode()
+
+
+def autotune_key(cfg: "Config", closure: "ClosureSpec | None" = None):
+    """The tuning-cache key of cfg and closure on the current device."""
+    L = lib()
+    buf = ct.create_string_buffer(4096)
+    check(L.lbm_autotune_key(ct.byref(cfg), ct.byref(closure.c) if closure is not None else None, buf, 4096))
+    return buf.value.decode()
+
+
+def autotune(cfg: "Config", closure: "ClosureSpec | None" = None, steps=200, cache=None, device="cuda"):
+    """Time the launch-shape candidates of cfg (lbm_autotune) in a scratch
+    arena and return the chosen tuning as a dict: tune_zc, tune_cpt and
+    tune_btx (keyword arguments of make_config), us_per_step, from_cache and
+    candidates.  cache: path of the tuning cache file (or None)."""
+    import torch
+    L = lib()
+    clp = ct.byref(closure.c) if closure is not None else None
+    nbytes = L.lbm_autotune_bytes(ct.byref(cfg), clp)
+    if nbytes == 0:
+        raise LbmError(EINVAL, L.lbm_last_error().decode())
+    out = Tuning()
+    path = None if cache is None else os.fsencode(cache)
+    arena = None
+    if cache is not None and os.path.exists(cache):
+        # a cache hit needs no arena: try without one first
+        rc = L.lbm_autotune(ct.byref(cfg), clp, None, 0, None, steps, path, ct.byref(out))
+        if rc == OK and out.from_cache:
+            return {f: getattr(out, f) for f, _ in Tuning._fields_}
+    arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    base = arena.data_ptr()
+    off = (-base) % 256
+    with torch.cuda.device(arena.device):
+        check(L.lbm_autotune(ct.byref(cfg), clp, ct.c_void_p(base + off), nbytes,
+                             ct.c_void_p(default_stream().cuda_stream), steps, path, ct.byref(out)))
+    del arena
+    return {f: getattr(out, f) for f, _ in Tuning._fields_}
 
 
 def lrs_fit(q_star, dq, h, lam, scale=None, flags=None):

@@ -134,3 +134,34 @@ def test_fourier_closure_validation(lbm):
     assert L.lbm_required_bytes(ct.byref(walls), ct.byref(ok.c)) == 0
     assert L.lbm_required_bytes(ct.byref(per), ct.byref(lbm.ClosureSpec([("E", "F5-4", 0)]).c)) == 0
     assert L.lbm_required_bytes(ct.byref(per), ct.byref(lbm.ClosureSpec([("E", "F0-4", 0), ("Z", "B", 0)]).c)) == 0
+
+
+def test_autotune_key_bytes_and_cache_hit(lbm, tmp_path):
+    """The tuning cache (host logic, no device needed for a hit): keys
+    separate grids and closures; a cached line is returned as is (the last
+    matching line wins, malformed lines are skipped); the scratch arena
+    covers every candidate."""
+    import synth
+    cfg = lbm.make_config(lattice=lbm.D3Q19, nx=64, ny=24, nz=16, walls_y=1, tau=0.51, substrate=1, cmodel=0.1)
+    nb, dmin, dmax = synth.channel_bands(24)
+    spec = lbm.ClosureSpec(synth.QOIS_3D, mode="off", nbands=nb, dmin=dmin, dmax=dmax)
+    key = lbm.autotune_key(cfg, spec)
+    assert "grid=64x24x16" in key and "nq=12" in key and "\t" not in key
+    other = lbm.make_config(lattice=lbm.D3Q19, nx=64, ny=24, nz=20, walls_y=1, tau=0.51, substrate=1, cmodel=0.1)
+    assert lbm.autotune_key(other, spec) != key
+    assert lbm.autotune_key(cfg, None) != key
+    L = lbm.lib()
+    import ctypes as ct
+    need = L.lbm_autotune_bytes(ct.byref(cfg), ct.byref(spec.c))
+    for zc in (0, 1, 16):
+        for cpt in (0, 8):
+            for btx in (0, 32, 64):
+                t = lbm.make_config(lattice=lbm.D3Q19, nx=64, ny=24, nz=16, walls_y=1, tau=0.51, substrate=1,
+                                    cmodel=0.1, tune_zc=zc, tune_cpt=cpt, tune_btx=btx)
+                assert L.lbm_required_bytes(ct.byref(t), ct.byref(spec.c)) <= need
+    path = tmp_path / "tune.txt"
+    path.write_text(f"{key}\t2 1 32 90.5\nnot a line\n{lbm.autotune_key(other, spec)}\t4 4 64 1.0\n"
+                    f"{key}\t1 4 64 80.25\n")
+    t = lbm.autotune(cfg, spec, cache=str(path))
+    assert t["from_cache"] == 1 and t["candidates"] == 0
+    assert (t["tune_zc"], t["tune_cpt"], t["tune_btx"], t["us_per_step"]) == (1, 4, 64, 80.25)

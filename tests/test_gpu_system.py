@@ -170,3 +170,33 @@ def test_write_through_and_plain_stores_bitwise_equal():
         _say(f"  {prec}: small member solo vs batched with a 0.74 M-cell member")
         assert np.array_equal(small.get_populations(), solo.get_populations())
         assert np.array_equal(small.record_arrays()["dq"], solo.record_arrays()["dq"])
+
+
+def test_autotune_times_candidates_and_caches(tmp_path):
+    """The autotuner times the candidates of a channel TO-LES on the device,
+    appends the choice to the cache and returns it from there on the next
+    call; the tuned run agrees with the untuned one (tile width and z chunk
+    leave every cell bitwise the same, the cells per thread of the reduction
+    only reorder its FP64 partial sums)."""
+    lbm = need_gpu()
+    cfg, u0 = synth.channel_workload(64, 24, 16, substrate=1, cmodel=0.1)
+    qois, cargs = closure_args("3d", ny=24, spinup=10)
+    spec = lbm.ClosureSpec(qois, **cargs)
+    path = tmp_path / "tune.txt"
+    t1 = lbm.autotune(lbm.make_config(precision="fp32", **cfg), spec, steps=40, cache=str(path))
+    _say(f"  autotune: {t1}")
+    assert t1["from_cache"] == 0 and t1["candidates"] >= 3 and t1["us_per_step"] > 0
+    assert t1["tune_btx"] in (0, 32, 64) and t1["tune_zc"] in (0, 1, 2, 4, 8, 16) and t1["tune_cpt"] in (0, 1, 2, 4, 8)
+    assert path.read_text().count("\n") == 1
+    t2 = lbm.autotune(lbm.make_config(precision="fp32", **cfg), spec, steps=40, cache=str(path))
+    assert t2["from_cache"] == 1
+    assert [t2[k] for k in ("tune_zc", "tune_cpt", "tune_btx")] == [t1[k] for k in ("tune_zc", "tune_cpt", "tune_btx")]
+    tuned = {k: t1[k] for k in ("tune_zc", "tune_cpt", "tune_btx")}
+    a = gpu_run(lbm, cfg, u0, "fp32", qois, cargs)
+    b = gpu_run(lbm, cfg, u0, "fp32", qois, cargs, **tuned)
+    a.step(50)
+    b.step(50)
+    a.sync()
+    b.sync()
+    ua, ub = a.fields()[1], b.fields()[1]
+    assert np.max(np.abs(ua - ub)) <= 1e-5 * np.max(np.abs(ua))
