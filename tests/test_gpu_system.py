@@ -200,3 +200,30 @@ def test_autotune_times_candidates_and_caches(tmp_path):
     b.sync()
     ua, ub = a.fields()[1], b.fields()[1]
     assert np.max(np.abs(ua - ub)) <= 1e-5 * np.max(np.abs(ua))
+
+
+def test_nan_member_flags_only_itself_in_a_batch():
+    """Failure isolation: a NaN put into one member's populations makes that
+    member unstable (sticky flag, LBM_EUNSTABLE from its sync and the
+    batch's), while its batch neighbour stays bitwise equal to a solo run."""
+    lbm = need_gpu()
+    cfg_a, u_a, qois, cargs_a = _case2d(48, seed=1)
+    cfg_b, u_b, _, cargs_b = _case2d(64, seed=2)
+    a = gpu_run(lbm, cfg_a, u_a, "fp32", qois, cargs_a)
+    b = gpu_run(lbm, cfg_b, u_b, "fp32", qois, cargs_b)
+    solo = gpu_run(lbm, cfg_b, u_b, "fp32", qois, cargs_b)
+    f = a.get_populations()
+    f[3, 100] = np.nan
+    a.set_populations(f)
+    batch = lbm.Batch([a, b])
+    batch.step(20)
+    with pytest.raises(lbm.LbmError):
+        batch.sync()
+    with pytest.raises(lbm.LbmError):
+        a.sync()
+    assert b.sync() == 0
+    assert np.any(a.record_arrays()["flags"] & 1)
+    assert not np.any(b.record_arrays()["flags"] & 1)
+    solo.step(20)
+    solo.sync()
+    assert np.array_equal(b.get_populations(), solo.get_populations())
