@@ -621,6 +621,9 @@ def main():
         print(f"[bench] batched: {forms['batched']}", file=sys.stderr, flush=True)
         forms["served"] = form_served(lbm, args.serve_requests, 20.0, 2000)
         print(f"[bench] served: {forms['served']}", file=sys.stderr, flush=True)
+        # the same trace under a 2 GB HBM budget: admission queues requests
+        forms["served_2gb"] = form_served(lbm, args.serve_requests, 20.0, 2000, budget=2 << 30)
+        print(f"[bench] served (2 GB budget): {forms['served_2gb']}", file=sys.stderr, flush=True)
         forms["fine_grid_plain"] = form_fine(lbm, 200)
         print(f"[bench] fine grid: {forms['fine_grid_plain']}", file=sys.stderr, flush=True)
         forms["hf_to_lf"] = form_hf_lf(lbm, 200)
