@@ -138,7 +138,11 @@ __device__ __forceinline__ void st_at(T* base, unsigned i, T v)
 // Measured on MI355X (FP32 channel TO-LES): 2427 -> 2592 MLUPS on
 // 96 x 48 x 48; no change on 384 x 192 x 192; but 1328 -> 1130 MLUPS for
 // the kernel-filter closure on 295 x 47 x 98, whose fields the next kernel
-// otherwise finds in the Infinity Cache.  Plain stores there.
+// otherwise finds in the Infinity Cache.  Larger launches store
+// non-temporally (5228 -> 5310..5321 MLUPS on 384 x 192 x 192; no change on
+// 295 x 47 x 98): the stream-collide itself slows (457 -> 485 us), but its
+// populations then no longer push the TO fields out of the Infinity Cache
+// (binomial pass 209 -> 203 us, reduce 453 -> 424 us, curl 86 -> 79 us).
 template <typename T>
 __device__ __forceinline__ void st_dev(T* p, T v)
 {
@@ -148,7 +152,7 @@ template <typename T>
 __device__ __forceinline__ void st_fld(T* p, T v, int wt)
 {
     if (wt) st_dev(p, v);
-    else *p = v;
+    else __builtin_nontemporal_store(v, p);
 }
 template <typename T>
 __device__ __forceinline__ void st_fld_at(T* base, unsigned i, T v, int wt)
