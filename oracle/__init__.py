@@ -441,6 +441,48 @@ def project(field, shape, m):
     return np.ascontiguousarray(out.reshape(out.shape[0], -1))
 
 
+def keys_cubic(t):
+    """The cubic convolution kernel of Keys (1981) with a = -1/2:
+    1.5|t|^3 - 2.5|t|^2 + 1 for |t| <= 1, -0.5|t|^3 + 2.5|t|^2 - 4|t| + 2 for
+    1 < |t| < 2, zero beyond."""
+    t = np.abs(np.asarray(t, dtype=np.float64))
+    return np.where(t <= 1, 1.5 * t ** 3 - 2.5 * t ** 2 + 1,
+                    np.where(t < 2, -0.5 * t ** 3 + 2.5 * t ** 2 - 4 * t + 2, 0.0))
+
+
+def bicubic_matrix(nf, m):
+    """The 1-D factor of the bicubic projection phi_m of a periodic axis
+    (Sec. 3, the Kolmogorov case): coarse cell i is the weighted mean of the
+    fine cells j = m i + o + r (o = (m - 1) / 2, m odd, periodic wrap), with
+    weights keys_cubic(r / m) for |r| < 2 m normalised to unit sum (the
+    kernel widened m-fold for the m-fold coarser grid).  Returns the
+    (nf / m) x nf matrix."""
+    if m < 1 or m % 2 == 0 or nf % m:
+        raise ValueError("m must be odd and divide the axis")
+    nc, o = nf // m, (m - 1) // 2
+    r = np.arange(-2 * m + 1, 2 * m)
+    w = keys_cubic(r / m)
+    w = w / w.sum()
+    W = np.zeros((nc, nf))
+    for i in range(nc):
+        for rr, ww in zip(r, w):
+            W[i, (m * i + o + rr) % nf] += ww
+    return W
+
+
+def project_bicubic(field, shape, m):
+    """Bicubic projection phi_m of a doubly periodic 2-D field (Sec. 3, the
+    Kolmogorov case), the tensor product of bicubic_matrix along y and x.
+    field: (ncomp, N) in the (1, ny, nx) layout of `shape`."""
+    nz, ny, nx = shape
+    if nz != 1:
+        raise ValueError("2-D fields only")
+    f = np.asarray(field, dtype=np.float64).reshape(-1, ny, nx)
+    Wy, Wx = bicubic_matrix(ny, m), bicubic_matrix(nx, m)
+    out = np.einsum("ab,cbd,ed->cae", Wy, f, Wx)
+    return np.ascontiguousarray(out.reshape(out.shape[0], -1))
+
+
 def ks_distance(a, b) -> float:
     """KS distance of two scalar samples (Sec. 3.1, eq. KS):
     the largest absolute difference between their empirical cumulative
