@@ -262,6 +262,20 @@ int lbm_stream_only(lbm_ctx* ctx);
 int lbm_project_state(lbm_ctx* fine, lbm_ctx* coarse, int m);
 int lbm_project_qoi(lbm_ctx* fine, lbm_ctx* probe, int m);
 
+/* The same with a choice of projection (Sec. 3): LBM_PROJ_STRIDE as above;
+ * LBM_PROJ_BICUBIC, the paper's projection for the doubly periodic
+ * Kolmogorov flow: coarse cell (i, j) is the mean of the fine cells
+ * (m i + o + rx, m j + o + ry), |rx|, |ry| < 2 m, periodic wrap, with
+ * weights K(rx / m) K(ry / m) normalised to unit sum, K the cubic
+ * convolution kernel of Keys with a = -1/2 (the bicubic kernel widened
+ * m-fold for the m-fold coarser grid).  Populations are projected as
+ * populations; the probe's QoIs are evaluated on the projected fine-cell
+ * velocities.  Bicubic needs D2Q9 without walls and m <= 15 (odd);
+ * LBM_EINVAL otherwise. */
+enum { LBM_PROJ_STRIDE = 0, LBM_PROJ_BICUBIC = 1 };
+int lbm_project_state_kind(lbm_ctx* fine, lbm_ctx* coarse, int m, int kind);
+int lbm_project_qoi_kind(lbm_ctx* fine, lbm_ctx* probe, int m, int kind);
+
 /* Checkpoint: opaque byte image of the dynamic state (populations,
  * counters, LRS scale, records).  Restoring it into a context created with
  * the same cfg and closure resumes bitwise identically. */

@@ -1126,10 +1126,13 @@ int lbm_stream_only(lbm_ctx* c)
 // HF -> LF projection (Sec. 3, phi_m; Sec. 7.1: wall-anchored stride-m
 // subsampling).  The coarse grid is the fine one divided by m on every axis
 // (z kept in 2-D), same lattice and wall setting; m odd.
-static int check_projection(const lbm_ctx* f, const lbm_ctx* c, int m)
+static int check_projection(const lbm_ctx* f, const lbm_ctx* c, int m, int kind)
 {
     if (!f || !c) return fail(LBM_EINVAL, "NULL context");
     if (m < 1 || m % 2 == 0) return fail(LBM_EINVAL, "projection: m must be odd and positive");
+    if (kind != LBM_PROJ_STRIDE && kind != LBM_PROJ_BICUBIC) return fail(LBM_EINVAL, "projection: bad kind");
+    if (kind == LBM_PROJ_BICUBIC && (f->cfg.lattice != LBM_D2Q9 || f->cfg.walls_y || m > 15))
+        return fail(LBM_EINVAL, "projection: bicubic needs a doubly periodic D2Q9 grid and m <= 15");
     if (f->cfg.lattice != c->cfg.lattice || f->cfg.walls_y != c->cfg.walls_y)
         return fail(LBM_EINVAL, "projection: lattice and walls must match");
     const bool d3 = f->cfg.lattice == LBM_D3Q19;
@@ -1139,16 +1142,19 @@ static int check_projection(const lbm_ctx* f, const lbm_ctx* c, int m)
     return LBM_OK;
 }
 
-int lbm_project_state(lbm_ctx* f, lbm_ctx* c, int m)
+int lbm_project_state(lbm_ctx* f, lbm_ctx* c, int m) { return lbm_project_state_kind(f, c, m, LBM_PROJ_STRIDE); }
+int lbm_project_qoi(lbm_ctx* f, lbm_ctx* p, int m) { return lbm_project_qoi_kind(f, p, m, LBM_PROJ_STRIDE); }
+
+int lbm_project_state_kind(lbm_ctx* f, lbm_ctx* c, int m, int kind)
 {
-    int rc = check_projection(f, c, m);
+    int rc = check_projection(f, c, m, kind);
     if (rc) return rc;
     const size_t Nc = c->plan.N, Q = c->plan.Q;
     HIPCHK(hipStreamSynchronize(f->stream));   // the fine run's pending steps
     double* buf = nullptr;
     HIPCHK(hipMalloc(&buf, sizeof(double) * Q * Nc));
     launch_project(f->cfg.lattice, f->cfg.precision, f->dm, f->phase, m, c->cfg.nx, c->cfg.ny, c->cfg.nz, buf,
-                   nullptr, 0, f->stream);
+                   nullptr, 0, kind, f->stream);
     if (hipStreamSynchronize(f->stream) != hipSuccess) rc = fail(LBM_EDEVICE, "projection kernel failed");
     if (!rc) {
         c->phase = 0;
@@ -1162,15 +1168,15 @@ int lbm_project_state(lbm_ctx* f, lbm_ctx* c, int m)
     return rc;
 }
 
-int lbm_project_qoi(lbm_ctx* f, lbm_ctx* p, int m)
+int lbm_project_qoi_kind(lbm_ctx* f, lbm_ctx* p, int m, int kind)
 {
-    int rc = check_projection(f, p, m);
+    int rc = check_projection(f, p, m, kind);
     if (rc) return rc;
     if (!p->has_to || p->cur.nq == 0 || p->hp.mode != LBM_CLOSURE_OFF)
         return fail(LBM_EINVAL, "project_qoi: the probe needs a closure in mode OFF");
     if (f->stream != p->stream) return fail(LBM_EINVAL, "project_qoi: fine run and probe must share one stream");
     launch_project(f->cfg.lattice, f->cfg.precision, f->dm, f->phase, m, p->cfg.nx, p->cfg.ny, p->cfg.nz, nullptr,
-                   p->arena + p->plan.vs, p->cfg.precision == LBM_FP64, p->stream);
+                   p->arena + p->plan.vs, p->cfg.precision == LBM_FP64, kind, p->stream);
     LaunchGroup g = ctx_group(p);
     g.probe = 1;
     launch_step(g, p->stream, p->phase);

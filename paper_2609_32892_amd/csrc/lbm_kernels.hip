@@ -1877,7 +1877,7 @@ __global__ void k_set_pop(const DevMember* __restrict__ mems, int flip, const do
 template <int LAT, typename T, int PREC>
 __global__ __launch_bounds__(kBlock) void k_project(const DevMember* __restrict__ fine, int flip, int m, int ncx,
                                                     int ncy, int ncz, double* __restrict__ fpop,
-                                                    void* __restrict__ vout, int vout_fp64)
+                                                    void* __restrict__ vout, int vout_fp64, int kind)
 {
     using L = Lat<LAT>;
     KMember& F = *kc(fine);
@@ -1886,6 +1886,58 @@ __global__ __launch_bounds__(kBlock) void k_project(const DevMember* __restrict_
     if (cell >= Nc) return;
     const int i = cell % ncx, t = cell / ncx, j = t % ncy, k = t / ncy;
     const int o = (m - 1) / 2;
+    if (L::D == 2 && kind == LBM_PROJ_BICUBIC) {
+        // bicubic (2-D, doubly periodic): the weighted mean over fine cells
+        // (m i + o + rx, m j + o + ry), |rx|, |ry| < 2 m, with weights
+        // K(rx / m) K(ry / m) / S^2, K the Keys cubic (a = -1/2), S the sum
+        // of K(r / m) over the window; of the populations, and of the
+        // velocity of each fine cell
+        const int R = 2 * m - 1;
+        auto keys = [](double x) {
+            x = fabs(x);
+            return x <= 1.0 ? (1.5 * x - 2.5) * x * x + 1.0 : (x < 2.0 ? ((-0.5 * x + 2.5) * x - 4.0) * x + 2.0 : 0.0);
+        };
+        double S = 0;
+        for (int r = -R; r <= R; ++r) S += keys((double)r / m);
+        const double rS = 1.0 / S;
+        const size_t NF = (size_t)F.N;
+        const T* g = (const T*)F.g[F.parity ^ flip];
+        double acc[L::Q], uacc[2] = {0, 0};
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) acc[q] = 0;
+        for (int ry = -R; ry <= R; ++ry) {
+            const double wy = keys((double)ry / m) * rS;
+            const int yf = modi(m * j + o + ry, F.ny);
+            for (int rx = -R; rx <= R; ++rx) {
+                const double w = wy * keys((double)rx / m) * rS;
+                const size_t fc = (size_t)yf * F.nx + (size_t)modi(m * i + o + rx, F.nx);
+                double drho = 0, jx = 0, jy = 0;
+#pragma unroll
+                for (int q = 0; q < L::Q; ++q) {
+                    const double gq = (double)g[(size_t)q * NF + fc];
+                    acc[q] += w * gq;
+                    drho += gq;
+                    jx += L::cx[q] * gq;
+                    jy += L::cy[q] * gq;
+                }
+                const double rho = PREC == LBM_FP32_PLAIN ? drho : 1.0 + drho;
+                uacc[0] += w * (jx / rho);
+                uacc[1] += w * (jy / rho);
+            }
+        }
+        if (fpop) {
+#pragma unroll
+            for (int q = 0; q < L::Q; ++q) fpop[(size_t)q * Nc + cell] = acc[q] + (PREC == LBM_FP32_PLAIN ? 0.0 : L::w[q]);
+        }
+        if (vout) {
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                if (vout_fp64) ((double*)vout)[(size_t)a * Nc + cell] = uacc[a];
+                else ((float*)vout)[(size_t)a * Nc + cell] = (float)uacc[a];
+            }
+        }
+        return;
+    }
     const int zf = L::D == 3 ? m * k + o : 0;
     const size_t fc = ((size_t)zf * F.ny + (size_t)(m * j + o)) * F.nx + (size_t)(m * i + o);
     const size_t NF = (size_t)F.N;
@@ -1913,12 +1965,13 @@ __global__ __launch_bounds__(kBlock) void k_project(const DevMember* __restrict_
 }
 
 void launch_project(int lattice, int precision, const DevMember* fine, int flip, int m, int ncx, int ncy, int ncz,
-                    double* fpop, void* vout, int vout_fp64, hipStream_t st)
+                    double* fpop, void* vout, int vout_fp64, int kind, hipStream_t st)
 {
     const int Nc = ncx * ncy * ncz;
     const dim3 blk(kBlock), grd((Nc + kBlock - 1) / kBlock);
-#define LBM_PROJ(LAT, T, PREC) \
-    hipLaunchKernelGGL((k_project<LAT, T, PREC>), grd, blk, 0, st, fine, flip, m, ncx, ncy, ncz, fpop, vout, vout_fp64)
+#define LBM_PROJ(LAT, T, PREC)                                                                                    \
+    hipLaunchKernelGGL((k_project<LAT, T, PREC>), grd, blk, 0, st, fine, flip, m, ncx, ncy, ncz, fpop, vout, vout_fp64, \
+                       kind)
     switch (lattice * 3 + precision) {
     case LBM_D2Q9 * 3 + LBM_FP32_SHIFTED: LBM_PROJ(LBM_D2Q9, float, LBM_FP32_SHIFTED); break;
     case LBM_D2Q9 * 3 + LBM_FP64: LBM_PROJ(LBM_D2Q9, double, LBM_FP64); break;

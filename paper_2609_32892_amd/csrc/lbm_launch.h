@@ -85,10 +85,12 @@ void launch_fields(int lattice, int precision, const DevMember* dm, const int2* 
 void launch_philox_test(const uint32_t* in, uint32_t* out, int n, hipStream_t st);
 void launch_normals_test(unsigned long long seed, long long step0, int nsteps, int n, double* out, hipStream_t st);
 int lattice_table(int lattice, int* c, double* w);
-// Wall-anchored stride-m projection of a fine member's state (coarse grid
-// ncx x ncy x ncz): full populations into fpop [Q][Nc] (nullable) and the
-// post-collision velocity into vout [D][Nc] (nullable; double if vout_fp64).
+// Projection of a fine member's state (coarse grid ncx x ncy x ncz; kind
+// LBM_PROJ_STRIDE: the wall-anchored stride-m subsampling; LBM_PROJ_BICUBIC:
+// the bicubic mean of a doubly periodic 2-D grid): full populations into
+// fpop [Q][Nc] (nullable) and the post-collision velocity into vout [D][Nc]
+// (nullable; double if vout_fp64).
 void launch_project(int lattice, int precision, const DevMember* fine, int flip, int m, int ncx, int ncy, int ncz,
-                    double* fpop, void* vout, int vout_fp64, hipStream_t st);
+                    double* fpop, void* vout, int vout_fp64, int kind, hipStream_t st);
 
 }  // namespace lbm

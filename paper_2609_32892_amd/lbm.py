@@ -94,9 +94,10 @@ EXPORTS = [
     "lbm_server_clock", "lbm_server_create", "lbm_server_submit", "lbm_server_advance", "lbm_server_poll",
     "lbm_server_pending", "lbm_server_stats", "lbm_server_state_bytes", "lbm_server_take_state",
     "lbm_server_destroy", "lbm_lrs_fit", "lbm_project_state", "lbm_project_qoi", "lbm_device_tag",
-    "lbm_autotune_bytes", "lbm_autotune", "lbm_autotune_key",
+    "lbm_autotune_bytes", "lbm_autotune", "lbm_autotune_key", "lbm_project_state_kind", "lbm_project_qoi_kind",
 ]
 PHASES = ["stream_collide", "curl", "binomial", "reduce", "solve", "apply"]
+PROJ = {"stride": 0, "bicubic": 1}
 
 _lib = None
 
@@ -164,6 +165,8 @@ def lib():
                                    ct.POINTER(Tuning)]
         L.lbm_project_state.argtypes = [P, P, I]
         L.lbm_project_qoi.argtypes = [P, P, I]
+        L.lbm_project_state_kind.argtypes = [P, P, I, I]
+        L.lbm_project_qoi_kind.argtypes = [P, P, I, I]
         _lib = L
     return _lib
 
@@ -404,15 +407,15 @@ class Run:
     def stream_only(self):
         check(self.L.lbm_stream_only(self.h))
 
-    def project_state_from(self, fine: "Run", m: int):
-        """This (coarse) run's state := the wall-anchored stride-m projection
-        of the fine run's state (lbm_project_state)."""
-        check(self.L.lbm_project_state(fine.h, self.h, m))
+    def project_state_from(self, fine: "Run", m: int, kind: str = "stride"):
+        """This (coarse) run's state becomes the projection phi_m of the fine
+        run's state (lbm_project_state_kind; kind "stride" or "bicubic")."""
+        check(self.L.lbm_project_state_kind(fine.h, self.h, m, PROJ[kind]))
 
-    def project_qoi_from(self, fine: "Run", m: int):
-        """Append the closure QoIs of the projected fine post-collision
-        velocity as this probe's next record (lbm_project_qoi)."""
-        check(self.L.lbm_project_qoi(fine.h, self.h, m))
+    def project_qoi_from(self, fine: "Run", m: int, kind: str = "stride"):
+        """Append the QoIs of the fine run's projected post-collision
+        velocity as this probe's next record (lbm_project_qoi_kind)."""
+        check(self.L.lbm_project_qoi_kind(fine.h, self.h, m, PROJ[kind]))
 
     def profile_phases(self, nsteps):
         """Mean ms per step and launches per step of each kernel phase."""

@@ -111,3 +111,48 @@ def test_hf_to_lf_tracking_workflow():
     drift = np.max(np.abs(runs["off"]["q"][S0:] - qref[S0:]) / np.abs(qref[S0:]))
     _say(f"  uncorrected coarse run vs projected reference: max rel {drift:.2e}")
     assert drift > 1e-3
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_bicubic_projection_matches_oracle(prec):
+    """The paper's projection of the periodic Kolmogorov case (Sec. 3):
+    bicubic mean of the fine populations and of the fine post-collision
+    velocities, against the oracle's bicubic projection."""
+    lbm = need_gpu()
+    cfg, u0, ccfg, qois, bands, m, _ = _cases("2d")
+    shape = (cfg["nz"], cfg["ny"], cfg["nx"])
+    fine = gpu_run(lbm, cfg, u0, prec)
+    coarse = gpu_run(lbm, ccfg, np.zeros((2, 1, ccfg["ny"], ccfg["nx"])), "fp64")
+    probe = gpu_run(lbm, ccfg, np.zeros((2, 1, ccfg["ny"], ccfg["nx"])), prec, qois, dict(mode="off"))
+    o = oracle.Oracle(**cfg)
+    o.init(u0)
+    oc = oracle.Oracle(**ccfg)
+    cl = oracle.make_closure(qois)
+    qo = []
+    for n in range(4):
+        fine.step(m)
+        probe.project_qoi_from(fine, m, "bicubic")
+        o.step(m)
+        _, up = o.post_collision_velocity()
+        qo.append(oc.qoi(cl, oracle.project_bicubic(up, shape, m))[0])
+    probe.sync()
+    qg = probe.record_arrays()["q"]
+    eq = np.max(np.abs(qg - np.array(qo)) / np.abs(np.array(qo)))
+    coarse.project_state_from(fine, m, "bicubic")
+    want = oracle.project_bicubic(o.get_fp(), shape, m)
+    got = match_populations(lbm, 0, coarse.get_populations())
+    ef = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    _say(f"  bicubic {prec}: QoIs {eq:.2e}, populations {ef:.2e}")
+    if prec == "fp64":
+        assert eq <= 1e-11 and ef <= 1e-13
+    else:
+        assert eq <= 1e-4 and ef <= 1e-6
+
+
+def test_bicubic_projection_needs_a_periodic_2d_grid():
+    lbm = need_gpu()
+    cfg, u0, ccfg, qois, bands, m, _ = _cases("3d")
+    fine = gpu_run(lbm, cfg, u0, "fp32")
+    coarse = gpu_run(lbm, ccfg, np.zeros((3, ccfg["nz"], ccfg["ny"], ccfg["nx"])), "fp32")
+    with pytest.raises(lbm.LbmError):
+        coarse.project_state_from(fine, m, "bicubic")
