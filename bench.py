@@ -503,6 +503,47 @@ def form_hf_lf(lbm, hf_steps, m=5):
     return out
 
 
+def form_hf_lf_kolmogorov(lbm, hf_steps, m=5):
+    """The HF -> LF pipeline of the periodic Kolmogorov case (Sec. 3, 6):
+    plain BGK on a 1280^2 HF grid and, after every m = 5 HF steps, the
+    {E_B, Z_B} QoIs of the bicubic projection onto the 256^2 LF grid
+    (lbm_project_qoi_kind, LBM_PROJ_BICUBIC).  Reports the HF throughput and
+    the added cost per reference evaluation."""
+    import numpy as np
+    import synth
+    n = 1280
+    cfg, _ = synth.kolmogorov_workload(n, tau=0.55, amp=2e-5, seed=14)
+    N = n * n
+    hf = lbm.Run(lbm.make_config(precision="fp32", **cfg))
+    hf.init_velocity(synth.turbulent_velocity_2d(n, 0.02, seed=14))
+    lcfg, _ = synth.kolmogorov_workload(n // m, tau=0.5 + 0.05 / m, amp=2e-5 * m, seed=14)
+    hf.step(10)
+    hf.sync()
+    t = time.perf_counter()
+    hf.step(hf_steps)
+    hf.sync()
+    t_plain = time.perf_counter() - t
+    probe = lbm.Run(lbm.make_config(precision="fp32", **lcfg), lbm.ClosureSpec(synth.QOIS_2D, mode="off"))
+    probe.init_velocity(np.zeros((2, probe.N)))
+    probe.project_qoi_from(hf, m, "bicubic")
+    hf.sync()
+    t = time.perf_counter()
+    for _ in range(hf_steps // m):
+        hf.step(m)
+        probe.project_qoi_from(hf, m, "bicubic")
+    hf.sync()
+    t_ref = time.perf_counter() - t
+    q = probe.record_arrays()["q"]
+    out = {"hf_grid": [n, n], "lf_grid": [n // m, n // m], "hf_steps": hf_steps,
+           "hf_mlups": round(N * hf_steps / t_plain / 1e6, 1),
+           "reference_ms_per_lf_step": round((t_ref - t_plain) / (hf_steps // m) * 1e3, 3),
+           "reference_overhead_frac": round((t_ref - t_plain) / t_plain, 4),
+           "qoi_records": int(q.shape[0]), "qoi_finite": bool(np.all(np.isfinite(q)))}
+    probe.close()
+    hf.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -628,6 +669,8 @@ def main():
         print(f"[bench] fine grid: {forms['fine_grid_plain']}", file=sys.stderr, flush=True)
         forms["hf_to_lf"] = form_hf_lf(lbm, 200)
         print(f"[bench] HF to LF: {forms['hf_to_lf']}", file=sys.stderr, flush=True)
+        forms["hf_to_lf_kolmogorov"] = form_hf_lf_kolmogorov(lbm, 500)
+        print(f"[bench] HF to LF (Kolmogorov, bicubic): {forms['hf_to_lf_kolmogorov']}", file=sys.stderr, flush=True)
         out["system_forms"] = forms
 
     if not args.no_cpu_baseline:

@@ -362,6 +362,8 @@ struct lbm_ctx {
     double* qref_dev = nullptr;
     size_t qref_cap = 0;
     double* chist_dev = nullptr;   // history rows of the LRS matrix
+    double* proj_tmp = nullptr;    // scratch of the separable bicubic projection (probe contexts)
+    size_t proj_tmp_bytes = 0;
     size_t chist_cap = 0;
     std::vector<int2> klev;        // kernel filters: (first job, job count) per launch level
     FourierProg fprog{};           // Fourier band QoIs (plans made at set_closure)
@@ -962,6 +964,7 @@ void lbm_destroy(lbm_ctx* c)
     drop_graphs(c);
     if (c->qref_dev) hipFree(c->qref_dev);
     if (c->chist_dev) hipFree(c->chist_dev);
+    if (c->proj_tmp) hipFree(c->proj_tmp);
     drop_fourier(c);
     if (c->own_stream) hipStreamDestroy(c->stream);
     delete c;
@@ -1175,8 +1178,20 @@ int lbm_project_qoi_kind(lbm_ctx* f, lbm_ctx* p, int m, int kind)
     if (!p->has_to || p->cur.nq == 0 || p->hp.mode != LBM_CLOSURE_OFF)
         return fail(LBM_EINVAL, "project_qoi: the probe needs a closure in mode OFF");
     if (f->stream != p->stream) return fail(LBM_EINVAL, "project_qoi: fine run and probe must share one stream");
+    if (kind == LBM_PROJ_BICUBIC) {   // the probe's scratch for the separable passes, made on first use
+        const size_t need = sizeof(double) * 2 * (size_t)f->cfg.ny * p->cfg.nx;
+        if (p->proj_tmp_bytes < need) {
+            HIPCHK(hipStreamSynchronize(p->stream));
+            if (p->proj_tmp) HIPCHK(hipFree(p->proj_tmp));
+            p->proj_tmp = nullptr;
+            p->proj_tmp_bytes = 0;
+            HIPCHK(hipMalloc(&p->proj_tmp, need));
+            p->proj_tmp_bytes = need;
+        }
+    }
     launch_project(f->cfg.lattice, f->cfg.precision, f->dm, f->phase, m, p->cfg.nx, p->cfg.ny, p->cfg.nz, nullptr,
-                   p->arena + p->plan.vs, p->cfg.precision == LBM_FP64, kind, p->stream);
+                   p->arena + p->plan.vs, p->cfg.precision == LBM_FP64, kind, p->stream,
+                   kind == LBM_PROJ_BICUBIC ? p->proj_tmp : nullptr);
     LaunchGroup g = ctx_group(p);
     g.probe = 1;
     launch_step(g, p->stream, p->phase);

@@ -1964,11 +1964,96 @@ __global__ __launch_bounds__(kBlock) void k_project(const DevMember* __restrict_
     }
 }
 
+// The bicubic velocity projection in two separable passes (the reference
+// QoIs of the Kolmogorov case): x, for every fine row yf and coarse column
+// i, the weighted sum over the fine columns of the fine-cell velocities
+// into tmp [2][fny][ncx]; then y, for every coarse cell, the weighted sum
+// of tmp over the fine rows.  Weights as in k_project.
+__device__ __forceinline__ double keys_w(int r, int m, double rS)
+{
+    const double x = fabs((double)r / m);
+    return (x <= 1.0 ? (1.5 * x - 2.5) * x * x + 1.0 : (x < 2.0 ? ((-0.5 * x + 2.5) * x - 4.0) * x + 2.0 : 0.0)) * rS;
+}
+
+template <typename T, int PREC>
+__global__ __launch_bounds__(kBlock) void k_proj_bx(const DevMember* __restrict__ fine, int flip, int m, int ncx,
+                                                    double rS, double* __restrict__ tmp)
+{
+    using L = Lat<LBM_D2Q9>;
+    KMember& F = *kc(fine);
+    const int n = F.ny * ncx;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    const int i = idx % ncx, yf = idx / ncx;
+    const int o = (m - 1) / 2, R = 2 * m - 1;
+    const size_t NF = (size_t)F.N;
+    const T* g = (const T*)F.g[F.parity ^ flip];
+    double ux = 0, uy = 0;
+    for (int rx = -R; rx <= R; ++rx) {
+        const size_t fc = (size_t)yf * F.nx + (size_t)modi(m * i + o + rx, F.nx);
+        double drho = 0, jx = 0, jy = 0;
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) {
+            const double gq = (double)g[(size_t)q * NF + fc];
+            drho += gq;
+            jx += L::cx[q] * gq;
+            jy += L::cy[q] * gq;
+        }
+        const double rho = PREC == LBM_FP32_PLAIN ? drho : 1.0 + drho;
+        const double w = keys_w(rx, m, rS);
+        ux += w * (jx / rho);
+        uy += w * (jy / rho);
+    }
+    tmp[idx] = ux;
+    tmp[(size_t)n + idx] = uy;
+}
+
+__global__ __launch_bounds__(kBlock) void k_proj_by(int m, int ncx, int ncy, int fny, double rS,
+                                                    const double* __restrict__ tmp, void* __restrict__ vout,
+                                                    int vout_fp64)
+{
+    const int Nc = ncx * ncy;
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= Nc) return;
+    const int i = cell % ncx, j = cell / ncx;
+    const int o = (m - 1) / 2, R = 2 * m - 1;
+    const size_t n = (size_t)fny * ncx;
+    double v[2] = {0, 0};
+    for (int ry = -R; ry <= R; ++ry) {
+        const size_t t = (size_t)modi(m * j + o + ry, fny) * ncx + i;
+        const double w = keys_w(ry, m, rS);
+        v[0] += w * tmp[t];
+        v[1] += w * tmp[n + t];
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        if (vout_fp64) ((double*)vout)[(size_t)a * Nc + cell] = v[a];
+        else ((float*)vout)[(size_t)a * Nc + cell] = (float)v[a];
+    }
+}
+
 void launch_project(int lattice, int precision, const DevMember* fine, int flip, int m, int ncx, int ncy, int ncz,
-                    double* fpop, void* vout, int vout_fp64, int kind, hipStream_t st)
+                    double* fpop, void* vout, int vout_fp64, int kind, hipStream_t st, double* tmp)
 {
     const int Nc = ncx * ncy * ncz;
     const dim3 blk(kBlock), grd((Nc + kBlock - 1) / kBlock);
+    if (kind == LBM_PROJ_BICUBIC && !fpop && tmp && lattice == LBM_D2Q9) {
+        double S = 0;   // the sum of the window's kernel values (host copy of k_project's)
+        for (int r = -(2 * m - 1); r <= 2 * m - 1; ++r) {
+            const double x = std::fabs((double)r / m);
+            S += x <= 1.0 ? (1.5 * x - 2.5) * x * x + 1.0 : (x < 2.0 ? ((-0.5 * x + 2.5) * x - 4.0) * x + 2.0 : 0.0);
+        }
+        const int fny = ncy * m, nx1 = fny * ncx;
+        const dim3 g1((nx1 + kBlock - 1) / kBlock);
+        if (precision == LBM_FP64)
+            hipLaunchKernelGGL((k_proj_bx<double, LBM_FP64>), g1, blk, 0, st, fine, flip, m, ncx, 1.0 / S, tmp);
+        else if (precision == LBM_FP32_PLAIN)
+            hipLaunchKernelGGL((k_proj_bx<float, LBM_FP32_PLAIN>), g1, blk, 0, st, fine, flip, m, ncx, 1.0 / S, tmp);
+        else
+            hipLaunchKernelGGL((k_proj_bx<float, LBM_FP32_SHIFTED>), g1, blk, 0, st, fine, flip, m, ncx, 1.0 / S, tmp);
+        hipLaunchKernelGGL(k_proj_by, grd, blk, 0, st, m, ncx, ncy, fny, 1.0 / S, (const double*)tmp, vout, vout_fp64);
+        return;
+    }
 #define LBM_PROJ(LAT, T, PREC)                                                                                    \
     hipLaunchKernelGGL((k_project<LAT, T, PREC>), grd, blk, 0, st, fine, flip, m, ncx, ncy, ncz, fpop, vout, vout_fp64, \
                        kind)

@@ -89,8 +89,10 @@ int lattice_table(int lattice, int* c, double* w);
 // LBM_PROJ_STRIDE: the wall-anchored stride-m subsampling; LBM_PROJ_BICUBIC:
 // the bicubic mean of a doubly periodic 2-D grid): full populations into
 // fpop [Q][Nc] (nullable) and the post-collision velocity into vout [D][Nc]
-// (nullable; double if vout_fp64).
+// (nullable; double if vout_fp64).  tmp (nullable): device scratch of
+// 2 * (ncy m) * ncx doubles, with which the bicubic velocity projection runs
+// as two separable passes.
 void launch_project(int lattice, int precision, const DevMember* fine, int flip, int m, int ncx, int ncy, int ncz,
-                    double* fpop, void* vout, int vout_fp64, int kind, hipStream_t st);
+                    double* fpop, void* vout, int vout_fp64, int kind, hipStream_t st, double* tmp = nullptr);
 
 }  // namespace lbm
