@@ -280,6 +280,33 @@ def form_fourier(lbm, steps):
     return out
 
 
+def form_wale(lbm, steps):
+    """The headline channel TO-LES (96 x 48 x 48, FP32, 12 QoIs, LRS) on the
+    WALE substrate at C_w = 2.20, the paper's stable WALE setting (Sec. 7),
+    next to the Smagorinsky headline."""
+    import synth
+    w = workload("channel")
+    cfg = dict(w["cfg"], substrate=2, cmodel=2.2)
+    N = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    spec = lbm.ClosureSpec(w["qois"], **dict(w["cargs"], spinup=steps // 4))
+    r = lbm.Run(lbm.make_config(precision=w["precision"], **cfg), spec)
+    r.init_velocity(w["u0"])
+    r.step(20)
+    r.sync()
+    t = time.perf_counter()
+    r.step(steps)
+    status = 0
+    try:
+        r.sync()
+    except lbm.LbmError as e:
+        status = e.code
+    dt = time.perf_counter() - t
+    out = {"grid": [cfg["nx"], cfg["ny"], cfg["nz"]], "c_w": 2.2, "steps": steps, "status": status,
+           "mlups": round(N * steps / dt / 1e6, 1)}
+    r.close()
+    return out
+
+
 def form_paper_table(lbm, steps):
     """The rows of the paper's 3-D timing table (tab:timing-3d, H100, FP32)
     that run on the LF channel grid, here on 295 x 47 x 98 fluid rows (the
@@ -665,6 +692,8 @@ def main():
         # the same trace under a 2 GB HBM budget: admission queues requests
         forms["served_2gb"] = form_served(lbm, args.serve_requests, 20.0, 2000, budget=2 << 30)
         print(f"[bench] served (2 GB budget): {forms['served_2gb']}", file=sys.stderr, flush=True)
+        forms["wale_to_les"] = form_wale(lbm, 2000)
+        print(f"[bench] WALE TO-LES: {forms['wale_to_les']}", file=sys.stderr, flush=True)
         forms["fine_grid_plain"] = form_fine(lbm, 200)
         print(f"[bench] fine grid: {forms['fine_grid_plain']}", file=sys.stderr, flush=True)
         forms["hf_to_lf"] = form_hf_lf(lbm, 200)
