@@ -1,0 +1,51 @@
+"""Parity at the largest sizes the benchmark runs, in its launch
+configurations, against the FP64 oracle: the 384 x 192 x 192 channel TO-LES
+(FP32, 12 QoIs, the LRS correction active from the first step) and the
+480 x 240 x 240 plain BGK channel (FP32).  The oracle steps these grids in
+tens of seconds, so a few steps are compared over every cell."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import gpu_run, need_gpu, oracle_run, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def test_channel_384x192x192_to_les_first_step():
+    lbm = need_gpu()
+    cfg, u0 = synth.channel_workload(384, 192, 192, substrate=1, cmodel=0.1, seed=6)
+    nb, dmin, dmax = synth.channel_bands(192)
+    C, mu, S = synth.lrs_model_channel(12, 7, 9)
+    cargs = dict(mode="lrs", spinup=0, C=C, mu=mu, Sigma=S, seed=8, nbands=nb, dmin=dmin, dmax=dmax)
+    _say("384x192x192 channel TO-LES, FP32, 1 step")
+    run = gpu_run(lbm, cfg, u0, "fp32", synth.QOIS_3D, cargs)
+    run.step(1)
+    assert run.sync() == 0
+    o = oracle_run(cfg, u0, synth.QOIS_3D, cargs)
+    o.step(1)
+    rg, ro = run.record_arrays(), o.record_arrays()
+    ev = rel_err(run.fields()[1], o.velocity()[1])
+    eq = np.max(np.abs(rg["q"] - ro["q"]) / np.abs(ro["q"]))
+    edq = np.max(np.abs(rg["dq"] - ro["dq"]) / np.abs(ro["dq"]))
+    _say(f"  velocity {ev:.2e}  q {eq:.2e}  dq {edq:.2e}")
+    assert np.array_equal(rg["flags"], ro["flags"]) and np.all(ro["dq"] != 0)
+    assert ev <= 3e-5 and eq <= 1e-4 and edq <= 1e-2
+
+
+def test_fine_grid_480x240x240_plain():
+    lbm = need_gpu()
+    cfg, u0 = synth.channel_workload(480, 240, 240, substrate=0, cmodel=0.0, seed=13)
+    _say("480x240x240 plain BGK, FP32, 3 steps")
+    run = gpu_run(lbm, cfg, u0, "fp32")
+    run.step(3)
+    assert run.sync() == 0
+    o = oracle_run(cfg, u0)
+    o.step(3)
+    ev = rel_err(run.fields()[1], o.velocity()[1])
+    _say(f"  velocity {ev:.2e}")
+    assert ev <= 1e-5
