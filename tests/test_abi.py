@@ -165,3 +165,21 @@ def test_autotune_key_bytes_and_cache_hit(lbm, tmp_path):
     t = lbm.autotune(cfg, spec, cache=str(path))
     assert t["from_cache"] == 1 and t["candidates"] == 0
     assert (t["tune_zc"], t["tune_cpt"], t["tune_btx"], t["us_per_step"]) == (1, 4, 64, 80.25)
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/lbm.h compiles as strict C99 (no C++ or torch types cross the
+    boundary)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = tmp_path / "abi.c"
+    src.write_text('#include "lbm.h"\nint main(void) { lbm_config c; lbm_closure k; lbm_tuning t; lbm_qoi_rec r;\n'
+                   '(void)c; (void)k; (void)t; (void)r; return LBM_OK; }\n')
+    out = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I",
+                          os.path.join(root, "include"), "-c", str(src), "-o", str(tmp_path / "abi.o")],
+                         capture_output=True, text=True)
+    assert out.returncode == 0, out.stderr
