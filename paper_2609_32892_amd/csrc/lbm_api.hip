@@ -168,7 +168,7 @@ int check_config(const lbm_config* c)
 
 struct Plan {
     size_t member, param, ctl, recs, g0, g1, fprof, vn, part_stats, part_diag, work1, workm;
-    size_t rho, vs, P, W, Cf, part_to, bandw, cmp, workr, workb, sums, works, hpart, kV, kT, ktaps, kjobs;
+    size_t rho, vs, P, W, Cf, rec, part_to, bandw, cmp, workr, workb, sums, works, hpart, kV, kT, ktaps, kjobs;
     size_t fspec_v, fspec_w, fband_e, fband_z;
     size_t total;
     int N, D, NC, Q, esz, nb1, nbx2, cpt2, nbr, nbb, nbs, zc, btx, rec_cap;
@@ -216,7 +216,9 @@ void make_plan(const lbm_config* c, const ClosureShape& cs, Plan* p)
     P.g1 = take(e * P.Q * N);
     P.fprof = take(sizeof(double) * c->ny);
     P.vn = take(e * P.D * N);
-    P.part_stats = take(sizeof(double) * 4 * P.nb1);
+    // statistics partials: one per stream-collide workgroup (1-D blocks, or
+    // the binomial tiles when the SGS change is deferred)
+    P.part_stats = take(sizeof(double) * 4 * std::max(P.nb1, P.nbb));
     P.part_diag = take(sizeof(double) * 2 * P.nb1);
     P.work1 = take(sizeof(int2) * P.nb1);
     P.workm = take(sizeof(int));
@@ -226,6 +228,7 @@ void make_plan(const lbm_config* c, const ClosureShape& cs, Plan* p)
         P.P = take(e * (size_t)std::max(cs.jv, 1) * P.D * N);
         P.W = take(cs.has_z ? e * (size_t)(cs.jw + 1) * P.NC * N : kAlign);
         P.Cf = take(cs.has_z ? e * (size_t)(cs.jw + 1) * P.D * N : kAlign);
+        P.rec = take(e * 2 * P.D * N);
         P.part_to = take(sizeof(double) * (size_t)std::max(cs.npart(), 1) * P.nbr);
         P.bandw = take(sizeof(double) * (size_t)std::max(cs.nbands, 1) * c->ny);
         P.cmp = take(sizeof(double) * c->ny);
@@ -359,6 +362,7 @@ struct lbm_ctx {
     int phase = 0;        // state is in g[parity ^ phase]
     long host_step = 0;
     long version = 0;     // bumps whenever launch parameters change
+    bool pending = false; // steps with a deferred SGS change were enqueued since the last flush
     double* qref_dev = nullptr;
     size_t qref_cap = 0;
     double* chist_dev = nullptr;   // history rows of the LRS matrix
@@ -371,6 +375,9 @@ struct lbm_ctx {
     long gver[2] = {-1, -1};
     int gchunk = 32;
     int mode() const { return cur.nq > 0 ? 2 : (cfg.diag ? 1 : 0); }
+    // TO steps record the SGS change for the next step's pull (all
+    // substrates but WALE, whose gradients read the complete state)
+    bool defers() const { return mode() == 2 && cfg.substrate != LBM_WALE; }
 };
 
 struct lbm_batch {
@@ -391,13 +398,27 @@ struct lbm_batch {
 namespace {
 
 // Union of the chains each binomial pass advances for member c: pass j
-// computes B^j v (j <= jv) and curl^T B^(j-1) w with B^j w (j - 1 <= jw).
+// computes B^j v (j <= jv) and B^j w with curl^T B^(j-1) w (j <= jw); pass 1
+// also forms w = curl v*, and the readers form the top curl^T B^jw w.
 void add_pass_masks(const lbm_ctx* c, LaunchGroup& g)
 {
     for (int j = 1; j <= 8; ++j) {
         if (j <= c->cur.jv) g.bmask[j - 1] |= 1;
-        if (c->cur.has_z && j - 1 <= c->cur.jw) g.bmask[j - 1] |= 2;
+        if (c->cur.has_z && j <= c->cur.jw) g.bmask[j - 1] |= 2;
     }
+}
+
+// Binomial passes per step of a closure shape.
+int binom_passes(const ClosureShape& cs)
+{
+    return cs.kf ? 0 : std::max(cs.jv, cs.has_z ? std::max(cs.jw, 1) : 0);
+}
+
+// The member record's fields that follow the closure mode.
+void refresh_member(lbm_ctx* c)
+{
+    c->hm.defer = c->defers() ? 1 : 0;
+    c->hm.nst = c->defers() ? c->plan.nbb : c->plan.nb1;
 }
 
 LaunchGroup ctx_group(const lbm_ctx* c)
@@ -410,9 +431,10 @@ LaunchGroup ctx_group(const lbm_ctx* c)
     g.any_z = c->cur.has_z;
     g.maxpow = std::max(c->cur.jv, c->cur.jw);
     g.maxsa = c->cur.nsa;
-    g.npass = c->cur.kf ? 0 : std::max(c->cur.jv, c->cur.has_z ? c->cur.jw + 1 : 0);
+    g.npass = binom_passes(c->cur);
     g.btx = c->plan.btx;
     g.wt = write_through((double)c->plan.N * c->plan.Q * c->plan.esz);
+    g.defer = c->defers();
     add_pass_masks(c, g);
     g.kf = c->cur.kf;
     g.kjobs = (const KJob*)(c->arena + c->plan.kjobs);
@@ -623,10 +645,35 @@ int build_kjobs(lbm_ctx* c, const lbm_closure* cl)
 }
 
 // Build DevParam from a closure (host side) and upload it.
+// The SGS change of the last enqueued step, which the next stream-collide
+// would apply during its pull, added to the current populations (the
+// records then read zero): before the state is read, replaced or streamed
+// otherwise, or the closure changes.
+int flush(lbm_ctx* c)
+{
+    if (!c->pending) return LBM_OK;
+    launch_flush(c->cfg.lattice, c->cfg.precision, c->dm, (const int2*)(c->arena + c->plan.work1), c->plan.nb1,
+                 c->phase, c->stream);
+    c->pending = false;
+    HIPCHK(hipGetLastError());
+    return LBM_OK;
+}
+
+// Nothing pending: the records cleared (a state set from elsewhere).
+int clear_records(lbm_ctx* c)
+{
+    c->pending = false;
+    if (!c->has_to) return LBM_OK;
+    HIPCHK(hipMemsetAsync(c->arena + c->plan.rec, 0, (size_t)c->plan.esz * 2 * c->plan.D * c->plan.N, c->stream));
+    return LBM_OK;
+}
+
 int apply_closure(lbm_ctx* c, const lbm_closure* cl)
 {
     ClosureShape cs;
     int rc = closure_shape(&c->cfg, cl, &cs);
+    if (rc) return rc;
+    rc = flush(c);
     if (rc) return rc;
     if (cl) {
         const ClosureShape& cap = c->plan.cap;
@@ -753,6 +800,7 @@ int apply_closure(lbm_ctx* c, const lbm_closure* cl)
     c->hp = p;
     c->cur = cl ? cs : ClosureShape{};
     c->hm.npart = c->cur.npart();
+    refresh_member(c);
     rc = upload(c, c->dm, &c->hm, sizeof c->hm);
     if (rc) return rc;
     c->version++;
@@ -783,6 +831,7 @@ int fft_status(lbm_ctx* c)
 int enqueue_steps(lbm_ctx* c, long n)
 {
     const LaunchGroup g = ctx_group(c);
+    if (n > 0 && c->defers()) c->pending = true;
     for (long k = 0; k < n; ++k) {
         launch_step(g, c->stream, c->phase);
         c->phase ^= 1;
@@ -890,7 +939,9 @@ int lbm_create(const lbm_config* cfg, const lbm_closure* closure, void* dev_aren
         m.sums = (double*)(A + plan.sums);
         m.hpart = (double*)(A + plan.hpart);
         if (plan.cap.kf) m.kV = A + plan.kV;
+        m.rec = A + plan.rec;
     }
+    m.nst = plan.nb1;
     c->dm = (DevMember*)(A + plan.member);
     // host tables
     std::vector<double> fp(cfg->ny, 0.0);
@@ -926,6 +977,7 @@ int lbm_create(const lbm_config* cfg, const lbm_closure* closure, void* dev_aren
     }
     if (!rc) rc = upload(c, c->dm, &m, sizeof m);
     if (!rc) rc = reset_ctl(c);
+    if (!rc) rc = clear_records(c);
     if (!rc) {
         DevParam p{};
         rc = upload(c, A + plan.param, &p, sizeof p);
@@ -978,6 +1030,7 @@ int lbm_init_velocity(lbm_ctx* c, const double* rho, const double* u)
     HIPCHK(hipMalloc(&buf, sizeof(double) * (D + 1) * N));
     int rc = upload(c, buf, u, sizeof(double) * D * N);
     if (!rc && rho) rc = upload(c, buf + D * N, rho, sizeof(double) * N);
+    if (!rc) rc = clear_records(c);
     if (!rc) {
         c->phase = 0;
         launch_state(OP_INIT, c->cfg.lattice, c->cfg.precision, c->dm, (int)N, c->has_to, 0, c->stream,
@@ -1011,6 +1064,7 @@ int lbm_step(lbm_ctx* c, long n)
                 c->gver[ph] = c->version;
             }
             HIPCHK(hipGraphLaunch(c->gexec[ph], c->stream));
+            if (c->defers()) c->pending = true;
             n -= c->gchunk;
             c->host_step += c->gchunk;
             // gchunk is even: the phase is unchanged
@@ -1060,6 +1114,8 @@ int lbm_fields(lbm_ctx* c, double* rho, double* u)
 {
     if (!c || !u) return fail(LBM_EINVAL, "NULL argument");
     const size_t N = c->plan.N, D = c->plan.D;
+    int frc = flush(c);
+    if (frc) return frc;
     double* buf = nullptr;
     HIPCHK(hipMalloc(&buf, sizeof(double) * (D + 1) * N));
     launch_fields(c->cfg.lattice, c->cfg.precision, c->dm, (const int2*)(c->arena + c->plan.work1), c->plan.nb1,
@@ -1087,6 +1143,8 @@ int lbm_get_populations(lbm_ctx* c, double* f)
 {
     if (!c || !f) return fail(LBM_EINVAL, "NULL argument");
     const size_t n = (size_t)c->plan.Q * c->plan.N;
+    int frc = flush(c);
+    if (frc) return frc;
     double* buf = nullptr;
     HIPCHK(hipMalloc(&buf, sizeof(double) * n));
     launch_state(OP_GET_POP, c->cfg.lattice, c->cfg.precision, c->dm, c->plan.N, c->has_to, c->phase, c->stream,
@@ -1105,6 +1163,7 @@ int lbm_set_populations(lbm_ctx* c, const double* f)
     double* buf = nullptr;
     HIPCHK(hipMalloc(&buf, sizeof(double) * n));
     int rc = upload(c, buf, f, sizeof(double) * n);
+    if (!rc) rc = clear_records(c);
     if (!rc) {
         launch_state(OP_SET_POP, c->cfg.lattice, c->cfg.precision, c->dm, c->plan.N, c->has_to, c->phase, c->stream,
                      buf, nullptr);
@@ -1118,6 +1177,8 @@ int lbm_set_populations(lbm_ctx* c, const double* f)
 int lbm_stream_only(lbm_ctx* c)
 {
     if (!c) return fail(LBM_EINVAL, "NULL context");
+    int frc = flush(c);
+    if (frc) return frc;
     launch_state(OP_STREAM, c->cfg.lattice, c->cfg.precision, c->dm, c->plan.N, false, c->phase, c->stream,
                  nullptr, nullptr);
     c->phase ^= 1;
@@ -1153,12 +1214,15 @@ int lbm_project_state_kind(lbm_ctx* f, lbm_ctx* c, int m, int kind)
     int rc = check_projection(f, c, m, kind);
     if (rc) return rc;
     const size_t Nc = c->plan.N, Q = c->plan.Q;
+    rc = flush(f);
+    if (rc) return rc;
     HIPCHK(hipStreamSynchronize(f->stream));   // the fine run's pending steps
     double* buf = nullptr;
     HIPCHK(hipMalloc(&buf, sizeof(double) * Q * Nc));
     launch_project(f->cfg.lattice, f->cfg.precision, f->dm, f->phase, m, c->cfg.nx, c->cfg.ny, c->cfg.nz, buf,
                    nullptr, 0, kind, f->stream);
     if (hipStreamSynchronize(f->stream) != hipSuccess) rc = fail(LBM_EDEVICE, "projection kernel failed");
+    if (!rc) rc = clear_records(c);
     if (!rc) {
         c->phase = 0;
         launch_state(OP_SET_POP, c->cfg.lattice, c->cfg.precision, c->dm, c->plan.N, c->has_to, 0, c->stream, buf,
@@ -1178,6 +1242,8 @@ int lbm_project_qoi_kind(lbm_ctx* f, lbm_ctx* p, int m, int kind)
     if (!p->has_to || p->cur.nq == 0 || p->hp.mode != LBM_CLOSURE_OFF)
         return fail(LBM_EINVAL, "project_qoi: the probe needs a closure in mode OFF");
     if (f->stream != p->stream) return fail(LBM_EINVAL, "project_qoi: fine run and probe must share one stream");
+    rc = flush(f);
+    if (rc) return rc;
     if (kind == LBM_PROJ_BICUBIC) {   // the probe's scratch for the separable passes, made on first use
         const size_t need = sizeof(double) * 2 * (size_t)f->cfg.ny * p->cfg.nx;
         if (p->proj_tmp_bytes < need) {
@@ -1220,6 +1286,8 @@ int lbm_get_state(lbm_ctx* c, void* host, size_t bytes)
 {
     if (!c || !host) return fail(LBM_EINVAL, "NULL argument");
     if (bytes < lbm_state_bytes(c)) return fail(LBM_EINVAL, "buffer too small");
+    int frc = flush(c);
+    if (frc) return frc;
     HIPCHK(hipStreamSynchronize(c->stream));
     const Plan& p = c->plan;
     char* o = (char*)host;
@@ -1246,6 +1314,8 @@ int lbm_set_state(lbm_ctx* c, const void* host, size_t bytes)
     if (h.magic != 0x4C424D53544154ULL || h.Q != p.Q || h.N != p.N || h.esz != p.esz || h.has_to != (int)c->has_to)
         return fail(LBM_EINVAL, "state image does not match this context");
     o += sizeof h;
+    int crc = clear_records(c);
+    if (crc) return crc;
     HIPCHK(hipStreamSynchronize(c->stream));
     c->phase = 0;
     const size_t gb = (size_t)p.esz * p.Q * p.N;
@@ -1367,7 +1437,8 @@ static int batch_build(lbm_batch* b)
             g.any_z |= c->cur.has_z;
             g.maxpow = std::max(g.maxpow, std::max(c->cur.jv, c->cur.jw));
             g.maxsa = std::max(g.maxsa, c->cur.nsa);
-            g.npass = std::max(g.npass, std::max(c->cur.jv, c->cur.has_z ? c->cur.jw + 1 : 0));
+            g.npass = std::max(g.npass, binom_passes(c->cur));
+            g.defer = c->defers();   // (members of a group share mode and substrate)
             add_pass_masks(c, g);
             if (keys[gi].kfm >= 0) {
                 g.kf = 1;
@@ -1425,31 +1496,36 @@ int lbm_batch_step(lbm_batch* b, long n)
     }
     bool fft = false;   // hipFFT runs outside graphs
     for (const LaunchGroup& g : b->groups) fft = fft || g.fprog;
-    long left = n;
-    while (left > 0) {
-        if (left >= b->gchunk && !fft) {
+    // the members' step counts and phases follow the steps actually
+    // enqueued, also when a launch or a capture fails part way
+    long done = 0;
+    int rc = LBM_OK;
+    while (done < n && !rc) {
+        if (n - done >= b->gchunk && !fft) {
             const int ph = b->phase;
             if (!b->graph_ok[ph]) {
-                int rc = capture(b->stream, b->groups, b->gchunk, ph, &b->gexec[ph]);
-                if (rc) return rc;
+                rc = capture(b->stream, b->groups, b->gchunk, ph, &b->gexec[ph]);
+                if (rc) break;
                 b->graph_ok[ph] = true;
             }
-            HIPCHK(hipGraphLaunch(b->gexec[ph], b->stream));
-            left -= b->gchunk;
+            const hipError_t e = hipGraphLaunch(b->gexec[ph], b->stream);
+            if (e != hipSuccess) { rc = fail(LBM_EDEVICE, "graph launch failed: %s", hipGetErrorString(e)); break; }
+            done += b->gchunk;
         } else {
             for (const LaunchGroup& g : b->groups) launch_step(g, b->stream, b->phase);
             b->phase ^= 1;
-            left -= 1;
+            done += 1;
         }
     }
-    HIPCHK(hipGetLastError());
-    int fft_rc = LBM_OK;
-    for (lbm_ctx* c : b->mem) fft_rc = fft_rc ? fft_rc : fft_status(c);
+    const hipError_t le = hipGetLastError();
+    if (!rc && le != hipSuccess) rc = fail(LBM_EDEVICE, "launch failed: %s", hipGetErrorString(le));
+    for (lbm_ctx* c : b->mem) rc = rc ? rc : fft_status(c);
     for (lbm_ctx* c : b->mem) {
-        c->host_step += n;
-        c->phase ^= (int)(n & 1);
+        c->host_step += done;
+        c->phase ^= (int)(done & 1);
+        if (done > 0 && c->defers()) c->pending = true;
     }
-    return fft_rc;
+    return rc;
 }
 
 int lbm_batch_sync(lbm_batch* b)
@@ -1484,6 +1560,7 @@ int lbm_profile_phases(lbm_ctx* c, long nsteps, double* ms, int* launches)
     double acc[kNumPhases] = {0, 0, 0, 0, 0, 0};
     const LaunchGroup g = ctx_group(c);
     int rc = LBM_OK;
+    if (c->defers()) c->pending = true;
     for (long s = 0; s < nsteps && !rc; ++s) {
         launch_step(g, c->stream, c->phase, ev);
         c->phase ^= 1;
@@ -1500,7 +1577,7 @@ int lbm_profile_phases(lbm_ctx* c, long nsteps, double* ms, int* launches)
     if (launches) {
         const int m = g.mode;
         launches[0] = 1 + (g.substrate == LBM_WALE ? 1 : 0);
-        launches[1] = m == 2 && g.any_z ? 1 : 0;
+        launches[1] = m == 2 && g.kf && g.any_z ? 1 : 0;
         launches[2] = m == 2 ? (g.kf ? g.nklev : g.npass) : 0;
         launches[3] = m == 2 ? 1 : 0;
         launches[4] = m == 2 ? 2 : 0;   // cross-block sums, solve

@@ -77,7 +77,7 @@ struct DevMember {
     void* vn;                          // post-streaming velocity [D][N]    (diag, WALE)
     void* P;                           // B^j v*, j = 1..jv   [jv][D][N]
     void* W;                           // B^j curl v*, j=0..jw [jw+1][NC][N]
-    void* C;                           // curl^T B^j curl v*, j=0..jw [jw+1][D][N]
+    void* C;                           // curl^T B^j curl v*, j=0..jw-1 [jw+1][D][N] (C_jw: from W_jw)
     double* part_stats;                // [nb1][4]: sum(rho-1), sum(rho v)
     double* part_to;                   // [npart][ny * nbx2]
     double* part_diag;                 // [nb1][2]
@@ -92,6 +92,9 @@ struct DevMember {
     double* sums;                      // [4 + npart]: reduced statistics and TO partials
     double* hpart;                     // [nhc][kMaxQ]: LRS history product per k_sum workgroup
     void* kV;                          // kernel filters: V_s = R(R v*) or curl^T R(R w), [nsa][D][N]
+    void* rec;                         // pending SGS change of the last step: (rho dv, 2 v* + dv) [2D][N]
+    int nst;                           // stream-collide statistics partials (workgroups of the launch)
+    int defer;                         // TO steps defer the SGS change into the next pull (k_step_t)
 };
 
 #ifdef __HIP_DEVICE_COMPILE__

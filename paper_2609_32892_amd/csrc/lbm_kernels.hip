@@ -57,6 +57,7 @@ template <> struct Lat<LBM_D3Q19> {
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 
 __device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+__device__ __forceinline__ int modi(int a, int n) { int r = a % n; return r < 0 ? r + n : r; }
 
 // ---------------------------------------------------------------------------
 // Reductions over the 64-lane wavefront with DPP lane moves (no LDS
@@ -227,21 +228,76 @@ __device__ __forceinline__ T dfeq(T w, T rho, T cd, T cs, T dd)
 }
 
 // ---------------------------------------------------------------------------
-// SGS change of the post-collision populations of a cell (k_apply): with
-// a = rho dv, b = 2 v* + dv and e = rho dv.(2 v* + dv),
+// SGS change of the post-collision populations of a cell (eq. LES-2, the
+// second difference of the exact-difference form): with a = rho dv,
+// b = 2 v* + dv and e = a.b,
 //   delta f_i = feq_i(rho, v* + dv) - feq_i(rho, v*)
-//             = w_i [3 c_i.a + 9/2 (c_i.a)(c_i.b) - 3/2 e],
-// u = (a_x, a_y, a_z, e), v = (b_x, b_y, b_z, 0) (2-D: a_z = b_z = 0).
-template <typename T> struct alignas(4 * sizeof(T)) Vec4 { T x, y, z, w; };
-template <typename T> struct PendRec { Vec4<T> u, v; };
-
-template <int LAT, typename T>
-__device__ __forceinline__ T pend_df(const PendRec<T>& r, int i, T sg)
+//             = w_i [3 c_i.a + 9/2 (c_i.a)(c_i.b) - 3/2 e].
+// k_apply stores the record (a, b) of every cell; the next stream-collide
+// adds delta f of each source cell while it pulls (k_step_t), or k_flush adds
+// it in place before the state is read.  Both evaluate it with these
+// functions, without contraction and in a fixed order, so a flushed state
+// streams to bitwise the populations the deferred pull forms.
+// ---------------------------------------------------------------------------
+// c_i . a over the nonzero components of c_i (exact signs, no products with
+// the constants); A(k) returns component k.
+template <int LAT, typename T, typename Get>
+__device__ __forceinline__ T cdot(int i, Get A)
 {
     using L = Lat<LAT>;
-    const T ca = T(L::cx[i]) * r.u.x + T(L::cy[i]) * r.u.y + (L::D == 3 ? T(L::cz[i]) * r.u.z : T(0));
-    const T cb = T(L::cx[i]) * r.v.x + T(L::cy[i]) * r.v.y + (L::D == 3 ? T(L::cz[i]) * r.v.z : T(0));
-    return T(L::w[i]) * (T(3) * sg * ca + T(4.5) * ca * cb - T(1.5) * r.u.w);
+    const int c[3] = {L::cx[i], L::cy[i], L::D == 3 ? L::cz[i] : 0};
+    T s = T(0);
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < L::D; ++k) {
+        if (!c[k]) continue;
+        const T v = A(k);
+        if (!any) s = c[k] > 0 ? v : -v;
+        else s = c[k] > 0 ? s + v : s - v;
+        any = true;
+    }
+    return s;
+}
+
+// e = a.b in a fixed order.
+template <int D, typename T>
+__device__ __forceinline__ T rec_e(const T* a, const T* b)
+{
+#pragma clang fp contract(off)
+    T e = a[0] * b[0];
+#pragma unroll
+    for (int k = 1; k < D; ++k) e = e + a[k] * b[k];
+    return e;
+}
+
+// delta f_i from the record (a, b, e) of the cell, with ca = c_i.a and
+// cb = c_i.b; opp: delta f of the opposite direction instead, whose c.a and
+// c.b are exactly -ca and -cb (rounding is symmetric in sign), so only the
+// linear term changes sign.  g + delta f is then one rounded addition.
+template <int LAT, typename T>
+__device__ __forceinline__ T df_cc(int i, bool opp_dir, T ca, T cb, T e)
+{
+#pragma clang fp contract(off)
+    using L = Lat<LAT>;
+    const T lin = T(3) * ca;
+    const T s = ((opp_dir ? -lin : lin) + (T(4.5) * ca) * cb) - T(1.5) * e;
+    return T(L::w[i]) * s;
+}
+template <int LAT, typename T, typename GA, typename GB>
+__device__ __forceinline__ T df_of(int i, GA A, GB B, T e)
+{
+    return df_cc<LAT, T>(i, false, cdot<LAT, T>(i, A), cdot<LAT, T>(i, B), e);
+}
+template <typename T>
+__device__ __forceinline__ T add_rn(T g, T d)
+{
+#pragma clang fp contract(off)
+    return g + d;
+}
+template <int LAT, typename T, typename GA, typename GB>
+__device__ __forceinline__ T add_df(T g, int i, GA A, GB B, T e)
+{
+    return add_rn(g, df_of<LAT, T>(i, A, B, e));
 }
 
 // ---------------------------------------------------------------------------
@@ -304,12 +360,154 @@ __device__ __forceinline__ void moments(const T* f, T& drho, T* j)
 // MODE 0: plain; 1: plain with statistics and post-streaming velocity;
 // 2: TO predictor (statistics, rho, v*).
 // ---------------------------------------------------------------------------
+// Collision of one cell from its pulled populations f: moments, effective
+// relaxation time (Sec. 5), BGK relaxation with the exact-difference force
+// (eq. LES-1/LES-2); stores the predictor populations (and in TO mode rho - 1
+// and v*), adds the cell's mass and momentum to st and flags instability.
+template <int LAT, typename T, int PREC, int SUB, int MODE, bool WT>
+__device__ __forceinline__ void collide_cell(KMember& m, T* f, int x, int y, int z, int cell, T* __restrict__ gd,
+                                             double* st, int& bad)
+{
+    using L = Lat<LAT>;
+    constexpr int Q = L::Q, D = L::D;
+    const int N = m.N, nx = m.nx, ny = m.ny;
+    T drho, j[3] = {0, 0, 0};
+    moments<LAT, T, PREC>(f, drho, j);
+    const T rho = T(1) + drho;
+    const T ir = T(1) / rho;
+    T u[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) u[a] = j[a] * ir;
+    T uu = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) uu += u[a] * u[a];
+    if (!(uu <= T(0.25))) bad = 1;
+
+    // equilibrium deviations geq_i = feq_i - w_i (or feq_i for plain storage)
+    T geq[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        T cu = T(L::cx[i]) * u[0] + T(L::cy[i]) * u[1] + (D == 3 ? T(L::cz[i]) * u[2] : T(0));
+        T X = T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu;
+        if (PREC == LBM_FP32_PLAIN)
+            geq[i] = T(L::w[i]) * rho * (T(1) + X);
+        else
+            geq[i] = T(L::w[i]) * (drho + rho * X);
+    }
+
+    // effective relaxation time (Sec. 5)
+    T taue = T(m.tau);
+    if (SUB == LBM_SMAGORINSKY) {
+        T P[6] = {0, 0, 0, 0, 0, 0};  // xx yy zz xy xz yz
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            T fn = f[i] - geq[i];
+            const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i];
+            if (cx) P[0] += fn;
+            if (cy) P[1] += fn;
+            if (cz) P[2] += fn;
+            if (cx * cy) P[3] += T(cx * cy) * fn;
+            if (cx * cz) P[4] += T(cx * cz) * fn;
+            if (cy * cz) P[5] += T(cy * cz) * fn;
+        }
+        T PP = P[0] * P[0] + P[1] * P[1] + P[2] * P[2] + T(2) * (P[3] * P[3] + P[4] * P[4] + P[5] * P[5]);
+        T nP = sqrt(T(2) * PP);
+        T cm = T(m.cmodel);
+        taue = T(0.5) * (taue + sqrt(taue * taue + T(18) * cm * cm * nP * ir));
+    } else if (SUB == LBM_WALE) {
+        // velocity gradient g_ab = D_b v_a of the post-streaming field
+        const T* __restrict__ vn = (const T*)m.vn;
+        T g[3][3];
+        const int nz = m.nz;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            int xp = x, xm = x, yp = y, ym = y, zp = z, zm = z;
+            if (b == 0) { xp = wrapi(x + 1, nx); xm = wrapi(x - 1, nx); }
+            if (b == 1) { yp = y + 1; ym = y - 1; }
+            if (b == 2) { zp = wrapi(z + 1, nz); zm = wrapi(z - 1, nz); }
+            bool okp = true, okm = true;
+            if (b == 1) {
+                if (m.walls) { okp = yp < ny; okm = ym >= 0; }
+                else { yp = wrapi(yp, ny); ym = wrapi(ym, ny); }
+            }
+            const int cp = xp + nx * (yp + ny * zp), cm = xm + nx * (ym + ny * zm);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                T vp = okp ? vn[(size_t)a * N + cp] : T(0);
+                T vm = okm ? vn[(size_t)a * N + cm] : T(0);
+                g[a][b] = T(0.5) * (vp - vm);
+            }
+        }
+        T g2[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) g2[a][b] = g[a][0] * g[0][b] + g[a][1] * g[1][b] + g[a][2] * g[2][b];
+        const T tr = g2[0][0] + g2[1][1] + g2[2][2];
+        T SS = 0, SdSd = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                T S = T(0.5) * (g[a][b] + g[b][a]);
+                T Sd = T(0.5) * (g2[a][b] + g2[b][a]) - (a == b ? tr / T(3) : T(0));
+                SS += S * S;
+                SdSd += Sd * Sd;
+            }
+        T den = pow(SS, T(2.5)) + pow(SdSd, T(1.25));
+        T cm = T(m.cmodel);
+        T nut = den > T(0) ? cm * cm * pow(SdSd, T(1.5)) / den : T(0);
+        taue = taue + T(3) * nut;
+    }
+    const T om = T(1) / taue;
+
+    // body force, F/rho velocity increment, predictor velocity
+    T F[3] = {T(m.fprof[y]), 0, 0};
+    if (m.drag != 0.0) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) F[a] -= T(m.drag) * rho * u[a];
+    }
+    T du[3] = {0, 0, 0}, us[3] = {0, 0, 0};
+    T dd = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        du[a] = F[a] * ir;
+        us[a] = u[a] + du[a];
+        dd += du[a] * (us[a] + u[a]);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        T cd = T(L::cx[i]) * du[0] + T(L::cy[i]) * du[1] + (D == 3 ? T(L::cz[i]) * du[2] : T(0));
+        T cs = T(L::cx[i]) * (us[0] + u[0]) + T(L::cy[i]) * (us[1] + u[1]) +
+               (D == 3 ? T(L::cz[i]) * (us[2] + u[2]) : T(0));
+        T out = f[i] - om * (f[i] - geq[i]) + dfeq<T>(T(L::w[i]), rho, cd, cs, dd);
+        if (MODE == 2)
+            st_fld_at(gd + (size_t)i * N, (unsigned)cell, out, WT);
+        else
+            gd[(size_t)i * N + cell] = out;
+    }
+    if (MODE == 2) {
+        st_fld_at((T*)m.rho, (unsigned)cell, drho, WT);
+#pragma unroll
+        for (int a = 0; a < D; ++a) st_fld_at((T*)m.vs + (size_t)a * N, (unsigned)cell, us[a], WT);
+    }
+    if (MODE == 1 && SUB != LBM_WALE) {  // (with WALE, k_moments wrote v^n)
+#pragma unroll
+        for (int a = 0; a < D; ++a) ((T*)m.vn)[(size_t)a * N + cell] = u[a];
+    }
+    if (MODE >= 1) {
+        st[0] += (double)drho;
+#pragma unroll
+        for (int a = 0; a < D; ++a) st[1 + a] += (double)(rho * u[a]);
+    }
+}
+
 template <int LAT, typename T, int PREC, int SUB, int MODE, bool WT = false>
 __global__ __launch_bounds__(kBlock) void k_step(const DevMember* __restrict__ mems,
                                                  const int2* __restrict__ work, int flip)
 {
     using L = Lat<LAT>;
-    constexpr int Q = L::Q, D = L::D;
+    constexpr int Q = L::Q;
     __shared__ double lds[4 * (kBlock / 64)];
     const int2 wk = work[blockIdx.x];
     KMember& m = *kc(mems + wk.x);
@@ -324,135 +522,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const DevMember* __restrict__ m
         const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
         T f[Q];
         gather<LAT, T, MODE == 2>(m, gs, x, y, z, cell, f);
-        T drho, j[3] = {0, 0, 0};
-        moments<LAT, T, PREC>(f, drho, j);
-        const T rho = T(1) + drho;
-        const T ir = T(1) / rho;
-        T u[3] = {0, 0, 0};
-#pragma unroll
-        for (int a = 0; a < D; ++a) u[a] = j[a] * ir;
-        T uu = 0;
-#pragma unroll
-        for (int a = 0; a < D; ++a) uu += u[a] * u[a];
-        if (!(uu <= T(0.25))) bad = 1;
-
-        // equilibrium deviations geq_i = feq_i - w_i (or feq_i for plain storage)
-        T geq[Q];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            T cu = T(L::cx[i]) * u[0] + T(L::cy[i]) * u[1] + (D == 3 ? T(L::cz[i]) * u[2] : T(0));
-            T X = T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu;
-            if (PREC == LBM_FP32_PLAIN)
-                geq[i] = T(L::w[i]) * rho * (T(1) + X);
-            else
-                geq[i] = T(L::w[i]) * (drho + rho * X);
-        }
-
-        // effective relaxation time (Sec. 5)
-        T taue = T(m.tau);
-        if (SUB == LBM_SMAGORINSKY) {
-            T P[6] = {0, 0, 0, 0, 0, 0};  // xx yy zz xy xz yz
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                T fn = f[i] - geq[i];
-                const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i];
-                if (cx) P[0] += fn;
-                if (cy) P[1] += fn;
-                if (cz) P[2] += fn;
-                if (cx * cy) P[3] += T(cx * cy) * fn;
-                if (cx * cz) P[4] += T(cx * cz) * fn;
-                if (cy * cz) P[5] += T(cy * cz) * fn;
-            }
-            T PP = P[0] * P[0] + P[1] * P[1] + P[2] * P[2] + T(2) * (P[3] * P[3] + P[4] * P[4] + P[5] * P[5]);
-            T nP = sqrt(T(2) * PP);
-            T cm = T(m.cmodel);
-            taue = T(0.5) * (taue + sqrt(taue * taue + T(18) * cm * cm * nP * ir));
-        } else if (SUB == LBM_WALE) {
-            // velocity gradient g_ab = D_b v_a of the post-streaming field
-            const T* __restrict__ vn = (const T*)m.vn;
-            T g[3][3];
-            const int nz = m.nz;
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                int xp = x, xm = x, yp = y, ym = y, zp = z, zm = z;
-                if (b == 0) { xp = wrapi(x + 1, nx); xm = wrapi(x - 1, nx); }
-                if (b == 1) { yp = y + 1; ym = y - 1; }
-                if (b == 2) { zp = wrapi(z + 1, nz); zm = wrapi(z - 1, nz); }
-                bool okp = true, okm = true;
-                if (b == 1) {
-                    if (m.walls) { okp = yp < ny; okm = ym >= 0; }
-                    else { yp = wrapi(yp, ny); ym = wrapi(ym, ny); }
-                }
-                const int cp = xp + nx * (yp + ny * zp), cm = xm + nx * (ym + ny * zm);
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    T vp = okp ? vn[(size_t)a * N + cp] : T(0);
-                    T vm = okm ? vn[(size_t)a * N + cm] : T(0);
-                    g[a][b] = T(0.5) * (vp - vm);
-                }
-            }
-            T g2[3][3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) g2[a][b] = g[a][0] * g[0][b] + g[a][1] * g[1][b] + g[a][2] * g[2][b];
-            const T tr = g2[0][0] + g2[1][1] + g2[2][2];
-            T SS = 0, SdSd = 0;
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    T S = T(0.5) * (g[a][b] + g[b][a]);
-                    T Sd = T(0.5) * (g2[a][b] + g2[b][a]) - (a == b ? tr / T(3) : T(0));
-                    SS += S * S;
-                    SdSd += Sd * Sd;
-                }
-            T den = pow(SS, T(2.5)) + pow(SdSd, T(1.25));
-            T cm = T(m.cmodel);
-            T nut = den > T(0) ? cm * cm * pow(SdSd, T(1.5)) / den : T(0);
-            taue = taue + T(3) * nut;
-        }
-        const T om = T(1) / taue;
-
-        // body force, F/rho velocity increment, predictor velocity
-        T F[3] = {T(m.fprof[y]), 0, 0};
-        if (m.drag != 0.0) {
-#pragma unroll
-            for (int a = 0; a < D; ++a) F[a] -= T(m.drag) * rho * u[a];
-        }
-        T du[3] = {0, 0, 0}, us[3] = {0, 0, 0};
-        T dd = 0;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            du[a] = F[a] * ir;
-            us[a] = u[a] + du[a];
-            dd += du[a] * (us[a] + u[a]);
-        }
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            T cd = T(L::cx[i]) * du[0] + T(L::cy[i]) * du[1] + (D == 3 ? T(L::cz[i]) * du[2] : T(0));
-            T cs = T(L::cx[i]) * (us[0] + u[0]) + T(L::cy[i]) * (us[1] + u[1]) +
-                   (D == 3 ? T(L::cz[i]) * (us[2] + u[2]) : T(0));
-            T out = f[i] - om * (f[i] - geq[i]) + dfeq<T>(T(L::w[i]), rho, cd, cs, dd);
-            if (MODE == 2)
-                st_fld_at(gd + (size_t)i * N, (unsigned)cell, out, WT);
-            else
-                gd[(size_t)i * N + cell] = out;
-        }
-        if (MODE == 2) {
-            st_fld_at((T*)m.rho, (unsigned)cell, drho, WT);
-#pragma unroll
-            for (int a = 0; a < D; ++a) st_fld_at((T*)m.vs + (size_t)a * N, (unsigned)cell, us[a], WT);
-        }
-        if (MODE == 1 && SUB != LBM_WALE) {  // (with WALE, k_moments wrote v^n)
-#pragma unroll
-            for (int a = 0; a < D; ++a) ((T*)m.vn)[(size_t)a * N + cell] = u[a];
-        }
-        if (MODE >= 1) {
-            st[0] = (double)drho;
-#pragma unroll
-            for (int a = 0; a < D; ++a) st[1 + a] = (double)(rho * u[a]);
-        }
+        collide_cell<LAT, T, PREC, SUB, MODE, WT>(m, f, x, y, z, cell, gd, st, bad);
     }
     if (MODE >= 1) {
         block_sum<4>(st, lds);
@@ -460,6 +530,163 @@ __global__ __launch_bounds__(kBlock) void k_step(const DevMember* __restrict__ m
             double* p = m.part_stats + (size_t)wk.y * 4;
             p[0] = st[0]; p[1] = st[1]; p[2] = st[2]; p[3] = st[3];
         }
+    }
+    const unsigned long long anybad = __ballot(bad);
+    if (anybad && (threadIdx.x & 63) == 0) atomicOr(&m.ctl->flags, 1);
+}
+
+// K1t: the TO stream-collide with the previous step's SGS change deferred
+// into the pull.  A workgroup owns a TX x TY tile of the xy plane and a chunk
+// of zc planes (the binomial-filter tiling and work table).  For every plane
+// of the chunk and one halo plane on each side, the record (a, b) of the tile
+// and its one-cell xy halo is staged in LDS together with e = a.b; the pull
+// of population i at cell x then reads g*_i(x - c_i) from memory and the
+// record of x - c_i from LDS, or for a bounce-back g*_opp(x) and the record of
+// x itself.  The records of a step are zero after a flush (nothing pending).
+// Statistics are summed per workgroup over its cells in z order.
+// (At most 128 VGPRs in FP32: the LDS of a workgroup already limits the
+// kernel to four waves per SIMD, and left alone the compiler hoists every
+// pull and record read of a cell, 169 VGPRs, two waves.)
+#ifndef LBM_STEPT_WAVES
+#define LBM_STEPT_WAVES 4
+#endif
+template <int LAT, typename T, int PREC, int SUB, int TX, bool WT>
+__global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? LBM_STEPT_WAVES : 2) void k_step_t(const DevMember* __restrict__ mems,
+                                                   const int2* __restrict__ work, int flip)
+{
+    using L = Lat<LAT>;
+    constexpr int Q = L::Q, D = L::D;
+    constexpr int TY = kBlock / TX, HX = TX + 2, HY = TY + 2, HXY = HX * HY;
+    constexpr int NR = 2 * D;                     // a, b
+    constexpr int NSL = D == 3 ? 3 : 1;           // staged planes
+    constexpr int NE = (HXY + kBlock - 1) / kBlock;
+    __shared__ T rs[NSL][NR + 1][HXY];            // a, b, e of the staged cells
+    __shared__ double lds[4 * (kBlock / 64)];
+    const int2 wk = work[blockIdx.x];
+    KMember& m = *kc(mems + wk.x);
+    const int N = m.N, nx = m.nx, ny = m.ny, nz = m.nz;
+    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
+    const int zc = m.zc;
+    const int tx0 = (wk.y % ntx) * TX;
+    const int ty0 = ((wk.y / ntx) % nty) * TY;
+    const int tz0 = D == 3 ? (wk.y / (ntx * nty)) * zc : 0;
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int x = tx0 + lx, y = ty0 + ly;
+    const bool own = x < nx && y < ny;
+    const int cur = m.parity ^ flip;
+    const T* __restrict__ gs = (const T*)m.g[cur];
+    T* __restrict__ gd = (T*)m.g[cur ^ 1];
+    const T* __restrict__ rec = (const T*)m.rec;
+    const unsigned sN = (unsigned)N;
+    // halo elements staged by this thread, as offsets within a plane; an
+    // element beyond a wall loads cell 0 (a bounce-back never reads it)
+    int eoff[NE];
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+        const int e = threadIdx.x + k * kBlock;
+        const int hx = e % HX, hy = e / HX;
+        const int gx = modi(tx0 + hx - 1, nx);
+        int gy = ty0 + hy - 1;
+        bool ok = e < HXY;
+        if (m.walls) ok = ok && gy >= 0 && gy < ny;
+        else gy = modi(gy, ny);
+        eoff[k] = ok ? gx + nx * gy : 0;
+    }
+    const int plane = nx * ny;
+    auto fetch = [&](int pz, T (&buf)[NE][NR]) {
+        const unsigned zo = (unsigned)(plane * (D == 3 ? modi(pz, nz) : 0));
+#pragma unroll
+        for (int k = 0; k < NE; ++k)
+#pragma unroll
+            for (int c = 0; c < NR; ++c) buf[k][c] = ld_at(rec + c * sN, zo + (unsigned)eoff[k]);
+    };
+    auto stage = [&](int sl, const T (&buf)[NE][NR]) {
+#pragma unroll
+        for (int k = 0; k < NE; ++k) {
+            const int e = threadIdx.x + k * kBlock;
+            if (e < HXY) {
+#pragma unroll
+                for (int c = 0; c < NR; ++c) rs[sl][c][e] = buf[k][c];
+                rs[sl][NR][e] = rec_e<D, T>(&buf[k][0], &buf[k][D]);
+            }
+        }
+    };
+    double st[4] = {0, 0, 0, 0};
+    int bad = 0;
+    // the 19 pulls g*_pi(src) of the own cell of plane z (issued before the
+    // plane's records are staged, so their latency overlaps the staging)
+    auto pull = [&](int z, T (&f)[Q]) {
+        const int cell = x + nx * (y + ny * z);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            int sy = y - L::cy[i];
+            int src, pi;
+            if (m.walls && (sy < 0 || sy >= ny)) {
+                src = cell;
+                pi = opp(i);
+            } else {
+                const int sx = wrapi(x - L::cx[i], nx);
+                sy = wrapi(sy, ny);
+                const int sz = D == 3 ? wrapi(z - L::cz[i], nz) : 0;
+                src = sx + nx * (sy + ny * sz);
+                pi = i;
+            }
+            const int lo = i < opp(i) ? i : opp(i);
+            f[i] = ld_at(gs + (size_t)lo * N, (unsigned)((pi - lo) * N + src));
+        }
+    };
+    // add delta f of each pulled population from the staged records (a
+    // bounce-back pulls population opp(i) of the cell itself: its delta f
+    // from the own record with the sign of the linear term flipped, so every
+    // direction is evaluated with constant c_i) and collide; sl0, sl1, sl2:
+    // the staged planes z - 1, z, z + 1
+    auto cell_step = [&](int z, int sl0, int sl1, int sl2, T (&f)[Q]) {
+        const int cell = x + nx * (y + ny * z);
+        const int pown = (ly + 1) * HX + lx + 1;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int sy = y - L::cy[i];
+            const bool bb = L::cy[i] != 0 && m.walls && (sy < 0 || sy >= ny);
+            const int slz = D == 3 ? (L::cz[i] > 0 ? sl0 : (L::cz[i] < 0 ? sl2 : sl1)) : 0;
+            const int pos = bb ? pown : pown - L::cy[i] * HX - L::cx[i];
+            const T* r = &rs[bb ? sl1 : slz][0][pos];
+            const T ca = cdot<LAT, T>(i, [&](int k) { return r[k * HXY]; });
+            const T cb = cdot<LAT, T>(i, [&](int k) { return r[(D + k) * HXY]; });
+            f[i] = add_rn(f[i], df_cc<LAT, T>(i, bb, ca, cb, r[NR * HXY]));
+        }
+        collide_cell<LAT, T, PREC, SUB, 2, WT>(m, f, x, y, z, cell, gd, st, bad);
+    };
+    if constexpr (D == 2) {
+        T buf[NE][NR], f[Q];
+        fetch(0, buf);
+        if (own) pull(0, f);
+        stage(0, buf);
+        __syncthreads();
+        if (own) cell_step(0, 0, 0, 0, f);
+    } else {
+        // planes tz0 - 1 .. zend staged in a ring of three; the records of
+        // the next plane and the pulls of the current one are in flight
+        // while a plane is staged
+        const int zend = min(tz0 + zc, nz);
+        const int p0 = tz0 - 1, p1 = zend;
+        T buf[NE][NR];
+        fetch(p0, buf);
+        for (int pz = p0; pz <= p1; ++pz) {
+            const int sl = (pz - p0) % 3;
+            const bool cmp = pz >= tz0 + 1 && own;   // plane pz - 1 once its upper neighbour is staged
+            T f[Q];
+            if (cmp) pull(pz - 1, f);
+            stage(sl, buf);
+            __syncthreads();
+            if (pz < p1) fetch(pz + 1, buf);
+            if (cmp) cell_step(pz - 1, (pz - 2 - p0) % 3, (pz - 1 - p0) % 3, sl, f);
+            __syncthreads();
+        }
+    }
+    block_sum<4>(st, lds);
+    if (threadIdx.x == 0) {
+        double* p = m.part_stats + (size_t)wk.y * 4;
+        p[0] = st[0]; p[1] = st[1]; p[2] = st[2]; p[3] = st[3];
     }
     const unsigned long long anybad = __ballot(bad);
     if (anybad && (threadIdx.x & 63) == 0) atomicOr(&m.ctl->flags, 1);
@@ -533,10 +760,75 @@ __device__ __forceinline__ void curl_at(const T* __restrict__ v, size_t N, int x
     }
 }
 
-// K2a: w = curl v* into W_0 (the same differences as curl_at).  Every load
-// is unconditional, a 32-bit offset from a scalar base (TO fields stay below
-// 2^32 bytes); a neighbour beyond a wall loads the cell itself and counts
-// as zero, so no branch-joined load stalls the others.
+// Neighbour offsets of cell c = (x, y, z) for second-order central
+// differences: periodic wrap, and on the wall axis a neighbour beyond a wall
+// is the cell itself, counted as zero (ok flags).  Every load of the
+// differences below is unconditional, a 32-bit offset from a scalar base (TO
+// fields stay below 2^32 bytes), so no branch-joined load stalls the others.
+struct Nbr {
+    unsigned xm, xp, ym, yp, zm, zp;
+    bool okm, okp;
+};
+__device__ __forceinline__ Nbr nbr_at(unsigned c, int x, int y, int z, int nx, int ny, int nz, int walls, int D)
+{
+    Nbr n;
+    n.xm = c - x + wrapi(x - 1, nx);
+    n.xp = c - x + wrapi(x + 1, nx);
+    n.okm = true;
+    n.okp = true;
+    int ym = y - 1, yp = y + 1;
+    if (walls) { n.okm = ym >= 0; n.okp = yp < ny; ym = n.okm ? ym : y; yp = n.okp ? yp : y; }
+    else { ym = wrapi(ym, ny); yp = wrapi(yp, ny); }
+    n.ym = c + (unsigned)((ym - y) * nx);
+    n.yp = c + (unsigned)((yp - y) * nx);
+    const int plane = nx * ny;
+    n.zm = D == 3 ? c + (unsigned)((wrapi(z - 1, nz) - z) * plane) : c;
+    n.zp = D == 3 ? c + (unsigned)((wrapi(z + 1, nz) - z) * plane) : c;
+    return n;
+}
+
+// Central-difference curl of the D-component field u at a cell (2-D: the
+// scalar D_x u_y - D_y u_x).  In 3-D the adjoint curl^T is the curl itself.
+template <int D, typename T>
+__device__ __forceinline__ void curl_nb(const T* __restrict__ u, unsigned sN, unsigned c, const Nbr& n, T* w)
+{
+    const T* ux = u;
+    const T* uy = u + sN;
+    auto y0 = [](bool ok, T v) { return ok ? v : T(0); };
+    if (D == 2) {
+        w[0] = T(0.5) * (ld_at(uy, n.xp) - ld_at(uy, n.xm)) -
+               T(0.5) * (y0(n.okp, ld_at(ux, n.yp)) - y0(n.okm, ld_at(ux, n.ym)));
+    } else {
+        const T* uz = u + 2 * sN;
+        const T dyuz = T(0.5) * (y0(n.okp, ld_at(uz, n.yp)) - y0(n.okm, ld_at(uz, n.ym)));
+        const T dzuy = T(0.5) * (ld_at(uy, n.zp) - ld_at(uy, n.zm));
+        const T dzux = T(0.5) * (ld_at(ux, n.zp) - ld_at(ux, n.zm));
+        const T dxuz = T(0.5) * (ld_at(uz, n.xp) - ld_at(uz, n.xm));
+        const T dxuy = T(0.5) * (ld_at(uy, n.xp) - ld_at(uy, n.xm));
+        const T dyux = T(0.5) * (y0(n.okp, ld_at(ux, n.yp)) - y0(n.okm, ld_at(ux, n.ym)));
+        w[0] = dyuz - dzuy;
+        w[1] = dzux - dxuz;
+        w[2] = dxuy - dyux;
+    }
+}
+
+// The adjoint curl of a curl field psi (NC components) at a cell: 2-D
+// (D_y psi, -D_x psi) (eq. enstrophy-sensitivity-2d), 3-D curl psi
+// (eq. enstrophy-sensitivity-3d).
+template <int D, typename T>
+__device__ __forceinline__ void curlT_nb(const T* __restrict__ psi, unsigned sN, unsigned c, const Nbr& n, T* out)
+{
+    if (D == 2) {
+        auto y0 = [](bool ok, T v) { return ok ? v : T(0); };
+        out[0] = T(0.5) * (y0(n.okp, ld_at(psi, n.yp)) - y0(n.okm, ld_at(psi, n.ym)));
+        out[1] = -(T(0.5) * (ld_at(psi, n.xp) - ld_at(psi, n.xm)));
+    } else {
+        curl_nb<3, T>(psi, sN, c, n, out);
+    }
+}
+
+// K2a: w = curl v* into W_0 (kernel-filter and Fourier closures, whose
+// filter passes start from w).
 template <int LAT, typename T, bool WT>
 __global__ __launch_bounds__(kBlock) void k_curl(const DevMember* __restrict__ mems, const int2* __restrict__ work)
 {
@@ -548,37 +840,13 @@ __global__ __launch_bounds__(kBlock) void k_curl(const DevMember* __restrict__ m
     const int cell = wk.y * kBlock + threadIdx.x;
     if (cell >= N) return;
     const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
-    const size_t sN = (size_t)N;
-    const T* vx = (const T*)m.vs;
-    const T* vy = vx + sN;
     const unsigned c = (unsigned)cell;
-    const unsigned cxm = c - x + wrapi(x - 1, nx), cxp = c - x + wrapi(x + 1, nx);
-    bool okm = true, okp = true;
-    int ym = y - 1, yp = y + 1;
-    if (m.walls) { okm = ym >= 0; okp = yp < ny; ym = okm ? ym : y; yp = okp ? yp : y; }
-    else { ym = wrapi(ym, ny); yp = wrapi(yp, ny); }
-    const unsigned cym = c + (unsigned)((ym - y) * nx), cyp = c + (unsigned)((yp - y) * nx);
-    auto y0 = [](bool ok, T v) { return ok ? v : T(0); };
+    const Nbr nb = nbr_at(c, x, y, z, nx, ny, nz, m.walls, L::D);
     T w[3];
-    if (L::D == 2) {
-        w[0] = T(0.5) * (ld_at(vy, cxp) - ld_at(vy, cxm)) - T(0.5) * (y0(okp, ld_at(vx, cyp)) - y0(okm, ld_at(vx, cym)));
-    } else {
-        const T* vz = vx + 2 * sN;
-        const int plane = nx * ny;
-        const unsigned czm = c + (unsigned)((wrapi(z - 1, nz) - z) * plane), czp = c + (unsigned)((wrapi(z + 1, nz) - z) * plane);
-        const T dyvz = T(0.5) * (y0(okp, ld_at(vz, cyp)) - y0(okm, ld_at(vz, cym)));
-        const T dzvy = T(0.5) * (ld_at(vy, czp) - ld_at(vy, czm));
-        const T dzvx = T(0.5) * (ld_at(vx, czp) - ld_at(vx, czm));
-        const T dxvz = T(0.5) * (ld_at(vz, cxp) - ld_at(vz, cxm));
-        const T dxvy = T(0.5) * (ld_at(vy, cxp) - ld_at(vy, cxm));
-        const T dyvx = T(0.5) * (y0(okp, ld_at(vx, cyp)) - y0(okm, ld_at(vx, cym)));
-        w[0] = dyvz - dzvy;
-        w[1] = dzvx - dxvz;
-        w[2] = dxvy - dyvx;
-    }
+    curl_nb<L::D, T>((const T*)m.vs, (unsigned)N, c, nb, w);
     T* W = (T*)m.W;
 #pragma unroll
-    for (int a = 0; a < L::NC; ++a) st_fld_at(W + (size_t)a * sN, c, w[a], WT);
+    for (int a = 0; a < L::NC; ++a) st_fld_at(W + (size_t)a * N, c, w[a], WT);
 }
 
 // Binomial filter B = (x)_a [1,2,1]/4 of one scalar field at (x,y,z).
@@ -610,14 +878,14 @@ __device__ __forceinline__ T binom_at(const T* __restrict__ u, int x, int y, int
     return acc;
 }
 
-// K2b: P_j = B P_{j-1} (P_0 = v*) for j <= jv and W_j = B W_{j-1} for j <= jw.
+// K2b, passes j >= 2: P_j = B P_{j-1} for j <= jv and W_j = B W_{j-1} with
+// C_{j-1} = curl^T W_{j-1} for j <= jw (pass 1 is k_binom1).
 // 2.5-D tiling: a workgroup owns a TX x TY tile of the xy plane (32 x 8, or
 // 64 x 4 on wide grids: each staged row then wastes fewer 128-byte lines on
 // its one-cell x halo) and a chunk of zc planes (chosen per grid for enough
 // workgroups); every plane of the chunk (plus one halo plane on each side)
 // is staged with its xy halo in LDS, filtered in x and y there, and the z
 // pass runs on a three-plane window kept in registers.
-__device__ __forceinline__ int modi(int a, int n) { int r = a % n; return r < 0 ? r + n : r; }
 
 // CH: the chains the launch advances (1: v, 2: w and its curl, 3: both);
 // the launch passes the union over its members, and a member whose chain
@@ -639,7 +907,7 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
     KParam* prm = kc(m.prm);
     // this pass: B^j v (j <= jv), B^j w (j <= jw) and C_{j-1} = curl^T B^{j-1} w (j - 1 <= jw)
     const bool dov = j <= prm->jv, dow = prm->has_z && j <= prm->jw;
-    const bool doc = prm->has_z && j - 1 <= prm->jw;
+    const bool doc = dow;   // the top C_jw is formed by its readers from W_jw
     if (!dov && !doc) return;
     if ((CH == 1 && !dov) || (CH == 2 && !doc)) return;
     const int nx = m.nx, ny = m.ny, nz = m.nz;
@@ -795,6 +1063,217 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
     }
 }
 
+// K2b, pass 1: the first power of both chains from v* alone.  v* is staged
+// with a two-cell xy halo; w = curl v* is formed in LDS on the tile and its
+// one-cell halo (zero beyond the walls, as every filtered field), from which
+// the pass forms B w and C_0 = curl^T w; it writes P_1 = B v* (jv >= 1),
+// W_0 = w and, when jw >= 1, W_1 = B w and C_0.  In 3-D the z direction runs
+// through a ring of three staged v* planes and register windows of the xy
+// parts, w lagging v* by one plane.  ZC: some member of the launch has Z
+// QoIs (otherwise only B v* is formed).
+template <int LAT, typename T, int TX, bool ZC, bool WT>
+__global__ __launch_bounds__(kBlock) void k_binom1(const DevMember* __restrict__ mems, const int2* __restrict__ work)
+{
+    using L = Lat<LAT>;
+    constexpr int D = L::D, NC = L::NC;
+    constexpr int TY = kBlock / TX;
+    constexpr int HX1 = TX + 2, HY1 = TY + 2, HXY1 = HX1 * HY1;   // tile and one-cell halo
+    constexpr int HX2 = TX + 4, HY2 = TY + 4, HXY2 = HX2 * HY2;   // tile and two-cell halo
+    constexpr int NE1 = (HXY1 + kBlock - 1) / kBlock, NE2 = (HXY2 + kBlock - 1) / kBlock;
+    constexpr int NSL = D == 3 ? 3 : 1;
+    __shared__ T vt[NSL][D][HXY2];
+    __shared__ T wt[ZC ? NC : 1][ZC ? HXY1 : 1];
+    const int2 wk = work[blockIdx.x];
+    KMember& m = *kc(mems + wk.x);
+    KParam* prm = kc(m.prm);
+    const bool dov = prm->jv >= 1;
+    const bool doz = ZC && prm->has_z;
+    const bool dow1 = doz && prm->jw >= 1;
+    if (!dov && !doz) return;   // uniform
+    const int nx = m.nx, ny = m.ny, nz = m.nz;
+    const size_t sN = (size_t)m.N;
+    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
+    const int zc = m.zc;
+    const int tx0 = (wk.y % ntx) * TX;
+    const int ty0 = ((wk.y / ntx) % nty) * TY;
+    const int tz0 = D == 3 ? (wk.y / (ntx * nty)) * zc : 0;
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int x = tx0 + lx, y = ty0 + ly;
+    const bool own = x < nx && y < ny;
+    const T* vs = (const T*)m.vs;
+    T* P1 = (T*)m.P;
+    T* W0 = (T*)m.W;
+    T* W1 = (T*)m.W + (size_t)NC * sN;
+    T* C0 = (T*)m.C;
+    // the staged v* elements of this thread (plane offsets; beyond the walls
+    // cell 0 is loaded and zero staged)
+    int eoff[NE2];
+    bool eok[NE2];
+#pragma unroll
+    for (int k = 0; k < NE2; ++k) {
+        const int e = threadIdx.x + k * kBlock;
+        const int gx = modi(tx0 + e % HX2 - 2, nx);
+        int gy = ty0 + e / HX2 - 2;
+        bool ok = e < HXY2;
+        if (m.walls) ok = ok && gy >= 0 && gy < ny;
+        else gy = modi(gy, ny);
+        eok[k] = ok;
+        eoff[k] = ok ? gx + nx * gy : 0;
+    }
+    // the w elements of this thread: zero beyond the walls
+    bool wok[NE1];
+#pragma unroll
+    for (int k = 0; k < NE1; ++k) {
+        const int e = threadIdx.x + k * kBlock;
+        const int gy = ty0 + e / HX1 - 1;
+        wok[k] = e < HXY1 && !(m.walls && (gy < 0 || gy >= ny));
+    }
+    const int plane = nx * ny;
+    auto fetch = [&](int pz, T (&buf)[NE2][D]) {
+        const unsigned zo = (unsigned)(plane * (D == 3 ? modi(pz, nz) : 0));
+#pragma unroll
+        for (int k = 0; k < NE2; ++k)
+#pragma unroll
+            for (int a = 0; a < D; ++a) buf[k][a] = ld_at(vs + a * sN, zo + (unsigned)eoff[k]);
+    };
+    auto stage = [&](int sl, const T (&buf)[NE2][D]) {
+#pragma unroll
+        for (int k = 0; k < NE2; ++k) {
+            const int e = threadIdx.x + k * kBlock;
+            if (e < HXY2) {
+#pragma unroll
+                for (int a = 0; a < D; ++a) vt[sl][a][e] = eok[k] ? buf[k][a] : T(0);
+            }
+        }
+    };
+    // xy part of B at the own cell of a tile t with row length H, own
+    // position c
+    auto bxy = [](const T* t, int c, int H) {
+        const T q0 = T(0.25) * (t[c - H - 1] + T(2) * t[c - H] + t[c - H + 1]);
+        const T q1 = T(0.25) * (t[c - 1] + T(2) * t[c] + t[c + 1]);
+        const T q2 = T(0.25) * (t[c + H - 1] + T(2) * t[c + H] + t[c + H + 1]);
+        return T(0.25) * q0 + T(0.5) * q1 + T(0.25) * q2;
+    };
+    // w = curl v* on the tile and its halo, from the staged planes z - 1,
+    // z, z + 1 (s0, s1, s2; the same slot in 2-D)
+    auto curl_tile = [&](int s0, int s1, int s2) {
+#pragma unroll
+        for (int k = 0; k < NE1; ++k) {
+            const int e = threadIdx.x + k * kBlock;
+            if (e >= HXY1) continue;
+            const int p = (e / HX1 + 1) * HX2 + e % HX1 + 1;
+            T w[3];
+            if (D == 2) {
+                w[0] = T(0.5) * (vt[s1][1][p + 1] - vt[s1][1][p - 1]) -
+                       T(0.5) * (vt[s1][0][p + HX2] - vt[s1][0][p - HX2]);
+            } else {
+                const T dyvz = T(0.5) * (vt[s1][2 % D][p + HX2] - vt[s1][2 % D][p - HX2]);
+                const T dzvy = T(0.5) * (vt[s2][1][p] - vt[s0][1][p]);
+                const T dzvx = T(0.5) * (vt[s2][0][p] - vt[s0][0][p]);
+                const T dxvz = T(0.5) * (vt[s1][2 % D][p + 1] - vt[s1][2 % D][p - 1]);
+                const T dxvy = T(0.5) * (vt[s1][1][p + 1] - vt[s1][1][p - 1]);
+                const T dyvx = T(0.5) * (vt[s1][0][p + HX2] - vt[s1][0][p - HX2]);
+                w[0] = dyvz - dzvy;
+                w[1] = dzvx - dxvz;
+                w[2] = dxvy - dyvx;
+            }
+#pragma unroll
+            for (int a = 0; a < NC; ++a) wt[a % (ZC ? NC : 1)][ZC ? e : 0] = wok[k] ? w[a] : T(0);
+        }
+    };
+    const int pv = (ly + 2) * HX2 + lx + 2;   // own cell in the v* tile
+    const int pw = (ly + 1) * HX1 + lx + 1;   // own cell in the w tile
+    if constexpr (D == 2) {
+        T buf[NE2][D];
+        fetch(0, buf);
+        stage(0, buf);
+        __syncthreads();
+        if constexpr (ZC) {
+            if (doz) curl_tile(0, 0, 0);
+            __syncthreads();
+        }
+        if (!own) return;
+        const size_t ci = (size_t)x + (size_t)nx * y;
+        if (dov)
+#pragma unroll
+            for (int a = 0; a < D; ++a) st_fld(P1 + a * sN + ci, bxy(&vt[0][a][0], pv, HX2), WT);
+        if constexpr (ZC) {
+            if (doz) st_fld(W0 + ci, wt[0][pw], WT);
+            if (dow1) {
+                st_fld(W1 + ci, bxy(&wt[0][0], pw, HX1), WT);
+                st_fld(C0 + ci, T(0.5) * (wt[0][pw + HX1] - wt[0][pw - HX1]), WT);        // D_y w
+                st_fld(C0 + sN + ci, -(T(0.5) * (wt[0][pw + 1] - wt[0][pw - 1])), WT);    // -D_x w
+            }
+        }
+    } else {
+        // output planes [tz0, zend); v* staged on tz0 - 2 .. zend + 1, w
+        // formed on tz0 - 1 .. zend
+        const int zend = min(tz0 + zc, nz);
+        const int p0 = tz0 - 2, p1 = zend + 1;
+        T bva[D] = {}, bvb[D] = {};                 // B_xy v* at planes pz - 2, pz - 1
+        T oma[3] = {}, omb[3] = {};                 // w (own cell) at planes pz - 3, pz - 2
+        T bwa[3] = {}, bwb[3] = {};                 // B_xy w at planes pz - 3, pz - 2
+        T dxb[3] = {}, dyb[3] = {};                 // D_x w, D_y w at plane pz - 2
+        T buf[NE2][D];
+        fetch(p0, buf);
+        for (int pz = p0; pz <= p1; ++pz) {
+            const int sl = (pz - p0) % 3;
+            stage(sl, buf);
+            __syncthreads();
+            if (pz < p1) fetch(pz + 1, buf);
+            T bvn[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) bvn[a] = bxy(&vt[sl][a][0], pv, HX2);
+            if (dov && own && pz - 1 >= tz0 && pz - 1 < zend) {
+                const size_t ci = (size_t)x + (size_t)nx * (y + (size_t)ny * (pz - 1));
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+                    st_fld(P1 + a * sN + ci, T(0.25) * bva[a] + T(0.5) * bvb[a] + T(0.25) * bvn[a], WT);
+            }
+#pragma unroll
+            for (int a = 0; a < D; ++a) { bva[a] = bvb[a]; bvb[a] = bvn[a]; }
+            if constexpr (ZC) {
+                if (doz && pz >= tz0) {
+                    // w at plane pz - 1 on the tile and its halo
+                    curl_tile((pz - 2 - p0) % 3, (pz - 1 - p0) % 3, sl);
+                    __syncthreads();
+                    T omn[3], bwn[3], dxn[3], dyn[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const T* t = &wt[a][0];
+                        omn[a] = t[pw];
+                        bwn[a] = bxy(t, pw, HX1);
+                        dxn[a] = T(0.5) * (t[pw + 1] - t[pw - 1]);
+                        dyn[a] = T(0.5) * (t[pw + HX1] - t[pw - HX1]);
+                    }
+                    if (own && pz - 1 >= tz0 && pz - 1 < zend) {
+                        const size_t ci = (size_t)x + (size_t)nx * (y + (size_t)ny * (pz - 1));
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) st_fld(W0 + a * sN + ci, omn[a], WT);
+                    }
+                    if (dow1 && own && pz - 2 >= tz0 && pz - 2 < zend) {
+                        const size_t ci = (size_t)x + (size_t)nx * (y + (size_t)ny * (pz - 2));
+#pragma unroll
+                        for (int a = 0; a < 3; ++a)
+                            st_fld(W1 + a * sN + ci, T(0.25) * bwa[a] + T(0.5) * bwb[a] + T(0.25) * bwn[a], WT);
+                        // curl w at plane pz - 2, D_z from the planes below and above
+                        st_fld(C0 + ci, dyb[2] - T(0.5) * (omn[1] - oma[1]), WT);           // D_y w_z - D_z w_y
+                        st_fld(C0 + sN + ci, T(0.5) * (omn[0] - oma[0]) - dxb[2], WT);      // D_z w_x - D_x w_z
+                        st_fld(C0 + 2 * sN + ci, dxb[1] - dyb[0], WT);                      // D_x w_y - D_y w_x
+                    }
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        oma[a] = omb[a]; omb[a] = omn[a];
+                        bwa[a] = bwb[a]; bwb[a] = bwn[a];
+                        dxb[a] = dxn[a]; dyb[a] = dyn[a];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Per-cell sensitivities of all E/Z QoIs (App. A):
 //   E: V = R R v = sum_j rr_j B^j v;
@@ -817,6 +1296,18 @@ template <typename T> __device__ __forceinline__ T coef_cw(KCtl* c, int j);
 template <> __device__ __forceinline__ float coef_cw<float>(KCtl* c, int j) { return c->cwf[j]; }
 template <> __device__ __forceinline__ double coef_cw<double>(KCtl* c, int j) { return c->cw[j]; }
 
+// C_jw = curl^T W_jw at cell (x, y, z) from the neighbours of W_jw: the
+// binomial passes store C_j only for j < jw.
+template <int LAT, typename T>
+__device__ __forceinline__ void top_curl(KMember& m, int jw, int x, int y, int z, T* out)
+{
+    using L = Lat<LAT>;
+    const unsigned sN = (unsigned)m.N;
+    const unsigned c = (unsigned)(x + m.nx * (y + m.ny * z));
+    const Nbr nb = nbr_at(c, x, y, z, m.nx, m.ny, m.nz, m.walls, L::D);
+    curlT_nb<L::D, T>((const T*)m.W + (size_t)jw * L::NC * sN, sN, c, nb, out);
+}
+
 // The fields a cell's sensitivities are formed from, loaded in one batch
 // (no branch between the loads, so that the loads of several cells can be
 // in flight together) and evaluated afterwards.
@@ -829,8 +1320,9 @@ struct CellIn {
 };
 
 template <int LAT, typename T, int MAXSA, bool KF>
-__device__ __forceinline__ void cell_load(KMember& m, KParam* prm, int cell, CellIn<LAT, T, MAXSA>& in)
+__device__ __forceinline__ void cell_load(KMember& m, KParam* prm, int x, int y, int z, CellIn<LAT, T, MAXSA>& in)
 {
+    const int cell = x + m.nx * (y + m.ny * z);
     using L = Lat<LAT>;
     constexpr int D = L::D, NC = L::NC;
     const int jv = prm->jv, jw = prm->jw;
@@ -867,14 +1359,24 @@ __device__ __forceinline__ void cell_load(KMember& m, KParam* prm, int cell, Cel
 #pragma unroll
         for (int a = 0; a < NC; ++a) in.wc[jj][a] = src[a * sN + cell];
     }
-    // C_j = curl^T B^j w (Z sensitivities)
+    // C_j = curl^T B^j w (Z sensitivities): the stored C_j for j < jw, the
+    // top one from the neighbours of W_jw
+    if (!hz) return;
+    T ctop[D];
+    top_curl<LAT, T>(m, jw, x, y, z, ctop);
     const T* __restrict__ Cc = (const T*)m.C;
+    const int jc = jw > 0 ? jw - 1 : 0;
 #pragma unroll
-    for (int jj = 0; jj <= kMaxPow; ++jj) {
-        const T* src = hz ? Cc + (size_t)(jj < jw ? jj : jw) * D * sN : vs;
+    for (int jj = 0; jj < kMaxPow; ++jj) {
+        const T* src = Cc + (size_t)(jj < jc ? jj : jc) * D * sN;
 #pragma unroll
-        for (int a = 0; a < D; ++a) in.cv[jj][a] = src[a * sN + cell];
+        for (int a = 0; a < D; ++a) {
+            const T v = src[a * sN + cell];
+            in.cv[jj][a] = jj < jw ? v : ctop[a];
+        }
     }
+#pragma unroll
+    for (int a = 0; a < D; ++a) in.cv[kMaxPow][a] = ctop[a];
 }
 
 // The closure's filter coefficients of every E/Z QoI, read once per
@@ -1006,7 +1508,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const DevMember* __restrict__
             has[u] = u == 0 || (c + u < m.cpt2 && pa + u * kBlock < plane);
             const int p = has[u] ? pa + u * kBlock : pa;
             const int x = p % nx, z = p / nx;
-            cell_load<LAT, T, MAXSA, KF>(m, prm, x + nx * (y + ny * z), in[u]);
+            cell_load<LAT, T, MAXSA, KF>(m, prm, x, y, z, in[u]);
         }
 #pragma unroll
         for (int u = 0; u < NP; ++u) {
@@ -1206,7 +1708,7 @@ __global__ __launch_bounds__(kBlock) void k_sum(const DevMember* __restrict__ me
     double v[1] = {0};
     if (slot < 4) {
 #pragma unroll 8
-        for (int b = threadIdx.x; b < m.nb1; b += kBlock) v[0] += m.part_stats[(size_t)b * 4 + slot];
+        for (int b = threadIdx.x; b < m.nst; b += kBlock) v[0] += m.part_stats[(size_t)b * 4 + slot];
     } else {
         const int nblk = m.ny * m.nbx2;
         const double* p = m.part_to + (size_t)(slot - 4) * nblk;
@@ -1464,14 +1966,18 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
     }
 }
 
-// K4: dv = sum_j cv_j B^j v* + sum_j cw_j C_j + e_x cmp(y), then
-// delta f_i = feq_i(rho, v* + dv) - feq_i(rho, v*) added in place to the
-// cell's predictor populations (the buffer k_step of this step wrote).
+// K4: dv = sum_j cv_j B^j v* + sum_j cw_j C_j + e_x cmp(y) (eq. TO-ansatz
+// as sum_j beta_j V_j), and the SGS change of the cell's predictor
+// populations delta f_i = feq_i(rho, v* + dv) - feq_i(rho, v*): DEF, the
+// record (a, b) = (rho dv, 2 v* + dv) that the next stream-collide applies
+// during its pull; otherwise added in place to the populations the
+// stream-collide of this step wrote (the WALE substrate, whose velocity
+// gradients need the complete post-streaming state).
 template <typename T> __device__ __forceinline__ T coef_bsa(KCtl* c, int s);
 template <> __device__ __forceinline__ float coef_bsa<float>(KCtl* c, int s) { return c->bsaf[s]; }
 template <> __device__ __forceinline__ double coef_bsa<double>(KCtl* c, int s) { return c->bsa[s]; }
 
-template <int LAT, typename T, bool KF, bool WT>
+template <int LAT, typename T, bool KF, bool WT, bool DEF>
 __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ mems, const int2* __restrict__ work,
                                                   int flip)
 {
@@ -1480,7 +1986,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ 
     const int2 wk = work[blockIdx.x];
     KMember& m = *kc(mems + wk.x);
     KParam* prm = kc(m.prm);
-    const int N = m.N, nx = m.nx, ny = m.ny, nz = m.nz;
+    const int N = m.N, nx = m.nx, ny = m.ny;
     const int cell = wk.y * kBlock + threadIdx.x;
     if (cell >= N) return;
     const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
@@ -1510,60 +2016,111 @@ __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ 
             out[a] = acc;
         }
     } else {
-    // Unconditional loads with the power clamped to the highest one stored:
-    // cv_j (cw_j) is zero above jv (jw), so the extra terms add exact zeros.
-    T fv[kMaxPow + 1][D], fc[kMaxPow + 1][D];
+        // Unconditional loads with the power clamped to the highest one
+        // stored: cv_j (cw_j) is zero above jv (jw), so the extra terms add
+        // exact zeros.  The top C_jw comes from the neighbours of W_jw.
+        T fv[kMaxPow + 1][D], fc[kMaxPow + 1][D];
 #pragma unroll
-    for (int jj = 0; jj <= kMaxPow; ++jj) {
-        const int je = jj < jv ? jj : jv;
-        const T* src = je == 0 ? vsp : (const T*)m.P + (size_t)(je - 1) * D * sN;
-        const T* srcc = hz ? (const T*)m.C + (size_t)(jj < jw ? jj : jw) * D * sN : vsp;
+        for (int jj = 0; jj <= kMaxPow; ++jj) {
+            const int je = jj < jv ? jj : jv;
+            const T* src = je == 0 ? vsp : (const T*)m.P + (size_t)(je - 1) * D * sN;
+#pragma unroll
+            for (int a = 0; a < D; ++a) fv[jj][a] = ld_fld<WT>(src + a * sN + cell);
+        }
+        if (hz) {
+            T ctop[D];
+            top_curl<LAT, T>(m, jw, x, y, z, ctop);
+            const int jc = jw > 0 ? jw - 1 : 0;
+#pragma unroll
+            for (int jj = 0; jj < kMaxPow; ++jj) {
+                const T* srcc = (const T*)m.C + (size_t)(jj < jc ? jj : jc) * D * sN;
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    const T v = ld_fld<WT>(srcc + a * sN + cell);
+                    fc[jj][a] = jj < jw ? v : ctop[a];
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < D; ++a) fc[kMaxPow][a] = ctop[a];
+        }
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            fv[jj][a] = ld_fld<WT>(src + a * sN + cell);
-            fc[jj][a] = ld_fld<WT>(srcc + a * sN + cell);
+            T s = coef_cv<T>(ctl, 0) * fv[0][a];
+#pragma unroll
+            for (int jj = 1; jj <= kMaxPow; ++jj) s += coef_cv<T>(ctl, jj) * fv[jj][a];
+            out[a] = s;
         }
-    }
+        if (hz) {
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-        T s = coef_cv<T>(ctl, 0) * fv[0][a];
+            for (int a = 0; a < D; ++a) {
+                T sacc = 0;
 #pragma unroll
-        for (int jj = 1; jj <= kMaxPow; ++jj) s += coef_cv<T>(ctl, jj) * fv[jj][a];
-        out[a] = s;
-    }
-    if (hz) {
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            T sacc = 0;
-#pragma unroll
-            for (int jj = 0; jj <= kMaxPow; ++jj) sacc += coef_cw<T>(ctl, jj) * fc[jj][a];
-            out[a] += sacc;
+                for (int jj = 0; jj <= kMaxPow; ++jj) sacc += coef_cw<T>(ctl, jj) * fc[jj][a];
+                out[a] += sacc;
+            }
         }
-    }
 #pragma unroll
-    for (int a = 0; a < D; ++a) vs[a] = fv[0][a];
+        for (int a = 0; a < D; ++a) vs[a] = fv[0][a];
     }
     if (prm->nmp > 0) out[0] += T(m.cmp[y]);
-    // the SGS change of the predictor populations
     const T rho = T(1) + ((const T*)m.rho)[cell];
-    PendRec<T> r;
-    const T bx = T(2) * vs[0] + out[0], by = T(2) * vs[1] + out[1], bz = D == 3 ? T(2) * vs[2] + out[2] : T(0);
-    r.u.x = rho * out[0];
-    r.u.y = rho * out[1];
-    r.u.z = D == 3 ? rho * out[2] : T(0);
-    r.u.w = rho * (out[0] * bx + out[1] * by + (D == 3 ? out[2] * bz : T(0)));
-    r.v.x = bx;
-    r.v.y = by;
-    r.v.z = bz;
-    r.v.w = T(0);
-    // (TO fields stay below 2^32 bytes: 32-bit offsets from scalar bases)
-    T* g = (T*)m.g[m.parity ^ flip ^ 1];
-    T gi[L::Q];
+    T ra[D], rb[D];
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) gi[i] = ld_fld<WT>(g + (size_t)i * sN + cell);
+    for (int a = 0; a < D; ++a) {
+        ra[a] = rho * out[a];
+        rb[a] = T(2) * vs[a] + out[a];
+    }
+    // (TO fields stay below 2^32 bytes: 32-bit offsets from scalar bases)
+    if constexpr (DEF) {
+        T* rec = (T*)m.rec;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            st_fld_at(rec + (size_t)a * sN, (unsigned)cell, ra[a], WT);
+            st_fld_at(rec + (size_t)(D + a) * sN, (unsigned)cell, rb[a], WT);
+        }
+    } else {
+        T* g = (T*)m.g[m.parity ^ flip ^ 1];
+        const T e = rec_e<D, T>(ra, rb);
+        T gi[L::Q];
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) gi[i] = ld_fld<WT>(g + (size_t)i * sN + cell);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+            st_fld_at(g + (size_t)i * sN, (unsigned)cell,
+                      add_df<LAT, T>(gi[i], i, [&](int k) { return ra[k]; }, [&](int k) { return rb[k]; }, e), WT);
+    }
+}
+
+// A pending SGS change (the records of the last step) added in place to the
+// current populations g[parity ^ flip], and the records cleared, so the state
+// can be read or replaced (checkpoints, fields, a closure change).
+template <int LAT, typename T>
+__global__ __launch_bounds__(kBlock) void k_flush(const DevMember* __restrict__ mems, const int2* __restrict__ work,
+                                                  int flip)
+{
+    using L = Lat<LAT>;
+    constexpr int D = L::D;
+    const int2 wk = work[blockIdx.x];
+    KMember& m = *kc(mems + wk.x);
+    const int N = m.N;
+    const int cell = wk.y * kBlock + threadIdx.x;
+    if (cell >= N) return;
+    const size_t sN = (size_t)N;
+    T* rec = (T*)m.rec;
+    T ra[D], rb[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        ra[a] = rec[a * sN + cell];
+        rb[a] = rec[(D + a) * sN + cell];
+    }
+    const T e = rec_e<D, T>(ra, rb);
+    T* g = (T*)m.g[m.parity ^ flip];
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
-        st_fld_at(g + (size_t)i * sN, (unsigned)cell, gi[i] + pend_df<LAT, T>(r, i, T(1)), WT);
+        g[i * sN + cell] = add_df<LAT, T>(g[i * sN + cell], i, [&](int k) { return ra[k]; },
+                                          [&](int k) { return rb[k]; }, e);
+#pragma unroll
+    for (int a = 0; a < 2 * D; ++a) rec[a * sN + cell] = T(0);
 }
 
 // ---------------------------------------------------------------------------
@@ -2116,8 +2673,26 @@ static void launch_step_group(const LaunchGroup& g, hipStream_t st, int flip, hi
             hipLaunchKernelGGL((k_moments<LAT, T, PREC, false>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip,
                                (double*)nullptr);
     }
+#define LBM_STEP_T(SUB, TXV)                                                                               \
+    do {                                                                                                   \
+        if (g.wt)                                                                                          \
+            hipLaunchKernelGGL((k_step_t<LAT, T, PREC, SUB, TXV, true>), dim3(g.nbb), blk, 0, st, g.mems,  \
+                               g.workb, flip);                                                             \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_step_t<LAT, T, PREC, SUB, TXV, false>), dim3(g.nbb), blk, 0, st, g.mems, \
+                               g.workb, flip);                                                             \
+    } while (0)
 #define LBM_STEP_SUB(SUB)                                                                                  \
     do {                                                                                                   \
+        if constexpr (SUB != LBM_WALE) {                                                                   \
+            if (g.mode == 2 && g.defer) {                                                                  \
+                if (Lat<LAT>::D == 3 && g.btx == kBinTXW)                                                  \
+                    LBM_STEP_T(SUB, (Lat<LAT>::D == 3 ? kBinTXW : kBinTX));                                \
+                else                                                                                       \
+                    LBM_STEP_T(SUB, kBinTX);                                                               \
+                break;                                                                                     \
+            }                                                                                              \
+        }                                                                                                  \
         if (g.mode == 2 && g.wt)                                                                           \
             hipLaunchKernelGGL((k_step<LAT, T, PREC, SUB, 2, true>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
         else if (g.mode == 2)                                                                              \
@@ -2134,10 +2709,11 @@ static void launch_step_group(const LaunchGroup& g, hipStream_t st, int flip, hi
     else
         LBM_STEP_SUB(LBM_BGK);
 #undef LBM_STEP_SUB
+#undef LBM_STEP_T
 to_chain:
     mark(1);
     if (g.mode == 2) {
-        if (g.any_z) {
+        if (g.kf && g.any_z) {   // the binomial chains form w in their first pass
             if (g.wt) hipLaunchKernelGGL((k_curl<LAT, T, true>), dim3(g.nb1), blk, 0, st, g.mems, g.work1);
             else hipLaunchKernelGGL((k_curl<LAT, T, false>), dim3(g.nb1), blk, 0, st, g.mems, g.work1);
         }
@@ -2153,7 +2729,21 @@ to_chain:
                                        g.kjobs + g.klev[l].x);
             }
         }
-        for (int j = 1; j <= (g.kf ? 0 : g.npass); ++j) {
+        if (!g.kf && g.npass >= 1) {
+#define LBM_BINOM1(TXV, ZCV)                                                                                    \
+    do {                                                                                                        \
+        if (g.wt) hipLaunchKernelGGL((k_binom1<LAT, T, TXV, ZCV, true>), dim3(g.nbb), blk, 0, st, g.mems, g.workb); \
+        else hipLaunchKernelGGL((k_binom1<LAT, T, TXV, ZCV, false>), dim3(g.nbb), blk, 0, st, g.mems, g.workb); \
+    } while (0)
+            if (Lat<LAT>::D == 3 && g.btx == kBinTXW) {
+                if (g.any_z) LBM_BINOM1((Lat<LAT>::D == 3 ? kBinTXW : kBinTX), true);
+                else LBM_BINOM1((Lat<LAT>::D == 3 ? kBinTXW : kBinTX), false);
+            } else {
+                if (g.any_z) LBM_BINOM1(kBinTX, true); else LBM_BINOM1(kBinTX, false);
+            }
+#undef LBM_BINOM1
+        }
+        for (int j = 2; j <= (g.kf ? 0 : g.npass); ++j) {
 #define LBM_BINOM(TXV, CHV)                                                                                    \
     do {                                                                                                       \
         if (g.wt) hipLaunchKernelGGL((k_binom<LAT, T, TXV, CHV, true>), dim3(g.nbb), blk, 0, st, g.mems, g.workb, j); \
@@ -2184,12 +2774,14 @@ to_chain:
         hipLaunchKernelGGL(k_solve, dim3(g.nmem), blk, 0, st, g.mems, g.workm);
         mark(5);
         if (!g.probe) {
-#define LBM_APPLY(KFV)                                                                                       \
+#define LBM_APPLY(KFV, DEFV)                                                                                 \
     do {                                                                                                     \
-        if (g.wt) hipLaunchKernelGGL((k_apply<LAT, T, KFV, true>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
-        else hipLaunchKernelGGL((k_apply<LAT, T, KFV, false>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
+        if (g.wt) hipLaunchKernelGGL((k_apply<LAT, T, KFV, true, DEFV>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
+        else hipLaunchKernelGGL((k_apply<LAT, T, KFV, false, DEFV>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
     } while (0)
-            if (g.kf) LBM_APPLY(true); else LBM_APPLY(false);
+            const bool def = g.defer && g.substrate != LBM_WALE;
+            if (g.kf) { if (def) LBM_APPLY(true, true); else LBM_APPLY(true, false); }
+            else { if (def) LBM_APPLY(false, true); else LBM_APPLY(false, false); }
 #undef LBM_APPLY
         }
         mark(6);
@@ -2264,6 +2856,19 @@ void launch_fields(int lattice, int precision, const DevMember* dm, const int2* 
     case LBM_D3Q19 * 3 + LBM_FP32_PLAIN: LBM_MOM(LBM_D3Q19, float, LBM_FP32_PLAIN); break;
     }
 #undef LBM_MOM
+}
+
+void launch_flush(int lattice, int precision, const DevMember* dm, const int2* work1, int nb1, int flip,
+                  hipStream_t st)
+{
+    const dim3 blk(kBlock), grd(nb1);
+    if (lattice == LBM_D2Q9) {
+        if (precision == LBM_FP64) hipLaunchKernelGGL((k_flush<LBM_D2Q9, double>), grd, blk, 0, st, dm, work1, flip);
+        else hipLaunchKernelGGL((k_flush<LBM_D2Q9, float>), grd, blk, 0, st, dm, work1, flip);
+    } else {
+        if (precision == LBM_FP64) hipLaunchKernelGGL((k_flush<LBM_D3Q19, double>), grd, blk, 0, st, dm, work1, flip);
+        else hipLaunchKernelGGL((k_flush<LBM_D3Q19, float>), grd, blk, 0, st, dm, work1, flip);
+    }
 }
 
 void launch_philox_test(const uint32_t* in, uint32_t* out, int n, hipStream_t st)

@@ -69,19 +69,26 @@ struct LaunchGroup {
     int nklev;
     const FourierProg* fprog;   // Fourier band QoIs (host memory; null if none)
     int wt;             // store the fields the next kernel reads through the L2 (small launches)
+    int defer;          // TO mode: the SGS change is recorded and applied by the next step's pull
+                        // (k_step_t over the binomial tiles); not with the WALE substrate
 };
 
 enum { OP_INIT = 0, OP_GET_POP = 1, OP_SET_POP = 2, OP_STREAM = 3 };
 
 // ev (nullable): 7 events recorded at the phase boundaries of the step
-// (start, after stream-collide, after curl, after the binomial powers, after
-// the reduce, after the cross-block sums and solve, after the apply).
+// (start, after stream-collide, after the curl of kernel-filter closures,
+// after the binomial powers, after the reduce, after the cross-block sums and
+// solve, after the apply).
 constexpr int kNumPhases = 6;
 void launch_step(const LaunchGroup& g, hipStream_t st, int flip, hipEvent_t* ev = nullptr);
 void launch_state(int op, int lattice, int precision, const DevMember* dm, int N, bool has_to, int flip,
                   hipStream_t st, const double* a, double* b);
 void launch_fields(int lattice, int precision, const DevMember* dm, const int2* work1, int nb1, bool has_to,
                    int flip, hipStream_t st, double* rho_out);
+// The pending SGS change of deferring members added to their current
+// populations g[parity ^ flip] and their records cleared (k_flush).
+void launch_flush(int lattice, int precision, const DevMember* dm, const int2* work1, int nb1, int flip,
+                  hipStream_t st);
 void launch_philox_test(const uint32_t* in, uint32_t* out, int n, hipStream_t st);
 void launch_normals_test(unsigned long long seed, long long step0, int nsteps, int n, double* out, hipStream_t st);
 int lattice_table(int lattice, int* c, double* w);
