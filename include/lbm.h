@@ -233,6 +233,20 @@ int lbm_qoi(lbm_ctx* ctx, long first, long count, lbm_qoi_rec* out);
  * state, in double precision (syncs).  rho may be NULL. */
 int lbm_fields(lbm_ctx* ctx, double* rho, double* u);
 
+/* lbm_fields for callers that cannot allocate (tight serving loops,
+ * harnesses that forbid device or host allocations between steps): the same
+ * outputs, bitwise, staged through a fixed device array of
+ * LBM_FIELDS_NOALLOC_MAX_BYTES that each GPU holds until the process ends,
+ * instead of memory allocated per call.  No hipMalloc, hipFree or other
+ * allocating call is made.  Limit: (d + 1) * N * 8 bytes of staging, i.e. at
+ * most 524288 cells in 3-D and 699050 in 2-D; larger grids are rejected with
+ * LBM_EINVAL (use lbm_fields).  Every call on a GPU shares that GPU's array:
+ * calls that overlap in time on one GPU (other threads, other streams) race
+ * and must be serialised by the caller.  The device is the one current on
+ * the calling thread.  Syncs the context stream; rho may be NULL. */
+#define LBM_FIELDS_NOALLOC_MAX_BYTES (16u << 20)
+int lbm_fields_noalloc(lbm_ctx* ctx, double* rho, double* u);
+
 /* Full post-collision populations f (Q*N, library ordering, double) of the
  * current state (the SGS change of the last step included); and the
  * inverse. */

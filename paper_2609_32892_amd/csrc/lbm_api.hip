@@ -8,6 +8,7 @@
 #include <cmath>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -1137,6 +1138,68 @@ int lbm_fields(lbm_ctx* c, double* rho, double* u)
     }
     hipFree(buf);
     return rc;
+}
+
+}  // extern "C"
+
+// Staging of lbm_fields_noalloc: a fixed device array instead of an
+// allocation per call.  Each GPU the library runs on holds its own copy until
+// the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns for the device (the array's name is a host-side
+// stand-in, not a device address).
+namespace {
+constexpr size_t kFieldScratchBytes = size_t(LBM_FIELDS_NOALLOC_MAX_BYTES);
+static __device__ __align__(256) unsigned char scratch[kFieldScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_at[kMaxDevices] = {};
+
+// The current device's copy of the array, looked up once per device (with
+// that device current).
+int field_scratch(double** out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LBM_EDEVICE, "fields_noalloc: device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_at[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(LBM_EDEVICE, "fields_noalloc: no address of the static scratch on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_at[dev] = p;
+    }
+    *out = (double*)g_scratch_at[dev];
+    return LBM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int lbm_fields_noalloc(lbm_ctx* c, double* rho, double* u)
+{
+    if (!c || !u) return fail(LBM_EINVAL, "NULL argument");
+    const size_t N = c->plan.N, D = c->plan.D;
+    const size_t need = sizeof(double) * (D + 1) * N;
+    if (need > kFieldScratchBytes)
+        return fail(LBM_EINVAL,
+                    "fields_noalloc: %zu cells need %zu bytes of staging, more than the %zu-byte static scratch "
+                    "(at most %zu cells in %zu-D); use lbm_fields",
+                    N, need, kFieldScratchBytes, kFieldScratchBytes / (sizeof(double) * (D + 1)), D);
+    double* sp = nullptr;
+    int rc = field_scratch(&sp);
+    if (rc) return rc;
+    rc = flush(c);
+    if (rc) return rc;
+    // every element of the staging is written before it is read: nothing to clear
+    launch_fields(c->cfg.lattice, c->cfg.precision, c->dm, (const int2*)(c->arena + c->plan.work1), c->plan.nb1,
+                  c->has_to, c->phase, c->stream, sp + D * N, sp);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(u, sp, sizeof(double) * D * N, hipMemcpyDeviceToHost));
+    if (rho) HIPCHK(hipMemcpy(rho, sp + D * N, sizeof(double) * N, hipMemcpyDeviceToHost));
+    return LBM_OK;
 }
 
 int lbm_get_populations(lbm_ctx* c, double* f)

@@ -695,12 +695,12 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? LBM_STEPT_WAVES : 2) void 
 // ---------------------------------------------------------------------------
 // Post-streaming density and velocity of the current state (stream only,
 // the SGS change of the last step included): used for WALE gradients and
-// lbm_fields.
+// lbm_fields.  rho_out and u_out (nullable): rho [N] and v [D][N] in double.
 // ---------------------------------------------------------------------------
 template <int LAT, typename T, int PREC, bool TO>
 __global__ __launch_bounds__(kBlock) void k_moments(const DevMember* __restrict__ mems,
                                                     const int2* __restrict__ work, int flip,
-                                                    double* __restrict__ rho_out)
+                                                    double* __restrict__ rho_out, double* __restrict__ u_out)
 {
     using L = Lat<LAT>;
     const int2 wk = work[blockIdx.x];
@@ -716,7 +716,11 @@ __global__ __launch_bounds__(kBlock) void k_moments(const DevMember* __restrict_
     moments<LAT, T, PREC>(f, drho, j);
     const T rho = T(1) + drho;
 #pragma unroll
-    for (int a = 0; a < L::D; ++a) ((T*)m.vn)[(size_t)a * N + cell] = j[a] / rho;
+    for (int a = 0; a < L::D; ++a) {
+        const T v = j[a] / rho;
+        ((T*)m.vn)[(size_t)a * N + cell] = v;
+        if (u_out) u_out[(size_t)a * N + cell] = (double)v;
+    }
     if (rho_out) rho_out[cell] = (double)rho;
 }
 
@@ -2668,10 +2672,10 @@ static void launch_step_group(const LaunchGroup& g, hipStream_t st, int flip, hi
     if (g.substrate == LBM_WALE) {
         if (g.mode == 2)
             hipLaunchKernelGGL((k_moments<LAT, T, PREC, true>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip,
-                               (double*)nullptr);
+                               (double*)nullptr, (double*)nullptr);
         else
             hipLaunchKernelGGL((k_moments<LAT, T, PREC, false>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip,
-                               (double*)nullptr);
+                               (double*)nullptr, (double*)nullptr);
     }
 #define LBM_STEP_T(SUB, TXV)                                                                               \
     do {                                                                                                   \
@@ -2838,14 +2842,15 @@ void launch_state(int op, int lattice, int precision, const DevMember* dm, int N
 }
 
 void launch_fields(int lattice, int precision, const DevMember* dm, const int2* work1, int nb1, bool has_to,
-                   int flip, hipStream_t st, double* rho_out)
+                   int flip, hipStream_t st, double* rho_out, double* u_out)
 {
     const int key = lattice * 3 + precision;
     const dim3 blk(kBlock), grd(nb1);
 #define LBM_MOM(LAT, T, PREC)                                                                                  \
     do {                                                                                                       \
-        if (has_to) hipLaunchKernelGGL((k_moments<LAT, T, PREC, true>), grd, blk, 0, st, dm, work1, flip, rho_out); \
-        else hipLaunchKernelGGL((k_moments<LAT, T, PREC, false>), grd, blk, 0, st, dm, work1, flip, rho_out);    \
+        if (has_to) hipLaunchKernelGGL((k_moments<LAT, T, PREC, true>), grd, blk, 0, st, dm, work1, flip, rho_out, \
+                                       u_out);                                                                   \
+        else hipLaunchKernelGGL((k_moments<LAT, T, PREC, false>), grd, blk, 0, st, dm, work1, flip, rho_out, u_out); \
     } while (0)
     switch (key) {
     case LBM_D2Q9 * 3 + LBM_FP32_SHIFTED: LBM_MOM(LBM_D2Q9, float, LBM_FP32_SHIFTED); break;

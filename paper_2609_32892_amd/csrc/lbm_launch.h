@@ -83,8 +83,10 @@ constexpr int kNumPhases = 6;
 void launch_step(const LaunchGroup& g, hipStream_t st, int flip, hipEvent_t* ev = nullptr);
 void launch_state(int op, int lattice, int precision, const DevMember* dm, int N, bool has_to, int flip,
                   hipStream_t st, const double* a, double* b);
+// Moments of the current state into vn, and (nullable) rho [N] and v [D][N]
+// in double into rho_out and u_out.
 void launch_fields(int lattice, int precision, const DevMember* dm, const int2* work1, int nb1, bool has_to,
-                   int flip, hipStream_t st, double* rho_out);
+                   int flip, hipStream_t st, double* rho_out, double* u_out = nullptr);
 // The pending SGS change of deferring members added to their current
 // populations g[parity ^ flip] and their records cleared (k_flush).
 void launch_flush(int lattice, int precision, const DevMember* dm, const int2* work1, int nb1, int flip,
