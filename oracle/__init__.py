@@ -27,6 +27,16 @@ FILT = {"I": 0, "B": 1, "B2": 2, "BMID": 3, "IMB": 4}
 KERNEL_FILT = {"G": 5, "L": 6}   # with a scale: "G3" is G_3, "L1" is L_1
 
 
+def set_threads(n: int) -> int:
+    """OpenMP threads of the oracle's cell loops; returns the count in effect."""
+    lib().orc_set_threads(int(n))
+    return int(lib().orc_get_threads())
+
+
+def threads() -> int:
+    return int(lib().orc_get_threads())
+
+
 def filter_code(name):
     """(code, scale, m) of a filter name: I, B, B2, BMID, IMB, G<s>, L<s>, or
     F<l>-<m> for the sharp Fourier band R_[l,m]."""
@@ -115,6 +125,11 @@ def lib():
         L.orc_set_closure.argtypes = [P, ct.POINTER(Closure), P, ct.c_long]
         L.orc_step.restype = I
         L.orc_step.argtypes = [P, ct.c_long]
+        L.orc_set_fp32_store.argtypes = [P, I]
+        L.orc_set_reverse_sums.argtypes = [P, I]
+        L.orc_set_reduced_form.argtypes = [P, I]
+        L.orc_set_threads.argtypes = [I]
+        L.orc_get_threads.restype = I
         L.orc_nrec.restype = ct.c_long
         L.orc_nrec.argtypes = [P]
         L.orc_get_recs.argtypes = [P, ct.c_long, ct.c_long, P]
@@ -256,6 +271,21 @@ class Oracle:
         if rc != 0:
             raise ValueError("oracle rejected the closure")
         return rc
+
+    def set_fp32_store(self, on=True):
+        """Diagnostic: round the stored state (populations as f - w, and v*)
+        to FP32 every step, all arithmetic still FP64 (the FP32 storage floor)."""
+        self.L.orc_set_fp32_store(self.h, 1 if on else 0)
+
+    def set_reverse_sums(self, on=True):
+        """Diagnostic: the TO step's global sums in reverse cell order (the
+        FP64 resolution of a closure against any other summation order)."""
+        self.L.orc_set_reverse_sums(self.h, 1 if on else 0)
+
+    def set_reduced_form(self, on=True):
+        """Diagnostic: the correction as sum_j (G^-1 dQ)_j V_j instead of the
+        literal patterns (equal in exact arithmetic)."""
+        self.L.orc_set_reduced_form(self.h, 1 if on else 0)
 
     def step(self, n=1):
         self.L.orc_step(self.h, n)

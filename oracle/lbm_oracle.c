@@ -35,6 +35,7 @@
  * depend on the OpenMP thread count.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -109,6 +110,9 @@ typedef struct {
     double *bandw;        /* nbands*ny */
     long step;
     orc_rec *recs; long nrec, caprec;
+    int fp32_store;       /* diagnostic: round the stored state to FP32 (see orc_set_fp32_store) */
+    int rev_sums;         /* diagnostic: global sums in reverse cell order (see orc_set_reverse_sums) */
+    int reduced;          /* diagnostic: the correction in its reduced form (see orc_set_reduced_form) */
 } Orc;
 
 /* ------------------------------------------------------------------ */
@@ -605,15 +609,19 @@ static void qoi_and_sens(const Orc *o, const orc_closure *cl, const double *bw,
         if (cl->kind[k] == 0) {
             apply_filter_b(o, cl->filt[k], cl->fs[k], cl->fm[k], v, r1, d);
             double s = 0;
-            for (long x = 0; x < N; x++)
+            for (long xi = 0; xi < N; xi++) {
+                const long x = o->rev_sums ? N - 1 - xi : xi;
                 for (int a = 0; a < d; a++) s += 0.5 * r1[a * N + x] * r1[a * N + x];
+            }
             q[k] = s;
             if (Vk) apply_filter_b(o, cl->filt[k], cl->fs[k], cl->fm[k], r1, Vk, d);
         } else if (cl->kind[k] == 1) {
             apply_filter_b(o, cl->filt[k], cl->fs[k], cl->fm[k], w, r1, nc);
             double s = 0;
-            for (long x = 0; x < N; x++)
+            for (long xi = 0; xi < N; xi++) {
+                const long x = o->rev_sums ? N - 1 - xi : xi;
                 for (int a = 0; a < nc; a++) s += 0.5 * r1[a * N + x] * r1[a * N + x];
+            }
             q[k] = s;
             if (Vk) {
                 apply_filter_b(o, cl->filt[k], cl->fs[k], cl->fm[k], r1, r2, nc);
@@ -622,7 +630,8 @@ static void qoi_and_sens(const Orc *o, const orc_closure *cl, const double *bw,
         } else {
             const double *wj = bw + (size_t)cl->band[k] * o->c.ny;
             double s = 0;
-            for (long x = 0; x < N; x++) {
+            for (long xi = 0; xi < N; xi++) {
+                const long x = o->rev_sums ? N - 1 - xi : xi;
                 int y = (int)((x / o->c.nx) % o->c.ny);
                 s += wj[y] * v[x];
             }
@@ -654,7 +663,10 @@ static double field_dot(const Orc *o, const double *a, const double *b)
 {
     double s = 0;
     const long n = (long)o->d * o->N;
-    for (long k = 0; k < n; k++) s += a[k] * b[k];
+    for (long ki = 0; ki < n; ki++) {
+        const long k = o->rev_sums ? n - 1 - ki : ki;
+        s += a[k] * b[k];
+    }
     return s;
 }
 
@@ -736,6 +748,28 @@ static int patterns(const Orc *o, int nq, const double *V, double *G, double *O,
             for (long x = 0; x < n; x++) Oi[x] += cij * Vj[x];
         }
         den[i] = field_dot(o, V + (size_t)i * n, Oi);
+    }
+    return 0;
+}
+
+/* The correction in its reduced form, equal to the literal patterns in
+ * exact arithmetic (pinned by the oracle tests): beta = G^-1 dQ,
+ * dv = sum_j beta_j V_j, gamma_k = dQ_k (G^-1)_kk.  Used only by the
+ * diagnostic of orc_set_reduced_form.  Returns 1 when G is singular. */
+static int reduced_correction(Orc *o, int nq, const double *V, const double *dq, double *gamma)
+{
+    const long n = (long)o->d * o->N;
+    double G[OQMAX * OQMAX], Gi[OQMAX * OQMAX];
+    for (int k = 0; k < nq; k++)
+        for (int l = 0; l < nq; l++)
+            G[k * nq + l] = field_dot(o, V + (size_t)k * n, V + (size_t)l * n);
+    if (gram_singular(G, nq) || invert(G, nq, Gi)) return 1;
+    for (int j = 0; j < nq; j++) {
+        double b = 0;
+        for (int k = 0; k < nq; k++) b += Gi[j * nq + k] * dq[k];
+        const double *Vj = V + (size_t)j * n;
+        for (long x = 0; x < n; x++) o->dv[x] += b * Vj[x];
+        gamma[j] = dq[j] * Gi[j * nq + j];
     }
     return 0;
 }
@@ -1032,6 +1066,7 @@ static void step_once(Orc *o)
         for (int a = 0; a < d; a++) {
             F[a] -= o->c.drag * o->rho[x] * o->v[a * N + x];
             o->vs[a * N + x] = o->v[a * N + x] + F[a] / o->rho[x];
+            if (o->fp32_store) o->vs[a * N + x] = (double)(float)o->vs[a * N + x];
         }
     }
 
@@ -1042,11 +1077,11 @@ static void step_once(Orc *o)
         double qs[OQMAX], G[OQMAX * OQMAX], den[OQMAX], dq[OQMAX];
         qoi_and_sens(o, &o->cl, o->bandw, o->vs, qs, o->V);
         closure_dq(o, qs, dq);
-        int sing = patterns(o, nq, o->V, G, o->O, den);
         rec.nq = nq;
         for (int k = 0; k < nq; k++) { rec.q[k] = qs[k]; rec.dq[k] = dq[k]; }
+        int sing = o->reduced ? reduced_correction(o, nq, o->V, dq, rec.gamma) : patterns(o, nq, o->V, G, o->O, den);
         if (sing) rec.flags |= 2;
-        else {
+        else if (!o->reduced) {
             for (int i = 0; i < nq; i++) {
                 double g = dq[i] / den[i];
                 rec.gamma[i] = g;
@@ -1070,6 +1105,8 @@ static void step_once(Orc *o)
             double fe = feq_one(o, i, o->rho[x], u);
             double fa = fi - (fi - fe) / o->taueff[x];
             o->fp[i * N + x] = fa + (feq_one(o, i, o->rho[x], uc) - fe);
+            if (o->fp32_store)
+                o->fp[i * N + x] = o->w[i] + (double)(float)(o->fp[i * N + x] - o->w[i]);
         }
     }
 
@@ -1081,6 +1118,28 @@ static void step_once(Orc *o)
     o->recs[o->nrec++] = rec;
     o->step++;
 }
+
+/* Diagnostic of the FP32 storage floor (not part of the method): with it on,
+ * the state is rounded to the nearest FP32 value where an FP32 run stores it
+ * -- the post-collision populations as deviations f - w from the lattice
+ * weights, and the predictor velocity v* before the TO step -- while all
+ * arithmetic stays FP64.  The difference to a plain FP64 run measures what
+ * FP32 storage alone costs. */
+void orc_set_fp32_store(void *h, int on) { ((Orc *)h)->fp32_store = on ? 1 : 0; }
+
+/* Diagnostic of the FP64 resolution of a closure (not part of the method):
+ * with it on, the global sums of the TO step (QoIs, Gram entries, pattern
+ * norms) run over the cells in reverse order.  Any implementation that sums
+ * in another order differs from the oracle by at least what this twin does;
+ * a near-singular Gram system amplifies that difference every step. */
+void orc_set_reverse_sums(void *h, int on) { ((Orc *)h)->rev_sums = on ? 1 : 0; }
+
+/* Diagnostic of the FP64 resolution of a closure (not part of the method):
+ * with it on, the correction is formed in its reduced form
+ * dv = sum_j (G^-1 dQ)_j V_j, gamma_k = dQ_k (G^-1)_kk instead of the literal
+ * patterns O_i and norms <V_i, O_i> -- the same value in exact arithmetic,
+ * different in its rounding when G is near-singular. */
+void orc_set_reduced_form(void *h, int on) { ((Orc *)h)->reduced = on ? 1 : 0; }
 
 int orc_step(void *h, long n)
 {
@@ -1105,6 +1164,11 @@ int orc_get_scale(void *h, double *s)
     memcpy(s, o->s, sizeof(double) * o->cl.nq);
     return 1;
 }
+
+/* OpenMP threads of the oracle's cell loops (its results do not depend on
+ * them: global sums are sequential). */
+void orc_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
+int orc_get_threads(void) { return omp_get_max_threads(); }
 
 int orc_sizeof_rec(void) { return (int)sizeof(orc_rec); }
 int orc_sizeof_closure(void) { return (int)sizeof(orc_closure); }

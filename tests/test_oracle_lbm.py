@@ -213,3 +213,35 @@ def test_diag_energy_enstrophy_closed_form(orc):
     assert abs(r["diag_e"][0] - E) < 1e-12 * E
     assert abs(r["diag_z"][0] - Z) < 1e-12 * Z
     assert abs(r["mass"][0] - N * N) < 1e-12 * N * N
+
+
+@pytest.mark.parametrize("lat", [0, 1])
+def test_fp32_store_diagnostic_rounds_only_the_stored_state(orc, lat):
+    """The FP32 storage diagnostic (used to measure the floor that FP32
+    storage alone sets): with it on, every stored deviation f - w of the
+    post-collision populations is an FP32 number, close to the unrounded
+    step; with it off the run is the plain FP64 one."""
+    if lat == 0:
+        cfg, u0 = synth.kolmogorov_workload(24, tau=0.6, seed=3)
+    else:
+        cfg, u0 = synth.channel_workload(10, 8, 6)
+    _, w = orc.lattice(lat)
+    a = orc.Oracle(**cfg)
+    a.init(u0)
+    a.set_fp32_store(True)
+    b = orc.Oracle(**cfg)
+    b.init(u0)
+    a.step(1)
+    b.step(1)
+    ga, gb = a.get_fp() - w[:, None], b.get_fp() - w[:, None]
+    assert np.array_equal(ga, ga.astype(np.float32).astype(np.float64))
+    # (v* is rounded too, before it enters the equilibrium, so a step moves by
+    # more than the final rounding alone, but only at the FP32 level)
+    assert np.max(np.abs(ga - gb)) <= 1e-6 * np.max(np.abs(gb))
+    assert not np.array_equal(ga, gb)
+    c = orc.Oracle(**cfg)
+    c.init(u0)
+    c.set_fp32_store(True)
+    c.set_fp32_store(False)
+    c.step(1)
+    assert np.array_equal(c.get_fp(), b.get_fp())

@@ -376,3 +376,51 @@ def test_oracle_deterministic_across_thread_counts(orc, tmp_path):
         subprocess.check_call([sys.executable, "-c", code, p], env=env)
         outs.append(np.load(p))
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_reverse_sums_diagnostic_changes_only_the_summation_order(orc):
+    """The reverse-order diagnostic (the FP64 resolution twin of the parity
+    tests): QoIs of a field whose every term and partial sum is exact agree
+    bitwise in both orders; on a general field they agree to rounding."""
+    import synth
+    cfg, _ = synth.channel_workload(10, 8, 6)
+    qois = synth.QOIS_3D
+    cl = orc.make_closure(qois, nbands=6, dmin=0.5, dmax=4.0)
+    o = orc.Oracle(**cfg)
+    rng = np.random.default_rng(3)
+    exact = rng.integers(-8, 9, size=(3, o.N)) * 2.0 ** -6      # dyadic: exact sums
+    general = rng.standard_normal((3, o.N))
+    for v, exact_sum in ((exact, True), (general, False)):
+        q0 = o.qoi(cl, v)[0]
+        o.set_reverse_sums(True)
+        q1 = o.qoi(cl, v)[0]
+        o.set_reverse_sums(False)
+        if exact_sum:   # dyadic fields, binomial filters and central differences: exact sums
+            assert np.array_equal(q0[:6], q1[:6])
+        assert np.allclose(q0, q1, rtol=1e-13, atol=0)
+
+
+def test_reduced_form_diagnostic_equals_the_literal_patterns(orc):
+    """The reduced-form diagnostic (sum_j (G^-1 dQ)_j V_j, gamma_k =
+    dQ_k (G^-1)_kk) is the literal correction of eq. O-from-V and
+    eq. tau-from-dQ-for-tracking in another exact form: on a well-conditioned
+    2-D closure the two runs agree to rounding over many steps, and their
+    records carry the same dQ at the first corrected step."""
+    import synth
+    cfg, _ = synth.kolmogorov_workload(24, tau=0.55, seed=4)
+    u0 = synth.turbulent_velocity_2d(24, 0.02, seed=4)
+    C, mu, S = synth.lrs_model(2, 3, 4, 5)
+    cl = dict(mode="lrs", spinup=2, C=C, mu=mu, Sigma=S, seed=9)
+    runs = []
+    for reduced in (False, True):
+        o = orc.Oracle(**cfg)
+        o.init(u0)
+        o.set_closure(orc.make_closure(synth.QOIS_2D, **cl))
+        o.set_reduced_form(reduced)
+        o.step(40)
+        runs.append(o)
+    ra, rb = runs[0].record_arrays(), runs[1].record_arrays()
+    assert np.array_equal(ra["dq"][2], rb["dq"][2]) and np.any(ra["dq"][2] != 0)
+    assert np.allclose(ra["gamma"], rb["gamma"], rtol=1e-10, atol=0)
+    va, vb = runs[0].velocity()[1], runs[1].velocity()[1]
+    assert np.max(np.abs(va - vb)) <= 1e-13 * np.max(np.abs(va))
