@@ -54,9 +54,11 @@ def test_fourier_lrs_parity(name, prec):
     assert np.array_equal(rg["flags"], ro["flags"])
     assert np.any(ro["dq"] != 0)
     if prec == "fp64":
-        assert ev <= 1e-11 and eq <= 1e-10 and edq <= 1e-7
+        assert ev <= 1e-12 and eq <= 1e-12 and edq <= 1e-10
     else:
-        assert ev <= 3e-5 and eq <= 1e-4 and edq <= 1e-2
+        # velocity: the stated 1e-5; q*, dQ about ten times the measured
+        # 1.6e-6 and 2.1e-6
+        assert ev <= 1e-5 and eq <= 2e-5 and edq <= 3e-5
 
 
 def test_fourier_member_in_batch_bitwise():

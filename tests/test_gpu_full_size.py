@@ -34,7 +34,8 @@ def test_channel_384x192x192_to_les_first_step():
     edq = np.max(np.abs(rg["dq"] - ro["dq"]) / np.abs(ro["dq"]))
     _say(f"  velocity {ev:.2e}  q {eq:.2e}  dq {edq:.2e}")
     assert np.array_equal(rg["flags"], ro["flags"]) and np.all(ro["dq"] != 0)
-    assert ev <= 3e-5 and eq <= 1e-4 and edq <= 1e-2
+    # velocity: the stated 1e-5; q* and dQ about ten times the measured 3.9e-8
+    assert ev <= 1e-5 and eq <= 5e-7 and edq <= 5e-7
 
 
 def test_fine_grid_480x240x240_plain():

@@ -70,12 +70,13 @@ def test_history_lrs_parity_2d_fp64_many_chunks():
     o.step(steps)
     ev, eq, edq, eg = _compare(run, o)
     _say(f"  velocity {ev:.2e}  q {eq:.2e}  dq {edq:.2e}  gamma {eg:.2e}")
-    assert ev <= 1e-11 and eq <= 1e-10 and edq <= 1e-8 and eg <= 1e-7
+    assert ev <= 1e-12 and eq <= 1e-12 and edq <= 1e-10 and eg <= 1e-10
 
 
 def test_history_lrs_parity_channel_fp32():
-    """The 12-QoI channel closure with h = 3 in FP32 (bars of the h = 0
-    channel parity test)."""
+    """The 12-QoI channel closure with h = 3 in FP32: velocity <= 1e-5 (the
+    stated bar); q*, dQ, gamma about ten times the measured 4.8e-6, 7.4e-5
+    and 1.2e-4."""
     lbm = need_gpu()
     cfg, u0, qois, cargs = _case3d(3, 8)
     _say("history channel fp32 h=3")
@@ -86,7 +87,7 @@ def test_history_lrs_parity_channel_fp32():
     o.step(60)
     ev, eq, edq, eg = _compare(run, o)
     _say(f"  velocity {ev:.2e}  q {eq:.2e}  dq {edq:.2e}  gamma {eg:.2e}")
-    assert ev <= 3e-5 and eq <= 1e-4 and edq <= 1e-2 and eg <= 1e-2
+    assert ev <= 1e-5 and eq <= 5e-5 and edq <= 1e-3 and eg <= 1e-3
 
 
 def test_zero_history_rows_bitwise_equal_h0():
@@ -173,7 +174,7 @@ def test_full_size_channel_h500_property():
         want = s * (X[n - h] @ C + eta) - q[n]
         err = np.max(np.abs(dq[n] - want) / s)
         _say(f"  step {n}: max |dQ - model| / s = {err:.2e}")
-        assert err <= 1e-11
+        assert err <= 1e-12
     assert np.all(dq[:S0] == 0)
 
 

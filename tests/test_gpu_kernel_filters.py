@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_util import gpu_run, need_gpu, oracle_run, rel_err
+from gpu_util import fp64_bars, gpu_run, need_gpu, oracle_floor, oracle_run, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -32,16 +32,6 @@ def _case(kind, mode="lrs", spinup=10):
                                dmax=dmax)
 
 
-def _oracle_floor(cfg, u0, qois, cargs, steps):
-    a = oracle_run(cfg, u0, qois, cargs)
-    a.step(steps)
-    up = u0 * (1 + 2.2e-16 * np.random.default_rng(0).choice([-1, 1], size=u0.shape))
-    b = oracle_run(cfg, up, qois, cargs)
-    b.step(steps)
-    ra, rb = a.record_arrays(), b.record_arrays()
-    return rel_err(b.velocity()[1], a.velocity()[1]), float(np.max(np.abs(ra["q"] - rb["q"]) / np.abs(ra["q"])))
-
-
 @pytest.mark.parametrize("kind,prec", [("2d", "fp64"), ("3d", "fp64"), ("3d", "fp32")])
 def test_kernel_filter_lrs_parity(kind, prec):
     lbm = need_gpu()
@@ -62,16 +52,17 @@ def test_kernel_filter_lrs_parity(kind, prec):
     assert np.array_equal(rg["flags"], ro["flags"])
     assert np.any(ro["dq"] != 0)
     if prec == "fp64":
-        # the channel Gram system amplifies last-bit differences: the bar is a
-        # multiple of the oracle's own spread under a 1-ulp change of the start.
-        # That change enters once; here the rounding differs at every filter
-        # application of every step (G_3 as three 1-D passes on the GPU, as
-        # one 2197-tap convolution in the oracle), hence 30 rather than 10.
-        fv, fq = _oracle_floor(cfg, u0, qois, cargs, steps) if kind == "3d" else (0.0, 0.0)
-        _say(f"  oracle 1-ulp floor: velocity {fv:.2e}  q {fq:.2e}")
-        assert ev <= max(1e-11, 30 * fv) and eq <= max(1e-10, 30 * fq) and edq <= 1e-7 and eg <= 1e-6
+        # the stated 1e-12, or ten times the workload's own FP64 resolution
+        # (the oracle against its twins: one ulp away, sums reversed) where
+        # the channel's near-singular Gram system makes that larger
+        floor = oracle_floor(cfg, u0, qois, cargs, steps, ref=o)
+        bars = fp64_bars(floor)
+        _say(f"  oracle floor: {np.array2string(floor, precision=2)}")
+        assert ev <= bars[0] and eq <= bars[1] and edq <= bars[2] and eg <= bars[3]
     else:
-        assert ev <= 3e-5 and eq <= 1e-4 and edq <= 1e-2 and eg <= 1e-2
+        # velocity: the stated 1e-5; q*, dQ, gamma: about ten times the
+        # measured 4.4e-5, 4.3e-4 and 3.9e-4
+        assert ev <= 1e-5 and eq <= 4e-4 and edq <= 5e-3 and eg <= 5e-3
 
 
 def test_kernel_filter_member_in_batch_bitwise():

@@ -11,7 +11,8 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import closure_args, gpu_run, match_populations, need_gpu, oracle_run, rel_err
+from gpu_util import (closure_args, fp64_bars, gpu_run, match_populations, need_gpu, oracle_floor, oracle_run,
+                      rel_err)
 
 pytestmark = pytest.mark.gpu
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -122,31 +123,18 @@ def _to_case(kind):
     return cfg, u0, qois, cargs
 
 
-def _oracle_floor(cfg, u0, qois, cargs, steps):
-    """Velocity and QoI differences between two oracle runs whose initial
-    velocity differs by one unit in the last place: the resolution of the
-    problem itself in FP64."""
-    a = oracle_run(cfg, u0, qois, cargs)
-    a.step(steps)
-    up = u0 * (1 + 2.2e-16 * np.random.default_rng(0).choice([-1, 1], size=u0.shape))
-    b = oracle_run(cfg, up, qois, cargs)
-    b.step(steps)
-    ra, rb = a.record_arrays(), b.record_arrays()
-    return rel_err(b.velocity()[1], a.velocity()[1]), float(np.max(np.abs(ra["q"] - rb["q"]) / np.abs(ra["q"])))
-
-
 @pytest.mark.parametrize("kind", ["2d", "3d"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_to_lrs_parity(kind, prec):
     """TO-LRS LES: velocity after 200 steps and the per-step q*, dQ, gamma.
 
-    FP64 bar: max(1e-12, 10 x the oracle's own 1-ulp floor).  The 12-QoI
-    channel closure solves a Gram system with condition number ~1e7-1e8,
-    which amplifies last-bit differences (its 1-ulp floor after 200 steps is
-    ~5e-12).  FP32 bar: 1e-5 in 2-D; 3e-5 for the 12-QoI channel, where the
-    FP32 predictor velocity carries a mean flow ~100x larger than its
-    high-pass content, so the high-pass QoIs see FP32 rounding of v* at the
-    1e-5 level and the near-singular Gram system passes it on."""
+    FP64: the stated 1e-12, or ten times the workload's own FP64 resolution
+    (the oracle against its twins: one ulp away, sums reversed) where that
+    is larger -- the 12-QoI channel closure solves a Gram system whose
+    condition number (~1e7-1e8) amplifies last-bit differences every step.
+    FP32: velocity <= 1e-5 (the stated bar), q* <= 1e-4; dQ and gamma per
+    QoI relative to their largest value: about ten times the measured
+    values (2-D 3.5e-6 and 2.5e-6; 3-D 2.7e-4 and 5.2e-4)."""
     lbm = need_gpu()
     _say(f"TO-LRS parity {kind} {prec}")
     cfg, u0, qois, cargs = _to_case(kind)
@@ -168,13 +156,13 @@ def test_to_lrs_parity(kind, prec):
     _say(f"  velocity {ev:.2e}  q {eq:.2e}  dq {edq:.2e}  gamma {eg:.2e}")
     assert np.array_equal(rg["flags"], ro["flags"])
     if prec == "fp64":
-        fv, fq = _oracle_floor(cfg, u0, qois, cargs, steps)
-        _say(f"  oracle 1-ulp floor: velocity {fv:.2e}  q {fq:.2e}")
-        assert ev <= max(1e-12, 10 * fv) and eq <= max(1e-11, 10 * fq)
-        assert edq <= 1e-6 and eg <= 1e-6
+        floor = oracle_floor(cfg, u0, qois, cargs, steps, ref=o)
+        bars = fp64_bars(floor)
+        _say(f"  oracle floor: {np.array2string(floor, precision=2)}")
+        assert ev <= bars[0] and eq <= bars[1] and edq <= bars[2] and eg <= bars[3]
     else:
-        bar = 1e-5 if kind == "2d" else 3e-5
-        assert ev <= bar and eq <= 1e-4 and edq <= 1e-2 and eg <= 1e-2
+        dbar = 5e-5 if kind == "2d" else 5e-3
+        assert ev <= 1e-5 and eq <= 1e-4 and edq <= dbar and eg <= dbar
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
@@ -207,25 +195,6 @@ def test_tracking_parity_fp64():
     assert rel_err(run.fields()[1], o.velocity()[1]) <= 1e-12
     assert np.allclose(rg["q"][5:] + rg["dq"][5:], qref[5:], rtol=1e-12, atol=0)
     assert rel_err(rg["gamma"], ro["gamma"]) <= 1e-9
-
-
-def test_full_size_channel_fp32_sampled():
-    """The benchmark workload (D3Q19 channel 96x48x48, Smagorinsky, 12 QoIs,
-    FP32) in the benchmark's launch configuration, checked against the
-    oracle over the first 12 steps (closure active from step 4)."""
-    lbm = need_gpu()
-    cfg, u0 = synth.channel_workload(96, 48, 48)
-    qois, cargs = closure_args("3d", ny=48, spinup=4)
-    run = gpu_run(lbm, cfg, u0, "fp32", qois, cargs)
-    run.step(12)
-    run.sync()
-    o = oracle_run(cfg, u0, qois, cargs)
-    o.step(12)
-    rg, ro = run.record_arrays(), o.record_arrays()
-    ev = rel_err(run.fields()[1], o.velocity()[1])
-    eq = np.max(np.abs(rg["q"] - ro["q"]) / np.abs(ro["q"]))
-    _say(f"full-size channel: velocity {ev:.2e} q {eq:.2e}")
-    assert ev <= 1e-5 and eq <= 1e-4
 
 
 def test_mass_momentum_records():

@@ -58,7 +58,8 @@ def test_project_qoi_matches_oracle(kind):
     qg = probe.record_arrays()["q"]
     err = np.max(np.abs(qg - qo) / np.abs(qo))
     _say(f"  max rel QoI error {err:.2e}")
-    assert err <= (1e-11 if prec == "fp64" else 1e-4)
+    # FP64: the stated 1e-12 (measured 1.2e-13); FP32: ten times the measured 1.2e-6
+    assert err <= (1e-12 if prec == "fp64" else 1e-5)
     assert np.all(probe.record_arrays()["dq"] == 0)
 
 
@@ -144,9 +145,9 @@ def test_bicubic_projection_matches_oracle(prec):
     ef = np.max(np.abs(got - want)) / np.max(np.abs(want))
     _say(f"  bicubic {prec}: QoIs {eq:.2e}, populations {ef:.2e}")
     if prec == "fp64":
-        assert eq <= 1e-11 and ef <= 1e-13
-    else:
-        assert eq <= 1e-4 and ef <= 1e-6
+        assert eq <= 1e-12 and ef <= 1e-13
+    else:   # about ten times the measured 4.5e-7 and 1.3e-10
+        assert eq <= 5e-6 and ef <= 1e-9
 
 
 def test_bicubic_projection_needs_a_periodic_2d_grid():
