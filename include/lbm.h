@@ -220,9 +220,15 @@ int lbm_init_velocity(lbm_ctx* ctx, const double* rho, const double* u);
  * closure must fit the workspace planned at creation (else LBM_ENOMEM). */
 int lbm_set_closure(lbm_ctx* ctx, const lbm_closure* closure);
 
-/* Enqueue nsteps LES steps on the context stream (non-blocking).  Repeated
- * chunks are replayed from a captured hipGraph. */
+/* Enqueue nsteps LES steps on the context stream (non-blocking).  Chunks of
+ * 32 steps, and the even part of a shorter remainder, are replayed from
+ * captured hipGraphs (cached by chunk length); a last odd step, and steps of
+ * closures with Fourier band QoIs (hipFFT), launch eagerly. */
 int lbm_step(lbm_ctx* ctx, long nsteps);
+/* Capture, without running anything, the graphs a following
+ * lbm_step(ctx, nsteps) replays, so that it pays no capture cost (timed
+ * regions).  Graphs are dropped when the closure or the state changes. */
+int lbm_step_prepare(lbm_ctx* ctx, long nsteps);
 int lbm_sync(lbm_ctx* ctx);             /* waits; LBM_EUNSTABLE if flagged */
 long lbm_step_count(const lbm_ctx* ctx);
 
@@ -339,15 +345,23 @@ void lbm_batch_destroy(lbm_batch* b);
  * Requests (a config, an optional closure and the initial velocity) queue
  * in arrival order.  lbm_server_advance admits every queued request whose
  * arrival time has passed while the sum of the admitted arenas stays within
- * the HBM budget (the server allocates and frees the arenas), advances all
- * admitted requests together as one batch for a chunk of steps (no request
- * runs past its own step count), and retires the finished ones.  Requests
- * join and leave between chunks, so their work overlaps on the device; each
- * request's result is bitwise the one it gets alone.  Times are seconds on
- * the clock of lbm_server_clock. */
+ * the HBM budget, advances all admitted requests together as one batch for a
+ * chunk of steps (no request runs past its own step count), and retires the
+ * finished ones.  Requests join and leave between chunks, so their work
+ * overlaps on the device; each request's result is bitwise the one it gets
+ * alone.  One chunk is in flight at a time: a call admits new arrivals while
+ * the previous chunk runs (their contexts are created and initialised on a
+ * second stream of the server), then waits for that chunk, retires, and
+ * enqueues the next chunk before it returns.  Arenas come from a pool keyed
+ * by size (a retired request's arena serves the next request of that size;
+ * cached arenas count against the budget and are freed when a request of
+ * another size needs the room).  A request that cannot start (larger than
+ * the budget, or a failed allocation) is retired at once with that status;
+ * the others go on.  Times are seconds on the clock of lbm_server_clock. */
 typedef struct {
     long id;
-    int status;                 /* LBM_OK, LBM_EUNSTABLE, or LBM_ENOMEM (larger than the budget) */
+    int status;                 /* LBM_OK, LBM_EUNSTABLE, or the status that kept it from starting
+                                   (LBM_ENOMEM: larger than the budget or no memory) */
     long steps;
     long cells;
     double t_arrival, t_admit, t_done;
@@ -357,14 +371,20 @@ double lbm_server_clock(void);
 /* hbm_budget: bytes for request arenas (0: 80% of the free device memory). */
 int lbm_server_create(size_t hbm_budget, void* stream, lbm_server** out);
 /* Copies everything it is given; keep_state retains the final state image
- * (lbm_get_state layout) for lbm_server_take_state. */
+ * (lbm_get_state layout) for lbm_server_take_state.  The config and closure
+ * are validated here (LBM_EINVAL, nothing queued), including an SPD Sigma
+ * for LRS closures and a spin-up covering a history model's length. */
 int lbm_server_submit(lbm_server* s, const lbm_config* cfg, const lbm_closure* closure, const double* u0,
                       long nsteps, double t_arrival, int keep_state, long* id);
-/* Admit, step at most max_chunk steps (0: 64), retire; synchronises. */
+/* Admit, account and retire the chunk in flight, enqueue the next chunk of at
+ * most max_chunk steps (0: 64) and return without waiting for it.  A caller
+ * loops until lbm_server_pending reads 0. */
 int lbm_server_advance(lbm_server* s, double now, long max_chunk, int* n_active);
 /* Move up to cap finished results into out (caller-owned). */
 int lbm_server_poll(lbm_server* s, lbm_result* out, int cap, int* n);
 int lbm_server_pending(const lbm_server* s);            /* queued + active requests */
+/* busy_s: device time of the chunks; lups: lattice updates done; used: bytes
+ * of active arenas; budget: the HBM budget. */
 int lbm_server_stats(const lbm_server* s, double* busy_s, double* lups, size_t* used, size_t* budget);
 size_t lbm_server_state_bytes(const lbm_server* s, long id);
 int lbm_server_take_state(lbm_server* s, long id, void* host, size_t bytes);

@@ -372,8 +372,10 @@ struct lbm_ctx {
     size_t chist_cap = 0;
     std::vector<int2> klev;        // kernel filters: (first job, job count) per launch level
     FourierProg fprog{};           // Fourier band QoIs (plans made at set_closure)
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    long gver[2] = {-1, -1};
+    // captured step graphs, keyed by chunk length, per starting phase; valid
+    // for launch parameters of version gver
+    std::map<int, hipGraphExec_t> gexec[2];
+    long gver = -1;
     int gchunk = 32;
     int mode() const { return cur.nq > 0 ? 2 : (cfg.diag ? 1 : 0); }
     // TO steps record the SGS change for the next step's pull (all
@@ -391,8 +393,7 @@ struct lbm_batch {
     int* dworkm = nullptr;
     std::vector<LaunchGroup> groups;
     int phase = 0;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    bool graph_ok[2] = {false, false};
+    std::map<int, hipGraphExec_t> gexec[2];   // captured step graphs by chunk length, per starting phase
     int gchunk = 16;
 };
 
@@ -466,10 +467,10 @@ int upload(lbm_ctx* c, void* dst, const void* src, size_t bytes)
 void drop_graphs(lbm_ctx* c)
 {
     for (int k = 0; k < 2; ++k) {
-        if (c->gexec[k]) hipGraphExecDestroy(c->gexec[k]);
-        c->gexec[k] = nullptr;
-        c->gver[k] = -1;
+        for (auto& kv : c->gexec[k]) hipGraphExecDestroy(kv.second);
+        c->gexec[k].clear();
     }
+    c->gver = -1;
 }
 
 // Fourier band QoIs: hipFFT plans (batched C2C / Z2Z over the components,
@@ -985,17 +986,8 @@ int lbm_create(const lbm_config* cfg, const lbm_closure* closure, void* dev_aren
     }
     // initial state rho = 1, v = 0
     if (!rc) {
-        std::vector<double> u((size_t)plan.D * plan.N, 0.0);
-        double* du = nullptr;
-        if (hipMalloc(&du, sizeof(double) * u.size()) != hipSuccess) rc = fail(LBM_ENOMEM, "staging allocation failed");
-        else {
-            rc = upload(c, du, u.data(), sizeof(double) * u.size());
-            if (!rc) {
-                launch_state(OP_INIT, cfg->lattice, cfg->precision, c->dm, plan.N, c->has_to, 0, c->stream, nullptr, du);
-                if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(LBM_EDEVICE, "init failed");
-            }
-            hipFree(du);
-        }
+        launch_state(OP_INIT, cfg->lattice, cfg->precision, c->dm, plan.N, c->has_to, 0, c->stream, nullptr, nullptr);
+        if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(LBM_EDEVICE, "init failed");
     }
     if (!rc && closure) rc = apply_closure(c, closure);
     if (rc) {
@@ -1023,6 +1015,28 @@ void lbm_destroy(lbm_ctx* c)
     delete c;
 }
 
+}  // extern "C"
+
+namespace {
+// The equilibrium state of density rho_dev [N] (NULL: 1) and velocity
+// u_dev [D][N] (device memory, double) on the context stream: nothing
+// pending, an empty record ring, step 0.
+int init_from_device(lbm_ctx* c, const double* rho_dev, const double* u_dev)
+{
+    int rc = clear_records(c);
+    if (rc) return rc;
+    c->phase = 0;
+    launch_state(OP_INIT, c->cfg.lattice, c->cfg.precision, c->dm, c->plan.N, c->has_to, 0, c->stream, rho_dev,
+                 (double*)u_dev);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(LBM_EDEVICE, "init kernel failed");
+    if (!rc) rc = reset_ctl(c);
+    c->version++;
+    return rc;
+}
+}  // namespace
+
+extern "C" {
+
 int lbm_init_velocity(lbm_ctx* c, const double* rho, const double* u)
 {
     if (!c || !u) return fail(LBM_EINVAL, "NULL argument");
@@ -1031,16 +1045,8 @@ int lbm_init_velocity(lbm_ctx* c, const double* rho, const double* u)
     HIPCHK(hipMalloc(&buf, sizeof(double) * (D + 1) * N));
     int rc = upload(c, buf, u, sizeof(double) * D * N);
     if (!rc && rho) rc = upload(c, buf + D * N, rho, sizeof(double) * N);
-    if (!rc) rc = clear_records(c);
-    if (!rc) {
-        c->phase = 0;
-        launch_state(OP_INIT, c->cfg.lattice, c->cfg.precision, c->dm, (int)N, c->has_to, 0, c->stream,
-                     rho ? buf + D * N : nullptr, buf);
-        if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(LBM_EDEVICE, "init kernel failed");
-    }
+    if (!rc) rc = init_from_device(c, rho ? buf + D * N : nullptr, buf);
     hipFree(buf);
-    if (!rc) rc = reset_ctl(c);
-    c->version++;
     return rc;
 }
 
@@ -1050,31 +1056,70 @@ int lbm_set_closure(lbm_ctx* c, const lbm_closure* cl)
     return apply_closure(c, cl);
 }
 
+// Steps run as replays of captured graphs: chunks of gchunk steps, and the
+// remainder as one chunk of its even part (so the phase a graph starts from is
+// unchanged after it); a last odd step, and steps with hipFFT work, launch
+// eagerly.
+static long graph_chunk(const lbm_ctx* c, long n)
+{
+    if (c->cur.nf) return 0;   // hipFFT runs outside graphs
+    const long len = n >= c->gchunk ? c->gchunk : (n & ~1L);
+    return len >= 2 ? len : 0;
+}
+
+// The graph of len steps from the current phase, captured if not cached.
+static int step_graph(lbm_ctx* c, int len, hipGraphExec_t* out)
+{
+    if (c->gver != c->version) drop_graphs(c);
+    c->gver = c->version;
+    auto& cache = c->gexec[c->phase];
+    auto it = cache.find(len);
+    if (it == cache.end()) {
+        hipGraphExec_t g = nullptr;
+        std::vector<LaunchGroup> gs{ctx_group(c)};
+        const int rc = capture(c->stream, gs, len, c->phase, &g);
+        if (rc) return rc;
+        it = cache.emplace(len, g).first;
+    }
+    *out = it->second;
+    return LBM_OK;
+}
+
 int lbm_step(lbm_ctx* c, long n)
 {
     if (!c || n < 0) return fail(LBM_EINVAL, "bad arguments");
     while (n > 0) {
-        if (n >= c->gchunk && !c->cur.nf) {   // hipFFT runs outside graphs
-            const int ph = c->phase;
-            if (!c->gexec[ph] || c->gver[ph] != c->version) {
-                if (c->gexec[ph]) hipGraphExecDestroy(c->gexec[ph]);
-                c->gexec[ph] = nullptr;
-                std::vector<LaunchGroup> gs{ctx_group(c)};
-                int rc = capture(c->stream, gs, c->gchunk, ph, &c->gexec[ph]);
-                if (rc) return rc;
-                c->gver[ph] = c->version;
-            }
-            HIPCHK(hipGraphLaunch(c->gexec[ph], c->stream));
-            if (c->defers()) c->pending = true;
-            n -= c->gchunk;
-            c->host_step += c->gchunk;
-            // gchunk is even: the phase is unchanged
-        } else {
-            int rc = enqueue_steps(c, n);
-            c->host_step += n;   // the steps were enqueued (and the phase advanced) even if one failed
+        const long len = graph_chunk(c, n);
+        if (len > 0) {
+            hipGraphExec_t g = nullptr;
+            int rc = step_graph(c, (int)len, &g);
             if (rc) return rc;
-            n = 0;
+            HIPCHK(hipGraphLaunch(g, c->stream));
+            if (c->defers()) c->pending = true;
+            n -= len;
+            c->host_step += len;
+            // len is even: the phase is unchanged
+        } else {
+            const long e = c->cur.nf ? n : 1;
+            int rc = enqueue_steps(c, e);
+            c->host_step += e;   // the steps were enqueued (and the phase advanced) even if one failed
+            if (rc) return rc;
+            n -= e;
         }
+    }
+    return LBM_OK;
+}
+
+int lbm_step_prepare(lbm_ctx* c, long n)
+{
+    if (!c || n < 0) return fail(LBM_EINVAL, "bad arguments");
+    while (n > 0) {
+        const long len = graph_chunk(c, n);
+        if (len == 0) break;   // the rest launches eagerly
+        hipGraphExec_t g = nullptr;
+        int rc = step_graph(c, (int)len, &g);
+        if (rc) return rc;
+        n -= len;
     }
     return LBM_OK;
 }
@@ -1398,9 +1443,8 @@ int lbm_set_state(lbm_ctx* c, const void* host, size_t bytes)
 static void batch_free_dev(lbm_batch* b)
 {
     for (int k = 0; k < 2; ++k) {
-        if (b->gexec[k]) hipGraphExecDestroy(b->gexec[k]);
-        b->gexec[k] = nullptr;
-        b->graph_ok[k] = false;
+        for (auto& kv : b->gexec[k]) hipGraphExecDestroy(kv.second);
+        b->gexec[k].clear();
     }
     if (b->dmem) hipFree(b->dmem);
     if (b->dwork) hipFree(b->dwork);
@@ -1564,16 +1608,22 @@ int lbm_batch_step(lbm_batch* b, long n)
     long done = 0;
     int rc = LBM_OK;
     while (done < n && !rc) {
-        if (n - done >= b->gchunk && !fft) {
+        // chunks of gchunk steps, then the even part of the rest, replayed
+        // from captured graphs; a last odd step launches eagerly
+        const long left = n - done;
+        const long len = fft ? 0 : (left >= b->gchunk ? b->gchunk : (left & ~1L));
+        if (len >= 2) {
             const int ph = b->phase;
-            if (!b->graph_ok[ph]) {
-                rc = capture(b->stream, b->groups, b->gchunk, ph, &b->gexec[ph]);
+            auto it = b->gexec[ph].find((int)len);
+            if (it == b->gexec[ph].end()) {
+                hipGraphExec_t g = nullptr;
+                rc = capture(b->stream, b->groups, (int)len, ph, &g);
                 if (rc) break;
-                b->graph_ok[ph] = true;
+                it = b->gexec[ph].emplace((int)len, g).first;
             }
-            const hipError_t e = hipGraphLaunch(b->gexec[ph], b->stream);
+            const hipError_t e = hipGraphLaunch(it->second, b->stream);
             if (e != hipSuccess) { rc = fail(LBM_EDEVICE, "graph launch failed: %s", hipGetErrorString(e)); break; }
-            done += b->gchunk;
+            done += len;
         } else {
             for (const LaunchGroup& g : b->groups) launch_step(g, b->stream, b->phase);
             b->phase ^= 1;
@@ -1735,10 +1785,19 @@ struct ServeReq {
 
 }  // namespace
 
+// The server steps its active requests as one batch on its stream, one chunk
+// in flight at a time: while the device runs a chunk, the host admits newly
+// arrived requests (their contexts are created and initialised on a second,
+// admission stream, then handed to the server stream), and only then waits
+// for the chunk, retires finished requests and enqueues the next chunk.
+// Arenas come from a pool keyed by size: a retired request's arena is kept
+// for the next request of the same size, so steady serving allocates
+// nothing; cached arenas count against the budget and are released when a
+// request of another size needs the room.
 struct lbm_server {
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr, adm = nullptr;
     bool own_stream = false;
-    size_t budget = 0, used = 0;
+    size_t budget = 0, used = 0, cached = 0;
     long next_id = 1;
     std::deque<ServeReq*> queue;
     std::vector<ServeReq*> active;
@@ -1746,19 +1805,97 @@ struct lbm_server {
     bool dirty = true;
     std::vector<lbm_result> results;
     std::map<long, std::vector<char>> states;
+    std::multimap<size_t, void*> pool;   // free arenas by size
+    double* stage = nullptr;             // device staging of initial velocities
+    size_t stage_bytes = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool inflight = false;               // a chunk is enqueued and not yet accounted
+    long inflight_chunk = 0;
+    std::vector<ServeReq*> inflight_reqs;
     long chunk_default = 64;
-    double busy = 0;   // seconds spent stepping
+    double busy = 0;   // device seconds spent stepping (events around each chunk)
     double lups = 0;   // lattice updates done
 };
 
 namespace {
 
+void* pool_take(lbm_server* s, size_t bytes)
+{
+    auto it = s->pool.find(bytes);
+    if (it != s->pool.end()) {
+        void* p = it->second;
+        s->pool.erase(it);
+        s->cached -= bytes;
+        return p;
+    }
+    while (!s->pool.empty() && s->used + s->cached + bytes > s->budget) {
+        auto big = std::prev(s->pool.end());
+        (void)hipFree(big->second);
+        s->cached -= big->first;
+        s->pool.erase(big);
+    }
+    void* p = nullptr;
+    return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+}
+
+void pool_put(lbm_server* s, void* p, size_t bytes)
+{
+    s->pool.emplace(bytes, p);
+    s->cached += bytes;
+}
+
 void server_release(lbm_server* s, ServeReq* r)
 {
     if (r->ctx) lbm_destroy(r->ctx);
-    if (r->arena) (void)hipFree(r->arena);
+    if (r->arena) pool_put(s, r->arena, r->bytes);
     s->used -= r->bytes;
     delete r;
+}
+
+void server_post(lbm_server* s, const ServeReq* r, int status, double now)
+{
+    lbm_result res{};
+    res.id = r->id;
+    res.status = status;
+    res.t_arrival = r->t_arr;
+    res.t_admit = now;
+    res.t_done = now;
+    res.cells = (long)r->cfg.nx * r->cfg.ny * r->cfg.nz;
+    s->results.push_back(res);
+}
+
+// A request's context on the admission stream: arena from the pool, the
+// closure, the initial state from the staged velocity; then its stream is
+// the server's.
+int server_start(lbm_server* s, ServeReq* r)
+{
+    r->arena = pool_take(s, r->bytes);
+    if (!r->arena) return fail(LBM_ENOMEM, "server: arena allocation failed");
+    int rc = lbm_create(&r->cfg, r->cl.get(), r->arena, r->bytes, s->adm, &r->ctx);
+    if (!rc) {
+        const size_t need = sizeof(double) * r->u0.size();
+        if (need > s->stage_bytes) {
+            HIPCHK(hipStreamSynchronize(s->adm));
+            if (s->stage) (void)hipFree(s->stage);
+            s->stage = nullptr;
+            s->stage_bytes = 0;
+            if (hipMalloc(&s->stage, need) != hipSuccess) rc = fail(LBM_ENOMEM, "server: staging allocation failed");
+            else s->stage_bytes = need;
+        }
+        if (!rc && hipMemcpyAsync(s->stage, r->u0.data(), need, hipMemcpyHostToDevice, s->adm) != hipSuccess)
+            rc = fail(LBM_EDEVICE, "server: initial state upload failed");
+        if (!rc) rc = init_from_device(r->ctx, nullptr, s->stage);
+    }
+    if (rc) {
+        if (r->ctx) lbm_destroy(r->ctx);
+        r->ctx = nullptr;
+        pool_put(s, r->arena, r->bytes);
+        r->arena = nullptr;
+        return rc;
+    }
+    r->ctx->stream = s->stream;
+    std::vector<double>().swap(r->u0);
+    return LBM_OK;
 }
 
 int server_admit(lbm_server* s, double now)
@@ -1767,29 +1904,16 @@ int server_admit(lbm_server* s, double now)
         ServeReq* r = s->queue.front();
         if (r->t_arr > now) break;
         if (s->used + r->bytes > s->budget && !s->active.empty()) break;  // wait for memory
-        if (s->used + r->bytes > s->budget) {
-            // larger than the whole budget: reject
-            s->queue.pop_front();
-            lbm_result res{};
-            res.id = r->id;
-            res.status = LBM_ENOMEM;
-            res.t_arrival = r->t_arr;
-            res.t_admit = now;
-            res.t_done = now;
-            s->results.push_back(res);
+        s->queue.pop_front();
+        // larger than the whole budget, or failing to start: a result with
+        // its status, and admission goes on
+        int rc = s->used + r->bytes > s->budget ? fail(LBM_ENOMEM, "server: request %ld exceeds the budget", r->id)
+                                                : server_start(s, r);
+        if (rc) {
+            server_post(s, r, rc, now);
             delete r;
             continue;
         }
-        if (hipMalloc(&r->arena, r->bytes) != hipSuccess) return fail(LBM_ENOMEM, "server: arena allocation failed");
-        int rc = lbm_create(&r->cfg, r->cl.get(), r->arena, r->bytes, s->stream, &r->ctx);
-        if (!rc) rc = lbm_init_velocity(r->ctx, nullptr, r->u0.data());
-        if (rc) {
-            (void)hipFree(r->arena);
-            r->arena = nullptr;
-            return rc;
-        }
-        std::vector<double>().swap(r->u0);
-        s->queue.pop_front();
         s->used += r->bytes;
         r->t_adm = server_clock_now();
         s->active.push_back(r);
@@ -1824,6 +1948,40 @@ int server_retire(lbm_server* s)
     return LBM_OK;
 }
 
+// Account and retire the chunk in flight (waits for it).
+int server_finish_chunk(lbm_server* s)
+{
+    if (!s->inflight) return LBM_OK;
+    HIPCHK(hipEventSynchronize(s->ev1));
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, s->ev0, s->ev1) == hipSuccess) s->busy += ms * 1e-3;
+    const double t1 = server_clock_now();
+    for (ServeReq* r : s->inflight_reqs) {
+        r->done += s->inflight_chunk;
+        s->lups += (double)s->inflight_chunk * r->cfg.nx * r->cfg.ny * r->cfg.nz;
+        if (r->done >= r->nsteps) r->t_done = t1;
+    }
+    s->inflight = false;
+    s->inflight_reqs.clear();
+    return server_retire(s);
+}
+
+// Validation of a request's closure that its creation would otherwise meet
+// only at admission: an SPD Sigma (LRS) and a spin-up that covers the
+// history (a request starts at step 0).
+int check_request_closure(const lbm_closure* cl)
+{
+    if (!cl) return LBM_OK;
+    if (cl->mode == LBM_CLOSURE_LRS) {
+        double L[LBM_MAX_QOI * LBM_MAX_QOI];
+        if (!cl->Sigma || !cholesky_host(cl->Sigma, cl->nq, L, LBM_MAX_QOI))
+            return fail(LBM_EINVAL, "server: closure Sigma is not SPD");
+    }
+    if (cl->h > 0 && cl->spinup < cl->h)
+        return fail(LBM_EINVAL, "server: closure spinup must be at least the history length");
+    return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1835,17 +1993,25 @@ int lbm_server_create(size_t hbm_budget, void* stream, lbm_server** out)
     if (!out) return fail(LBM_EINVAL, "out is NULL");
     lbm_server* s = new lbm_server();
     s->stream = (hipStream_t)stream;
+    bool ok = true;
     if (!s->stream) {
-        if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
-            delete s;
-            return fail(LBM_EDEVICE, "stream creation failed");
-        }
-        s->own_stream = true;
+        ok = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
+        s->own_stream = ok;
     }
-    if (hbm_budget == 0) {
+    ok = ok && hipStreamCreateWithFlags(&s->adm, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreate(&s->ev0) == hipSuccess && hipEventCreate(&s->ev1) == hipSuccess;
+    if (ok && hbm_budget == 0) {
         size_t fr = 0, tot = 0;
-        if (hipMemGetInfo(&fr, &tot) != hipSuccess) { delete s; return fail(LBM_EDEVICE, "hipMemGetInfo failed"); }
+        ok = hipMemGetInfo(&fr, &tot) == hipSuccess;
         hbm_budget = (size_t)(0.8 * (double)fr);
+    }
+    if (!ok) {
+        if (s->ev0) (void)hipEventDestroy(s->ev0);
+        if (s->ev1) (void)hipEventDestroy(s->ev1);
+        if (s->adm) (void)hipStreamDestroy(s->adm);
+        if (s->own_stream) (void)hipStreamDestroy(s->stream);
+        delete s;
+        return fail(LBM_EDEVICE, "server: stream, event or memory query failed");
     }
     s->budget = hbm_budget;
     *out = s;
@@ -1858,6 +2024,8 @@ int lbm_server_submit(lbm_server* s, const lbm_config* cfg, const lbm_closure* c
     if (!s || !cfg || !u0 || nsteps < 1) return fail(LBM_EINVAL, "bad arguments");
     const size_t bytes = lbm_required_bytes(cfg, cl);
     if (!bytes) return LBM_EINVAL;  // message set by the validation
+    int rc = check_request_closure(cl);
+    if (rc) return rc;
     ServeReq* r = new ServeReq();
     r->id = s->next_id++;
     r->cfg = *cfg;
@@ -1879,7 +2047,10 @@ int lbm_server_submit(lbm_server* s, const lbm_config* cfg, const lbm_closure* c
 int lbm_server_advance(lbm_server* s, double now, long max_chunk, int* n_active)
 {
     if (!s) return fail(LBM_EINVAL, "NULL server");
+    // admission overlaps the chunk in flight
     int rc = server_admit(s, now);
+    if (rc) return rc;
+    rc = server_finish_chunk(s);
     if (rc) return rc;
     if (n_active) *n_active = (int)s->active.size();
     if (s->active.empty()) return LBM_OK;
@@ -1894,20 +2065,14 @@ int lbm_server_advance(lbm_server* s, double now, long max_chunk, int* n_active)
         if (rc) return rc;
         s->dirty = false;
     }
-    const double t0 = server_clock_now();
+    HIPCHK(hipEventRecord(s->ev0, s->stream));
     rc = lbm_batch_step(s->batch, chunk);
     if (rc) return rc;
-    HIPCHK(hipStreamSynchronize(s->stream));
-    const double t1 = server_clock_now();
-    s->busy += t1 - t0;
-    for (ServeReq* r : s->active) {
-        r->done += chunk;
-        s->lups += (double)chunk * r->cfg.nx * r->cfg.ny * r->cfg.nz;
-        if (r->done >= r->nsteps) r->t_done = t1;
-    }
-    rc = server_retire(s);
-    if (n_active) *n_active = (int)s->active.size();
-    return rc;
+    HIPCHK(hipEventRecord(s->ev1, s->stream));
+    s->inflight = true;
+    s->inflight_chunk = chunk;
+    s->inflight_reqs = s->active;
+    return LBM_OK;
 }
 
 int lbm_server_poll(lbm_server* s, lbm_result* out, int cap, int* n)
@@ -1954,9 +2119,15 @@ void lbm_server_destroy(lbm_server* s)
 {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
+    (void)hipStreamSynchronize(s->adm);
     if (s->batch) lbm_batch_destroy(s->batch);
     for (ServeReq* r : s->active) server_release(s, r);
     for (ServeReq* r : s->queue) delete r;
+    for (auto& kv : s->pool) (void)hipFree(kv.second);
+    if (s->stage) (void)hipFree(s->stage);
+    (void)hipEventDestroy(s->ev0);
+    (void)hipEventDestroy(s->ev1);
+    (void)hipStreamDestroy(s->adm);
     if (s->own_stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }

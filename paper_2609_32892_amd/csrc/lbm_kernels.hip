@@ -2393,7 +2393,7 @@ __global__ void k_init(const DevMember* __restrict__ mems, int flip, const doubl
     T* g = (T*)m.g[m.parity ^ flip];
     const double r = rho0 ? rho0[cell] : 1.0;
     double u[3] = {0, 0, 0}, uu = 0;
-    for (int a = 0; a < L::D; ++a) { u[a] = u0[(size_t)a * N + cell]; uu += u[a] * u[a]; }
+    for (int a = 0; a < L::D; ++a) { u[a] = u0 ? u0[(size_t)a * N + cell] : 0.0; uu += u[a] * u[a]; }
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         const double cu = L::cx[i] * u[0] + L::cy[i] * u[1] + L::cz[i] * u[2];

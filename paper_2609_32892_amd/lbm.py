@@ -87,7 +87,8 @@ class Result(ct.Structure):
 #: symbols declared in include/lbm.h
 EXPORTS = [
     "lbm_last_error", "lbm_version", "lbm_lattice_info", "lbm_required_bytes", "lbm_create",
-    "lbm_destroy", "lbm_init_velocity", "lbm_set_closure", "lbm_step", "lbm_sync", "lbm_step_count",
+    "lbm_destroy", "lbm_init_velocity", "lbm_set_closure", "lbm_step", "lbm_step_prepare", "lbm_sync",
+    "lbm_step_count",
     "lbm_qoi", "lbm_fields", "lbm_fields_noalloc", "lbm_get_populations", "lbm_set_populations", "lbm_stream_only",
     "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_batch_create", "lbm_batch_step",
     "lbm_batch_sync", "lbm_batch_destroy", "lbm_profile_phases", "lbm_test_philox", "lbm_test_normals",
@@ -121,6 +122,7 @@ def lib():
         L.lbm_init_velocity.argtypes = [P, P, P]
         L.lbm_set_closure.argtypes = [P, ct.POINTER(Closure)]
         L.lbm_step.argtypes = [P, ct.c_long]
+        L.lbm_step_prepare.argtypes = [P, ct.c_long]
         L.lbm_sync.argtypes = [P]
         L.lbm_step_count.restype = ct.c_long
         L.lbm_step_count.argtypes = [P]
@@ -360,6 +362,10 @@ class Run:
 
     def step(self, n=1):
         check(self.L.lbm_step(self.h, n))
+
+    def prepare(self, n):
+        """Capture the graphs step(n) will replay (nothing runs)."""
+        check(self.L.lbm_step_prepare(self.h, n))
 
     def sync(self):
         return check(self.L.lbm_sync(self.h))
