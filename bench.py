@@ -6,12 +6,20 @@ Default workload: the D3Q19 turbulent-channel TO-LES, 96x48x48 fluid nodes
 populations with FP64 reductions, Smagorinsky substrate Cs = 0.1, 12 QoIs
 ({E, Z} x {B^2, B - B^2, I - B} + 6 mean-profile bands), h = 0 LRS closure
 switched on at step 2500, 10000 steps.  Inputs are synthetic and seeded.
+The timed steps replay captured graphs (captured before the timed region).
 
 Prints one JSON line with the contract fields plus
-  roofline:     the dominant kernel's achieved algorithmic bandwidth, timed
-                live with HIP events on the stream it runs on;
-  cpu_baseline: the FP64 CPU oracle timed on a bounded sample of the same
-                workload on the host cores.
+  roofline:        the whole step against the HBM roofline on the fixed
+                   algorithmic bytes per lattice update (232 B/LUP), with the
+                   HBM bytes per step the counters measured (traffic) and
+                   their ratio to the algorithmic bytes (traffic_ratio);
+  dominant_kernel: the kernel phase with the largest share of the step, its
+                   achieved algorithmic bandwidth per launch timed live with
+                   HIP events on the stream it runs on;
+  cpu_baseline:    the FP64 CPU oracle timed on a bounded sample of the same
+                   workload on the host cores (and on one core);
+  system_forms:    the HBM-resident 384x192x192 scale-up, the precision,
+                   batched and served forms and the other comparisons.
 """
 from __future__ import annotations
 
@@ -86,22 +94,25 @@ def phase_bytes(w, ms, launches):
         jv = max([2 * deg[f] for k, f, _ in w["qois"] if k == "E"] + [0])
         jw = max([2 * deg[f] for k, f, _ in w["qois"] if k == "Z"] + [0])
         has_z = any(k == "Z" for k, _, _ in w["qois"])
-    npass = max(jv, jw + 1 if has_z else 0)
+    npass = max(jv, max(jw, 1) if has_z else 0)
     binom = 0
     for j in range(1, npass + 1):
-        dov, dow, doc = j <= jv, has_z and j <= jw, has_z and j - 1 <= jw
-        binom += (d if dov else 0) * 2 + (nc if doc else 0) + (nc if dow else 0) + (d if doc else 0)
+        dov, dow = j <= jv, has_z and j <= jw
+        if j == 1:   # v* in; B v*, w and (jw >= 1) B w, curl^T w out
+            binom += d + (d if dov else 0) + (nc if has_z else 0) + ((nc + d) if dow else 0)
+        else:        # B^(j-1) v, B^(j-1) w in; B^j v, B^j w, curl^T B^(j-1) w out
+            binom += (d if dov else 0) * 2 + (nc if dow else 0) * 2 + (d if dow else 0)
     binom = binom / npass if npass else 0
     wz = (min(jw, 2) + 1) * nc if has_z else 0   # W_0..W_2 read for the Z QoI densities
-    cz = (jw + 1) * d if has_z else 0             # C_0..C_jw
+    cz = jw * d + nc if has_z else 0             # C_0..C_jw-1, and W_jw for the top curl
     per_cell = {
-        # populations in and out, rho and v* out
-        "stream_collide": e * (2 * Q + (1 + d if to else 0)),
-        "curl": e * (d + nc),
+        # populations in and out, rho and v* out, and the SGS record (2d) in
+        "stream_collide": e * (2 * Q + ((1 + d) + 2 * d if to else 0)),
+        "curl": 0,
         "binomial": e * binom,
         "reduce": e * (d + jv * d + wz + cz),
-        # v*, P_j, C_j and rho in; the populations read and written in place
-        "apply": e * (d + jv * d + cz + 1 + 2 * Q),
+        # v*, P_j, C_j, W_jw and rho in; the record (rho dv, 2 v* + dv) out
+        "apply": e * (d + jv * d + cz + 1 + 2 * d),
         "solve": 0,
     }
     return {k: per_cell[k] * N for k in per_cell}
@@ -111,11 +122,10 @@ KERNEL_SYMBOL = {"stream_collide": "k_step", "curl": "k_curl", "binomial": "k_bi
                  "solve": "k_solve", "apply": "k_apply"}
 
 
-def measured_traffic(workload_name, phase):
-    """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, scaled by the copy-kernel
-    calibration; None if there is none for this kernel or the kernel source
-    has changed since the counters were taken."""
+def _profile_kv(workload_name):
+    """Key-value lines of the committed rocprofv3 counter summary of a
+    workload, or None when there is none or the kernel sources have changed
+    since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"{workload_name}_hbm_traffic.txt")
     srcs = [os.path.join(ROOT, "paper_2609_32892_amd", "csrc", f) for f in ("lbm_kernels.hip", "lbm_api.hip")]
@@ -127,10 +137,68 @@ def measured_traffic(workload_name, phase):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in srcs)).hexdigest()
-    key = f"{KERNEL_SYMBOL[phase]}_bytes_per_launch"
-    if kv.get("kernel_source_sha256") != sha or key not in kv:
+    return kv if kv.get("kernel_source_sha256") == sha else None
+
+
+def measured_traffic(workload_name, phase=None):
+    """HBM bytes from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary,
+    scaled by the copy-kernel calibration: per step of the whole TO step
+    (phase None) or per launch of one phase's kernel; None if not measured
+    for the current sources."""
+    kv = _profile_kv(workload_name)
+    if kv is None:
         return None
-    return float(kv[key])
+    key = "bytes_per_step" if phase is None else f"{KERNEL_SYMBOL[phase]}_bytes_per_launch"
+    return float(kv[key]) if key in kv else None
+
+
+def step_roofline(w, mlups, workload_name):
+    """The whole TO step against the HBM roofline on the fixed algorithmic
+    bytes per lattice update (232 B/LUP for the D3Q19 FP32 TO-LES: 152 B of
+    populations, 16 B of rho and v* written, 28 B of rho, v*, dv read at the
+    next pull, 12 B of v* read twice and 12 B of dv written), with the HBM
+    bytes per step the counters measured and their ratio to those bytes."""
+    cfg = w["cfg"]
+    N = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    achieved = mlups * 1e6 * w["b_alg"] / 1e9
+    traffic = measured_traffic(workload_name)
+    return {"bound": "hbm", "kernel": "whole step (every kernel of one step)", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "b_alg_bytes_per_lup": w["b_alg"],
+            "traffic": None if traffic is None else round(traffic),
+            "traffic_ratio": None if traffic is None else round(traffic / (w["b_alg"] * N), 3)}
+
+
+def dominant_kernel(w, ms, nl, workload_name):
+    """The kernel phase with the largest share of the step: its achieved
+    algorithmic bandwidth per launch from the live per-phase event timing,
+    and the HBM bytes per launch the counters measured."""
+    bytes_per_launch = phase_bytes(w, ms, nl)
+    dom = max((k for k in ms if nl[k] > 0), key=lambda k: ms[k])
+    dur_ms = ms[dom] / nl[dom]
+    achieved = bytes_per_launch[dom] / (dur_ms * 1e-3) / 1e9
+    traffic = measured_traffic(workload_name, dom)
+    return {"kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_launch_us": round(dur_ms * 1e3, 2),
+            "bytes_per_launch": bytes_per_launch[dom], "traffic": None if traffic is None else round(traffic)}
+
+
+def timed_steps(run, K):
+    """K steps of a run after its graphs are captured: host clock and HIP
+    events on the run's own stream around the same region."""
+    import torch
+    run.prepare(K)
+    run.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(run.stream)
+    run.step(K)
+    e1.record(run.stream)
+    status = run.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt, e0.elapsed_time(e1) * 1e-3, status
 
 
 def kolmogorov_member(lbm, n, ic_seed, noise_seed, spinup, precision="fp32"):
@@ -417,14 +485,16 @@ def form_batched(lbm, nmem, steps):
     return res
 
 
-def form_served(lbm, nreq, rate, steps, budget=0):
+def form_served(lbm, nreq, rate, steps, budget=0, sequential=True, sample_every=25):
     """System form (5): continuous-batching server on a Poisson trace of mixed
-    2-D/3-D TO-LES requests; latency = completion - arrival."""
+    2-D/3-D TO-LES requests (latency = completion - arrival), and the same
+    requests run one after another, each alone, as the sequential baseline;
+    every sample_every-th request's final state is compared bitwise between
+    the two."""
+    import hashlib
     import numpy as np
     import synth
     trace = synth.serve_trace(nreq, rate, steps=steps)
-    srv = lbm.Server(hbm_budget=budget)
-    t0 = srv.clock() + 0.05
     reqs = []
     for q in trace:
         if q["kind"] == "2d":
@@ -432,13 +502,16 @@ def form_served(lbm, nreq, rate, steps, budget=0):
         else:
             cfg, spec, u0 = channel_request(lbm, q["m"], q["seed"], spinup=steps // 4)
         reqs.append((cfg, spec, u0, q["t"]))
+    sample = set(range(0, len(reqs), sample_every)) if sequential else set()
+    srv = lbm.Server(hbm_budget=budget)
+    t0 = srv.clock() + 0.05
     # submit as arrivals happen; advance the server in between
-    results, k = [], 0
+    results, k, ids = [], 0, {}
     while k < len(reqs) or srv.pending() > 0:
         now = srv.clock()
         while k < len(reqs) and t0 + reqs[k][3] <= now:
             cfg, spec, u0, ta = reqs[k]
-            srv.submit(cfg, spec, u0, steps, t0 + ta)
+            ids[k] = srv.submit(cfg, spec, u0, steps, t0 + ta, keep_state=k in sample)
             k += 1
         if srv.pending() > 0:
             srv.advance(srv.clock(), 64)
@@ -449,13 +522,32 @@ def form_served(lbm, nreq, rate, steps, budget=0):
     span = max(r.t_done for r in results) - t0
     st = srv.stats()
     ok = sum(1 for r in results if r.status == 0)
+    images = {j: srv.take_state(ids[j]) for j in sample}
     srv.close()
-    return {"requests": len(results), "completed_ok": ok, "rate_per_s": rate, "steps": steps,
-            "p50_latency_s": round(float(np.percentile(lat, 50)), 3),
-            "p99_latency_s": round(float(np.percentile(lat, 99)), 3),
-            "aggregate_mlups": round(st["lups"] / span / 1e6, 1),
-            "busy_mlups": round(st["lups"] / st["busy_s"] / 1e6, 1),
-            "budget_gb": round(st["budget"] / 1e9, 2)}
+    out = {"requests": len(results), "completed_ok": ok, "rate_per_s": rate, "steps": steps,
+           "p50_latency_s": round(float(np.percentile(lat, 50)), 3),
+           "p99_latency_s": round(float(np.percentile(lat, 99)), 3),
+           "aggregate_mlups": round(st["lups"] / span / 1e6, 1),
+           "busy_mlups": round(st["lups"] / st["busy_s"] / 1e6, 1),
+           "span_s": round(span, 2), "budget_gb": round(st["budget"] / 1e9, 2)}
+    if sequential:
+        lups, same = 0.0, True
+        t = time.perf_counter()
+        for j, (cfg, spec, u0, _) in enumerate(reqs):
+            r = lbm.Run(cfg, spec)
+            r.init_velocity(u0)
+            r.step(steps)
+            r.sync()
+            lups += r.N * steps
+            if j in sample:
+                same = same and hashlib.sha256(r.get_state()).digest() == hashlib.sha256(images[j]).digest()
+            r.close()
+        ts = time.perf_counter() - t
+        out["sequential_mlups"] = round(lups / ts / 1e6, 1)
+        out["sequential_s"] = round(ts, 2)
+        out["served_over_sequential"] = round(out["aggregate_mlups"] / out["sequential_mlups"], 3)
+        out["bitwise_equal_to_solo"] = {"sampled": len(sample), "equal": bool(same)}
+    return out
 
 
 def form_fine(lbm, steps):
@@ -571,6 +663,71 @@ def form_hf_lf_kolmogorov(lbm, hf_steps, m=5):
     return out
 
 
+def form_large(lbm, steps):
+    """The HBM-resident scale-up of the headline (384 x 192 x 192, the same
+    physics per cell; about 2.5 GB of state): MLUPS over a timed stretch
+    after warm-up, the whole step against the HBM roofline on 232 B/LUP with
+    the counters' HBM bytes per step, and the dominant kernel."""
+    w = workload("channel_large")
+    cfg = w["cfg"]
+    N = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    spec = lbm.ClosureSpec(w["qois"], **dict(w["cargs"], spinup=10))
+    r = lbm.Run(lbm.make_config(precision=w["precision"], **cfg), spec)
+    r.init_velocity(w["u0"])
+    r.step(20)
+    r.sync()
+    dt, dt_ev, status = timed_steps(r, steps)
+    ms, nl = r.profile_phases(20)
+    r.close()
+    mlups = N * steps / dt / 1e6
+    return {"grid": [cfg["nx"], cfg["ny"], cfg["nz"]], "cells": N, "steps": steps, "status": status,
+            "mlups": round(mlups, 1), "ms_per_step": round(dt / steps * 1e3, 4),
+            "ms_per_step_events": round(dt_ev / steps * 1e3, 4),
+            "roofline": step_roofline(w, mlups, "channel_large"),
+            "dominant_kernel": dominant_kernel(w, ms, nl, "channel_large"),
+            "phases": {k: {"ms_per_step": round(ms[k], 4), "launches": nl[k]} for k in ms}}
+
+
+def cpu_baseline(w, seconds):
+    """The FP64 oracle on the host's cores on a bounded sample of the same
+    workload (its first steps: same grid, closure and inputs), once on every
+    core OpenMP uses and once on one core, scaled to MLUPS."""
+    import oracle
+    cfg = w["cfg"]
+    N = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    out = {}
+    for label, nthreads in (("all", oracle.threads()), ("one", 1)):
+        cores = oracle.set_threads(nthreads)
+        o = oracle.Oracle(**cfg)
+        o.init(w["u0"])
+        if w["qois"] is not None:
+            o.set_closure(oracle.make_closure(w["qois"], **w["cargs"]))
+        t = time.perf_counter()
+        o.step(1)
+        one = time.perf_counter() - t
+        n = max(1, min(2000, int(seconds / 2 / max(one, 1e-6))))
+        t = time.perf_counter()
+        o.step(n)
+        tc = time.perf_counter() - t
+        out[label] = dict(value=round(N * n / tc / 1e6, 4), cores=cores, steps=n, seconds=round(tc, 1))
+        del o
+    oracle.set_threads(out["all"]["cores"])
+    return {"value": out["all"]["value"], "unit": "MLUPS", "cores": out["all"]["cores"], "kind": "oracle",
+            "sample": f"steps 2..{out['all']['steps'] + 1} of the same workload (same grid, closure, inputs), "
+                      f"{out['all']['seconds']} s on {out['all']['cores']} threads",
+            "one_core": {"value": out["one"]["value"], "unit": "MLUPS", "cores": 1,
+                         "sample": f"steps 2..{out['one']['steps'] + 1}, {out['one']['seconds']} s"},
+            "cpu_model": model}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -582,7 +739,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-system-forms", action="store_true",
                     help="skip the precision / batched / served / fine-grid comparisons")
-    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--ensemble-steps", type=int, default=200)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of this many MiB (calibrates HBM byte counters)")
@@ -626,30 +783,17 @@ def main():
     run = make_run()
     run.step(W)
     run.sync()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run.step(K)
-    status = run.sync()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    dt = t1 - t0
+    dt, dt_ev, status = timed_steps(run, K)
     mlups = N * K / dt / 1e6
-    print(f"[bench] {args.workload}: {K} steps in {dt:.3f} s -> {mlups:.1f} MLUPS (status {status})",
-          file=sys.stderr, flush=True)
+    print(f"[bench] {args.workload}: {K} steps in {dt:.4f} s (events {dt_ev:.4f} s) -> {mlups:.1f} MLUPS "
+          f"(status {status})", file=sys.stderr, flush=True)
+    run.close()
 
     # live per-kernel timing (HIP events on the run's stream)
     prof = make_run()
     prof.step(W)
     ms, nl = prof.profile_phases(args.profile_steps)
-    bytes_per_launch = phase_bytes(w, ms, nl)
-    dom = max((k for k in ms if nl[k] > 0), key=lambda k: ms[k])
-    dur_ms = ms[dom] / nl[dom]
-    achieved = bytes_per_launch[dom] / (dur_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, dom)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if traffic is None else round(traffic),
-                "avg_launch_us": round(dur_ms * 1e3, 2), "bytes_per_launch": bytes_per_launch[dom]}
+    prof.close()
     phases = {k: {"ms_per_step": round(ms[k], 5), "launches": nl[k]} for k in ms}
 
     out = {
@@ -660,6 +804,7 @@ def main():
         "steps": K,
         "warmup": W,
         "ms_per_step": round(dt / K * 1e3, 5),
+        "ms_per_step_events": round(dt_ev / K * 1e3, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -667,14 +812,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["desc"], "grid": [cfg["nx"], cfg["ny"], cfg["nz"]], "cells": N,
                    "job_steps": w["job_steps"], "parallelism": "single-gpu"},
-        "hbm_fraction_step": {"b_alg_bytes_per_lup": w["b_alg"],
-                              "frac": round(mlups * 1e6 * w["b_alg"] / (HBM_PEAK_GBS * 1e9), 4)},
-        "roofline": roofline,
+        "roofline": step_roofline(w, mlups, args.workload),
+        "dominant_kernel": dominant_kernel(w, ms, nl, args.workload),
         "phases": phases,
     }
 
     if args.workload == "channel" and not args.no_system_forms:
         forms = {}
+        forms["channel_large"] = form_large(lbm, 200)
+        print(f"[bench] HBM-resident TO-LES: {forms['channel_large']}", file=sys.stderr, flush=True)
         forms["precision"] = form_precision(lbm, w, 1000)
         print(f"[bench] precision forms: {forms['precision']}", file=sys.stderr, flush=True)
         forms["kernel_filters"] = form_kernel_filters(lbm, w, 1000)
@@ -690,7 +836,7 @@ def main():
         forms["served"] = form_served(lbm, args.serve_requests, 20.0, 2000)
         print(f"[bench] served: {forms['served']}", file=sys.stderr, flush=True)
         # the same trace under a 2 GB HBM budget: admission queues requests
-        forms["served_2gb"] = form_served(lbm, args.serve_requests, 20.0, 2000, budget=2 << 30)
+        forms["served_2gb"] = form_served(lbm, args.serve_requests, 20.0, 2000, budget=2 << 30, sequential=False)
         print(f"[bench] served (2 GB budget): {forms['served_2gb']}", file=sys.stderr, flush=True)
         forms["wale_to_les"] = form_wale(lbm, 2000)
         print(f"[bench] WALE TO-LES: {forms['wale_to_les']}", file=sys.stderr, flush=True)
@@ -703,24 +849,7 @@ def main():
         out["system_forms"] = forms
 
     if not args.no_cpu_baseline:
-        import oracle
-        import synth  # noqa: F401
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        o = oracle.Oracle(**cfg)
-        o.init(w["u0"])
-        if w["qois"] is not None:
-            o.set_closure(oracle.make_closure(w["qois"], **w["cargs"]))
-        t = time.perf_counter()
-        o.step(1)
-        one = time.perf_counter() - t
-        n = max(1, min(2000, int(args.cpu_seconds / max(one, 1e-6))))
-        t = time.perf_counter()
-        o.step(n)
-        tc = time.perf_counter() - t
-        out["cpu_baseline"] = {"value": round(N * n / tc / 1e6, 4), "unit": "MLUPS", "cores": cores,
-                               "kind": "oracle",
-                               "sample": f"steps 1..{n} of the same workload (same grid, closure, inputs), "
-                                         f"{tc:.1f} s"}
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
