@@ -118,10 +118,6 @@ def phase_bytes(w, ms, launches):
     return {k: per_cell[k] * N for k in per_cell}
 
 
-KERNEL_SYMBOL = {"stream_collide": "k_step", "curl": "k_curl", "binomial": "k_binom", "reduce": "k_reduce",
-                 "solve": "k_solve", "apply": "k_apply"}
-
-
 def _profile_kv(workload_name):
     """Key-value lines of the committed rocprofv3 counter summary of a
     workload, or None when there is none or the kernel sources have changed
@@ -148,7 +144,7 @@ def measured_traffic(workload_name, phase=None):
     kv = _profile_kv(workload_name)
     if kv is None:
         return None
-    key = "bytes_per_step" if phase is None else f"{KERNEL_SYMBOL[phase]}_bytes_per_launch"
+    key = "bytes_per_step" if phase is None else f"phase_{phase}_bytes_per_launch"
     return float(kv[key]) if key in kv else None
 
 
