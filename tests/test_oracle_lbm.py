@@ -245,3 +245,57 @@ def test_fp32_store_diagnostic_rounds_only_the_stored_state(orc, lat):
     c.set_fp32_store(False)
     c.step(1)
     assert np.array_equal(c.get_fp(), b.get_fp())
+
+
+@pytest.mark.parametrize("a,b", [(0, 1), (0, 2), (1, 0), (1, 2), (2, 0), (2, 1)])
+def test_diag_energy_enstrophy_closed_form_3d(orc, a, b):
+    """3-D counterpart of the 2-D closed form: D3Q19 on a periodic
+    12 x 10 x 8 box, f = feq(1, u) with the single shear mode
+    u_a = U0 sin(k x_b) (every ordered pair a != b, so that each of the six
+    derivative terms of the 3-D curl is exercised once).  One stream step
+    gives rho = 1 and v_a = U0 sin(k x_b) (2 + cos k)/3 exactly (the
+    quadratic equilibrium terms cancel within the D3Q19 weight classes), so
+    E = 1/4 N (U0 g)^2 and Z = 1/4 N (U0 g sin k)^2, the central difference
+    of sin(k x_b) being sin(k) cos(k x_b)."""
+    dims = (12, 10, 8)
+    o = orc.Oracle(lattice=1, nx=dims[0], ny=dims[1], nz=dims[2], walls_y=0, tau=0.8)
+    N = dims[0] * dims[1] * dims[2]
+    k = 2 * np.pi * 2 / dims[b]
+    zz, yy, xx = np.meshgrid(np.arange(dims[2]), np.arange(dims[1]), np.arange(dims[0]), indexing="ij")
+    coord = (xx, yy, zz)[b].ravel()
+    u = np.zeros((3, N))
+    U0 = 1e-3
+    u[a] = U0 * np.sin(k * coord)
+    o.init(u)
+    o.step(1)
+    r = o.record_arrays()
+    g = (2 + np.cos(k)) / 3
+    E = 0.25 * (U0 * g) ** 2 * N
+    Z = 0.25 * (U0 * g * np.sin(k)) ** 2 * N
+    assert abs(r["diag_e"][0] - E) < 1e-12 * E
+    assert abs(r["diag_z"][0] - Z) < 1e-12 * Z
+    assert abs(r["mass"][0] - N) < 1e-12 * N
+
+
+def test_curl_3d_closed_form(orc):
+    """The 3-D central-difference curl of a sum of six shear modes with six
+    different amplitudes, v_x = A sin(ky y) + A' sin(kz z),
+    v_y = B sin(kz z) + B' sin(kx x), v_z = C sin(kx x) + C' sin(ky y), on a
+    periodic 12 x 10 x 8 box, against its exact value cell by cell:
+    w_x = C' sy cos(ky y) - B sz cos(kz z), w_y = A' sz cos(kz z) - C sx cos(kx x),
+    w_z = B' sx cos(kx x) - A sy cos(ky y), with s = sin k.  Each term has its
+    own amplitude, so a wrong sign, axis or component fails it."""
+    dims = (12, 10, 8)
+    o = orc.Oracle(lattice=1, nx=dims[0], ny=dims[1], nz=dims[2], walls_y=0, tau=0.8)
+    zz, yy, xx = [c.ravel() for c in np.meshgrid(np.arange(dims[2]), np.arange(dims[1]), np.arange(dims[0]), indexing="ij")]
+    kx, ky, kz = (2 * np.pi * m / n for m, n in zip((1, 2, 3), dims))
+    A, A2, B, B2, C, C2 = 1.0, 0.3, -0.7, 0.45, 0.2, -1.3
+    v = np.stack([A * np.sin(ky * yy) + A2 * np.sin(kz * zz),
+                  B * np.sin(kz * zz) + B2 * np.sin(kx * xx),
+                  C * np.sin(kx * xx) + C2 * np.sin(ky * yy)])
+    sx, sy, sz = np.sin(kx), np.sin(ky), np.sin(kz)
+    want = np.stack([C2 * sy * np.cos(ky * yy) - B * sz * np.cos(kz * zz),
+                     A2 * sz * np.cos(kz * zz) - C * sx * np.cos(kx * xx),
+                     B2 * sx * np.cos(kx * xx) - A * sy * np.cos(ky * yy)])
+    w = o.curl(v)
+    assert np.max(np.abs(w - want)) < 1e-14
