@@ -62,6 +62,20 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def build_sanitized(outdir: str) -> str:
+    """The oracle built with clang's AddressSanitizer and
+    UndefinedBehaviorSanitizer into outdir (same arithmetic flags), for the
+    host-sanitizer run of the CPU tests; load it by setting LBM_ORACLE_LIB."""
+    os.makedirs(outdir, exist_ok=True)
+    out = os.path.join(outdir, "liblbm_oracle.so")
+    cmd = ["/opt/rocm/llvm/bin/clang", "-O1", "-g", "-fno-omit-frame-pointer", "-ffp-contract=off",
+           "-fno-fast-math", "-fopenmp", "-fsanitize=address", "-fsanitize=undefined",
+           "-fno-sanitize-recover=undefined", "-shared-libsan", "-shared", "-fPIC", "-std=c99", "-Wall",
+           "-o", out, _SRC, "-lm", "-L/opt/rocm/llvm/lib", "-Wl,-rpath,/opt/rocm/llvm/lib"]
+    subprocess.check_call(cmd)
+    return out
+
+
 class Cfg(ct.Structure):
     _fields_ = [("lattice", ct.c_int), ("nx", ct.c_int), ("ny", ct.c_int), ("nz", ct.c_int),
                 ("walls_y", ct.c_int), ("tau", ct.c_double), ("substrate", ct.c_int),
@@ -92,9 +106,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = ct.CDLL(_LIB)
+        path = os.environ.get("LBM_ORACLE_LIB")
+        if path is None:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+            path = _LIB
+        L = ct.CDLL(path)
         P, D, I = ct.c_void_p, ct.POINTER(ct.c_double), ct.c_int
         L.orc_create.restype = P
         L.orc_create.argtypes = [ct.POINTER(Cfg)]

@@ -12,7 +12,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblbm_hip.so")
+# LBM_HIP_LIB selects another build of the library (the host-sanitizer
+# build of the CPU tests); by default the in-tree one.
+LIB_PATH = os.environ.get("LBM_HIP_LIB") or os.path.join(HERE, "liblbm_hip.so")
 MAX_QOI = 16
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
