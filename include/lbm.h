@@ -238,6 +238,8 @@ int lbm_qoi(lbm_ctx* ctx, long first, long count, lbm_qoi_rec* out);
 /* Density (N) and post-streaming moment velocity (d*N) of the current
  * state, in double precision (syncs).  rho may be NULL. */
 int lbm_fields(lbm_ctx* ctx, double* rho, double* u);
+/* The velocity alone: lbm_fields(ctx, NULL, u). */
+int lbm_velocity(lbm_ctx* ctx, double* u);
 
 /* lbm_fields for callers that cannot allocate (tight serving loops,
  * harnesses that forbid device or host allocations between steps): the same

@@ -1156,6 +1156,11 @@ int lbm_qoi(lbm_ctx* c, long first, long count, lbm_qoi_rec* out)
     return LBM_OK;
 }
 
+int lbm_velocity(lbm_ctx* c, double* u)
+{
+    return lbm_fields(c, nullptr, u);
+}
+
 int lbm_fields(lbm_ctx* c, double* rho, double* u)
 {
     if (!c || !u) return fail(LBM_EINVAL, "NULL argument");

@@ -91,7 +91,7 @@ EXPORTS = [
     "lbm_last_error", "lbm_version", "lbm_lattice_info", "lbm_required_bytes", "lbm_create",
     "lbm_destroy", "lbm_init_velocity", "lbm_set_closure", "lbm_step", "lbm_step_prepare", "lbm_sync",
     "lbm_step_count",
-    "lbm_qoi", "lbm_fields", "lbm_fields_noalloc", "lbm_get_populations", "lbm_set_populations", "lbm_stream_only",
+    "lbm_qoi", "lbm_fields", "lbm_velocity", "lbm_fields_noalloc", "lbm_get_populations", "lbm_set_populations", "lbm_stream_only",
     "lbm_state_bytes", "lbm_get_state", "lbm_set_state", "lbm_batch_create", "lbm_batch_step",
     "lbm_batch_sync", "lbm_batch_destroy", "lbm_profile_phases", "lbm_test_philox", "lbm_test_normals",
     "lbm_server_clock", "lbm_server_create", "lbm_server_submit", "lbm_server_advance", "lbm_server_poll",
@@ -130,6 +130,7 @@ def lib():
         L.lbm_step_count.argtypes = [P]
         L.lbm_qoi.argtypes = [P, ct.c_long, ct.c_long, P]
         L.lbm_fields.argtypes = [P, P, P]
+        L.lbm_velocity.argtypes = [P, P]
         L.lbm_fields_noalloc.argtypes = [P, P, P]
         L.lbm_get_populations.argtypes = [P, P]
         L.lbm_set_populations.argtypes = [P, P]
@@ -403,6 +404,12 @@ class Run:
         u = np.zeros((self.d, self.N))
         check(self.L.lbm_fields(self.h, _p(rho), _p(u)))
         return rho, u
+
+    def velocity(self):
+        """The velocity alone (lbm_velocity)."""
+        u = np.zeros((self.d, self.N))
+        check(self.L.lbm_velocity(self.h, _p(u)))
+        return u
 
     def fields_noalloc(self):
         """fields() through lbm_fields_noalloc (no allocation in the library)."""

@@ -37,6 +37,9 @@ def test_repeat_runs_bitwise_and_graph_equals_eager():
     assert np.array_equal(fa, fb)
     assert np.array_equal(fa, fc)
     assert np.array_equal(a.record_arrays()["q"], b.record_arrays()["q"])
+    # lbm_velocity is the velocity of lbm_fields, bitwise
+    _, u = a.fields()
+    assert np.array_equal(a.velocity(), u)
 
 
 def test_batch_members_bitwise_equal_to_solo():
