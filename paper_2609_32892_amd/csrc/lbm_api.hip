@@ -173,6 +173,7 @@ struct Plan {
     size_t fspec_v, fspec_w, fband_e, fband_z;
     size_t total;
     int N, D, NC, Q, esz, nb1, nbx2, cpt2, nbr, nbb, nbs, zc, btx, rec_cap;
+    size_t popn;   // elements of one population buffer: Q * N rounded up to whole blocks of kPopBlk cells
     ClosureShape cap;
 };
 
@@ -213,8 +214,9 @@ void make_plan(const lbm_config* c, const ClosureShape& cs, Plan* p)
     P.param = take(sizeof(DevParam));
     P.ctl = take(sizeof(DevCtl));
     P.recs = take(sizeof(lbm_qoi_rec) * P.rec_cap);
-    P.g0 = take(e * P.Q * N);
-    P.g1 = take(e * P.Q * N);
+    P.popn = (size_t)P.Q * ((N + kPopBlk - 1) / kPopBlk) * kPopBlk;
+    P.g0 = take(e * P.popn);
+    P.g1 = take(e * P.popn);
     P.fprof = take(sizeof(double) * c->ny);
     P.vn = take(e * P.D * N);
     // statistics partials: one per stream-collide workgroup (1-D blocks, or
@@ -279,6 +281,10 @@ constexpr int kXcd = 8;
 // 96 x 48 x 48 channel, slower on 295 x 47 x 98, whose fields the next
 // kernel otherwise finds in the Infinity Cache).
 int write_through(double pop_bytes) { return pop_bytes <= 24.0 * 1024 * 1024; }
+// Plain stream-collide launches whose population buffers are well beyond
+// the 256 MB Infinity Cache store non-temporally; smaller ones keep their
+// populations in it from one step to the next.
+int non_temporal(double pop_bytes) { return pop_bytes >= 1024.0 * 1024 * 1024; }
 std::vector<int> xcd_order(int n)
 {
     std::vector<int> order;
@@ -436,6 +442,8 @@ LaunchGroup ctx_group(const lbm_ctx* c)
     g.npass = binom_passes(c->cur);
     g.btx = c->plan.btx;
     g.wt = write_through((double)c->plan.N * c->plan.Q * c->plan.esz);
+    g.a32 = (double)c->plan.popn * c->plan.esz < 4294967296.0;
+    g.nt = non_temporal((double)c->plan.popn * c->plan.esz);
     g.defer = c->defers();
     add_pass_masks(c, g);
     g.kf = c->cur.kf;
@@ -984,7 +992,16 @@ int lbm_create(const lbm_config* cfg, const lbm_closure* closure, void* dev_aren
         DevParam p{};
         rc = upload(c, A + plan.param, &p, sizeof p);
     }
-    // initial state rho = 1, v = 0
+    // initial state rho = 1, v = 0; the padding cells of the last population
+    // block (never read or written by the kernels) are zeroed, so that state
+    // images of equal states are equal byte for byte
+    if (!rc) {
+        const size_t blk = (size_t)plan.esz * plan.Q * kPopBlk;
+        const size_t last = (size_t)plan.esz * plan.popn - blk;
+        if (hipMemsetAsync(A + plan.g0 + last, 0, blk, c->stream) != hipSuccess ||
+            hipMemsetAsync(A + plan.g1 + last, 0, blk, c->stream) != hipSuccess)
+            rc = fail(LBM_EDEVICE, "init failed");
+    }
     if (!rc) {
         launch_state(OP_INIT, cfg->lattice, cfg->precision, c->dm, plan.N, c->has_to, 0, c->stream, nullptr, nullptr);
         if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(LBM_EDEVICE, "init failed");
@@ -1387,11 +1404,14 @@ struct StateHeader {
     int32_t Q, N, esz, has_to;
 };
 
+// State images hold the populations in the device's blocked layout.
+constexpr unsigned long long kStateMagic = 0x4C424D53544155ULL;
+
 size_t lbm_state_bytes(const lbm_ctx* c)
 {
     if (!c) return 0;
     const Plan& p = c->plan;
-    size_t b = sizeof(StateHeader) + (size_t)p.esz * p.Q * p.N + sizeof(DevCtl) + sizeof(lbm_qoi_rec) * p.rec_cap;
+    size_t b = sizeof(StateHeader) + (size_t)p.esz * p.popn + sizeof(DevCtl) + sizeof(lbm_qoi_rec) * p.rec_cap;
     return b;
 }
 
@@ -1404,10 +1424,10 @@ int lbm_get_state(lbm_ctx* c, void* host, size_t bytes)
     HIPCHK(hipStreamSynchronize(c->stream));
     const Plan& p = c->plan;
     char* o = (char*)host;
-    StateHeader h{0x4C424D53544154ULL, c->host_step, p.Q, p.N, p.esz, c->has_to};
+    StateHeader h{kStateMagic, c->host_step, p.Q, p.N, p.esz, c->has_to};
     memcpy(o, &h, sizeof h);
     o += sizeof h;
-    const size_t gb = (size_t)p.esz * p.Q * p.N;
+    const size_t gb = (size_t)p.esz * p.popn;
     HIPCHK(hipMemcpy(o, c->hm.g[c->hm.parity ^ c->phase], gb, hipMemcpyDeviceToHost));
     o += gb;
     HIPCHK(hipMemcpy(o, c->arena + p.ctl, sizeof(DevCtl), hipMemcpyDeviceToHost));
@@ -1424,14 +1444,14 @@ int lbm_set_state(lbm_ctx* c, const void* host, size_t bytes)
     const char* o = (const char*)host;
     StateHeader h;
     memcpy(&h, o, sizeof h);
-    if (h.magic != 0x4C424D53544154ULL || h.Q != p.Q || h.N != p.N || h.esz != p.esz || h.has_to != (int)c->has_to)
+    if (h.magic != kStateMagic || h.Q != p.Q || h.N != p.N || h.esz != p.esz || h.has_to != (int)c->has_to)
         return fail(LBM_EINVAL, "state image does not match this context");
     o += sizeof h;
     int crc = clear_records(c);
     if (crc) return crc;
     HIPCHK(hipStreamSynchronize(c->stream));
     c->phase = 0;
-    const size_t gb = (size_t)p.esz * p.Q * p.N;
+    const size_t gb = (size_t)p.esz * p.popn;
     HIPCHK(hipMemcpy(c->hm.g[c->hm.parity], o, gb, hipMemcpyHostToDevice));
     o += gb;
     HIPCHK(hipMemcpy(c->arena + p.ctl, o, sizeof(DevCtl), hipMemcpyHostToDevice));
@@ -1544,7 +1564,10 @@ static int batch_build(lbm_batch* b)
         double pop_bytes = 0;   // one launch covers the whole group
         for (int i : gm[gi]) pop_bytes += (double)b->mem[i]->plan.N * b->mem[i]->plan.Q * b->mem[i]->plan.esz;
         g.wt = write_through(pop_bytes);
+        g.nt = non_temporal(pop_bytes);
+        g.a32 = 1;
         for (int i : gm[gi]) {
+            g.a32 &= (double)b->mem[i]->plan.popn * b->mem[i]->plan.esz < 4294967296.0;
             const lbm_ctx* c = b->mem[i];
             g.any_z |= c->cur.has_z;
             g.maxpow = std::max(g.maxpow, std::max(c->cur.jv, c->cur.jw));

@@ -15,6 +15,10 @@ constexpr int kMaxQ = LBM_MAX_QOI;
 constexpr int kMaxSA = 8;       // E/Z QoIs per closure
 constexpr int kMaxPow = 4;      // highest power of B in R R (filters up to degree 2)
 constexpr int kBlock = 256;     // threads per workgroup of the cell kernels
+// Population layout: consecutive blocks of kPopBlk cells, each block holding
+// its Q populations one after another, [ceil(N / kPopBlk)][Q][kPopBlk].
+constexpr int kPopLog = 10;
+constexpr int kPopBlk = 1 << kPopLog;
 constexpr int kBinTX = 32;      // binomial-filter tile: x extent
 constexpr int kBinTY = kBlock / kBinTX;  // y extent
 constexpr int kBinTXW = 64;     // the wide tile (64 x 4) of the one-pass binomial kernel

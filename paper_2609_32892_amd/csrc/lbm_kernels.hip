@@ -132,6 +132,22 @@ __device__ __forceinline__ void st_at(T* base, unsigned i, T v)
     *(T*)((char*)base + i * (unsigned)sizeof(T)) = v;
 }
 
+// Element index of population i of cell c in the blocked population layout
+// ([block][Q][kPopBlk]): a wavefront's loads of one population stay within
+// one block, and the Q arrays a cell touches sit next to each other, which
+// the memory system serves faster than Q separate full-length streams.  The
+// 32-bit form needs Q * ceil(N / kPopBlk) * kPopBlk elements below 2^32 bytes.
+template <int Q>
+__device__ __forceinline__ unsigned pop_at(int i, unsigned c)
+{
+    return (((c >> kPopLog) * Q + (unsigned)i) << kPopLog) | (c & (kPopBlk - 1));
+}
+template <int Q>
+__device__ __forceinline__ size_t pop_at64(int i, size_t c)
+{
+    return (((c >> kPopLog) * Q + (size_t)i) << kPopLog) | (c & (kPopBlk - 1));
+}
+
 // Stores of fields that the next kernel reads.  On small grids (kernels
 // instantiated with WT) they are relaxed device-scope atomic stores, written
 // through each XCD's L2, so that no dirty lines are left for the L2
@@ -305,13 +321,30 @@ __device__ __forceinline__ T add_df(T g, int i, GA A, GB B, T e)
 // run keeps 2 N * sizeof(T) below 4 GiB (every TO run does), so each load is
 // a 32-bit offset from a scalar base.
 // ---------------------------------------------------------------------------
-template <int LAT, typename T, bool A32>
+template <int LAT, typename T, bool A32, bool FAST = true>
 __device__ __forceinline__ void gather(KMember& m, const T* __restrict__ gs, int x, int y, int z,
                                        int cell, T* f)
 {
     using L = Lat<LAT>;
     constexpr int Q = L::Q, D = L::D;
     const int N = m.N, nx = m.nx, ny = m.ny, nz = m.nz;
+    // Wavefronts whose cells are all at least one cell from the walls and
+    // from the z wrap pull from constant offsets, corrected per cell for the
+    // periodic x wrap; the others resolve wrap and bounce-back per population.
+    const bool inner = y > 0 && y < ny - 1 && (D == 2 || (z > 0 && z < nz - 1));
+    if (FAST && __all(inner)) {
+        const int wxm = x == 0 ? nx : 0, wxp = x == nx - 1 ? -nx : 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int off = L::cx[i] + nx * (L::cy[i] + (D == 3 ? ny * L::cz[i] : 0));
+            const int src = cell - off + (L::cx[i] == 1 ? wxm : L::cx[i] == -1 ? wxp : 0);
+            if (A32)
+                f[i] = ld_at(gs, pop_at<Q>(i, (unsigned)src));
+            else
+                f[i] = gs[pop_at64<Q>(i, (size_t)src)];
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         int sy = y - L::cy[i];
@@ -327,13 +360,10 @@ __device__ __forceinline__ void gather(KMember& m, const T* __restrict__ gs, int
             src = sx + nx * (sy + ny * sz);
             pi = i;
         }
-        if (A32) {
-            // base: population min(i, opp(i)); the bounce-back one is 0 or N further
-            const int lo = i < opp(i) ? i : opp(i);
-            f[i] = ld_at(gs + (size_t)lo * N, (unsigned)((pi - lo) * N + src));
-        } else {
-            f[i] = gs[(size_t)pi * N + src];
-        }
+        if (A32)
+            f[i] = ld_at(gs, pop_at<Q>(pi, (unsigned)src));
+        else
+            f[i] = gs[pop_at64<Q>(pi, (size_t)src)];
     }
 }
 
@@ -376,7 +406,7 @@ __device__ __forceinline__ void moments(const T* f, T& drho, T* j)
 // population is updated as f_i + (force term - omega (f_i - feq_i)), one
 // rounding at its own magnitude.  Plain FP32 storage keeps the direct form
 // as the baseline.
-template <int LAT, typename T, int PREC, int SUB, int MODE, bool WT>
+template <int LAT, typename T, int PREC, int SUB, int MODE, bool WT, bool A32 = MODE == 2, bool NT = false>
 __device__ __forceinline__ void collide_cell(KMember& m, T* f, int x, int y, int z, int cell, T* __restrict__ gd,
                                              double* st, int& bad)
 {
@@ -509,10 +539,16 @@ __device__ __forceinline__ void collide_cell(KMember& m, T* f, int x, int y, int
                      (D == 3 ? T(L::cz[i]) * (us[2] + u[2]) : T(0));
         const T df = dfeq<T>(T(L::w[i]), rho, cd, cs, dd);
         const T out = PROJ ? f[i] + (df - om * fn[i]) : (f[i] - om * fn[i]) + df;
-        if (MODE == 2)
-            st_fld_at(gd + (size_t)i * N, (unsigned)cell, out, WT);
+        if (A32 && MODE == 2)
+            st_fld_at(gd, pop_at<Q>(i, (unsigned)cell), out, WT);
+        else if (A32 && NT)
+            __builtin_nontemporal_store(out, (T*)((char*)gd + pop_at<Q>(i, (unsigned)cell) * (unsigned)sizeof(T)));
+        else if (A32)
+            st_at(gd, pop_at<Q>(i, (unsigned)cell), out);
+        else if (NT)
+            __builtin_nontemporal_store(out, gd + pop_at64<Q>(i, (size_t)cell));
         else
-            gd[(size_t)i * N + cell] = out;
+            gd[pop_at64<Q>(i, (size_t)cell)] = out;
     }
     if (MODE == 2) {
         st_fld_at((T*)m.rho, (unsigned)cell, drho, WT);
@@ -530,8 +566,12 @@ __device__ __forceinline__ void collide_cell(KMember& m, T* f, int x, int y, int
     }
 }
 
-template <int LAT, typename T, int PREC, int SUB, int MODE, bool WT = false>
-__global__ __launch_bounds__(kBlock) void k_step(const DevMember* __restrict__ mems,
+// A32: every population buffer of the launch spans less than 4 GiB, so
+// pulls and stores use 32-bit offsets.  NT (plain modes): the populations are
+// stored non-temporally, on launches whose populations exceed the Infinity
+// Cache.
+template <int LAT, typename T, int PREC, int SUB, int MODE, bool WT = false, bool A32 = MODE == 2, bool NT = false>
+__global__ __launch_bounds__(kBlock, MODE == 2 ? 1 : 8) void k_step(const DevMember* __restrict__ mems,
                                                  const int2* __restrict__ work, int flip)
 {
     using L = Lat<LAT>;
@@ -549,8 +589,8 @@ __global__ __launch_bounds__(kBlock) void k_step(const DevMember* __restrict__ m
     if (cell < N) {
         const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
         T f[Q];
-        gather<LAT, T, MODE == 2>(m, gs, x, y, z, cell, f);
-        collide_cell<LAT, T, PREC, SUB, MODE, WT>(m, f, x, y, z, cell, gd, st, bad);
+        gather<LAT, T, A32>(m, gs, x, y, z, cell, f);
+        collide_cell<LAT, T, PREC, SUB, MODE, WT, A32, NT>(m, f, x, y, z, cell, gd, st, bad);
     }
     if (MODE >= 1) {
         block_sum<4>(st, lds);
@@ -578,7 +618,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const DevMember* __restrict__ m
 #ifndef LBM_STEPT_WAVES
 #define LBM_STEPT_WAVES 4
 #endif
-template <int LAT, typename T, int PREC, int SUB, int TX, bool WT>
+template <int LAT, typename T, int PREC, int SUB, int TX, bool WT, bool A32 = true>
 __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? LBM_STEPT_WAVES : 2) void k_step_t(const DevMember* __restrict__ mems,
                                                    const int2* __restrict__ work, int flip)
 {
@@ -643,26 +683,9 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? LBM_STEPT_WAVES : 2) void 
     int bad = 0;
     // the 19 pulls g*_pi(src) of the own cell of plane z (issued before the
     // plane's records are staged, so their latency overlaps the staging)
-    auto pull = [&](int z, T (&f)[Q]) {
-        const int cell = x + nx * (y + ny * z);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            int sy = y - L::cy[i];
-            int src, pi;
-            if (m.walls && (sy < 0 || sy >= ny)) {
-                src = cell;
-                pi = opp(i);
-            } else {
-                const int sx = wrapi(x - L::cx[i], nx);
-                sy = wrapi(sy, ny);
-                const int sz = D == 3 ? wrapi(z - L::cz[i], nz) : 0;
-                src = sx + nx * (sy + ny * sz);
-                pi = i;
-            }
-            const int lo = i < opp(i) ? i : opp(i);
-            f[i] = ld_at(gs + (size_t)lo * N, (unsigned)((pi - lo) * N + src));
-        }
-    };
+    // (the general pull only: a constant-offset branch here costs the
+    // kernel spills within its 128-VGPR budget)
+    auto pull = [&](int z, T (&f)[Q]) { gather<LAT, T, A32, false>(m, gs, x, y, z, x + nx * (y + ny * z), f); };
     // add delta f of each pulled population from the staged records (a
     // bounce-back pulls population opp(i) of the cell itself: its delta f
     // from the own record with the sign of the linear term flipped, so every
@@ -682,7 +705,7 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? LBM_STEPT_WAVES : 2) void 
             const T cb = cdot<LAT, T>(i, [&](int k) { return r[(D + k) * HXY]; });
             f[i] = add_rn(f[i], df_cc<LAT, T>(i, bb, ca, cb, r[NR * HXY]));
         }
-        collide_cell<LAT, T, PREC, SUB, 2, WT>(m, f, x, y, z, cell, gd, st, bad);
+        collide_cell<LAT, T, PREC, SUB, 2, WT, A32>(m, f, x, y, z, cell, gd, st, bad);
     };
     if constexpr (D == 2) {
         T buf[NE][NR], f[Q];
@@ -739,7 +762,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(const DevMember* __restrict_
     const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
     const T* gs = (const T*)m.g[m.parity ^ flip];
     T f[L::Q];
-    gather<LAT, T, TO>(m, gs, x, y, z, cell, f);
+    gather<LAT, T, false>(m, gs, x, y, z, cell, f);
     T drho, j[3] = {0, 0, 0};
     moments<LAT, T, PREC>(f, drho, j);
     const T rho = T(1) + drho;
@@ -2115,11 +2138,11 @@ __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ 
         const T e = rec_e<D, T>(ra, rb);
         T gi[L::Q];
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) gi[i] = ld_fld<WT>(g + (size_t)i * sN + cell);
+        for (int i = 0; i < L::Q; ++i) gi[i] = ld_fld<WT>(g + pop_at64<L::Q>(i, (size_t)cell));
 #pragma unroll
         for (int i = 0; i < L::Q; ++i)
-            st_fld_at(g + (size_t)i * sN, (unsigned)cell,
-                      add_df<LAT, T>(gi[i], i, [&](int k) { return ra[k]; }, [&](int k) { return rb[k]; }, e), WT);
+            st_fld(g + pop_at64<L::Q>(i, (size_t)cell),
+                   add_df<LAT, T>(gi[i], i, [&](int k) { return ra[k]; }, [&](int k) { return rb[k]; }, e), WT);
     }
 }
 
@@ -2149,8 +2172,9 @@ __global__ __launch_bounds__(kBlock) void k_flush(const DevMember* __restrict__ 
     T* g = (T*)m.g[m.parity ^ flip];
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
-        g[i * sN + cell] = add_df<LAT, T>(g[i * sN + cell], i, [&](int k) { return ra[k]; },
-                                          [&](int k) { return rb[k]; }, e);
+        g[pop_at64<L::Q>(i, (size_t)cell)] = add_df<LAT, T>(g[pop_at64<L::Q>(i, (size_t)cell)], i,
+                                                             [&](int k) { return ra[k]; },
+                                                             [&](int k) { return rb[k]; }, e);
 #pragma unroll
     for (int a = 0; a < 2 * D; ++a) rec[a * sN + cell] = T(0);
 }
@@ -2427,7 +2451,7 @@ __global__ void k_init(const DevMember* __restrict__ mems, int flip, const doubl
         const double cu = L::cx[i] * u[0] + L::cy[i] * u[1] + L::cz[i] * u[2];
         const double X = 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
         const double feq = L::w[i] * r * (1.0 + X);
-        g[(size_t)i * N + cell] = PREC == LBM_FP32_PLAIN ? (T)feq : (T)(L::w[i] * ((r - 1.0) + r * X));
+        g[pop_at64<L::Q>(i, (size_t)cell)] = PREC == LBM_FP32_PLAIN ? (T)feq : (T)(L::w[i] * ((r - 1.0) + r * X));
     }
     if (m.has_to) {
         ((T*)m.rho)[cell] = 0;
@@ -2446,7 +2470,7 @@ __global__ void k_get_pop(const DevMember* __restrict__ mems, int flip, double* 
     const T* g = (const T*)m.g[m.parity ^ flip];
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
-        f[(size_t)i * N + cell] = (double)g[(size_t)i * N + cell] + (PREC == LBM_FP32_PLAIN ? 0.0 : L::w[i]);
+        f[(size_t)i * N + cell] = (double)g[pop_at64<L::Q>(i, (size_t)cell)] + (PREC == LBM_FP32_PLAIN ? 0.0 : L::w[i]);
 }
 
 template <int LAT, typename T, int PREC>
@@ -2460,7 +2484,7 @@ __global__ void k_set_pop(const DevMember* __restrict__ mems, int flip, const do
     T* g = (T*)m.g[m.parity ^ flip];
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
-        g[(size_t)i * N + cell] = (T)(f[(size_t)i * N + cell] - (PREC == LBM_FP32_PLAIN ? 0.0 : L::w[i]));
+        g[pop_at64<L::Q>(i, (size_t)cell)] = (T)(f[(size_t)i * N + cell] - (PREC == LBM_FP32_PLAIN ? 0.0 : L::w[i]));
     if (m.has_to) {
         ((T*)m.rho)[cell] = 0;
         for (int a = 0; a < L::D; ++a) ((T*)m.vs)[(size_t)a * N + cell] = 0;
@@ -2499,7 +2523,6 @@ __global__ __launch_bounds__(kBlock) void k_project(const DevMember* __restrict_
         double S = 0;
         for (int r = -R; r <= R; ++r) S += keys((double)r / m);
         const double rS = 1.0 / S;
-        const size_t NF = (size_t)F.N;
         const T* g = (const T*)F.g[F.parity ^ flip];
         double acc[L::Q], uacc[2] = {0, 0};
 #pragma unroll
@@ -2513,7 +2536,7 @@ __global__ __launch_bounds__(kBlock) void k_project(const DevMember* __restrict_
                 double drho = 0, jx = 0, jy = 0;
 #pragma unroll
                 for (int q = 0; q < L::Q; ++q) {
-                    const double gq = (double)g[(size_t)q * NF + fc];
+                    const double gq = (double)g[pop_at64<L::Q>(q, fc)];
                     acc[q] += w * gq;
                     drho += gq;
                     jx += L::cx[q] * gq;
@@ -2539,12 +2562,11 @@ __global__ __launch_bounds__(kBlock) void k_project(const DevMember* __restrict_
     }
     const int zf = L::D == 3 ? m * k + o : 0;
     const size_t fc = ((size_t)zf * F.ny + (size_t)(m * j + o)) * F.nx + (size_t)(m * i + o);
-    const size_t NF = (size_t)F.N;
     const T* g = (const T*)F.g[F.parity ^ flip];
     double drho = 0, jm[3] = {0, 0, 0};
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
-        const double gq = (double)g[(size_t)q * NF + fc];
+        const double gq = (double)g[pop_at64<L::Q>(q, fc)];
         if (fpop) fpop[(size_t)q * Nc + cell] = gq + (PREC == LBM_FP32_PLAIN ? 0.0 : L::w[q]);
         drho += gq;
         jm[0] += L::cx[q] * gq;
@@ -2585,7 +2607,6 @@ __global__ __launch_bounds__(kBlock) void k_proj_bx(const DevMember* __restrict_
     if (idx >= n) return;
     const int i = idx % ncx, yf = idx / ncx;
     const int o = (m - 1) / 2, R = 2 * m - 1;
-    const size_t NF = (size_t)F.N;
     const T* g = (const T*)F.g[F.parity ^ flip];
     double ux = 0, uy = 0;
     for (int rx = -R; rx <= R; ++rx) {
@@ -2593,7 +2614,7 @@ __global__ __launch_bounds__(kBlock) void k_proj_bx(const DevMember* __restrict_
         double drho = 0, jx = 0, jy = 0;
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) {
-            const double gq = (double)g[(size_t)q * NF + fc];
+            const double gq = (double)g[pop_at64<L::Q>(q, fc)];
             drho += gq;
             jx += L::cx[q] * gq;
             jy += L::cy[q] * gq;
@@ -2678,10 +2699,10 @@ __global__ void k_stream_only(const DevMember* __restrict__ mems, int flip)
     if (cell >= N) return;
     const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
     T f[L::Q];
-    gather<LAT, T, TO>(m, (const T*)m.g[m.parity ^ flip], x, y, z, cell, f);
+    gather<LAT, T, false>(m, (const T*)m.g[m.parity ^ flip], x, y, z, cell, f);
     T* gd = (T*)m.g[m.parity ^ flip ^ 1];
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) gd[(size_t)i * N + cell] = f[i];
+    for (int i = 0; i < L::Q; ++i) gd[pop_at64<L::Q>(i, (size_t)cell)] = f[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -2707,7 +2728,10 @@ static void launch_step_group(const LaunchGroup& g, hipStream_t st, int flip, hi
     }
 #define LBM_STEP_T(SUB, TXV)                                                                               \
     do {                                                                                                   \
-        if (g.wt)                                                                                          \
+        if (!g.a32)                                                                                        \
+            hipLaunchKernelGGL((k_step_t<LAT, T, PREC, SUB, TXV, false, false>), dim3(g.nbb), blk, 0, st, \
+                               g.mems, g.workb, flip);                                                     \
+        else if (g.wt)                                                                                     \
             hipLaunchKernelGGL((k_step_t<LAT, T, PREC, SUB, TXV, true>), dim3(g.nbb), blk, 0, st, g.mems,  \
                                g.workb, flip);                                                             \
         else                                                                                               \
@@ -2725,12 +2749,22 @@ static void launch_step_group(const LaunchGroup& g, hipStream_t st, int flip, hi
                 break;                                                                                     \
             }                                                                                              \
         }                                                                                                  \
-        if (g.mode == 2 && g.wt)                                                                           \
+        if (g.mode == 2 && !g.a32)                                                                         \
+            hipLaunchKernelGGL((k_step<LAT, T, PREC, SUB, 2, false, false>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
+        else if (g.mode == 2 && g.wt)                                                                      \
             hipLaunchKernelGGL((k_step<LAT, T, PREC, SUB, 2, true>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
         else if (g.mode == 2)                                                                              \
             hipLaunchKernelGGL((k_step<LAT, T, PREC, SUB, 2>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
+        else if (g.mode == 1 && g.a32)                                                                     \
+            hipLaunchKernelGGL((k_step<LAT, T, PREC, SUB, 1, false, true>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
         else if (g.mode == 1)                                                                              \
             hipLaunchKernelGGL((k_step<LAT, T, PREC, SUB, 1>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
+        else if (g.a32 && g.nt)                                                                            \
+            hipLaunchKernelGGL((k_step<LAT, T, PREC, SUB, 0, false, true, true>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
+        else if (g.a32)                                                                                    \
+            hipLaunchKernelGGL((k_step<LAT, T, PREC, SUB, 0, false, true>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
+        else if (g.nt)                                                                                     \
+            hipLaunchKernelGGL((k_step<LAT, T, PREC, SUB, 0, false, false, true>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
         else                                                                                               \
             hipLaunchKernelGGL((k_step<LAT, T, PREC, SUB, 0>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
     } while (0)

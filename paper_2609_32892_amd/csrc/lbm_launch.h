@@ -70,6 +70,8 @@ struct LaunchGroup {
     const FourierProg* fprog;   // Fourier band QoIs (host memory; null if none)
     int wt;             // store the fields the next kernel reads through the L2 (small launches)
     int defer;          // TO mode: the SGS change is recorded and applied by the next step's pull
+    int a32;            // every member's population buffer spans less than 4 GiB (32-bit offsets)
+    int nt;             // plain runs: the launch's populations exceed the Infinity Cache (non-temporal stores)
                         // (k_step_t over the binomial tiles); not with the WALE substrate
 };
 
