@@ -1548,11 +1548,12 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const DevMember* __restrict__
     for (int k = 0; k < NV; ++k) acc[k] = 0;
     SensCoef<T, MAXSA> cf;
     sens_coef<T, MAXSA>(prm, cf);
-    // FP32: cells in pairs, both cells' fields loaded before either is
-    // evaluated (a second cell past the plane re-loads the first and is not
-    // added); FP64 one cell at a time (a pair would take the FP64 variant to
-    // one wave per SIMD).  The additions keep the order of the cells.
-    constexpr int NP = sizeof(T) == 4 ? 2 : 1;
+    // One cell at a time (NP = 1), its fields loaded in one batch before it
+    // is evaluated.  (Measured on MI355X: pairs of cells in FP32 took 197
+    // VGPRs and two waves per SIMD, 510 us on 384 x 192 x 192 against 434 us
+    // for single cells at three waves; 18.4 against 17.4 us on 96 x 48 x 48.)
+    // The additions keep the order of the cells.
+    constexpr int NP = 1;
     for (int c = 0; c < m.cpt2; c += NP) {
         const int pa = (bx * m.cpt2 + c) * kBlock + threadIdx.x;
         if (pa >= plane) break;
