@@ -180,8 +180,9 @@ def dominant_kernel(w, ms, nl, workload_name):
 
 
 def timed_steps(run, K):
-    """K steps of a run after its graphs are captured: host clock and HIP
-    events on the run's own stream around the same region."""
+    """K steps of a run after its graphs are captured (already, when the
+    caller prepared them before its warm-up steps): host clock and HIP events
+    on the run's own stream around the same region."""
     import torch
     run.prepare(K)
     run.sync()
@@ -670,6 +671,7 @@ def form_large(lbm, steps):
     spec = lbm.ClosureSpec(w["qois"], **dict(w["cargs"], spinup=10))
     r = lbm.Run(lbm.make_config(precision=w["precision"], **cfg), spec)
     r.init_velocity(w["u0"])
+    r.prepare(steps)
     r.step(20)
     r.sync()
     dt, dt_ev, status = timed_steps(r, steps)
@@ -777,6 +779,7 @@ def main():
         return r
 
     run = make_run()
+    run.prepare(K)      # graphs of the timed chunk first: the warm-up runs right before the timed steps
     run.step(W)
     run.sync()
     dt, dt_ev, status = timed_steps(run, K)

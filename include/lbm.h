@@ -225,8 +225,9 @@ int lbm_set_closure(lbm_ctx* ctx, const lbm_closure* closure);
  * captured hipGraphs (cached by chunk length); a last odd step, and steps of
  * closures with Fourier band QoIs (hipFFT), launch eagerly. */
 int lbm_step(lbm_ctx* ctx, long nsteps);
-/* Capture, without running anything, the graphs a following
- * lbm_step(ctx, nsteps) replays, so that it pays no capture cost (timed
+/* Capture and upload, without running anything, the graphs a later
+ * lbm_step(ctx, nsteps) replays (from either ping-pong phase, so that other
+ * steps may run in between), so that it pays no capture cost (timed
  * regions).  Graphs are dropped when the closure or the state changes. */
 int lbm_step_prepare(lbm_ctx* ctx, long nsteps);
 int lbm_sync(lbm_ctx* ctx);             /* waits; LBM_EUNSTABLE if flagged */

@@ -861,6 +861,10 @@ int capture(hipStream_t st, const std::vector<LaunchGroup>& groups, int nsteps, 
     e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
     hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(LBM_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    // move the executable graph to the device now, so that its first launch
+    // does not pay for the upload
+    e = hipGraphUpload(*out, st);
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "graph upload failed: %s", hipGetErrorString(e));
     return LBM_OK;
 }
 
@@ -1084,17 +1088,17 @@ static long graph_chunk(const lbm_ctx* c, long n)
     return len >= 2 ? len : 0;
 }
 
-// The graph of len steps from the current phase, captured if not cached.
-static int step_graph(lbm_ctx* c, int len, hipGraphExec_t* out)
+// The graph of len steps from ping-pong phase ph, captured if not cached.
+static int step_graph(lbm_ctx* c, int len, int ph, hipGraphExec_t* out)
 {
     if (c->gver != c->version) drop_graphs(c);
     c->gver = c->version;
-    auto& cache = c->gexec[c->phase];
+    auto& cache = c->gexec[ph];
     auto it = cache.find(len);
     if (it == cache.end()) {
         hipGraphExec_t g = nullptr;
         std::vector<LaunchGroup> gs{ctx_group(c)};
-        const int rc = capture(c->stream, gs, len, c->phase, &g);
+        const int rc = capture(c->stream, gs, len, ph, &g);
         if (rc) return rc;
         it = cache.emplace(len, g).first;
     }
@@ -1109,7 +1113,7 @@ int lbm_step(lbm_ctx* c, long n)
         const long len = graph_chunk(c, n);
         if (len > 0) {
             hipGraphExec_t g = nullptr;
-            int rc = step_graph(c, (int)len, &g);
+            int rc = step_graph(c, (int)len, c->phase, &g);
             if (rc) return rc;
             HIPCHK(hipGraphLaunch(g, c->stream));
             if (c->defers()) c->pending = true;
@@ -1133,9 +1137,13 @@ int lbm_step_prepare(lbm_ctx* c, long n)
     while (n > 0) {
         const long len = graph_chunk(c, n);
         if (len == 0) break;   // the rest launches eagerly
-        hipGraphExec_t g = nullptr;
-        int rc = step_graph(c, (int)len, &g);
-        if (rc) return rc;
+        // both ping-pong phases, so that steps taken in between (an odd
+        // number, say) do not make the prepared graphs miss
+        for (int ph = 0; ph < 2; ++ph) {
+            hipGraphExec_t g = nullptr;
+            int rc = step_graph(c, (int)len, ph, &g);
+            if (rc) return rc;
+        }
         n -= len;
     }
     return LBM_OK;
