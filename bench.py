@@ -118,13 +118,18 @@ def phase_bytes(w, ms, launches):
     return {k: per_cell[k] * N for k in per_cell}
 
 
+# The kernel sources a counter summary is valid for (the kernels and the
+# headers they share with the launch code).
+KERNEL_SOURCES = ("lbm_kernels.hip", "lbm_dev.h", "lbm_launch.h")
+
+
 def _profile_kv(workload_name):
     """Key-value lines of the committed rocprofv3 counter summary of a
     workload, or None when there is none or the kernel sources have changed
     since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"{workload_name}_hbm_traffic.txt")
-    srcs = [os.path.join(ROOT, "paper_2609_32892_amd", "csrc", f) for f in ("lbm_kernels.hip", "lbm_api.hip")]
+    srcs = [os.path.join(ROOT, "paper_2609_32892_amd", "csrc", f) for f in KERNEL_SOURCES]
     if not os.path.exists(path):
         return None
     kv = {}
