@@ -160,6 +160,7 @@ int check_config(const lbm_config* c)
     if (c->force_kind < LBM_FORCE_NONE || c->force_kind > LBM_FORCE_CONST_X) return fail(LBM_EINVAL, "bad force kind");
     if (c->rec_cap < 0) return fail(LBM_EINVAL, "rec_cap < 0");
     if (c->tune_zc < 0 || c->tune_cpt < 0) return fail(LBM_EINVAL, "tuning values must be >= 0");
+    if (c->tune_mem < 0 || c->tune_mem > 3) return fail(LBM_EINVAL, "tune_mem must be in 0..3");
     if (c->tune_btx != 0 && c->tune_btx != kBinTX && c->tune_btx != kBinTXW)
         return fail(LBM_EINVAL, "tune_btx must be 0, %d or %d", kBinTX, kBinTXW);
     if (c->tune_btx == kBinTXW && c->lattice != LBM_D3Q19)
@@ -442,8 +443,8 @@ LaunchGroup ctx_group(const lbm_ctx* c)
     g.npass = binom_passes(c->cur);
     g.btx = c->plan.btx;
     g.wt = write_through((double)c->plan.N * c->plan.Q * c->plan.esz);
-    g.a32 = (double)c->plan.popn * c->plan.esz < 4294967296.0;
-    g.nt = non_temporal((double)c->plan.popn * c->plan.esz);
+    g.a32 = (double)c->plan.popn * c->plan.esz < 4294967296.0 && !(c->cfg.tune_mem & 1);
+    g.nt = non_temporal((double)c->plan.popn * c->plan.esz) || (c->cfg.tune_mem & 2);
     g.defer = c->defers();
     add_pass_masks(c, g);
     g.kf = c->cur.kf;
@@ -1575,7 +1576,9 @@ static int batch_build(lbm_batch* b)
         g.nt = non_temporal(pop_bytes);
         g.a32 = 1;
         for (int i : gm[gi]) {
-            g.a32 &= (double)b->mem[i]->plan.popn * b->mem[i]->plan.esz < 4294967296.0;
+            g.a32 &= (double)b->mem[i]->plan.popn * b->mem[i]->plan.esz < 4294967296.0 &&
+                     !(b->mem[i]->cfg.tune_mem & 1);
+            g.nt |= (b->mem[i]->cfg.tune_mem & 2) != 0;
             const lbm_ctx* c = b->mem[i];
             g.any_z |= c->cur.has_z;
             g.maxpow = std::max(g.maxpow, std::max(c->cur.jv, c->cur.jw));

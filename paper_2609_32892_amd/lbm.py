@@ -51,7 +51,8 @@ class Config(ct.Structure):
                 ("nz", ct.c_int), ("walls_y", ct.c_int), ("tau", ct.c_double), ("substrate", ct.c_int),
                 ("c_model", ct.c_double), ("force_kind", ct.c_int), ("force_amp", ct.c_double),
                 ("force_k", ct.c_int), ("drag", ct.c_double), ("diag", ct.c_int), ("rec_cap", ct.c_int),
-                ("tune_zc", ct.c_int), ("tune_cpt", ct.c_int), ("tune_btx", ct.c_int)]
+                ("tune_zc", ct.c_int), ("tune_cpt", ct.c_int), ("tune_btx", ct.c_int),
+                ("tune_mem", ct.c_int)]
 
 
 class QoiSpec(ct.Structure):
@@ -264,11 +265,12 @@ def lattice_info(lattice: int):
 
 def make_config(lattice=D2Q9, precision=FP32_SHIFTED, nx=64, ny=64, nz=1, walls_y=0, tau=0.6,
                 substrate=BGK, cmodel=0.0, force_kind=FORCE_NONE, force_amp=0.0, force_k=0, drag=0.0,
-                diag=0, rec_cap=0, tune_zc=0, tune_cpt=0, tune_btx=0) -> Config:
+                diag=0, rec_cap=0, tune_zc=0, tune_cpt=0, tune_btx=0, tune_mem=0) -> Config:
     if isinstance(precision, str):
         precision = PRECISION[precision]
     return Config(lattice, precision, nx, ny, nz if lattice == D3Q19 else 1, walls_y, tau, substrate,
-                  cmodel, force_kind, force_amp, force_k, drag, diag, rec_cap, tune_zc, tune_cpt, tune_btx)
+                  cmodel, force_kind, force_amp, force_k, drag, diag, rec_cap, tune_zc, tune_cpt, tune_btx,
+                  tune_mem)
 
 
 class ClosureSpec:

@@ -151,6 +151,33 @@ def test_binomial_tile_widths_bitwise_equal(walls):
             r.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_large_grid_memory_forms_bitwise_equal(prec):
+    """The forms the stream-collide takes on large grids only (64-bit
+    population offsets once a population buffer reaches 4 GiB; non-temporal
+    population stores beyond the Infinity Cache), forced on a small channel
+    through tune_mem: bitwise the default result, for the deferred TO
+    predictor, the WALE TO predictor (no deferral) and the plain step."""
+    lbm = need_gpu()
+    cfg, u0 = synth.channel_workload(40, 18, 10, seed=8)
+    qois, cargs = closure_args("3d", ny=18, spinup=3)
+    wale = dict(cfg, substrate=2, cmodel=2.2)
+    for name, c, q in (("TO", cfg, qois), ("WALE TO", wale, qois), ("plain", cfg, None)):
+        for mem in (1, 2, 3):
+            _say(f"{prec} {name}: tune_mem={mem}")
+            runs = [gpu_run(lbm, c, u0, prec, q, cargs if q else None, tune_mem=t) for t in (0, mem)]
+            for r in runs:
+                r.step(7)
+                r.sync()
+            fa, fb = (r.get_populations() for r in runs)
+            assert np.array_equal(fa, fb), f"{prec} {name} tune_mem={mem}: populations differ"
+            if q:
+                qa, qb = (r.record_arrays()["q"] for r in runs)
+                assert np.array_equal(qa, qb)
+            for r in runs:
+                r.close()
+
+
 def test_write_through_and_plain_stores_bitwise_equal():
     """Launches whose populations fit the L2s store their fields through it,
     larger ones with plain stores; a batch decides for all its members
