@@ -716,7 +716,7 @@ def cpu_baseline(w, seconds):
         t = time.perf_counter()
         o.step(1)
         one = time.perf_counter() - t
-        n = max(1, min(2000, int(seconds / 2 / max(one, 1e-6))))
+        n = max(1, min(2000, int(seconds / max(one, 1e-6))))
         t = time.perf_counter()
         o.step(n)
         tc = time.perf_counter() - t
@@ -738,7 +738,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="channel", choices=["channel", "channel_large", "kolmogorov", "fine"])
     ap.add_argument("--profile-steps", type=int, default=200)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target length of each oracle sample (all cores, then one core)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-system-forms", action="store_true",
                     help="skip the precision / batched / served / fine-grid comparisons")
