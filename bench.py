@@ -197,9 +197,9 @@ def timed_steps(run, K):
     e0.record(run.stream)
     run.step(K)
     e1.record(run.stream)
-    status = run.sync()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    status = run.sync()   # the run's instability flag, read once the timed work is complete
     return dt, e0.elapsed_time(e1) * 1e-3, status
 
 
