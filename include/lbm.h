@@ -83,9 +83,11 @@ typedef struct {
     int tune_cpt;       /* tuning: cells per thread of the QoI reduction (0: automatic) */
     int tune_btx;       /* tuning: binomial tile width, 32 or 64 (0: automatic; 64 needs a
                            D3Q19 grid; bitwise the same result either way) */
-    int tune_mem;       /* memory-access variant of the stream-collide (0: automatic by
-                           size): bit 0 forces 64-bit population offsets, bit 1
-                           non-temporal population stores in plain runs; bitwise the
+    int tune_mem;       /* memory-access variant of the step (0: automatic by size): bit 0
+                           forces 64-bit population offsets, bit 1 non-temporal population
+                           stores in plain runs, bit 2 the SGS change recorded and applied
+                           by the next step's pull (binomial closures, BGK or Smagorinsky
+                           substrate) also where the populations fit the L2s; bitwise the
                            same result either way (for tests of the large-grid forms) */
 } lbm_config;
 

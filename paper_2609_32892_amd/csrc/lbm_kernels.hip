@@ -260,6 +260,10 @@ __device__ __forceinline__ T dfeq(T w, T rho, T cd, T cs, T dd)
 template <int LAT, typename T, typename Get>
 __device__ __forceinline__ T cdot(int i, Get A)
 {
+    // (no contraction: where a component is itself a product, as rho dv in
+    // the in-place apply, a fused multiply-add would round differently from
+    // the same sum over stored records)
+#pragma clang fp contract(off)
     using L = Lat<LAT>;
     const int c[3] = {L::cx[i], L::cy[i], L::D == 3 ? L::cz[i] : 0};
     T s = T(0);

@@ -16,26 +16,32 @@ def _say(msg):
     print(msg, flush=True)
 
 
-def test_channel_384x192x192_to_les_first_step():
+def test_channel_384x192x192_to_les_two_steps():
+    """The HBM-resident grid over every cell, two steps with the LRS active
+    from the first: the second step's pull applies the first step's SGS
+    records (the form this grid size takes)."""
     lbm = need_gpu()
     cfg, u0 = synth.channel_workload(384, 192, 192, substrate=1, cmodel=0.1, seed=6)
     nb, dmin, dmax = synth.channel_bands(192)
     C, mu, S = synth.lrs_model_channel(12, 7, 9)
     cargs = dict(mode="lrs", spinup=0, C=C, mu=mu, Sigma=S, seed=8, nbands=nb, dmin=dmin, dmax=dmax)
-    _say("384x192x192 channel TO-LES, FP32, 1 step")
+    _say("384x192x192 channel TO-LES, FP32, 2 steps")
     run = gpu_run(lbm, cfg, u0, "fp32", synth.QOIS_3D, cargs)
-    run.step(1)
+    run.step(2)
     assert run.sync() == 0
     o = oracle_run(cfg, u0, synth.QOIS_3D, cargs)
-    o.step(1)
+    o.step(2)
     rg, ro = run.record_arrays(), o.record_arrays()
     ev = rel_err(run.fields()[1], o.velocity()[1])
     eq = np.max(np.abs(rg["q"] - ro["q"]) / np.abs(ro["q"]))
     edq = np.max(np.abs(rg["dq"] - ro["dq"]) / np.abs(ro["dq"]))
     _say(f"  velocity {ev:.2e}  q {eq:.2e}  dq {edq:.2e}")
     assert np.array_equal(rg["flags"], ro["flags"]) and np.all(ro["dq"] != 0)
-    # velocity: the stated 1e-5; q* and dQ about ten times the measured 3.9e-8
-    assert ev <= 1e-5 and eq <= 5e-7 and edq <= 5e-7
+    # velocity: the stated 1e-5; q* about four times the measured 1.3e-7; dQ
+    # the bar of the other 3-D FP32 parity tests (measured 7.3e-4: after the
+    # first corrected step dQ = s z - q* is a difference small against q*,
+    # which FP32 resolves to about 1e-7 of itself)
+    assert ev <= 1e-5 and eq <= 5e-7 and edq <= 5e-3
 
 
 def test_fine_grid_480x240x240_plain():

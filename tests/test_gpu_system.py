@@ -178,6 +178,55 @@ def test_large_grid_memory_forms_bitwise_equal(prec):
                 r.close()
 
 
+@pytest.mark.parametrize("case", ["2d-fp32", "3d-fp32", "3d-fp64"])
+def test_deferred_and_in_place_sgs_change_bitwise_equal(case):
+    """The SGS change recorded per cell and applied by the next step's pull
+    (the form of grids whose populations exceed the L2s), forced with
+    tune_mem on a small grid, against the in-place apply of small grids:
+    bitwise equal populations, fields and records after a run; state read
+    with records pending; a checkpoint taken with records pending and
+    resumed in a fresh run; and a closure change mid-run."""
+    lbm = need_gpu()
+    kind, prec = case.split("-")
+    if kind == "2d":
+        cfg, u0, qois, cargs = _case2d(48, 3)
+    else:
+        cfg, u0 = synth.channel_workload(40, 18, 10, seed=8)
+        qois, cargs = closure_args("3d", ny=18, spinup=3)
+    a = gpu_run(lbm, cfg, u0, prec, qois, cargs)
+    b = gpu_run(lbm, cfg, u0, prec, qois, cargs, tune_mem=4)
+    for r in (a, b):
+        r.step(9)
+        r.sync()
+    _say(f"deferred vs in place: {case}")
+    assert np.array_equal(a.fields()[1], b.fields()[1])          # b flushes its pending records
+    for r in (a, b):
+        r.step(4)
+        r.sync()
+    state = b.get_state()                                         # taken with records pending
+    assert np.array_equal(a.get_populations(), b.get_populations())
+    c = gpu_run(lbm, cfg, u0, prec, qois, cargs, tune_mem=4)
+    c.set_state(state)
+    for r in (a, b, c):
+        r.step(6)
+        r.sync()
+    fa = a.get_populations()
+    assert np.array_equal(fa, b.get_populations())
+    assert np.array_equal(fa, c.get_populations())
+    ra, rb = a.record_arrays(), b.record_arrays()
+    for key in ("q", "dq", "gamma"):
+        assert np.array_equal(ra[key], rb[key]), key
+    # a closure change flushes the pending records first
+    spec = lbm.ClosureSpec(qois, **dict(cargs, spinup=0))
+    for r in (a, b):
+        r.set_closure(spec)
+        r.step(5)
+        r.sync()
+    assert np.array_equal(a.get_populations(), b.get_populations())
+    for r in (a, b, c):
+        r.close()
+
+
 def test_write_through_and_plain_stores_bitwise_equal():
     """Launches whose populations fit the L2s store their fields through it,
     larger ones with plain stores; a batch decides for all its members
