@@ -387,7 +387,10 @@ int lbm_server_submit(lbm_server* s, const lbm_config* cfg, const lbm_closure* c
                       long nsteps, double t_arrival, int keep_state, long* id);
 /* Admit, account and retire the chunk in flight, enqueue the next chunk of at
  * most max_chunk steps (0: 64) and return without waiting for it.  A caller
- * loops until lbm_server_pending reads 0. */
+ * loops until lbm_server_pending reads 0.  If the batch of the active
+ * requests cannot be built or stepped, those requests are retired with that
+ * status (their results say so) and the status is returned; queued requests
+ * are served by later calls. */
 int lbm_server_advance(lbm_server* s, double now, long max_chunk, int* n_active);
 /* Move up to cap finished results into out (caller-owned). */
 int lbm_server_poll(lbm_server* s, lbm_result* out, int cap, int* n);

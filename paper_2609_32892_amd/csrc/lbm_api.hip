@@ -1999,6 +1999,22 @@ int server_retire(lbm_server* s)
 }
 
 // Account and retire the chunk in flight (waits for it).
+// A batch that cannot be built or stepped: every active request is retired
+// with that status (its state is no longer consistent with its step count),
+// so that later calls serve the queue instead of retrying it.
+void server_fail_active(lbm_server* s, int status)
+{
+    const double now = server_clock_now();
+    if (s->batch) lbm_batch_destroy(s->batch);
+    s->batch = nullptr;
+    for (ServeReq* r : s->active) {
+        server_post(s, r, status, now);
+        server_release(s, r);
+    }
+    s->active.clear();
+    s->dirty = true;
+}
+
 int server_finish_chunk(lbm_server* s)
 {
     if (!s->inflight) return LBM_OK;
@@ -2112,12 +2128,19 @@ int lbm_server_advance(lbm_server* s, double now, long max_chunk, int* n_active)
         std::vector<lbm_ctx*> m;
         for (ServeReq* r : s->active) m.push_back(r->ctx);
         rc = lbm_batch_create((int)m.size(), m.data(), &s->batch);
-        if (rc) return rc;
+        if (rc) {
+            server_fail_active(s, rc);
+            return rc;
+        }
         s->dirty = false;
     }
     HIPCHK(hipEventRecord(s->ev0, s->stream));
     rc = lbm_batch_step(s->batch, chunk);
-    if (rc) return rc;
+    if (rc) {
+        (void)hipStreamSynchronize(s->stream);
+        server_fail_active(s, rc);
+        return rc;
+    }
     HIPCHK(hipEventRecord(s->ev1, s->stream));
     s->inflight = true;
     s->inflight_chunk = chunk;
