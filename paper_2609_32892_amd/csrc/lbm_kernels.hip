@@ -1,22 +1,31 @@
 // lbm_kernels.hip -- HIP kernels of the TO-LRS lattice Boltzmann LES step for
 // gfx950 (MI355X).
 //
-// Populations are stored structure-of-arrays [Q][N] (x fastest) in two
-// ping-pong buffers.  One step (eqs. LES-1..LES-3 with the TO correction):
+// Populations are stored in blocks of kPopBlk cells (x-fastest cell order),
+// each block holding its Q populations one after another, in two ping-pong
+// buffers; the other fields are [component][N].  One step (eqs. LES-1..LES-3
+// with the TO correction):
 //   k_step     pull-stream with halfway bounce-back (eq. LES-3, Sec. 7.1),
 //              moments, effective relaxation time (Sec. 5), BGK relaxation and
 //              exact-difference forcing (eq. LES-1/LES-2); writes the
 //              predictor populations and rho, v* = v^{p,n*}.
-//   k_curl     w = curl v* (second-order central differences).
-//   k_binom    powers B^j v*, B^j w of the binomial filter (Sec. 4.1).
+//   k_step_t   the same on 2.5-D tiles, adding during the pull the SGS change
+//              the previous step recorded per cell (grids whose populations
+//              exceed the L2s).
+//   k_binom1   first powers of the binomial filter (Sec. 4.1): w = curl v*,
+//              B v*, B w and curl^T w from v* staged with a two-cell halo.
+//   k_binom    further powers B^j v*, B^j w and curl^T B^(j-1) w.
 //   k_reduce   per-cell QoIs, sensitivities (App. A) and Gram products,
 //              reduced per workgroup in FP64.
-//   k_solve    one workgroup per member: fixed-order sums, dQ (tracking or
-//              LRS, eqs. dQ-from-ref, LRS), Gram solve (eq. O-from-V,
-//              eq. orthogonality), gamma (eq. tau-from-dQ-for-tracking).
+//   k_sum      fixed-order cross-workgroup sums; the step's LRS draw.
+//   k_solve    one workgroup per member: dQ (tracking or LRS, eqs.
+//              dQ-from-ref, LRS), Gram solve (eq. O-from-V, eq.
+//              orthogonality), gamma (eq. tau-from-dQ-for-tracking).
 //   k_apply    dv_SGS = sum_i gamma_i O_i (eq. TO-ansatz), evaluated as
-//              sum_j beta_j V_j with beta = G^-1 dQ, and its change of the
-//              equilibrium added to the predictor populations in place.
+//              sum_j beta_j V_j with beta = G^-1 dQ; its change of the
+//              equilibrium is added to the predictor populations in place, or
+//              recorded as (rho dv, 2 v* + dv) for the next k_step_t (k_flush
+//              applies pending records before the state is read).
 // Every kernel takes a table of members and a work table mapping each
 // workgroup to (member, local block), so one launch serves a whole ensemble.
 // All reductions have a fixed order that depends only on the member's own
