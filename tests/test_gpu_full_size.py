@@ -56,3 +56,38 @@ def test_fine_grid_480x240x240_plain():
     ev = rel_err(run.fields()[1], o.velocity()[1])
     _say(f"  velocity {ev:.2e}")
     assert ev <= 1e-5
+
+
+def test_paper_hf_grid_plain_rows_equal_a_thin_slab():
+    """The paper's HF grid, 1475 x 235 x 490 plain BGK in FP32 (170 M cells:
+    its populations exceed 4 GiB, so the step runs with 64-bit offsets and
+    non-temporal stores), started from a field that does not depend on x:
+    x-periodic streaming keeps every x row the same, so after 4 steps every
+    row must equal, bitwise, the rows of a 5 x 235 x 490 slab started from
+    the same field, which is itself checked against the oracle."""
+    lbm = need_gpu()
+    nx, ny, nz, steps = 1475, 235, 490, 4
+    cfg, _ = synth.channel_workload(5, ny, nz, substrate=0, cmodel=0.0, seed=13)
+    rng = np.random.default_rng(21)
+    yz = synth.channel_velocity(1, ny, nz, seed=13).reshape(3, nz, ny, 1)
+    yz = yz + 1e-3 * (2 * rng.random(yz.shape) - 1)
+    slab_u0 = np.ascontiguousarray(np.broadcast_to(yz, (3, nz, ny, 5))).reshape(3, -1)
+    _say("thin slab 5x235x490 vs oracle, 4 steps")
+    slab = gpu_run(lbm, cfg, slab_u0, "fp32")
+    slab.step(steps)
+    assert slab.sync() == 0
+    us = slab.fields()[1].reshape(3, nz, ny, 5)
+    o = oracle_run(cfg, slab_u0)
+    o.step(steps)
+    assert rel_err(us.reshape(3, -1), o.velocity()[1]) <= 1e-5
+    assert np.array_equal(us, np.broadcast_to(us[..., :1], us.shape))   # x-invariant
+    slab.close()
+    _say("HF grid 1475x235x490 plain, 4 steps")
+    big_cfg = dict(cfg, nx=nx)
+    big_u0 = np.broadcast_to(yz, (3, nz, ny, nx)).reshape(3, -1)
+    big = gpu_run(lbm, big_cfg, big_u0, "fp32")
+    big.step(steps)
+    assert big.sync() == 0
+    ub = big.fields()[1].reshape(3, nz, ny, nx)
+    big.close()
+    assert np.array_equal(ub, np.broadcast_to(us[..., :1], ub.shape))
