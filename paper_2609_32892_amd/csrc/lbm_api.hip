@@ -194,14 +194,15 @@ void make_plan(const lbm_config* c, const ClosureShape& cs, Plan* p)
     P.nbx2 = (plane + kBlock * P.cpt2 - 1) / (kBlock * P.cpt2);
     P.nbr = P.nbx2 * c->ny;
     {
-        // tile: 64 x 4 on 3-D grids whose rows are whole multiples of 64
-        // cells and at least 256 long (measured on MI355X: 9% less binomial
-        // time on a 384 x 192 x 192 channel)
+        // tile: 64 x 8 (512-thread workgroups) on 3-D grids whose rows are
+        // whole multiples of 64 cells and at least 256 long, else 32 x 8
+        // (measured on MI355X on a 384 x 192 x 192 channel: 64-wide tiles 9%
+        // less binomial time than 32 x 8; 64 x 8 another 6% less than 64 x 4)
         P.btx = c->tune_btx ? c->tune_btx : (P.D == 3 && c->nx % kBinTXW == 0 && c->nx >= 256 ? kBinTXW : kBinTX);
         // z chunk: as many planes per workgroup as keeps about 400 or more
         // workgroups (measured on MI355X: fewer staged halo planes pay more
         // than extra workgroups once the chip has 1.5 per CU)
-        const int bty = kBlock / P.btx;
+        const int bty = kBinTY;
         const int nxy = ((c->nx + P.btx - 1) / P.btx) * ((c->ny + bty - 1) / bty);
         P.zc = P.D == 3 ? (c->tune_zc > 0 ? std::min(c->tune_zc, c->nz)
                                            : std::max(1, std::min(kBinZCMax, nxy * c->nz / 400)))
@@ -992,7 +993,7 @@ int lbm_create(const lbm_config* cfg, const lbm_closure* closure, void* dev_aren
         rc = upload(c, A + plan.workr, wr.data(), sizeof(int2) * wr.size());
         std::vector<int2> wb(plan.nbb);
         {
-            const int ntx = (cfg->nx + plan.btx - 1) / plan.btx, nty = (cfg->ny + kBlock / plan.btx - 1) / (kBlock / plan.btx);
+            const int ntx = (cfg->nx + plan.btx - 1) / plan.btx, nty = (cfg->ny + kBinTY - 1) / kBinTY;
             const std::vector<int> o = xcd_tile_order(ntx, nty, plan.nbb / (ntx * nty));
             for (int b = 0; b < plan.nbb; ++b) wb[b] = make_int2(0, o[b]);
         }
@@ -1541,7 +1542,7 @@ static int batch_build(lbm_batch* b)
             for (int i : gm[gi]) {
                 const lbm_config& mc = b->mem[i]->cfg;
                 const int btx = b->mem[i]->plan.btx;
-                const int ntx = (mc.nx + btx - 1) / btx, nty = (mc.ny + kBlock / btx - 1) / (kBlock / btx);
+                const int ntx = (mc.nx + btx - 1) / btx, nty = (mc.ny + kBinTY - 1) / kBinTY;
                 const std::vector<int> o = xcd_tile_order(ntx, nty, b->mem[i]->plan.nbb / (ntx * nty));
                 for (int k = 0; k < b->mem[i]->plan.nbb; ++k) work.push_back(make_int2(i, o[k]));
             }

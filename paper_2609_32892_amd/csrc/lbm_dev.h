@@ -21,7 +21,7 @@ constexpr int kPopLog = 10;
 constexpr int kPopBlk = 1 << kPopLog;
 constexpr int kBinTX = 32;      // binomial-filter tile: x extent
 constexpr int kBinTY = kBlock / kBinTX;  // y extent
-constexpr int kBinTXW = 64;     // the wide tile (64 x 4) of the one-pass binomial kernel
+constexpr int kBinTXW = 64;     // the wide tile (64 x 8, 512 threads) of the tiled kernels
 constexpr int kBinZCMax = 16;   // most z planes per workgroup chosen automatically (3-D)
 constexpr int kHistRows = 512;   // LRS history rows (x entries) per k_sum workgroup
 constexpr int kMaxHistChunks = 64;                 // so 2 h nq <= 32768

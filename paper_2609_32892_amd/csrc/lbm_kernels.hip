@@ -102,16 +102,16 @@ __device__ __forceinline__ double wave_sum(double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Sum NV values over the workgroup (blockDim.x = kBlock); result valid in
-// thread 0.  Uses NV * 4 doubles of LDS.
-template <int NV>
+// Sum NV values over the workgroup of NW wavefronts; result valid in
+// thread 0.  Uses NV * NW doubles of LDS.
+template <int NV, int NW = kBlock / 64>
 __device__ __forceinline__ void block_sum(double* v, double* lds)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         double s = wave_sum(v[k]);
-        if (lane == 0) lds[k * (kBlock / 64) + wv] = s;
+        if (lane == 0) lds[k * NW + wv] = s;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -119,7 +119,7 @@ __device__ __forceinline__ void block_sum(double* v, double* lds)
         for (int k = 0; k < NV; ++k) {
             double s = 0;
 #pragma unroll
-            for (int j = 0; j < kBlock / 64; ++j) s += lds[k * (kBlock / 64) + j];
+            for (int j = 0; j < NW; ++j) s += lds[k * NW + j];
             v[k] = s;
         }
     }
@@ -632,17 +632,17 @@ __global__ __launch_bounds__(kBlock, MODE == 2 ? 1 : 8) void k_step(const DevMem
 #define LBM_STEPT_WAVES 4
 #endif
 template <int LAT, typename T, int PREC, int SUB, int TX, bool WT, bool A32 = true>
-__global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? LBM_STEPT_WAVES : 2) void k_step_t(const DevMember* __restrict__ mems,
+__global__ __launch_bounds__(TX * kBinTY, sizeof(T) == 4 ? LBM_STEPT_WAVES : 2) void k_step_t(const DevMember* __restrict__ mems,
                                                    const int2* __restrict__ work, int flip)
 {
     using L = Lat<LAT>;
     constexpr int Q = L::Q, D = L::D;
-    constexpr int TY = kBlock / TX, HX = TX + 2, HY = TY + 2, HXY = HX * HY;
+    constexpr int NT = TX * kBinTY, TY = kBinTY, HX = TX + 2, HY = TY + 2, HXY = HX * HY;
     constexpr int NR = 2 * D;                     // a, b
     constexpr int NSL = D == 3 ? 3 : 1;           // staged planes
-    constexpr int NE = (HXY + kBlock - 1) / kBlock;
+    constexpr int NE = (HXY + NT - 1) / NT;
     __shared__ T rs[NSL][NR + 1][HXY];            // a, b, e of the staged cells
-    __shared__ double lds[4 * (kBlock / 64)];
+    __shared__ double lds[4 * (NT / 64)];
     const int2 wk = work[blockIdx.x];
     KMember& m = *kc(mems + wk.x);
     const int N = m.N, nx = m.nx, ny = m.ny, nz = m.nz;
@@ -664,7 +664,7 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? LBM_STEPT_WAVES : 2) void 
     int eoff[NE];
 #pragma unroll
     for (int k = 0; k < NE; ++k) {
-        const int e = threadIdx.x + k * kBlock;
+        const int e = threadIdx.x + k * NT;
         const int hx = e % HX, hy = e / HX;
         const int gx = modi(tx0 + hx - 1, nx);
         int gy = ty0 + hy - 1;
@@ -684,7 +684,7 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? LBM_STEPT_WAVES : 2) void 
     auto stage = [&](int sl, const T (&buf)[NE][NR]) {
 #pragma unroll
         for (int k = 0; k < NE; ++k) {
-            const int e = threadIdx.x + k * kBlock;
+            const int e = threadIdx.x + k * NT;
             if (e < HXY) {
 #pragma unroll
                 for (int c = 0; c < NR; ++c) rs[sl][c][e] = buf[k][c];
@@ -747,7 +747,7 @@ __global__ __launch_bounds__(kBlock, sizeof(T) == 4 ? LBM_STEPT_WAVES : 2) void 
             __syncthreads();
         }
     }
-    block_sum<4>(st, lds);
+    block_sum<4, NT / 64>(st, lds);
     if (threadIdx.x == 0) {
         double* p = m.part_stats + (size_t)wk.y * 4;
         p[0] = st[0]; p[1] = st[1]; p[2] = st[2]; p[3] = st[3];
@@ -948,9 +948,9 @@ __device__ __forceinline__ T binom_at(const T* __restrict__ u, int x, int y, int
 
 // K2b, passes j >= 2: P_j = B P_{j-1} for j <= jv and W_j = B W_{j-1} with
 // C_{j-1} = curl^T W_{j-1} for j <= jw (pass 1 is k_binom1).
-// 2.5-D tiling: a workgroup owns a TX x TY tile of the xy plane (32 x 8, or
-// 64 x 4 on wide grids: each staged row then wastes fewer 128-byte lines on
-// its one-cell x halo) and a chunk of zc planes (chosen per grid for enough
+// 2.5-D tiling: a workgroup of 8 TX threads owns a TX x 8 tile of the xy
+// plane (32 x 8, or 64 x 8 on wide grids: each staged row then wastes fewer
+// 128-byte lines on its one-cell x halo) and a chunk of zc planes (chosen per grid for enough
 // workgroups); every plane of the chunk (plus one halo plane on each side)
 // is staged with its xy halo in LDS, filtered in x and y there, and the z
 // pass runs on a three-plane window kept in registers.
@@ -960,13 +960,13 @@ __device__ __forceinline__ T binom_at(const T* __restrict__ u, int x, int y, int
 // this pass does not advance either returns (CH = 1, 2) or re-reads the
 // other chain's source (CH = 3).
 template <int LAT, typename T, int TX, int CH, bool WT>
-__global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ mems, const int2* __restrict__ work,
+__global__ __launch_bounds__(TX * kBinTY) void k_binom(const DevMember* __restrict__ mems, const int2* __restrict__ work,
                                                   int j)
 {
     using L = Lat<LAT>;
     constexpr int D = L::D, NC = L::NC;
     constexpr int NV = (CH & 1) ? D : 0, NW = (CH & 2) ? NC : 0, NCMP = NV + NW;   // tile: v, then w
-    constexpr int TY = kBlock / TX;   // tile TX x TY (32 x 8 or 64 x 4)
+    constexpr int NT = TX * kBinTY, TY = kBinTY;   // tile TX x 8, one cell per thread
     constexpr int HX = TX + 2, HY = TY + 2, HXY = HX * HY;
     // the staged plane [component][halo tile]
     __shared__ T tile[NCMP * HXY];
@@ -1011,12 +1011,12 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
     const int zend = D == 3 ? min(tz0 + zc, nz) : 1;
     // the (at most two) halo elements this thread stages, as offsets within
     // a plane; an element outside the walls loads cell 0 and stages zero
-    constexpr int NE = (HXY + kBlock - 1) / kBlock;
+    constexpr int NE = (HXY + NT - 1) / NT;
     int eoff[NE];
     bool eok[NE];
 #pragma unroll
     for (int k = 0; k < NE; ++k) {
-        const int e = threadIdx.x + k * kBlock;
+        const int e = threadIdx.x + k * NT;
         const int hx = e % HX, hy = e / HX;
         int gx = tx0 + hx - 1;       // in [-1, nx + TX - 1]
         gx = gx < 0 ? gx + nx : (gx >= nx ? modi(gx, nx) : gx);
@@ -1039,7 +1039,7 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
     auto stage = [&](int pl, const T (&buf)[NE][NCMP]) {
 #pragma unroll
         for (int k = 0; k < NE; ++k) {
-            const int e = threadIdx.x + k * kBlock;
+            const int e = threadIdx.x + k * NT;
             if (e < HXY) {
 #pragma unroll
                 for (int c = 0; c < NCMP; ++c) tile[(pl * NCMP + c) * HXY + e] = eok[k] ? buf[k][c] : T(0);
@@ -1140,14 +1140,14 @@ __global__ __launch_bounds__(kBlock) void k_binom(const DevMember* __restrict__ 
 // parts, w lagging v* by one plane.  ZC: some member of the launch has Z
 // QoIs (otherwise only B v* is formed).
 template <int LAT, typename T, int TX, bool ZC, bool WT>
-__global__ __launch_bounds__(kBlock) void k_binom1(const DevMember* __restrict__ mems, const int2* __restrict__ work)
+__global__ __launch_bounds__(TX * kBinTY) void k_binom1(const DevMember* __restrict__ mems, const int2* __restrict__ work)
 {
     using L = Lat<LAT>;
     constexpr int D = L::D, NC = L::NC;
-    constexpr int TY = kBlock / TX;
+    constexpr int NT = TX * kBinTY, TY = kBinTY;
     constexpr int HX1 = TX + 2, HY1 = TY + 2, HXY1 = HX1 * HY1;   // tile and one-cell halo
     constexpr int HX2 = TX + 4, HY2 = TY + 4, HXY2 = HX2 * HY2;   // tile and two-cell halo
-    constexpr int NE1 = (HXY1 + kBlock - 1) / kBlock, NE2 = (HXY2 + kBlock - 1) / kBlock;
+    constexpr int NE1 = (HXY1 + NT - 1) / NT, NE2 = (HXY2 + NT - 1) / NT;
     constexpr int NSL = D == 3 ? 3 : 1;
     __shared__ T vt[NSL][D][HXY2];
     __shared__ T wt[ZC ? NC : 1][ZC ? HXY1 : 1];
@@ -1179,7 +1179,7 @@ __global__ __launch_bounds__(kBlock) void k_binom1(const DevMember* __restrict__
     bool eok[NE2];
 #pragma unroll
     for (int k = 0; k < NE2; ++k) {
-        const int e = threadIdx.x + k * kBlock;
+        const int e = threadIdx.x + k * NT;
         const int gx = modi(tx0 + e % HX2 - 2, nx);
         int gy = ty0 + e / HX2 - 2;
         bool ok = e < HXY2;
@@ -1192,7 +1192,7 @@ __global__ __launch_bounds__(kBlock) void k_binom1(const DevMember* __restrict__
     bool wok[NE1];
 #pragma unroll
     for (int k = 0; k < NE1; ++k) {
-        const int e = threadIdx.x + k * kBlock;
+        const int e = threadIdx.x + k * NT;
         const int gy = ty0 + e / HX1 - 1;
         wok[k] = e < HXY1 && !(m.walls && (gy < 0 || gy >= ny));
     }
@@ -1207,7 +1207,7 @@ __global__ __launch_bounds__(kBlock) void k_binom1(const DevMember* __restrict__
     auto stage = [&](int sl, const T (&buf)[NE2][D]) {
 #pragma unroll
         for (int k = 0; k < NE2; ++k) {
-            const int e = threadIdx.x + k * kBlock;
+            const int e = threadIdx.x + k * NT;
             if (e < HXY2) {
 #pragma unroll
                 for (int a = 0; a < D; ++a) vt[sl][a][e] = eok[k] ? buf[k][a] : T(0);
@@ -1227,7 +1227,7 @@ __global__ __launch_bounds__(kBlock) void k_binom1(const DevMember* __restrict__
     auto curl_tile = [&](int s0, int s1, int s2) {
 #pragma unroll
         for (int k = 0; k < NE1; ++k) {
-            const int e = threadIdx.x + k * kBlock;
+            const int e = threadIdx.x + k * NT;
             if (e >= HXY1) continue;
             const int p = (e / HX1 + 1) * HX2 + e % HX1 + 1;
             T w[3];
@@ -2743,13 +2743,13 @@ static void launch_step_group(const LaunchGroup& g, hipStream_t st, int flip, hi
 #define LBM_STEP_T(SUB, TXV)                                                                               \
     do {                                                                                                   \
         if (!g.a32)                                                                                        \
-            hipLaunchKernelGGL((k_step_t<LAT, T, PREC, SUB, TXV, false, false>), dim3(g.nbb), blk, 0, st, \
+            hipLaunchKernelGGL((k_step_t<LAT, T, PREC, SUB, TXV, false, false>), dim3(g.nbb), dim3(TXV * kBinTY), 0, st, \
                                g.mems, g.workb, flip);                                                     \
         else if (g.wt)                                                                                     \
-            hipLaunchKernelGGL((k_step_t<LAT, T, PREC, SUB, TXV, true>), dim3(g.nbb), blk, 0, st, g.mems,  \
+            hipLaunchKernelGGL((k_step_t<LAT, T, PREC, SUB, TXV, true>), dim3(g.nbb), dim3(TXV * kBinTY), 0, st, g.mems,  \
                                g.workb, flip);                                                             \
         else                                                                                               \
-            hipLaunchKernelGGL((k_step_t<LAT, T, PREC, SUB, TXV, false>), dim3(g.nbb), blk, 0, st, g.mems, \
+            hipLaunchKernelGGL((k_step_t<LAT, T, PREC, SUB, TXV, false>), dim3(g.nbb), dim3(TXV * kBinTY), 0, st, g.mems, \
                                g.workb, flip);                                                             \
     } while (0)
 #define LBM_STEP_SUB(SUB)                                                                                  \
@@ -2812,8 +2812,8 @@ to_chain:
         if (!g.kf && g.npass >= 1) {
 #define LBM_BINOM1(TXV, ZCV)                                                                                    \
     do {                                                                                                        \
-        if (g.wt) hipLaunchKernelGGL((k_binom1<LAT, T, TXV, ZCV, true>), dim3(g.nbb), blk, 0, st, g.mems, g.workb); \
-        else hipLaunchKernelGGL((k_binom1<LAT, T, TXV, ZCV, false>), dim3(g.nbb), blk, 0, st, g.mems, g.workb); \
+        if (g.wt) hipLaunchKernelGGL((k_binom1<LAT, T, TXV, ZCV, true>), dim3(g.nbb), dim3(TXV * kBinTY), 0, st, g.mems, g.workb); \
+        else hipLaunchKernelGGL((k_binom1<LAT, T, TXV, ZCV, false>), dim3(g.nbb), dim3(TXV * kBinTY), 0, st, g.mems, g.workb); \
     } while (0)
             if (Lat<LAT>::D == 3 && g.btx == kBinTXW) {
                 if (g.any_z) LBM_BINOM1((Lat<LAT>::D == 3 ? kBinTXW : kBinTX), true);
@@ -2826,8 +2826,8 @@ to_chain:
         for (int j = 2; j <= (g.kf ? 0 : g.npass); ++j) {
 #define LBM_BINOM(TXV, CHV)                                                                                    \
     do {                                                                                                       \
-        if (g.wt) hipLaunchKernelGGL((k_binom<LAT, T, TXV, CHV, true>), dim3(g.nbb), blk, 0, st, g.mems, g.workb, j); \
-        else hipLaunchKernelGGL((k_binom<LAT, T, TXV, CHV, false>), dim3(g.nbb), blk, 0, st, g.mems, g.workb, j); \
+        if (g.wt) hipLaunchKernelGGL((k_binom<LAT, T, TXV, CHV, true>), dim3(g.nbb), dim3(TXV * kBinTY), 0, st, g.mems, g.workb, j); \
+        else hipLaunchKernelGGL((k_binom<LAT, T, TXV, CHV, false>), dim3(g.nbb), dim3(TXV * kBinTY), 0, st, g.mems, g.workb, j); \
     } while (0)
             const int ch = g.bmask[j - 1];
             if (g.btx == kBinTXW) {

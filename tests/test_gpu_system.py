@@ -123,7 +123,7 @@ def test_invalid_arguments_rejected():
 
 @pytest.mark.parametrize("walls", [1, 0])
 def test_binomial_tile_widths_bitwise_equal(walls):
-    """The 64 x 4 tile of the one-pass binomial kernel gives bitwise the
+    """The 64 x 8 tile of the tiled kernels gives bitwise the
     result of the 32 x 8 tile (rows of 128 cells, a ragged y extent, z
     chunks of 1 and 3 planes)."""
     lbm = need_gpu()
