@@ -58,7 +58,7 @@ def test_fourier_lrs_parity(name, prec):
     else:
         # velocity: the stated 1e-5; q*, dQ about ten times the measured
         # 1.6e-6 and 2.1e-6
-        assert ev <= 1e-5 and eq <= 2e-5 and edq <= 3e-5
+        assert ev <= 1e-5 and eq <= 1e-5 and edq <= 1e-5   # measured 5.6e-7, 9.8e-7, 6.5e-7
 
 
 def test_fourier_member_in_batch_bitwise():

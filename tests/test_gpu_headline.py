@@ -5,8 +5,8 @@ periodic; Smagorinsky C_s = 0.1; 12 QoIs {E, Z} x {B^2, B - B^2, I - B} and
 six mean-profile bands; LRS h = 0) with the correction active from step 4,
 over 200 steps.  FP32 shifted populations: max relative velocity error
 <= 1e-5 (the stated bar), QoIs per step <= 1e-4, dQ and gamma per step
-<= 1e-2 of each QoI's largest |dQ| and |gamma| (about ten times the
-measured 9e-4 and 7e-4).  FP64: the stated 1e-12, or ten times the
+<= 5e-3 of each QoI's largest |dQ| and |gamma| (about ten and twenty
+times the measured 4.3e-4 and 2.5e-4).  FP64: the stated 1e-12, or ten times the
 workload's own FP64 resolution where that is larger -- the oracle against
 its twins (started one ulp away; global sums in reverse order): the 12-QoI
 Gram system is near-singular, so last-bit differences grow every step."""
@@ -60,7 +60,7 @@ def test_headline_channel_fp32_200_steps(reference):
     assert run.sync() == 0
     ev, eq, edq, eg = _errors(run, uo, ro)
     _say(f"  FP32: velocity {ev:.2e}  q {eq:.2e}  dq {edq:.2e}  gamma {eg:.2e}")
-    assert ev <= 1e-5 and eq <= 1e-4 and edq <= 1e-2 and eg <= 1e-2
+    assert ev <= 1e-5 and eq <= 1e-4 and edq <= 5e-3 and eg <= 5e-3
 
 
 def test_headline_channel_fp64_200_steps(reference):
