@@ -87,7 +87,8 @@ typedef struct {
                            forces 64-bit population offsets, bit 1 non-temporal population
                            stores in plain runs, bit 2 the SGS change recorded and applied
                            by the next step's pull (binomial closures, BGK or Smagorinsky
-                           substrate) also where the populations fit the L2s; bitwise the
+                           substrate) also where the populations (up to 192 MB) would
+                           apply it in place; bitwise the
                            same result either way (for tests of the large-grid forms) */
 } lbm_config;
 

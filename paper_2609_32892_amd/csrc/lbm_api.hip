@@ -386,19 +386,19 @@ struct lbm_ctx {
     long gver = -1;
     int gchunk = 32;
     int mode() const { return cur.nq > 0 ? 2 : (cfg.diag ? 1 : 0); }
-    // TO steps record the SGS change for the next step's pull (all
-    // substrates but WALE, whose gradients read the complete state)
     // The SGS change goes into the next step's pull (a record per cell)
     // except with the WALE substrate, whose velocity gradients need the
-    // complete post-streaming state, and on grids whose populations fit the
-    // L2s (written through; measured on MI355X: 2659 -> 2714 MLUPS on the
-    // 96 x 48 x 48 channel, 2295 -> 2375 on the 256^2 Kolmogorov flow, where
-    // the tiled pull with its staged records costs more than the in-place
-    // apply saves).  Either way the result is bitwise the same.
+    // complete post-streaming state, and on grids whose populations stay in
+    // the 256 MB Infinity Cache (up to 192 MB), where the in-place apply is
+    // cheaper than the tiled pull with its staged records (measured on
+    // MI355X, FP32 channel TO-LES: 96 x 48 x 48 2659 -> 2714 MLUPS, 295 x 47
+    // x 98 3866 -> 4230, 192 x 96 x 96 4858 -> 4897; at 256 x 128 x 128, 304
+    // MB of populations, the record form is faster, 6329 against 5938).
+    // Either way the result is bitwise the same.
     bool defers() const
     {
         return mode() == 2 && cfg.substrate != LBM_WALE &&
-               ((cfg.tune_mem & 4) || !write_through((double)plan.N * plan.Q * plan.esz));
+               ((cfg.tune_mem & 4) || (double)plan.N * plan.Q * plan.esz > 192.0 * 1024 * 1024);
     }
 };
 
