@@ -283,10 +283,12 @@ constexpr int kXcd = 8;
 // 96 x 48 x 48 channel, slower on 295 x 47 x 98, whose fields the next
 // kernel otherwise finds in the Infinity Cache).
 int write_through(double pop_bytes) { return pop_bytes <= 24.0 * 1024 * 1024; }
-// Plain stream-collide launches whose population buffers are well beyond
-// the 256 MB Infinity Cache store non-temporally; smaller ones keep their
-// populations in it from one step to the next.
-int non_temporal(double pop_bytes) { return pop_bytes >= 1024.0 * 1024 * 1024; }
+// Plain stream-collide launches whose population buffer exceeds half the
+// 256 MB Infinity Cache store non-temporally; smaller ones keep their
+// populations in it from one step to the next (measured on MI355X, plain
+// BGK channels: non-temporal stores -5% at 74 MB and -9% at 98 MB, +4% at
+// 145 MB, +6-8% from 204 to 594 MB, equal beyond 1 GB).
+int non_temporal(double pop_bytes) { return pop_bytes >= 128.0 * 1024 * 1024; }
 std::vector<int> xcd_order(int n)
 {
     std::vector<int> order;
