@@ -227,6 +227,32 @@ def test_deferred_and_in_place_sgs_change_bitwise_equal(case):
         r.close()
 
 
+def test_batch_mixing_both_sgs_forms_bitwise_equal_to_solo():
+    """A batch whose members take different SGS forms (one recording the
+    change for the next pull, forced with tune_mem, one applying it in
+    place) launches them in separate groups; each member equals its solo
+    run bitwise, and the two forms equal each other."""
+    lbm = need_gpu()
+    cfg, u0 = synth.channel_workload(40, 18, 10, seed=8)
+    qois, cargs = closure_args("3d", ny=18, spinup=3)
+    solo = [gpu_run(lbm, cfg, u0, "fp32", qois, cargs, tune_mem=t) for t in (0, 4)]
+    for r in solo:
+        r.step(11)
+        r.sync()
+    members = [gpu_run(lbm, cfg, u0, "fp32", qois, cargs, tune_mem=t) for t in (0, 4)]
+    batch = lbm.Batch(members)
+    batch.step(11)
+    assert batch.sync() == 0
+    ref = solo[0].get_populations()
+    for r, s_ in zip(members, solo):
+        f = r.get_populations()
+        assert np.array_equal(f, s_.get_populations())
+        assert np.array_equal(f, ref)
+    batch.close()
+    for r in members + solo:
+        r.close()
+
+
 def test_write_through_and_plain_stores_bitwise_equal():
     """Launches whose populations fit the L2s store their fields through it,
     larger ones with plain stores; a batch decides for all its members
