@@ -490,7 +490,7 @@ int upload(lbm_ctx* c, void* dst, const void* src, size_t bytes)
 void drop_graphs(lbm_ctx* c)
 {
     for (int k = 0; k < 2; ++k) {
-        for (auto& kv : c->gexec[k]) hipGraphExecDestroy(kv.second);
+        for (auto& kv : c->gexec[k]) (void)hipGraphExecDestroy(kv.second);
         c->gexec[k].clear();
     }
     c->gver = -1;
@@ -874,7 +874,7 @@ int capture(hipStream_t st, const std::vector<LaunchGroup>& groups, int nsteps, 
     hipError_t e = hipStreamEndCapture(st, &graph);
     if (e != hipSuccess) return fail(LBM_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
     e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(LBM_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
     // move the executable graph to the device now, so that its first launch
     // does not pay for the upload
@@ -1027,10 +1027,10 @@ int lbm_create(const lbm_config* cfg, const lbm_closure* closure, void* dev_aren
     }
     if (!rc && closure) rc = apply_closure(c, closure);
     if (rc) {
-        if (c->qref_dev) hipFree(c->qref_dev);
-        if (c->chist_dev) hipFree(c->chist_dev);
+        if (c->qref_dev) (void)hipFree(c->qref_dev);
+        if (c->chist_dev) (void)hipFree(c->chist_dev);
         drop_fourier(c);
-        if (c->own_stream) hipStreamDestroy(c->stream);
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
         delete c;
         return rc;
     }
@@ -1041,13 +1041,13 @@ int lbm_create(const lbm_config* cfg, const lbm_closure* closure, void* dev_aren
 void lbm_destroy(lbm_ctx* c)
 {
     if (!c) return;
-    hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
-    if (c->qref_dev) hipFree(c->qref_dev);
-    if (c->chist_dev) hipFree(c->chist_dev);
-    if (c->proj_tmp) hipFree(c->proj_tmp);
+    if (c->qref_dev) (void)hipFree(c->qref_dev);
+    if (c->chist_dev) (void)hipFree(c->chist_dev);
+    if (c->proj_tmp) (void)hipFree(c->proj_tmp);
     drop_fourier(c);
-    if (c->own_stream) hipStreamDestroy(c->stream);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
 
@@ -1082,7 +1082,7 @@ int lbm_init_velocity(lbm_ctx* c, const double* rho, const double* u)
     int rc = upload(c, buf, u, sizeof(double) * D * N);
     if (!rc && rho) rc = upload(c, buf + D * N, rho, sizeof(double) * N);
     if (!rc) rc = init_from_device(c, rho ? buf + D * N : nullptr, buf);
-    hipFree(buf);
+    (void)hipFree(buf);
     return rc;
 }
 
@@ -1226,7 +1226,7 @@ int lbm_fields(lbm_ctx* c, double* rho, double* u)
                 rc = fail(LBM_EDEVICE, "copy failed");
         }
     }
-    hipFree(buf);
+    (void)hipFree(buf);
     return rc;
 }
 
@@ -1305,7 +1305,7 @@ int lbm_get_populations(lbm_ctx* c, double* f)
     int rc = LBM_OK;
     if (hipStreamSynchronize(c->stream) != hipSuccess || hipMemcpy(f, buf, sizeof(double) * n, hipMemcpyDeviceToHost) != hipSuccess)
         rc = fail(LBM_EDEVICE, "population read failed");
-    hipFree(buf);
+    (void)hipFree(buf);
     return rc;
 }
 
@@ -1322,7 +1322,7 @@ int lbm_set_populations(lbm_ctx* c, const double* f)
                      buf, nullptr);
         if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(LBM_EDEVICE, "population write failed");
     }
-    hipFree(buf);
+    (void)hipFree(buf);
     c->version++;
     return rc;
 }
@@ -1382,7 +1382,7 @@ int lbm_project_state_kind(lbm_ctx* f, lbm_ctx* c, int m, int kind)
                      nullptr);
         if (hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(LBM_EDEVICE, "population write failed");
     }
-    hipFree(buf);
+    (void)hipFree(buf);
     if (!rc) rc = reset_ctl(c);
     c->version++;
     return rc;
@@ -1491,12 +1491,12 @@ int lbm_set_state(lbm_ctx* c, const void* host, size_t bytes)
 static void batch_free_dev(lbm_batch* b)
 {
     for (int k = 0; k < 2; ++k) {
-        for (auto& kv : b->gexec[k]) hipGraphExecDestroy(kv.second);
+        for (auto& kv : b->gexec[k]) (void)hipGraphExecDestroy(kv.second);
         b->gexec[k].clear();
     }
-    if (b->dmem) hipFree(b->dmem);
-    if (b->dwork) hipFree(b->dwork);
-    if (b->dworkm) hipFree(b->dworkm);
+    if (b->dmem) (void)hipFree(b->dmem);
+    if (b->dwork) (void)hipFree(b->dwork);
+    if (b->dworkm) (void)hipFree(b->dworkm);
     b->dmem = nullptr;
     b->dwork = nullptr;
     b->dworkm = nullptr;
@@ -1709,7 +1709,7 @@ int lbm_batch_sync(lbm_batch* b)
 void lbm_batch_destroy(lbm_batch* b)
 {
     if (!b) return;
-    hipStreamSynchronize(b->stream);
+    (void)hipStreamSynchronize(b->stream);
     batch_free_dev(b);
     delete b;
 }
@@ -1762,8 +1762,8 @@ int lbm_test_philox(const uint32_t* in6, uint32_t* out4, int n)
     launch_philox_test(din, dout, n, nullptr);
     HIPCHK(hipDeviceSynchronize());
     HIPCHK(hipMemcpy(out4, dout, sizeof(uint32_t) * 4 * n, hipMemcpyDeviceToHost));
-    hipFree(din);
-    hipFree(dout);
+    (void)hipFree(din);
+    (void)hipFree(dout);
     return LBM_OK;
 }
 
@@ -1775,7 +1775,7 @@ int lbm_test_normals(uint64_t seed, long step0, int nsteps, int n, double* out)
     launch_normals_test(seed, step0, nsteps, n, d, nullptr);
     HIPCHK(hipDeviceSynchronize());
     HIPCHK(hipMemcpy(out, d, sizeof(double) * (size_t)nsteps * n, hipMemcpyDeviceToHost));
-    hipFree(d);
+    (void)hipFree(d);
     return LBM_OK;
 }
 

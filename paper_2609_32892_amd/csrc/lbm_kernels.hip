@@ -340,7 +340,7 @@ __device__ __forceinline__ void gather(KMember& m, const T* __restrict__ gs, int
 {
     using L = Lat<LAT>;
     constexpr int Q = L::Q, D = L::D;
-    const int N = m.N, nx = m.nx, ny = m.ny, nz = m.nz;
+    const int nx = m.nx, ny = m.ny, nz = m.nz;
     // Wavefronts whose cells are all at least one cell from the walls and
     // from the z wrap pull from constant offsets, corrected per cell for the
     // periodic x wrap; the others resolve wrap and bounce-back per population.
