@@ -161,3 +161,36 @@ def test_zero_steps():
     assert run.step_count == 3
     assert np.array_equal(run.get_populations(), f0)
     assert run.record_arrays()["q"].shape[0] == 3
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_singular_gram_skips_the_correction(prec):
+    """The method's degenerate case: a uniform flow (periodic, unforced)
+    stays uniform, so (I - B) v* = 0 and the Gram matrix of {E_B, E_(I-B)}
+    is singular.  Every corrected step is flagged (record flag bit 1, as the
+    oracle flags it), gamma is zero and the correction is skipped: the
+    populations equal, bitwise, those of the same run with the closure off."""
+    lbm = need_gpu()
+    n, steps = 16, 10
+    cfg = dict(lattice=0, nx=n, ny=n, nz=1, walls_y=0, tau=0.6, substrate=0, cmodel=0.0,
+               force_kind=0, force_amp=0.0, force_k=0, drag=0.0)
+    u0 = np.zeros((2, n * n))
+    u0[0], u0[1] = 0.01, -0.005
+    qois = [("E", "B", 0), ("E", "IMB", 0)]
+    C, mu, S = synth.lrs_model(2, 3, 4, 5)
+    cargs = dict(mode="lrs", spinup=2, C=C, mu=mu, Sigma=S, seed=3)
+    run = gpu_run(lbm, cfg, u0, prec, qois, cargs)
+    off = gpu_run(lbm, cfg, u0, prec, qois, dict(mode="off"))
+    for r in (run, off):
+        r.step(steps)
+        r.sync()
+    rg = run.record_arrays()
+    o = oracle_run(cfg, u0, qois, cargs)
+    o.step(steps)
+    ro = o.record_arrays()
+    _say(f"singular Gram {prec}: flags {rg['flags'].tolist()}")
+    assert np.all(ro["flags"][2:] & 2) and np.array_equal(rg["flags"], ro["flags"])
+    assert np.all(rg["gamma"] == 0) and np.any(rg["dq"][2:] != 0)
+    assert np.array_equal(run.get_populations(), off.get_populations())
+    if prec == "fp64":
+        assert rel_err(run.fields()[1], o.velocity()[1]) <= 1e-12
