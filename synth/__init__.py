@@ -197,6 +197,19 @@ def channel_bands(ny: int, nb: int = 6):
     return nb, 0.5, ny / 2.0
 
 
+def largest_closure_workload():
+    """The largest closure the library takes (16 QoIs) on the 20 x 24 x 12
+    channel: energy and enstrophy of the four binomial filter forms (B, B^2,
+    B - B^2, I - B) and eight mean-profile bands, with an LRS model from
+    the fifth step.  Returns (cfg, u0, qois, closure arguments)."""
+    cfg, u0 = channel_workload(20, 24, 12, substrate=1, cmodel=0.1)
+    qois = [(k, f, 0) for f in ("B", "B2", "BMID", "IMB") for k in ("E", "Z")] + [("MP", "I", j) for j in range(8)]
+    C, mu, S = lrs_model_channel(16, 7, 9)
+    nb, dmin, dmax = channel_bands(24, 8)
+    cargs = dict(mode="lrs", spinup=5, C=C, mu=mu, Sigma=S, seed=5, nbands=nb, dmin=dmin, dmax=dmax)
+    return cfg, u0, qois, cargs
+
+
 # ---------------------------------------------------------------------------
 # Ensembles and request traces
 # ---------------------------------------------------------------------------

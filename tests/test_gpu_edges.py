@@ -194,3 +194,53 @@ def test_singular_gram_skips_the_correction(prec):
     assert np.array_equal(run.get_populations(), off.get_populations())
     if prec == "fp64":
         assert rel_err(run.fields()[1], o.velocity()[1]) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_largest_closure_sixteen_qois(prec):
+    """The largest closure the library takes: 16 QoIs, 8 of them energy and
+    enstrophy of the four binomial filter forms (B, B^2, B - B^2, I - B) and
+    8 mean-profile bands, on the 20 x 24 x 12 channel with an LRS closure;
+    a 16 x 16 Gram system each step.
+
+    The four forms are nearly linearly dependent (B = (B - B^2) + B^2) and
+    the bands overlap, so the Gram matrix of the patterns, scaled to unit
+    diagonal, has a condition number near 3e7 at the first correction (an
+    oracle test checks this).  FP64 is compared everywhere, within the
+    workload's own resolution bars.  In FP32 the pattern rounding (a few
+    ulp of the filtered fields) reaches gamma amplified by up to that
+    condition number, and through gamma every later step; there the run is
+    compared where no solve has intervened: q* up to the first corrected
+    step and that step's dQ, to 1e-5 of each QoI's largest value, and the
+    flags over the run."""
+    lbm = need_gpu()
+    cfg, u0, qois, cargs = synth.largest_closure_workload()
+    steps, first = 30, cargs["spinup"]
+    _say(f"largest closure {prec}: 16 QoIs on 20x24x12")
+    run = gpu_run(lbm, cfg, u0, prec, qois, cargs)
+    run.step(steps)
+    assert run.sync() == 0
+    o = oracle_run(cfg, u0, qois, cargs)
+    o.step(steps)
+    rg, ro = run.record_arrays(), o.record_arrays()
+    ev = rel_err(run.fields()[1], o.velocity()[1])
+
+    def per_qoi(key, rows=slice(None)):
+        sc = np.max(np.abs(ro[key]), axis=0) + 1e-300
+        return float(np.max(np.abs(rg[key][rows] - ro[key][rows]) / sc))
+
+    eq, edq, eg = per_qoi("q"), per_qoi("dq"), per_qoi("gamma")
+    _say(f"  velocity {ev:.2e}  q {eq:.2e}  dq {edq:.2e}  gamma {eg:.2e}")
+    assert np.array_equal(rg["flags"], ro["flags"]) and not np.any(ro["flags"])
+    assert np.all(np.any(ro["dq"][first:] != 0, axis=0))
+    if prec == "fp64":
+        floor = oracle_floor(cfg, u0, qois, cargs, steps, ref=o)
+        bars = fp64_bars(floor)
+        _say(f"  oracle floor: {np.array2string(floor, precision=2)}")
+        assert ev <= bars[0] and eq <= bars[1] and edq <= bars[2] and eg <= bars[3]
+    else:
+        eq0, edq0 = per_qoi("q", slice(0, first + 1)), per_qoi("dq", slice(first, first + 1))
+        _say(f"  before any solve: q {eq0:.2e}  first dQ {edq0:.2e}")
+        assert eq0 <= 1e-5 and edq0 <= 1e-5
+        assert all(np.all(np.isfinite(rg[k])) for k in ("q", "dq", "gamma"))
+        assert np.all(np.isfinite(run.fields()[1]))

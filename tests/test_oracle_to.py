@@ -188,6 +188,29 @@ def test_gram_singular_rule(orc):
     assert sing and np.all(dv == 0) and np.all(gamma == 0)
 
 
+def test_largest_closure_gram_conditioning(orc):
+    """The Gram matrix of the 16-QoI closure (E and Z of B, B^2, B - B^2 and
+    I - B, eight overlapping mean-profile bands), scaled to unit diagonal,
+    is ill-conditioned at the first corrected step of the 20 x 24 x 12
+    channel: a condition number above 1e7 (the four filter forms are nearly
+    dependent), where the standard 12-QoI set ({E, Z} x {B^2, B - B^2,
+    I - B}, six bands) stays below 1e6.  This fixes how far the FP32 path
+    can follow the oracle through the solve on that closure."""
+    cfg, u0, qois, cargs = synth.largest_closure_workload()
+    o = orc.Oracle(**cfg)
+    o.init(u0)
+    o.step(cargs["spinup"] + 1)
+    _, v = o.post_collision_velocity()
+
+    def cond(q, nb):
+        cl = orc.make_closure(q, nbands=nb, dmin=cargs["dmin"], dmax=cargs["dmax"])
+        G = o.patterns(cl, v)["G"]
+        d = np.sqrt(np.diag(G))
+        return float(np.linalg.cond(G / np.outer(d, d)))
+
+    assert cond(qois, 8) > 1e7 and cond(synth.QOIS_3D, 6) < 1e6
+
+
 @pytest.mark.parametrize("lat", [0, 1])
 def test_sgs_moment_identities_in_step(orc, lat):
     """The SGS correction changes f^p by feq(rho, v*+dv) - feq(rho, v*): mass
