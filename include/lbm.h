@@ -88,8 +88,10 @@ typedef struct {
                            stores in plain runs, bit 2 the SGS change recorded and applied
                            by the next step's pull (binomial closures, BGK or Smagorinsky
                            substrate) also where the populations (up to 192 MB) would
-                           apply it in place; bitwise the
-                           same result either way (for tests of the large-grid forms) */
+                           apply it in place, bit 3 the closure's solve in a launch of its
+                           own also where the apply would form it (binomial closures on
+                           grids of at most 1024 blocks of 256 cells); bitwise the same
+                           result either way (for tests of the large-grid forms); 0..15 */
 } lbm_config;
 
 enum { LBM_QOI_E = 0, LBM_QOI_Z = 1, LBM_QOI_MP = 2 };

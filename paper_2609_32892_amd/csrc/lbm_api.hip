@@ -160,7 +160,7 @@ int check_config(const lbm_config* c)
     if (c->force_kind < LBM_FORCE_NONE || c->force_kind > LBM_FORCE_CONST_X) return fail(LBM_EINVAL, "bad force kind");
     if (c->rec_cap < 0) return fail(LBM_EINVAL, "rec_cap < 0");
     if (c->tune_zc < 0 || c->tune_cpt < 0) return fail(LBM_EINVAL, "tuning values must be >= 0");
-    if (c->tune_mem < 0 || c->tune_mem > 7) return fail(LBM_EINVAL, "tune_mem must be in 0..7");
+    if (c->tune_mem < 0 || c->tune_mem > 15) return fail(LBM_EINVAL, "tune_mem must be in 0..15");
     if (c->tune_btx != 0 && c->tune_btx != kBinTX && c->tune_btx != kBinTXW)
         return fail(LBM_EINVAL, "tune_btx must be 0, %d or %d", kBinTX, kBinTXW);
     if (c->tune_btx == kBinTXW && c->lattice != LBM_D3Q19)
@@ -460,6 +460,7 @@ LaunchGroup ctx_group(const lbm_ctx* c)
     g.a32 = (double)c->plan.popn * c->plan.esz < 4294967296.0 && !(c->cfg.tune_mem & 1);
     g.nt = non_temporal((double)c->plan.popn * c->plan.esz) || (c->cfg.tune_mem & 2);
     g.defer = c->defers();
+    g.sep_solve = (c->cfg.tune_mem & 8) != 0;
     add_pass_masks(c, g);
     g.kf = c->cur.kf;
     g.kjobs = (const KJob*)(c->arena + c->plan.kjobs);
@@ -820,6 +821,7 @@ int apply_closure(lbm_ctx* c, const lbm_closure* cl)
     HIPCHK(hipMemcpyAsync(&ctl, c->arena + c->plan.ctl, sizeof ctl, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     ctl.s_set = 0;
+    ctl.s_pend = 0;
     rc = upload(c, c->arena + c->plan.ctl, &ctl, sizeof ctl);
     if (rc) return rc;
     c->hp = p;
@@ -1508,13 +1510,13 @@ static int batch_build(lbm_batch* b)
     batch_free_dev(b);
     const int n = (int)b->mem.size();
     // group members by kernel kind
-    struct Key { int lat, prec, sub, mode, sab, btx, kfm, def; };   // kfm: kernel-filter member (own group)
+    struct Key { int lat, prec, sub, mode, sab, btx, kfm, def, sep; };   // kfm: kernel-filter member (own group)
     std::vector<Key> keys;
     std::vector<std::vector<int>> gm;
     for (int i = 0; i < n; ++i) {
         const lbm_ctx* c = b->mem[i];
         Key k{c->cfg.lattice, c->cfg.precision, c->cfg.substrate, c->mode(), c->cur.nsa <= 2 ? 2 : (c->cur.nsa <= 6 ? 6 : 8),
-              c->plan.btx, c->mode() == 2 && c->cur.kf ? i : -1, (int)c->defers()};
+              c->plan.btx, c->mode() == 2 && c->cur.kf ? i : -1, (int)c->defers(), (c->cfg.tune_mem & 8) != 0};
         int gi = -1;
         for (size_t j = 0; j < keys.size(); ++j)
             if (!memcmp(&keys[j], &k, sizeof k)) gi = (int)j;
@@ -1599,6 +1601,7 @@ static int batch_build(lbm_batch* b)
             g.maxsa = std::max(g.maxsa, c->cur.nsa);
             g.npass = std::max(g.npass, binom_passes(c->cur));
             g.defer = c->defers();   // (members of a group share mode and substrate)
+            g.sep_solve = (c->cfg.tune_mem & 8) != 0;
             add_pass_masks(c, g);
             if (keys[gi].kfm >= 0) {
                 g.kf = 1;
@@ -1746,7 +1749,7 @@ int lbm_profile_phases(lbm_ctx* c, long nsteps, double* ms, int* launches)
         launches[1] = m == 2 && g.kf && g.any_z ? 1 : 0;
         launches[2] = m == 2 ? (g.kf ? g.nklev : g.npass) : 0;
         launches[3] = m == 2 ? 1 : 0;
-        launches[4] = m == 2 ? 2 : 0;   // cross-block sums, solve
+        launches[4] = m == 2 ? (fused_solve(g) ? 1 : 2) : 0;   // cross-block sums, solve (unless the apply forms it)
         launches[5] = m == 2 ? 1 : (m == 1 ? 2 : 0);
     }
     return rc;

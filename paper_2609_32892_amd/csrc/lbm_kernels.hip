@@ -1774,6 +1774,17 @@ __global__ __launch_bounds__(kBlock) void k_sum(const DevMember* __restrict__ me
         return;
     }
     if (slot >= 4 + m.npart) return;
+    if (slot == 0 && threadIdx.x == 0) {
+        // the step this launch belongs to, for a fused apply, and a first LRS
+        // scale that the last fused apply left pending
+        DevCtl* ctl = m.ctl;
+        ctl->step_snap = ctl->step;
+        if (ctl->s_pend) {
+            for (int k = 0; k < kMaxQ; ++k) ctl->s[k] = ctl->s_next[k];
+            ctl->s_set = 1;
+            ctl->s_pend = 0;
+        }
+    }
     double v[1] = {0};
     if (slot < 4) {
 #pragma unroll 8
@@ -1789,7 +1800,7 @@ __global__ __launch_bounds__(kBlock) void k_sum(const DevMember* __restrict__ me
 }
 
 // ---------------------------------------------------------------------------
-// K3: one workgroup per member.  The QoI vector and Gram matrix from the
+// K3: the member's solve.  The QoI vector and Gram matrix from the
 // fixed-order sums (k_sum), dQ, beta = G^-1 dQ and gamma_k = dQ_k (G^-1)_kk,
 // the per-step record and the coefficients of the dv build.  Every input is
 // first staged into LDS in one parallel pass, and all small matrices live
@@ -1798,115 +1809,155 @@ __global__ __launch_bounds__(kBlock) void k_sum(const DevMember* __restrict__ me
 // as singular when one of them is not above 1e-14 times the largest diagonal
 // entry.  The elimination takes four pivots per barrier, ping-ponging between
 // two copies of [G | I].
+//
+// It runs in one of two places.  k_solve: one workgroup per member (all its
+// threads), writing the coefficients, the record and the control state for
+// k_apply.  Or at the head of every workgroup of the binomial k_apply, on its
+// first wave (the apply's own field loads in flight meanwhile), each
+// workgroup forming the same coefficients from the same sums with the same
+// arithmetic; there the member's block 0 alone writes the record, advances
+// the step counter and leaves a first LRS scale to be committed by the next
+// step's k_sum, and every workgroup takes the step from the snapshot k_sum
+// made of it, so no workgroup reads a value another one of the launch writes.
 // ---------------------------------------------------------------------------
 constexpr int kMaxSums = 4 + kMaxSA + kMaxSA * (kMaxSA + 1) / 2 + kMaxQ * (1 + kMaxSA);
 
-__global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ mems, const int* __restrict__ work)
+struct SolveLds {
+    double M[2][kMaxQ][2 * kMaxQ];
+    double sf[kMaxSums];
+    double Cs[(kMaxQ + 1) * kMaxQ], es[kMaxQ], hps[kMaxHistChunks * kMaxQ];
+    double q[kMaxQ], dq[kMaxQ], beta[kMaxQ], gam[kMaxQ], sc[kMaxQ], qs[kMaxQ];
+    double rrs[kMaxSA][kMaxPow + 1], gmps[kMaxQ * kMaxQ];
+    double cv[kMaxPow + 1], cw[kMaxPow + 1];
+    int kinds[kMaxSA], saslot[kMaxSA], mpslot[kMaxQ], mpband[kMaxQ];
+    long long step;
+    int sset, flags;
+};
+
+// Ordering of the LDS traffic between the phases: a workgroup barrier when
+// the whole workgroup solves, else (one wave) a wave-level fence, the LDS
+// operations of one wave completing in order.
+template <int NTH>
+__device__ __forceinline__ void solve_sync()
 {
-    __shared__ double M[2][kMaxQ][2 * kMaxQ];
-    __shared__ double sf[kMaxSums];
-    __shared__ double Cs[(kMaxQ + 1) * kMaxQ], es[kMaxQ], hps[kMaxHistChunks * kMaxQ];
-    __shared__ double q[kMaxQ], dq[kMaxQ], beta[kMaxQ], gam[kMaxQ], sc[kMaxQ], qs[kMaxQ];
-    __shared__ double rrs[kMaxSA][kMaxPow + 1], gmps[kMaxQ * kMaxQ];
-    __shared__ int kinds[kMaxSA], saslot[kMaxSA], mpslot[kMaxQ], mpband[kMaxQ];
-    __shared__ long long step_s;
-    __shared__ int sset_s, flags_s;
-    KMember& m = *kc(mems + work[blockIdx.x]);
+    if constexpr (NTH == kBlock) {
+        __syncthreads();
+    } else {
+        static_assert(NTH == 64, "a solve runs on the workgroup or on one wave");
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// ROLE 0: k_solve (every output, the step counter from ctl->step); 1: the
+// leader of a fused apply (the record, the step counter, a pending scale);
+// 2: another workgroup of a fused apply (LDS outputs only).  Threads
+// 0..NTH-1 call it; S.cv, S.cw and S.beta hold the results.
+template <int NTH, int ROLE>
+__device__ void solve_member(KMember& m, SolveLds& S)
+{
     KParam* prm = kc(m.prm);
     DevCtl* ctl = m.ctl;
     const int tid = threadIdx.x;
     const int nq = prm->nq, nsa = prm->nsa, nmp = prm->nmp;
     const int ny = m.ny;
     const int nflat = nsa + nsa * (nsa + 1) / 2;
-    const int nsum = 4 + nflat + nmp * (1 + nsa);
     const bool lrs = prm->mode == LBM_CLOSURE_LRS;
 
-    // (a) stage the sums, the LRS model and the control state; clear M
-    for (int k = tid; k < nsum; k += kBlock) sf[k] = m.sums[k];
-    if (lrs) {
-        for (int k = tid; k < (nq + 1) * kMaxQ; k += kBlock) Cs[k] = prm->C[k];
-        if (tid < nq) es[tid] = ctl->lrs_e[tid];
-        for (int k = tid; k < prm->nhc * kMaxQ; k += kBlock) hps[k] = m.hpart[k];
-    }
-    for (int k = tid; k < 2 * kMaxQ * 2 * kMaxQ; k += kBlock) (&M[0][0][0])[k] = 0.0;
-    if (tid < kMaxSA * (kMaxPow + 1)) (&rrs[0][0])[tid] = (&prm->rr[0][0])[tid];
-    if (tid < kMaxSA) { kinds[tid] = prm->sa_kind[tid]; saslot[tid] = prm->sa_slot[tid]; }
-    if (tid < kMaxQ) { mpslot[tid] = prm->mp_slot[tid]; mpband[tid] = prm->mp_band[tid]; }
-    for (int pr = tid; pr < nmp * nmp; pr += kBlock) gmps[pr] = prm->gmp[(pr / nmp) * kMaxQ + pr % nmp];
+    // (a) stage the sums, the LRS model and the control state; clear M.
+    // Every load's address and count come from the member record itself or
+    // are fixed, none from a value loaded from the closure parameters, so
+    // all of them are in flight after one dependent load.
+    for (int k = tid; k < 4 + m.npart; k += NTH) S.sf[k] = m.sums[k];   // 4 + npart = nsum
+    for (int k = tid; k < (kMaxQ + 1) * kMaxQ; k += NTH) S.Cs[k] = prm->C[k];
+    if (tid < kMaxQ) S.es[tid] = ctl->lrs_e[tid];
+    if (lrs)
+        for (int k = tid; k < prm->nhc * kMaxQ; k += NTH) S.hps[k] = m.hpart[k];
+    for (int k = tid; k < 2 * kMaxQ * 2 * kMaxQ; k += NTH) (&S.M[0][0][0])[k] = 0.0;
+    if (tid < kMaxSA * (kMaxPow + 1)) (&S.rrs[0][0])[tid] = (&prm->rr[0][0])[tid];
+    if (tid < kMaxSA) { S.kinds[tid] = prm->sa_kind[tid]; S.saslot[tid] = prm->sa_slot[tid]; }
+    if (tid < kMaxQ) { S.mpslot[tid] = prm->mp_slot[tid]; S.mpband[tid] = prm->mp_band[tid]; }
+    for (int pr = tid; pr < kMaxQ * kMaxQ; pr += NTH) S.gmps[pr] = prm->gmp[pr];
     if (tid < kMaxQ) {
-        q[tid] = 0; dq[tid] = 0; beta[tid] = 0; gam[tid] = 0;
-        sc[tid] = ctl->s[tid];
+        S.q[tid] = 0; S.dq[tid] = 0; S.beta[tid] = 0; S.gam[tid] = 0;
+        S.sc[tid] = ctl->s[tid];
     }
-    if (tid == 0) { step_s = ctl->step; sset_s = ctl->s_set; flags_s = ctl->flags; }
+    if (tid == 0) {
+        S.step = ROLE == 0 ? ctl->step : ctl->step_snap;
+        S.sset = ctl->s_set;
+        S.flags = ctl->flags;
+    }
     // band weights of row y = tid, used at the end (clamped index; loaded now
     // so that their latency overlaps the solve)
     double wv0[kMaxQ];
-    if (nmp > 0 && tid < ny) {
+    if (ROLE == 0 && nmp > 0 && tid < ny) {
 #pragma unroll
         for (int jm = 0; jm < kMaxQ; ++jm) wv0[jm] = m.bandw[(size_t)prm->mp_band[jm < nmp ? jm : nmp - 1] * ny + tid];
     }
-    __syncthreads();
-    const long long step = step_s;
+    solve_sync<NTH>();
+    const long long step = S.step;
     const bool active = step >= prm->spinup;
     // (b) assemble q and G (left half of M), the mean-profile entries and
     // the identity (right half)
-    const double* sfp = sf + 4;
+    const double* sfp = S.sf + 4;
     if (tid < nsa) {
         const int s = tid;
-        q[saslot[s]] = sfp[s];
+        S.q[S.saslot[s]] = sfp[s];
         int g = nsa + s * nsa - s * (s - 1) / 2;
         for (int t = s; t < nsa; ++t, ++g) {
-            M[0][saslot[s]][saslot[t]] = sfp[g];
-            M[0][saslot[t]][saslot[s]] = sfp[g];
+            S.M[0][S.saslot[s]][S.saslot[t]] = sfp[g];
+            S.M[0][S.saslot[t]][S.saslot[s]] = sfp[g];
         }
     }
-    for (int pr = tid; pr < nmp * (1 + nsa); pr += kBlock) {
+    for (int pr = tid; pr < nmp * (1 + nsa); pr += NTH) {
         const int jm = pr / (1 + nsa), c = pr % (1 + nsa);
         const double v = sfp[nflat + pr];
-        const int uj = mpslot[jm];
+        const int uj = S.mpslot[jm];
         if (c == 0)
-            q[uj] = v;
+            S.q[uj] = v;
         else {
-            const int us = saslot[c - 1];
-            M[0][uj][us] = v;
-            M[0][us][uj] = v;
+            const int us = S.saslot[c - 1];
+            S.M[0][uj][us] = v;
+            S.M[0][us][uj] = v;
         }
     }
-    for (int pr = tid; pr < nmp * nmp; pr += kBlock) {
+    for (int pr = tid; pr < nmp * nmp; pr += NTH) {
         const int a = pr / nmp, b = pr % nmp;
-        M[0][mpslot[a]][mpslot[b]] = gmps[pr];
+        S.M[0][S.mpslot[a]][S.mpslot[b]] = S.gmps[a * kMaxQ + b];
     }
-    if (tid < nq) M[0][tid][kMaxQ + tid] = 1.0;
-    __syncthreads();
+    if (tid < nq) S.M[0][tid][kMaxQ + tid] = 1.0;
+    solve_sync<NTH>();
     // (c) dQ for tracking; the LRS scale (fixed at the first active step)
     if (active && tid < nq) {
         const int k = tid;
         if (prm->mode == LBM_CLOSURE_TRACK) {
-            if (step < prm->nref) dq[k] = prm->qref[(size_t)step * nq + k] - q[k];
+            if (step < prm->nref) S.dq[k] = prm->qref[(size_t)step * nq + k] - S.q[k];
         } else if (lrs) {
-            if (!sset_s) {
-                sc[k] = prm->have_scale ? prm->scale[k] : (q[k] != 0.0 ? fabs(q[k]) : 1.0);
-                ctl->s[k] = sc[k];
+            if (!S.sset) {
+                S.sc[k] = prm->have_scale ? prm->scale[k] : (S.q[k] != 0.0 ? fabs(S.q[k]) : 1.0);
+                if (ROLE == 0) ctl->s[k] = S.sc[k];
+                if (ROLE == 1) ctl->s_next[k] = S.sc[k];
             }
-            qs[k] = q[k] / sc[k];
+            S.qs[k] = S.q[k] / S.sc[k];
         }
     }
-    __syncthreads();
+    solve_sync<NTH>();
     // (d) the LRS draw: dQ = s (x C + e) - q*, with e = mu + L xi and the
     // history part of x C formed ahead of this kernel (k_sum); terms past nq
     // add exact zeros
     if (active && lrs && tid < nq) {
         const int k = tid;
-        double zh = es[k];
-        for (int c = 0; c < prm->nhc; ++c) zh += hps[c * kMaxQ + k];
+        double zh = S.es[k];
+        for (int c = 0; c < prm->nhc; ++c) zh += S.hps[c * kMaxQ + k];
 #pragma unroll
         for (int i = 0; i < kMaxQ; ++i) {
             const int ic = i < nq ? i : 0;
-            const double t = qs[ic] * Cs[ic * kMaxQ + k];
+            const double t = S.qs[ic] * S.Cs[ic * kMaxQ + k];
             zh += i < nq ? t : 0.0;
         }
-        zh += Cs[nq * kMaxQ + k];
-        dq[k] = sc[k] * zh - q[k];
+        zh += S.Cs[nq * kMaxQ + k];
+        S.dq[k] = S.sc[k] * zh - S.q[k];
     }
     // (e) Gauss-Jordan on [G | I] (only columns 0..nq-1 and kMaxQ..kMaxQ+nq-1
     // are nonzero), four pivots per barrier.  For pivot rows j0..j0+3 every
@@ -1918,23 +1969,23 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
     // same pivots from the same values, so the singular flag is uniform.
     // The four eliminations of a block are those of four consecutive pivots.
     double mx = 0;
-    for (int k = 0; k < nq; ++k) mx = fmax(mx, M[0][k][k]);
+    for (int k = 0; k < nq; ++k) mx = fmax(mx, S.M[0][k][k]);
     int sing = mx > 0 ? 0 : 1;
     int cur = 0;
     // thread layout: one column of [G | I] each, rows split over the
-    // kBlock / (2 nq) groups of threads
-    const int ncol = 2 * nq, ngrp = kBlock / ncol;
+    // NTH / (2 nq) groups of threads
+    const int ncol = 2 * nq, ngrp = NTH / ncol;
     const int gcol = tid % ncol, grow = tid / ncol;
     const int cc = gcol < nq ? gcol : kMaxQ + gcol - nq;
-    __syncthreads();
+    solve_sync<NTH>();
     for (int j0 = 0; j0 < nq && !sing; j0 += 4) {
         const int bs = min(4, nq - j0);   // rows j0..j0+3 stay inside M (nq <= kMaxQ)
         double P[4][4], t[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
 #pragma unroll
-            for (int b2 = 0; b2 < 4; ++b2) P[a][b2] = a < bs && b2 < bs ? M[cur][j0 + a][j0 + b2] : (a == b2 ? 1.0 : 0.0);
-            t[a] = a < bs ? M[cur][j0 + a][cc] : 0.0;
+            for (int b2 = 0; b2 < 4; ++b2) P[a][b2] = a < bs && b2 < bs ? S.M[cur][j0 + a][j0 + b2] : (a == b2 ? 1.0 : 0.0);
+            t[a] = a < bs ? S.M[cur][j0 + a][cc] : 0.0;
         }
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
@@ -1962,77 +2013,96 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
                     v = d == 0 ? t[0] : d == 1 ? t[1] : d == 2 ? t[2] : t[3];
                 } else {
                     // past nq the block columns of M are zero and t is zero
-                    v = M[cur][i][cc];
+                    v = S.M[cur][i][cc];
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) v -= M[cur][i][j0 + a] * t[a];
+                    for (int a = 0; a < 4; ++a) v -= S.M[cur][i][j0 + a] * t[a];
                 }
-                M[cur ^ 1][i][cc] = v;
+                S.M[cur ^ 1][i][cc] = v;
             }
         }
         cur ^= 1;
-        __syncthreads();
+        solve_sync<NTH>();
     }
     // (f) beta = G^-1 dQ, gamma_k = dQ_k (G^-1)_kk
     if (!sing && tid < nq) {
         double b = 0;
-        for (int j = 0; j < nq; ++j) b += M[cur][tid][kMaxQ + j] * dq[j];
-        beta[tid] = b;
-        gam[tid] = dq[tid] * M[cur][tid][kMaxQ + tid];
+        for (int j = 0; j < nq; ++j) b += S.M[cur][tid][kMaxQ + j] * S.dq[j];
+        S.beta[tid] = b;
+        S.gam[tid] = S.dq[tid] * S.M[cur][tid][kMaxQ + tid];
     }
-    __syncthreads();
+    solve_sync<NTH>();
     // (g) dv coefficients, record, counters
-    if (tid < kMaxSA) {
-        const double b = tid < nsa ? beta[saslot[tid]] : 0.0;
+    if (ROLE == 0 && tid < kMaxSA) {
+        const double b = tid < nsa ? S.beta[S.saslot[tid]] : 0.0;
         ctl->bsa[tid] = b;
         ctl->bsaf[tid] = (float)b;
     }
     if (tid <= kMaxPow) {
         double a = 0, b = 0;
         for (int s = 0; s < nsa; ++s) {
-            const double bs = beta[saslot[s]];
-            if (kinds[s] == 0) a += bs * rrs[s][tid];
-            else b += bs * rrs[s][tid];
+            const double bs = S.beta[S.saslot[s]];
+            if (S.kinds[s] == 0) a += bs * S.rrs[s][tid];
+            else b += bs * S.rrs[s][tid];
         }
-        ctl->cv[tid] = a;
-        ctl->cw[tid] = b;
-        ctl->cvf[tid] = (float)a;
-        ctl->cwf[tid] = (float)b;
-    }
-    lbm_qoi_rec* rec = m.recs + (size_t)(step % m.rec_cap);
-    if (tid < kMaxQ) {
-        rec->q[tid] = tid < nq ? q[tid] : 0.0;
-        rec->dq[tid] = tid < nq ? dq[tid] : 0.0;
-        rec->gamma[tid] = tid < nq ? gam[tid] : 0.0;
-    }
-    if (tid == 0) {
-        rec->step = step;
-        rec->flags = (flags_s & 1) | (sing ? 2 : 0);
-        rec->nq = nq;
-        rec->mass = (double)m.N + sf[0];
-        rec->mom[0] = sf[1];
-        rec->mom[1] = sf[2];
-        rec->mom[2] = sf[3];
-        rec->diag_e = 0;
-        rec->diag_z = 0;
-        if (active && lrs) ctl->s_set = 1;
-        ctl->step = step + 1;
-    }
-    // (h) mean-profile part of dv: cmp(y) = sum_j beta_mp_j w_j(y)
-    if (nmp > 0) {
-        for (int yy = tid; yy < ny; yy += kBlock) {
-            // all band-weight loads first (clamped index; terms past nmp add exact zeros)
-            double wv[kMaxQ];
-#pragma unroll
-            for (int jm = 0; jm < kMaxQ; ++jm)
-                wv[jm] = yy == tid ? wv0[jm] : m.bandw[(size_t)mpband[jm < nmp ? jm : nmp - 1] * ny + yy];
-            double c = 0;
-#pragma unroll
-            for (int jm = 0; jm < kMaxQ; ++jm) c += jm < nmp ? beta[mpslot[jm]] * wv[jm] : 0.0;
-            m.cmp[yy] = c;
+        S.cv[tid] = a;
+        S.cw[tid] = b;
+        if (ROLE == 0) {
+            ctl->cv[tid] = a;
+            ctl->cw[tid] = b;
+            ctl->cvf[tid] = (float)a;
+            ctl->cwf[tid] = (float)b;
         }
-    } else {
-        for (int yy = tid; yy < ny; yy += kBlock) m.cmp[yy] = 0.0;
     }
+    if (ROLE <= 1) {
+        lbm_qoi_rec* rec = m.recs + (size_t)(step % m.rec_cap);
+        if (tid < kMaxQ) {
+            rec->q[tid] = tid < nq ? S.q[tid] : 0.0;
+            rec->dq[tid] = tid < nq ? S.dq[tid] : 0.0;
+            rec->gamma[tid] = tid < nq ? S.gam[tid] : 0.0;
+        }
+        if (tid == 0) {
+            rec->step = step;
+            rec->flags = (S.flags & 1) | (sing ? 2 : 0);
+            rec->nq = nq;
+            rec->mass = (double)m.N + S.sf[0];
+            rec->mom[0] = S.sf[1];
+            rec->mom[1] = S.sf[2];
+            rec->mom[2] = S.sf[3];
+            rec->diag_e = 0;
+            rec->diag_z = 0;
+            if (active && lrs && !S.sset) {
+                if (ROLE == 0) ctl->s_set = 1;
+                else ctl->s_pend = 1;
+            }
+            ctl->step = step + 1;
+        }
+    }
+    // (h) mean-profile part of dv: cmp(y) = sum_j beta_mp_j w_j(y) (in a
+    // fused apply every cell forms its own row's value)
+    if (ROLE == 0) {
+        if (nmp > 0) {
+            for (int yy = tid; yy < ny; yy += NTH) {
+                // all band-weight loads first (clamped index; terms past nmp add exact zeros)
+                double wv[kMaxQ];
+#pragma unroll
+                for (int jm = 0; jm < kMaxQ; ++jm)
+                    wv[jm] = yy == tid ? wv0[jm] : m.bandw[(size_t)S.mpband[jm < nmp ? jm : nmp - 1] * ny + yy];
+                double c = 0;
+#pragma unroll
+                for (int jm = 0; jm < kMaxQ; ++jm) c += jm < nmp ? S.beta[S.mpslot[jm]] * wv[jm] : 0.0;
+                m.cmp[yy] = c;
+            }
+        } else {
+            for (int yy = tid; yy < ny; yy += NTH) m.cmp[yy] = 0.0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ mems, const int* __restrict__ work)
+{
+    __shared__ SolveLds S;
+    KMember& m = *kc(mems + work[blockIdx.x]);
+    solve_member<kBlock, 0>(m, S);
 }
 
 // K4: dv = sum_j cv_j B^j v* + sum_j cw_j C_j + e_x cmp(y) (eq. TO-ansatz
@@ -2046,18 +2116,23 @@ template <typename T> __device__ __forceinline__ T coef_bsa(KCtl* c, int s);
 template <> __device__ __forceinline__ float coef_bsa<float>(KCtl* c, int s) { return c->bsaf[s]; }
 template <> __device__ __forceinline__ double coef_bsa<double>(KCtl* c, int s) { return c->bsa[s]; }
 
-template <int LAT, typename T, bool KF, bool WT, bool DEF>
-__global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ mems, const int2* __restrict__ work,
+template <int LAT, typename T, bool KF, bool WT, bool DEF, bool FS>
+__global__ __launch_bounds__(kBlock, FS ? 4 : 1) void k_apply(const DevMember* __restrict__ mems, const int2* __restrict__ work,
                                                   int flip)
 {
     using L = Lat<LAT>;
     constexpr int D = L::D;
+    static_assert(!(FS && KF), "the kernel-filter build takes its coefficients from k_solve");
     const int2 wk = work[blockIdx.x];
     KMember& m = *kc(mems + wk.x);
     KParam* prm = kc(m.prm);
     const int N = m.N, nx = m.nx, ny = m.ny;
-    const int cell = wk.y * kBlock + threadIdx.x;
-    if (cell >= N) return;
+    int cell = wk.y * kBlock + threadIdx.x;
+    if (!FS && cell >= N) return;
+    // FS: every thread stays for the barrier after the solve; a thread past
+    // the grid works on cell 0 and stores nothing
+    const bool own = cell < N;
+    if (!own) cell = 0;
     const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
     const size_t sN = (size_t)N;
     KCtl* ctl = kc(m.ctl);
@@ -2066,6 +2141,22 @@ __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ 
     const T* __restrict__ vsp = (const T*)m.vs;
     T out[3] = {0, 0, 0};
     T vs[3] = {0, 0, 0};
+    // FS: the member's solve first, with few registers live, so that every
+    // workgroup of the launch is resident at once (the launch is used where
+    // the grid has few enough blocks); the field loads follow it
+    __shared__ SolveLds S;
+    if constexpr (FS) {
+        if (wk.y == 0) solve_member<kBlock, 1>(m, S);
+        else solve_member<kBlock, 2>(m, S);
+        __syncthreads();   // S.cv and S.cw of (g)
+    }
+    // in place: the populations the stream-collide of this step wrote
+    T* g = (T*)m.g[m.parity ^ flip ^ 1];
+    T gi[L::Q];
+    if constexpr (!DEF) {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) gi[i] = ld_fld<WT>(g + pop_at64<L::Q>(i, (size_t)cell));
+    }
     if constexpr (KF) {
         // dv = sum_s beta_s V_s (clamped loads; beta_s = 0 past nsa)
         const int nsa = prm->nsa;
@@ -2084,6 +2175,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ 
             for (int s2 = 0; s2 < kMaxSA; ++s2) acc += coef_bsa<T>(ctl, s2) * kv[s2][a];
             out[a] = acc;
         }
+        if (prm->nmp > 0) out[0] += T(m.cmp[y]);
     } else {
         // Unconditional loads with the power clamped to the highest one
         // stored: cv_j (cw_j) is zero above jv (jw), so the extra terms add
@@ -2112,11 +2204,41 @@ __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ 
 #pragma unroll
             for (int a = 0; a < D; ++a) fc[kMaxPow][a] = ctop[a];
         }
+        T cvc[kMaxPow + 1], cwc[kMaxPow + 1];
+        double cmp = 0;
+        if constexpr (FS) {
+            // this cell's row of the mean-profile part, cmp(y) = sum_j
+            // beta_mp_j w_j(y), in the order and precision k_solve forms it
+            const int nmp = prm->nmp;
+            double wv[kMaxQ];
+            if (nmp > 0) {
+#pragma unroll
+                for (int jm = 0; jm < kMaxQ; ++jm)
+                    wv[jm] = jm < nmp ? m.bandw[(size_t)prm->mp_band[jm] * ny + y] : 0.0;
+            }
+#pragma unroll
+            for (int jj = 0; jj <= kMaxPow; ++jj) {
+                cvc[jj] = T(S.cv[jj]);
+                cwc[jj] = T(S.cw[jj]);
+            }
+            if (nmp > 0) {
+#pragma unroll
+                for (int jm = 0; jm < kMaxQ; ++jm) cmp += jm < nmp ? S.beta[S.mpslot[jm]] * wv[jm] : 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int jj = 0; jj <= kMaxPow; ++jj) {
+                cvc[jj] = coef_cv<T>(ctl, jj);
+                cwc[jj] = coef_cw<T>(ctl, jj);
+            }
+            if (prm->nmp > 0) cmp = m.cmp[y];
+        }
+        if (!own) return;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            T s = coef_cv<T>(ctl, 0) * fv[0][a];
+            T s = cvc[0] * fv[0][a];
 #pragma unroll
-            for (int jj = 1; jj <= kMaxPow; ++jj) s += coef_cv<T>(ctl, jj) * fv[jj][a];
+            for (int jj = 1; jj <= kMaxPow; ++jj) s += cvc[jj] * fv[jj][a];
             out[a] = s;
         }
         if (hz) {
@@ -2124,14 +2246,14 @@ __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ 
             for (int a = 0; a < D; ++a) {
                 T sacc = 0;
 #pragma unroll
-                for (int jj = 0; jj <= kMaxPow; ++jj) sacc += coef_cw<T>(ctl, jj) * fc[jj][a];
+                for (int jj = 0; jj <= kMaxPow; ++jj) sacc += cwc[jj] * fc[jj][a];
                 out[a] += sacc;
             }
         }
 #pragma unroll
         for (int a = 0; a < D; ++a) vs[a] = fv[0][a];
+        if (prm->nmp > 0) out[0] += T(cmp);
     }
-    if (prm->nmp > 0) out[0] += T(m.cmp[y]);
     const T rho = T(1) + ((const T*)m.rho)[cell];
     T ra[D], rb[D];
 #pragma unroll
@@ -2148,11 +2270,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ 
             st_fld_at(rec + (size_t)(D + a) * sN, (unsigned)cell, rb[a], WT);
         }
     } else {
-        T* g = (T*)m.g[m.parity ^ flip ^ 1];
         const T e = rec_e<D, T>(ra, rb);
-        T gi[L::Q];
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i) gi[i] = ld_fld<WT>(g + pop_at64<L::Q>(i, (size_t)cell));
 #pragma unroll
         for (int i = 0; i < L::Q; ++i)
             st_fld(g + pop_at64<L::Q>(i, (size_t)cell),
@@ -2851,17 +2969,20 @@ to_chain:
 #undef LBM_REDUCE
         mark(4);
         hipLaunchKernelGGL(k_sum, dim3(g.nbs), blk, 0, st, g.mems, g.works);
-        hipLaunchKernelGGL(k_solve, dim3(g.nmem), blk, 0, st, g.mems, g.workm);
+        // the binomial apply forms the solve itself (one launch less per step)
+        const bool fused = fused_solve(g);
+        if (!fused) hipLaunchKernelGGL(k_solve, dim3(g.nmem), blk, 0, st, g.mems, g.workm);
         mark(5);
         if (!g.probe) {
-#define LBM_APPLY(KFV, DEFV)                                                                                 \
+#define LBM_APPLY(KFV, DEFV, FSV)                                                                            \
     do {                                                                                                     \
-        if (g.wt) hipLaunchKernelGGL((k_apply<LAT, T, KFV, true, DEFV>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
-        else hipLaunchKernelGGL((k_apply<LAT, T, KFV, false, DEFV>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
+        if (g.wt) hipLaunchKernelGGL((k_apply<LAT, T, KFV, true, DEFV, FSV>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
+        else hipLaunchKernelGGL((k_apply<LAT, T, KFV, false, DEFV, FSV>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
     } while (0)
             const bool def = g.defer && g.substrate != LBM_WALE;
-            if (g.kf) { if (def) LBM_APPLY(true, true); else LBM_APPLY(true, false); }
-            else { if (def) LBM_APPLY(false, true); else LBM_APPLY(false, false); }
+            if (g.kf) { if (def) LBM_APPLY(true, true, false); else LBM_APPLY(true, false, false); }
+            else if (fused) { if (def) LBM_APPLY(false, true, true); else LBM_APPLY(false, false, true); }
+            else { if (def) LBM_APPLY(false, true, false); else LBM_APPLY(false, false, false); }
 #undef LBM_APPLY
         }
         mark(6);

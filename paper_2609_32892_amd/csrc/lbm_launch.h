@@ -72,8 +72,17 @@ struct LaunchGroup {
     int defer;          // TO mode: the SGS change is recorded and applied by the next step's pull
     int a32;            // every member's population buffer spans less than 4 GiB (32-bit offsets)
     int nt;             // plain runs: the launch's populations exceed the Infinity Cache (non-temporal stores)
+    int sep_solve;      // TO mode: the solve in its own launch (k_solve) even where k_apply could form it
                         // (k_step_t over the binomial tiles); not with the WALE substrate
 };
+
+// TO mode: the binomial apply forms the solve itself (no k_solve launch):
+// not for kernel-filter closures, probe steps (no apply) or a forced own
+// launch, and only where the apply's blocks are all resident at once.
+inline bool fused_solve(const LaunchGroup& g)
+{
+    return !g.kf && !g.probe && !g.sep_solve && g.nb1 <= kFusedApplyBlocks;
+}
 
 enum { OP_INIT = 0, OP_GET_POP = 1, OP_SET_POP = 2, OP_STREAM = 3 };
 

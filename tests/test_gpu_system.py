@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_util import closure_args, gpu_run, need_gpu
+from gpu_util import closure_args, gpu_run, need_gpu, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -223,6 +223,56 @@ def test_deferred_and_in_place_sgs_change_bitwise_equal(case):
         r.step(5)
         r.sync()
     assert np.array_equal(a.get_populations(), b.get_populations())
+    for r in (a, b, c):
+        r.close()
+
+
+@pytest.mark.parametrize("case", ["2d-fp32-lrs", "2d-fp64-track", "3d-fp32-lrs", "3d-fp32-lrs-recorded", "3d-fp64-lrs"])
+def test_solve_in_apply_and_in_its_own_launch_bitwise_equal(case):
+    """The solve formed by every workgroup of the binomial apply (the
+    default) against the solve in its own launch (k_solve, forced with
+    tune_mem bit 3): bitwise equal populations and records.  The LRS scale
+    is fixed from |q*| at the first corrected step (no scale given), which
+    the fused form leaves pending for the next step's k_sum: a checkpoint
+    taken right after that step, with the scale still pending, resumes
+    bitwise.  Tracking runs read their reference by the step counter, which
+    the fused form takes from k_sum's snapshot."""
+    lbm = need_gpu()
+    kind, prec, mode = case.split("-")[:3]
+    tm = 4 if case.endswith("recorded") else 0
+    S0 = 3
+    if kind == "2d":
+        cfg, u0, qois, _ = _case2d(48, 3)
+        _, cargs = closure_args("2d", spinup=S0, mode=mode)
+    else:
+        cfg, u0 = synth.channel_workload(40, 18, 10, seed=8)
+        qois, cargs = closure_args("3d", ny=18, spinup=S0, mode=mode)
+    qref = None
+    if mode == "track":
+        o = oracle_run(cfg, u0, qois, dict(mode="off"))
+        o.step(40)
+        qref = o.record_arrays()["q"] * 1.01
+        cargs = dict(mode="track", spinup=S0)
+    _say(f"solve in apply vs own launch: {case}")
+    a = gpu_run(lbm, cfg, u0, prec, qois, cargs, qref=qref, tune_mem=tm)
+    b = gpu_run(lbm, cfg, u0, prec, qois, cargs, qref=qref, tune_mem=tm | 8)
+    for r in (a, b):
+        r.step(S0 + 1)   # through the first corrected step
+        r.sync()
+    state = a.get_state()
+    c = gpu_run(lbm, cfg, u0, prec, qois, cargs, qref=qref, tune_mem=tm)
+    c.set_state(state)
+    for r in (a, b, c):
+        r.step(12)
+        r.sync()
+    fa = a.get_populations()
+    assert np.array_equal(fa, b.get_populations())
+    assert np.array_equal(fa, c.get_populations())
+    ra, rb, rc = a.record_arrays(), b.record_arrays(), c.record_arrays()
+    for key in ("q", "dq", "gamma", "flags"):
+        assert np.array_equal(ra[key], rb[key]), key
+        assert np.array_equal(ra[key][S0 + 1:], rc[key][S0 + 1:]), key
+    assert np.any(ra["dq"][S0:] != 0)
     for r in (a, b, c):
         r.close()
 
