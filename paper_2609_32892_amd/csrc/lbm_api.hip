@@ -169,11 +169,11 @@ int check_config(const lbm_config* c)
 }
 
 struct Plan {
-    size_t member, param, ctl, recs, g0, g1, fprof, vn, part_stats, part_diag, work1, workm;
+    size_t member, param, ctl, recs, g0, g1, fprof, vn, part_stats, part_diag, work1, workp, workm;
     size_t rho, vs, P, W, Cf, rec, part_to, bandw, cmp, workr, workb, sums, works, hpart, kV, kT, ktaps, kjobs;
     size_t fspec_v, fspec_w, fband_e, fband_z;
     size_t total;
-    int N, D, NC, Q, esz, nb1, nbx2, cpt2, nbr, nbb, nbs, zc, btx, rec_cap;
+    int N, D, NC, Q, esz, nb1, nbp, nbx2, cpt2, nbr, nbb, nbs, zc, btx, rec_cap;
     size_t popn;   // elements of one population buffer: Q * N rounded up to whole blocks of kPopBlk cells
     ClosureShape cap;
 };
@@ -187,6 +187,7 @@ void make_plan(const lbm_config* c, const ClosureShape& cs, Plan* p)
     P.Q = c->lattice == LBM_D2Q9 ? 9 : 19;
     P.esz = c->precision == LBM_FP64 ? 8 : 4;
     P.nb1 = (P.N + kBlock - 1) / kBlock;
+    P.nbp = (P.nb1 + 1) / 2;
     P.rec_cap = c->rec_cap > 0 ? c->rec_cap : 4096;
     P.cap = cs;
     const int plane = c->nx * c->nz;
@@ -226,6 +227,7 @@ void make_plan(const lbm_config* c, const ClosureShape& cs, Plan* p)
     P.part_stats = take(sizeof(double) * 4 * std::max(P.nb1, P.nbb));
     P.part_diag = take(sizeof(double) * 2 * P.nb1);
     P.work1 = take(sizeof(int2) * P.nb1);
+    P.workp = take(sizeof(int2) * P.nbp);
     P.workm = take(sizeof(int));
     if (cs.nq > 0) {
         P.rho = take(e * N);
@@ -470,6 +472,8 @@ LaunchGroup ctx_group(const lbm_ctx* c)
     g.mems = c->dm;
     g.work1 = (const int2*)(c->arena + c->plan.work1);
     g.nb1 = c->plan.nb1;
+    g.workp = (const int2*)(c->arena + c->plan.workp);
+    g.nbp = c->plan.nbp;
     g.workr = (const int2*)(c->arena + c->plan.workr);
     g.nbr = c->plan.nbr;
     g.workb = (const int2*)(c->arena + c->plan.workb);
@@ -982,14 +986,17 @@ int lbm_create(const lbm_config* cfg, const lbm_closure* closure, void* dev_aren
         else if (cfg->force_kind == LBM_FORCE_CONST_X)
             fp[y] = cfg->force_amp;
     }
-    std::vector<int2> w1(plan.nb1);
+    std::vector<int2> w1(plan.nb1), wp(plan.nbp);
     {
         const std::vector<int> o = xcd_order(plan.nb1);
         for (int b = 0; b < plan.nb1; ++b) w1[b] = make_int2(0, o[b]);
+        const std::vector<int> op = xcd_order(plan.nbp);
+        for (int b = 0; b < plan.nbp; ++b) wp[b] = make_int2(0, op[b]);
     }
     int zero = 0;
     rc = upload(c, A + plan.fprof, fp.data(), sizeof(double) * fp.size());
     if (!rc) rc = upload(c, A + plan.work1, w1.data(), sizeof(int2) * w1.size());
+    if (!rc) rc = upload(c, A + plan.workp, wp.data(), sizeof(int2) * wp.size());
     if (!rc) rc = upload(c, A + plan.workm, &zero, sizeof zero);
     if (!rc && c->has_to) {
         std::vector<int2> wr(plan.nbr);
@@ -1526,7 +1533,7 @@ static int batch_build(lbm_batch* b)
     std::vector<DevMember> hmem(n);
     std::vector<int2> work;
     std::vector<int> workm;
-    struct Off { size_t w1, nb1, wr, nbr, wb, nbb, ws, nbs, wm, nm; };
+    struct Off { size_t w1, nb1, wp, nbp, wr, nbr, wb, nbb, ws, nbs, wm, nm; };
     std::vector<Off> offs;
     for (size_t gi = 0; gi < keys.size(); ++gi) {
         Off o{};
@@ -1536,6 +1543,12 @@ static int batch_build(lbm_batch* b)
             for (int k = 0; k < b->mem[i]->plan.nb1; ++k) work.push_back(make_int2(i, o[k]));
         }
         o.nb1 = work.size() - o.w1;
+        o.wp = work.size();
+        for (int i : gm[gi]) {
+            const std::vector<int> op = xcd_order(b->mem[i]->plan.nbp);
+            for (int k = 0; k < b->mem[i]->plan.nbp; ++k) work.push_back(make_int2(i, op[k]));
+        }
+        o.nbp = work.size() - o.wp;
         o.wr = work.size();
         if (keys[gi].mode == 2)
             for (int i : gm[gi])
@@ -1615,6 +1628,8 @@ static int batch_build(lbm_batch* b)
         g.mems = b->dmem;
         g.work1 = b->dwork + offs[gi].w1;
         g.nb1 = (int)offs[gi].nb1;
+        g.workp = b->dwork + offs[gi].wp;
+        g.nbp = (int)offs[gi].nbp;
         g.workr = b->dwork + offs[gi].wr;
         g.nbr = (int)offs[gi].nbr;
         g.workb = b->dwork + offs[gi].wb;

@@ -23,11 +23,12 @@ constexpr int kBinTX = 32;      // binomial-filter tile: x extent
 constexpr int kBinTY = kBlock / kBinTX;  // y extent
 constexpr int kBinTXW = 64;     // the wide tile (64 x 8, 512 threads) of the tiled kernels
 constexpr int kBinZCMax = 16;   // most z planes per workgroup chosen automatically (3-D)
-// The binomial apply forms the member's solve in every workgroup where its
-// launch has at most this many blocks: with the solve's registers (5 waves
-// per SIMD) they are all resident at once on the 256 CUs, so the solve's
-// latency is paid once per launch; larger launches keep k_solve.
-constexpr int kFusedApplyBlocks = 1024;
+// The binomial apply forms the member's solve in every workgroup (one per
+// pair of 256-cell blocks of a member) where its launch has at most this
+// many workgroups: at two waves per SIMD they are all resident at once on
+// the 256 CUs, so the solve's latency is paid once per launch, under the
+// apply's own loads; larger launches keep k_solve.
+constexpr int kFusedApplyPairs = 512;
 constexpr int kHistRows = 512;   // LRS history rows (x entries) per k_sum workgroup
 constexpr int kMaxHistChunks = 64;                 // so 2 h nq <= 32768
 constexpr int kMaxRad = 12;     // kernel filters: largest radius of a 1-D factor

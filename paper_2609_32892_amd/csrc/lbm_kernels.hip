@@ -1810,15 +1810,15 @@ __global__ __launch_bounds__(kBlock) void k_sum(const DevMember* __restrict__ me
 // entry.  The elimination takes four pivots per barrier, ping-ponging between
 // two copies of [G | I].
 //
-// It runs in one of two places.  k_solve: one workgroup per member (all its
-// threads), writing the coefficients, the record and the control state for
-// k_apply.  Or at the head of every workgroup of the binomial k_apply, on its
-// first wave (the apply's own field loads in flight meanwhile), each
-// workgroup forming the same coefficients from the same sums with the same
-// arithmetic; there the member's block 0 alone writes the record, advances
-// the step counter and leaves a first LRS scale to be committed by the next
-// step's k_sum, and every workgroup takes the step from the snapshot k_sum
-// made of it, so no workgroup reads a value another one of the launch writes.
+// It runs in one of two places.  k_solve: one workgroup per member, writing
+// the coefficients, the record and the control state for k_apply.  Or in
+// every workgroup of the binomial apply k_apply_fs (small launches), with
+// the apply's own field loads in flight meanwhile, each workgroup forming
+// the same coefficients from the same sums with the same arithmetic; there
+// the member's first workgroup alone writes the record, advances the step
+// counter and leaves a first LRS scale to be committed by the next step's
+// k_sum, and every workgroup takes the step from the snapshot k_sum made of
+// it, so no workgroup reads a value another one of the launch writes.
 // ---------------------------------------------------------------------------
 constexpr int kMaxSums = 4 + kMaxSA + kMaxSA * (kMaxSA + 1) / 2 + kMaxQ * (1 + kMaxSA);
 
@@ -1834,29 +1834,15 @@ struct SolveLds {
     int sset, flags;
 };
 
-// Ordering of the LDS traffic between the phases: a workgroup barrier when
-// the whole workgroup solves, else (one wave) a wave-level fence, the LDS
-// operations of one wave completing in order.
-template <int NTH>
-__device__ __forceinline__ void solve_sync()
-{
-    if constexpr (NTH == kBlock) {
-        __syncthreads();
-    } else {
-        static_assert(NTH == 64, "a solve runs on the workgroup or on one wave");
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-}
-
 // ROLE 0: k_solve (every output, the step counter from ctl->step); 1: the
 // leader of a fused apply (the record, the step counter, a pending scale);
-// 2: another workgroup of a fused apply (LDS outputs only).  Threads
-// 0..NTH-1 call it; S.cv, S.cw and S.beta hold the results.
-template <int NTH, int ROLE>
-__device__ void solve_member(KMember& m, SolveLds& S)
+// 2: another workgroup of a fused apply (LDS outputs only).  Every thread of
+// the workgroup calls it; pre() issues the caller's loads right after the
+// solve's own; S.cv, S.cw and S.beta hold the results.
+template <int NTH, int ROLE, typename Pre>
+__device__ void solve_member(KMember& m, SolveLds& S, Pre&& pre)
 {
+    static_assert(NTH == kBlock, "the solve runs on a whole workgroup");
     KParam* prm = kc(m.prm);
     DevCtl* ctl = m.ctl;
     const int tid = threadIdx.x;
@@ -1868,26 +1854,56 @@ __device__ void solve_member(KMember& m, SolveLds& S)
     // (a) stage the sums, the LRS model and the control state; clear M.
     // Every load's address and count come from the member record itself or
     // are fixed, none from a value loaded from the closure parameters, so
-    // all of them are in flight after one dependent load.
-    for (int k = tid; k < 4 + m.npart; k += NTH) S.sf[k] = m.sums[k];   // 4 + npart = nsum
-    for (int k = tid; k < (kMaxQ + 1) * kMaxQ; k += NTH) S.Cs[k] = prm->C[k];
-    if (tid < kMaxQ) S.es[tid] = ctl->lrs_e[tid];
+    // all of them are in flight after one dependent load.  They are issued
+    // first, then the caller's own loads (pre), then stored to LDS: a wave's
+    // loads complete in order, so the stores wait only for the solve's own.
+    // (Measured on MI355X: the caller's loads issued after the staging
+    // barrier instead are no faster.)
+    static_assert(kMaxSums <= kBlock && kMaxQ * kMaxQ <= kBlock && kMaxSA * (kMaxPow + 1) <= kBlock &&
+                  (kMaxQ + 1) * kMaxQ <= 2 * kBlock, "one or two staged values per thread");
+    const double r_sf = tid < 4 + m.npart ? m.sums[tid] : 0.0;   // 4 + npart sums
+    const double r_c0 = prm->C[tid];
+    const double r_c1 = tid < (kMaxQ + 1) * kMaxQ - kBlock ? prm->C[kBlock + tid] : 0.0;
+    const double r_g = prm->gmp[tid];
+    const double r_rr = tid < kMaxSA * (kMaxPow + 1) ? (&prm->rr[0][0])[tid] : 0.0;
+    double r_es = 0, r_s = 0;
+    int r_kind = 0, r_sas = 0, r_mps = 0, r_mpb = 0;
+    if (tid < kMaxQ) {
+        r_es = ctl->lrs_e[tid];
+        r_s = ctl->s[tid];
+        r_mps = prm->mp_slot[tid];
+        r_mpb = prm->mp_band[tid];
+    }
+    if (tid < kMaxSA) { r_kind = prm->sa_kind[tid]; r_sas = prm->sa_slot[tid]; }
+    long long r_step = 0;
+    int r_sset = 0, r_flags = 0;
+    if (tid == 0) {
+        r_step = ROLE == 0 ? ctl->step : ctl->step_snap;
+        r_sset = ctl->s_set;
+        r_flags = ctl->flags;
+    }
+    pre();
+    if (tid < 4 + m.npart) S.sf[tid] = r_sf;
+    S.Cs[tid] = r_c0;
+    if (tid < (kMaxQ + 1) * kMaxQ - kBlock) S.Cs[kBlock + tid] = r_c1;
+    S.gmps[tid] = r_g;
+    if (tid < kMaxSA * (kMaxPow + 1)) (&S.rrs[0][0])[tid] = r_rr;
+    if (tid < kMaxQ) {
+        S.es[tid] = r_es;
+        S.sc[tid] = r_s;
+        S.mpslot[tid] = r_mps;
+        S.mpband[tid] = r_mpb;
+        S.q[tid] = 0; S.dq[tid] = 0; S.beta[tid] = 0; S.gam[tid] = 0;
+    }
+    if (tid < kMaxSA) { S.kinds[tid] = r_kind; S.saslot[tid] = r_sas; }
+    if (tid == 0) {
+        S.step = r_step;
+        S.sset = r_sset;
+        S.flags = r_flags;
+    }
     if (lrs)
         for (int k = tid; k < prm->nhc * kMaxQ; k += NTH) S.hps[k] = m.hpart[k];
     for (int k = tid; k < 2 * kMaxQ * 2 * kMaxQ; k += NTH) (&S.M[0][0][0])[k] = 0.0;
-    if (tid < kMaxSA * (kMaxPow + 1)) (&S.rrs[0][0])[tid] = (&prm->rr[0][0])[tid];
-    if (tid < kMaxSA) { S.kinds[tid] = prm->sa_kind[tid]; S.saslot[tid] = prm->sa_slot[tid]; }
-    if (tid < kMaxQ) { S.mpslot[tid] = prm->mp_slot[tid]; S.mpband[tid] = prm->mp_band[tid]; }
-    for (int pr = tid; pr < kMaxQ * kMaxQ; pr += NTH) S.gmps[pr] = prm->gmp[pr];
-    if (tid < kMaxQ) {
-        S.q[tid] = 0; S.dq[tid] = 0; S.beta[tid] = 0; S.gam[tid] = 0;
-        S.sc[tid] = ctl->s[tid];
-    }
-    if (tid == 0) {
-        S.step = ROLE == 0 ? ctl->step : ctl->step_snap;
-        S.sset = ctl->s_set;
-        S.flags = ctl->flags;
-    }
     // band weights of row y = tid, used at the end (clamped index; loaded now
     // so that their latency overlaps the solve)
     double wv0[kMaxQ];
@@ -1895,7 +1911,7 @@ __device__ void solve_member(KMember& m, SolveLds& S)
 #pragma unroll
         for (int jm = 0; jm < kMaxQ; ++jm) wv0[jm] = m.bandw[(size_t)prm->mp_band[jm < nmp ? jm : nmp - 1] * ny + tid];
     }
-    solve_sync<NTH>();
+    __syncthreads();
     const long long step = S.step;
     const bool active = step >= prm->spinup;
     // (b) assemble q and G (left half of M), the mean-profile entries and
@@ -1927,7 +1943,7 @@ __device__ void solve_member(KMember& m, SolveLds& S)
         S.M[0][S.mpslot[a]][S.mpslot[b]] = S.gmps[a * kMaxQ + b];
     }
     if (tid < nq) S.M[0][tid][kMaxQ + tid] = 1.0;
-    solve_sync<NTH>();
+    __syncthreads();
     // (c) dQ for tracking; the LRS scale (fixed at the first active step)
     if (active && tid < nq) {
         const int k = tid;
@@ -1942,7 +1958,7 @@ __device__ void solve_member(KMember& m, SolveLds& S)
             S.qs[k] = S.q[k] / S.sc[k];
         }
     }
-    solve_sync<NTH>();
+    __syncthreads();
     // (d) the LRS draw: dQ = s (x C + e) - q*, with e = mu + L xi and the
     // history part of x C formed ahead of this kernel (k_sum); terms past nq
     // add exact zeros
@@ -1977,7 +1993,7 @@ __device__ void solve_member(KMember& m, SolveLds& S)
     const int ncol = 2 * nq, ngrp = NTH / ncol;
     const int gcol = tid % ncol, grow = tid / ncol;
     const int cc = gcol < nq ? gcol : kMaxQ + gcol - nq;
-    solve_sync<NTH>();
+    __syncthreads();
     for (int j0 = 0; j0 < nq && !sing; j0 += 4) {
         const int bs = min(4, nq - j0);   // rows j0..j0+3 stay inside M (nq <= kMaxQ)
         double P[4][4], t[4];
@@ -2021,7 +2037,7 @@ __device__ void solve_member(KMember& m, SolveLds& S)
             }
         }
         cur ^= 1;
-        solve_sync<NTH>();
+        __syncthreads();
     }
     // (f) beta = G^-1 dQ, gamma_k = dQ_k (G^-1)_kk
     if (!sing && tid < nq) {
@@ -2030,7 +2046,7 @@ __device__ void solve_member(KMember& m, SolveLds& S)
         S.beta[tid] = b;
         S.gam[tid] = S.dq[tid] * S.M[cur][tid][kMaxQ + tid];
     }
-    solve_sync<NTH>();
+    __syncthreads();
     // (g) dv coefficients, record, counters
     if (ROLE == 0 && tid < kMaxSA) {
         const double b = tid < nsa ? S.beta[S.saslot[tid]] : 0.0;
@@ -2102,7 +2118,7 @@ __global__ __launch_bounds__(kBlock) void k_solve(const DevMember* __restrict__ 
 {
     __shared__ SolveLds S;
     KMember& m = *kc(mems + work[blockIdx.x]);
-    solve_member<kBlock, 0>(m, S);
+    solve_member<kBlock, 0>(m, S, [] {});
 }
 
 // K4: dv = sum_j cv_j B^j v* + sum_j cw_j C_j + e_x cmp(y) (eq. TO-ansatz
@@ -2116,49 +2132,195 @@ template <typename T> __device__ __forceinline__ T coef_bsa(KCtl* c, int s);
 template <> __device__ __forceinline__ float coef_bsa<float>(KCtl* c, int s) { return c->bsaf[s]; }
 template <> __device__ __forceinline__ double coef_bsa<double>(KCtl* c, int s) { return c->bsa[s]; }
 
-template <int LAT, typename T, bool KF, bool WT, bool DEF, bool FS>
-__global__ __launch_bounds__(kBlock, FS ? 4 : 1) void k_apply(const DevMember* __restrict__ mems, const int2* __restrict__ work,
+// One cell of the binomial apply: its fields (loaded by apply_load, the
+// power clamped to the highest one stored: cv_j (cw_j) is zero above jv
+// (jw), so the extra terms add exact zeros; the top C_jw from the
+// neighbours of W_jw), and in place the populations the stream-collide of
+// this step wrote.
+template <int LAT, typename T, bool DEF>
+struct ApplyIn {
+    T fv[kMaxPow + 1][Lat<LAT>::D], fc[kMaxPow][Lat<LAT>::D];
+    T nb[Lat<LAT>::D == 2 ? 4 : 12];   // W_jw at the neighbours the top curl takes
+    bool okm, okp;                     // y neighbours inside the walls
+    T rho1;                            // rho - 1
+    T gi[DEF ? 1 : Lat<LAT>::Q];
+};
+
+// The top C_jw = curl^T W_jw of a cell in two steps, so that a caller can
+// hold the loads and form the curl later: the neighbour values (2-D: psi at
+// y+1, y-1, x+1, x-1; 3-D: w_z, w_y, w_x at the pairs of neighbours of
+// D_y w_z, D_z w_y, D_z w_x, D_x w_z, D_x w_y, D_y w_x), then central
+// differences (zero beyond the walls), without contraction.
+template <int LAT, typename T>
+__device__ __forceinline__ void top_curl_load(KMember& m, int jw, int x, int y, int z, T* r, bool& okm, bool& okp)
+{
+    using L = Lat<LAT>;
+    const unsigned sN = (unsigned)m.N;
+    const unsigned c = (unsigned)(x + m.nx * (y + m.ny * z));
+    const Nbr n = nbr_at(c, x, y, z, m.nx, m.ny, m.nz, m.walls, L::D);
+    const T* psi = (const T*)m.W + (size_t)jw * L::NC * sN;
+    okm = n.okm;
+    okp = n.okp;
+    if constexpr (L::D == 2) {
+        r[0] = ld_at(psi, n.yp); r[1] = ld_at(psi, n.ym);
+        r[2] = ld_at(psi, n.xp); r[3] = ld_at(psi, n.xm);
+    } else {
+        const T* ux = psi;
+        const T* uy = psi + sN;
+        const T* uz = psi + 2 * sN;
+        r[0] = ld_at(uz, n.yp); r[1] = ld_at(uz, n.ym);
+        r[2] = ld_at(uy, n.zp); r[3] = ld_at(uy, n.zm);
+        r[4] = ld_at(ux, n.zp); r[5] = ld_at(ux, n.zm);
+        r[6] = ld_at(uz, n.xp); r[7] = ld_at(uz, n.xm);
+        r[8] = ld_at(uy, n.xp); r[9] = ld_at(uy, n.xm);
+        r[10] = ld_at(ux, n.yp); r[11] = ld_at(ux, n.ym);
+    }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void top_curl_eval(const T* r, bool okm, bool okp, T* out)
+{
+#pragma clang fp contract(off)
+    auto y0 = [](bool ok, T v) { return ok ? v : T(0); };
+    if constexpr (D == 2) {
+        out[0] = T(0.5) * (y0(okp, r[0]) - y0(okm, r[1]));
+        out[1] = -(T(0.5) * (r[2] - r[3]));
+    } else {
+        const T dyuz = T(0.5) * (y0(okp, r[0]) - y0(okm, r[1]));
+        const T dzuy = T(0.5) * (r[2] - r[3]);
+        const T dzux = T(0.5) * (r[4] - r[5]);
+        const T dxuz = T(0.5) * (r[6] - r[7]);
+        const T dxuy = T(0.5) * (r[8] - r[9]);
+        const T dyux = T(0.5) * (y0(okp, r[10]) - y0(okm, r[11]));
+        out[0] = dyuz - dzuy;
+        out[1] = dzux - dxuz;
+        out[2] = dxuy - dyux;
+    }
+}
+
+template <int LAT, typename T, bool WT, bool DEF>
+__device__ __forceinline__ void apply_load(KMember& m, KParam* prm, int flip, int cell, ApplyIn<LAT, T, DEF>& in)
+{
+    using L = Lat<LAT>;
+    constexpr int D = L::D;
+    const int nx = m.nx, ny = m.ny;
+    const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
+    const size_t sN = (size_t)m.N;
+    const int jv = prm->jv, jw = prm->jw;
+    const T* __restrict__ vsp = (const T*)m.vs;
+    if constexpr (!DEF) {
+        const T* g = (const T*)m.g[m.parity ^ flip ^ 1];
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) in.gi[i] = ld_fld<WT>(g + pop_at64<L::Q>(i, (size_t)cell));
+    }
+#pragma unroll
+    for (int jj = 0; jj <= kMaxPow; ++jj) {
+        const int je = jj < jv ? jj : jv;
+        const T* src = je == 0 ? vsp : (const T*)m.P + (size_t)(je - 1) * D * sN;
+#pragma unroll
+        for (int a = 0; a < D; ++a) in.fv[jj][a] = ld_fld<WT>(src + a * sN + cell);
+    }
+    if (prm->has_z) {
+        top_curl_load<LAT, T>(m, jw, x, y, z, in.nb, in.okm, in.okp);
+        const int jc = jw > 0 ? jw - 1 : 0;
+#pragma unroll
+        for (int jj = 0; jj < kMaxPow; ++jj) {
+            const T* srcc = (const T*)m.C + (size_t)(jj < jc ? jj : jc) * D * sN;
+#pragma unroll
+            for (int a = 0; a < D; ++a) in.fc[jj][a] = ld_fld<WT>(srcc + a * sN + cell);
+        }
+    }
+    in.rho1 = ((const T*)m.rho)[cell];
+}
+
+// The rest of the cell: the SGS change (rho dv, 2 v* + dv) from dv (out) and
+// v*, stored as the record (DEF) or added in place to the populations.
+template <int LAT, typename T, bool WT, bool DEF>
+__device__ __forceinline__ void apply_finish(KMember& m, int flip, int cell, const T (&vs)[Lat<LAT>::D],
+                                             const T (&out)[3], T rho1, const T* gi)
+{
+    using L = Lat<LAT>;
+    constexpr int D = L::D;
+    const size_t sN = (size_t)m.N;
+    const T rho = T(1) + rho1;
+    T ra[D], rb[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        ra[a] = rho * out[a];
+        rb[a] = T(2) * vs[a] + out[a];
+    }
+    // (TO fields stay below 2^32 bytes: 32-bit offsets from scalar bases)
+    if constexpr (DEF) {
+        T* rec = (T*)m.rec;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            st_fld_at(rec + (size_t)a * sN, (unsigned)cell, ra[a], WT);
+            st_fld_at(rec + (size_t)(D + a) * sN, (unsigned)cell, rb[a], WT);
+        }
+    } else {
+        T* g = (T*)m.g[m.parity ^ flip ^ 1];
+        const T e = rec_e<D, T>(ra, rb);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+            st_fld(g + pop_at64<L::Q>(i, (size_t)cell),
+                   add_df<LAT, T>(gi[i], i, [&](int k) { return ra[k]; }, [&](int k) { return rb[k]; }, e), WT);
+    }
+}
+
+// dv of a binomial cell from its fields and the coefficients: sum_j cv_j
+// B^j v* + sum_j cw_j C_j + e_x cmp(y).
+template <int LAT, typename T, bool DEF>
+__device__ __forceinline__ void apply_dv(const ApplyIn<LAT, T, DEF>& in, bool hz, int jw, const T (&cvc)[kMaxPow + 1],
+                                         const T (&cwc)[kMaxPow + 1], bool hasmp, double cmp, T (&out)[3])
+{
+    constexpr int D = Lat<LAT>::D;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        T s = cvc[0] * in.fv[0][a];
+#pragma unroll
+        for (int jj = 1; jj <= kMaxPow; ++jj) s += cvc[jj] * in.fv[jj][a];
+        out[a] = s;
+    }
+    if (hz) {
+        T ctop[D];
+        top_curl_eval<D, T>(in.nb, in.okm, in.okp, ctop);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            T sacc = 0;
+#pragma unroll
+            for (int jj = 0; jj <= kMaxPow; ++jj) sacc += cwc[jj] * (jj < jw && jj < kMaxPow ? in.fc[jj < kMaxPow ? jj : 0][a] : ctop[a]);
+            out[a] += sacc;
+        }
+    }
+    if (hasmp) out[0] += T(cmp);
+}
+
+template <int LAT, typename T, bool KF, bool WT, bool DEF>
+__global__ __launch_bounds__(kBlock) void k_apply(const DevMember* __restrict__ mems, const int2* __restrict__ work,
                                                   int flip)
 {
     using L = Lat<LAT>;
     constexpr int D = L::D;
-    static_assert(!(FS && KF), "the kernel-filter build takes its coefficients from k_solve");
     const int2 wk = work[blockIdx.x];
     KMember& m = *kc(mems + wk.x);
     KParam* prm = kc(m.prm);
     const int N = m.N, nx = m.nx, ny = m.ny;
-    int cell = wk.y * kBlock + threadIdx.x;
-    if (!FS && cell >= N) return;
-    // FS: every thread stays for the barrier after the solve; a thread past
-    // the grid works on cell 0 and stores nothing
-    const bool own = cell < N;
-    if (!own) cell = 0;
-    const int x = cell % nx, t = cell / nx, y = t % ny, z = t / ny;
-    const size_t sN = (size_t)N;
+    const int cell = wk.y * kBlock + threadIdx.x;
+    if (cell >= N) return;
+    const int y = (cell / nx) % ny;
     KCtl* ctl = kc(m.ctl);
-    const int jv = prm->jv, jw = prm->jw;
-    const bool hz = prm->has_z;
-    const T* __restrict__ vsp = (const T*)m.vs;
     T out[3] = {0, 0, 0};
-    T vs[3] = {0, 0, 0};
-    // FS: the member's solve first, with few registers live, so that every
-    // workgroup of the launch is resident at once (the launch is used where
-    // the grid has few enough blocks); the field loads follow it
-    __shared__ SolveLds S;
-    if constexpr (FS) {
-        if (wk.y == 0) solve_member<kBlock, 1>(m, S);
-        else solve_member<kBlock, 2>(m, S);
-        __syncthreads();   // S.cv and S.cw of (g)
-    }
-    // in place: the populations the stream-collide of this step wrote
-    T* g = (T*)m.g[m.parity ^ flip ^ 1];
-    T gi[L::Q];
-    if constexpr (!DEF) {
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i) gi[i] = ld_fld<WT>(g + pop_at64<L::Q>(i, (size_t)cell));
-    }
+    T vs[D];
     if constexpr (KF) {
         // dv = sum_s beta_s V_s (clamped loads; beta_s = 0 past nsa)
+        const size_t sN = (size_t)N;
+        const T* __restrict__ vsp = (const T*)m.vs;
+        T gi[DEF ? 1 : L::Q];
+        if constexpr (!DEF) {
+            const T* g = (const T*)m.g[m.parity ^ flip ^ 1];
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) gi[i] = ld_fld<WT>(g + pop_at64<L::Q>(i, (size_t)cell));
+        }
         const int nsa = prm->nsa;
         const T* __restrict__ kV = (const T*)m.kV;
 #pragma unroll
@@ -2176,105 +2338,88 @@ __global__ __launch_bounds__(kBlock, FS ? 4 : 1) void k_apply(const DevMember* _
             out[a] = acc;
         }
         if (prm->nmp > 0) out[0] += T(m.cmp[y]);
+        apply_finish<LAT, T, WT, DEF>(m, flip, cell, vs, out, ((const T*)m.rho)[cell], gi);
     } else {
-        // Unconditional loads with the power clamped to the highest one
-        // stored: cv_j (cw_j) is zero above jv (jw), so the extra terms add
-        // exact zeros.  The top C_jw comes from the neighbours of W_jw.
-        T fv[kMaxPow + 1][D], fc[kMaxPow + 1][D];
+        ApplyIn<LAT, T, DEF> in;
+        apply_load<LAT, T, WT, DEF>(m, prm, flip, cell, in);
+        T cvc[kMaxPow + 1], cwc[kMaxPow + 1];
 #pragma unroll
         for (int jj = 0; jj <= kMaxPow; ++jj) {
-            const int je = jj < jv ? jj : jv;
-            const T* src = je == 0 ? vsp : (const T*)m.P + (size_t)(je - 1) * D * sN;
-#pragma unroll
-            for (int a = 0; a < D; ++a) fv[jj][a] = ld_fld<WT>(src + a * sN + cell);
+            cvc[jj] = coef_cv<T>(ctl, jj);
+            cwc[jj] = coef_cw<T>(ctl, jj);
         }
-        if (hz) {
-            T ctop[D];
-            top_curl<LAT, T>(m, jw, x, y, z, ctop);
-            const int jc = jw > 0 ? jw - 1 : 0;
+        const bool hasmp = prm->nmp > 0;
+        apply_dv<LAT, T, DEF>(in, prm->has_z, prm->jw, cvc, cwc, hasmp, hasmp ? m.cmp[y] : 0.0, out);
 #pragma unroll
-            for (int jj = 0; jj < kMaxPow; ++jj) {
-                const T* srcc = (const T*)m.C + (size_t)(jj < jc ? jj : jc) * D * sN;
+        for (int a = 0; a < D; ++a) vs[a] = in.fv[0][a];
+        apply_finish<LAT, T, WT, DEF>(m, flip, cell, vs, out, in.rho1, in.gi);
+    }
+}
+
+// The binomial apply with the member's solve at its head (launches of at
+// most kFusedApplyPairs workgroups).  A workgroup takes a pair of
+// blocks of one member (work entry (member, p): blocks 2p and 2p + 1), issues
+// the loads of both cells of every thread, then solves on all its threads
+// while they are in flight (two waves per SIMD: every workgroup of the launch
+// is resident at once), and finishes both cells with the solve's
+// coefficients; cmp(y) = sum_j beta_mp_j w_j(y) is formed per cell in the
+// order and precision k_solve forms it.  Pair 0 is the member's leader.
+template <int LAT, typename T, bool WT, bool DEF>
+__global__ __launch_bounds__(kBlock, 2) void k_apply_fs(const DevMember* __restrict__ mems,
+                                                         const int2* __restrict__ work, int flip)
+{
+    using L = Lat<LAT>;
+    constexpr int D = L::D;
+    __shared__ SolveLds S;
+    const int2 wk = work[blockIdx.x];
+    KMember& m = *kc(mems + wk.x);
+    KParam* prm = kc(m.prm);
+    const int N = m.N, nx = m.nx, ny = m.ny;
+    const int nmp = prm->nmp;
+    int cells[2];
+    bool own[2];
+    ApplyIn<LAT, T, DEF> in[2];
+    double wv[2][kMaxQ];
+    // the cells' loads, issued right after the solve's own
+    auto load = [&] {
 #pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    const T v = ld_fld<WT>(srcc + a * sN + cell);
-                    fc[jj][a] = jj < jw ? v : ctop[a];
-                }
-            }
-#pragma unroll
-            for (int a = 0; a < D; ++a) fc[kMaxPow][a] = ctop[a];
-        }
-        T cvc[kMaxPow + 1], cwc[kMaxPow + 1];
-        double cmp = 0;
-        if constexpr (FS) {
-            // this cell's row of the mean-profile part, cmp(y) = sum_j
-            // beta_mp_j w_j(y), in the order and precision k_solve forms it
-            const int nmp = prm->nmp;
-            double wv[kMaxQ];
+        for (int u = 0; u < 2; ++u) {
+            const int c = (2 * wk.y + u) * kBlock + threadIdx.x;
+            own[u] = c < N;
+            cells[u] = own[u] ? c : 0;   // a thread past the grid loads cell 0 and stores nothing
+            apply_load<LAT, T, WT, DEF>(m, prm, flip, cells[u], in[u]);
+            const int y = (cells[u] / nx) % ny;
             if (nmp > 0) {
 #pragma unroll
                 for (int jm = 0; jm < kMaxQ; ++jm)
-                    wv[jm] = jm < nmp ? m.bandw[(size_t)prm->mp_band[jm] * ny + y] : 0.0;
-            }
-#pragma unroll
-            for (int jj = 0; jj <= kMaxPow; ++jj) {
-                cvc[jj] = T(S.cv[jj]);
-                cwc[jj] = T(S.cw[jj]);
-            }
-            if (nmp > 0) {
-#pragma unroll
-                for (int jm = 0; jm < kMaxQ; ++jm) cmp += jm < nmp ? S.beta[S.mpslot[jm]] * wv[jm] : 0.0;
-            }
-        } else {
-#pragma unroll
-            for (int jj = 0; jj <= kMaxPow; ++jj) {
-                cvc[jj] = coef_cv<T>(ctl, jj);
-                cwc[jj] = coef_cw<T>(ctl, jj);
-            }
-            if (prm->nmp > 0) cmp = m.cmp[y];
-        }
-        if (!own) return;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            T s = cvc[0] * fv[0][a];
-#pragma unroll
-            for (int jj = 1; jj <= kMaxPow; ++jj) s += cvc[jj] * fv[jj][a];
-            out[a] = s;
-        }
-        if (hz) {
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                T sacc = 0;
-#pragma unroll
-                for (int jj = 0; jj <= kMaxPow; ++jj) sacc += cwc[jj] * fc[jj][a];
-                out[a] += sacc;
+                    wv[u][jm] = jm < nmp ? m.bandw[(size_t)prm->mp_band[jm] * ny + y] : 0.0;
             }
         }
+    };
+    if (wk.y == 0) solve_member<kBlock, 1>(m, S, load);
+    else solve_member<kBlock, 2>(m, S, load);
+    __syncthreads();   // S.cv and S.cw of (g)
+    T cvc[kMaxPow + 1], cwc[kMaxPow + 1];
 #pragma unroll
-        for (int a = 0; a < D; ++a) vs[a] = fv[0][a];
-        if (prm->nmp > 0) out[0] += T(cmp);
+    for (int jj = 0; jj <= kMaxPow; ++jj) {
+        cvc[jj] = T(S.cv[jj]);
+        cwc[jj] = T(S.cw[jj]);
     }
-    const T rho = T(1) + ((const T*)m.rho)[cell];
-    T ra[D], rb[D];
+    const bool hz = prm->has_z;
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-        ra[a] = rho * out[a];
-        rb[a] = T(2) * vs[a] + out[a];
-    }
-    // (TO fields stay below 2^32 bytes: 32-bit offsets from scalar bases)
-    if constexpr (DEF) {
-        T* rec = (T*)m.rec;
+    for (int u = 0; u < 2; ++u) {
+        if (!own[u]) continue;
+        double cmp = 0;
+        if (nmp > 0) {
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-            st_fld_at(rec + (size_t)a * sN, (unsigned)cell, ra[a], WT);
-            st_fld_at(rec + (size_t)(D + a) * sN, (unsigned)cell, rb[a], WT);
+            for (int jm = 0; jm < kMaxQ; ++jm) cmp += jm < nmp ? S.beta[S.mpslot[jm]] * wv[u][jm] : 0.0;
         }
-    } else {
-        const T e = rec_e<D, T>(ra, rb);
+        T out[3] = {0, 0, 0};
+        apply_dv<LAT, T, DEF>(in[u], hz, prm->jw, cvc, cwc, nmp > 0, cmp, out);
+        T vs[D];
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i)
-            st_fld(g + pop_at64<L::Q>(i, (size_t)cell),
-                   add_df<LAT, T>(gi[i], i, [&](int k) { return ra[k]; }, [&](int k) { return rb[k]; }, e), WT);
+        for (int a = 0; a < D; ++a) vs[a] = in[u].fv[0][a];
+        apply_finish<LAT, T, WT, DEF>(m, flip, cells[u], vs, out, in[u].rho1, in[u].gi);
     }
 }
 
@@ -2974,16 +3119,22 @@ to_chain:
         if (!fused) hipLaunchKernelGGL(k_solve, dim3(g.nmem), blk, 0, st, g.mems, g.workm);
         mark(5);
         if (!g.probe) {
-#define LBM_APPLY(KFV, DEFV, FSV)                                                                            \
+#define LBM_APPLY(KFV, DEFV)                                                                                 \
     do {                                                                                                     \
-        if (g.wt) hipLaunchKernelGGL((k_apply<LAT, T, KFV, true, DEFV, FSV>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
-        else hipLaunchKernelGGL((k_apply<LAT, T, KFV, false, DEFV, FSV>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
+        if (g.wt) hipLaunchKernelGGL((k_apply<LAT, T, KFV, true, DEFV>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
+        else hipLaunchKernelGGL((k_apply<LAT, T, KFV, false, DEFV>), dim3(g.nb1), blk, 0, st, g.mems, g.work1, flip); \
+    } while (0)
+#define LBM_APPLY_FS(DEFV)                                                                                   \
+    do {                                                                                                     \
+        if (g.wt) hipLaunchKernelGGL((k_apply_fs<LAT, T, true, DEFV>), dim3(g.nbp), blk, 0, st, g.mems, g.workp, flip); \
+        else hipLaunchKernelGGL((k_apply_fs<LAT, T, false, DEFV>), dim3(g.nbp), blk, 0, st, g.mems, g.workp, flip); \
     } while (0)
             const bool def = g.defer && g.substrate != LBM_WALE;
-            if (g.kf) { if (def) LBM_APPLY(true, true, false); else LBM_APPLY(true, false, false); }
-            else if (fused) { if (def) LBM_APPLY(false, true, true); else LBM_APPLY(false, false, true); }
-            else { if (def) LBM_APPLY(false, true, false); else LBM_APPLY(false, false, false); }
+            if (g.kf) { if (def) LBM_APPLY(true, true); else LBM_APPLY(true, false); }
+            else if (fused) { if (def) LBM_APPLY_FS(true); else LBM_APPLY_FS(false); }
+            else { if (def) LBM_APPLY(false, true); else LBM_APPLY(false, false); }
 #undef LBM_APPLY
+#undef LBM_APPLY_FS
         }
         mark(6);
     } else if (g.mode == 1) {

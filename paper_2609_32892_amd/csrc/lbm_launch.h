@@ -53,6 +53,8 @@ struct LaunchGroup {
     const DevMember* mems;
     const int2* work1;  // cell kernels: (member, block of kBlock cells)
     int nb1;
+    const int2* workp;  // the apply with the solve: (member, pair p of blocks 2p and 2p + 1)
+    int nbp;
     const int2* workr;  // reduce: (member, y * nbx2 + bx)
     int nbr;
     const int2* workb;  // binomial filter: (member, xyz tile)
@@ -78,10 +80,10 @@ struct LaunchGroup {
 
 // TO mode: the binomial apply forms the solve itself (no k_solve launch):
 // not for kernel-filter closures, probe steps (no apply) or a forced own
-// launch, and only where the apply's blocks are all resident at once.
+// launch, and only where the apply's workgroups are all resident at once.
 inline bool fused_solve(const LaunchGroup& g)
 {
-    return !g.kf && !g.probe && !g.sep_solve && g.nb1 <= kFusedApplyBlocks;
+    return !g.kf && !g.probe && !g.sep_solve && g.nbp <= kFusedApplyPairs;
 }
 
 enum { OP_INIT = 0, OP_GET_POP = 1, OP_SET_POP = 2, OP_STREAM = 3 };
