@@ -1376,6 +1376,58 @@ __device__ __forceinline__ void top_curl(KMember& m, int jw, int x, int y, int z
     curlT_nb<L::D, T>((const T*)m.W + (size_t)jw * L::NC * sN, sN, c, nb, out);
 }
 
+// The top C_jw = curl^T W_jw of a cell in two steps, so that a caller can
+// hold the loads and form the curl later: the neighbour values (2-D: psi at
+// y+1, y-1, x+1, x-1; 3-D: w_z, w_y, w_x at the pairs of neighbours of
+// D_y w_z, D_z w_y, D_z w_x, D_x w_z, D_x w_y, D_y w_x), then central
+// differences (zero beyond the walls), without contraction.
+template <int LAT, typename T>
+__device__ __forceinline__ void top_curl_load(KMember& m, int jw, int x, int y, int z, T* r, bool& okm, bool& okp)
+{
+    using L = Lat<LAT>;
+    const unsigned sN = (unsigned)m.N;
+    const unsigned c = (unsigned)(x + m.nx * (y + m.ny * z));
+    const Nbr n = nbr_at(c, x, y, z, m.nx, m.ny, m.nz, m.walls, L::D);
+    const T* psi = (const T*)m.W + (size_t)jw * L::NC * sN;
+    okm = n.okm;
+    okp = n.okp;
+    if constexpr (L::D == 2) {
+        r[0] = ld_at(psi, n.yp); r[1] = ld_at(psi, n.ym);
+        r[2] = ld_at(psi, n.xp); r[3] = ld_at(psi, n.xm);
+    } else {
+        const T* ux = psi;
+        const T* uy = psi + sN;
+        const T* uz = psi + 2 * sN;
+        r[0] = ld_at(uz, n.yp); r[1] = ld_at(uz, n.ym);
+        r[2] = ld_at(uy, n.zp); r[3] = ld_at(uy, n.zm);
+        r[4] = ld_at(ux, n.zp); r[5] = ld_at(ux, n.zm);
+        r[6] = ld_at(uz, n.xp); r[7] = ld_at(uz, n.xm);
+        r[8] = ld_at(uy, n.xp); r[9] = ld_at(uy, n.xm);
+        r[10] = ld_at(ux, n.yp); r[11] = ld_at(ux, n.ym);
+    }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void top_curl_eval(const T* r, bool okm, bool okp, T* out)
+{
+#pragma clang fp contract(off)
+    auto y0 = [](bool ok, T v) { return ok ? v : T(0); };
+    if constexpr (D == 2) {
+        out[0] = T(0.5) * (y0(okp, r[0]) - y0(okm, r[1]));
+        out[1] = -(T(0.5) * (r[2] - r[3]));
+    } else {
+        const T dyuz = T(0.5) * (y0(okp, r[0]) - y0(okm, r[1]));
+        const T dzuy = T(0.5) * (r[2] - r[3]);
+        const T dzux = T(0.5) * (r[4] - r[5]);
+        const T dxuz = T(0.5) * (r[6] - r[7]);
+        const T dxuy = T(0.5) * (r[8] - r[9]);
+        const T dyux = T(0.5) * (y0(okp, r[10]) - y0(okm, r[11]));
+        out[0] = dyuz - dzuy;
+        out[1] = dzux - dxuz;
+        out[2] = dxuy - dyux;
+    }
+}
+
 // The fields a cell's sensitivities are formed from, loaded in one batch
 // (no branch between the loads, so that the loads of several cells can be
 // in flight together) and evaluated afterwards.
@@ -1383,7 +1435,9 @@ template <int LAT, typename T, int MAXSA>
 struct CellIn {
     T pv[kMaxPow + 1][Lat<LAT>::D];   // B^j v*, j = 0..kMaxPow (clamped to jv)
     T wc[3][Lat<LAT>::NC];            // B^j w, j = 0..2 (clamped to jw)
-    T cv[kMaxPow + 1][Lat<LAT>::D];   // C_j (clamped to jw)
+    T cv[kMaxPow][Lat<LAT>::D];       // stored C_j (clamped to jw - 1)
+    T nb[Lat<LAT>::D == 2 ? 4 : 12];  // W_jw at the neighbours of the top curl
+    bool okm, okp;
     T kv[MAXSA][Lat<LAT>::D];         // kernel filters: V_s (clamped to nsa - 1)
 };
 
@@ -1428,23 +1482,18 @@ __device__ __forceinline__ void cell_load(KMember& m, KParam* prm, int x, int y,
         for (int a = 0; a < NC; ++a) in.wc[jj][a] = src[a * sN + cell];
     }
     // C_j = curl^T B^j w (Z sensitivities): the stored C_j for j < jw, the
-    // top one from the neighbours of W_jw
+    // top one formed at evaluation from the neighbours of W_jw (no
+    // arithmetic here, so the loads of a next cell need not wait for these)
     if (!hz) return;
-    T ctop[D];
-    top_curl<LAT, T>(m, jw, x, y, z, ctop);
+    top_curl_load<LAT, T>(m, jw, x, y, z, in.nb, in.okm, in.okp);
     const T* __restrict__ Cc = (const T*)m.C;
     const int jc = jw > 0 ? jw - 1 : 0;
 #pragma unroll
     for (int jj = 0; jj < kMaxPow; ++jj) {
         const T* src = Cc + (size_t)(jj < jc ? jj : jc) * D * sN;
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-            const T v = src[a * sN + cell];
-            in.cv[jj][a] = jj < jw ? v : ctop[a];
-        }
+        for (int a = 0; a < D; ++a) in.cv[jj][a] = src[a * sN + cell];
     }
-#pragma unroll
-    for (int a = 0; a < D; ++a) in.cv[kMaxPow][a] = ctop[a];
 }
 
 // The closure's filter coefficients of every E/Z QoI, read once per
@@ -1454,7 +1503,7 @@ template <typename T, int MAXSA>
 struct SensCoef {
     T r[MAXSA][3], rr[MAXSA][kMaxPow + 1];
     int z[MAXSA];
-    int nsa, hz;
+    int nsa, hz, jw;
 };
 
 template <typename T, int MAXSA>
@@ -1462,6 +1511,7 @@ __device__ __forceinline__ void sens_coef(KParam* prm, SensCoef<T, MAXSA>& c)
 {
     c.nsa = prm->nsa;
     c.hz = prm->has_z;
+    c.jw = prm->jw;
 #pragma unroll
     for (int s = 0; s < MAXSA; ++s) {
         c.z[s] = prm->sa_kind[s];
@@ -1519,7 +1569,10 @@ __device__ __forceinline__ void cell_eval(const SensCoef<T, MAXSA>& cf, const Ce
         }
     }
     if (!cf.hz) return;
-    // Z sensitivities from the stored C_j = curl^T B^j w
+    // Z sensitivities from C_j = curl^T B^j w: the stored ones for j < jw,
+    // the top one above
+    T ctop[D];
+    top_curl_eval<D, T>(in.nb, in.okm, in.okp, ctop);
 #pragma unroll
     for (int s = 0; s < MAXSA; ++s) {
         if (s >= nsa || cf.z[s] == 0) continue;
@@ -1527,7 +1580,8 @@ __device__ __forceinline__ void cell_eval(const SensCoef<T, MAXSA>& cf, const Ce
         for (int a = 0; a < D; ++a) {
             T vv = 0;
 #pragma unroll
-            for (int jj = 0; jj <= kMaxPow; ++jj) vv += cf.rr[s][jj] * in.cv[jj][a];
+            for (int jj = 0; jj <= kMaxPow; ++jj)
+                vv += cf.rr[s][jj] * (jj < cf.jw && jj < kMaxPow ? in.cv[jj < kMaxPow ? jj : 0][a] : ctop[a]);
             V[s][a] = vv;
         }
     }
@@ -2145,58 +2199,6 @@ struct ApplyIn {
     T rho1;                            // rho - 1
     T gi[DEF ? 1 : Lat<LAT>::Q];
 };
-
-// The top C_jw = curl^T W_jw of a cell in two steps, so that a caller can
-// hold the loads and form the curl later: the neighbour values (2-D: psi at
-// y+1, y-1, x+1, x-1; 3-D: w_z, w_y, w_x at the pairs of neighbours of
-// D_y w_z, D_z w_y, D_z w_x, D_x w_z, D_x w_y, D_y w_x), then central
-// differences (zero beyond the walls), without contraction.
-template <int LAT, typename T>
-__device__ __forceinline__ void top_curl_load(KMember& m, int jw, int x, int y, int z, T* r, bool& okm, bool& okp)
-{
-    using L = Lat<LAT>;
-    const unsigned sN = (unsigned)m.N;
-    const unsigned c = (unsigned)(x + m.nx * (y + m.ny * z));
-    const Nbr n = nbr_at(c, x, y, z, m.nx, m.ny, m.nz, m.walls, L::D);
-    const T* psi = (const T*)m.W + (size_t)jw * L::NC * sN;
-    okm = n.okm;
-    okp = n.okp;
-    if constexpr (L::D == 2) {
-        r[0] = ld_at(psi, n.yp); r[1] = ld_at(psi, n.ym);
-        r[2] = ld_at(psi, n.xp); r[3] = ld_at(psi, n.xm);
-    } else {
-        const T* ux = psi;
-        const T* uy = psi + sN;
-        const T* uz = psi + 2 * sN;
-        r[0] = ld_at(uz, n.yp); r[1] = ld_at(uz, n.ym);
-        r[2] = ld_at(uy, n.zp); r[3] = ld_at(uy, n.zm);
-        r[4] = ld_at(ux, n.zp); r[5] = ld_at(ux, n.zm);
-        r[6] = ld_at(uz, n.xp); r[7] = ld_at(uz, n.xm);
-        r[8] = ld_at(uy, n.xp); r[9] = ld_at(uy, n.xm);
-        r[10] = ld_at(ux, n.yp); r[11] = ld_at(ux, n.ym);
-    }
-}
-
-template <int D, typename T>
-__device__ __forceinline__ void top_curl_eval(const T* r, bool okm, bool okp, T* out)
-{
-#pragma clang fp contract(off)
-    auto y0 = [](bool ok, T v) { return ok ? v : T(0); };
-    if constexpr (D == 2) {
-        out[0] = T(0.5) * (y0(okp, r[0]) - y0(okm, r[1]));
-        out[1] = -(T(0.5) * (r[2] - r[3]));
-    } else {
-        const T dyuz = T(0.5) * (y0(okp, r[0]) - y0(okm, r[1]));
-        const T dzuy = T(0.5) * (r[2] - r[3]);
-        const T dzux = T(0.5) * (r[4] - r[5]);
-        const T dxuz = T(0.5) * (r[6] - r[7]);
-        const T dxuy = T(0.5) * (r[8] - r[9]);
-        const T dyux = T(0.5) * (y0(okp, r[10]) - y0(okm, r[11]));
-        out[0] = dyuz - dzuy;
-        out[1] = dzux - dxuz;
-        out[2] = dxuy - dyux;
-    }
-}
 
 template <int LAT, typename T, bool WT, bool DEF>
 __device__ __forceinline__ void apply_load(KMember& m, KParam* prm, int flip, int cell, ApplyIn<LAT, T, DEF>& in)
