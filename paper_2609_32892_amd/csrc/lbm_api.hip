@@ -1436,8 +1436,9 @@ struct StateHeader {
     int32_t Q, N, esz, has_to;
 };
 
-// State images hold the populations in the device's blocked layout.
-constexpr unsigned long long kStateMagic = 0x4C424D53544155ULL;
+// State images hold the populations in the device's blocked layout and the
+// control block with its step snapshot and pending LRS scale.
+constexpr unsigned long long kStateMagic = 0x4C424D53544156ULL;
 
 size_t lbm_state_bytes(const lbm_ctx* c)
 {
