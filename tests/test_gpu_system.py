@@ -74,6 +74,33 @@ def test_batch_members_bitwise_equal_to_solo():
         assert np.array_equal(r.get_populations(), s.get_populations())
 
 
+def test_batch_past_the_fused_solve_limit_bitwise_equal_to_solo():
+    """Five 256 x 256 Kolmogorov members (128 apply workgroups of two blocks
+    each when alone, so each solo run forms its solve in the apply) batched
+    into one launch group of 640 workgroups, past the 512 whose workgroups
+    are all resident at once, so the batch solves in k_solve: every member
+    equals its solo run bitwise, records included."""
+    lbm = need_gpu()
+    members = [_case2d(256, seed=s) for s in (11, 12, 13, 14, 15)]
+    solo = [gpu_run(lbm, cfg, u0, "fp32", qois, dict(cargs, spinup=4)) for cfg, u0, qois, cargs in members]
+    batched = [gpu_run(lbm, cfg, u0, "fp32", qois, dict(cargs, spinup=4)) for cfg, u0, qois, cargs in members]
+    for r in solo:
+        r.step(12)
+        r.sync()
+    batch = lbm.Batch(batched)
+    batch.step(12)
+    batch.sync()
+    for r, s in zip(batched, solo):
+        assert np.array_equal(r.get_populations(), s.get_populations())
+        ra, rs = r.record_arrays(), s.record_arrays()
+        for key in ("q", "dq", "gamma", "flags"):
+            assert np.array_equal(ra[key], rs[key]), key
+        assert np.any(ra["dq"][4:] != 0)
+    batch.close()
+    for r in solo + batched:
+        r.close()
+
+
 def test_checkpoint_resume_bitwise():
     lbm = need_gpu()
     cfg, u0, qois, cargs = _case2d()
