@@ -90,7 +90,8 @@ typedef struct {
                            substrate) also where the populations (up to 192 MB) would
                            apply it in place, bit 3 the closure's solve in a launch of its
                            own also where the apply would form it (binomial closures on
-                           grids of at most 1024 blocks of 256 cells); bitwise the same
+                           launches of at most 1024 blocks of 256 cells, paired into 512
+                           workgroups); bitwise the same
                            result either way (for tests of the large-grid forms); 0..15 */
 } lbm_config;
 
