@@ -1448,6 +1448,29 @@ size_t lbm_state_bytes(const lbm_ctx* c)
     return b;
 }
 
+// The control block of a state image in one form whichever launch formed the
+// solve: a first LRS scale that the apply left pending is committed (as the
+// next k_sum would commit it), and the values every step forms afresh before
+// reading them (the dv coefficients, the step snapshot) are cleared.
+static void canonical_ctl(DevCtl& t)
+{
+    if (t.s_pend) {
+        for (int k = 0; k < kMaxQ; ++k) t.s[k] = t.s_next[k];
+        t.s_set = 1;
+        t.s_pend = 0;
+    }
+    t.step_snap = 0;
+    for (int k = 0; k < kMaxQ; ++k) t.s_next[k] = 0.0;
+    for (int j = 0; j <= kMaxPow; ++j) {
+        t.cv[j] = t.cw[j] = 0.0;
+        t.cvf[j] = t.cwf[j] = 0.0f;
+    }
+    for (int k = 0; k < kMaxSA; ++k) {
+        t.bsa[k] = 0.0;
+        t.bsaf[k] = 0.0f;
+    }
+}
+
 int lbm_get_state(lbm_ctx* c, void* host, size_t bytes)
 {
     if (!c || !host) return fail(LBM_EINVAL, "NULL argument");
@@ -1463,7 +1486,10 @@ int lbm_get_state(lbm_ctx* c, void* host, size_t bytes)
     const size_t gb = (size_t)p.esz * p.popn;
     HIPCHK(hipMemcpy(o, c->hm.g[c->hm.parity ^ c->phase], gb, hipMemcpyDeviceToHost));
     o += gb;
-    HIPCHK(hipMemcpy(o, c->arena + p.ctl, sizeof(DevCtl), hipMemcpyDeviceToHost));
+    DevCtl ctl;
+    HIPCHK(hipMemcpy(&ctl, c->arena + p.ctl, sizeof ctl, hipMemcpyDeviceToHost));
+    canonical_ctl(ctl);
+    memcpy(o, &ctl, sizeof ctl);
     o += sizeof(DevCtl);
     HIPCHK(hipMemcpy(o, c->arena + p.recs, sizeof(lbm_qoi_rec) * p.rec_cap, hipMemcpyDeviceToHost));
     return LBM_OK;
@@ -2081,25 +2107,28 @@ int lbm_server_create(size_t hbm_budget, void* stream, lbm_server** out)
     if (!out) return fail(LBM_EINVAL, "out is NULL");
     lbm_server* s = new lbm_server();
     s->stream = (hipStream_t)stream;
-    bool ok = true;
+    const char* what = nullptr;
+    hipError_t e = hipSuccess;
     if (!s->stream) {
-        ok = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
-        s->own_stream = ok;
+        e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+        s->own_stream = e == hipSuccess;
+        if (e != hipSuccess) what = "stream creation";
     }
-    ok = ok && hipStreamCreateWithFlags(&s->adm, hipStreamNonBlocking) == hipSuccess;
-    ok = ok && hipEventCreate(&s->ev0) == hipSuccess && hipEventCreate(&s->ev1) == hipSuccess;
-    if (ok && hbm_budget == 0) {
+    if (!what && (e = hipStreamCreateWithFlags(&s->adm, hipStreamNonBlocking)) != hipSuccess) what = "admission stream creation";
+    if (!what && (e = hipEventCreate(&s->ev0)) != hipSuccess) what = "event creation";
+    if (!what && (e = hipEventCreate(&s->ev1)) != hipSuccess) what = "event creation";
+    if (!what && hbm_budget == 0) {
         size_t fr = 0, tot = 0;
-        ok = hipMemGetInfo(&fr, &tot) == hipSuccess;
+        if ((e = hipMemGetInfo(&fr, &tot)) != hipSuccess) what = "memory query";
         hbm_budget = (size_t)(0.8 * (double)fr);
     }
-    if (!ok) {
+    if (what) {
         if (s->ev0) (void)hipEventDestroy(s->ev0);
         if (s->ev1) (void)hipEventDestroy(s->ev1);
         if (s->adm) (void)hipStreamDestroy(s->adm);
         if (s->own_stream) (void)hipStreamDestroy(s->stream);
         delete s;
-        return fail(LBM_EDEVICE, "server: stream, event or memory query failed");
+        return fail(LBM_EDEVICE, "server: %s failed (%s)", what, hipGetErrorString(e));
     }
     s->budget = hbm_budget;
     *out = s;

@@ -112,6 +112,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2609_32892_amd/build.py")
+        # torch first, so that the library binds to the HIP runtime torch
+        # loads (the one that owns the streams and memory passed in); loaded
+        # the other way round, a server created before any run found no device
+        import torch  # noqa: F401
         L = ct.CDLL(LIB_PATH)
         P, I, Z = ct.c_void_p, ct.c_int, ct.c_size_t
         L.lbm_last_error.restype = ct.c_char_p

@@ -165,3 +165,31 @@ def test_server_rejects_bad_requests_and_serves_the_rest():
     st = srv.stats()
     assert st["used"] == 0
     srv.close()
+
+
+def test_server_as_the_first_gpu_object_of_a_process():
+    """A server created before any run in a fresh process (the library then
+    loads first) finds the device, admits a request and completes it."""
+    import os
+    import subprocess
+    import sys
+    need_gpu()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys; sys.path.insert(0, %r); sys.path.insert(0, %r)\n"
+        "from paper_2609_32892_amd import lbm\n"
+        "import synth\n"
+        "srv = lbm.Server()\n"
+        "cfg, _ = synth.kolmogorov_workload(32, tau=0.51, seed=1)\n"
+        "u0 = synth.turbulent_velocity_2d(32, 0.03, seed=1)\n"
+        "c = lbm.make_config(precision='fp32', **cfg)\n"
+        "srv.submit(c, None, u0, 20, srv.clock())\n"
+        "res = []\n"
+        "while srv.pending() > 0:\n"
+        "    srv.advance(srv.clock(), 16)\n"
+        "    res += srv.poll()\n"
+        "assert len(res) == 1 and res[0].status == 0, res\n"
+        "print('first-object server ok', flush=True)\n"
+    ) % (root, os.path.join(root, "tests"))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240)
+    assert out.returncode == 0 and "first-object server ok" in out.stdout, out.stderr[-2000:]

@@ -92,6 +92,7 @@ def test_batch_past_the_fused_solve_limit_bitwise_equal_to_solo():
     batch.sync()
     for r, s in zip(batched, solo):
         assert np.array_equal(r.get_populations(), s.get_populations())
+        assert bytes(r.get_state()) == bytes(s.get_state())
         ra, rs = r.record_arrays(), s.record_arrays()
         for key in ("q", "dq", "gamma", "flags"):
             assert np.array_equal(ra[key], rs[key]), key
@@ -287,6 +288,9 @@ def test_solve_in_apply_and_in_its_own_launch_bitwise_equal(case):
         r.step(S0 + 1)   # through the first corrected step
         r.sync()
     state = a.get_state()
+    # the images are the same bytes: the pending scale committed, the
+    # per-step coefficients cleared
+    assert bytes(state) == bytes(b.get_state())
     c = gpu_run(lbm, cfg, u0, prec, qois, cargs, qref=qref, tune_mem=tm)
     c.set_state(state)
     for r in (a, b, c):
@@ -295,6 +299,7 @@ def test_solve_in_apply_and_in_its_own_launch_bitwise_equal(case):
     fa = a.get_populations()
     assert np.array_equal(fa, b.get_populations())
     assert np.array_equal(fa, c.get_populations())
+    assert bytes(a.get_state()) == bytes(b.get_state()) == bytes(c.get_state())
     ra, rb, rc = a.record_arrays(), b.record_arrays(), c.record_arrays()
     for key in ("q", "dq", "gamma", "flags"):
         assert np.array_equal(ra[key], rb[key]), key
