@@ -26,6 +26,8 @@
 //              equilibrium is added to the predictor populations in place, or
 //              recorded as (rho dv, 2 v* + dv) for the next k_step_t (k_flush
 //              applies pending records before the state is read).
+//   k_apply_fs the same with the member's solve at its head, in every
+//              workgroup (small launches: no k_solve launch).
 // Every kernel takes a table of members and a work table mapping each
 // workgroup to (member, local block), so one launch serves a whole ensemble.
 // All reductions have a fixed order that depends only on the member's own
