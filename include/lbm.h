@@ -311,7 +311,9 @@ int lbm_project_qoi_kind(lbm_ctx* fine, lbm_ctx* probe, int m, int kind);
 
 /* Checkpoint: opaque byte image of the dynamic state (populations,
  * counters, LRS scale, records).  Restoring it into a context created with
- * the same cfg and closure resumes bitwise identically. */
+ * the same cfg and closure resumes bitwise identically.  Two runs in the same
+ * state give the same bytes, whichever launch forms their solve (alone, in a
+ * batch, in a server, tune_mem bit 3). */
 size_t lbm_state_bytes(const lbm_ctx* ctx);
 int lbm_get_state(lbm_ctx* ctx, void* host, size_t bytes);
 int lbm_set_state(lbm_ctx* ctx, const void* host, size_t bytes);
